@@ -1,0 +1,8 @@
+"""FP64 CPU oracle for the isotropic Gaussian splatting rasterizer.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py``, never by the GPU library or its Python binding.
+"""
+from .isogs64 import *  # noqa: F401,F403
+from .isogs64 import (ALPHA_MIN, ALPHA_MAX, T_MIN, TILE, RADIUS_GROW, RADIUS_PAD,  # noqa: F401
+                      ALPHA_FLAG_REL, TERM_FLAG_REL)
