@@ -1,0 +1,194 @@
+/*
+ * isogs.h - C ABI of the MI355X (gfx950) rasterizer for isotropic Gaussian splatting.
+ *
+ * Method: Gong, Yu, Yue, "Isotropic Gaussian Splatting for Real-Time Radiance Field
+ * Rendering" (arXiv 2403.14244). A pixel's colour is the front-to-back composite of eq. 4,
+ * C = sum_k c_k alpha_k prod_{j<k}(1 - alpha_j), with the isotropic kernel of eq. 8,
+ * g = exp(-|x - mu|^2 / sigma^2). On the image plane the kernel is a circle of screen
+ * scale s = f sigma / z: by Section 2 ("View Dependency", and Table 1) an isotropic
+ * kernel's size depends only on its distance to the view point. alpha = min(0.99, o g);
+ * an entry contributes only where alpha >= 1/255 (the compact support of eq. 2); a pixel
+ * stops after the entry that takes its transmittance T below 1e-4.
+ *
+ * Pipeline (one call each, all asynchronous on the caller's HIP stream):
+ *   isogs_project    particles -> screen footprints and per-particle tile counts
+ *   isogs_bin_sort   footprints -> (tile, depth)-sorted entry lists per 16x16 tile
+ *   isogs_render_fwd entry lists -> image, final transmittance, last contributor
+ *   isogs_render_bwd dL/dimage -> dL/d(particle parameters), for back-propagation
+ *                    (the optimisation mode of Section 3, "Optimization")
+ *
+ * Conventions shared by every call:
+ *   - Every buffer pointer is DEVICE memory owned by the caller, except the arrays of
+ *     isogs_scene / isogs_camera structs themselves, which are HOST memory read during
+ *     the call only. The library keeps no pointer after a call returns and allocates no
+ *     device memory; scratch space comes from the caller's workspace (query with
+ *     ws == NULL).
+ *   - A batch holds V views. View v renders scene scenes[v] with camera cams[v]; views
+ *     may share a scene and may have different resolutions. Per-view arrays are packed
+ *     back to back in view order: particles (sum of n_v), tiles (sum of TX_v * TY_v with
+ *     TX = ceil(W/16), TY = ceil(H/16)), pixels (sum of H_v * W_v).
+ *   - Return codes: ISOGS_OK, or ISOGS_ERR_* below; isogs_last_error() then describes the
+ *     failure. Data-dependent failures (entry capacity) cannot be known at launch time;
+ *     they are reported through the device-side status word of isogs_bins.
+ *   - Per-particle garbage (non-finite values, sigma <= 0, o < 1/255, depth <= near) is
+ *     not an error: such a particle is culled (tile count 0).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef ISOGS_H
+#define ISOGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISOGS_OK 0
+#define ISOGS_ERR_INVALID (-1)   /* bad argument: NULL pointer, V <= 0, n < 0, degree > 3, ... */
+#define ISOGS_ERR_CAPACITY (-2)  /* entry count exceeds isogs_bins.capacity (device status) */
+#define ISOGS_ERR_WORKSPACE (-3) /* workspace NULL-sized or too small */
+#define ISOGS_ERR_DEVICE (-4)    /* a HIP launch failed */
+
+/* Method constants (readings of the paper; the oracle states the same values). */
+#define ISOGS_TILE 16            /* tile edge, pixels */
+#define ISOGS_ALPHA_MIN_INV 255  /* entries with alpha < 1/255 are skipped (eq. 2 support) */
+#define ISOGS_ALPHA_MAX 0.99f    /* alpha clamp */
+#define ISOGS_T_MIN 1e-4f        /* termination threshold on transmittance */
+#define ISOGS_NEAR_DEFAULT 0.2f
+#define ISOGS_MAX_SH_DEGREE 3
+
+/* A scene: structure-of-arrays FP32 particle parameters (device memory).
+ *   pos      [3][n]     centres mu, rows x, y, z
+ *   scale    [n]        isotropic scale sigma > 0 (linear; eq. 8)
+ *   opacity  [n]        activated opacity o
+ *   color    [3K][n]    colour coefficients, K = (sh_degree + 1)^2; row 3k + ch holds
+ *                       coefficient k (k = l^2 + l + m) of channel ch. Colour seen along
+ *                       the unit direction d = (mu - eye)/|mu - eye| is
+ *                       max(0, c_0 + sum_{l>=1} c_lm Y_lm(d)) with real orthonormal
+ *                       spherical harmonics Y_lm without the Condon-Shortley phase.
+ * In isogs_render_bwd the same struct describes gradient OUTPUT buffers (non-const use). */
+typedef struct {
+    const float* pos;
+    const float* scale;
+    const float* opacity;
+    const float* color;
+    int32_t n;
+    int32_t sh_degree;
+} isogs_scene;
+
+/* A pinhole camera (host struct). World point mu maps to p = R mu + t (R row-major,
+ * rows = camera x right, y down, z forward); depth z = p_z; pixel coordinates
+ * u = f p_x / z + cx, v = f p_y / z + cy; pixel (i, j) has its centre at (i + 1/2, j + 1/2).
+ * eye is the camera centre in world space (used for the colour direction). */
+typedef struct {
+    float R[9];
+    float t[3];
+    float eye[3];
+    float f;
+    float cx;
+    float cy;
+    float near_z;   /* particles with depth <= near_z are culled; must be > 0 */
+    int32_t width;
+    int32_t height;
+} isogs_camera;
+
+/* Screen footprints, one record per (view, particle), packed over views (device memory).
+ *   footprint     [N][4]  {u, v, 1/s^2, o}        (16-byte aligned)
+ *   color_radius  [N][4]  {r, g, b, radius}       (16-byte aligned); radius is the binning
+ *                         radius s sqrt(ln(255 o)) (1 + 2^-10) + 2^-6 pixels, 0 if culled
+ *   depth         [N]     z (FP32)
+ *   tile_count    [N]     number of member tiles (0 if culled)
+ * A tile is a member when the FP32 distance from (u, v) to the rectangle of its pixel
+ * centres, evaluated as dx = max(max(x_lo - u, u - x_hi), 0), dy likewise,
+ * dx*dx + dy*dy <= radius*radius, one rounded operation at a time, holds. */
+typedef struct {
+    float* footprint;
+    float* color_radius;
+    float* depth;
+    uint32_t* tile_count;
+} isogs_projected;
+
+/* Binned and sorted entries (device memory).
+ *   keys        [capacity]  (global tile id << 32) | bits(depth), ascending; ties in emit
+ *                           order (view, particle, row-major tile), i.e. a stable sort
+ *   emit_index  [capacity]  emit position of each sorted entry
+ *   pidx        [capacity]  packed particle index (into isogs_projected) of each entry
+ *   ranges      [T][2]      [start, end) of each global tile's entries; [0, 0) if empty
+ *   offsets     [N]         first emit position of each particle (exclusive scan of
+ *                           tile_count)
+ *   capacity    number of entries the three entry arrays can hold
+ *   count       [1]         written: total entries (even when it exceeds capacity)
+ *   status      [1]         written: ISOGS_OK, or ISOGS_ERR_CAPACITY when count > capacity
+ *                           (then every later call on these bins leaves its outputs
+ *                           untouched; re-run isogs_bin_sort with a larger capacity) */
+typedef struct {
+    uint64_t* keys;
+    uint32_t* emit_index;
+    uint32_t* pidx;
+    uint32_t* ranges;
+    uint32_t* offsets;
+    uint64_t capacity;
+    uint32_t* count;
+    int32_t* status;
+} isogs_bins;
+
+/* Projects every particle of every view (eq. 8 kernel as a circle of scale s = f sigma/z),
+ * evaluates its colour for the view direction and counts its member tiles.
+ *   scenes, cams  host arrays of V structs; out  packed over views (sum n_v records).
+ * Errors: ISOGS_ERR_INVALID for NULL arrays, V <= 0, n < 0, sh_degree outside 0..3,
+ * width/height <= 0, near_z <= 0, f <= 0, or a NULL buffer with n > 0. */
+int isogs_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
+                  const isogs_projected* out, void* stream);
+
+/* Bins the footprints into 16x16 tiles and sorts the (tile, depth) keys with a device
+ * LSD radix sort (stable), then fills tile ranges and per-entry particle indices.
+ *   n_per_view  host array [V]: particles of each view (the n of its scene)
+ *   ws, ws_bytes  workspace; with ws == NULL only *ws_bytes is written (the bytes needed
+ *                 for this capacity and these views), and nothing is launched.
+ * Errors: ISOGS_ERR_INVALID (bad arguments), ISOGS_ERR_WORKSPACE (ws too small),
+ * ISOGS_ERR_DEVICE; overflow of `capacity` is reported in *status on the device. */
+int isogs_bin_sort(const isogs_projected* proj, const int32_t* n_per_view,
+                   const isogs_camera* cams, int32_t n_views, const isogs_bins* bins,
+                   void* ws, size_t* ws_bytes, void* stream);
+
+/* Front-to-back compositing (eq. 4) of every pixel over its tile's sorted entries.
+ *   bg        host [3] background colour added as T_final * bg
+ *   image     [sum 3 H_v W_v]  planar per view: [V][3][H][W]
+ *   T_final   [sum H_v W_v]    transmittance left after the last composited entry
+ *   n_last    [sum H_v W_v]    1 + tile-list position of the last contributing entry
+ *                              (0 if none); the backward pass starts there
+ * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_DEVICE. */
+int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
+                     const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
+                     const float* bg, float* image, float* T_final, uint32_t* n_last,
+                     void* stream);
+
+/* Gradients of a scalar loss L with respect to the particle parameters, given dL/dimage.
+ * Walks each pixel's entries in reverse from n_last, recovering the transmittance before
+ * each entry as T / (1 - alpha) (no per-entry state is stored by the forward pass), and
+ * sums each entry's gradient over the tile's pixels with wavefront reductions in a fixed
+ * order (no floating-point atomics: results are bitwise reproducible).
+ *   scenes, cams   the same arrays as given to isogs_project
+ *   dL_dimage      [sum 3 H_v W_v], same layout as image
+ *   grads          host array [V] of output buffers in scene layout; views whose scene
+ *                  pointers (pos) are equal must pass equal grads entries: their
+ *                  gradients are summed in view order. Outputs are overwritten.
+ *   ws, ws_bytes   workspace (query with ws == NULL): 32 bytes per entry of capacity
+ * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
+int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
+                     const isogs_projected* proj, const isogs_bins* bins, const float* bg,
+                     const float* dL_dimage, const float* T_final, const uint32_t* n_last,
+                     const isogs_scene* grads, void* ws, size_t* ws_bytes, void* stream);
+
+/* Message describing the last error returned on the calling thread ("" if none). */
+const char* isogs_last_error(void);
+
+/* Library version string. */
+const char* isogs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISOGS_H */

@@ -1,0 +1,15 @@
+"""MI355X (gfx950) rasterizer for isotropic Gaussian splatting (arXiv 2403.14244).
+
+The hot path (projection, tile binning, radix sort, compositing and its backward) runs
+in hand-written HIP kernels behind the C ABI of include/isogs.h; this package is the
+thin binding. Importing it loads the in-tree library and fails if it is not built.
+"""
+from ._abi import lib as _lib, IsoGSError  # noqa: F401
+
+_lib()
+
+from .rasterizer import (GaussianScene, Footprints, TileBins, Rasterizer, IsoGSRender,  # noqa: E402,F401
+                         split_images, tiles_of)
+
+__all__ = ["GaussianScene", "Footprints", "TileBins", "Rasterizer", "IsoGSRender", "IsoGSError",
+           "split_images", "tiles_of"]

@@ -1,0 +1,113 @@
+"""ctypes declarations of the C ABI in include/isogs.h (argument marshalling only).
+
+The shared library is built in-tree (``paper_2403_14244_amd/libisogs.so``, see build.py);
+importing this module without it raises ImportError: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libisogs.so")
+
+ISOGS_OK = 0
+ISOGS_ERR_INVALID = -1
+ISOGS_ERR_CAPACITY = -2
+ISOGS_ERR_WORKSPACE = -3
+ISOGS_ERR_DEVICE = -4
+
+EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_bwd",
+            "isogs_last_error", "isogs_version")
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("opacity", ctypes.c_void_p),
+                ("color", ctypes.c_void_p), ("n", ctypes.c_int32), ("sh_degree", ctypes.c_int32)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("eye", ctypes.c_float * 3),
+                ("f", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("near_z", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Projected(ctypes.Structure):
+    _fields_ = [("footprint", ctypes.c_void_p), ("color_radius", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+                ("tile_count", ctypes.c_void_p)]
+
+
+class Bins(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("emit_index", ctypes.c_void_p), ("pidx", ctypes.c_void_p),
+                ("ranges", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("count", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class IsoGSError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"isogs error {code}: {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_14244_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.isogs_project.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), vp]
+        L.isogs_bin_sort.argtypes = [P(Projected), P(ctypes.c_int32), P(Camera), ctypes.c_int32, P(Bins), vp,
+                                     P(ctypes.c_size_t), vp]
+        L.isogs_render_fwd.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera), ctypes.c_int32,
+                                       P(ctypes.c_float), vp, vp, vp, vp]
+        L.isogs_render_bwd.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), P(Bins),
+                                       P(ctypes.c_float), vp, vp, vp, P(Scene), vp, P(ctypes.c_size_t), vp]
+        for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_bwd"):
+            getattr(L, name).restype = ctypes.c_int
+        L.isogs_last_error.restype = ctypes.c_char_p
+        L.isogs_last_error.argtypes = []
+        L.isogs_version.restype = ctypes.c_char_p
+        L.isogs_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != ISOGS_OK:
+        raise IsoGSError(rc, lib().isogs_last_error().decode())
+    return rc
+
+
+def camera_struct(cam) -> Camera:
+    """Any object with R (3x3), t, eye, f, cx, cy, width, height and optionally near."""
+    c = Camera()
+    R = [float(x) for row in cam.R for x in row]
+    c.R[:] = R
+    c.t[:] = [float(x) for x in cam.t]
+    c.eye[:] = [float(x) for x in cam.eye]
+    c.f = float(cam.f)
+    c.cx = float(cam.cx)
+    c.cy = float(cam.cy)
+    c.near_z = float(getattr(cam, "near", 0.2))
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    return c
+
+
+def camera_array(cams):
+    arr = (Camera * len(cams))()
+    for i, cam in enumerate(cams):
+        arr[i] = camera_struct(cam)
+    return arr
+
+
+def int_array(vals):
+    arr = (ctypes.c_int32 * len(vals))()
+    arr[:] = [int(v) for v in vals]
+    return arr

@@ -1,0 +1,213 @@
+// C ABI entry points: argument validation, workspace sizing and dispatch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "kernels.h"
+
+namespace {
+
+thread_local char g_error[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof(g_error), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int device_fail(const char* where) {
+    const hipError_t e = hipGetLastError();
+    return fail(ISOGS_ERR_DEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+constexpr int32_t kMaxBatchViews = 4096;
+
+int check_cameras(const isogs_camera* cams, int32_t nv) {
+    if (!cams) return fail(ISOGS_ERR_INVALID, "cams is NULL");
+    for (int v = 0; v < nv; ++v) {
+        const isogs_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 32768 || c.height > 32768)
+            return fail(ISOGS_ERR_INVALID, "view %d: image size %dx%d outside 1..32768", v, c.width, c.height);
+        if (!(c.f > 0.0f) || !isfinite(c.f))
+            return fail(ISOGS_ERR_INVALID, "view %d: focal length must be positive and finite", v);
+        if (!(c.near_z > 0.0f) || !isfinite(c.near_z))
+            return fail(ISOGS_ERR_INVALID, "view %d: near_z must be positive and finite", v);
+        bool ok = isfinite(c.cx) && isfinite(c.cy);
+        for (int k = 0; k < 9; ++k) ok = ok && isfinite(c.R[k]);
+        for (int k = 0; k < 3; ++k) ok = ok && isfinite(c.t[k]) && isfinite(c.eye[k]);
+        if (!ok) return fail(ISOGS_ERR_INVALID, "view %d: non-finite camera parameter", v);
+    }
+    return ISOGS_OK;
+}
+
+int check_views(int32_t nv) {
+    if (nv <= 0 || nv > kMaxBatchViews) return fail(ISOGS_ERR_INVALID, "n_views = %d outside 1..%d", nv, kMaxBatchViews);
+    return ISOGS_OK;
+}
+
+int check_totals(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv, uint64_t* n_total,
+                 uint64_t* tiles, uint64_t* pixels) {
+    uint64_t n = 0, t = 0, p = 0;
+    for (int v = 0; v < nv; ++v) {
+        if (n_per_view[v] < 0) return fail(ISOGS_ERR_INVALID, "view %d: negative particle count", v);
+        n += (uint64_t)n_per_view[v];
+        t += (uint64_t)((cams[v].width + 15) / 16) * (uint64_t)((cams[v].height + 15) / 16);
+        p += (uint64_t)cams[v].width * (uint64_t)cams[v].height;
+    }
+    if (n >= (1ull << 31)) return fail(ISOGS_ERR_INVALID, "total particles over all views must be < 2^31");
+    if (t >= (1ull << 31)) return fail(ISOGS_ERR_INVALID, "total tiles over all views must be < 2^31");
+    if (p >= (1ull << 32)) return fail(ISOGS_ERR_INVALID, "total pixels over all views must be < 2^32");
+    if (n_total) *n_total = n;
+    if (tiles) *tiles = t;
+    if (pixels) *pixels = p;
+    return ISOGS_OK;
+}
+
+int check_projected(const isogs_projected* p, uint64_t n) {
+    if (!p) return fail(ISOGS_ERR_INVALID, "projected is NULL");
+    if (n && (!p->footprint || !p->color_radius || !p->depth || !p->tile_count))
+        return fail(ISOGS_ERR_INVALID, "projected buffer is NULL");
+    if (((uintptr_t)p->footprint | (uintptr_t)p->color_radius) & 15)
+        return fail(ISOGS_ERR_INVALID, "footprint and color_radius must be 16-byte aligned");
+    return ISOGS_OK;
+}
+
+int check_bins(const isogs_bins* b, uint64_t n, uint64_t tiles) {
+    if (!b) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    if (!b->count || !b->status) return fail(ISOGS_ERR_INVALID, "bins count/status is NULL");
+    if (tiles && !b->ranges) return fail(ISOGS_ERR_INVALID, "bins ranges is NULL");
+    if (n && !b->offsets) return fail(ISOGS_ERR_INVALID, "bins offsets is NULL");
+    if (b->capacity && (!b->keys || !b->emit_index || !b->pidx))
+        return fail(ISOGS_ERR_INVALID, "bins entry arrays are NULL");
+    if (b->capacity >= (1ull << 30) - 1) return fail(ISOGS_ERR_INVALID, "bins capacity must be < 2^30 - 1");
+    return ISOGS_OK;
+}
+
+int check_scene(const isogs_scene& s, int v, bool grads) {
+    if (s.n < 0) return fail(ISOGS_ERR_INVALID, "%s %d: n < 0", grads ? "grads" : "scene", v);
+    if (s.sh_degree < 0 || s.sh_degree > ISOGS_MAX_SH_DEGREE)
+        return fail(ISOGS_ERR_INVALID, "%s %d: sh_degree %d outside 0..3", grads ? "grads" : "scene", v, s.sh_degree);
+    if (s.n > 0 && (!s.pos || !s.scale || !s.opacity || !s.color))
+        return fail(ISOGS_ERR_INVALID, "%s %d: NULL parameter buffer", grads ? "grads" : "scene", v);
+    return ISOGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* isogs_last_error(void) { return g_error; }
+
+const char* isogs_version(void) { return "isogs 0.1 gfx950"; }
+
+int isogs_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views, const isogs_projected* out,
+                  void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!scenes) return fail(ISOGS_ERR_INVALID, "scenes is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    int32_t npv[kMaxBatchViews];
+    for (int v = 0; v < n_views; ++v) {
+        if ((rc = check_scene(scenes[v], v, false))) return rc;
+        npv[v] = scenes[v].n;
+    }
+    uint64_t n;
+    if ((rc = check_totals(npv, cams, n_views, &n, nullptr, nullptr))) return rc;
+    if ((rc = check_projected(out, n))) return rc;
+    if (isogs::launch_project(scenes, cams, n_views, out, (hipStream_t)stream)) return device_fail("isogs_project");
+    return ISOGS_OK;
+}
+
+int isogs_bin_sort(const isogs_projected* proj, const int32_t* n_per_view, const isogs_camera* cams, int32_t n_views,
+                   const isogs_bins* bins, void* ws, size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    uint64_t n, tiles;
+    if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    const isogs::BinSortPlan plan = isogs::plan_bin_sort(n_per_view, cams, n_views, bins->capacity);
+    if (!ws) {
+        *ws_bytes = plan.bytes;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < plan.bytes)
+        return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, plan.bytes);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if ((rc = check_projected(proj, n))) return rc;
+    if ((rc = check_bins(bins, n, tiles))) return rc;
+    if (isogs::launch_bin_sort(plan, proj, n_per_view, cams, n_views, bins, ws, (hipStream_t)stream))
+        return device_fail("isogs_bin_sort");
+    return ISOGS_OK;
+}
+
+int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                     const isogs_camera* cams, int32_t n_views, const float* bg, float* image, float* T_final,
+                     uint32_t* n_last, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
+    if (!bg) return fail(ISOGS_ERR_INVALID, "bg is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    uint64_t n, tiles;
+    if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
+    if ((rc = check_projected(proj, n))) return rc;
+    if ((rc = check_bins(bins, n, tiles))) return rc;
+    if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (isogs::launch_render_fwd(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
+                                 (hipStream_t)stream))
+        return device_fail("isogs_render_fwd");
+    return ISOGS_OK;
+}
+
+int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
+                     const isogs_projected* proj, const isogs_bins* bins, const float* bg, const float* dL_dimage,
+                     const float* T_final, const uint32_t* n_last, const isogs_scene* grads, void* ws,
+                     size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!scenes || !grads) return fail(ISOGS_ERR_INVALID, "scenes or grads is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    const size_t need = (size_t)bins->capacity * 32 + 256;
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    int32_t npv[kMaxBatchViews];
+    for (int v = 0; v < n_views; ++v) {
+        if ((rc = check_scene(scenes[v], v, false))) return rc;
+        if ((rc = check_scene(grads[v], v, true))) return rc;
+        if (grads[v].n != scenes[v].n || grads[v].sh_degree != scenes[v].sh_degree)
+            return fail(ISOGS_ERR_INVALID, "view %d: grads must match the scene's n and sh_degree", v);
+        npv[v] = scenes[v].n;
+    }
+    for (int v = 0; v < n_views; ++v)
+        for (int u = 0; u < v; ++u)
+            if (scenes[u].pos == scenes[v].pos &&
+                (grads[u].pos != grads[v].pos || scenes[u].n != scenes[v].n ||
+                 scenes[u].sh_degree != scenes[v].sh_degree || scenes[u].color != scenes[v].color))
+                return fail(ISOGS_ERR_INVALID, "views %d and %d share a scene but not its grads buffers", u, v);
+    uint64_t n, tiles;
+    if ((rc = check_totals(npv, cams, n_views, &n, &tiles, nullptr))) return rc;
+    if ((rc = check_projected(proj, n))) return rc;
+    if ((rc = check_bins(bins, n, tiles))) return rc;
+    if (!bg || !dL_dimage || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "input buffer is NULL");
+    if (isogs::launch_render_bwd(scenes, cams, n_views, proj, bins, bg, dL_dimage, T_final, n_last, grads, ws,
+                                 (hipStream_t)stream))
+        return device_fail("isogs_render_bwd");
+    return ISOGS_OK;
+}
+
+}  // extern "C"

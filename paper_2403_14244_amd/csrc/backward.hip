@@ -1,0 +1,385 @@
+// Backward pass: gradients of a loss through compositing (eq. 4), the isotropic kernel
+// (eq. 8), the projection and the spherical-harmonic colour.
+//
+//   1. composite_bwd  per tile: walk each pixel's entries in reverse from n_last,
+//                     recovering T before each entry as T_after / (1 - alpha); reduce each
+//                     entry's screen-space gradient over the tile's pixels (wavefront DPP
+//                     sums, then the four waves in fixed order) into one record per entry,
+//                     stored at the entry's emit position.
+//   2. grad_project   per particle: sum its records (consecutive in emit order, views in
+//                     order) and chain them to mu, sigma, o and the colour coefficients.
+// There are no floating-point atomics: every sum has a fixed order.
+#include "raster.h"
+
+namespace isogs {
+
+// One workgroup per tile. Record of an entry: {du, dv, d(1/s^2), do} {dr, dg, db, 0}.
+__global__ void __launch_bounds__(256) composite_bwd_kernel(
+    const RenderPack pk, const float4* __restrict__ footprint, const float4* __restrict__ color_radius,
+    const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ emit_index,
+    const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
+    const float* __restrict__ dL_dimage, const float* __restrict__ T_final, const uint32_t* __restrict__ n_last,
+    float4* __restrict__ rec) {
+    __shared__ StagedBatch sb;
+    __shared__ float s_part[4][7][kBatch];
+    __shared__ uint32_t s_max_last;
+    if (*status != kStatusOk) return;
+    int vi, tx, ty;
+    locate_tile(pk, xcd_swizzle(blockIdx.x, gridDim.x), vi, tx, ty);
+    const ViewDesc& vd = pk.v[vi];
+    const uint32_t t = threadIdx.x, w = t >> 6;
+    const int x = tx * kTile + (int)(t & 15), y = ty * kTile + (int)(t >> 4);
+    const bool inside = x < vd.width && y < vd.height;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
+    const uint32_t start = ranges[2 * gt], end = min(ranges[2 * gt + 1], pk.n_entries_cap);
+    const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
+
+    float T = 1.0f, dr = 0.0f, dg = 0.0f, db = 0.0f;
+    uint32_t last = 0;
+    if (inside) {
+        const size_t hw = (size_t)vd.width * vd.height;
+        const size_t pix = (size_t)y * vd.width + x;
+        const float* dimg = dL_dimage + (size_t)3 * vd.pix_off;
+        dr = dimg[pix];
+        dg = dimg[hw + pix];
+        db = dimg[2 * hw + pix];
+        T = T_final[vd.pix_off + pix];
+        last = n_last[vd.pix_off + pix];
+    }
+    // light arriving from behind the current entry: sum of later c alpha T, plus T_final bg
+    float Sr = T * bg_r, Sg = T * bg_g, Sb = T * bg_b;
+
+    if (t == 0) s_max_last = 0u;
+    __syncthreads();
+    if (last) atomicMax(&s_max_last, last);
+    __syncthreads();
+    const uint32_t max_last = s_max_last;
+    // entries no pixel reached carry zero gradient
+    for (uint32_t e = start + max_last + t; e < end; e += 256) {
+        const uint32_t slot = emit_index[e];
+        if (slot >= pk.n_entries_cap) continue;
+        rec[2 * (size_t)slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        rec[2 * (size_t)slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+
+    for (uint32_t hi = start + max_last; hi > start;) {
+        const uint32_t lo = hi - min((uint32_t)kBatch, hi - start);
+        const uint32_t nb = hi - lo;
+        const uint32_t n_mine = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, lo, nb, true,
+                                            tx * kTile, ty * kTile, w_lim, h_lim);
+        // staged index j holds list position lo + nb - 1 - j (0-based within the tile: - start)
+        for (uint32_t k = 0; k < n_mine; ++k) {
+            const uint32_t j = __builtin_amdgcn_readfirstlane(sb.list[w][k]);
+            const uint32_t pos1 = lo + nb - j - start;   // 1-based list position
+            float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            bool hit = false;
+            if (pos1 <= last) {
+                const float4 f = sb.fp[j];
+                const float dx = px - f.x, dy = py - f.y;
+                float G;
+                const float a = entry_alpha(dx, dy, f.z, f.w, G);
+                if (a >= kAlphaMin) {
+                    hit = true;
+                    const float4 c = sb.col[j];
+                    const float om = 1.0f - a;
+                    const float inv_om = 1.0f / om;
+                    T = T * inv_om;                      // transmittance before this entry
+                    const float wgt = a * T;
+                    g[4] = dr * wgt;
+                    g[5] = dg * wgt;
+                    g[6] = db * wgt;
+                    const float dLda = dr * (c.x * T - Sr * inv_om) + dg * (c.y * T - Sg * inv_om) +
+                                       db * (c.z * T - Sb * inv_om);
+                    Sr = fmaf(c.x, wgt, Sr);
+                    Sg = fmaf(c.y, wgt, Sg);
+                    Sb = fmaf(c.z, wgt, Sb);
+                    if (f.w * G < kAlphaMax) {
+                        const float inv_s2 = f.z * (1.0f / kLog2e);
+                        const float dLdG = dLda * f.w;
+                        const float k2 = 2.0f * dLdG * G * inv_s2;
+                        g[0] = k2 * dx;
+                        g[1] = k2 * dy;
+                        g[2] = -dLdG * G * fmaf(dx, dx, dy * dy);
+                        g[3] = dLda * G;
+                    }
+                }
+            }
+            if (ballot64(hit) != 0) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) g[q] = wave_sum(g[q]);
+            }
+            if (lane_id() == 0) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) s_part[w][q][j] = g[q];
+            }
+        }
+        __syncthreads();
+        if (t < nb) {
+            const uint32_t m = sb.mask[t];
+            float s[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            for (int ww = 0; ww < 4; ++ww) {
+                if ((m >> ww) & 1u) {
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) s[q] += s_part[ww][q][t];
+                }
+            }
+            const uint32_t slot = emit_index[lo + nb - 1 - t];
+            if (slot < pk.n_entries_cap) {
+                rec[2 * (size_t)slot] = make_float4(s[0], s[1], s[2], s[3]);
+                rec[2 * (size_t)slot + 1] = make_float4(s[4], s[5], s[6], 0.0f);
+            }
+        }
+        __syncthreads();
+        hi = lo;
+    }
+}
+
+// Gradient of each real SH basis polynomial (the forms used in the forward colour
+// evaluation) at direction (x, y, z); the tangential projection happens in the caller.
+__device__ __forceinline__ void sh_eval_grad(int deg, float x, float y, float z, float Y[16], float gx[16],
+                                             float gy[16], float gz[16]) {
+    constexpr float c1 = 0.48860251190291992f, c2a = 1.09254843059207907f, c2b = 0.31539156525252005f,
+                    c2c = 0.54627421529603959f, c3a = 0.59004358992664352f, c3b = 2.89061144264055405f,
+                    c3c = 0.45704579946446573f, c3d = 0.37317633259011540f, c3e = 1.44530572132027702f;
+    for (int k = 0; k < 16; ++k) Y[k] = gx[k] = gy[k] = gz[k] = 0.0f;
+    Y[0] = 1.0f;
+    if (deg < 1) return;
+    Y[1] = c1 * y; gy[1] = c1;
+    Y[2] = c1 * z; gz[2] = c1;
+    Y[3] = c1 * x; gx[3] = c1;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = c2a * x * y; gx[4] = c2a * y; gy[4] = c2a * x;
+    Y[5] = c2a * y * z; gy[5] = c2a * z; gz[5] = c2a * y;
+    Y[6] = c2b * (3.0f * zz - 1.0f); gz[6] = 6.0f * c2b * z;
+    Y[7] = c2a * x * z; gx[7] = c2a * z; gz[7] = c2a * x;
+    Y[8] = c2c * (xx - yy); gx[8] = 2.0f * c2c * x; gy[8] = -2.0f * c2c * y;
+    if (deg < 3) return;
+    Y[9] = c3a * y * (3.0f * xx - yy); gx[9] = 6.0f * c3a * x * y; gy[9] = 3.0f * c3a * (xx - yy);
+    Y[10] = c3b * x * y * z; gx[10] = c3b * y * z; gy[10] = c3b * x * z; gz[10] = c3b * x * y;
+    Y[11] = c3c * y * (5.0f * zz - 1.0f); gy[11] = c3c * (5.0f * zz - 1.0f); gz[11] = 10.0f * c3c * y * z;
+    Y[12] = c3d * z * (5.0f * zz - 3.0f); gz[12] = c3d * (15.0f * zz - 3.0f);
+    Y[13] = c3c * x * (5.0f * zz - 1.0f); gx[13] = c3c * (5.0f * zz - 1.0f); gz[13] = 10.0f * c3c * x * z;
+    Y[14] = c3e * z * (xx - yy); gx[14] = 2.0f * c3e * x * z; gy[14] = -2.0f * c3e * y * z; gz[14] = c3e * (xx - yy);
+    Y[15] = c3a * x * (xx - 3.0f * yy); gx[15] = 3.0f * c3a * (xx - yy); gy[15] = -6.0f * c3a * x * y;
+}
+
+struct GradView {
+    uint32_t p_off;
+    float R[9], t[3], eye[3], f, cx, cy;
+};
+
+struct GradPack {
+    int32_t nv;            // views of this scene in this launch, in view order
+    int32_t accumulate;    // add to the outputs (a previous launch covered earlier views)
+    const float* pos;
+    const float* scale;
+    const float* opacity;
+    const float* color;
+    uint32_t n;
+    int32_t sh_degree;
+    float* g_pos;
+    float* g_scale;
+    float* g_opacity;
+    float* g_color;
+    GradView v[kMaxViews];
+};
+
+// One thread per particle of one scene; DEG is the scene's SH degree.
+template <int DEG>
+__global__ void __launch_bounds__(256) grad_project_kernel(const GradPack pk, const float4* __restrict__ rec,
+                                                           const uint32_t* __restrict__ tile_count,
+                                                           const uint32_t* __restrict__ offsets,
+                                                           const uint32_t* __restrict__ count_p,
+                                                           const int32_t* __restrict__ status) {
+    if (*status != kStatusOk) return;
+    const uint32_t n_entries = *count_p;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pk.n) return;
+    const uint32_t n = pk.n;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const float mx = pk.pos[i], my = pk.pos[n + i], mz = pk.pos[2 * n + i];
+    const float sigma = pk.scale[i];
+
+    float gmx = 0.0f, gmy = 0.0f, gmz = 0.0f, gsig = 0.0f, gop = 0.0f;
+    float gcol[3 * K];
+    float coef[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) {
+        gcol[k] = 0.0f;
+        coef[k] = pk.color[(size_t)k * n + i];
+    }
+
+    for (int vv = 0; vv < pk.nv; ++vv) {
+        const GradView& gv = pk.v[vv];
+        const uint32_t pi = gv.p_off + i;
+        const uint32_t cnt = tile_count[pi];
+        if (cnt == 0) continue;
+        const uint32_t e0 = offsets[pi];
+        if ((uint64_t)e0 + cnt > n_entries) continue;
+        float du = 0.0f, dv = 0.0f, dis2 = 0.0f, dop = 0.0f, drgb[3] = {0.0f, 0.0f, 0.0f};
+        for (uint32_t e = e0; e < e0 + cnt; ++e) {
+            const float4 a = rec[2 * (size_t)e];
+            const float4 b = rec[2 * (size_t)e + 1];
+            du += a.x;
+            dv += a.y;
+            dis2 += a.z;
+            dop += a.w;
+            drgb[0] += b.x;
+            drgb[1] += b.y;
+            drgb[2] += b.z;
+        }
+        gop += dop;
+        // projection: p = R mu + t, u = f p_x/z + cx, v = f p_y/z + cy, s = f sigma/z, 1/s^2
+        const double pxd = (double)gv.R[0] * mx + (double)gv.R[1] * my + (double)gv.R[2] * mz + (double)gv.t[0];
+        const double pyd = (double)gv.R[3] * mx + (double)gv.R[4] * my + (double)gv.R[5] * mz + (double)gv.t[1];
+        const double pzd = (double)gv.R[6] * mx + (double)gv.R[7] * my + (double)gv.R[8] * mz + (double)gv.t[2];
+        const float inv_z = (float)(1.0 / pzd);
+        const float s = (float)((double)gv.f * (double)sigma / pzd);
+        const float inv_s = 1.0f / s;
+        // d(1/s^2)/ds = -2/s^3
+        const float ds = -2.0f * dis2 * inv_s * inv_s * inv_s;
+        gsig += ds * gv.f * inv_z;
+        const float gpx = du * gv.f * inv_z, gpy = dv * gv.f * inv_z;
+        const float ucx = (float)((double)gv.f * pxd / pzd), vcy = (float)((double)gv.f * pyd / pzd);
+        const float gpz = -(ds * s + du * ucx + dv * vcy) * inv_z;
+        gmx += gv.R[0] * gpx + gv.R[3] * gpy + gv.R[6] * gpz;
+        gmy += gv.R[1] * gpx + gv.R[4] * gpy + gv.R[7] * gpz;
+        gmz += gv.R[2] * gpx + gv.R[5] * gpy + gv.R[8] * gpz;
+        // colour: rgb = max(0, c_0 + sum_k c_k Y_k(d)), d = (mu - eye)/|mu - eye|
+        const float ex = mx - gv.eye[0], ey = my - gv.eye[1], ez = mz - gv.eye[2];
+        const float inv_dist = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+        const float dxn = ex * inv_dist, dyn = ey * inv_dist, dzn = ez * inv_dist;
+        float Y[16], gx[16], gy[16], gz[16];
+        sh_eval_grad(DEG, dxn, dyn, dzn, Y, gx, gy, gz);
+        float wdx = 0.0f, wdy = 0.0f, wdz = 0.0f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float raw = coef[ch];
+#pragma unroll
+            for (int k = 1; k < K; ++k) raw = fmaf(coef[3 * k + ch], Y[k], raw);
+            const float d = (raw > 0.0f) ? drgb[ch] : 0.0f;
+            gcol[ch] += d;
+#pragma unroll
+            for (int k = 1; k < K; ++k) {
+                gcol[3 * k + ch] += d * Y[k];
+                const float wk = d * coef[3 * k + ch];
+                wdx = fmaf(wk, gx[k], wdx);
+                wdy = fmaf(wk, gy[k], wdy);
+                wdz = fmaf(wk, gz[k], wdz);
+            }
+        }
+        const float radial = wdx * dxn + wdy * dyn + wdz * dzn;
+        gmx += (wdx - radial * dxn) * inv_dist;
+        gmy += (wdy - radial * dyn) * inv_dist;
+        gmz += (wdz - radial * dzn) * inv_dist;
+    }
+    if (pk.accumulate) {
+        pk.g_pos[i] += gmx;
+        pk.g_pos[n + i] += gmy;
+        pk.g_pos[2 * n + i] += gmz;
+        pk.g_scale[i] += gsig;
+        pk.g_opacity[i] += gop;
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) pk.g_color[(size_t)k * n + i] += gcol[k];
+    } else {
+        pk.g_pos[i] = gmx;
+        pk.g_pos[n + i] = gmy;
+        pk.g_pos[2 * n + i] = gmz;
+        pk.g_scale[i] = gsig;
+        pk.g_opacity[i] = gop;
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) pk.g_color[(size_t)k * n + i] = gcol[k];
+    }
+}
+
+int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
+                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,
+                      const float* dL_dimage, const float* T_final, const uint32_t* n_last,
+                      const isogs_scene* grads, void* ws, hipStream_t stream) {
+    float4* rec = static_cast<float4*>(ws);
+    int32_t n_per_view[kMaxViews];
+    int32_t n_all[4096];
+    if (nv > 4096) return -1;
+    for (int v = 0; v < nv; ++v) n_all[v] = scenes[v].n;
+    // 1. per-tile reverse compositing
+    uint32_t p_off = 0, tile_base = 0, pix_off = 0;
+    for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
+        const int m = min(kMaxViews, nv - v0);
+        for (int j = 0; j < m; ++j) n_per_view[j] = scenes[v0 + j].n;
+        RenderPack pk{};
+        uint32_t blocks;
+        fill_render_pack(pk, cams + v0, n_per_view, 0, m, p_off, tile_base, pix_off, blocks);
+        set_render_limits(pk, n_all, nv, bins->capacity);
+        if (!blocks) continue;
+        hipLaunchKernelGGL(composite_bwd_kernel, dim3(blocks), dim3(256), 0, stream, pk,
+                           reinterpret_cast<const float4*>(proj->footprint),
+                           reinterpret_cast<const float4*>(proj->color_radius), bins->pidx, bins->emit_index,
+                           bins->ranges, bins->status, bg[0], bg[1], bg[2], dL_dimage, T_final, n_last, rec);
+        if (hipPeekAtLastError() != hipSuccess) return -1;
+    }
+    // 2. per scene: reduce records over its views (in view order) and chain to parameters
+    uint32_t view_off[4096];
+    if (nv > 4096) return -1;
+    {
+        uint32_t o = 0;
+        for (int v = 0; v < nv; ++v) {
+            view_off[v] = o;
+            o += (uint32_t)scenes[v].n;
+        }
+    }
+    bool handled[4096] = {false};
+    for (int v = 0; v < nv; ++v) {
+        if (handled[v]) continue;
+        const isogs_scene& sc = scenes[v];
+        int pending[4096];
+        int np = 0;
+        for (int u = v; u < nv; ++u)
+            if (!handled[u] && scenes[u].pos == sc.pos) {
+                handled[u] = true;
+                pending[np++] = u;
+            }
+        const isogs_scene& gs = grads[v];
+        for (int b0 = 0; b0 < np; b0 += kMaxViews) {
+            GradPack gp{};
+            gp.nv = min(kMaxViews, np - b0);
+            gp.accumulate = b0 > 0;
+            gp.pos = sc.pos;
+            gp.scale = sc.scale;
+            gp.opacity = sc.opacity;
+            gp.color = sc.color;
+            gp.n = (uint32_t)sc.n;
+            gp.sh_degree = sc.sh_degree;
+            gp.g_pos = const_cast<float*>(gs.pos);
+            gp.g_scale = const_cast<float*>(gs.scale);
+            gp.g_opacity = const_cast<float*>(gs.opacity);
+            gp.g_color = const_cast<float*>(gs.color);
+            for (int j = 0; j < gp.nv; ++j) {
+                const int u = pending[b0 + j];
+                const isogs_camera& c = cams[u];
+                GradView& g = gp.v[j];
+                g.p_off = view_off[u];
+                for (int k = 0; k < 9; ++k) g.R[k] = c.R[k];
+                for (int k = 0; k < 3; ++k) g.t[k] = c.t[k], g.eye[k] = c.eye[k];
+                g.f = c.f;
+                g.cx = c.cx;
+                g.cy = c.cy;
+            }
+            if (sc.n > 0) {
+                const dim3 grid((sc.n + 255) / 256);
+                const float4* r = rec;
+                switch (sc.sh_degree) {
+                    case 0: hipLaunchKernelGGL(grad_project_kernel<0>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                    case 1: hipLaunchKernelGGL(grad_project_kernel<1>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                    case 2: hipLaunchKernelGGL(grad_project_kernel<2>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                    default: hipLaunchKernelGGL(grad_project_kernel<3>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                }
+            }
+            if (hipPeekAtLastError() != hipSuccess) return -1;
+        }
+    }
+    return 0;
+}
+
+}  // namespace isogs

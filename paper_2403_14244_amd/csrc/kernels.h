@@ -1,0 +1,39 @@
+// Launchers of the device kernels, called by the C ABI layer (abi.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/isogs.h"
+
+namespace isogs {
+
+int launch_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv, const isogs_projected* out,
+                   hipStream_t stream);
+
+// Workspace layout of isogs_bin_sort for a given capacity and batch.
+struct BinSortPlan {
+    uint64_t capacity;
+    uint32_t n_total;       // packed particles over all views
+    uint32_t tiles_total;   // global tiles over all views
+    int passes;             // radix passes (8-bit digits) over the compacted key
+    uint32_t sort_tiles;    // 4096-entry sort tiles for `capacity`
+    uint32_t scan_blocks;   // 2048-particle scan blocks
+    size_t off_keys_alt, off_vals_alt, off_pidx_emit, off_hist, off_tickets, off_lookback, off_block_sums,
+        off_flags, bytes;
+};
+
+BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv, uint64_t capacity);
+
+int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const int32_t* n_per_view,
+                    const isogs_camera* cams, int32_t nv, const isogs_bins* bins, void* ws, hipStream_t stream);
+
+int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                      const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
+                      uint32_t* n_last, hipStream_t stream);
+
+int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
+                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,
+                      const float* dL_dimage, const float* T_final, const uint32_t* n_last,
+                      const isogs_scene* grads, void* ws, hipStream_t stream);
+
+}  // namespace isogs

@@ -1,0 +1,272 @@
+"""Torch-facing binding of the isotropic-splatting rasterizer.
+
+PyTorch supplies device memory and the current HIP stream; every step of the pipeline
+runs in the library's HIP kernels (see include/isogs.h for the contract of each call).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+_F32 = torch.float32
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def sh_count(deg: int) -> int:
+    return (deg + 1) ** 2
+
+
+@dataclass
+class GaussianScene:
+    """Particle parameters on the device (FP32, structure of arrays).
+
+    pos [3, N], scale [N] (sigma, linear), opacity [N] (activated), color [3K, N]."""
+    pos: torch.Tensor
+    scale: torch.Tensor
+    opacity: torch.Tensor
+    color: torch.Tensor
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.scale.shape[0])
+
+    @staticmethod
+    def from_host(scene, device="cuda") -> "GaussianScene":
+        """From any object with numpy pos/scale/opacity/color/sh_degree (e.g. scenegen.Scene)."""
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        return GaussianScene(t(scene.pos), t(scene.scale), t(scene.opacity), t(scene.color), int(scene.sh_degree))
+
+    def validate(self):
+        n = self.n
+        K = sh_count(self.sh_degree)
+        for name, x, shape in (("pos", self.pos, (3, n)), ("scale", self.scale, (n,)),
+                               ("opacity", self.opacity, (n,)), ("color", self.color, (3 * K, n))):
+            if tuple(x.shape) != shape or x.dtype != _F32 or not x.is_contiguous() or not x.is_cuda:
+                raise ValueError(f"scene.{name}: need a contiguous CUDA float32 tensor of shape {shape}")
+
+    def abi(self) -> A.Scene:
+        s = A.Scene()
+        s.pos, s.scale, s.opacity, s.color = _p(self.pos), _p(self.scale), _p(self.opacity), _p(self.color)
+        s.n = self.n
+        s.sh_degree = self.sh_degree
+        return s
+
+    def zeros_like(self) -> "GaussianScene":
+        return GaussianScene(torch.zeros_like(self.pos), torch.zeros_like(self.scale),
+                             torch.zeros_like(self.opacity), torch.zeros_like(self.color), self.sh_degree)
+
+
+@dataclass
+class Footprints:
+    """Output of project: per (view, particle) records packed over views."""
+    footprint: torch.Tensor      # [N, 4] {u, v, 1/s^2, o}
+    color_radius: torch.Tensor   # [N, 4] {r, g, b, radius}
+    depth: torch.Tensor          # [N]
+    tile_count: torch.Tensor     # [N] int32 (uint32 on the device)
+
+    def abi(self) -> A.Projected:
+        p = A.Projected()
+        p.footprint, p.color_radius = _p(self.footprint), _p(self.color_radius)
+        p.depth, p.tile_count = _p(self.depth), _p(self.tile_count)
+        return p
+
+    @staticmethod
+    def empty(n, device="cuda") -> "Footprints":
+        return Footprints(torch.empty((n, 4), dtype=_F32, device=device), torch.empty((n, 4), dtype=_F32, device=device),
+                          torch.empty(n, dtype=_F32, device=device), torch.empty(n, dtype=torch.int32, device=device))
+
+
+@dataclass
+class TileBins:
+    """Output of bin_sort. Entry arrays hold `capacity` slots; `count` and `status` live
+    on the device."""
+    keys: torch.Tensor           # [capacity] int64 (uint64 on the device)
+    emit_index: torch.Tensor     # [capacity] int32
+    pidx: torch.Tensor           # [capacity] int32
+    ranges: torch.Tensor         # [T, 2] int32
+    offsets: torch.Tensor        # [N] int32
+    count: torch.Tensor          # [1] int32
+    status: torch.Tensor         # [1] int32
+    capacity: int
+
+    def abi(self) -> A.Bins:
+        b = A.Bins()
+        b.keys, b.emit_index, b.pidx = _p(self.keys), _p(self.emit_index), _p(self.pidx)
+        b.ranges, b.offsets = _p(self.ranges), _p(self.offsets)
+        b.capacity = self.capacity
+        b.count, b.status = _p(self.count), _p(self.status)
+        return b
+
+    def n_entries(self) -> int:
+        return int(self.count.item())
+
+    def verify(self):
+        st = int(self.status.item())
+        if st != A.ISOGS_OK:
+            raise A.IsoGSError(st, f"bin_sort status {st} (entries {self.n_entries()}, capacity {self.capacity})")
+
+
+def tiles_of(cam) -> int:
+    return ((int(cam.width) + 15) // 16) * ((int(cam.height) + 15) // 16)
+
+
+def _alloc_bins(capacity, n_total, tiles_total, device) -> TileBins:
+    cap = max(int(capacity), 1)
+    return TileBins(keys=torch.empty(cap, dtype=torch.int64, device=device),
+                    emit_index=torch.empty(cap, dtype=torch.int32, device=device),
+                    pidx=torch.empty(cap, dtype=torch.int32, device=device),
+                    ranges=torch.empty((tiles_total, 2), dtype=torch.int32, device=device),
+                    offsets=torch.empty(max(n_total, 1), dtype=torch.int32, device=device)[:n_total],
+                    count=torch.zeros(1, dtype=torch.int32, device=device),
+                    status=torch.zeros(1, dtype=torch.int32, device=device), capacity=cap)
+
+
+class Rasterizer:
+    """Runs project -> bin_sort -> render_fwd (and render_bwd) through the C ABI, keeping
+    workspaces and the entry capacity between calls. The capacity grows on demand: when a
+    bin_sort reports overflow it is re-run once with the exact count plus headroom."""
+
+    def __init__(self, device="cuda", headroom=1.25):
+        self.device = torch.device(device)
+        self.headroom = headroom
+        self.capacity = 0
+        self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    def _workspace(self, nbytes):
+        if self._ws.numel() < nbytes:
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    # -- the four ABI calls -----------------------------------------------------------
+    def project(self, scenes, cams) -> Footprints:
+        n_total = sum(s.n for s in scenes)
+        fp = Footprints.empty(n_total, self.device)
+        sc = (A.Scene * len(scenes))(*[s.abi() for s in scenes])
+        A.check(A.lib().isogs_project(sc, A.camera_array(cams), len(cams), ctypes.byref(fp.abi()), _stream()))
+        return fp
+
+    def bin_sort(self, fp: Footprints, n_per_view, cams, check=True, capacity=None) -> TileBins:
+        npv = A.int_array(n_per_view)
+        carr = A.camera_array(cams)
+        n_total = int(sum(n_per_view))
+        tiles_total = sum(tiles_of(c) for c in cams)
+        cap = self.capacity if capacity is None else capacity
+        for _ in range(2):
+            bins = _alloc_bins(cap, n_total, tiles_total, self.device)
+            ab = bins.abi()
+            need = ctypes.c_size_t(0)
+            A.check(A.lib().isogs_bin_sort(ctypes.byref(fp.abi()), npv, carr, len(cams), ctypes.byref(ab), None,
+                                           ctypes.byref(need), _stream()))
+            ws = self._workspace(need.value)
+            have = ctypes.c_size_t(ws.numel())
+            A.check(A.lib().isogs_bin_sort(ctypes.byref(fp.abi()), npv, carr, len(cams), ctypes.byref(ab),
+                                           _p(ws), ctypes.byref(have), _stream()))
+            if not check:
+                return bins
+            st = int(bins.status.item())
+            if st == A.ISOGS_OK:
+                return bins
+            if st != A.ISOGS_ERR_CAPACITY:
+                raise A.IsoGSError(st, "bin_sort failed on the device")
+            cap = int(bins.n_entries() * self.headroom) + 4096
+            if capacity is None:
+                self.capacity = cap
+        raise A.IsoGSError(A.ISOGS_ERR_CAPACITY, "bin_sort capacity still too small after growing")
+
+    def render_fwd(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0)):
+        pix = sum(int(c.width) * int(c.height) for c in cams)
+        image = torch.empty(3 * pix, dtype=_F32, device=self.device)
+        T = torch.empty(pix, dtype=_F32, device=self.device)
+        n_last = torch.empty(pix, dtype=torch.int32, device=self.device)
+        bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
+        A.check(A.lib().isogs_render_fwd(ctypes.byref(fp.abi()), A.int_array(n_per_view), ctypes.byref(bins.abi()),
+                                         A.camera_array(cams), len(cams), bgc, _p(image), _p(T), _p(n_last),
+                                         _stream()))
+        return image, T, n_last
+
+    def render_bwd(self, scenes, cams, fp: Footprints, bins: TileBins, bg, dL_dimage, T_final, n_last, grads=None):
+        """Returns one GaussianScene of gradients per distinct scene (by pos pointer), in
+        order of first appearance; views of one scene are summed."""
+        if grads is None:
+            uniq = {}
+            for s in scenes:
+                if s.pos.data_ptr() not in uniq:
+                    uniq[s.pos.data_ptr()] = s.zeros_like()
+            grads = [uniq[s.pos.data_ptr()] for s in scenes]
+        sc = (A.Scene * len(scenes))(*[s.abi() for s in scenes])
+        gs = (A.Scene * len(scenes))(*[g.abi() for g in grads])
+        bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
+        need = ctypes.c_size_t(0)
+        ab = bins.abi()
+        args = (sc, A.camera_array(cams), len(cams), ctypes.byref(fp.abi()), ctypes.byref(ab), bgc,
+                _p(dL_dimage.contiguous()), _p(T_final), _p(n_last), gs)
+        A.check(A.lib().isogs_render_bwd(*args, None, ctypes.byref(need), _stream()))
+        ws = self._workspace(need.value)
+        have = ctypes.c_size_t(ws.numel())
+        A.check(A.lib().isogs_render_bwd(*args, _p(ws), ctypes.byref(have), _stream()))
+        out, seen = [], set()
+        for g in grads:
+            if g.pos.data_ptr() not in seen:
+                seen.add(g.pos.data_ptr())
+                out.append(g)
+        return out
+
+    # -- convenience ------------------------------------------------------------------
+    def render(self, scenes, cams, bg=(0.0, 0.0, 0.0), check=True):
+        """Full forward pass. Returns (list of [3, H, W] images, state for backward)."""
+        fp = self.project(scenes, cams)
+        npv = [s.n for s in scenes]
+        bins = self.bin_sort(fp, npv, cams, check=check)
+        image, T, n_last = self.render_fwd(fp, npv, bins, cams, bg)
+        return split_images(image, cams), dict(fp=fp, bins=bins, image=image, T=T, n_last=n_last, npv=npv)
+
+
+def split_images(flat, cams):
+    out, off = [], 0
+    for c in cams:
+        h, w = int(c.height), int(c.width)
+        out.append(flat[off:off + 3 * h * w].view(3, h, w))
+        off += 3 * h * w
+    return out
+
+
+class IsoGSRender(torch.autograd.Function):
+    """Differentiable render of one scene from V cameras of equal size.
+
+    forward(pos, scale, opacity, color, sh_degree, cams, bg, rasterizer) -> [V, 3, H, W].
+    Parameters are the activated values (sigma > 0, o in (0, 1)); gradients flow to all
+    four parameter tensors; views are summed in order by the library."""
+
+    @staticmethod
+    def forward(ctx, pos, scale, opacity, color, sh_degree, cams, bg, rasterizer):
+        scene = GaussianScene(pos.contiguous(), scale.contiguous(), opacity.contiguous(), color.contiguous(),
+                              int(sh_degree))
+        scenes = [scene] * len(cams)
+        images, st = rasterizer.render(scenes, cams, bg, check=True)
+        ctx.rasterizer = rasterizer
+        ctx.cams = cams
+        ctx.bg = bg
+        ctx.scene = scene
+        ctx.st = st
+        return torch.stack(images)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        st = ctx.st
+        scenes = [ctx.scene] * len(ctx.cams)
+        g = ctx.rasterizer.render_bwd(scenes, ctx.cams, st["fp"], st["bins"], ctx.bg,
+                                      grad_out.contiguous().reshape(-1), st["T"], st["n_last"])[0]
+        return g.pos, g.scale, g.opacity, g.color, None, None, None, None

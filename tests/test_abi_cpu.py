@@ -1,0 +1,130 @@
+"""Host-side checks of the C ABI: the library loads, exports what include/isogs.h
+declares, and rejects invalid arguments before touching a device. No GPU needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "isogs.h")
+
+
+def _abi():
+    from paper_2403_14244_amd import _abi as A
+    if not os.path.exists(A.LIB_PATH):
+        pytest.skip("libisogs.so not built (run python -m paper_2403_14244_amd.build)")
+    return A
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(isogs_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_four_pipeline_calls():
+    fns = header_functions()
+    for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_bwd", "isogs_last_error"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    A = _abi()
+    L = ctypes.CDLL(A.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(L, name), name
+    assert set(header_functions()) <= set(A.EXPORTED)
+
+
+def test_header_constants_match_the_oracle():
+    """The method constants stated in the header and in the oracle agree (they are
+    written independently in both places)."""
+    import oracle as O
+    text = open(HEADER).read()
+    val = lambda name: float(re.search(rf"#define {name} \(?([-0-9.e]+)f?\)?", text).group(1))
+    assert val("ISOGS_TILE") == O.TILE
+    assert 1.0 / val("ISOGS_ALPHA_MIN_INV") == O.ALPHA_MIN
+    assert val("ISOGS_ALPHA_MAX") == O.ALPHA_MAX
+    assert val("ISOGS_T_MIN") == O.T_MIN
+
+
+def test_struct_layouts_match_header():
+    A = _abi()
+    assert ctypes.sizeof(A.Camera) == 4 * (9 + 3 + 3 + 4) + 8
+    assert ctypes.sizeof(A.Scene) == 4 * 8 + 8
+    assert ctypes.sizeof(A.Projected) == 4 * 8
+    assert ctypes.sizeof(A.Bins) == 8 * 8
+    assert A.Bins.capacity.offset == 40
+
+
+def _cam(w=64, h=48):
+    import scenegen
+    return scenegen.look_at_camera((0, 0, 3.0), width=w, height=h)
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    A = _abi()
+    L = A.lib()
+    cams = A.camera_array([_cam()])
+    sc = (A.Scene * 1)()
+    sc[0].n = 4
+    sc[0].sh_degree = 0            # NULL buffers with n > 0
+    proj = A.Projected()
+    assert L.isogs_project(sc, cams, 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    assert b"NULL" in L.isogs_last_error()
+    assert L.isogs_project(sc, cams, 0, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    sc[0].sh_degree = 4
+    assert L.isogs_project(sc, cams, 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    assert b"sh_degree" in L.isogs_last_error()
+    sc[0].sh_degree = 0
+    sc[0].n = -1
+    assert L.isogs_project(sc, cams, 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    bad = _cam()
+    bad.f = -1.0
+    assert L.isogs_project(sc, A.camera_array([bad]), 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    bad = _cam()
+    bad.near = 0.0
+    assert L.isogs_project(sc, A.camera_array([bad]), 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    bad = _cam(w=0)
+    assert L.isogs_project(sc, A.camera_array([bad]), 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+
+
+def test_workspace_query_and_too_small_workspace():
+    A = _abi()
+    L = A.lib()
+    cams = A.camera_array([_cam(64, 48), _cam(33, 17)])
+    npv = A.int_array([100, 50])
+    bins = A.Bins()
+    bins.capacity = 5000
+    need = ctypes.c_size_t(0)
+    proj = A.Projected()
+    assert L.isogs_bin_sort(ctypes.byref(proj), npv, cams, 2, ctypes.byref(bins), None, ctypes.byref(need),
+                            None) == A.ISOGS_OK
+    # keys + values + particle index per entry, plus bookkeeping
+    assert need.value >= 5000 * 16
+    small = ctypes.c_size_t(need.value - 1)
+    fake_ws = ctypes.c_void_p(1 << 20)   # never dereferenced: rejected first
+    assert L.isogs_bin_sort(ctypes.byref(proj), npv, cams, 2, ctypes.byref(bins), fake_ws, ctypes.byref(small),
+                            None) == A.ISOGS_ERR_WORKSPACE
+    bins.capacity = 1 << 31
+    assert L.isogs_bin_sort(ctypes.byref(proj), npv, cams, 2, ctypes.byref(bins), fake_ws, ctypes.byref(need),
+                            None) in (A.ISOGS_ERR_INVALID, A.ISOGS_ERR_WORKSPACE)
+    # render_bwd workspace: 32 bytes per entry
+    bins.capacity = 1000
+    sc = (A.Scene * 1)()
+    gs = (A.Scene * 1)()
+    assert L.isogs_render_bwd(sc, cams, 1, ctypes.byref(proj), ctypes.byref(bins), None, None, None, None, gs,
+                              None, ctypes.byref(need), None) == A.ISOGS_OK
+    assert need.value >= 32 * 1000
+
+
+def test_negative_view_particle_counts_rejected():
+    A = _abi()
+    L = A.lib()
+    cams = A.camera_array([_cam()])
+    bins = A.Bins()
+    need = ctypes.c_size_t(0)
+    proj = A.Projected()
+    assert L.isogs_bin_sort(ctypes.byref(proj), A.int_array([-3]), cams, 1, ctypes.byref(bins), None,
+                            ctypes.byref(need), None) == A.ISOGS_ERR_INVALID

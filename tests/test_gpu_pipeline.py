@@ -1,0 +1,314 @@
+"""GPU parity of every stage of the rasterizer against the FP64 oracle, through the C ABI.
+
+Stage tests give both sides identical FP32 inputs produced by the oracle, so:
+  * binning and sorting must be bit-exact (integer work);
+  * compositing must match to max-abs 1e-4 on every pixel whose FP64 walk does not pass
+    within a hair of a discrete decision (alpha = 1/255, T = 1e-4) - such pixels are
+    counted, must be rare, and are held to the size of one skipped entry instead;
+  * projection must match the FP64 values to within FP32 rounding.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import scenegen as S
+from tests import _helpers as H
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P(torch_cuda):
+    import paper_2403_14244_amd as P   # fails loudly if libisogs.so is missing
+    return P
+
+
+def ulp32(x):
+    return np.spacing(np.abs(x).astype(np.float32)).astype(np.float64)
+
+
+def small_mix(n=20_000, seed=3, deg=3):
+    return S.mixture_scene(n, seed=seed, log_scale_mean=math.log(0.012), sh_degree=deg)
+
+
+PROJECT_CASES = {
+    "cube10k_256": lambda: ([S.workload_scene("cube10k_256")], S.workload_cameras("cube10k_256")),
+    "mix20k_deg3_321x203": lambda: ([small_mix()], [S.orbit_camera(0.7, 4.0, 321, 203)]),
+    "batch_mixed": lambda: ([S.workload_scene("cube10k_256"), small_mix(5000, 4, 2)],
+                            [S.workload_cameras("cube10k_256")[0], S.orbit_camera(2.0, 3.5, 100, 60)]),
+}
+
+
+@pytest.mark.parametrize("case", list(PROJECT_CASES))
+def test_project_matches_oracle(P, torch_cuda, case):
+    note(f"project {case}")
+    scenes, cams = PROJECT_CASES[case]()
+    R = P.Rasterizer()
+    fp = R.project([P.GaussianScene.from_host(s) for s in scenes], cams)
+    torch_cuda.cuda.synchronize()
+    foot = fp.footprint.cpu().numpy()
+    colr = fp.color_radius.cpu().numpy()
+    z = fp.depth.cpu().numpy()
+    tc = fp.tile_count.cpu().numpy()
+    projs = [O.project64(s, c) for s, c in zip(scenes, cams)]
+    views = H.oracle_f32_footprints(projs, cams)
+    ob = O.bin_sort_ref(O.f32_views(projs, cams))
+    off = 0
+    for pr, vw in zip(projs, views):
+        n = pr.u.shape[0]
+        sl = slice(off, off + n)
+        vis = pr.visible
+        assert ((foot[sl, 3] > 0) == vis).all()
+        assert vis.sum() > 0.3 * n
+        # u, v, z: FP64 computation rounded once -> within one FP32 ulp of the oracle
+        for k, arr, ref in (("u", foot[sl, 0], vw["u"]), ("v", foot[sl, 1], vw["v"]), ("z", z[sl], vw["z"])):
+            d = np.abs(arr[vis].astype(np.float64) - ref[vis].astype(np.float64))
+            assert (d <= ulp32(ref[vis])).all(), (k, d.max())
+        np.testing.assert_allclose(foot[sl, 2][vis], vw["is2"][vis], rtol=2 ** -21)
+        np.testing.assert_array_equal(foot[sl, 3][vis], vw["o"][vis])
+        np.testing.assert_allclose(colr[sl, :3][vis].T, vw["rgb"][:, vis], atol=1e-5)
+        np.testing.assert_allclose(colr[sl, 3][vis], vw["r"][vis], rtol=2 ** -21)
+        # tile counts: identical wherever the FP32 footprint is bit-identical
+        same = ((foot[sl, 0] == vw["u"]) & (foot[sl, 1] == vw["v"]) & (colr[sl, 3] == vw["r"]))
+        assert same[vis].mean() > 0.99
+        np.testing.assert_array_equal(tc[sl][same], ob.tile_count[sl][same].astype(np.int64))
+        off += n
+
+
+def _bin_case(name):
+    if name == "cube10k_256":
+        sc, cams = [S.workload_scene("cube10k_256")], S.workload_cameras("cube10k_256")
+        projs = [O.project64(s, c) for s, c in zip(sc, cams)]
+        return H.oracle_f32_footprints(projs, cams), cams
+    if name == "mix_batch_3views":
+        sc = small_mix(30_000, 5, 3)
+        cams = [S.orbit_camera(0.3 * i, 4.0, w, h) for i, (w, h) in enumerate([(256, 256), (333, 190), (64, 48)])]
+        projs = [O.project64(sc, c) for c in cams]
+        return H.oracle_f32_footprints(projs, cams), cams
+    if name in ("random_ties", "random_wide"):
+        ties = name == "random_ties"
+        views, cams = [], []
+        for k, (w, h) in enumerate([(200, 120), (47, 33)]):
+            u, v, z, r = S.random_projected(3000, w, h, seed=20 + k, max_radius=40.0 if not ties else 10.0,
+                                            depth_ties=ties)
+            views.append(H.synthetic_f32_footprints(u, v, z, r, w, h, seed=k))
+            cams.append(S.look_at_camera((0, 0, 3), width=w, height=h))
+        return views, cams
+    if name == "mix200k_1080p":
+        sc = S.mixture_scene(200_000, seed=7)
+        cams = [S.orbit_camera(1.0, 4.0, 1920, 1080)]
+        projs = [O.project64(sc, c) for c in cams]
+        return H.oracle_f32_footprints(projs, cams), cams
+    if name == "empty_and_culled":
+        sc = small_mix(500, 6, 0)
+        sc.pos[2, :] = 50.0     # all behind a camera looking down -z from z=3 ... culled
+        cams = [S.look_at_camera((0, 0, 3), width=40, height=40), S.look_at_camera((0, 0, 3), width=16, height=16)]
+        projs = [O.project64(sc, cams[0])]
+        views = H.oracle_f32_footprints(projs, cams[:1])
+        empty = H.synthetic_f32_footprints(*(np.zeros(0, np.float32),) * 4, 16, 16)
+        return views + [empty], cams
+    raise KeyError(name)
+
+
+BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled"]
+
+
+@pytest.mark.parametrize("case", BIN_CASES)
+def test_bin_sort_bit_exact(P, torch_cuda, case):
+    views, cams = _bin_case(case)
+    ob = O.bin_sort_ref(views)
+    note(f"bin_sort {case}: {ob.keys.shape[0]} entries")
+    R = P.Rasterizer()
+    fp = H.upload_footprints(views, ob)
+    npv = [v["u"].shape[0] for v in views]
+    bins = R.bin_sort(fp, npv, cams)
+    torch_cuda.cuda.synchronize()
+    cnt = bins.n_entries()
+    assert cnt == ob.keys.shape[0]
+    np.testing.assert_array_equal(bins.keys[:cnt].cpu().numpy().view(np.uint64), ob.keys)
+    np.testing.assert_array_equal(bins.emit_index[:cnt].cpu().numpy().view(np.uint32), ob.emit_index)
+    np.testing.assert_array_equal(bins.pidx[:cnt].cpu().numpy().view(np.uint32), ob.pidx)
+    np.testing.assert_array_equal(bins.ranges.cpu().numpy().view(np.uint32), ob.ranges)
+    np.testing.assert_array_equal(bins.offsets.cpu().numpy().view(np.uint32), ob.offsets)
+
+
+def test_bin_sort_capacity_overflow_reports_and_recovers(P, torch_cuda):
+    views, cams = _bin_case("cube10k_256")
+    ob = O.bin_sort_ref(views)
+    note("bin_sort capacity overflow")
+    R = P.Rasterizer()
+    fp = H.upload_footprints(views, ob)
+    small = R.bin_sort(fp, [views[0]["u"].shape[0]], cams, check=False, capacity=1000)
+    torch_cuda.cuda.synchronize()
+    assert int(small.status.item()) == P._abi.ISOGS_ERR_CAPACITY
+    assert small.n_entries() == ob.keys.shape[0]
+    with pytest.raises(P.IsoGSError):
+        small.verify()
+    # the render of an overflowed bin set leaves its outputs untouched
+    img, T, nl = R.render_fwd(fp, [views[0]["u"].shape[0]], small, cams)
+    # growing on demand gives the exact lists
+    ok = R.bin_sort(fp, [views[0]["u"].shape[0]], cams)
+    assert ok.capacity >= ob.keys.shape[0]
+    np.testing.assert_array_equal(ok.keys[:ok.n_entries()].cpu().numpy().view(np.uint64), ob.keys)
+
+
+def _check_image(gimg, oimg, flags, tol=IMG_TOL, what=""):
+    d = np.abs(gimg.astype(np.float64) - oimg).max(axis=0)
+    unflagged = ~flags
+    assert d[unflagged].max() <= tol, (what, float(d[unflagged].max()))
+    # a flagged pixel differs by at most one entry near the 1/255 threshold or the tail
+    # left after the termination threshold
+    assert flags.mean() < 1e-2, (what, int(flags.sum()))
+    if flags.any():
+        assert d[flags].max() <= 0.01, (what, float(d[flags].max()))
+    return float(d[unflagged].max()), int(flags.sum())
+
+
+RENDER_CASES = ["cube10k_256", "mix_batch_3views", "dense_termination"]
+
+
+def _render_case(name):
+    if name == "dense_termination":
+        sc = S.uniform_cube_scene(6000, seed=9, log_scale_mean=math.log(0.08))
+        sc.opacity[:] = np.float32(0.85)
+        cams = [S.look_at_camera((0, 0, 3), width=96, height=80)]
+        projs = [O.project64(sc, cams[0])]
+        return H.oracle_f32_footprints(projs, cams), cams
+    return _bin_case(name)
+
+
+@pytest.mark.parametrize("case", RENDER_CASES)
+def test_render_fwd_matches_oracle(P, torch_cuda, case):
+    views, cams = _render_case(case)
+    ob = O.bin_sort_ref(views)
+    bg = (0.1, 0.3, 0.2)
+    note(f"render_fwd {case}: {ob.keys.shape[0]} entries")
+    R = P.Rasterizer()
+    fp = H.upload_footprints(views, ob)
+    gb = H.upload_bins(ob)
+    img, T, nl = R.render_fwd(fp, [v["u"].shape[0] for v in views], gb, cams, bg)
+    torch_cuda.cuda.synchronize()
+    gi = H.split_flat(img.cpu().numpy(), cams)
+    gT = H.split_flat(T.cpu().numpy(), cams, 1)
+    gn = H.split_flat(nl.cpu().numpy(), cams, 1)
+    ref = H.oracle_render_f32(views, ob, bg)
+    for k, (oimg, oT, onl, ofl) in enumerate(ref):
+        mx, nfl = _check_image(gi[k], oimg, ofl, what=f"{case} view {k}")
+        note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl}")
+        assert np.abs(gT[k][~ofl] - oT[~ofl]).max() <= IMG_TOL
+        np.testing.assert_array_equal(gn[k][~ofl], onl[~ofl])
+    if case == "dense_termination":
+        assert (ref[0][1] < O.T_MIN).mean() > 0.2
+
+
+def _e2e_scenes(name):
+    if name == "cube10k_256":
+        return [S.workload_scene("cube10k_256")], S.workload_cameras("cube10k_256")
+    if name == "mix50k_deg3_480x270":
+        sc = S.mixture_scene(50_000, seed=2, log_scale_mean=math.log(0.008))
+        return [sc, sc], [S.orbit_camera(0.5, 4.0, 480, 270), S.orbit_camera(2.5, 4.0, 480, 270)]
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("case", ["cube10k_256", "mix50k_deg3_480x270"])
+def test_end_to_end_matches_oracle(P, torch_cuda, case):
+    """Whole pipeline from particle parameters: GPU FP32 footprints vs the FP64 oracle."""
+    scenes, cams = _e2e_scenes(case)
+    note(f"end-to-end {case}")
+    R = P.Rasterizer()
+    gsc = [P.GaussianScene.from_host(s) for s in scenes]
+    imgs, st = R.render(gsc, cams, bg=(0.0, 0.0, 0.0))
+    torch_cuda.cuda.synchronize()
+    ores = O.render_views(scenes, cams, alpha_band=2.0 ** -12, term_band=2.0 ** -8)
+    for k in range(len(cams)):
+        mx, nfl = _check_image(imgs[k].cpu().numpy(), ores[0][k], ores[3][k], what=f"{case} view {k}")
+        note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl}")
+
+
+def _grad_scene(deg, n=400, seed=12):
+    rng = np.random.default_rng(seed)
+    sc = S.uniform_cube_scene(n, seed=seed, log_scale_mean=math.log(0.05), log_scale_std=0.4)
+    if deg:
+        K = (deg + 1) ** 2
+        col = np.zeros((3 * K, n), np.float32)
+        col[:3] = sc.color
+        col[3:] = rng.normal(0, 0.1, (3 * K - 3, n))
+        sc = S.Scene(sc.pos, sc.scale, sc.opacity, col, deg)
+    return sc
+
+
+def _grad_check(g_gpu, g_ref, name, rel=2e-3, floor=2e-4):
+    a = g_gpu.astype(np.float64)
+    b = g_ref.astype(np.float64)
+    scale = np.abs(b).max()
+    bad = np.abs(a - b) > rel * np.abs(b) + floor * scale
+    # a few particles may sit on a discrete decision in FP32 but not FP64
+    assert bad.mean() <= 0.01, (name, int(bad.sum()), bad.size, float(np.abs(a - b).max()), float(scale))
+    return float(np.abs(a - b).max() / max(scale, 1e-30))
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_render_bwd_matches_oracle(P, torch_cuda, deg):
+    """Backward pass through the ABI vs the FP64 oracle gradient of L = <W, C>."""
+    torch = torch_cuda
+    sc = _grad_scene(deg)
+    cams = [S.look_at_camera((0.3, 0.2, 3.0), width=72, height=56),
+            S.look_at_camera((-0.4, 0.1, 2.8), width=64, height=64)]
+    rng = np.random.default_rng(deg)
+    Ws = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    note(f"render_bwd deg {deg}")
+    R = P.Rasterizer()
+    gs = P.GaussianScene.from_host(sc)
+    imgs, st = R.render([gs, gs], cams)
+    dL = torch.from_numpy(np.concatenate([w.ravel() for w in Ws])).cuda()
+    g = R.render_bwd([gs, gs], cams, st["fp"], st["bins"], (0.0, 0.0, 0.0), dL, st["T"], st["n_last"])[0]
+    torch.cuda.synchronize()
+    ref = O.scene_grads(sc, cams, [w.astype(np.float64) for w in Ws])
+    for name in ("pos", "scale", "opacity", "color"):
+        r = _grad_check(getattr(g, name).cpu().numpy(), ref[name], name)
+        note(f"  {name}: max rel-to-max {r:.2e}")
+
+
+def test_autograd_function_and_determinism(P, torch_cuda):
+    torch = torch_cuda
+    sc = _grad_scene(2, n=300, seed=5)
+    cams = [S.look_at_camera((0.1, 0.1, 3.0), width=48, height=40) for _ in range(2)]
+    cams[1] = S.look_at_camera((-0.3, 0.2, 2.9), width=48, height=40)
+    note("autograd + determinism")
+    R = P.Rasterizer()
+    target = torch.rand(2, 3, 40, 48, device="cuda")
+    outs = []
+    for rep in range(2):
+        params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+                  for a in (sc.pos, sc.scale, sc.opacity, sc.color)]
+        img = P.IsoGSRender.apply(*params, sc.sh_degree, cams, (0.0, 0.0, 0.0), R)
+        loss = (img - target).abs().mean()
+        loss.backward()
+        outs.append((img.detach().cpu().numpy(), [p.grad.cpu().numpy() for p in params]))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1], outs[1][1]):
+        np.testing.assert_array_equal(a, b)
+    # the L1 gradient through the oracle
+    t = target.cpu().numpy().astype(np.float64)
+    ores = O.render_views([sc, sc], cams)
+    dCs = [np.sign(ores[0][k] - t[k]) / t.size for k in range(2)]
+    ref = O.scene_grads(sc, cams, dCs)
+    for name, gg in zip(("pos", "scale", "opacity", "color"), outs[0][1]):
+        _grad_check(gg, ref[name], name, rel=5e-3, floor=1e-3)
