@@ -1,0 +1,208 @@
+"""Benchmark of the isotropic-splatting rasterizer on one MI355X.
+
+Workload (the forward metric): 1,000,000 isotropic Gaussians (64 clusters + 8 sphere
+shells, degree-3 SH colour) rendered from 100 orbit views at 1920x1080. One step renders
+all 100 views: projection, binning, radix sort and compositing for every view, inputs
+resident in HBM. `value` is forward megapixels per second over the timed steps.
+
+Also reported: fwd+bwd iterations/s (one 1080p view of the same scene through the
+autograd function with an L1 loss), per-stage times, the roofline of the dominant
+kernel (measured with HIP events on the launch stream) and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed instructions: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--views", type=int, default=100)
+    ap.add_argument("--batch-views", type=int, default=10)
+    ap.add_argument("--gaussians", type=int, default=1_000_000)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--train-iters", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(scene, cam, budget_s):
+    """FP64 oracle on one view: full projection and binning, compositing on as many tiles
+    (largest lists first excluded: tiles taken in a fixed stride) as fit the budget."""
+    import oracle as O
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        pr = O.project64(scene, cam)
+        t1 = time.perf_counter()
+        bins = O.bin_sort_ref(O.f32_views([pr], [cam]))
+        t2 = time.perf_counter()
+        TX, TY = O.tile_grid(cam.width, cam.height)
+        order = np.random.default_rng(0).permutation(TX * TY)
+        done_tiles, pix = 0, 0
+        t_render = 0.0
+        for k in order:
+            tx, ty = int(k % TX), int(k // TX)
+            ts = time.perf_counter()
+            O.render64_tiled(pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bins, 0, cam.width, cam.height,
+                             tiles=[(tx, ty)])
+            t_render += time.perf_counter() - ts
+            done_tiles += 1
+            pix += len(O.tile_pixels(tx, ty, cam.width, cam.height)[0])
+            if t_render + (t2 - t0) > budget_s:
+                break
+    total_pix = cam.width * cam.height
+    per_view = (t1 - t0) + (t2 - t1) + t_render * (total_pix / pix)
+    return dict(value=total_pix / per_view / 1e6, unit="Mpix/s", cores=1, kind="oracle",
+                sample=f"1 view of 1920x1080 / 1M Gaussians: FP64 projection and binning of all "
+                       f"particles ({t1 - t0:.1f}s + {t2 - t1:.1f}s), compositing of {done_tiles} random "
+                       f"tiles ({pix} px, {t_render:.1f}s) extrapolated to the full frame; one thread")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(rendering and serving shard by view/request; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import scenegen as S
+    import paper_2403_14244_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = time.perf_counter()
+    scene = S.mixture_scene(args.gaussians, seed=0)
+    cams = [S.orbit_camera(2.0 * math.pi * i / args.views, 4.0, args.width, args.height) for i in range(args.views)]
+    log(f"scene generated in {time.perf_counter() - t:.1f}s")
+    gs = P.GaussianScene.from_host(scene, dev)
+    R = P.Rasterizer(dev, headroom=1.1)
+    B = args.batch_views
+    batches = [cams[i:i + B] for i in range(0, len(cams), B)]
+
+    # size the entry capacity on the warm-up pass
+    def forward_step(check):
+        stage = dict(project=[], bin_sort=[], render_fwd=[])
+        bins_all = []
+        for bc in batches:
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            scenes = [gs] * len(bc)
+            ev[0].record()
+            fp = R.project(scenes, bc)
+            ev[1].record()
+            bins = R.bin_sort(fp, [gs.n] * len(bc), bc, check=check)
+            ev[2].record()
+            R.render_fwd(fp, [gs.n] * len(bc), bins, bc)
+            ev[3].record()
+            stage["project"].append((ev[0], ev[1]))
+            stage["bin_sort"].append((ev[1], ev[2]))
+            stage["render_fwd"].append((ev[2], ev[3]))
+            bins_all.append(bins)
+        return stage, bins_all
+
+    for _ in range(max(args.warmup, 1)):
+        _, bins_all = forward_step(check=True)
+    torch.cuda.synchronize()
+    entries = [b.n_entries() for b in bins_all]
+    log(f"warm-up done: entries per batch {entries}, capacity {R.capacity}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stages = []
+    for _ in range(args.steps):
+        st, bins_all = forward_step(check=False)
+        stages.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for b in bins_all:
+        b.verify()
+    ms_step = elapsed / args.steps * 1e3
+    mpix = args.steps * args.views * args.width * args.height / elapsed / 1e6
+    stage_ms = {k: sum(a.elapsed_time(b) for st in stages for a, b in st[k]) / args.steps for k in stages[0]}
+    log(f"forward: {ms_step:.2f} ms/step, {mpix:.1f} Mpix/s, stages {stage_ms}")
+
+    # dominant kernel: compositing (one launch per batch of views)
+    n_comp = args.steps * len(batches)
+    comp_ms = stage_ms["render_fwd"] * args.steps / n_comp
+    pix_per_launch = B * args.width * args.height
+    ent_per_launch = float(np.mean(entries))
+    tiles_per_launch = B * ((args.width + 15) // 16) * ((args.height + 15) // 16)
+    # algorithmic bytes of one launch: per entry its particle index (4 B) and footprint
+    # record (32 B); per pixel the image (12 B), final transmittance (4 B) and last index
+    # (4 B); per tile its range (8 B)
+    comp_bytes = ent_per_launch * 36 + pix_per_launch * 20 + tiles_per_launch * 8
+    roof = dict(kernel="composite_fwd_kernel", bound="hbm", achieved=comp_bytes / (comp_ms * 1e-3) / 1e9,
+                peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, launch_ms=comp_ms,
+                bytes_per_launch=comp_bytes)
+    roof["frac"] = roof["achieved"] / roof["peak"]
+
+    # fwd+bwd iterations per second: one 1080p view, L1 loss, autograd
+    cam1 = [cams[0]]
+    target = torch.rand(1, 3, args.height, args.width, device=dev)
+    params = [gs.pos.clone().requires_grad_(True), gs.scale.clone().requires_grad_(True),
+              gs.opacity.clone().requires_grad_(True), gs.color.clone().requires_grad_(True)]
+    Rt = P.Rasterizer(dev, headroom=1.1)
+
+    def train_iter():
+        img = P.IsoGSRender.apply(*params, gs.sh_degree, cam1, (0.0, 0.0, 0.0), Rt)
+        loss = (img - target).abs().mean()
+        loss.backward()
+        return loss
+
+    for _ in range(2):
+        train_iter()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.train_iters):
+        train_iter()
+    torch.cuda.synchronize()
+    it_s = args.train_iters / (time.perf_counter() - t1)
+    log(f"fwd+bwd: {it_s:.1f} it/s")
+
+    out = {
+        "metric": "forward Mpix/s at 1920x1080, 1M Gaussians (SH3), 100 orbit views",
+        "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded generator; no dataset)",
+        "config": {"workload": "mix1m_1080p_x100", "gaussians": args.gaussians, "views": args.views,
+                   "width": args.width, "height": args.height, "sh_degree": 3, "views_per_call": B},
+        "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},
+        "entries_per_view": round(ent_per_launch / B),
+        "fwd_bwd_iters_per_s": round(it_s, 2),
+        "roofline": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(scene, cams[0], args.cpu_seconds)
+        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 5)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
