@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
     locate_tile(pk, xcd_swizzle(blockIdx.x, gridDim.x), vi, tx, ty);
     const ViewDesc& vd = pk.v[vi];
     const uint32_t t = threadIdx.x, w = t >> 6;
-    const int x = tx * kTile + (int)(t & 15), y = ty * kTile + (int)(t >> 4);
+    const int x = tx * kTile + quad_x(t), y = ty * kTile + quad_y(t);
     const bool inside = x < vd.width && y < vd.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
@@ -66,24 +66,24 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
     for (uint32_t hi = start + max_last; hi > start;) {
         const uint32_t lo = hi - min((uint32_t)kBatch, hi - start);
         const uint32_t nb = hi - lo;
-        const uint32_t n_mine = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, lo, nb, true,
-                                            tx * kTile, ty * kTile, w_lim, h_lim);
+        const uint32_t n4 = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, lo, nb, true,
+                                        tx * kTile, ty * kTile, w_lim, h_lim);
         // staged index j holds list position lo + nb - 1 - j (0-based within the tile: - start)
-        for (uint32_t k = 0; k < n_mine; ++k) {
+        for (uint32_t k = 0; k < n4; ++k) {
             const uint32_t j = __builtin_amdgcn_readfirstlane(sb.list[w][k]);
+            if (j == kDummy) break;
             const uint32_t pos1 = lo + nb - j - start;   // 1-based list position
             float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             bool hit = false;
             if (pos1 <= last) {
                 const float4 f = sb.fp[j];
                 const float dx = px - f.x, dy = py - f.y;
-                float G;
-                const float a = entry_alpha(dx, dy, f.z, f.w, G);
+                float ga;
+                const float a = entry_alpha(dx, dy, f.z, f.w, ga);
                 if (a >= kAlphaMin) {
                     hit = true;
                     const float4 c = sb.col[j];
-                    const float om = 1.0f - a;
-                    const float inv_om = 1.0f / om;
+                    const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
                     T = T * inv_om;                      // transmittance before this entry
                     const float wgt = a * T;
                     g[4] = dr * wgt;
@@ -94,14 +94,15 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
                     Sr = fmaf(c.x, wgt, Sr);
                     Sg = fmaf(c.y, wgt, Sg);
                     Sb = fmaf(c.z, wgt, Sb);
-                    if (f.w * G < kAlphaMax) {
+                    if (ga < kAlphaMax) {
+                        // alpha = o exp(-d^2 / s^2): d/du = 2 alpha dx / s^2, d/d(1/s^2) = -alpha d^2,
+                        // d/do = alpha / o
                         const float inv_s2 = f.z * (1.0f / kLog2e);
-                        const float dLdG = dLda * f.w;
-                        const float k2 = 2.0f * dLdG * G * inv_s2;
+                        const float k2 = 2.0f * dLda * ga * inv_s2;
                         g[0] = k2 * dx;
                         g[1] = k2 * dy;
-                        g[2] = -dLdG * G * fmaf(dx, dx, dy * dy);
-                        g[3] = dLda * G;
+                        g[2] = -dLda * ga * fmaf(dx, dx, dy * dy);
+                        g[3] = dLda * ga * __builtin_amdgcn_rcpf(c.w);
                     }
                 }
             }

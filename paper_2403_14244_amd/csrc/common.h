@@ -77,13 +77,14 @@ __device__ __forceinline__ void tile_box(float u, float v, float r, int tiles_x,
     ty1 = min(tiles_y - 1, (int)floorf((v + r) * (1.0f / kTile)));
 }
 
-// alpha of an entry at a pixel: min(0.99, o exp(-d^2 / s^2)), with q = log2(e) / s^2.
-// The forward and backward kernels call this one function, so they take identical
-// threshold decisions.
-__device__ __forceinline__ float entry_alpha(float dx, float dy, float q, float o, float& G) {
+// alpha of an entry at a pixel: min(0.99, o exp(-d^2 / s^2)), evaluated as
+// exp2(log2(o) - d^2 log2(e)/s^2) with lo = log2(o) and q = log2(e)/s^2. `g` returns the
+// value before the clamp (o times the kernel). The forward and backward kernels call this
+// one function, so they take identical threshold decisions.
+__device__ __forceinline__ float entry_alpha(float dx, float dy, float q, float lo, float& g) {
     const float d2 = fmaf(dx, dx, dy * dy);
-    G = __builtin_amdgcn_exp2f(-d2 * q);
-    return fminf(kAlphaMax, o * G);
+    g = __builtin_amdgcn_exp2f(fmaf(-d2, q, lo));
+    return fminf(kAlphaMax, g);
 }
 
 // Sum over the 64 lanes of a wavefront with DPP row operations; the total ends in lane 63

@@ -3,7 +3,25 @@
 
 namespace isogs {
 
-// One 256-thread workgroup per tile, one lane per pixel; wave w owns pixel rows 4w..4w+3.
+// Composites one entry into a pixel's running state (branch-free; the dummy pad record
+// has log2(o) = -inf, so alpha = 0 and it changes nothing).
+__device__ __forceinline__ void composite_entry(const float4& f, const float4& c, float px, float py, uint32_t pos,
+                                                float& T, float& cr, float& cg, float& cb, uint32_t& last,
+                                                bool& done) {
+    float g;
+    float a = entry_alpha(px - f.x, py - f.y, f.z, f.w, g);
+    const bool use = (a >= kAlphaMin) && !done;
+    a = use ? a : 0.0f;
+    const float wgt = a * T;
+    cr = fmaf(c.x, wgt, cr);
+    cg = fmaf(c.y, wgt, cg);
+    cb = fmaf(c.z, wgt, cb);
+    T = T * (1.0f - a);
+    last = use ? pos : last;
+    done = done || (T < kTMin);
+}
+
+// One 256-thread workgroup per tile, one lane per pixel; wave w owns quadrant w.
 __global__ void __launch_bounds__(256) composite_fwd_kernel(
     const RenderPack pk, const float4* __restrict__ footprint, const float4* __restrict__ color_radius,
     const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
@@ -15,7 +33,7 @@ __global__ void __launch_bounds__(256) composite_fwd_kernel(
     locate_tile(pk, xcd_swizzle(blockIdx.x, gridDim.x), vi, tx, ty);
     const ViewDesc& vd = pk.v[vi];
     const uint32_t t = threadIdx.x, w = t >> 6;
-    const int x = tx * kTile + (int)(t & 15), y = ty * kTile + (int)(t >> 4);
+    const int x = tx * kTile + quad_x(t), y = ty * kTile + quad_y(t);
     const bool inside = x < vd.width && y < vd.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
@@ -28,26 +46,18 @@ __global__ void __launch_bounds__(256) composite_fwd_kernel(
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_and(done)) break;
         const uint32_t nb = min((uint32_t)kBatch, end - b0);
-        const uint32_t n_mine = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, b0, nb, false,
-                                            tx * kTile, ty * kTile, w_lim, h_lim);
-        const uint32_t pos0 = b0 - start + 1;
-        for (uint32_t k = 0; k < n_mine; ++k) {
-            const uint32_t j = __builtin_amdgcn_readfirstlane(sb.list[w][k]);
-            const float4 f = sb.fp[j];
-            if (!done) {
-                float G;
-                const float a = entry_alpha(px - f.x, py - f.y, f.z, f.w, G);
-                if (a >= kAlphaMin) {
-                    const float4 c = sb.col[j];
-                    const float wgt = a * T;
-                    cr = fmaf(c.x, wgt, cr);
-                    cg = fmaf(c.y, wgt, cg);
-                    cb = fmaf(c.z, wgt, cb);
-                    T = T * (1.0f - a);
-                    last = pos0 + j;
-                    done = T < kTMin;
-                }
-            }
+        const uint32_t n4 = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, b0, nb, false,
+                                        tx * kTile, ty * kTile, w_lim, h_lim);
+        const uint32_t pos0 = b0 - start + 1;   // 1-based list position of staged slot 0
+        for (uint32_t k = 0; k < n4; k += 4) {
+            uint32_t j[4];
+            list4(sb, w, k, j);
+            const float4 f0 = sb.fp[j[0]], f1 = sb.fp[j[1]], f2 = sb.fp[j[2]], f3 = sb.fp[j[3]];
+            const float4 c0 = sb.col[j[0]], c1 = sb.col[j[1]], c2 = sb.col[j[2]], c3 = sb.col[j[3]];
+            composite_entry(f0, c0, px, py, pos0 + j[0], T, cr, cg, cb, last, done);
+            composite_entry(f1, c1, px, py, pos0 + j[1], T, cr, cg, cb, last, done);
+            composite_entry(f2, c2, px, py, pos0 + j[2], T, cr, cg, cb, last, done);
+            composite_entry(f3, c3, px, py, pos0 + j[3], T, cr, cg, cb, last, done);
             if (ballot64(!done) == 0) break;
         }
     }

@@ -45,137 +45,154 @@ __device__ __forceinline__ void sh_eval(int deg, float x, float y, float z, floa
     Y[15] = SHConst::c3a * x * (xx - 3.0f * yy);
 }
 
-struct ProjViewArgs {
+struct ProjCam {
+    float R[9], t[3], eye[3], f, cx, cy, near_z;
+    int32_t width, height;
+    uint32_t p_off;   // first packed record of this view
+};
+
+// All views of one launch render the same scene.
+struct ProjPack {
     const float* pos;
     const float* scale;
     const float* opacity;
     const float* color;
     uint32_t n;
-    int32_t sh_degree;
-    uint32_t p_off;
-    int32_t width, height;
-    float R[9], t[3], eye[3], f, cx, cy, near_z;
-};
-
-struct ProjPack {
     int32_t nv;
-    uint32_t block_begin[kMaxViews + 1];
-    ProjViewArgs v[kMaxViews];
+    ProjCam c[kMaxViews];
 };
 
-// One thread per particle of one view; blocks are grouped by view. Parameters are read
-// structure-of-arrays (consecutive lanes read consecutive floats of each plane).
-// Geometry (camera transform, pixel position, screen scale, radius) is evaluated in FP64
-// and rounded once to FP32: this memory-bound kernel has FP64 throughput to spare, and
-// the stored footprints then differ from the exact values by half an FP32 ulp.
+// One thread per particle: its parameters are read once (structure of arrays, coalesced)
+// and projected into every view of the launch. Geometry (camera transform, pixel position,
+// screen scale, radius) is evaluated in FP64 and rounded once to FP32: this memory-bound
+// kernel has FP64 throughput to spare, and the stored footprints then differ from the
+// exact values by half an FP32 ulp. DEG is the SH degree of the scene.
+template <int DEG>
 __global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4* __restrict__ footprint,
                                                       float4* __restrict__ color_radius,
                                                       float* __restrict__ depth,
                                                       uint32_t* __restrict__ tile_count) {
-    int vi = 0;
-    for (int i = 1; i < pk.nv; ++i) vi = (blockIdx.x >= pk.block_begin[i]) ? i : vi;
-    vi = __builtin_amdgcn_readfirstlane(vi);
-    const ProjViewArgs& pv = pk.v[vi];
-    const uint32_t i = (blockIdx.x - pk.block_begin[vi]) * blockDim.x + threadIdx.x;
-    if (i >= pv.n) return;
-    const uint32_t n = pv.n;
-    const uint32_t o = pv.p_off + i;
-
-    const float mx = pv.pos[i], my = pv.pos[n + i], mz = pv.pos[2 * n + i];
-    const float sigma = pv.scale[i], opa = pv.opacity[i];
-
-    const double px = (double)pv.R[0] * mx + (double)pv.R[1] * my + (double)pv.R[2] * mz + (double)pv.t[0];
-    const double py = (double)pv.R[3] * mx + (double)pv.R[4] * my + (double)pv.R[5] * mz + (double)pv.t[1];
-    const double pz = (double)pv.R[6] * mx + (double)pv.R[7] * my + (double)pv.R[8] * mz + (double)pv.t[2];
-    const double f = (double)pv.f;
-    const double u64 = f * px / pz + (double)pv.cx;
-    const double v64 = f * py / pz + (double)pv.cy;
-    const double s64 = f * (double)sigma / pz;
-
-    bool vis = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(sigma) && isfinite(opa) &&
-               sigma > 0.0f && (double)opa >= 1.0 / 255.0 && pz > (double)pv.near_z;
-    vis = vis && isfinite(u64) && isfinite(v64) && isfinite(s64) && s64 > 0.0;
-
-    // colour for the direction from the camera centre to the particle (world frame)
-    const int K = (pv.sh_degree + 1) * (pv.sh_degree + 1);
-    float rgb[3] = {0.0f, 0.0f, 0.0f};
-    {
-        const float dx = mx - pv.eye[0], dy = my - pv.eye[1], dz = mz - pv.eye[2];
-        const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-        float Y[16];
-        sh_eval(pv.sh_degree, dx * inv, dy * inv, dz * inv, Y);
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pk.n) return;
+    const uint32_t n = pk.n;
+    const float mx = pk.pos[i], my = pk.pos[n + i], mz = pk.pos[2 * n + i];
+    const float sigma = pk.scale[i], opa = pk.opacity[i];
+    float coef[3 * K];
+    bool finite_in = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(sigma) && isfinite(opa);
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = pv.color[(size_t)ch * n + i];
+    for (int k = 0; k < 3 * K; ++k) {
+        coef[k] = pk.color[(size_t)k * n + i];
+        finite_in = finite_in && isfinite(coef[k]);
+    }
+    const bool param_ok = finite_in && sigma > 0.0f && (double)opa >= 1.0 / 255.0;
+    const double root = param_ok ? sqrt(log(255.0 * (double)opa)) : 0.0;
+
+    for (int vi = 0; vi < pk.nv; ++vi) {
+        const ProjCam& pv = pk.c[vi];
+        const uint32_t o = pv.p_off + i;
+        const double px = (double)pv.R[0] * mx + (double)pv.R[1] * my + (double)pv.R[2] * mz + (double)pv.t[0];
+        const double py = (double)pv.R[3] * mx + (double)pv.R[4] * my + (double)pv.R[5] * mz + (double)pv.t[1];
+        const double pz = (double)pv.R[6] * mx + (double)pv.R[7] * my + (double)pv.R[8] * mz + (double)pv.t[2];
+        const double f = (double)pv.f;
+        const double u64 = f * px / pz + (double)pv.cx;
+        const double v64 = f * py / pz + (double)pv.cy;
+        const double s64 = f * (double)sigma / pz;
+        const bool vis = param_ok && pz > (double)pv.near_z && isfinite(u64) && isfinite(v64) && isfinite(s64) &&
+                         s64 > 0.0;
+        float4 fp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float4 cr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float z32 = 1.0f;
+        uint32_t cnt = 0;
+        if (vis) {
+            // colour for the direction from the camera centre to the particle (world frame)
+            const float ex = mx - pv.eye[0], ey = my - pv.eye[1], ez = mz - pv.eye[2];
+            const float inv = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+            float Y[16];
+            sh_eval(DEG, ex * inv, ey * inv, ez * inv, Y);
+            float rgb[3];
 #pragma unroll
-            for (int k = 1; k < 16; ++k)
-                if (k < K) acc = fmaf(pv.color[(size_t)(3 * k + ch) * n + i], Y[k], acc);
-            rgb[ch] = fmaxf(acc, 0.0f);
-            vis = vis && isfinite(acc);
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = coef[ch];
+#pragma unroll
+                for (int k = 1; k < K; ++k) acc = fmaf(coef[3 * k + ch], Y[k], acc);
+                rgb[ch] = fmaxf(acc, 0.0f);
+            }
+            const float u = (float)u64, v = (float)v64;
+            const float r = (float)(s64 * root * (1.0 + 0x1p-10) + 0x1p-6);
+            z32 = (float)pz;
+            fp = make_float4(u, v, (float)(1.0 / (s64 * s64)), opa);
+            cr = make_float4(rgb[0], rgb[1], rgb[2], r);
+            int tx0, tx1, ty0, ty1;
+            const int TX = (pv.width + kTile - 1) / kTile, TY = (pv.height + kTile - 1) / kTile;
+            tile_box(u, v, r, TX, TY, tx0, tx1, ty0, ty1);
+            const float r2 = r * r;
+            const float w_lim = (float)pv.width - 0.5f, h_lim = (float)pv.height - 0.5f;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) cnt += tile_member(u, v, r2, tx, ty, w_lim, h_lim) ? 1u : 0u;
         }
+        footprint[o] = fp;
+        color_radius[o] = cr;
+        depth[o] = z32;
+        tile_count[o] = cnt;
     }
-
-    float4 fp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float4 cr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float z32 = 1.0f;
-    uint32_t cnt = 0;
-    if (vis) {
-        const float u = (float)u64, v = (float)v64;
-        const double r64 = s64 * sqrt(log(255.0 * (double)opa)) * (1.0 + 0x1p-10) + 0x1p-6;
-        const float r = (float)r64;
-        z32 = (float)pz;
-        fp = make_float4(u, v, (float)(1.0 / (s64 * s64)), opa);
-        cr = make_float4(rgb[0], rgb[1], rgb[2], r);
-        int tx0, tx1, ty0, ty1;
-        const int TX = (pv.width + kTile - 1) / kTile, TY = (pv.height + kTile - 1) / kTile;
-        tile_box(u, v, r, TX, TY, tx0, tx1, ty0, ty1);
-        const float r2 = r * r;
-        const float w_lim = (float)pv.width - 0.5f, h_lim = (float)pv.height - 0.5f;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) cnt += tile_member(u, v, r2, tx, ty, w_lim, h_lim) ? 1u : 0u;
-    }
-    footprint[o] = fp;
-    color_radius[o] = cr;
-    depth[o] = z32;
-    tile_count[o] = cnt;
 }
 
 int launch_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv, const isogs_projected* out,
                    hipStream_t stream) {
-    uint32_t p_off = 0;
-    for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
+    // record offset of every view
+    uint32_t off[4096];
+    if (nv > 4096) return -1;
+    uint32_t p = 0;
+    for (int v = 0; v < nv; ++v) {
+        off[v] = p;
+        p += (uint32_t)scenes[v].n;
+    }
+    // views grouped by scene (same parameter buffers), up to kMaxViews per launch
+    bool done[4096] = {false};
+    for (int v = 0; v < nv; ++v) {
+        if (done[v]) continue;
+        const isogs_scene& sc = scenes[v];
         ProjPack pk{};
-        pk.nv = min(kMaxViews, nv - v0);
-        uint32_t blocks = 0;
-        for (int j = 0; j < pk.nv; ++j) {
-            const isogs_scene& sc = scenes[v0 + j];
-            const isogs_camera& cam = cams[v0 + j];
-            ProjViewArgs& a = pk.v[j];
-            a.pos = sc.pos;
-            a.scale = sc.scale;
-            a.opacity = sc.opacity;
-            a.color = sc.color;
-            a.n = (uint32_t)sc.n;
-            a.sh_degree = sc.sh_degree;
-            a.p_off = p_off;
-            a.width = cam.width;
-            a.height = cam.height;
-            for (int k = 0; k < 9; ++k) a.R[k] = cam.R[k];
-            for (int k = 0; k < 3; ++k) a.t[k] = cam.t[k], a.eye[k] = cam.eye[k];
-            a.f = cam.f;
-            a.cx = cam.cx;
-            a.cy = cam.cy;
-            a.near_z = cam.near_z;
-            pk.block_begin[j] = blocks;
-            blocks += (a.n + 255u) / 256u;
-            p_off += a.n;
+        pk.pos = sc.pos;
+        pk.scale = sc.scale;
+        pk.opacity = sc.opacity;
+        pk.color = sc.color;
+        pk.n = (uint32_t)sc.n;
+        auto flush = [&]() -> int {
+            if (pk.nv == 0 || pk.n == 0) return 0;
+            const dim3 grid((pk.n + 255) / 256);
+            float4* fp = reinterpret_cast<float4*>(out->footprint);
+            float4* cr = reinterpret_cast<float4*>(out->color_radius);
+            switch (sc.sh_degree) {
+                case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
+                case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
+                case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
+                default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
+            }
+            pk.nv = 0;
+            return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+        };
+        for (int u = v; u < nv; ++u) {
+            const isogs_scene& su = scenes[u];
+            if (done[u] || su.pos != sc.pos || su.scale != sc.scale || su.opacity != sc.opacity ||
+                su.color != sc.color || su.n != sc.n || su.sh_degree != sc.sh_degree)
+                continue;
+            done[u] = true;
+            const isogs_camera& cam = cams[u];
+            ProjCam& c = pk.c[pk.nv++];
+            for (int k = 0; k < 9; ++k) c.R[k] = cam.R[k];
+            for (int k = 0; k < 3; ++k) c.t[k] = cam.t[k], c.eye[k] = cam.eye[k];
+            c.f = cam.f;
+            c.cx = cam.cx;
+            c.cy = cam.cy;
+            c.near_z = cam.near_z;
+            c.width = cam.width;
+            c.height = cam.height;
+            c.p_off = off[u];
+            if (pk.nv == kMaxViews && flush()) return -1;
         }
-        pk.block_begin[pk.nv] = blocks;
-        if (blocks == 0) continue;
-        hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                           reinterpret_cast<float4*>(out->footprint), reinterpret_cast<float4*>(out->color_radius),
-                           out->depth, out->tile_count);
-        if (hipPeekAtLastError() != hipSuccess) return -1;
+        if (flush()) return -1;
     }
     return 0;
 }

@@ -7,19 +7,29 @@
 namespace isogs {
 
 constexpr int kBatch = 256;   // entries staged in LDS per round (one per thread)
+constexpr int kDummy = kBatch; // staged slot of a zero-opacity record that pads wave lists
 
-// Stages one batch of a tile's entries in LDS and builds, for each of the four waves, the
-// ordered list of entries whose binning disk touches that wave's 16x4 pixel rows. A wave
-// then walks only its own list: footprints are small against a tile, so most entries
-// concern one or two of the four waves. Contains __syncthreads.
+// Pixel of lane l in wave w of a tile workgroup: the four waves own the four 8x8
+// quadrants of the 16x16 tile (a square quadrant is touched by fewer small disks than a
+// 16x4 strip of the same area).
+__device__ __forceinline__ int quad_x(uint32_t t) { return (int)(((t >> 6) & 1u) * 8u + (t & 7u)); }
+__device__ __forceinline__ int quad_y(uint32_t t) { return (int)(((t >> 6) >> 1) * 8u + ((t >> 3) & 7u)); }
+
+// One batch of a tile's entries staged in LDS, plus, for each of the four waves, the
+// ordered list of staged entries whose binning disk touches that wave's quadrant. A wave
+// walks only its own list: footprints are small against a tile, so most entries concern
+// one or two quadrants. Lists are padded to a multiple of four with kDummy.
 struct StagedBatch {
-    float4 fp[kBatch];      // {u, v, q = log2(e)/s^2, o}
-    float4 col[kBatch];     // {r, g, b, radius}
-    uint8_t list[4][kBatch];
-    uint8_t mask[kBatch];   // waves whose rows each staged entry touches
-    uint32_t cnt[4][4];     // [loader wave][target wave]
+    float4 fp[kBatch + 1];      // {u, v, q = log2(e)/s^2, log2(o)}
+    float4 col[kBatch + 1];     // {r, g, b, o}
+    uint16_t list[4][kBatch + 4];
+    uint8_t mask[kBatch];       // quadrants each staged entry touches
+    uint32_t cnt[4][4];         // [loader wave][target wave]
 };
 
+// Stages entries [first, first + n_in_batch) (reversed when `reverse`, so lists then run
+// back to front). Returns the length of the calling wave's padded list (a multiple of 4).
+// Contains __syncthreads.
 __device__ __forceinline__ uint32_t stage_batch(StagedBatch& sb, const float4* __restrict__ footprint,
                                                 const float4* __restrict__ color_radius,
                                                 const uint32_t* __restrict__ pidx, uint32_t n_particles,
@@ -29,24 +39,26 @@ __device__ __forceinline__ uint32_t stage_batch(StagedBatch& sb, const float4* _
     uint32_t mask = 0;
     const uint32_t e = reverse ? first + n_in_batch - 1 - t : first + t;
     const uint32_t g = t < n_in_batch ? pidx[e] : 0xFFFFFFFFu;
-    // reverse batches are staged back to front so lists run in decreasing depth order
     if (g < n_particles) {
-        float4 f = footprint[g];
+        const float4 f = footprint[g];
         const float4 c = color_radius[g];
-        f.z *= kLog2e;
-        sb.fp[t] = f;
-        sb.col[t] = c;
+        sb.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
+        sb.col[t] = make_float4(c.x, c.y, c.z, f.w);
         const float r2 = c.w * c.w;
-        const float x_lo = (float)tile_x0 + 0.5f, x_hi = fminf((float)tile_x0 + 15.5f, w_lim);
 #pragma unroll
         for (int ww = 0; ww < 4; ++ww) {
-            const float y_lo = (float)(tile_y0 + 4 * ww) + 0.5f;
-            const float y_hi = fminf((float)(tile_y0 + 4 * ww) + 3.5f, h_lim);
+            const float x_lo = (float)(tile_x0 + (ww & 1) * 8) + 0.5f;
+            const float y_lo = (float)(tile_y0 + (ww >> 1) * 8) + 0.5f;
+            const float x_hi = fminf(x_lo + 7.0f, w_lim), y_hi = fminf(y_lo + 7.0f, h_lim);
             const float dx = fmaxf(fmaxf(x_lo - f.x, f.x - x_hi), 0.0f);
             const float dy = fmaxf(fmaxf(y_lo - f.y, f.y - y_hi), 0.0f);
-            // rows beyond the image (y_lo > h_lim) have no pixels
-            if (y_lo <= h_lim && dx * dx + dy * dy <= r2) mask |= 1u << ww;
+            // a quadrant starting beyond the image has no pixels
+            if (x_lo <= w_lim && y_lo <= h_lim && dx * dx + dy * dy <= r2) mask |= 1u << ww;
         }
+    }
+    if (t == 0) {
+        sb.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
+        sb.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     sb.mask[t] = (uint8_t)mask;
     uint64_t bal[4];
@@ -61,13 +73,27 @@ __device__ __forceinline__ uint32_t stage_batch(StagedBatch& sb, const float4* _
     for (int ww = 0; ww < 4; ++ww) {
         if ((mask >> ww) & 1u) {
             uint32_t pos = rank_below(bal[ww]);
-            for (uint32_t lw = 0; lw < w; ++lw) pos += sb.cnt[lw][ww];
-            sb.list[ww][pos] = (uint8_t)t;
+            pos += (w > 0 ? sb.cnt[0][ww] : 0u) + (w > 1 ? sb.cnt[1][ww] : 0u) + (w > 2 ? sb.cnt[2][ww] : 0u);
+            sb.list[ww][pos] = (uint16_t)t;
         }
     }
-    const uint32_t mine = sb.cnt[0][w] + sb.cnt[1][w] + sb.cnt[2][w] + sb.cnt[3][w];
+    const uint32_t mine = __builtin_amdgcn_readfirstlane(sb.cnt[0][w] + sb.cnt[1][w] + sb.cnt[2][w] + sb.cnt[3][w]);
+    const uint32_t padded = (mine + 3u) & ~3u;
+    const uint32_t lane = lane_id();
+    if (lane < 4 && mine + lane < padded) sb.list[w][mine + lane] = (uint16_t)kDummy;
     __syncthreads();
-    return __builtin_amdgcn_readfirstlane(mine);
+    return padded;
+}
+
+// Four consecutive entries of a wave's list (uniform: scalar registers).
+__device__ __forceinline__ void list4(const StagedBatch& sb, uint32_t w, uint32_t k, uint32_t j[4]) {
+    const uint64_t q = *reinterpret_cast<const uint64_t*>(&sb.list[w][k]);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)q);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(q >> 32));
+    j[0] = lo & 0xFFFFu;
+    j[1] = lo >> 16;
+    j[2] = hi & 0xFFFFu;
+    j[3] = hi >> 16;
 }
 
 struct RenderPack {
