@@ -56,6 +56,9 @@ def lib():
     """The loaded library (raises ImportError if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch has loaded, so one
+        # process never holds two copies of the runtime
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_14244_amd.build`")
         L = ctypes.CDLL(LIB_PATH)

@@ -69,50 +69,47 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
         const uint32_t n4 = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, lo, nb, true,
                                         tx * kTile, ty * kTile, w_lim, h_lim);
         // staged index j holds list position lo + nb - 1 - j (0-based within the tile: - start)
-        for (uint32_t k = 0; k < n4; ++k) {
-            const uint32_t j = __builtin_amdgcn_readfirstlane(sb.list[w][k]);
-            if (j == kDummy) break;
-            const uint32_t pos1 = lo + nb - j - start;   // 1-based list position
-            float g[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            bool hit = false;
-            if (pos1 <= last) {
+        const uint32_t lane = lane_id();
+        for (uint32_t k = 0; k < n4; k += 4) {
+            uint32_t jj[4];
+            list4(sb, w, k, jj);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t j = jj[r];
+                if (j == kDummy) break;
+                const uint32_t pos1 = lo + nb - j - start;   // 1-based list position
                 const float4 f = sb.fp[j];
+                const float4 c = sb.col[j];
                 const float dx = px - f.x, dy = py - f.y;
                 float ga;
-                const float a = entry_alpha(dx, dy, f.z, f.w, ga);
-                if (a >= kAlphaMin) {
-                    hit = true;
-                    const float4 c = sb.col[j];
-                    const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
-                    T = T * inv_om;                      // transmittance before this entry
-                    const float wgt = a * T;
-                    g[4] = dr * wgt;
-                    g[5] = dg * wgt;
-                    g[6] = db * wgt;
-                    const float dLda = dr * (c.x * T - Sr * inv_om) + dg * (c.y * T - Sg * inv_om) +
-                                       db * (c.z * T - Sb * inv_om);
-                    Sr = fmaf(c.x, wgt, Sr);
-                    Sg = fmaf(c.y, wgt, Sg);
-                    Sb = fmaf(c.z, wgt, Sb);
-                    if (ga < kAlphaMax) {
-                        // alpha = o exp(-d^2 / s^2): d/du = 2 alpha dx / s^2, d/d(1/s^2) = -alpha d^2,
-                        // d/do = alpha / o
-                        const float inv_s2 = f.z * (1.0f / kLog2e);
-                        const float k2 = 2.0f * dLda * ga * inv_s2;
-                        g[0] = k2 * dx;
-                        g[1] = k2 * dy;
-                        g[2] = -dLda * ga * fmaf(dx, dx, dy * dy);
-                        g[3] = dLda * ga * __builtin_amdgcn_rcpf(c.w);
-                    }
-                }
-            }
-            if (ballot64(hit) != 0) {
-#pragma unroll
-                for (int q = 0; q < 7; ++q) g[q] = wave_sum(g[q]);
-            }
-            if (lane_id() == 0) {
-#pragma unroll
-                for (int q = 0; q < 7; ++q) s_part[w][q][j] = g[q];
+                float a = entry_alpha(dx, dy, f.z, f.w, ga);
+                // an entry this pixel composited in the forward pass (same decision)
+                const bool use = (pos1 <= last) && (a >= kAlphaMin);
+                a = use ? a : 0.0f;
+                const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
+                T = T * inv_om;                              // transmittance before this entry
+                const float wgt = a * T;
+                const float dLda = dr * (c.x * T - Sr * inv_om) + dg * (c.y * T - Sg * inv_om) +
+                                   db * (c.z * T - Sb * inv_om);
+                Sr = fmaf(c.x, wgt, Sr);
+                Sg = fmaf(c.y, wgt, Sg);
+                Sb = fmaf(c.z, wgt, Sb);
+                // alpha = o exp(-d^2 / s^2) below the clamp: d/du = 2 alpha dx / s^2,
+                // d/d(1/s^2) = -alpha d^2, d/do = alpha / o
+                const float kk = (use && ga < kAlphaMax) ? dLda * ga : 0.0f;
+                const float inv_s2 = f.z * (1.0f / kLog2e);
+                float g[8];
+                g[0] = 2.0f * kk * inv_s2 * dx;
+                g[1] = 2.0f * kk * inv_s2 * dy;
+                g[2] = -kk * fmaf(dx, dx, dy * dy);
+                g[3] = kk * __builtin_amdgcn_rcpf(c.w);
+                g[4] = dr * wgt;
+                g[5] = dg * wgt;
+                g[6] = db * wgt;
+                g[7] = 0.0f;
+                const float red = (ballot64(use) != 0) ? wave_sum8(g, lane) : 0.0f;
+                const uint32_t q8 = rev3(lane);
+                if (lane < 8 && q8 < 7) s_part[w][q8][j] = red;
             }
         }
         __syncthreads();

@@ -104,6 +104,33 @@ __device__ __forceinline__ float wave_sum(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// Sums eight per-lane values over the 64 lanes of a wave with a transposing butterfly:
+// each exchange step halves the values a lane carries (quad swaps, a row rotation by 4,
+// a row rotation by 8, then two cross-row swaps). Afterwards lane l < 8 holds the total of
+// value rev3(l), where rev3 reverses the three low bits of l. ~28 instructions for all
+// eight sums; the combination order is fixed, so results are bitwise reproducible.
+__device__ __forceinline__ float wave_sum8(const float v[8], uint32_t lane) {
+    const bool p = lane & 1u, q = lane & 2u, b = lane & 4u;
+    float a[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = (p ? v[k + 4] : v[k]) + dpp<0xB1>(p ? v[k] : v[k + 4]);
+    float c[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) c[k] = (q ? a[k + 2] : a[k]) + dpp<0x4E>(q ? a[k] : a[k + 2]);
+    float d = (b ? c[1] : c[0]) + dpp<0x124>(b ? c[0] : c[1]);   // row_ror:4
+    d += dpp<0x128>(d);                                             // row_ror:8
+    d += __shfl_xor(d, 16, kWave);
+    d += __shfl_xor(d, 32, kWave);
+    return d;
+}
+
+__device__ __forceinline__ uint32_t rev3(uint32_t l) { return ((l & 1u) << 2) | (l & 2u) | ((l >> 2) & 1u); }
+
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
