@@ -49,12 +49,60 @@ def parse():
     ap.add_argument("--train-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for counter runs: one copy kernel of known size, then one forward call")
     return ap.parse_args()
 
 
+COPY_BYTES = 512 << 20
+FLOPS_PER_PAIR = 9   # dx, dy, dx^2 + dy^2 (3), times -log2(e)/s^2, exp, times o, clamp
+
+
+def composite_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("common.h", "raster.h", "composite.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2403_14244_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(bytes_per_launch_alg):
+    """HBM bytes per compositing launch from the committed counter summary, if it was taken
+    on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_composite_fwd_mix1m_1080p.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("sources_digest") != composite_sources_digest():
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
+def walk_pairs(T, n_last, ranges, cams, tile_base0=0):
+    """Evaluated (pixel, entry) pairs of the plain tiled walk: every pixel walks its tile's
+    list until it terminates (then up to its last contributor) or to the end."""
+    import torch
+    total = 0
+    pix_off, tile_off = 0, tile_base0
+    for c in cams:
+        W, H = int(c.width), int(c.height)
+        TX, TY = (W + 15) // 16, (H + 15) // 16
+        lens = (ranges[tile_off:tile_off + TX * TY, 1] - ranges[tile_off:tile_off + TX * TY, 0]).long()
+        ys = torch.arange(H, device=T.device) // 16
+        xs = torch.arange(W, device=T.device) // 16
+        tid = (ys[:, None] * TX + xs[None, :]).reshape(-1)
+        t = T[pix_off:pix_off + W * H]
+        nl = n_last[pix_off:pix_off + W * H].long()
+        walk = torch.where(t < 1e-4, nl, lens[tid])
+        total += int(walk.sum().item())
+        pix_off += W * H
+        tile_off += TX * TY
+    return total
+
+
 def cpu_baseline(scene, cam, budget_s):
-    """FP64 oracle on one view: full projection and binning, compositing on as many tiles
-    (largest lists first excluded: tiles taken in a fixed stride) as fit the budget."""
+    """FP64 oracle on one view: full projection and binning, then compositing of tiles in a
+    seeded random order until the time budget is spent, extrapolated to the full frame."""
     import oracle as O
     from threadpoolctl import threadpool_limits
     with threadpool_limits(1):
@@ -126,6 +174,22 @@ def main():
             bins_all.append(bins)
         return stage, bins_all
 
+    if args.pmc_probe:
+        fp = R.project([gs] * len(batches[0]), batches[0])
+        R.bin_sort(fp, [gs.n] * len(batches[0]), batches[0], check=True)
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                      # plain copy: COPY_BYTES read + COPY_BYTES written
+        torch.cuda.synchronize()
+        fp = R.project([gs] * len(batches[0]), batches[0])
+        bins = R.bin_sort(fp, [gs.n] * len(batches[0]), batches[0], check=True)
+        R.render_fwd(fp, [gs.n] * len(batches[0]), bins, batches[0])
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES, "views": len(batches[0]),
+                          "entries": bins.n_entries(), "sources_digest": composite_sources_digest()}))
+        return
+
     for _ in range(max(args.warmup, 1)):
         _, bins_all = forward_step(check=True)
     torch.cuda.synchronize()
@@ -147,9 +211,18 @@ def main():
     stage_ms = {k: sum(a.elapsed_time(b) for st in stages for a, b in st[k]) / args.steps for k in stages[0]}
     log(f"forward: {ms_step:.2f} ms/step, {mpix:.1f} Mpix/s, stages {stage_ms}")
 
-    # dominant kernel: compositing (one launch per batch of views)
+    # dominant kernel: compositing (one launch per batch of views). Its binding roof is the
+    # FP32 VALU: work = evaluated (pixel, entry) pairs of the plain tiled walk x 9 flops.
     n_comp = args.steps * len(batches)
     comp_ms = stage_ms["render_fwd"] * args.steps / n_comp
+    pairs = 0
+    for bc in batches:
+        fp = R.project([gs] * len(bc), bc)
+        bins = R.bin_sort(fp, [gs.n] * len(bc), bc, check=True)
+        _, T, n_last = R.render_fwd(fp, [gs.n] * len(bc), bins, bc)
+        pairs += walk_pairs(T, n_last, bins.ranges, bc)
+    pairs_per_launch = pairs / len(batches)
+    flops = pairs_per_launch * FLOPS_PER_PAIR
     pix_per_launch = B * args.width * args.height
     ent_per_launch = float(np.mean(entries))
     tiles_per_launch = B * ((args.width + 15) // 16) * ((args.height + 15) // 16)
@@ -157,10 +230,14 @@ def main():
     # record (32 B); per pixel the image (12 B), final transmittance (4 B) and last index
     # (4 B); per tile its range (8 B)
     comp_bytes = ent_per_launch * 36 + pix_per_launch * 20 + tiles_per_launch * 8
-    roof = dict(kernel="composite_fwd_kernel", bound="hbm", achieved=comp_bytes / (comp_ms * 1e-3) / 1e9,
-                peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, launch_ms=comp_ms,
-                bytes_per_launch=comp_bytes)
+    roof = dict(kernel="composite_fwd_kernel", bound="alu",
+                achieved=flops / (comp_ms * 1e-3) / 1e12, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                traffic=measured_traffic(comp_bytes), launch_ms=comp_ms, pairs_per_launch=pairs_per_launch,
+                flops_per_pair=FLOPS_PER_PAIR, alg_bytes_per_launch=comp_bytes,
+                hbm_gbs_alg=comp_bytes / (comp_ms * 1e-3) / 1e9)
     roof["frac"] = roof["achieved"] / roof["peak"]
+    log(f"composite: {comp_ms * 1e3:.0f} us/launch, {pairs_per_launch:.3e} pairs, "
+        f"{roof['achieved']:.2f} TFLOP/s ({roof['frac']:.3f} of {VALU_PEAK_TFLOPS:.1f})")
 
     # fwd+bwd iterations per second: one 1080p view, L1 loss, autograd
     cam1 = [cams[0]]
@@ -196,6 +273,7 @@ def main():
         "entries_per_view": round(ent_per_launch / B),
         "fwd_bwd_iters_per_s": round(it_s, 2),
         "roofline": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
+        "stage_us_per_view": {k: round(v * 1e3 / args.views, 1) for k, v in stage_ms.items()},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

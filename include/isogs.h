@@ -94,17 +94,17 @@ typedef struct {
 } isogs_camera;
 
 /* Screen footprints, one record per (view, particle), packed over views (device memory).
- *   footprint     [N][4]  {u, v, 1/s^2, o}        (16-byte aligned)
- *   color_radius  [N][4]  {r, g, b, radius}       (16-byte aligned); radius is the binning
- *                         radius s sqrt(ln(255 o)) (1 + 2^-10) + 2^-6 pixels, 0 if culled
- *   depth         [N]     z (FP32)
- *   tile_count    [N]     number of member tiles (0 if culled)
+ *   record      [N][8]  {u, v, 1/s^2, o, r, g, b, radius}, 32-byte aligned: one aligned
+ *                       32-byte gather per entry when compositing. radius is the binning
+ *                       radius s sqrt(ln(255 o)) (1 + 2^-10) + 2^-6 pixels; a culled particle
+ *                       has an all-zero record
+ *   depth       [N]     z (FP32)
+ *   tile_count  [N]     number of member tiles (0 if culled)
  * A tile is a member when the FP32 distance from (u, v) to the rectangle of its pixel
  * centres, evaluated as dx = max(max(x_lo - u, u - x_hi), 0), dy likewise,
  * dx*dx + dy*dy <= radius*radius, one rounded operation at a time, holds. */
 typedef struct {
-    float* footprint;
-    float* color_radius;
+    float* record;
     float* depth;
     uint32_t* tile_count;
 } isogs_projected;
@@ -112,19 +112,18 @@ typedef struct {
 /* Binned and sorted entries (device memory).
  *   keys        [capacity]  (global tile id << 32) | bits(depth), ascending; ties in emit
  *                           order (view, particle, row-major tile), i.e. a stable sort
- *   emit_index  [capacity]  emit position of each sorted entry
  *   pidx        [capacity]  packed particle index (into isogs_projected) of each entry
  *   ranges      [T][2]      [start, end) of each global tile's entries; [0, 0) if empty
  *   offsets     [N]         first emit position of each particle (exclusive scan of
- *                           tile_count)
- *   capacity    number of entries the three entry arrays can hold
+ *                           tile_count); entry (particle p, j-th member tile in row-major
+ *                           order) has emit position offsets[p] + j
+ *   capacity    number of entries the two entry arrays can hold
  *   count       [1]         written: total entries (even when it exceeds capacity)
  *   status      [1]         written: ISOGS_OK, or ISOGS_ERR_CAPACITY when count > capacity
  *                           (then every later call on these bins leaves its outputs
  *                           untouched; re-run isogs_bin_sort with a larger capacity) */
 typedef struct {
     uint64_t* keys;
-    uint32_t* emit_index;
     uint32_t* pidx;
     uint32_t* ranges;
     uint32_t* offsets;
@@ -174,7 +173,9 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
  *   grads          host array [V] of output buffers in scene layout; views whose scene
  *                  pointers (pos) are equal must pass equal grads entries: their
  *                  gradients are summed in view order. Outputs are overwritten.
- *   ws, ws_bytes   workspace (query with ws == NULL): 32 bytes per entry of capacity
+ *   ws, ws_bytes   workspace (query with ws == NULL): 32 bytes per entry of capacity;
+ *                  each entry's gradient record is stored at its emit position, so a
+ *                  particle's records are contiguous
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
 int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,

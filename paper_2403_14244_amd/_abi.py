@@ -33,14 +33,13 @@ class Camera(ctypes.Structure):
 
 
 class Projected(ctypes.Structure):
-    _fields_ = [("footprint", ctypes.c_void_p), ("color_radius", ctypes.c_void_p), ("depth", ctypes.c_void_p),
-                ("tile_count", ctypes.c_void_p)]
+    _fields_ = [("record", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("tile_count", ctypes.c_void_p)]
 
 
 class Bins(ctypes.Structure):
-    _fields_ = [("keys", ctypes.c_void_p), ("emit_index", ctypes.c_void_p), ("pidx", ctypes.c_void_p),
-                ("ranges", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
-                ("count", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+    _fields_ = [("keys", ctypes.c_void_p), ("pidx", ctypes.c_void_p), ("ranges", ctypes.c_void_p),
+                ("offsets", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("count", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
 
 
 class IsoGSError(RuntimeError):

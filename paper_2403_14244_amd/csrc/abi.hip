@@ -67,10 +67,8 @@ int check_totals(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv
 
 int check_projected(const isogs_projected* p, uint64_t n) {
     if (!p) return fail(ISOGS_ERR_INVALID, "projected is NULL");
-    if (n && (!p->footprint || !p->color_radius || !p->depth || !p->tile_count))
-        return fail(ISOGS_ERR_INVALID, "projected buffer is NULL");
-    if (((uintptr_t)p->footprint | (uintptr_t)p->color_radius) & 15)
-        return fail(ISOGS_ERR_INVALID, "footprint and color_radius must be 16-byte aligned");
+    if (n && (!p->record || !p->depth || !p->tile_count)) return fail(ISOGS_ERR_INVALID, "projected buffer is NULL");
+    if ((uintptr_t)p->record & 31) return fail(ISOGS_ERR_INVALID, "projected record must be 32-byte aligned");
     return ISOGS_OK;
 }
 
@@ -79,7 +77,7 @@ int check_bins(const isogs_bins* b, uint64_t n, uint64_t tiles) {
     if (!b->count || !b->status) return fail(ISOGS_ERR_INVALID, "bins count/status is NULL");
     if (tiles && !b->ranges) return fail(ISOGS_ERR_INVALID, "bins ranges is NULL");
     if (n && !b->offsets) return fail(ISOGS_ERR_INVALID, "bins offsets is NULL");
-    if (b->capacity && (!b->keys || !b->emit_index || !b->pidx))
+    if (b->capacity && (!b->keys || !b->pidx))
         return fail(ISOGS_ERR_INVALID, "bins entry arrays are NULL");
     if (b->capacity >= (1ull << 30) - 1) return fail(ISOGS_ERR_INVALID, "bins capacity must be < 2^30 - 1");
     return ISOGS_OK;

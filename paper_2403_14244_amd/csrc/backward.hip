@@ -15,14 +15,14 @@ namespace isogs {
 
 // One workgroup per tile. Record of an entry: {du, dv, d(1/s^2), do} {dr, dg, db, 0}.
 __global__ void __launch_bounds__(256) composite_bwd_kernel(
-    const RenderPack pk, const float4* __restrict__ footprint, const float4* __restrict__ color_radius,
-    const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ emit_index,
-    const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
+    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
+    float bg_r, float bg_g, float bg_b,
     const float* __restrict__ dL_dimage, const float* __restrict__ T_final, const uint32_t* __restrict__ n_last,
     float4* __restrict__ rec) {
     __shared__ StagedBatch sb;
     __shared__ float s_part[4][7][kBatch];
-    __shared__ uint32_t s_max_last;
+    __shared__ uint32_t s_wmax[4];
     if (*status != kStatusOk) return;
     int vi, tx, ty;
     locate_tile(pk, xcd_swizzle(blockIdx.x, gridDim.x), vi, tx, ty);
@@ -50,24 +50,35 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
     // light arriving from behind the current entry: sum of later c alpha T, plus T_final bg
     float Sr = T * bg_r, Sg = T * bg_g, Sb = T * bg_b;
 
-    if (t == 0) s_max_last = 0u;
+    if (t < 4) s_wmax[t] = 0u;
     __syncthreads();
-    if (last) atomicMax(&s_max_last, last);
+    if (last) atomicMax(&s_wmax[w], last);
     __syncthreads();
-    const uint32_t max_last = s_max_last;
+    // the walk starts at the largest n_last of the tile; each wave skips the entries above
+    // its own largest n_last
+    const uint32_t wmax = __builtin_amdgcn_readfirstlane(s_wmax[w]);
+    const uint32_t max_last = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
     // entries no pixel reached carry zero gradient
-    for (uint32_t e = start + max_last + t; e < end; e += 256) {
-        const uint32_t slot = emit_index[e];
-        if (slot >= pk.n_entries_cap) continue;
-        rec[2 * (size_t)slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        rec[2 * (size_t)slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (uint32_t b0 = start + max_last; b0 < end; b0 += kBatch) {
+        const uint32_t e = b0 + t;
+        const uint32_t g = e < end ? pidx[e] : 0xFFFFFFFFu;
+        if (g < pk.n_particles) {
+            const float4 f = record[2 * (size_t)g];
+            const float r = record[2 * (size_t)g + 1].w;
+            const uint32_t slot =
+                emit_slot(offsets[g], f.x, f.y, r, tx, ty, vd.tiles_x, vd.tiles_y, w_lim, h_lim);
+            if (slot < pk.n_entries_cap) {
+                rec[2 * (size_t)slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                rec[2 * (size_t)slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+        }
     }
 
     for (uint32_t hi = start + max_last; hi > start;) {
         const uint32_t lo = hi - min((uint32_t)kBatch, hi - start);
         const uint32_t nb = hi - lo;
-        const uint32_t n4 = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, lo, nb, true,
-                                        tx * kTile, ty * kTile, w_lim, h_lim);
+        const uint32_t n4 = stage_batch<true>(sb, record, pidx, pk.n_particles, lo, nb, true, tx * kTile,
+                                              ty * kTile, w_lim, h_lim, offsets, vd.tiles_x, vd.tiles_y);
         // staged index j holds list position lo + nb - 1 - j (0-based within the tile: - start)
         const uint32_t lane = lane_id();
         for (uint32_t k = 0; k < n4; k += 4) {
@@ -78,6 +89,7 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
                 const uint32_t j = jj[r];
                 if (j == kDummy) break;
                 const uint32_t pos1 = lo + nb - j - start;   // 1-based list position
+                if (pos1 > wmax) continue;                   // no pixel of this wave reached it
                 const float4 f = sb.fp[j];
                 const float4 c = sb.col[j];
                 const float dx = px - f.x, dy = py - f.y;
@@ -116,13 +128,14 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
         if (t < nb) {
             const uint32_t m = sb.mask[t];
             float s[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            const uint32_t pos1 = lo + nb - t - start;
             for (int ww = 0; ww < 4; ++ww) {
-                if ((m >> ww) & 1u) {
+                if (((m >> ww) & 1u) && pos1 <= s_wmax[ww]) {
 #pragma unroll
                     for (int q = 0; q < 7; ++q) s[q] += s_part[ww][q][t];
                 }
             }
-            const uint32_t slot = emit_index[lo + nb - 1 - t];
+            const uint32_t slot = sb.slot[t];
             if (slot < pk.n_entries_cap) {
                 rec[2 * (size_t)slot] = make_float4(s[0], s[1], s[2], s[3]);
                 rec[2 * (size_t)slot + 1] = make_float4(s[4], s[5], s[6], 0.0f);
@@ -312,9 +325,8 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
         set_render_limits(pk, n_all, nv, bins->capacity);
         if (!blocks) continue;
         hipLaunchKernelGGL(composite_bwd_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                           reinterpret_cast<const float4*>(proj->footprint),
-                           reinterpret_cast<const float4*>(proj->color_radius), bins->pidx, bins->emit_index,
-                           bins->ranges, bins->status, bg[0], bg[1], bg[2], dL_dimage, T_final, n_last, rec);
+                           reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->offsets, bins->ranges,
+                           bins->status, bg[0], bg[1], bg[2], dL_dimage, T_final, n_last, rec);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     // 2. per scene: reduce records over its views (in view order) and chain to parameters

@@ -3,11 +3,11 @@
 // Steps (all on the caller's stream, no host synchronisation):
 //   1. fill        zero tile ranges, radix histograms, tickets and look-back words
 //   2. scan        exclusive scan of per-particle tile counts -> emit offsets, total, status
-//   3. emit        one (key, emit index) pair per (particle, member tile), row-major tiles
+//   3. emit        one (key, particle index) pair per (particle, member tile), row-major tiles
 //   4. histogram   digit counts of every radix pass in one read of the keys
 //   5. passes      LSD radix passes over the compacted key (31 depth bits + tile bits),
 //                  8-bit digits, each a single kernel with decoupled look-back
-//   6. finalize    tile ranges [start, end) and particle index per sorted entry
+//   6. finalize    tile ranges [start, end)
 #include "common.h"
 #include <algorithm>
 
@@ -131,14 +131,12 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
 // Step 3: one entry per (particle, member tile); entries of a particle are consecutive
 // from its offset, tiles in row-major order. A particle writes no more entries than its
 // tile count says (the count may come from elsewhere); missing ones get a sentinel key.
-__global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ footprint,
-                                                   const float4* __restrict__ color_radius,
+__global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ record,
                                                    const float* __restrict__ depth,
                                                    const uint32_t* __restrict__ tile_count,
                                                    const uint32_t* __restrict__ offsets,
                                                    const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                   uint32_t* __restrict__ pidx_of_emit) {
+                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     const int vi = view_of_block(pk, blockIdx.x);
@@ -150,8 +148,8 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
     if (want == 0) return;
     const uint32_t e0 = offsets[i];
     if ((uint64_t)e0 + want > count) return;
-    const float4 fp = footprint[i];
-    const float r = color_radius[i].w;
+    const float4 fp = record[2 * (size_t)i];
+    const float r = record[2 * (size_t)i + 1].w;
     const uint64_t zbits = (uint64_t)__float_as_uint(depth[i]);
     int tx0, tx1, ty0, ty1;
     tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
@@ -164,15 +162,13 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
             const uint32_t e = e0 + j++;
             const uint64_t tid = (uint64_t)(vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx));
             keys[e] = (tid << 32) | zbits;
-            vals[e] = e;
-            pidx_of_emit[e] = i;
+            vals[e] = i;
         }
     }
     for (; j < want; ++j) {
         const uint32_t e = e0 + j;
         keys[e] = ~0ull;
-        vals[e] = e;
-        pidx_of_emit[e] = i;
+        vals[e] = i;
     }
 }
 
@@ -323,13 +319,10 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
     }
 }
 
-// Step 6: tile ranges and the particle index of every sorted entry.
+// Step 6: tile ranges.
 __global__ void __launch_bounds__(256) finalize_kernel(const uint64_t* __restrict__ keys,
-                                                       const uint32_t* __restrict__ emit_index,
-                                                       const uint32_t* __restrict__ pidx_of_emit,
                                                        const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                       uint32_t tiles_total, uint32_t* __restrict__ ranges,
-                                                       uint32_t* __restrict__ pidx) {
+                                                       uint32_t tiles_total, uint32_t* __restrict__ ranges) {
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
@@ -340,8 +333,6 @@ __global__ void __launch_bounds__(256) finalize_kernel(const uint64_t* __restric
             if (tl != prev) ranges[2 * tl] = i;
             if (tl != next) ranges[2 * tl + 1] = i + 1;
         }
-        const uint32_t e = emit_index[i];
-        pidx[i] = e < count ? pidx_of_emit[e] : 0xFFFFFFFFu;
     }
 }
 
@@ -365,7 +356,6 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     size_t off = 0;
     p.off_keys_alt = off;   off = align256(off + capacity * 8);
     p.off_vals_alt = off;   off = align256(off + capacity * 4);
-    p.off_pidx_emit = off;  off = align256(off + capacity * 4);
     // zero-initialised region: histograms, tickets, look-back words (contiguous)
     p.off_hist = off;       off += (size_t)kMaxPasses * kRadix * 4;
     p.off_tickets = off;    off += (size_t)kMaxPasses * 4;
@@ -381,7 +371,6 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     char* base = static_cast<char*>(ws);
     uint64_t* keys_alt = reinterpret_cast<uint64_t*>(base + plan.off_keys_alt);
     uint32_t* vals_alt = reinterpret_cast<uint32_t*>(base + plan.off_vals_alt);
-    uint32_t* pidx_emit = reinterpret_cast<uint32_t*>(base + plan.off_pidx_emit);
     uint32_t* hist = reinterpret_cast<uint32_t*>(base + plan.off_hist);
     uint32_t* tickets = reinterpret_cast<uint32_t*>(base + plan.off_tickets);
     uint32_t* lookback = reinterpret_cast<uint32_t*>(base + plan.off_lookback);
@@ -414,9 +403,9 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     // ping-pong so that the last pass lands in the caller's arrays
     const bool odd = plan.passes & 1;
     uint64_t* k_emit = odd ? keys_alt : bins->keys;
-    uint32_t* v_emit = odd ? vals_alt : bins->emit_index;
+    uint32_t* v_emit = odd ? vals_alt : bins->pidx;
     uint64_t* k_other = odd ? bins->keys : keys_alt;
-    uint32_t* v_other = odd ? bins->emit_index : vals_alt;
+    uint32_t* v_other = odd ? bins->pidx : vals_alt;
 
     // 3. emit, per group of views
     uint32_t p_off = 0, tile_base = 0;
@@ -442,9 +431,8 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         pk.block_begin[pk.nv] = blocks;
         if (blocks)
             hipLaunchKernelGGL(emit_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                               reinterpret_cast<const float4*>(proj->footprint),
-                               reinterpret_cast<const float4*>(proj->color_radius), proj->depth, proj->tile_count,
-                               bins->offsets, bins->count, plan.capacity, k_emit, v_emit, pidx_emit);
+                               reinterpret_cast<const float4*>(proj->record), proj->depth, proj->tile_count,
+                               bins->offsets, bins->count, plan.capacity, k_emit, v_emit);
     }
     if (plan.capacity == 0) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 
@@ -468,10 +456,10 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         kout = const_cast<uint64_t*>(tk);
         vout = const_cast<uint32_t*>(tv);
     }
-    // 6. ranges and particle indices
+    // 6. ranges
     const unsigned fin_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 255) / 256);
-    hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks), dim3(256), 0, stream, bins->keys, bins->emit_index,
-                       pidx_emit, bins->count, plan.capacity, plan.tiles_total, bins->ranges, bins->pidx);
+    hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks), dim3(256), 0, stream, bins->keys, bins->count,
+                       plan.capacity, plan.tiles_total, bins->ranges);
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -23,8 +23,8 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
 
 // One 256-thread workgroup per tile, one lane per pixel; wave w owns quadrant w.
 __global__ void __launch_bounds__(256) composite_fwd_kernel(
-    const RenderPack pk, const float4* __restrict__ footprint, const float4* __restrict__ color_radius,
-    const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
+    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
+    const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
     float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
     uint32_t* __restrict__ n_last) {
     __shared__ StagedBatch sb;
@@ -46,8 +46,8 @@ __global__ void __launch_bounds__(256) composite_fwd_kernel(
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_and(done)) break;
         const uint32_t nb = min((uint32_t)kBatch, end - b0);
-        const uint32_t n4 = stage_batch(sb, footprint, color_radius, pidx, pk.n_particles, b0, nb, false,
-                                        tx * kTile, ty * kTile, w_lim, h_lim);
+        const uint32_t n4 = stage_batch<false>(sb, record, pidx, pk.n_particles, b0, nb, false, tx * kTile,
+                                               ty * kTile, w_lim, h_lim);
         const uint32_t pos0 = b0 - start + 1;   // 1-based list position of staged slot 0
         for (uint32_t k = 0; k < n4; k += 4) {
             uint32_t j[4];
@@ -83,8 +83,7 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
         set_render_limits(pk, n_per_view, nv, bins->capacity);
         if (!blocks) continue;
         hipLaunchKernelGGL(composite_fwd_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                           reinterpret_cast<const float4*>(proj->footprint),
-                           reinterpret_cast<const float4*>(proj->color_radius), bins->pidx, bins->ranges,
+                           reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges,
                            bins->status, bg[0], bg[1], bg[2], image, T_final, n_last);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }

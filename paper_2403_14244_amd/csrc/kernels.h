@@ -18,7 +18,7 @@ struct BinSortPlan {
     int passes;             // radix passes (8-bit digits) over the compacted key
     uint32_t sort_tiles;    // 4096-entry sort tiles for `capacity`
     uint32_t scan_blocks;   // 2048-particle scan blocks
-    size_t off_keys_alt, off_vals_alt, off_pidx_emit, off_hist, off_tickets, off_lookback, off_block_sums,
+    size_t off_keys_alt, off_vals_alt, off_hist, off_tickets, off_lookback, off_block_sums,
         off_flags, bytes;
 };
 

@@ -68,8 +68,7 @@ struct ProjPack {
 // kernel has FP64 throughput to spare, and the stored footprints then differ from the
 // exact values by half an FP32 ulp. DEG is the SH degree of the scene.
 template <int DEG>
-__global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4* __restrict__ footprint,
-                                                      float4* __restrict__ color_radius,
+__global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4* __restrict__ record,
                                                       float* __restrict__ depth,
                                                       uint32_t* __restrict__ tile_count) {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -131,8 +130,8 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4*
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) cnt += tile_member(u, v, r2, tx, ty, w_lim, h_lim) ? 1u : 0u;
         }
-        footprint[o] = fp;
-        color_radius[o] = cr;
+        record[2 * (size_t)o] = fp;
+        record[2 * (size_t)o + 1] = cr;
         depth[o] = z32;
         tile_count[o] = cnt;
     }
@@ -162,13 +161,12 @@ int launch_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t 
         auto flush = [&]() -> int {
             if (pk.nv == 0 || pk.n == 0) return 0;
             const dim3 grid((pk.n + 255) / 256);
-            float4* fp = reinterpret_cast<float4*>(out->footprint);
-            float4* cr = reinterpret_cast<float4*>(out->color_radius);
+            float4* rec = reinterpret_cast<float4*>(out->record);
             switch (sc.sh_degree) {
-                case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
-                case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
-                case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
-                default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, stream, pk, fp, cr, out->depth, out->tile_count); break;
+                case 0: hipLaunchKernelGGL(project_kernel<0>, grid, dim3(256), 0, stream, pk, rec, out->depth, out->tile_count); break;
+                case 1: hipLaunchKernelGGL(project_kernel<1>, grid, dim3(256), 0, stream, pk, rec, out->depth, out->tile_count); break;
+                case 2: hipLaunchKernelGGL(project_kernel<2>, grid, dim3(256), 0, stream, pk, rec, out->depth, out->tile_count); break;
+                default: hipLaunchKernelGGL(project_kernel<3>, grid, dim3(256), 0, stream, pk, rec, out->depth, out->tile_count); break;
             }
             pk.nv = 0;
             return hipPeekAtLastError() == hipSuccess ? 0 : -1;

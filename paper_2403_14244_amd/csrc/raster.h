@@ -24,24 +24,47 @@ struct StagedBatch {
     float4 col[kBatch + 1];     // {r, g, b, o}
     uint16_t list[4][kBatch + 4];
     uint8_t mask[kBatch];       // quadrants each staged entry touches
+    uint32_t slot[kBatch];      // emit position of each staged entry (backward only)
     uint32_t cnt[4][4];         // [loader wave][target wave]
 };
+
+// Emit position of the entry (particle with footprint u, v, r; tile tx, ty): the
+// particle's offset plus the number of its member tiles before (tx, ty) in row-major
+// order, counted with the same FP32 test the binning used.
+__device__ __forceinline__ uint32_t emit_slot(uint32_t offset, float u, float v, float r, int tx, int ty,
+                                              int tiles_x, int tiles_y, float w_lim, float h_lim) {
+    int tx0, tx1, ty0, ty1;
+    tile_box(u, v, r, tiles_x, tiles_y, tx0, tx1, ty0, ty1);
+    const float r2 = r * r;
+    uint32_t j = 0;
+    for (int yy = ty0; yy <= ty; ++yy) {
+        const int xe = (yy == ty) ? tx - 1 : tx1;
+        for (int xx = tx0; xx <= xe; ++xx) j += tile_member(u, v, r2, xx, yy, w_lim, h_lim) ? 1u : 0u;
+    }
+    return offset + j;
+}
 
 // Stages entries [first, first + n_in_batch) (reversed when `reverse`, so lists then run
 // back to front). Returns the length of the calling wave's padded list (a multiple of 4).
 // Contains __syncthreads.
-__device__ __forceinline__ uint32_t stage_batch(StagedBatch& sb, const float4* __restrict__ footprint,
-                                                const float4* __restrict__ color_radius,
+template <bool WITH_SLOT>
+__device__ __forceinline__ uint32_t stage_batch(StagedBatch& sb, const float4* __restrict__ record,
                                                 const uint32_t* __restrict__ pidx, uint32_t n_particles,
                                                 uint32_t first, uint32_t n_in_batch, bool reverse, int tile_x0,
-                                                int tile_y0, float w_lim, float h_lim) {
+                                                int tile_y0, float w_lim, float h_lim,
+                                                const uint32_t* __restrict__ offsets = nullptr,
+                                                int tiles_x = 0, int tiles_y = 0) {
     const uint32_t t = threadIdx.x, w = t >> 6;
     uint32_t mask = 0;
     const uint32_t e = reverse ? first + n_in_batch - 1 - t : first + t;
     const uint32_t g = t < n_in_batch ? pidx[e] : 0xFFFFFFFFu;
+    if (WITH_SLOT) sb.slot[t] = 0xFFFFFFFFu;
     if (g < n_particles) {
-        const float4 f = footprint[g];
-        const float4 c = color_radius[g];
+        const float4 f = record[2 * (size_t)g];
+        const float4 c = record[2 * (size_t)g + 1];
+        if (WITH_SLOT)
+            sb.slot[t] = emit_slot(offsets[g], f.x, f.y, c.w, tile_x0 / kTile, tile_y0 / kTile, tiles_x, tiles_y,
+                                   w_lim, h_lim);
         sb.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
         sb.col[t] = make_float4(c.x, c.y, c.z, f.w);
         const float r2 = c.w * c.w;

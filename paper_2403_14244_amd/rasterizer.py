@@ -72,21 +72,19 @@ class GaussianScene:
 @dataclass
 class Footprints:
     """Output of project: per (view, particle) records packed over views."""
-    footprint: torch.Tensor      # [N, 4] {u, v, 1/s^2, o}
-    color_radius: torch.Tensor   # [N, 4] {r, g, b, radius}
+    record: torch.Tensor         # [N, 8] {u, v, 1/s^2, o, r, g, b, radius}
     depth: torch.Tensor          # [N]
     tile_count: torch.Tensor     # [N] int32 (uint32 on the device)
 
     def abi(self) -> A.Projected:
         p = A.Projected()
-        p.footprint, p.color_radius = _p(self.footprint), _p(self.color_radius)
-        p.depth, p.tile_count = _p(self.depth), _p(self.tile_count)
+        p.record, p.depth, p.tile_count = _p(self.record), _p(self.depth), _p(self.tile_count)
         return p
 
     @staticmethod
     def empty(n, device="cuda") -> "Footprints":
-        return Footprints(torch.empty((n, 4), dtype=_F32, device=device), torch.empty((n, 4), dtype=_F32, device=device),
-                          torch.empty(n, dtype=_F32, device=device), torch.empty(n, dtype=torch.int32, device=device))
+        return Footprints(torch.empty((n, 8), dtype=_F32, device=device), torch.empty(n, dtype=_F32, device=device),
+                          torch.empty(n, dtype=torch.int32, device=device))
 
 
 @dataclass
@@ -94,7 +92,6 @@ class TileBins:
     """Output of bin_sort. Entry arrays hold `capacity` slots; `count` and `status` live
     on the device."""
     keys: torch.Tensor           # [capacity] int64 (uint64 on the device)
-    emit_index: torch.Tensor     # [capacity] int32
     pidx: torch.Tensor           # [capacity] int32
     ranges: torch.Tensor         # [T, 2] int32
     offsets: torch.Tensor        # [N] int32
@@ -104,7 +101,7 @@ class TileBins:
 
     def abi(self) -> A.Bins:
         b = A.Bins()
-        b.keys, b.emit_index, b.pidx = _p(self.keys), _p(self.emit_index), _p(self.pidx)
+        b.keys, b.pidx = _p(self.keys), _p(self.pidx)
         b.ranges, b.offsets = _p(self.ranges), _p(self.offsets)
         b.capacity = self.capacity
         b.count, b.status = _p(self.count), _p(self.status)
@@ -126,7 +123,6 @@ def tiles_of(cam) -> int:
 def _alloc_bins(capacity, n_total, tiles_total, device) -> TileBins:
     cap = max(int(capacity), 1)
     return TileBins(keys=torch.empty(cap, dtype=torch.int64, device=device),
-                    emit_index=torch.empty(cap, dtype=torch.int32, device=device),
                     pidx=torch.empty(cap, dtype=torch.int32, device=device),
                     ranges=torch.empty((tiles_total, 2), dtype=torch.int32, device=device),
                     offsets=torch.empty(max(n_total, 1), dtype=torch.int32, device=device)[:n_total],

@@ -35,12 +35,12 @@ def upload_footprints(views, bins, device="cuda"):
     """Packs per-view FP32 footprints (+ the oracle's tile counts) into device Footprints."""
     import torch
     from paper_2403_14244_amd import Footprints
-    fp = np.concatenate([np.stack([v["u"], v["v"], v["is2"], v["o"]], 1) for v in views]).astype(np.float32)
-    cr = np.concatenate([np.stack([v["rgb"][0], v["rgb"][1], v["rgb"][2], v["r"]], 1) for v in views]).astype(np.float32)
+    rec = np.concatenate([np.stack([v["u"], v["v"], v["is2"], v["o"], v["rgb"][0], v["rgb"][1], v["rgb"][2],
+                                    v["r"]], 1) for v in views]).astype(np.float32)
     z = np.concatenate([v["z"] for v in views]).astype(np.float32)
     tc = bins.tile_count.astype(np.int64).astype(np.int32)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
-    return Footprints(t(fp), t(cr), t(z), t(tc))
+    return Footprints(t(rec), t(z), t(tc))
 
 
 def upload_bins(b, capacity=None, device="cuda"):
@@ -50,12 +50,10 @@ def upload_bins(b, capacity=None, device="cuda"):
     cap = max(count, 1) if capacity is None else capacity
     keys = np.zeros(cap, np.uint64)
     keys[:count] = b.keys
-    ei = np.zeros(cap, np.uint32)
-    ei[:count] = b.emit_index
     pi = np.zeros(cap, np.uint32)
     pi[:count] = b.pidx
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a).view(dt)).to(device)
-    return TileBins(keys=t(keys, np.int64), emit_index=t(ei, np.int32), pidx=t(pi, np.int32),
+    return TileBins(keys=t(keys, np.int64), pidx=t(pi, np.int32),
                     ranges=t(b.ranges, np.int32), offsets=t(b.offsets, np.int32),
                     count=torch.tensor([count], dtype=torch.int32, device=device),
                     status=torch.zeros(1, dtype=torch.int32, device=device), capacity=cap)

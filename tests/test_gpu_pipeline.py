@@ -63,8 +63,8 @@ def test_project_matches_oracle(P, torch_cuda, case):
     R = P.Rasterizer()
     fp = R.project([P.GaussianScene.from_host(s) for s in scenes], cams)
     torch_cuda.cuda.synchronize()
-    foot = fp.footprint.cpu().numpy()
-    colr = fp.color_radius.cpu().numpy()
+    foot = fp.record[:, :4].cpu().numpy()
+    colr = fp.record[:, 4:].cpu().numpy()
     z = fp.depth.cpu().numpy()
     tc = fp.tile_count.cpu().numpy()
     projs = [O.project64(s, c) for s, c in zip(scenes, cams)]
@@ -143,7 +143,6 @@ def test_bin_sort_bit_exact(P, torch_cuda, case):
     cnt = bins.n_entries()
     assert cnt == ob.keys.shape[0]
     np.testing.assert_array_equal(bins.keys[:cnt].cpu().numpy().view(np.uint64), ob.keys)
-    np.testing.assert_array_equal(bins.emit_index[:cnt].cpu().numpy().view(np.uint32), ob.emit_index)
     np.testing.assert_array_equal(bins.pidx[:cnt].cpu().numpy().view(np.uint32), ob.pidx)
     np.testing.assert_array_equal(bins.ranges.cpu().numpy().view(np.uint32), ob.ranges)
     np.testing.assert_array_equal(bins.offsets.cpu().numpy().view(np.uint32), ob.offsets)
