@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--train-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="length of the request trace of the serving measurement (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one copy kernel of known size, then one forward call")
     return ap.parse_args()
@@ -98,6 +101,50 @@ def walk_pairs(T, n_last, ranges, cams, tile_base0=0):
         pix_off += W * H
         tile_off += TX * TY
     return total
+
+
+def poisson_trace(n, rate_hz, scene_names, resolutions, seed=4, radius=4.0, start_id=0):
+    """Serving requests: exponential inter-arrival times (mean 1/rate), a uniformly chosen
+    resident scene, an orbit camera at a uniform angle and a uniformly chosen resolution."""
+    import scenegen as S
+    from paper_2403_14244_amd.serving import Request
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate_hz)
+        name = scene_names[int(rng.integers(len(scene_names)))]
+        th = float(rng.uniform(0, 2 * math.pi))
+        w, h = resolutions[int(rng.integers(len(resolutions)))]
+        out.append(Request(rid=start_id + i, scene=name, cam=S.orbit_camera(th, radius, w, h), arrival=t))
+    return out
+
+
+def serving_benchmark(args, dev):
+    """Four resident scenes (200k, 1M, 2M, 3M Gaussians), Poisson arrivals, mixed
+    resolutions, continuous batching on two streams; latency = completion - arrival."""
+    import torch
+    import scenegen as S
+    import paper_2403_14244_amd as P
+    from paper_2403_14244_amd.serving import GpuExecutor, Server
+    sizes = {"mix200k": (200_000, 10), "mix1m": (1_000_000, 11), "mix2m": (2_000_000, 12), "mix3m": (3_000_000, 13)}
+    scenes = {k: P.GaussianScene.from_host(S.mixture_scene(n, seed=sd), dev) for k, (n, sd) in sizes.items()}
+    res = [(512, 512), (1280, 720), (1920, 1080)]
+    n = max(1, int(args.serve_seconds * args.serve_rate))
+    warm = poisson_trace(100, args.serve_rate, list(scenes), res, seed=3)
+    reqs = poisson_trace(n, args.serve_rate, list(scenes), res, seed=4, start_id=1000)
+    ex = GpuExecutor(scenes, dev)
+    ex.calibrate(warm + reqs)
+    Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=2).run(warm)
+    torch.cuda.synchronize()
+    srv = Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=2)
+    st = srv.run(reqs)
+    sel = [r.latency * 1e3 for r in reqs if r.scene == "mix1m" and r.cam.width == 1920]
+    st["p99_ms_1080p_1m"] = float(np.percentile(sel, 99)) if sel else None
+    st["rate_hz"] = args.serve_rate
+    st["scenes"] = {k: v[0] for k, v in sizes.items()}
+    st["capacity_overflows"] = ex.overflows
+    st.pop("pool_bytes", None)
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
 
 
 def cpu_baseline(scene, cam, budget_s):
@@ -262,6 +309,13 @@ def main():
     it_s = args.train_iters / (time.perf_counter() - t1)
     log(f"fwd+bwd: {it_s:.1f} it/s")
 
+    serving = None
+    if args.serve_seconds > 0:
+        log("serving ...")
+        serving = serving_benchmark(args, dev)
+        log(f"serving: p50 {serving['p50_ms']} ms, p99 {serving['p99_ms']} ms, "
+            f"1080p/1M p99 {serving['p99_ms_1080p_1m']} ms, {serving['mpix_per_s']} Mpix/s")
+
     out = {
         "metric": "forward Mpix/s at 1920x1080, 1M Gaussians (SH3), 100 orbit views",
         "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -274,6 +328,7 @@ def main():
         "fwd_bwd_iters_per_s": round(it_s, 2),
         "roofline": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
         "stage_us_per_view": {k: round(v * 1e3 / args.views, 1) for k, v in stage_ms.items()},
+        "serving": serving,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

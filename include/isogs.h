@@ -163,6 +163,19 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
                      const float* bg, float* image, float* T_final, uint32_t* n_last,
                      void* stream);
 
+/* Same outputs as isogs_render_fwd (bitwise), computed by a persistent grid - as many
+ * workgroups as the GPU holds at once - that takes tiles from a global queue ordered
+ * longest entry list first, so that the few very long tiles of skewed scenes start early
+ * instead of trailing the launch. Used by the serving loop for batches of mixed-resolution
+ * requests.
+ *   ws, ws_bytes  workspace (query with ws == NULL): the queue, 4 bytes per tile of the
+ *                 largest group of 16 views, plus bookkeeping
+ * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
+int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view,
+                                const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
+                                const float* bg, float* image, float* T_final, uint32_t* n_last,
+                                void* ws, size_t* ws_bytes, void* stream);
+
 /* Gradients of a scalar loss L with respect to the particle parameters, given dL/dimage.
  * Walks each pixel's entries in reverse from n_last, recovering the transmittance before
  * each entry as T / (1 - alpha) (no per-entry state is stored by the forward pass), and

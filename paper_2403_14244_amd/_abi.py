@@ -17,8 +17,8 @@ ISOGS_ERR_CAPACITY = -2
 ISOGS_ERR_WORKSPACE = -3
 ISOGS_ERR_DEVICE = -4
 
-EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_bwd",
-            "isogs_last_error", "isogs_version")
+EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_persistent",
+            "isogs_render_bwd", "isogs_last_error", "isogs_version")
 
 
 class Scene(ctypes.Structure):
@@ -59,7 +59,7 @@ def lib():
         # process never holds two copies of the runtime
         import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_14244_amd.build`")
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2403_14244_amd/build.py`")
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         vp = ctypes.c_void_p
@@ -68,9 +68,13 @@ def lib():
                                      P(ctypes.c_size_t), vp]
         L.isogs_render_fwd.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera), ctypes.c_int32,
                                        P(ctypes.c_float), vp, vp, vp, vp]
+        L.isogs_render_fwd_persistent.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera),
+                                                  ctypes.c_int32, P(ctypes.c_float), vp, vp, vp, vp,
+                                                  P(ctypes.c_size_t), vp]
         L.isogs_render_bwd.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), P(Bins),
                                        P(ctypes.c_float), vp, vp, vp, P(Scene), vp, P(ctypes.c_size_t), vp]
-        for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_bwd"):
+        for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_persistent",
+                     "isogs_render_bwd"):
             getattr(L, name).restype = ctypes.c_int
         L.isogs_last_error.restype = ctypes.c_char_p
         L.isogs_last_error.argtypes = []

@@ -1,6 +1,6 @@
 """Builds libisogs.so in-tree with hipcc for gfx950.
 
-    python -m paper_2403_14244_amd.build
+    python paper_2403_14244_amd/build.py
 """
 from __future__ import annotations
 

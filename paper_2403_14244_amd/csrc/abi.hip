@@ -165,6 +165,34 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, con
     return ISOGS_OK;
 }
 
+int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                                const isogs_camera* cams, int32_t n_views, const float* bg, float* image,
+                                float* T_final, uint32_t* n_last, void* ws, size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    const size_t need = isogs::render_fwd_persistent_ws(cams, n_views);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!bg) return fail(ISOGS_ERR_INVALID, "bg is NULL");
+    uint64_t n, tiles;
+    if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
+    if ((rc = check_projected(proj, n))) return rc;
+    if ((rc = check_bins(bins, n, tiles))) return rc;
+    if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (isogs::launch_render_fwd_persistent(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last, ws,
+                                            (hipStream_t)stream))
+        return device_fail("isogs_render_fwd_persistent");
+    return ISOGS_OK;
+}
+
 int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
                      const isogs_projected* proj, const isogs_bins* bins, const float* bg, const float* dL_dimage,
                      const float* T_final, const uint32_t* n_last, const isogs_scene* grads, void* ws,

@@ -1,4 +1,6 @@
 // Front-to-back compositing (eq. 4) of every pixel over its tile's depth-sorted entries.
+#include <algorithm>
+
 #include "raster.h"
 
 namespace isogs {
@@ -21,16 +23,16 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
     done = done || (T < kTMin);
 }
 
-// One 256-thread workgroup per tile, one lane per pixel; wave w owns quadrant w.
-__global__ void __launch_bounds__(256) composite_fwd_kernel(
-    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
-    const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
-    float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
-    uint32_t* __restrict__ n_last) {
-    __shared__ StagedBatch sb;
-    if (*status != kStatusOk) return;
+// Composites one tile (logical index within the launch) with a 256-thread workgroup, one
+// lane per pixel; wave w owns quadrant w. Contains __syncthreads.
+__device__ __forceinline__ void composite_tile(StagedBatch& sb, const RenderPack& pk, uint32_t logical,
+                                               const float4* __restrict__ record,
+                                               const uint32_t* __restrict__ pidx,
+                                               const uint32_t* __restrict__ ranges, float bg_r, float bg_g,
+                                               float bg_b, float* __restrict__ image, float* __restrict__ T_final,
+                                               uint32_t* __restrict__ n_last) {
     int vi, tx, ty;
-    locate_tile(pk, xcd_swizzle(blockIdx.x, gridDim.x), vi, tx, ty);
+    locate_tile(pk, logical, vi, tx, ty);
     const ViewDesc& vd = pk.v[vi];
     const uint32_t t = threadIdx.x, w = t >> 6;
     const int x = tx * kTile + quad_x(t), y = ty * kTile + quad_y(t);
@@ -72,6 +74,91 @@ __global__ void __launch_bounds__(256) composite_fwd_kernel(
     n_last[vd.pix_off + pix] = last;
 }
 
+// One workgroup per tile, tiles in XCD-banded order.
+__global__ void __launch_bounds__(256) composite_fwd_kernel(
+    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
+    const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
+    float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
+    uint32_t* __restrict__ n_last) {
+    __shared__ StagedBatch sb;
+    if (*status != kStatusOk) return;
+    composite_tile(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, ranges, bg_r, bg_g, bg_b, image,
+                   T_final, n_last);
+}
+
+// Persistent variant: a fixed grid of workgroups takes tiles from a global queue ordered
+// longest list first, so a few very long tiles start early instead of trailing the launch.
+// Every workgroup leaves once the counter passes the last item.
+__global__ void __launch_bounds__(256) composite_fwd_persistent_kernel(
+    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
+    const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
+    float* __restrict__ image, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
+    const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* __restrict__ counter) {
+    __shared__ StagedBatch sb;
+    __shared__ uint32_t s_item;
+    if (*status != kStatusOk) return;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        composite_tile(sb, pk, order[item], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last);
+    }
+}
+
+__global__ void __launch_bounds__(128) fill_u32_kernel_c(uint32_t* __restrict__ p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+constexpr int kBuckets = 33;   // list length classes: 0, then 32 - clz(length)
+
+__device__ __forceinline__ uint32_t length_bucket(const uint32_t* ranges, uint32_t gt, uint32_t cap) {
+    const uint32_t s = ranges[2 * gt], e = min(ranges[2 * gt + 1], cap);
+    const uint32_t len = e > s ? e - s : 0u;
+    return len ? 32u - (uint32_t)__clz(len) : 0u;
+}
+
+// Queue order, pass 1: how many tiles fall in each length class.
+__global__ void __launch_bounds__(256) tile_class_hist_kernel(const uint32_t* __restrict__ ranges, uint32_t tile0,
+                                                              uint32_t n_items, uint32_t cap,
+                                                              uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kBuckets];
+    if (threadIdx.x < kBuckets) h[threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += gridDim.x * blockDim.x)
+        atomicAdd(&h[length_bucket(ranges, tile0 + i, cap)], 1u);
+    __syncthreads();
+    if (threadIdx.x < kBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// Queue order, pass 2: tiles placed class by class, longest class first (the order inside
+// a class is arbitrary; each tile's result does not depend on it).
+__global__ void __launch_bounds__(256) tile_class_scatter_kernel(const uint32_t* __restrict__ ranges,
+                                                                 uint32_t tile0, uint32_t n_items, uint32_t cap,
+                                                                 const uint32_t* __restrict__ hist,
+                                                                 uint32_t* __restrict__ cursor,
+                                                                 uint32_t* __restrict__ order) {
+    __shared__ uint32_t start[kBuckets], cnt[kBuckets], base[kBuckets];
+    if (threadIdx.x < kBuckets) {
+        uint32_t s = 0;
+        for (int b = kBuckets - 1; b > (int)threadIdx.x; --b) s += hist[b];
+        start[threadIdx.x] = s;
+        cnt[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t b = 0, local = 0;
+    if (i < n_items) {
+        b = length_bucket(ranges, tile0 + i, cap);
+        local = atomicAdd(&cnt[b], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBuckets && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (i < n_items) order[start[b] + base[b] + local] = i;
+}
+
 int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                       const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
                       uint32_t* n_last, hipStream_t stream) {
@@ -85,6 +172,60 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
         hipLaunchKernelGGL(composite_fwd_kernel, dim3(blocks), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges,
                            bins->status, bg[0], bg[1], bg[2], image, T_final, n_last);
+        if (hipPeekAtLastError() != hipSuccess) return -1;
+    }
+    return 0;
+}
+
+size_t render_fwd_persistent_ws(const isogs_camera* cams, int32_t nv) {
+    size_t most = 0;
+    for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
+        size_t tiles = 0;
+        for (int j = v0; j < min(nv, v0 + kMaxViews); ++j)
+            tiles += (size_t)((cams[j].width + kTile - 1) / kTile) * ((cams[j].height + kTile - 1) / kTile);
+        most = tiles > most ? tiles : most;
+    }
+    return (most + 2 * kBuckets + 1) * 4 + 256;
+}
+
+int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                                 const isogs_camera* cams, int32_t nv, const float* bg, float* image,
+                                 float* T_final, uint32_t* n_last, void* ws, hipStream_t stream) {
+    static int cu_count = 0, per_cu = 0;
+    if (!cu_count) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
+        cu_count = prop.multiProcessorCount;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, composite_fwd_persistent_kernel, 256, 0) !=
+                hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+    }
+    uint32_t* bookkeeping = static_cast<uint32_t*>(ws);   // hist[33], cursor[33], counter
+    uint32_t* hist = bookkeeping;
+    uint32_t* cursor = bookkeeping + kBuckets;
+    uint32_t* counter = bookkeeping + 2 * kBuckets;
+    uint32_t* order = bookkeeping + 2 * kBuckets + 1;
+    uint32_t p_off = 0, tile_base = 0, pix_off = 0;
+    for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
+        RenderPack pk{};
+        uint32_t blocks;
+        const uint32_t tile0 = tile_base;
+        fill_render_pack(pk, cams, n_per_view, v0, nv, p_off, tile_base, pix_off, blocks);
+        set_render_limits(pk, n_per_view, nv, bins->capacity);
+        if (!blocks) continue;
+        const uint32_t cap = pk.n_entries_cap;
+        hipLaunchKernelGGL(fill_u32_kernel_c, dim3(1), dim3(128), 0, stream, bookkeeping, (uint32_t)(2 * kBuckets + 1));
+        const unsigned hb = std::min<unsigned>(256u, (blocks + 255u) / 256u);
+        hipLaunchKernelGGL(tile_class_hist_kernel, dim3(hb), dim3(256), 0, stream, bins->ranges, tile0, blocks, cap,
+                           hist);
+        hipLaunchKernelGGL(tile_class_scatter_kernel, dim3((blocks + 255u) / 256u), dim3(256), 0, stream,
+                           bins->ranges, tile0, blocks, cap, hist, cursor, order);
+        const unsigned grid = std::min<unsigned>(blocks, (unsigned)(cu_count * per_cu));
+        hipLaunchKernelGGL(composite_fwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
+                           reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
+                           bg[0], bg[1], bg[2], image, T_final, n_last, order, blocks, counter);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     return 0;

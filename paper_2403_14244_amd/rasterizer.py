@@ -193,6 +193,33 @@ class Rasterizer:
                                          _stream()))
         return image, T, n_last
 
+    def render_fwd_persistent(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0),
+                              out=None):
+        """render_fwd through the persistent, longest-list-first kernel (same result).
+        `out` optionally supplies (image, T_final, n_last) buffers."""
+        pix = sum(int(c.width) * int(c.height) for c in cams)
+        if out is None:
+            out = (torch.empty(3 * pix, dtype=_F32, device=self.device),
+                   torch.empty(pix, dtype=_F32, device=self.device),
+                   torch.empty(pix, dtype=torch.int32, device=self.device))
+        image, T, n_last = out
+        bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
+        carr = A.camera_array(cams)
+        npv = A.int_array(n_per_view)
+        need = ctypes.c_size_t(0)
+        args = (ctypes.byref(fp.abi()), npv, ctypes.byref(bins.abi()), carr, len(cams), bgc, _p(image), _p(T),
+                _p(n_last))
+        A.check(A.lib().isogs_render_fwd_persistent(*args, None, ctypes.byref(need), _stream()))
+        ws = self._workspace_q(need.value)
+        have = ctypes.c_size_t(ws.numel())
+        A.check(A.lib().isogs_render_fwd_persistent(*args, _p(ws), ctypes.byref(have), _stream()))
+        return image, T, n_last
+
+    def _workspace_q(self, nbytes):
+        if not hasattr(self, "_wsq") or self._wsq.numel() < nbytes:
+            self._wsq = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        return self._wsq
+
     def render_bwd(self, scenes, cams, fp: Footprints, bins: TileBins, bg, dL_dimage, T_final, n_last, grads=None):
         """Returns one GaussianScene of gradients per distinct scene (by pos pointer), in
         order of first appearance; views of one scene are summed."""

@@ -1,0 +1,302 @@
+"""Serving loop: resident scenes, memory-admitted continuous batching, latency statistics.
+
+Requests (scene, camera, arrival time) are admitted in arrival order into batches of
+views. A batch is formed whenever an execution slot is free, from every request that has
+arrived and fits the memory pool; requests that arrive while batches are running are
+admitted as soon as a slot and pool memory free up, and up to `max_inflight` batches run
+concurrently on separate HIP streams, so their work overlaps on the device. Each batch is
+one projection (grouped by scene), one bin sort and one persistent compositing launch.
+
+The scheduler is written against a small executor interface so that its admission,
+batching and statistics logic also runs on the CPU with a simulated executor and a
+virtual clock (see `SimulatedExecutor`); `GpuExecutor` drives the C ABI.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    scene: str
+    cam: object
+    arrival: float                 # seconds on the server clock
+    submit: float | None = None
+    done: float | None = None
+    batch: int | None = None
+    result: object = None
+
+    @property
+    def pixels(self) -> int:
+        return int(self.cam.width) * int(self.cam.height)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class RealClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def sleep_until(self, t: float):
+        dt = t - self.now()
+        if dt > 0:
+            time.sleep(min(dt, 0.002))
+
+
+class VirtualClock:
+    """Deterministic clock for tests: sleeping advances time."""
+
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def sleep_until(self, t: float):
+        self.t = max(self.t, t)
+
+
+class Executor:
+    """What the scheduler needs from a device."""
+
+    def bytes_needed(self, req: Request) -> int:
+        raise NotImplementedError
+
+    def submit(self, batch: list[Request]):
+        """Starts a batch asynchronously; returns a handle."""
+        raise NotImplementedError
+
+    def poll(self, handle) -> bool:
+        raise NotImplementedError
+
+    def finish(self, handle) -> None:
+        """Called once poll() is true: stores each request's result."""
+        raise NotImplementedError
+
+    def next_event_time(self, handle) -> float | None:
+        """For simulated executors: when the batch completes (None if unknown)."""
+        return None
+
+
+class Server:
+    def __init__(self, executor: Executor, pool_bytes: int, max_batch: int = 16, max_inflight: int = 2,
+                 clock=None, keep_results: bool = False):
+        self.ex = executor
+        self.pool = int(pool_bytes)
+        self.max_batch = max_batch
+        self.max_inflight = max_inflight
+        self.clock = clock or RealClock()
+        self.keep_results = keep_results
+        self.used = 0
+        self.peak_used = 0
+        self.batches = []          # (size, submit time, bytes)
+
+    def run(self, requests: list[Request]) -> dict:
+        pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        ready: deque[Request] = deque()
+        inflight = []              # (handle, batch, bytes)
+        finished = []
+        nb = 0
+        for r in pending:
+            if self.ex.bytes_needed(r) > self.pool:
+                raise ValueError(f"request {r.rid} needs more memory than the whole pool")
+        while pending or ready or inflight:
+            now = self.clock.now()
+            while pending and pending[0].arrival <= now:
+                ready.append(pending.popleft())
+            # admit: one new batch per free slot, FIFO, bounded by the pool
+            while ready and len(inflight) < self.max_inflight:
+                batch, need = [], 0
+                while ready and len(batch) < self.max_batch:
+                    b = self.ex.bytes_needed(ready[0])
+                    if self.used + need + b > self.pool:
+                        break
+                    need += b
+                    batch.append(ready.popleft())
+                if not batch:
+                    break
+                t = self.clock.now()
+                for r in batch:
+                    r.submit, r.batch = t, nb
+                h = self.ex.submit(batch)
+                self.used += need
+                self.peak_used = max(self.peak_used, self.used)
+                inflight.append((h, batch, need))
+                self.batches.append((len(batch), t, need))
+                nb += 1
+            # completions
+            still = []
+            for h, batch, need in inflight:
+                if self.ex.poll(h):
+                    self.ex.finish(h)
+                    t = self.clock.now()
+                    for r in batch:
+                        r.done = t
+                        if not self.keep_results:
+                            r.result = None
+                    finished.extend(batch)
+                    self.used -= need
+                else:
+                    still.append((h, batch, need))
+            progressed = len(still) != len(inflight)
+            inflight = still
+            if not progressed:
+                # nothing completed: wait for the next arrival or completion
+                wake = [pending[0].arrival] if pending else []
+                for h, _, _ in inflight:
+                    te = self.ex.next_event_time(h)
+                    if te is not None:
+                        wake.append(te)
+                nxt = min(wake) if wake else self.clock.now() + 1e-4
+                if inflight and not any(self.ex.next_event_time(h) is not None for h, _, _ in inflight):
+                    nxt = min(nxt, self.clock.now() + 5e-5)
+                self.clock.sleep_until(nxt)
+        return self.stats(finished)
+
+    def stats(self, finished: list[Request]) -> dict:
+        if not finished:
+            return dict(requests=0)
+        lat = np.array([r.latency for r in finished]) * 1e3
+        first = min(r.arrival for r in finished)
+        last = max(r.done for r in finished)
+        pix = sum(r.pixels for r in finished)
+        sizes = [b[0] for b in self.batches]
+        by_res = {}
+        for r in finished:
+            by_res.setdefault(f"{r.cam.width}x{r.cam.height}", []).append(r.latency * 1e3)
+        return dict(requests=len(finished), p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), max_ms=float(lat.max()),
+                    mpix_per_s=pix / (last - first) / 1e6, wall_s=last - first,
+                    batches=len(sizes), mean_batch=float(np.mean(sizes)), peak_pool_bytes=self.peak_used,
+                    pool_bytes=self.pool,
+                    p99_ms_by_resolution={k: float(np.percentile(v, 99)) for k, v in sorted(by_res.items())})
+
+
+class SimulatedExecutor(Executor):
+    """CPU stand-in: a batch takes base + per_mpix * megapixels seconds on the clock.
+    Optionally renders each request with a supplied function (e.g. the oracle)."""
+
+    def __init__(self, clock, scenes_n: dict, base=1e-3, per_mpix=2e-4, render=None):
+        self.clock = clock
+        self.scenes_n = scenes_n
+        self.base = base
+        self.per_mpix = per_mpix
+        self.render = render
+        self.n_submitted = 0
+
+    def bytes_needed(self, req):
+        return 40 * self.scenes_n[req.scene] + 20 * req.pixels
+
+    def submit(self, batch):
+        self.n_submitted += 1
+        t = self.clock.now()
+        return dict(batch=batch, t_done=t + self.base + self.per_mpix * sum(r.pixels for r in batch) / 1e6)
+
+    def poll(self, h):
+        return self.clock.now() >= h["t_done"]
+
+    def next_event_time(self, h):
+        return h["t_done"]
+
+    def finish(self, h):
+        if self.render is not None:
+            for r in h["batch"]:
+                r.result = self.render(r)
+
+
+class GpuExecutor(Executor):
+    """Runs batches through the C ABI on `n_streams` HIP streams (default priority)."""
+
+    def __init__(self, scenes: dict, device="cuda", n_streams=2, headroom=1.3):
+        import torch
+        from .rasterizer import Rasterizer
+        self.torch = torch
+        self.scenes = scenes                    # name -> GaussianScene (resident)
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        self.busy = [False] * n_streams
+        self.rasters = [Rasterizer(self.device) for _ in range(n_streams)]
+        self.headroom = headroom
+        self.entries_per_view = {}              # (scene, W, H) -> entries seen
+        self.overflows = 0
+
+    def _key(self, r):
+        return (r.scene, int(r.cam.width), int(r.cam.height))
+
+    def calibrate(self, requests):
+        """Measures entries per (scene, resolution) once, synchronously."""
+        seen = {}
+        for r in requests:
+            seen.setdefault(self._key(r), r)
+        for k, r in seen.items():
+            R = self.rasters[0]
+            g = self.scenes[r.scene]
+            fp = R.project([g], [r.cam])
+            b = R.bin_sort(fp, [g.n], [r.cam])
+            self.entries_per_view[k] = b.n_entries()
+        self.torch.cuda.synchronize()
+
+    def _entries(self, r):
+        k = self._key(r)
+        if k not in self.entries_per_view:
+            self.entries_per_view[k] = 4 * self.scenes[r.scene].n
+        return self.entries_per_view[k]
+
+    def bytes_needed(self, r):
+        n = self.scenes[r.scene].n
+        ent = self._entries(r) * self.headroom
+        # footprints (40 B/particle), entries with ping-pong (24 B), image + state (20 B/px)
+        return int(40 * n + 24 * ent + 20 * r.pixels)
+
+    def submit(self, batch):
+        torch = self.torch
+        si = self.busy.index(False)
+        self.busy[si] = True
+        s = self.streams[si]
+        R = self.rasters[si]
+        cams = [r.cam for r in batch]
+        scenes = [self.scenes[r.scene] for r in batch]
+        npv = [g.n for g in scenes]
+        cap = int(sum(self._entries(r) for r in batch) * self.headroom) + 4096
+        with torch.cuda.stream(s):
+            fp = R.project(scenes, cams)
+            bins = R.bin_sort(fp, npv, cams, check=False, capacity=cap)
+            img, T, nl = R.render_fwd_persistent(fp, npv, bins, cams)
+            status = torch.empty(2, dtype=torch.int32, pin_memory=True)
+            status[0:1].copy_(bins.status, non_blocking=True)
+            status[1:2].copy_(bins.count, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return dict(si=si, batch=batch, ev=ev, fp=fp, bins=bins, img=img, status=status, npv=npv, cams=cams,
+                    scenes=scenes)
+
+    def poll(self, h):
+        return h["ev"].query()
+
+    def finish(self, h):
+        torch = self.torch
+        from .rasterizer import split_images
+        st, count = int(h["status"][0]), int(h["status"][1])
+        R = self.rasters[h["si"]]
+        img = h["img"]
+        if st != 0:
+            # entry capacity overflow: redo this batch with the exact count (rare)
+            self.overflows += 1
+            with torch.cuda.stream(self.streams[h["si"]]):
+                bins = R.bin_sort(h["fp"], h["npv"], h["cams"], check=True,
+                                  capacity=int(count * self.headroom) + 4096)
+                img, _, _ = R.render_fwd_persistent(h["fp"], h["npv"], bins, h["cams"])
+            self.streams[h["si"]].synchronize()
+        for r, im in zip(h["batch"], split_images(img, h["cams"])):
+            r.result = im
+        self.busy[h["si"]] = False

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "isogs.h")
 def _abi():
     from paper_2403_14244_amd import _abi as A
     if not os.path.exists(A.LIB_PATH):
-        pytest.skip("libisogs.so not built (run python -m paper_2403_14244_amd.build)")
+        pytest.skip("libisogs.so not built (run python paper_2403_14244_amd/build.py)")
     return A
 
 

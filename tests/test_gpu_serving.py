@@ -1,0 +1,80 @@
+"""GPU checks of the serving path: the persistent longest-first compositing launch equals
+the one-workgroup-per-tile launch bitwise, and every request served in a mixed,
+continuously batched stream gets exactly the image it gets when rendered alone."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import scenegen as S
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible device"
+    import paper_2403_14244_amd as P
+    return P
+
+
+def _scenes():
+    return {"small": S.mixture_scene(20_000, seed=21, log_scale_mean=math.log(0.01)),
+            "mid": S.mixture_scene(60_000, seed=22),
+            "cube": S.uniform_cube_scene(8000, seed=23, log_scale_mean=math.log(0.03))}
+
+
+def test_persistent_equals_per_tile_launch(P):
+    import torch
+    note("persistent == per-tile")
+    sc = S.mixture_scene(100_000, seed=3)
+    cams = [S.orbit_camera(0.4 * i, 4.0, w, h) for i, (w, h) in enumerate([(640, 360), (512, 512), (333, 190)])]
+    R = P.Rasterizer()
+    g = P.GaussianScene.from_host(sc)
+    fp = R.project([g] * 3, cams)
+    b = R.bin_sort(fp, [g.n] * 3, cams)
+    a = R.render_fwd(fp, [g.n] * 3, b, cams, (0.1, 0.2, 0.3))
+    c = R.render_fwd_persistent(fp, [g.n] * 3, b, cams, (0.1, 0.2, 0.3))
+    torch.cuda.synchronize()
+    for x, y in zip(a, c):
+        assert torch.equal(x, y)
+
+
+def test_served_images_equal_alone_and_in_mix(P):
+    import torch
+    from paper_2403_14244_amd.serving import GpuExecutor, Request, Server
+    note("serving: alone vs mixed")
+    host = _scenes()
+    dev = {k: P.GaussianScene.from_host(v) for k, v in host.items()}
+    rng = np.random.default_rng(5)
+    res = [(96, 64), (128, 128), (200, 120)]
+    reqs, t = [], 0.0
+    for i in range(40):
+        t += rng.exponential(1 / 2000.0)
+        w, h = res[int(rng.integers(3))]
+        reqs.append(Request(rid=i, scene=list(host)[int(rng.integers(3))],
+                            cam=S.orbit_camera(float(rng.uniform(0, 2 * math.pi)), 4.0, w, h), arrival=t))
+    ex = GpuExecutor(dev)
+    ex.calibrate(reqs)
+    srv = Server(ex, pool_bytes=1 << 30, max_batch=8, max_inflight=2, keep_results=True)
+    st = srv.run(reqs)
+    torch.cuda.synchronize()
+    note(f"  served {st['requests']} in {st['batches']} batches, mean {st['mean_batch']:.2f}")
+    assert st["requests"] == 40 and st["mean_batch"] > 1.0
+    R = P.Rasterizer()
+    for r in reqs:
+        alone, _ = R.render([dev[r.scene]], [r.cam])
+        assert torch.equal(alone[0], r.result), r.rid
+    # and a few against the oracle (end to end, FP64)
+    for r in reqs[:3]:
+        ref, _, _, flags, _, _ = O.render_views([host[r.scene]], [r.cam], alpha_band=2.0 ** -12, term_band=2.0 ** -8)
+        d = np.abs(r.result.cpu().numpy().astype(np.float64) - ref[0]).max(axis=0)
+        assert d[~flags[0]].max() <= 1e-4, (r.rid, float(d[~flags[0]].max()))
