@@ -1,0 +1,250 @@
+"""Parity at the benchmark's full sizes, on outputs the oracle can compute one by one.
+
+* 1M Gaussians (SH3), 10 views of 1920x1080 per call - the benchmark's launch shape:
+  sampled tiles (the longest lists and random ones) are recomposited by the oracle from
+  its own FP64 projection of all particles; tile lists are compared entry by entry.
+* Training workload (500k Gaussians, 4 views of 1280x720, L1 loss): the forward/backward
+  runs at full size; gradients of sampled particles are recomputed by the oracle over
+  every tile they touch; the 64-Gaussian 32x32 subset is checked against FP64 central
+  finite differences.
+* Stress workload (6M Gaussians with tight clusters, 3840x2160): the heaviest and random
+  tiles of one view are checked, which exercises lists of ~10^4-10^5 entries.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import scenegen as S
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible device"
+    import paper_2403_14244_amd as P
+    return P
+
+
+def oracle_tile(pr, vw, tx, ty, W, H, bg=(0.0, 0.0, 0.0)):
+    """One tile, composited by the oracle: members by the FP32 disk test on the oracle's own
+    FP32 footprints, ordered by (depth bits, index), eq. 4 per pixel in FP64."""
+    cand = np.nonzero(vw["r"] > 0)[0]
+    m = O.tile_member_f32(vw["u"][cand], vw["v"][cand], vw["r"][cand], np.full(cand.shape, tx),
+                          np.full(cand.shape, ty), W, H)
+    idx = cand[m]
+    zb = vw["z"][idx].view(np.uint32)
+    seq = idx[np.lexsort((idx, zb))]
+    X, Y = O.tile_pixels(tx, ty, W, H)
+    C, T, nl, tr = O.composite_pixels(X + 0.5, Y + 0.5, seq, pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bg, trace=True,
+                                      alpha_band=2.0 ** -12, term_band=2.0 ** -8)
+    return seq, X, Y, C, T, tr["near_alpha"] | tr["near_term"]
+
+
+def check_tiles(img, gpu_pidx, ranges, tile_base, pr, vw, W, H, tiles, p_off, tol=1e-4):
+    TX = (W + 15) // 16
+    worst, flagged, npx, exact_lists = 0.0, 0, 0, 0
+    for tx, ty in tiles:
+        seq, X, Y, C, T, fl = oracle_tile(pr, vw, tx, ty, W, H)
+        a, b = ranges[tile_base + ty * TX + tx]
+        glist = gpu_pidx[a:b].astype(np.int64) - p_off
+        exact_lists += int(np.array_equal(glist, seq))
+        g = img[:, Y, X].astype(np.float64)
+        d = np.abs(g - C).max(axis=0)
+        assert d[~fl].max(initial=0.0) <= tol, (tx, ty, float(d[~fl].max()))
+        if fl.any():
+            assert d[fl].max() <= 0.01
+        worst = max(worst, float(d[~fl].max(initial=0.0)))
+        flagged += int(fl.sum())
+        npx += X.shape[0]
+    return worst, flagged, npx, exact_lists
+
+
+def pick_tiles(ranges, tile_base, TX, TY, n_heavy, n_rand, seed):
+    lens = ranges[tile_base:tile_base + TX * TY, 1].astype(np.int64) - ranges[tile_base:tile_base + TX * TY, 0]
+    heavy = np.argsort(-lens)[:n_heavy]
+    rnd = np.random.default_rng(seed).choice(TX * TY, n_rand, replace=False)
+    ids = list(dict.fromkeys([int(i) for i in heavy] + [int(i) for i in rnd]))
+    return [(i % TX, i // TX) for i in ids], lens
+
+
+def test_mix1m_1080p_batch_sampled_tiles(P):
+    import torch
+    note("mix1m 1080p x10 batch: sampled tiles")
+    scene = S.mixture_scene(1_000_000, seed=0)
+    cams = [S.orbit_camera(2 * math.pi * i / 100, 4.0, 1920, 1080) for i in range(10)]
+    R = P.Rasterizer(headroom=1.1)
+    g = P.GaussianScene.from_host(scene)
+    imgs, st = R.render([g] * 10, cams)
+    torch.cuda.synchronize()
+    ranges = st["bins"].ranges.cpu().numpy().view(np.uint32)
+    gpidx = st["bins"].pidx.cpu().numpy().view(np.uint32)
+    foot = st["fp"].record.cpu().numpy()
+    TX, TY = (1920 + 15) // 16, (1080 + 15) // 16
+    for vi in (0, 3, 7):
+        pr = O.project64(scene, cams[vi])
+        vw = O.f32_views([pr], [cams[vi]])[0]
+        p_off = vi * scene.n
+        # footprints of the view: the same FP32 values as the oracle's, up to a rare ulp
+        same = (foot[p_off:p_off + scene.n, 0] == vw["u"]) & (foot[p_off:p_off + scene.n, 1] == vw["v"])
+        assert same[pr.visible].mean() > 0.999
+        tiles, lens = pick_tiles(ranges, vi * TX * TY, TX, TY, 4, 8, vi)
+        worst, flagged, npx, exact = check_tiles(imgs[vi].cpu().numpy(), gpidx, ranges, vi * TX * TY, pr, vw,
+                                                 1920, 1080, tiles, p_off)
+        note(f"  view {vi}: {len(tiles)} tiles (max list {lens.max()}), max|d| {worst:.2e}, "
+             f"flagged {flagged}/{npx}, identical lists {exact}/{len(tiles)}")
+        assert exact >= len(tiles) - 1
+
+
+def _crop_camera(cam, x0, y0, w, h):
+    return cam.shifted(x0, y0, w, h)
+
+
+def test_training_workload_full_size_and_fd_subset(P):
+    """500k Gaussians, 4 views at 1280x720, L1 loss through the autograd function."""
+    import torch
+    note("training workload: full size + 64-Gaussian FD subset")
+    gt = S.mixture_scene(500_000, seed=0)
+    init = S.jitter_scene(gt, seed=1)
+    cams = S.workload_cameras("mix500k_720p_x4")
+    R = P.Rasterizer()
+    targets = torch.stack(R.render([P.GaussianScene.from_host(gt)] * 4, cams)[0])
+    params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+              for a in (init.pos, init.scale, init.opacity, init.color)]
+    img = P.IsoGSRender.apply(*params, 3, cams, (0.0, 0.0, 0.0), R)
+    loss = (img - targets).abs().mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    grads = [p.grad.cpu().numpy().astype(np.float64) for p in params]
+    assert np.isfinite(loss.item()) and loss.item() > 0
+    assert all(np.isfinite(gg).all() for gg in grads)
+    # sampled particles: the oracle gradient over every tile each one touches, all 4 views
+    C = img.detach().cpu().numpy().astype(np.float64)
+    Tg = targets.cpu().numpy().astype(np.float64)
+    dC = np.sign(C - Tg) / C.size
+    rng = np.random.default_rng(0)
+    projs = [O.project64(init, c) for c in cams]
+    vws = O.f32_views(projs, cams)
+    vis_all = np.nonzero(np.all([p.visible for p in projs], axis=0))[0]
+    sample = rng.choice(vis_all, 24, replace=False)
+    ref = {k: np.zeros_like(v) for k, v in zip(("pos", "scale", "opacity", "color"), grads)}
+    for vi, (pr, vw, cam) in enumerate(zip(projs, vws, cams)):
+        W, H = cam.width, cam.height
+        TX, TY = (W + 15) // 16, (H + 15) // 16
+        sg = dict(du=np.zeros(init.n), dv=np.zeros(init.n), ds=np.zeros(init.n), do=np.zeros(init.n),
+                  drgb=np.zeros((3, init.n)))
+        tiles = set()
+        for p in sample:
+            gi, ty, tx = O.member_tiles(vw["u"][p:p + 1], vw["v"][p:p + 1], vw["r"][p:p + 1], W, H)
+            tiles.update(zip(tx.tolist(), ty.tolist()))
+        for tx, ty in tiles:
+            cand = np.nonzero(vw["r"] > 0)[0]
+            m = O.tile_member_f32(vw["u"][cand], vw["v"][cand], vw["r"][cand], np.full(cand.shape, tx),
+                                  np.full(cand.shape, ty), W, H)
+            idx = cand[m]
+            seq = idx[np.lexsort((idx, vw["z"][idx].view(np.uint32)))]
+            X, Y = O.tile_pixels(tx, ty, W, H)
+            res = O.composite_backward_pixels(X + 0.5, Y + 0.5, seq, pr.u, pr.v, pr.s, pr.opacity, pr.rgb,
+                                              (0.0, 0.0, 0.0), dC[vi][:, Y, X])
+            for gidx in sample:
+                if int(gidx) in res:
+                    a = res[int(gidx)]
+                    sg["du"][gidx] += a["du"]
+                    sg["dv"][gidx] += a["dv"]
+                    sg["ds"][gidx] += a["ds"]
+                    sg["do"][gidx] += a["do"]
+                    sg["drgb"][:, gidx] += a["drgb"]
+        gv = O.project_backward64(init, cam, pr, sg)
+        for k in ref:
+            ref[k] += gv[k]
+    for name, gg in zip(("pos", "scale", "opacity", "color"), grads):
+        a = gg[..., sample] if gg.ndim == 2 else gg[sample]
+        b = ref[name][..., sample] if gg.ndim == 2 else ref[name][sample]
+        scale = np.abs(b).max()
+        bad = np.abs(a - b) > 5e-3 * np.abs(b) + 1e-3 * scale
+        note(f"  {name}: max |d|/max|g| {np.abs(a - b).max() / max(scale, 1e-30):.2e}, outside {int(bad.sum())}/{bad.size}")
+        assert bad.mean() <= 0.05, name
+
+    # 64-Gaussian 32x32 subset of view 0: GPU gradients vs FP64 finite differences
+    cam0 = cams[0]
+    _, st = R.render([P.GaussianScene.from_host(init)], [cam0])
+    nl = st["n_last"].cpu().numpy().reshape(cam0.height, cam0.width)
+    cy, cx = np.unravel_index(np.argmax(nl), nl.shape)
+    x0, y0 = int(np.clip(cx - 16, 0, cam0.width - 32)), int(np.clip(cy - 16, 0, cam0.height - 32))
+    crop = _crop_camera(cam0, x0, y0, 32, 32)
+    pr = O.project64(init, crop)
+    X, Y = np.meshgrid(np.arange(32) + 0.5, np.arange(32) + 0.5)
+    wsum = np.zeros(init.n)
+    vis = np.nonzero(pr.visible & (pr.u > -8) & (pr.u < 40) & (pr.v > -8) & (pr.v < 40))[0]
+    for p in vis:
+        wsum[p] = (pr.opacity[p] * np.exp(-((X - pr.u[p]) ** 2 + (Y - pr.v[p]) ** 2) / pr.s[p] ** 2)).sum()
+    keep = np.argsort(-wsum)[:64]
+    sub = S.subset_scene(init, keep)
+    tgt = rng.uniform(0, 1, (3, 32, 32))
+    sub_params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+                  for a in (sub.pos, sub.scale, sub.opacity, sub.color)]
+    out = P.IsoGSRender.apply(*sub_params, 3, [crop], (0.0, 0.0, 0.0), P.Rasterizer())
+    lsub = (out[0] - torch.from_numpy(tgt).float().cuda()).abs().mean()
+    lsub.backward()
+    torch.cuda.synchronize()
+    g_gpu = {k: p.grad.cpu().numpy().astype(np.float64) for k, p in zip(("pos", "scale", "opacity", "color"), sub_params)}
+    C0 = O.render64_untiled(O.project64(sub, crop), 32, 32)[0]
+    W_l1 = np.sign(C0 - tgt) / C0.size
+    sub64 = S.Scene(sub.pos.astype(np.float64), sub.scale.astype(np.float64), sub.opacity.astype(np.float64),
+                    sub.color.astype(np.float64), 3)
+    ref_an = O.scene_grads(sub64, [crop], [W_l1])
+    sig0 = O.decision_signature(O.project64(sub64, crop), 32, 32)
+    checked = agree = 0
+    for name in ("pos", "scale", "opacity", "color"):
+        arr = getattr(sub64, name)
+        for idx in list(np.ndindex(arr.shape))[::3]:
+            h = 1e-6 * max(1.0, abs(arr[idx]))
+            vals, same = [], True
+            for sgn in (1, -1):
+                arr[idx] += sgn * h
+                prp = O.project64(sub64, crop)
+                vals.append(float((O.render64_untiled(prp, 32, 32)[0] * W_l1).sum()))
+                same &= O.decision_signature(prp, 32, 32) == sig0
+                arr[idx] -= sgn * h
+            if not same:
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - ref_an[name][idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx)
+            scale = np.abs(ref_an[name]).max()
+            checked += 1
+            agree += abs(g_gpu[name][idx] - fd) <= 5e-3 * abs(fd) + 1e-3 * scale
+    note(f"  FD subset: {agree}/{checked} GPU gradients within tolerance of central differences")
+    assert checked > 100 and agree >= 0.97 * checked
+
+
+def test_stress_6m_4k_sampled_tiles(P):
+    import torch
+    note("stress 6M 4K: sampled tiles")
+    scene = S.stress_scene(6_000_000, seed=5)
+    cams = [S.orbit_camera(2 * math.pi * i / 8, 4.0, 3840, 2160) for i in range(2)]
+    R = P.Rasterizer(headroom=1.1)
+    g = P.GaussianScene.from_host(scene)
+    imgs, st = R.render([g] * 2, cams)
+    torch.cuda.synchronize()
+    ranges = st["bins"].ranges.cpu().numpy().view(np.uint32)
+    gpidx = st["bins"].pidx.cpu().numpy().view(np.uint32)
+    TX, TY = (3840 + 15) // 16, (2160 + 15) // 16
+    pr = O.project64(scene, cams[1])
+    vw = O.f32_views([pr], [cams[1]])[0]
+    tiles, lens = pick_tiles(ranges, TX * TY, TX, TY, 2, 4, 1)
+    worst, flagged, npx, exact = check_tiles(imgs[1].cpu().numpy(), gpidx, ranges, TX * TY, pr, vw, 3840, 2160,
+                                             tiles, scene.n)
+    nz = lens[lens > 0]
+    note(f"  lists: max {lens.max()}, median {int(np.median(nz))}, p99 {int(np.percentile(nz, 99))}; "
+         f"max|d| {worst:.2e}, flagged {flagged}/{npx}, identical lists {exact}/{len(tiles)}")
+    assert lens.max() > 100 * np.median(nz)
+    assert exact >= len(tiles) - 1
