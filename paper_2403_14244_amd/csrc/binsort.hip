@@ -202,8 +202,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ count_p, uint64_t capacity, int pass,
     const uint32_t* __restrict__ hist, uint32_t* __restrict__ lookback, uint32_t* __restrict__ ticket,
     int32_t* __restrict__ status) {
-    __shared__ uint64_t s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint64_t s_buf[kSortTile];   // tile reordered by digit: keys, then values
     __shared__ uint32_t s_wcnt[4][kRadix];
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint32_t s_base[kRadix];
@@ -296,26 +295,42 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
     s_local[t] = lbase;
     __syncthreads();
 
-    // reorder in LDS by digit (stable), then write runs
+    // reorder in LDS by digit (stable), then write runs: keys first, then the values
+    // through the same buffer (halves the LDS a workgroup needs)
+    uint32_t lpos[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
+        lpos[i] = 0xFFFFFFFFu;
         if (wbase + i * kWave + lane < count) {
             const uint32_t d = digit_of(k[i], shift);
-            const uint32_t pos = s_local[d] + s_wcnt[w][d] + rk[i];
-            s_keys[pos] = k[i];
-            s_vals[pos] = v[i];
+            lpos[i] = s_local[d] + s_wcnt[w][d] + rk[i];
+            s_buf[lpos[i]] = k[i];
         }
     }
     __syncthreads();
     const uint32_t n_here = min((uint32_t)kSortTile, count - tile * kSortTile);
-    for (uint32_t j = t; j < n_here; j += kSortThreads) {
-        const uint64_t key = s_keys[j];
-        const uint32_t d = digit_of(key, shift);
-        const uint32_t dst = s_base[d] + (j - s_local[d]);
-        if (dst < count) {
-            kout[dst] = key;
-            vout[dst] = s_vals[j];
+    uint32_t dst[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t j = t + i * kSortThreads;
+        dst[i] = 0xFFFFFFFFu;
+        if (j < n_here) {
+            const uint64_t key = s_buf[j];
+            const uint32_t d = digit_of(key, shift);
+            dst[i] = s_base[d] + (j - s_local[d]);
+            if (dst[i] < count) kout[dst[i]] = key;
         }
+    }
+    __syncthreads();
+    uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (lpos[i] != 0xFFFFFFFFu) s_val[lpos[i]] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t j = t + i * kSortThreads;
+        if (j < n_here && dst[i] < count) vout[dst[i]] = s_val[j];
     }
 }
 
