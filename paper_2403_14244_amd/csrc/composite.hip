@@ -24,8 +24,8 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
 }
 
 // Composites one tile (logical index within the launch) with a 256-thread workgroup, one
-// lane per pixel; wave w owns quadrant w. Contains __syncthreads.
-__device__ __forceinline__ void composite_tile(StagedBatch& sb, const RenderPack& pk, uint32_t logical,
+// lane per pixel; each 16-lane row owns a 4x4 sub-block. Contains __syncthreads.
+__device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& pk, uint32_t logical,
                                                const float4* __restrict__ record,
                                                const uint32_t* __restrict__ pidx,
                                                const uint32_t* __restrict__ ranges, float bg_r, float bg_g,
@@ -35,12 +35,13 @@ __device__ __forceinline__ void composite_tile(StagedBatch& sb, const RenderPack
     locate_tile(pk, logical, vi, tx, ty);
     const ViewDesc& vd = pk.v[vi];
     const uint32_t t = threadIdx.x, w = t >> 6;
-    const int x = tx * kTile + quad_x(t), y = ty * kTile + quad_y(t);
+    const int x = tx * kTile + sub_x(t), y = ty * kTile + sub_y(t);
     const bool inside = x < vd.width && y < vd.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
     const uint32_t start = ranges[2 * gt], end = min(ranges[2 * gt + 1], pk.n_entries_cap);
     const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
+    const uint32_t sbk = 4 * w + ((t >> 4) & 3u);   // this lane's sub-block
 
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     uint32_t last = 0;
@@ -48,12 +49,12 @@ __device__ __forceinline__ void composite_tile(StagedBatch& sb, const RenderPack
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_and(done)) break;
         const uint32_t nb = min((uint32_t)kBatch, end - b0);
-        const uint32_t n4 = stage_batch<false>(sb, record, pidx, pk.n_particles, b0, nb, false, tx * kTile,
-                                               ty * kTile, w_lim, h_lim);
+        const uint32_t steps = stage_batch_sub(sb, record, pidx, pk.n_particles, b0, nb, tx * kTile, ty * kTile,
+                                               w_lim, h_lim);
         const uint32_t pos0 = b0 - start + 1;   // 1-based list position of staged slot 0
-        for (uint32_t k = 0; k < n4; k += 4) {
+        for (uint32_t k = 0; k < steps; k += 4) {
             uint32_t j[4];
-            list4(sb, w, k, j);
+            list4_sub(sb, sbk, k, j);
             const float4 f0 = sb.fp[j[0]], f1 = sb.fp[j[1]], f2 = sb.fp[j[2]], f3 = sb.fp[j[3]];
             const float4 c0 = sb.col[j[0]], c1 = sb.col[j[1]], c2 = sb.col[j[2]], c3 = sb.col[j[3]];
             composite_entry(f0, c0, px, py, pos0 + j[0], T, cr, cg, cb, last, done);
@@ -80,7 +81,7 @@ __global__ void __launch_bounds__(256) composite_fwd_kernel(
     const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
     float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
     uint32_t* __restrict__ n_last) {
-    __shared__ StagedBatch sb;
+    __shared__ StagedSub sb;
     if (*status != kStatusOk) return;
     composite_tile(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, ranges, bg_r, bg_g, bg_b, image,
                    T_final, n_last);
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(256) composite_fwd_persistent_kernel(
     const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
     float* __restrict__ image, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
     const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* __restrict__ counter) {
-    __shared__ StagedBatch sb;
+    __shared__ StagedSub sb;
     __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
     for (;;) {

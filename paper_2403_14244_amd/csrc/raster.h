@@ -119,6 +119,99 @@ __device__ __forceinline__ void list4(const StagedBatch& sb, uint32_t w, uint32_
     j[3] = hi >> 16;
 }
 
+// ---- Forward-pass staging with 4x4 sub-blocks -------------------------------------------
+// Each wave owns an 8x8 quadrant; its four 16-lane rows own the quadrant's four 4x4
+// sub-blocks (lane l: row g = l / 16 covers sub-block g, pixel (l % 4, (l / 4) % 4)). Every
+// sub-block gets its own ordered list of the staged entries whose binning disk touches
+// it, and the rows of a wave walk their lists side by side: a footprint much smaller than
+// a quadrant costs a quarter of a wave step instead of a full one.
+__device__ __forceinline__ int sub_x(uint32_t t) {
+    return (int)(((t >> 6) & 1u) * 8u + (((t >> 4) & 3u) & 1u) * 4u + (t & 3u));
+}
+__device__ __forceinline__ int sub_y(uint32_t t) {
+    return (int)(((t >> 6) >> 1) * 8u + (((t >> 4) & 3u) >> 1) * 4u + ((t >> 2) & 3u));
+}
+
+struct StagedSub {
+    float4 fp[kBatch + 1];      // {u, v, q = log2(e)/s^2, log2(o)}
+    float4 col[kBatch + 1];     // {r, g, b, o}
+    uint16_t list[16][kBatch + 4];
+    uint32_t cnt[4][16];        // [loader wave][sub-block]
+    uint32_t len[16];           // padded list lengths (multiples of 4)
+};
+
+// Stages entries [first, first + n_in_batch) and builds the 16 sub-block lists. Returns the
+// number of list steps of the calling wave (the longest of its four rows' padded lists).
+// Contains __syncthreads.
+__device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4* __restrict__ record,
+                                                    const uint32_t* __restrict__ pidx, uint32_t n_particles,
+                                                    uint32_t first, uint32_t n_in_batch, int tile_x0, int tile_y0,
+                                                    float w_lim, float h_lim) {
+    const uint32_t t = threadIdx.x, w = t >> 6;
+    uint32_t mask = 0;
+    const uint32_t g = t < n_in_batch ? pidx[first + t] : 0xFFFFFFFFu;
+    if (g < n_particles) {
+        const float4 f = record[2 * (size_t)g];
+        const float4 c = record[2 * (size_t)g + 1];
+        sb.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
+        sb.col[t] = make_float4(c.x, c.y, c.z, f.w);
+        const float r2 = c.w * c.w;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            // sub-block k = 4 * quadrant + row; quadrant (k/4) at (8 (k/4 % 2), 8 (k/4 / 2))
+            const int qx = ((k >> 2) & 1) * 8 + (k & 1) * 4, qy = ((k >> 2) >> 1) * 8 + ((k & 3) >> 1) * 4;
+            const float x_lo = (float)(tile_x0 + qx) + 0.5f, y_lo = (float)(tile_y0 + qy) + 0.5f;
+            const float x_hi = fminf(x_lo + 3.0f, w_lim), y_hi = fminf(y_lo + 3.0f, h_lim);
+            const float dx = fmaxf(fmaxf(x_lo - f.x, f.x - x_hi), 0.0f);
+            const float dy = fmaxf(fmaxf(y_lo - f.y, f.y - y_hi), 0.0f);
+            if (x_lo <= w_lim && y_lo <= h_lim && dx * dx + dy * dy <= r2) mask |= 1u << k;
+        }
+    }
+    if (t == 0) {
+        sb.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
+        sb.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    uint64_t bal[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) bal[k] = ballot64((mask >> k) & 1u);
+    if (lane_id() < 16) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c = (lane_id() == (uint32_t)k) ? (uint32_t)__popcll(bal[k]) : c;
+        sb.cnt[w][lane_id()] = c;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if ((mask >> k) & 1u) {
+            uint32_t pos = rank_below(bal[k]);
+            pos += (w > 0 ? sb.cnt[0][k] : 0u) + (w > 1 ? sb.cnt[1][k] : 0u) + (w > 2 ? sb.cnt[2][k] : 0u);
+            sb.list[k][pos] = (uint16_t)t;
+        }
+    }
+    if (t < 64) {
+        // pad sub-block k = t / 4 with dummies up to a multiple of four
+        const uint32_t k = t >> 2;
+        const uint32_t n = sb.cnt[0][k] + sb.cnt[1][k] + sb.cnt[2][k] + sb.cnt[3][k];
+        const uint32_t padded = (n + 3u) & ~3u;
+        if (n + (t & 3u) < padded) sb.list[k][n + (t & 3u)] = (uint16_t)kDummy;
+        if ((t & 3u) == 0) sb.len[k] = padded;
+    }
+    __syncthreads();
+    const uint32_t a = sb.len[4 * w], b = sb.len[4 * w + 1], c = sb.len[4 * w + 2], d = sb.len[4 * w + 3];
+    return __builtin_amdgcn_readfirstlane(max(max(a, b), max(c, d)));
+}
+
+// Four consecutive entries of this lane's sub-block list from step k (dummies past its end).
+__device__ __forceinline__ void list4_sub(const StagedSub& sb, uint32_t sbk, uint32_t k, uint32_t j[4]) {
+    uint64_t q = 0x0100010001000100ull;   // four kDummy (256) indices
+    if (k < sb.len[sbk]) q = *reinterpret_cast<const uint64_t*>(&sb.list[sbk][k]);
+    j[0] = (uint32_t)q & 0xFFFFu;
+    j[1] = (uint32_t)(q >> 16) & 0xFFFFu;
+    j[2] = (uint32_t)(q >> 32) & 0xFFFFu;
+    j[3] = (uint32_t)(q >> 48);
+}
+
 struct RenderPack {
     int32_t nv;
     uint32_t n_particles;                  // packed particles of the whole batch
