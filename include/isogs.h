@@ -186,9 +186,11 @@ int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_pe
  *   grads          host array [V] of output buffers in scene layout; views whose scene
  *                  pointers (pos) are equal must pass equal grads entries: their
  *                  gradients are summed in view order. Outputs are overwritten.
- *   ws, ws_bytes   workspace (query with ws == NULL): 32 bytes per entry of capacity;
- *                  each entry's gradient record is stored at its emit position, so a
- *                  particle's records are contiguous
+ *   ws, ws_bytes   workspace (query with ws == NULL, 256-byte aligned): 32 bytes per
+ *                  entry of capacity - each entry's gradient record is stored at its emit
+ *                  position, so a particle's records are contiguous - plus a tile queue of
+ *                  4 bytes per tile of the largest group of 16 views (tiles are walked
+ *                  longest entry list first by a persistent grid)
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
 int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,

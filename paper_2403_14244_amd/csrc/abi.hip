@@ -203,14 +203,14 @@ int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_
     if (!scenes || !grads) return fail(ISOGS_ERR_INVALID, "scenes or grads is NULL");
     if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
     if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
-    const size_t need = (size_t)bins->capacity * 32 + 256;
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    const size_t need = isogs::render_bwd_ws(bins->capacity, cams, n_views);
     if (!ws) {
         *ws_bytes = need;
         return ISOGS_OK;
     }
     if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
     if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    if ((rc = check_cameras(cams, n_views))) return rc;
     int32_t npv[kMaxBatchViews];
     for (int v = 0; v < n_views; ++v) {
         if ((rc = check_scene(scenes[v], v, false))) return rc;

@@ -9,26 +9,103 @@
 //   2. grad_project   per particle: sum its records (consecutive in emit order, views in
 //                     order) and chain them to mu, sigma, o and the colour coefficients.
 // There are no floating-point atomics: every sum has a fixed order.
+#include <algorithm>
+
 #include "raster.h"
 
 namespace isogs {
 
-// One workgroup per tile. Record of an entry: {du, dv, d(1/s^2), do} {dr, dg, db, 0}.
-__global__ void __launch_bounds__(256) composite_bwd_kernel(
-    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
-    float bg_r, float bg_g, float bg_b,
-    const float* __restrict__ dL_dimage, const float* __restrict__ T_final, const uint32_t* __restrict__ n_last,
-    float4* __restrict__ rec) {
-    __shared__ StagedBatch sb;
-    __shared__ float s_part[4][7][kBatch];
-    __shared__ uint32_t s_wmax[4];
-    if (*status != kStatusOk) return;
+constexpr int kBwdBatch = 64;          // entries staged per round (one per lane of a wave)
+constexpr int kBwdDummy = kBwdBatch;   // staged slot of the zero-opacity pad record
+
+// One batch of a tile's entries in LDS, back to front, with the 16 sub-block lists.
+struct StagedBwd {
+    float4 fp[kBwdBatch + 1];            // {u, v, q = log2(e)/s^2, log2(o)}
+    float4 col[kBwdBatch + 1];           // {r, g, b, o}
+    uint16_t list[16][kBwdBatch + 4];    // per sub-block, staged slots in walk order
+    uint32_t slot[kBwdBatch];            // emit position of each staged entry
+    uint8_t mask[4][kBwdBatch];          // [wave] which of its sub-blocks listed the entry
+    float part[16][7][kBwdBatch];        // per-sub-block gradient sums of each entry
+    uint32_t gmax[16];                   // largest n_last of each sub-block
+};
+
+// Stages the nb entries below list position `hi` back to front (staged slot l holds entry
+// hi - 1 - l, 1-based tile position pos_hi - l) and builds the 16 sub-block lists. Every
+// wave tests the entries against its own quadrant's four sub-blocks, so the lists of a
+// wave are built from its own ballots. An entry joins a sub-block's list when its binning
+// disk touches the sub-block and its position is at most the sub-block's largest n_last
+// (no later entry was composited there). Returns the number of list steps of the calling
+// wave; `len` receives the padded length of this lane's row list. Contains __syncthreads.
+__device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __restrict__ record,
+                                              const uint32_t* __restrict__ pidx,
+                                              const uint32_t* __restrict__ offsets, uint32_t n_particles,
+                                              uint32_t hi, uint32_t nb, uint32_t pos_hi, int tx, int ty,
+                                              int tiles_x, int tiles_y, float w_lim, float h_lim, uint32_t& len) {
+    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+    const uint32_t g = l < nb ? pidx[hi - 1 - l] : 0xFFFFFFFFu;
+    uint32_t mask = 0;
+    if (g < n_particles) {
+        const float4 f = record[2 * (size_t)g];
+        const float4 c = record[2 * (size_t)g + 1];
+        if (w == 0) {
+            sb.fp[l] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
+            sb.col[l] = make_float4(c.x, c.y, c.z, f.w);
+        } else if (w == 1) {
+            sb.slot[l] = emit_slot(offsets[g], f.x, f.y, c.w, tx, ty, tiles_x, tiles_y, w_lim, h_lim);
+        }
+        const float r2 = c.w * c.w;
+        const uint32_t pos1 = pos_hi - l;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 4 * (int)w + r;
+            if (pos1 <= sb.gmax[k] && sub_block_touched(f.x, f.y, r2, k, tx * kTile, ty * kTile, w_lim, h_lim))
+                mask |= 1u << r;
+        }
+    } else if (w == 1) {
+        sb.slot[l] = 0xFFFFFFFFu;
+    }
+    if (t == 0) {
+        sb.fp[kBwdDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
+        sb.col[kBwdDummy] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    sb.mask[w][l] = (uint8_t)mask;
+    uint64_t bal[4];
+    uint32_t cnt[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        bal[r] = ballot64((mask >> r) & 1u);
+        cnt[r] = (uint32_t)__popcll(bal[r]);
+        if ((mask >> r) & 1u) sb.list[4 * w + r][rank_below(bal[r])] = (uint16_t)l;
+    }
+    if (l < 16) {
+        // pad row l / 4 of this wave with dummies up to a multiple of four
+        const uint32_t r = l >> 2;
+        const uint32_t n = r == 0 ? cnt[0] : r == 1 ? cnt[1] : r == 2 ? cnt[2] : cnt[3];
+        if (n + (l & 3u) < ((n + 3u) & ~3u)) sb.list[4 * w + r][n + (l & 3u)] = (uint16_t)kBwdDummy;
+    }
+    const uint32_t row = l >> 4;
+    const uint32_t mine = row == 0 ? cnt[0] : row == 1 ? cnt[1] : row == 2 ? cnt[2] : cnt[3];
+    len = (mine + 3u) & ~3u;
+    const uint32_t most = max(max(cnt[0], cnt[1]), max(cnt[2], cnt[3]));
+    __syncthreads();
+    return (most + 3u) & ~3u;
+}
+
+// Reverse walk of one tile (logical index within the launch) by a 256-thread workgroup,
+// one lane per pixel, each 16-lane row owning a 4x4 sub-block (the forward pixel layout).
+// Record of an entry: {du, dv, d(1/s^2), do} {dr, dg, db, 0}, at its emit position.
+// Contains __syncthreads.
+__device__ __forceinline__ void composite_bwd_tile(
+    StagedBwd& sb, const RenderPack& pk, uint32_t logical, const float4* __restrict__ record,
+    const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges,
+    float bg_r, float bg_g, float bg_b, const float* __restrict__ dL_dimage, const float* __restrict__ T_final,
+    const uint32_t* __restrict__ n_last, float4* __restrict__ rec) {
     int vi, tx, ty;
-    locate_tile(pk, xcd_swizzle(blockIdx.x, gridDim.x), vi, tx, ty);
+    locate_tile(pk, logical, vi, tx, ty);
     const ViewDesc& vd = pk.v[vi];
-    const uint32_t t = threadIdx.x, w = t >> 6;
-    const int x = tx * kTile + quad_x(t), y = ty * kTile + quad_y(t);
+    const uint32_t t = threadIdx.x, w = t >> 6, lane = lane_id();
+    const uint32_t sbk = 4 * w + ((t >> 4) & 3u);   // this lane's sub-block
+    const int x = tx * kTile + sub_x(t), y = ty * kTile + sub_y(t);
     const bool inside = x < vd.width && y < vd.height;
     const float px = (float)x + 0.5f, py = (float)y + 0.5f;
     const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
@@ -50,23 +127,22 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
     // light arriving from behind the current entry: sum of later c alpha T, plus T_final bg
     float Sr = T * bg_r, Sg = T * bg_g, Sb = T * bg_b;
 
-    if (t < 4) s_wmax[t] = 0u;
+    if (t < 16) sb.gmax[t] = 0u;
     __syncthreads();
-    if (last) atomicMax(&s_wmax[w], last);
+    if (last) atomicMax(&sb.gmax[sbk], last);
     __syncthreads();
-    // the walk starts at the largest n_last of the tile; each wave skips the entries above
-    // its own largest n_last
-    const uint32_t wmax = __builtin_amdgcn_readfirstlane(s_wmax[w]);
-    const uint32_t max_last = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
+    uint32_t max_last = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) max_last = max(max_last, sb.gmax[k]);
+    max_last = min(max_last, end > start ? end - start : 0u);
+
     // entries no pixel reached carry zero gradient
-    for (uint32_t b0 = start + max_last; b0 < end; b0 += kBatch) {
-        const uint32_t e = b0 + t;
-        const uint32_t g = e < end ? pidx[e] : 0xFFFFFFFFu;
+    for (uint32_t e = start + max_last + t; e < end; e += 256) {
+        const uint32_t g = pidx[e];
         if (g < pk.n_particles) {
             const float4 f = record[2 * (size_t)g];
             const float r = record[2 * (size_t)g + 1].w;
-            const uint32_t slot =
-                emit_slot(offsets[g], f.x, f.y, r, tx, ty, vd.tiles_x, vd.tiles_y, w_lim, h_lim);
+            const uint32_t slot = emit_slot(offsets[g], f.x, f.y, r, tx, ty, vd.tiles_x, vd.tiles_y, w_lim, h_lim);
             if (slot < pk.n_entries_cap) {
                 rec[2 * (size_t)slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 rec[2 * (size_t)slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -74,28 +150,28 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
         }
     }
 
+    const uint32_t q8 = rev3(lane & 7u);
+    const bool writer = (lane & 15u) < 8u && q8 < 7u;
     for (uint32_t hi = start + max_last; hi > start;) {
-        const uint32_t lo = hi - min((uint32_t)kBatch, hi - start);
-        const uint32_t nb = hi - lo;
-        const uint32_t n4 = stage_batch<true>(sb, record, pidx, pk.n_particles, lo, nb, true, tx * kTile,
-                                              ty * kTile, w_lim, h_lim, offsets, vd.tiles_x, vd.tiles_y);
-        // staged index j holds list position lo + nb - 1 - j (0-based within the tile: - start)
-        const uint32_t lane = lane_id();
-        for (uint32_t k = 0; k < n4; k += 4) {
-            uint32_t jj[4];
-            list4(sb, w, k, jj);
+        const uint32_t nb = min((uint32_t)kBwdBatch, hi - start);
+        const uint32_t pos_hi = hi - start;
+        uint32_t len;
+        const uint32_t steps = stage_bwd(sb, record, pidx, offsets, pk.n_particles, hi, nb, pos_hi, tx, ty,
+                                         vd.tiles_x, vd.tiles_y, w_lim, h_lim, len);
+        for (uint32_t k = 0; k < steps; k += 4) {
+            uint64_t q4 = 0x0040004000400040ull;   // four kBwdDummy (64) slots
+            if (k < len) q4 = *reinterpret_cast<const uint64_t*>(&sb.list[sbk][k]);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const uint32_t j = jj[r];
-                if (j == kDummy) break;
-                const uint32_t pos1 = lo + nb - j - start;   // 1-based list position
-                if (pos1 > wmax) continue;                   // no pixel of this wave reached it
+                const uint32_t j = (uint32_t)(q4 >> (16 * r)) & 0xFFFFu;
+                const uint32_t pos1 = pos_hi - j;            // 1-based list position
                 const float4 f = sb.fp[j];
                 const float4 c = sb.col[j];
                 const float dx = px - f.x, dy = py - f.y;
                 float ga;
                 float a = entry_alpha(dx, dy, f.z, f.w, ga);
-                // an entry this pixel composited in the forward pass (same decision)
+                // an entry this pixel composited in the forward pass (same decision); the
+                // pad record has alpha 0
                 const bool use = (pos1 <= last) && (a >= kAlphaMin);
                 a = use ? a : 0.0f;
                 const float inv_om = __builtin_amdgcn_rcpf(1.0f - a);
@@ -110,39 +186,77 @@ __global__ void __launch_bounds__(256) composite_bwd_kernel(
                 // d/d(1/s^2) = -alpha d^2, d/do = alpha / o
                 const float kk = (use && ga < kAlphaMax) ? dLda * ga : 0.0f;
                 const float inv_s2 = f.z * (1.0f / kLog2e);
-                float g[8];
-                g[0] = 2.0f * kk * inv_s2 * dx;
-                g[1] = 2.0f * kk * inv_s2 * dy;
-                g[2] = -kk * fmaf(dx, dx, dy * dy);
-                g[3] = kk * __builtin_amdgcn_rcpf(c.w);
-                g[4] = dr * wgt;
-                g[5] = dg * wgt;
-                g[6] = db * wgt;
-                g[7] = 0.0f;
-                const float red = (ballot64(use) != 0) ? wave_sum8(g, lane) : 0.0f;
-                const uint32_t q8 = rev3(lane);
-                if (lane < 8 && q8 < 7) s_part[w][q8][j] = red;
+                float gv[8];
+                gv[0] = 2.0f * kk * inv_s2 * dx;
+                gv[1] = 2.0f * kk * inv_s2 * dy;
+                gv[2] = -kk * fmaf(dx, dx, dy * dy);
+                gv[3] = kk * __builtin_amdgcn_rcpf(c.w);
+                gv[4] = dr * wgt;
+                gv[5] = dg * wgt;
+                gv[6] = db * wgt;
+                gv[7] = 0.0f;
+                const float red = (ballot64(use) != 0) ? row_sum8(gv, lane) : 0.0f;
+                if (writer && j != kBwdDummy) sb.part[sbk][q8][j] = red;
             }
         }
         __syncthreads();
-        if (t < nb) {
-            const uint32_t m = sb.mask[t];
-            float s[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            const uint32_t pos1 = lo + nb - t - start;
-            for (int ww = 0; ww < 4; ++ww) {
-                if (((m >> ww) & 1u) && pos1 <= s_wmax[ww]) {
+        // combine: the sub-blocks that listed an entry, in fixed order; waves 0 and 1 write
+        // the two halves of each record
+        const uint32_t l = lane;
+        if (w < 2 && l < nb) {
+            const uint32_t m = (uint32_t)sb.mask[0][l] | ((uint32_t)sb.mask[1][l] << 4) |
+                               ((uint32_t)sb.mask[2][l] << 8) | ((uint32_t)sb.mask[3][l] << 12);
+            const int q0 = 4 * (int)w;
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
-                    for (int q = 0; q < 7; ++q) s[q] += s_part[ww][q][t];
+            for (int k = 0; k < 16; ++k) {
+                if ((m >> k) & 1u) {
+                    s0 += sb.part[k][q0][l];
+                    s1 += sb.part[k][q0 + 1][l];
+                    s2 += sb.part[k][q0 + 2][l];
+                    if (w == 0) s3 += sb.part[k][3][l];
                 }
             }
-            const uint32_t slot = sb.slot[t];
-            if (slot < pk.n_entries_cap) {
-                rec[2 * (size_t)slot] = make_float4(s[0], s[1], s[2], s[3]);
-                rec[2 * (size_t)slot + 1] = make_float4(s[4], s[5], s[6], 0.0f);
-            }
+            const uint32_t slot = sb.slot[l];
+            if (slot < pk.n_entries_cap) rec[2 * (size_t)slot + w] = make_float4(s0, s1, s2, s3);
         }
         __syncthreads();
-        hi = lo;
+        hi -= nb;
+    }
+}
+
+// One workgroup per tile, tiles in XCD-banded order.
+__global__ void __launch_bounds__(256) composite_bwd_kernel(
+    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
+    float bg_r, float bg_g, float bg_b, const float* __restrict__ dL_dimage, const float* __restrict__ T_final,
+    const uint32_t* __restrict__ n_last, float4* __restrict__ rec) {
+    __shared__ StagedBwd sb;
+    if (*status != kStatusOk) return;
+    composite_bwd_tile(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, offsets, ranges, bg_r, bg_g, bg_b,
+                       dL_dimage, T_final, n_last, rec);
+}
+
+// Persistent variant: a fixed grid takes tiles from the longest-list-first queue, so the
+// few tiles with very long lists start first instead of trailing the launch. Every
+// workgroup leaves once the counter passes the last item.
+__global__ void __launch_bounds__(256) composite_bwd_persistent_kernel(
+    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
+    float bg_r, float bg_g, float bg_b, const float* __restrict__ dL_dimage, const float* __restrict__ T_final,
+    const uint32_t* __restrict__ n_last, float4* __restrict__ rec, const uint32_t* __restrict__ order,
+    uint32_t n_items, uint32_t* __restrict__ counter) {
+    __shared__ StagedBwd sb;
+    __shared__ uint32_t s_item;
+    if (*status != kStatusOk) return;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        composite_bwd_tile(sb, pk, order[item], record, pidx, offsets, ranges, bg_r, bg_g, bg_b, dL_dimage,
+                           T_final, n_last, rec);
     }
 }
 
@@ -305,28 +419,42 @@ __global__ void __launch_bounds__(256) grad_project_kernel(const GradPack pk, co
     }
 }
 
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv) {
+    return round256((size_t)capacity * 32) + tile_queue_words(max_group_tiles(cams, nv)) * 4 + 256;
+}
+
 int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
                       const isogs_projected* proj, const isogs_bins* bins, const float* bg,
                       const float* dL_dimage, const float* T_final, const uint32_t* n_last,
                       const isogs_scene* grads, void* ws, hipStream_t stream) {
+    static int grid_max = 0;
+    if (!grid_max) grid_max = resident_blocks(reinterpret_cast<const void*>(composite_bwd_persistent_kernel), 256);
+    if (!grid_max) return -1;
     float4* rec = static_cast<float4*>(ws);
+    uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + round256((size_t)bins->capacity * 32));
     int32_t n_per_view[kMaxViews];
     int32_t n_all[4096];
     if (nv > 4096) return -1;
     for (int v = 0; v < nv; ++v) n_all[v] = scenes[v].n;
-    // 1. per-tile reverse compositing
+    // 1. per-tile reverse compositing, longest lists first
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         const int m = min(kMaxViews, nv - v0);
         for (int j = 0; j < m; ++j) n_per_view[j] = scenes[v0 + j].n;
         RenderPack pk{};
         uint32_t blocks;
+        const uint32_t tile0 = tile_base;
         fill_render_pack(pk, cams + v0, n_per_view, 0, m, p_off, tile_base, pix_off, blocks);
         set_render_limits(pk, n_all, nv, bins->capacity);
         if (!blocks) continue;
-        hipLaunchKernelGGL(composite_bwd_kernel, dim3(blocks), dim3(256), 0, stream, pk,
+        uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
+        const unsigned grid = std::min<unsigned>(blocks, (unsigned)grid_max);
+        hipLaunchKernelGGL(composite_bwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->offsets, bins->ranges,
-                           bins->status, bg[0], bg[1], bg[2], dL_dimage, T_final, n_last, rec);
+                           bins->status, bg[0], bg[1], bg[2], dL_dimage, T_final, n_last, rec, order, blocks,
+                           order - 1);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     // 2. per scene: reduce records over its views (in view order) and chain to parameters

@@ -87,34 +87,18 @@ __device__ __forceinline__ float entry_alpha(float dx, float dy, float q, float 
     return fminf(kAlphaMax, g);
 }
 
-// Sum over the 64 lanes of a wavefront with DPP row operations; the total ends in lane 63
-// and is broadcast to every lane. The reduction tree is fixed, so the result is bitwise
-// reproducible.
-__device__ __forceinline__ float wave_sum(float x) {
-    // quad_perm [1,0,3,2] and [2,3,0,1]: each lane holds the sum of its quad
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
-    // row_half_mirror: sum of 8; row_mirror: sum of 16 (every lane of each row)
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x141, 0xF, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x140, 0xF, 0xF, false));
-    // row_bcast:15 adds row r's total into row r+1 (rows 1 and 3); row_bcast:31 adds
-    // lanes 0-31's total into rows 2 and 3: lane 63 ends with the wave total
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x142, 0xA, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x143, 0xC, 0xF, false));
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
-}
-
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
 }
 
-// Sums eight per-lane values over the 64 lanes of a wave with a transposing butterfly:
-// each exchange step halves the values a lane carries (quad swaps, a row rotation by 4,
-// a row rotation by 8, then two cross-row swaps). Afterwards lane l < 8 holds the total of
-// value rev3(l), where rev3 reverses the three low bits of l. ~28 instructions for all
-// eight sums; the combination order is fixed, so results are bitwise reproducible.
-__device__ __forceinline__ float wave_sum8(const float v[8], uint32_t lane) {
+// Sums eight per-lane values over each 16-lane row of a wave with a transposing
+// butterfly: each exchange step halves the values a lane carries (two quad swaps, then
+// row rotations by 4 and by 8). Afterwards lanes l and l + 8 of a row both hold the row
+// total of value rev3(l), where rev3 reverses the three low bits of l < 8. About twenty
+// instructions for all eight sums; the combination order is fixed, so results are
+// bitwise reproducible.
+__device__ __forceinline__ float row_sum8(const float v[8], uint32_t lane) {
     const bool p = lane & 1u, q = lane & 2u, b = lane & 4u;
     float a[4];
 #pragma unroll
@@ -124,8 +108,6 @@ __device__ __forceinline__ float wave_sum8(const float v[8], uint32_t lane) {
     for (int k = 0; k < 2; ++k) c[k] = (q ? a[k + 2] : a[k]) + dpp<0x4E>(q ? a[k] : a[k + 2]);
     float d = (b ? c[1] : c[0]) + dpp<0x124>(b ? c[0] : c[1]);   // row_ror:4
     d += dpp<0x128>(d);                                             // row_ror:8
-    d += __shfl_xor(d, 16, kWave);
-    d += __shfl_xor(d, 32, kWave);
     return d;
 }
 

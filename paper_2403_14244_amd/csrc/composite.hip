@@ -179,35 +179,51 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
 }
 
 size_t render_fwd_persistent_ws(const isogs_camera* cams, int32_t nv) {
-    size_t most = 0;
+    return tile_queue_words(max_group_tiles(cams, nv)) * 4 + 256;
+}
+
+uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv) {
+    uint32_t most = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
-        size_t tiles = 0;
+        uint32_t tiles = 0;
         for (int j = v0; j < min(nv, v0 + kMaxViews); ++j)
-            tiles += (size_t)((cams[j].width + kTile - 1) / kTile) * ((cams[j].height + kTile - 1) / kTile);
+            tiles += (uint32_t)(((cams[j].width + kTile - 1) / kTile) * ((cams[j].height + kTile - 1) / kTile));
         most = tiles > most ? tiles : most;
     }
-    return (most + 2 * kBuckets + 1) * 4 + 256;
+    return most;
+}
+
+size_t tile_queue_words(uint32_t n_tiles) { return 2 * kBuckets + 1 + (size_t)n_tiles; }
+
+uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0, uint32_t n_tiles, uint32_t cap,
+                            hipStream_t stream) {
+    uint32_t* hist = q;
+    uint32_t* cursor = q + kBuckets;
+    uint32_t* order = q + 2 * kBuckets + 1;
+    hipLaunchKernelGGL(fill_u32_kernel_c, dim3(1), dim3(128), 0, stream, q, (uint32_t)(2 * kBuckets + 1));
+    const unsigned hb = std::min<unsigned>(256u, (n_tiles + 255u) / 256u);
+    hipLaunchKernelGGL(tile_class_hist_kernel, dim3(hb), dim3(256), 0, stream, ranges, tile0, n_tiles, cap, hist);
+    hipLaunchKernelGGL(tile_class_scatter_kernel, dim3((n_tiles + 255u) / 256u), dim3(256), 0, stream, ranges, tile0,
+                       n_tiles, cap, hist, cursor, order);
+    return order;
+}
+
+int resident_blocks(const void* kernel, int threads) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
 }
 
 int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                                  const isogs_camera* cams, int32_t nv, const float* bg, float* image,
                                  float* T_final, uint32_t* n_last, void* ws, hipStream_t stream) {
-    static int cu_count = 0, per_cu = 0;
-    if (!cu_count) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return -1;
-        cu_count = prop.multiProcessorCount;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, composite_fwd_persistent_kernel, 256, 0) !=
-                hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-    }
-    uint32_t* bookkeeping = static_cast<uint32_t*>(ws);   // hist[33], cursor[33], counter
-    uint32_t* hist = bookkeeping;
-    uint32_t* cursor = bookkeeping + kBuckets;
-    uint32_t* counter = bookkeeping + 2 * kBuckets;
-    uint32_t* order = bookkeeping + 2 * kBuckets + 1;
+    static int grid_max = 0;
+    if (!grid_max) grid_max = resident_blocks(reinterpret_cast<const void*>(composite_fwd_persistent_kernel), 256);
+    if (!grid_max) return -1;
+    uint32_t* q = static_cast<uint32_t*>(ws);
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         RenderPack pk{};
@@ -216,17 +232,11 @@ int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_p
         fill_render_pack(pk, cams, n_per_view, v0, nv, p_off, tile_base, pix_off, blocks);
         set_render_limits(pk, n_per_view, nv, bins->capacity);
         if (!blocks) continue;
-        const uint32_t cap = pk.n_entries_cap;
-        hipLaunchKernelGGL(fill_u32_kernel_c, dim3(1), dim3(128), 0, stream, bookkeeping, (uint32_t)(2 * kBuckets + 1));
-        const unsigned hb = std::min<unsigned>(256u, (blocks + 255u) / 256u);
-        hipLaunchKernelGGL(tile_class_hist_kernel, dim3(hb), dim3(256), 0, stream, bins->ranges, tile0, blocks, cap,
-                           hist);
-        hipLaunchKernelGGL(tile_class_scatter_kernel, dim3((blocks + 255u) / 256u), dim3(256), 0, stream,
-                           bins->ranges, tile0, blocks, cap, hist, cursor, order);
-        const unsigned grid = std::min<unsigned>(blocks, (unsigned)(cu_count * per_cu));
+        uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
+        const unsigned grid = std::min<unsigned>(blocks, (unsigned)grid_max);
         hipLaunchKernelGGL(composite_fwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
-                           bg[0], bg[1], bg[2], image, T_final, n_last, order, blocks, counter);
+                           bg[0], bg[1], bg[2], image, T_final, n_last, order, blocks, order - 1);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     return 0;

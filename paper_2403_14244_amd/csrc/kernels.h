@@ -33,6 +33,17 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
 
 size_t render_fwd_persistent_ws(const isogs_camera* cams, int32_t nv);
 
+// Longest-list-first tile queue of one launch group: words needed, the largest group, the
+// launch (returns the order array; the queue counter is the word before it).
+size_t tile_queue_words(uint32_t n_tiles);
+uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv);
+uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0, uint32_t n_tiles, uint32_t cap,
+                            hipStream_t stream);
+// Workgroups of `threads` threads of `kernel` resident on the whole GPU at once.
+int resident_blocks(const void* kernel, int threads);
+
+size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv);
+
 int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                                  const isogs_camera* cams, int32_t nv, const float* bg, float* image,
                                  float* T_final, uint32_t* n_last, void* ws, hipStream_t stream);

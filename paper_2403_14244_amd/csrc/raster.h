@@ -6,27 +6,8 @@
 
 namespace isogs {
 
-constexpr int kBatch = 256;   // entries staged in LDS per round (one per thread)
-constexpr int kDummy = kBatch; // staged slot of a zero-opacity record that pads wave lists
-
-// Pixel of lane l in wave w of a tile workgroup: the four waves own the four 8x8
-// quadrants of the 16x16 tile (a square quadrant is touched by fewer small disks than a
-// 16x4 strip of the same area).
-__device__ __forceinline__ int quad_x(uint32_t t) { return (int)(((t >> 6) & 1u) * 8u + (t & 7u)); }
-__device__ __forceinline__ int quad_y(uint32_t t) { return (int)(((t >> 6) >> 1) * 8u + ((t >> 3) & 7u)); }
-
-// One batch of a tile's entries staged in LDS, plus, for each of the four waves, the
-// ordered list of staged entries whose binning disk touches that wave's quadrant. A wave
-// walks only its own list: footprints are small against a tile, so most entries concern
-// one or two quadrants. Lists are padded to a multiple of four with kDummy.
-struct StagedBatch {
-    float4 fp[kBatch + 1];      // {u, v, q = log2(e)/s^2, log2(o)}
-    float4 col[kBatch + 1];     // {r, g, b, o}
-    uint16_t list[4][kBatch + 4];
-    uint8_t mask[kBatch];       // quadrants each staged entry touches
-    uint32_t slot[kBatch];      // emit position of each staged entry (backward only)
-    uint32_t cnt[4][4];         // [loader wave][target wave]
-};
+constexpr int kBatch = 256;   // forward: entries staged in LDS per round (one per thread)
+constexpr int kDummy = kBatch; // staged slot of a zero-opacity record that pads the lists
 
 // Emit position of the entry (particle with footprint u, v, r; tile tx, ty): the
 // particle's offset plus the number of its member tiles before (tx, ty) in row-major
@@ -44,82 +25,7 @@ __device__ __forceinline__ uint32_t emit_slot(uint32_t offset, float u, float v,
     return offset + j;
 }
 
-// Stages entries [first, first + n_in_batch) (reversed when `reverse`, so lists then run
-// back to front). Returns the length of the calling wave's padded list (a multiple of 4).
-// Contains __syncthreads.
-template <bool WITH_SLOT>
-__device__ __forceinline__ uint32_t stage_batch(StagedBatch& sb, const float4* __restrict__ record,
-                                                const uint32_t* __restrict__ pidx, uint32_t n_particles,
-                                                uint32_t first, uint32_t n_in_batch, bool reverse, int tile_x0,
-                                                int tile_y0, float w_lim, float h_lim,
-                                                const uint32_t* __restrict__ offsets = nullptr,
-                                                int tiles_x = 0, int tiles_y = 0) {
-    const uint32_t t = threadIdx.x, w = t >> 6;
-    uint32_t mask = 0;
-    const uint32_t e = reverse ? first + n_in_batch - 1 - t : first + t;
-    const uint32_t g = t < n_in_batch ? pidx[e] : 0xFFFFFFFFu;
-    if (WITH_SLOT) sb.slot[t] = 0xFFFFFFFFu;
-    if (g < n_particles) {
-        const float4 f = record[2 * (size_t)g];
-        const float4 c = record[2 * (size_t)g + 1];
-        if (WITH_SLOT)
-            sb.slot[t] = emit_slot(offsets[g], f.x, f.y, c.w, tile_x0 / kTile, tile_y0 / kTile, tiles_x, tiles_y,
-                                   w_lim, h_lim);
-        sb.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
-        sb.col[t] = make_float4(c.x, c.y, c.z, f.w);
-        const float r2 = c.w * c.w;
-#pragma unroll
-        for (int ww = 0; ww < 4; ++ww) {
-            const float x_lo = (float)(tile_x0 + (ww & 1) * 8) + 0.5f;
-            const float y_lo = (float)(tile_y0 + (ww >> 1) * 8) + 0.5f;
-            const float x_hi = fminf(x_lo + 7.0f, w_lim), y_hi = fminf(y_lo + 7.0f, h_lim);
-            const float dx = fmaxf(fmaxf(x_lo - f.x, f.x - x_hi), 0.0f);
-            const float dy = fmaxf(fmaxf(y_lo - f.y, f.y - y_hi), 0.0f);
-            // a quadrant starting beyond the image has no pixels
-            if (x_lo <= w_lim && y_lo <= h_lim && dx * dx + dy * dy <= r2) mask |= 1u << ww;
-        }
-    }
-    if (t == 0) {
-        sb.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
-        sb.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-    sb.mask[t] = (uint8_t)mask;
-    uint64_t bal[4];
-#pragma unroll
-    for (int ww = 0; ww < 4; ++ww) bal[ww] = ballot64((mask >> ww) & 1u);
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int ww = 0; ww < 4; ++ww) sb.cnt[w][ww] = (uint32_t)__popcll(bal[ww]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ww = 0; ww < 4; ++ww) {
-        if ((mask >> ww) & 1u) {
-            uint32_t pos = rank_below(bal[ww]);
-            pos += (w > 0 ? sb.cnt[0][ww] : 0u) + (w > 1 ? sb.cnt[1][ww] : 0u) + (w > 2 ? sb.cnt[2][ww] : 0u);
-            sb.list[ww][pos] = (uint16_t)t;
-        }
-    }
-    const uint32_t mine = __builtin_amdgcn_readfirstlane(sb.cnt[0][w] + sb.cnt[1][w] + sb.cnt[2][w] + sb.cnt[3][w]);
-    const uint32_t padded = (mine + 3u) & ~3u;
-    const uint32_t lane = lane_id();
-    if (lane < 4 && mine + lane < padded) sb.list[w][mine + lane] = (uint16_t)kDummy;
-    __syncthreads();
-    return padded;
-}
-
-// Four consecutive entries of a wave's list (uniform: scalar registers).
-__device__ __forceinline__ void list4(const StagedBatch& sb, uint32_t w, uint32_t k, uint32_t j[4]) {
-    const uint64_t q = *reinterpret_cast<const uint64_t*>(&sb.list[w][k]);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)q);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(q >> 32));
-    j[0] = lo & 0xFFFFu;
-    j[1] = lo >> 16;
-    j[2] = hi & 0xFFFFu;
-    j[3] = hi >> 16;
-}
-
-// ---- Forward-pass staging with 4x4 sub-blocks -------------------------------------------
+// ---- Staging with 4x4 sub-blocks -----------------------------------------------------------
 // Each wave owns an 8x8 quadrant; its four 16-lane rows own the quadrant's four 4x4
 // sub-blocks (lane l: row g = l / 16 covers sub-block g, pixel (l % 4, (l / 4) % 4)). Every
 // sub-block gets its own ordered list of the staged entries whose binning disk touches
@@ -130,6 +36,21 @@ __device__ __forceinline__ int sub_x(uint32_t t) {
 }
 __device__ __forceinline__ int sub_y(uint32_t t) {
     return (int)(((t >> 6) >> 1) * 8u + (((t >> 4) & 3u) >> 1) * 4u + ((t >> 2) & 3u));
+}
+
+// Whether the binning disk (centre u, v, radius^2 r2) reaches a pixel centre of sub-block
+// k = 4 * quadrant + row of the tile at (tile_x0, tile_y0); quadrant q sits at
+// (8 (q % 2), 8 (q / 2)), row g of it at (4 (g % 2), 4 (g / 2)). A sub-block starting
+// beyond the image has no pixels. The forward and backward passes share this test, so
+// they cull the same entries.
+__device__ __forceinline__ bool sub_block_touched(float u, float v, float r2, int k, int tile_x0, int tile_y0,
+                                                  float w_lim, float h_lim) {
+    const int qx = ((k >> 2) & 1) * 8 + (k & 1) * 4, qy = ((k >> 2) >> 1) * 8 + ((k & 3) >> 1) * 4;
+    const float x_lo = (float)(tile_x0 + qx) + 0.5f, y_lo = (float)(tile_y0 + qy) + 0.5f;
+    const float x_hi = fminf(x_lo + 3.0f, w_lim), y_hi = fminf(y_lo + 3.0f, h_lim);
+    const float dx = fmaxf(fmaxf(x_lo - u, u - x_hi), 0.0f);
+    const float dy = fmaxf(fmaxf(y_lo - v, v - y_hi), 0.0f);
+    return x_lo <= w_lim && y_lo <= h_lim && dx * dx + dy * dy <= r2;
 }
 
 struct StagedSub {
@@ -157,15 +78,8 @@ __device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4*
         sb.col[t] = make_float4(c.x, c.y, c.z, f.w);
         const float r2 = c.w * c.w;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            // sub-block k = 4 * quadrant + row; quadrant (k/4) at (8 (k/4 % 2), 8 (k/4 / 2))
-            const int qx = ((k >> 2) & 1) * 8 + (k & 1) * 4, qy = ((k >> 2) >> 1) * 8 + ((k & 3) >> 1) * 4;
-            const float x_lo = (float)(tile_x0 + qx) + 0.5f, y_lo = (float)(tile_y0 + qy) + 0.5f;
-            const float x_hi = fminf(x_lo + 3.0f, w_lim), y_hi = fminf(y_lo + 3.0f, h_lim);
-            const float dx = fmaxf(fmaxf(x_lo - f.x, f.x - x_hi), 0.0f);
-            const float dy = fmaxf(fmaxf(y_lo - f.y, f.y - y_hi), 0.0f);
-            if (x_lo <= w_lim && y_lo <= h_lim && dx * dx + dy * dy <= r2) mask |= 1u << k;
-        }
+        for (int k = 0; k < 16; ++k)
+            if (sub_block_touched(f.x, f.y, r2, k, tile_x0, tile_y0, w_lim, h_lim)) mask |= 1u << k;
     }
     if (t == 0) {
         sb.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
