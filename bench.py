@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--views", type=int, default=100)
     ap.add_argument("--batch-views", type=int, default=10)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="HIP streams the forward batches alternate over (sort of one batch overlaps "
+                         "compositing of another)")
     ap.add_argument("--gaussians", type=int, default=1_000_000)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
@@ -200,25 +203,40 @@ def main():
     R = P.Rasterizer(dev, headroom=1.1)
     B = args.batch_views
     batches = [cams[i:i + B] for i in range(0, len(cams), B)]
+    # batch k runs on stream k mod S with its own rasterizer (workspace), so that the
+    # memory-bound sort of one batch overlaps the ALU-bound compositing of another
+    main = torch.cuda.current_stream()
+    streams = [main] + [torch.cuda.Stream(device=dev) for _ in range(max(args.streams, 1) - 1)]
+    rasters = [R] + [P.Rasterizer(dev, headroom=1.1) for _ in streams[1:]]
 
     # size the entry capacity on the warm-up pass
     def forward_step(check):
         stage = dict(project=[], bin_sort=[], render_fwd=[])
         bins_all = []
-        for bc in batches:
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            scenes = [gs] * len(bc)
-            ev[0].record()
-            fp = R.project(scenes, bc)
-            ev[1].record()
-            bins = R.bin_sort(fp, [gs.n] * len(bc), bc, check=check)
-            ev[2].record()
-            R.render_fwd(fp, [gs.n] * len(bc), bins, bc)
-            ev[3].record()
+        go = torch.cuda.Event()
+        go.record(main)
+        for s in streams[1:]:
+            s.wait_event(go)
+        for k, bc in enumerate(batches):
+            s, Rk = streams[k % len(streams)], rasters[k % len(streams)]
+            with torch.cuda.stream(s):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                scenes = [gs] * len(bc)
+                ev[0].record(s)
+                fp = Rk.project(scenes, bc)
+                ev[1].record(s)
+                bins = Rk.bin_sort(fp, [gs.n] * len(bc), bc, check=check)
+                ev[2].record(s)
+                Rk.render_fwd(fp, [gs.n] * len(bc), bins, bc)
+                ev[3].record(s)
             stage["project"].append((ev[0], ev[1]))
             stage["bin_sort"].append((ev[1], ev[2]))
             stage["render_fwd"].append((ev[2], ev[3]))
             bins_all.append(bins)
+        for s in streams[1:]:
+            done = torch.cuda.Event()
+            done.record(s)
+            main.wait_event(done)
         return stage, bins_all
 
     if args.pmc_probe:
@@ -241,7 +259,8 @@ def main():
         _, bins_all = forward_step(check=True)
     torch.cuda.synchronize()
     entries = [b.n_entries() for b in bins_all]
-    log(f"warm-up done: entries per batch {entries}, capacity {R.capacity}")
+    log(f"warm-up done: entries per batch {entries}, capacity {[r.capacity for r in rasters]}, "
+        f"{len(streams)} stream(s)")
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -263,11 +282,17 @@ def main():
     n_comp = args.steps * len(batches)
     comp_ms = stage_ms["render_fwd"] * args.steps / n_comp
     pairs = 0
+    iso = []
     for bc in batches:
         fp = R.project([gs] * len(bc), bc)
         bins = R.bin_sort(fp, [gs.n] * len(bc), bc, check=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         _, T, n_last = R.render_fwd(fp, [gs.n] * len(bc), bins, bc)
+        e1.record()
+        iso.append((e0, e1))
         pairs += walk_pairs(T, n_last, bins.ranges, bc)
+    iso_ms = sum(a.elapsed_time(b) for a, b in iso) / len(iso)
     pairs_per_launch = pairs / len(batches)
     flops = pairs_per_launch * FLOPS_PER_PAIR
     pix_per_launch = B * args.width * args.height
@@ -279,11 +304,13 @@ def main():
     comp_bytes = ent_per_launch * 36 + pix_per_launch * 20 + tiles_per_launch * 8
     roof = dict(kernel="composite_fwd_kernel", bound="alu",
                 achieved=flops / (comp_ms * 1e-3) / 1e12, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                traffic=measured_traffic(comp_bytes), launch_ms=comp_ms, pairs_per_launch=pairs_per_launch,
+                traffic=measured_traffic(comp_bytes), launch_ms=comp_ms, launch_ms_alone=iso_ms,
+                pairs_per_launch=pairs_per_launch,
                 flops_per_pair=FLOPS_PER_PAIR, alg_bytes_per_launch=comp_bytes,
                 hbm_gbs_alg=comp_bytes / (comp_ms * 1e-3) / 1e9)
     roof["frac"] = roof["achieved"] / roof["peak"]
-    log(f"composite: {comp_ms * 1e3:.0f} us/launch, {pairs_per_launch:.3e} pairs, "
+    log(f"composite: {comp_ms * 1e3:.0f} us/launch in the timed region ({iso_ms * 1e3:.0f} us alone), "
+        f"{pairs_per_launch:.3e} pairs, "
         f"{roof['achieved']:.2f} TFLOP/s ({roof['frac']:.3f} of {VALU_PEAK_TFLOPS:.1f})")
 
     # fwd+bwd iterations per second: one 1080p view, L1 loss, autograd
@@ -299,15 +326,24 @@ def main():
         loss.backward()
         return loss
 
-    for _ in range(2):
-        train_iter()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.train_iters):
-        train_iter()
-    torch.cuda.synchronize()
-    it_s = args.train_iters / (time.perf_counter() - t1)
-    log(f"fwd+bwd: {it_s:.1f} it/s")
+    def train_rate():
+        for _ in range(2):
+            train_iter()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.train_iters):
+            train_iter()
+        torch.cuda.synchronize()
+        return args.train_iters / (time.perf_counter() - t1)
+
+    # compositing of a single view is tail-bound by its longest tiles: the persistent,
+    # longest-first kernel is measured beside the one-workgroup-per-tile kernel
+    it_by_kernel = {}
+    for persistent in (False, True):
+        Rt.persistent_fwd = persistent
+        it_by_kernel["persistent" if persistent else "per_tile"] = round(train_rate(), 2)
+    it_s = max(it_by_kernel.values())
+    log(f"fwd+bwd: {it_s:.1f} it/s ({it_by_kernel})")
 
     serving = None
     if args.serve_seconds > 0:
@@ -322,10 +358,12 @@ def main():
         "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded generator; no dataset)",
         "config": {"workload": "mix1m_1080p_x100", "gaussians": args.gaussians, "views": args.views,
-                   "width": args.width, "height": args.height, "sh_degree": 3, "views_per_call": B},
+                   "width": args.width, "height": args.height, "sh_degree": 3, "views_per_call": B,
+                   "streams": len(streams)},
         "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},
         "entries_per_view": round(ent_per_launch / B),
         "fwd_bwd_iters_per_s": round(it_s, 2),
+        "fwd_bwd_iters_per_s_by_fwd_kernel": it_by_kernel,
         "roofline": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
         "stage_us_per_view": {k: round(v * 1e3 / args.views, 1) for k, v in stage_ms.items()},
         "serving": serving,

@@ -110,9 +110,11 @@ typedef struct {
 } isogs_projected;
 
 /* Binned and sorted entries (device memory).
- *   keys        [capacity]  (global tile id << 32) | bits(depth), ascending; ties in emit
- *                           order (view, particle, row-major tile), i.e. a stable sort
- *   pidx        [capacity]  packed particle index (into isogs_projected) of each entry
+ *   keys        [capacity]  optional (NULL: not written): (global tile id << 32) |
+ *                           bits(depth), ascending; ties in emit order (view, particle,
+ *                           row-major tile), i.e. a stable sort
+ *   pidx        [capacity]  packed particle index (into isogs_projected) of each entry, in
+ *                           the order of the keys
  *   ranges      [T][2]      [start, end) of each global tile's entries; [0, 0) if empty
  *   offsets     [N]         first emit position of each particle (exclusive scan of
  *                           tile_count); entry (particle p, j-th member tile in row-major
@@ -140,8 +142,9 @@ typedef struct {
 int isogs_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
                   const isogs_projected* out, void* stream);
 
-/* Bins the footprints into 16x16 tiles and sorts the (tile, depth) keys with a device
- * LSD radix sort (stable), then fills tile ranges and per-entry particle indices.
+/* Bins the footprints into 16x16 tiles and sorts the entries stably by (tile, depth): a
+ * device LSD radix sort on the tile id, then a stable sort of every tile's segment on the
+ * depth bits; fills tile ranges, per-entry particle indices and, if requested, the keys.
  *   n_per_view  host array [V]: particles of each view (the n of its scene)
  *   ws, ws_bytes  workspace; with ws == NULL only *ws_bytes is written (the bytes needed
  *                 for this capacity and these views), and nothing is launched.

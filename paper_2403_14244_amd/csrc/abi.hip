@@ -77,8 +77,7 @@ int check_bins(const isogs_bins* b, uint64_t n, uint64_t tiles) {
     if (!b->count || !b->status) return fail(ISOGS_ERR_INVALID, "bins count/status is NULL");
     if (tiles && !b->ranges) return fail(ISOGS_ERR_INVALID, "bins ranges is NULL");
     if (n && !b->offsets) return fail(ISOGS_ERR_INVALID, "bins offsets is NULL");
-    if (b->capacity && (!b->keys || !b->pidx))
-        return fail(ISOGS_ERR_INVALID, "bins entry arrays are NULL");
+    if (b->capacity && !b->pidx) return fail(ISOGS_ERR_INVALID, "bins pidx is NULL");
     if (b->capacity >= (1ull << 30) - 1) return fail(ISOGS_ERR_INVALID, "bins capacity must be < 2^30 - 1");
     return ISOGS_OK;
 }

@@ -1,13 +1,22 @@
-// Binning of footprints into 16x16 tiles and the stable (tile, depth) key sort.
+// Binning of footprints into 16x16 tiles and the stable (tile, depth) sort.
+//
+// The sort is split by key part. Entries are emitted in particle order, which is the tie
+// order of the (tile, depth) sort; a stable sort on the tile id alone therefore leaves
+// each tile's entries in emit order, and a stable sort of every tile's segment on depth
+// then yields exactly the stable (tile, depth) order. The global passes move 8 bytes per
+// entry over ceil(tile bits / 8) passes instead of 12 bytes over ceil((tile bits + 31) / 8),
+// and the depth sort runs per tile in LDS.
 //
 // Steps (all on the caller's stream, no host synchronisation):
 //   1. fill        zero tile ranges, radix histograms, tickets and look-back words
 //   2. scan        exclusive scan of per-particle tile counts -> emit offsets, total, status
-//   3. emit        one (key, particle index) pair per (particle, member tile), row-major tiles
-//   4. histogram   digit counts of every radix pass in one read of the keys
-//   5. passes      LSD radix passes over the compacted key (31 depth bits + tile bits),
-//                  8-bit digits, each a single kernel with decoupled look-back
+//   3. emit        one (tile id, particle index) pair per (particle, member tile)
+//   4. histogram   digit counts of every tile-id pass in one read of the ids
+//   5. passes      stable LSD radix passes over the tile id, 8-bit digits, each a single
+//                  kernel with decoupled look-back
 //   6. finalize    tile ranges [start, end)
+//   7. segments    stable sort of each tile's segment on the depth bits (and the 64-bit
+//                  (tile, depth) keys, when the caller asks for them)
 #include "common.h"
 #include <algorithm>
 
@@ -23,20 +32,13 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;    // entries per sort workgroup
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kMaxPasses = 8;
+constexpr int kMaxPasses = 4;                             // tile ids have at most 32 bits
+constexpr int kSegItems = 16;
+constexpr uint32_t kSegMax = kSortThreads * kSegItems;   // longest segment sorted in LDS
 constexpr uint32_t kLbAggregate = 1u << 30;              // look-back word: tile's own count
 constexpr uint32_t kLbInclusive = 2u << 30;              // look-back word: prefix through tile
 constexpr uint32_t kLbValue = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 22;
-
-// (tile << 32 | depth bits) -> (tile << 31 | depth bits): depth > 0, so its sign bit is 0.
-__device__ __forceinline__ uint64_t compact_key(uint64_t k) {
-    return ((k >> 32) << 31) | (k & 0x7FFFFFFFull);
-}
-
-__device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
-    return (uint32_t)(compact_key(k) >> shift) & (kRadix - 1);
-}
 
 // Inclusive scan over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
@@ -128,15 +130,16 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
     }
 }
 
+
 // Step 3: one entry per (particle, member tile); entries of a particle are consecutive
 // from its offset, tiles in row-major order. A particle writes no more entries than its
-// tile count says (the count may come from elsewhere); missing ones get a sentinel key.
+// tile count says (the count may come from elsewhere); missing ones get the sentinel id
+// 0xFFFFFFFF, which sorts last and belongs to no tile.
 __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ record,
-                                                   const float* __restrict__ depth,
                                                    const uint32_t* __restrict__ tile_count,
                                                    const uint32_t* __restrict__ offsets,
                                                    const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     const int vi = view_of_block(pk, blockIdx.x);
@@ -150,7 +153,6 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
     if ((uint64_t)e0 + want > count) return;
     const float4 fp = record[2 * (size_t)i];
     const float r = record[2 * (size_t)i + 1].w;
-    const uint64_t zbits = (uint64_t)__float_as_uint(depth[i]);
     int tx0, tx1, ty0, ty1;
     tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
     const float r2 = r * r;
@@ -160,20 +162,18 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
         for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
             if (!tile_member(fp.x, fp.y, r2, tx, ty, w_lim, h_lim)) continue;
             const uint32_t e = e0 + j++;
-            const uint64_t tid = (uint64_t)(vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx));
-            keys[e] = (tid << 32) | zbits;
+            keys[e] = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
             vals[e] = i;
         }
     }
     for (; j < want; ++j) {
-        const uint32_t e = e0 + j;
-        keys[e] = ~0ull;
-        vals[e] = i;
+        keys[e0 + j] = 0xFFFFFFFFu;
+        vals[e0 + j] = i;
     }
 }
 
-// Step 4: digit histograms of all passes in one sweep over the keys.
-__global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t* __restrict__ keys,
+// Step 4: digit histograms of all tile-id passes in one sweep over the ids.
+__global__ void __launch_bounds__(256) sort_hist_kernel(const uint32_t* __restrict__ keys,
                                                         const uint32_t* __restrict__ count_p, uint64_t capacity,
                                                         int passes, uint32_t* __restrict__ hist) {
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
@@ -181,9 +181,23 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t* __restri
     __syncthreads();
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        const uint64_t c = compact_key(keys[i]);
-        for (int p = 0; p < passes; ++p) atomicAdd(&s_h[p][(uint32_t)(c >> (p * kRadixBits)) & (kRadix - 1)], 1u);
+    // neighbouring entries mostly share their high digits: a wave whose lanes all hold the
+    // same digit adds once instead of 64 times to one LDS word
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < count; i0 += stride) {
+        const uint32_t i = i0 + threadIdx.x;
+        const bool ok = i < count;
+        const uint32_t c = ok ? keys[i] : 0u;
+        const uint64_t act = ballot64(ok);
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = (c >> (p * kRadixBits)) & (kRadix - 1);
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            if (ballot64(ok && d != d0) == 0) {
+                if (lane_id() == 0 && act) atomicAdd(&s_h[p][d0], (uint32_t)__popcll(act));
+            } else if (ok) {
+                atomicAdd(&s_h[p][d], 1u);
+            }
+        }
     }
     __syncthreads();
     for (int p = 0; p < passes; ++p) {
@@ -192,17 +206,47 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint64_t* __restri
     }
 }
 
-// Step 5: one stable LSD pass. Each workgroup takes the next 4096-entry tile in ticket
-// order, ranks its entries per digit with wavefront ballots (lanes with equal digits are
-// matched bit by bit; the rank is the count of matching lanes below), publishes its digit
-// counts and resolves its global offsets by looking back over earlier tiles' words, then
-// reorders the tile in LDS so the scatter writes contiguous runs per digit.
+// Ranks up to ITEMS items per lane within the wave by 8-bit digit. Items are taken in
+// rounds (item i of every lane in round i, lanes in order), so ranks follow the order
+// (round, lane). Lanes with equal digits are matched bit by bit with ballots; an item's
+// rank is the wave's count of its digit in earlier rounds plus the matching lanes below
+// it. `cnt` holds the wave's 256 digit counters (zero on entry) and ends with the wave's
+// digit totals. Bit i of `valid` marks item i as present; `items` (uniform) bounds the
+// rounds.
+template <int ITEMS>
+__device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift, uint32_t valid, int items,
+                                          uint32_t* __restrict__ cnt, uint32_t (&rk)[ITEMS]) {
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (i >= items) break;
+        const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+        const bool ok = (valid >> i) & 1u;
+        uint64_t m = ballot64(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = ballot64(bit);
+            m &= bit ? bal : ~bal;
+        }
+        const uint32_t below = rank_below(m);
+        const uint32_t prior = cnt[d];
+        rk[i] = prior + below;
+        if (ok && below == 0) cnt[d] = prior + (uint32_t)__popcll(m);
+    }
+}
+
+// Step 5: one stable LSD pass over the tile ids (digit at `shift`). Each workgroup takes
+// the next 4096-entry tile in ticket order, ranks its entries per digit within each wave,
+// publishes its digit counts and resolves its global offsets by looking back over earlier
+// tiles' words, then reorders the tile in LDS so the scatter writes contiguous runs per
+// digit.
 __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ count_p, uint64_t capacity, int pass,
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ count_p, uint64_t capacity, int shift,
     const uint32_t* __restrict__ hist, uint32_t* __restrict__ lookback, uint32_t* __restrict__ ticket,
     int32_t* __restrict__ status) {
-    __shared__ uint64_t s_buf[kSortTile];   // tile reordered by digit: keys, then values
+    __shared__ uint32_t s_buf[kSortTile];   // tile reordered by digit: keys, then values
+    __shared__ uint8_t s_dig[kSortTile];     // digit at each reordered position
     __shared__ uint32_t s_wcnt[4][kRadix];
     __shared__ uint32_t s_local[kRadix];
     __shared__ uint32_t s_base[kRadix];
@@ -218,40 +262,24 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
     __syncthreads();
     const uint32_t tile = s_ticket;
     if (tile >= ntiles) return;
-    const int shift = pass * kRadixBits;
 
     // load: wave w owns entries [tile*4096 + w*1024, +1024), item i of lane l at i*64 + l
     const uint32_t wbase = tile * kSortTile + w * (kSortTile / 4);
-    uint64_t k[kSortItems];
-    uint32_t v[kSortItems];
-    uint32_t rk[kSortItems];
+    uint32_t k[kSortItems], v[kSortItems], rk[kSortItems];
+    uint32_t valid = 0;
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t idx = wbase + i * kWave + lane;
-        if (idx < count) {
-            k[i] = kin[idx];
-            v[i] = vin[idx];
-        } else {
-            k[i] = 0;
-            v[i] = 0;
-        }
+        const bool ok = idx < count;
+        valid |= (uint32_t)ok << i;
+        k[i] = ok ? kin[idx] : 0u;
     }
-    // rank within the wave, rounds in entry order
+    wave_rank<kSortItems>(k, shift, valid, kSortItems, s_wcnt[w], rk);
+    // values are needed only after the keys are placed: their loads overlap the look-back
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        const bool valid = wbase + i * kWave + lane < count;
-        const uint32_t d = digit_of(k[i], shift);
-        uint64_t m = ballot64(valid);
-#pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = ballot64(bit);
-            m &= bit ? bal : ~bal;
-        }
-        const uint32_t below = rank_below(m);
-        const uint32_t prior = s_wcnt[w][d];
-        rk[i] = prior + below;
-        if (valid && below == 0) s_wcnt[w][d] = prior + (uint32_t)__popcll(m);
+        const uint32_t idx = wbase + i * kWave + lane;
+        v[i] = ((valid >> i) & 1u) ? vin[idx] : 0u;
     }
     __syncthreads();
 
@@ -289,66 +317,278 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
                            __HIP_MEMORY_SCOPE_AGENT);
     }
     uint32_t tot;
-    const uint32_t gbase = block_exclusive_scan(hist[pass * kRadix + t], s_tmp, tot);
+    const uint32_t gbase = block_exclusive_scan(hist[t], s_tmp, tot);
     const uint32_t lbase = block_exclusive_scan(mine, s_tmp, tot);
     s_base[t] = gbase + excl;
     s_local[t] = lbase;
     __syncthreads();
 
     // reorder in LDS by digit (stable), then write runs: keys first, then the values
-    // through the same buffer (halves the LDS a workgroup needs)
+    // through the same buffer
     uint32_t lpos[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         lpos[i] = 0xFFFFFFFFu;
-        if (wbase + i * kWave + lane < count) {
-            const uint32_t d = digit_of(k[i], shift);
+        if ((valid >> i) & 1u) {
+            const uint32_t d = (k[i] >> shift) & (kRadix - 1);
             lpos[i] = s_local[d] + s_wcnt[w][d] + rk[i];
             s_buf[lpos[i]] = k[i];
         }
     }
     __syncthreads();
     const uint32_t n_here = min((uint32_t)kSortTile, count - tile * kSortTile);
-    uint32_t dst[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t j = t + i * kSortThreads;
-        dst[i] = 0xFFFFFFFFu;
         if (j < n_here) {
-            const uint64_t key = s_buf[j];
-            const uint32_t d = digit_of(key, shift);
-            dst[i] = s_base[d] + (j - s_local[d]);
-            if (dst[i] < count) kout[dst[i]] = key;
+            const uint32_t key = s_buf[j];
+            const uint32_t dd = (key >> shift) & (kRadix - 1);
+            s_dig[j] = (uint8_t)dd;
+            const uint32_t dst = s_base[dd] + (j - s_local[dd]);
+            if (dst < count) kout[dst] = key;
         }
     }
     __syncthreads();
-    uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i)
-        if (lpos[i] != 0xFFFFFFFFu) s_val[lpos[i]] = v[i];
+        if (lpos[i] != 0xFFFFFFFFu) s_buf[lpos[i]] = v[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t j = t + i * kSortThreads;
-        if (j < n_here && dst[i] < count) vout[dst[i]] = s_val[j];
+        if (j < n_here) {
+            const uint32_t dd = s_dig[j];
+            const uint32_t dst = s_base[dd] + (j - s_local[dd]);
+            if (dst < count) vout[dst] = s_buf[j];
+        }
     }
 }
 
-// Step 6: tile ranges.
-__global__ void __launch_bounds__(256) finalize_kernel(const uint64_t* __restrict__ keys,
+// Step 6: tile ranges from the sorted tile ids.
+__global__ void __launch_bounds__(256) finalize_kernel(const uint32_t* __restrict__ keys,
                                                        const uint32_t* __restrict__ count_p, uint64_t capacity,
                                                        uint32_t tiles_total, uint32_t* __restrict__ ranges) {
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        const uint32_t tl = (uint32_t)(keys[i] >> 32);
-        const uint32_t prev = i > 0 ? (uint32_t)(keys[i - 1] >> 32) : 0xFFFFFFFFu;
-        const uint32_t next = i + 1 < count ? (uint32_t)(keys[i + 1] >> 32) : 0xFFFFFFFFu;
+        const uint32_t tl = keys[i];
+        const uint32_t prev = i > 0 ? keys[i - 1] : 0xFFFFFFFFu;
+        const uint32_t next = i + 1 < count ? keys[i + 1] : 0xFFFFFFFFu;
         if (tl < tiles_total) {
             if (tl != prev) ranges[2 * tl] = i;
             if (tl != next) ranges[2 * tl + 1] = i + 1;
         }
     }
+}
+
+// OR and AND of x over the workgroup (s_tmp: 8 words). Contains __syncthreads.
+__device__ __forceinline__ void block_or_and(uint32_t x_or, uint32_t x_and, uint32_t* s_tmp, uint32_t& r_or,
+                                             uint32_t& r_and) {
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        x_or |= __shfl_xor(x_or, o, kWave);
+        x_and &= __shfl_xor(x_and, o, kWave);
+    }
+    const uint32_t w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        s_tmp[w] = x_or;
+        s_tmp[4 + w] = x_and;
+    }
+    __syncthreads();
+    r_or = s_tmp[0] | s_tmp[1] | s_tmp[2] | s_tmp[3];
+    r_and = s_tmp[4] & s_tmp[5] & s_tmp[6] & s_tmp[7];
+    __syncthreads();
+}
+
+struct SegShared {
+    uint32_t buf[kSegMax];        // segment reordered by digit: keys, then values
+    uint32_t wcnt[4][kRadix];
+    uint32_t local[kRadix];       // LDS path: digit bases; global path: digit histogram
+    uint32_t run[kRadix];         // global path: next output position of each digit
+    uint32_t tmp[8];
+};
+
+// Thread t's digit: wave prefixes written back into wcnt, returns the total over waves.
+__device__ __forceinline__ uint32_t digit_wave_prefix(SegShared& sh, uint32_t t) {
+    const uint32_t c0 = sh.wcnt[0][t], c1 = sh.wcnt[1][t], c2 = sh.wcnt[2][t], c3 = sh.wcnt[3][t];
+    sh.wcnt[0][t] = 0u;
+    sh.wcnt[1][t] = c0;
+    sh.wcnt[2][t] = c0 + c1;
+    sh.wcnt[3][t] = c0 + c1 + c2;
+    return c0 + c1 + c2 + c3;
+}
+
+// Segment of n <= kSegMax entries sorted in LDS: items stay in registers between passes,
+// each pass ranks by one 8-bit digit of the depth bits, reorders through LDS and reloads
+// in position order. Only the bits that differ within the segment are sorted on.
+__device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, uint32_t start, uint32_t n,
+                                                 const float* __restrict__ depth, uint32_t* __restrict__ pidx,
+                                                 uint64_t* __restrict__ keys64) {
+    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+    const int items = (int)((n + kSortThreads - 1) / kSortThreads);
+    const uint32_t wbase = w * kWave * (uint32_t)items;   // wave w owns positions [wbase, wbase + 64 items)
+    uint32_t k[kSegItems], v[kSegItems], rk[kSegItems];
+    uint32_t valid = 0;
+    uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < kSegItems; ++i) {
+        const uint32_t p = wbase + (uint32_t)i * kWave + l;
+        const bool ok = i < items && p < n;
+        valid |= (uint32_t)ok << i;
+        v[i] = ok ? pidx[start + p] : 0u;
+        k[i] = ok ? __float_as_uint(depth[v[i]]) : 0u;
+        if (ok) {
+            k_or |= k[i];
+            k_and &= k[i];
+        }
+    }
+    uint32_t all_or, all_and;
+    block_or_and(k_or, k_and, sh.tmp, all_or, all_and);
+    const uint32_t diff = all_or ^ all_and;
+    const int lo = diff ? __builtin_ctz(diff) : 0, hi = diff ? 32 - __builtin_clz(diff) : 0;
+    for (int shift = lo; shift < hi; shift += kRadixBits) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh.wcnt[q][t] = 0u;
+        __syncthreads();
+        wave_rank<kSegItems>(k, shift, valid, items, sh.wcnt[w], rk);
+        __syncthreads();
+        const uint32_t tot = digit_wave_prefix(sh, t);
+        uint32_t all;
+        sh.local[t] = block_exclusive_scan(tot, sh.tmp, all);
+        __syncthreads();
+        uint32_t pos[kSegItems];
+#pragma unroll
+        for (int i = 0; i < kSegItems; ++i) {
+            if ((valid >> i) & 1u) {
+                const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+                pos[i] = sh.local[d] + sh.wcnt[w][d] + rk[i];
+                sh.buf[pos[i]] = k[i];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSegItems; ++i)
+            if ((valid >> i) & 1u) k[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSegItems; ++i)
+            if ((valid >> i) & 1u) sh.buf[pos[i]] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSegItems; ++i)
+            if ((valid >> i) & 1u) v[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
+    }
+    // every read of the segment happened before block_or_and's barrier: in place is safe
+#pragma unroll
+    for (int i = 0; i < kSegItems; ++i) {
+        if (!((valid >> i) & 1u)) continue;
+        const uint32_t p = wbase + (uint32_t)i * kWave + l;
+        pidx[start + p] = v[i];
+        if (keys64) keys64[start + p] = ((uint64_t)tile << 32) | k[i];
+    }
+}
+
+// Segment longer than kSegMax, sorted by one workgroup through global scratch: each pass
+// histograms the digit over the whole segment, then ranks chunk after chunk in order and
+// scatters every entry straight to its place. The ping-pong buffers are chosen so that the
+// last pass lands in pidx.
+__device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile, uint32_t start, uint32_t n,
+                                                 const float* __restrict__ depth, uint32_t* __restrict__ pidx,
+                                                 uint64_t* __restrict__ keys64, uint32_t* __restrict__ sk0,
+                                                 uint32_t* __restrict__ sk1, uint32_t* __restrict__ sv) {
+    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+    uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
+    for (uint32_t p = t; p < n; p += kSortThreads) {
+        const uint32_t key = __float_as_uint(depth[pidx[start + p]]);
+        k_or |= key;
+        k_and &= key;
+    }
+    uint32_t all_or, all_and;
+    block_or_and(k_or, k_and, sh.tmp, all_or, all_and);
+    const uint32_t diff = all_or ^ all_and;
+    const int lo = diff ? __builtin_ctz(diff) : 0, hi = diff ? 32 - __builtin_clz(diff) : 0;
+    const int passes = (hi - lo + kRadixBits - 1) / kRadixBits;
+    // source of the first pass: (sk1, pidx) for an even pass count, (sk0, sv) for odd
+    uint32_t *src_k = (passes & 1) ? sk0 : sk1, *src_v = (passes & 1) ? sv : pidx;
+    uint32_t *dst_k = (passes & 1) ? sk1 : sk0, *dst_v = (passes & 1) ? pidx : sv;
+    for (uint32_t p = t; p < n; p += kSortThreads) {
+        const uint32_t g = pidx[start + p];
+        src_k[start + p] = __float_as_uint(depth[g]);
+        if (passes & 1) src_v[start + p] = g;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = lo + pass * kRadixBits;
+        sh.local[t] = 0u;
+        __syncthreads();
+        for (uint32_t p = t; p < n; p += kSortThreads)
+            atomicAdd(&sh.local[(src_k[start + p] >> shift) & (kRadix - 1)], 1u);
+        __syncthreads();
+        uint32_t all;
+        sh.run[t] = block_exclusive_scan(sh.local[t], sh.tmp, all);
+        for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
+            const uint32_t cn = min(kSegMax, n - c0);
+            const int items = (int)((cn + kSortThreads - 1) / kSortThreads);
+            const uint32_t wbase = c0 + w * kWave * (uint32_t)items;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sh.wcnt[q][t] = 0u;
+            __syncthreads();
+            uint32_t k[kSegItems], v[kSegItems], rk[kSegItems];
+            uint32_t valid = 0;
+#pragma unroll
+            for (int i = 0; i < kSegItems; ++i) {
+                const uint32_t p = wbase + (uint32_t)i * kWave + l;
+                const bool ok = i < items && p < c0 + cn;
+                valid |= (uint32_t)ok << i;
+                k[i] = ok ? src_k[start + p] : 0u;
+                v[i] = ok ? src_v[start + p] : 0u;
+            }
+            wave_rank<kSegItems>(k, shift, valid, items, sh.wcnt[w], rk);
+            __syncthreads();
+            const uint32_t tot = digit_wave_prefix(sh, t);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kSegItems; ++i) {
+                if (!((valid >> i) & 1u)) continue;
+                const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+                const uint32_t o = sh.run[d] + sh.wcnt[w][d] + rk[i];
+                dst_k[start + o] = k[i];
+                dst_v[start + o] = v[i];
+            }
+            __syncthreads();
+            sh.run[t] += tot;
+        }
+        __syncthreads();
+        uint32_t* tk = src_k;
+        uint32_t* tv = src_v;
+        src_k = dst_k;
+        src_v = dst_v;
+        dst_k = tk;
+        dst_v = tv;
+    }
+    // the last pass wrote (sk1, pidx); with no pass the keys are in sk1 and pidx unchanged
+    if (keys64)
+        for (uint32_t p = t; p < n; p += kSortThreads) keys64[start + p] = ((uint64_t)tile << 32) | sk1[start + p];
+}
+
+// Step 7: one workgroup per tile sorts the tile's segment on the depth bits, stably.
+__global__ void __launch_bounds__(kSortThreads) segment_sort_kernel(
+    const uint32_t* __restrict__ ranges, uint32_t tiles_total, const float* __restrict__ depth,
+    uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p,
+    uint64_t capacity, const int32_t* __restrict__ status, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
+    uint32_t* __restrict__ sv) {
+    __shared__ SegShared sh;
+    if (*status != kStatusOk) return;
+    if ((uint64_t)*count_p > capacity) return;
+    const uint32_t tile = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (tile >= tiles_total) return;
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    if (end <= start) return;
+    const uint32_t n = end - start;
+    if (n <= kSegMax)
+        segment_sort_lds(sh, tile, start, n, depth, pidx, keys64);
+    else
+        segment_sort_global(sh, tile, start, n, depth, pidx, keys64, sk0, sk1, sv);
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -365,11 +605,12 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.tiles_total = (uint32_t)tiles;
     int tile_bits = 0;
     while (tile_bits < 32 && (1ull << tile_bits) < tiles) ++tile_bits;
-    p.passes = (31 + tile_bits + kRadixBits - 1) / kRadixBits;
+    p.passes = (tile_bits + kRadixBits - 1) / kRadixBits;
     p.sort_tiles = (uint32_t)((capacity + kSortTile - 1) / kSortTile);
     p.scan_blocks = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
     size_t off = 0;
-    p.off_keys_alt = off;   off = align256(off + capacity * 8);
+    p.off_keys_a = off;     off = align256(off + capacity * 4);
+    p.off_keys_b = off;     off = align256(off + capacity * 4);
     p.off_vals_alt = off;   off = align256(off + capacity * 4);
     // zero-initialised region: histograms, tickets, look-back words (contiguous)
     p.off_hist = off;       off += (size_t)kMaxPasses * kRadix * 4;
@@ -384,7 +625,8 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
 int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const int32_t* n_per_view,
                     const isogs_camera* cams, int32_t nv, const isogs_bins* bins, void* ws, hipStream_t stream) {
     char* base = static_cast<char*>(ws);
-    uint64_t* keys_alt = reinterpret_cast<uint64_t*>(base + plan.off_keys_alt);
+    uint32_t* keys_a = reinterpret_cast<uint32_t*>(base + plan.off_keys_a);
+    uint32_t* keys_b = reinterpret_cast<uint32_t*>(base + plan.off_keys_b);
     uint32_t* vals_alt = reinterpret_cast<uint32_t*>(base + plan.off_vals_alt);
     uint32_t* hist = reinterpret_cast<uint32_t*>(base + plan.off_hist);
     uint32_t* tickets = reinterpret_cast<uint32_t*>(base + plan.off_tickets);
@@ -415,11 +657,9 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     }
     if (hipPeekAtLastError() != hipSuccess) return -1;
 
-    // ping-pong so that the last pass lands in the caller's arrays
+    // ping-pong so that the last tile pass lands the values in the caller's pidx
     const bool odd = plan.passes & 1;
-    uint64_t* k_emit = odd ? keys_alt : bins->keys;
     uint32_t* v_emit = odd ? vals_alt : bins->pidx;
-    uint64_t* k_other = odd ? bins->keys : keys_alt;
     uint32_t* v_other = odd ? bins->pidx : vals_alt;
 
     // 3. emit, per group of views
@@ -446,35 +686,42 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         pk.block_begin[pk.nv] = blocks;
         if (blocks)
             hipLaunchKernelGGL(emit_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                               reinterpret_cast<const float4*>(proj->record), proj->depth, proj->tile_count,
-                               bins->offsets, bins->count, plan.capacity, k_emit, v_emit);
+                               reinterpret_cast<const float4*>(proj->record), proj->tile_count, bins->offsets,
+                               bins->count, plan.capacity, keys_a, v_emit);
     }
     if (plan.capacity == 0) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 
     // 4. histograms
-    const unsigned hist_blocks = (unsigned)std::min<uint64_t>(512, (plan.capacity + 255) / 256);
-    hipLaunchKernelGGL(sort_hist_kernel, dim3(hist_blocks), dim3(256), 0, stream, k_emit, bins->count,
-                       plan.capacity, plan.passes, hist);
-    // 5. radix passes
-    const uint64_t* kin = k_emit;
+    if (plan.passes) {
+        const unsigned hist_blocks = (unsigned)std::min<uint64_t>(512, (plan.capacity + 255) / 256);
+        hipLaunchKernelGGL(sort_hist_kernel, dim3(hist_blocks), dim3(256), 0, stream, keys_a, bins->count,
+                           plan.capacity, plan.passes, hist);
+    }
+    // 5. radix passes over the tile id
+    const uint32_t* kin = keys_a;
     const uint32_t* vin = v_emit;
-    uint64_t* kout = k_other;
+    uint32_t* kout = keys_b;
     uint32_t* vout = v_other;
     for (int p = 0; p < plan.passes; ++p) {
         hipLaunchKernelGGL(sort_pass_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, kout,
-                           vout, bins->count, plan.capacity, p, hist,
+                           vout, bins->count, plan.capacity, p * kRadixBits, hist + p * kRadix,
                            lookback + (size_t)p * plan.sort_tiles * kRadix, tickets + p, bins->status);
-        const uint64_t* tk = kin;
+        const uint32_t* tk = kin;
         const uint32_t* tv = vin;
         kin = kout;
         vin = vout;
-        kout = const_cast<uint64_t*>(tk);
+        kout = const_cast<uint32_t*>(tk);
         vout = const_cast<uint32_t*>(tv);
     }
     // 6. ranges
     const unsigned fin_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 255) / 256);
-    hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks), dim3(256), 0, stream, bins->keys, bins->count,
-                       plan.capacity, plan.tiles_total, bins->ranges);
+    hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks), dim3(256), 0, stream, kin, bins->count, plan.capacity,
+                       plan.tiles_total, bins->ranges);
+    // 7. depth order within every tile (the tile-id arrays and vals_alt are scratch now)
+    if (plan.tiles_total)
+        hipLaunchKernelGGL(segment_sort_kernel, dim3(plan.tiles_total), dim3(kSortThreads), 0, stream, bins->ranges,
+                           plan.tiles_total, proj->depth, bins->pidx, bins->keys, bins->count, plan.capacity,
+                           bins->status, keys_a, keys_b, vals_alt);
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }
 

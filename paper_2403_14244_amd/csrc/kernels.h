@@ -15,10 +15,10 @@ struct BinSortPlan {
     uint64_t capacity;
     uint32_t n_total;       // packed particles over all views
     uint32_t tiles_total;   // global tiles over all views
-    int passes;             // radix passes (8-bit digits) over the compacted key
+    int passes;             // radix passes (8-bit digits) over the tile id
     uint32_t sort_tiles;    // 4096-entry sort tiles for `capacity`
     uint32_t scan_blocks;   // 2048-particle scan blocks
-    size_t off_keys_alt, off_vals_alt, off_hist, off_tickets, off_lookback, off_block_sums,
+    size_t off_keys_a, off_keys_b, off_vals_alt, off_hist, off_tickets, off_lookback, off_block_sums,
         off_flags, bytes;
 };
 

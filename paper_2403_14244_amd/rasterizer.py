@@ -91,7 +91,7 @@ class Footprints:
 class TileBins:
     """Output of bin_sort. Entry arrays hold `capacity` slots; `count` and `status` live
     on the device."""
-    keys: torch.Tensor           # [capacity] int64 (uint64 on the device)
+    keys: torch.Tensor | None    # [capacity] int64 (uint64 on the device); None: not requested
     pidx: torch.Tensor           # [capacity] int32
     ranges: torch.Tensor         # [T, 2] int32
     offsets: torch.Tensor        # [N] int32
@@ -101,7 +101,8 @@ class TileBins:
 
     def abi(self) -> A.Bins:
         b = A.Bins()
-        b.keys, b.pidx = _p(self.keys), _p(self.pidx)
+        b.keys = _p(self.keys) if self.keys is not None else None
+        b.pidx = _p(self.pidx)
         b.ranges, b.offsets = _p(self.ranges), _p(self.offsets)
         b.capacity = self.capacity
         b.count, b.status = _p(self.count), _p(self.status)
@@ -120,9 +121,9 @@ def tiles_of(cam) -> int:
     return ((int(cam.width) + 15) // 16) * ((int(cam.height) + 15) // 16)
 
 
-def _alloc_bins(capacity, n_total, tiles_total, device) -> TileBins:
+def _alloc_bins(capacity, n_total, tiles_total, device, with_keys=False) -> TileBins:
     cap = max(int(capacity), 1)
-    return TileBins(keys=torch.empty(cap, dtype=torch.int64, device=device),
+    return TileBins(keys=torch.empty(cap, dtype=torch.int64, device=device) if with_keys else None,
                     pidx=torch.empty(cap, dtype=torch.int32, device=device),
                     ranges=torch.empty((tiles_total, 2), dtype=torch.int32, device=device),
                     offsets=torch.empty(max(n_total, 1), dtype=torch.int32, device=device)[:n_total],
@@ -139,6 +140,7 @@ class Rasterizer:
         self.device = torch.device(device)
         self.headroom = headroom
         self.capacity = 0
+        self.persistent_fwd = False
         self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
 
     def _workspace(self, nbytes):
@@ -154,14 +156,16 @@ class Rasterizer:
         A.check(A.lib().isogs_project(sc, A.camera_array(cams), len(cams), ctypes.byref(fp.abi()), _stream()))
         return fp
 
-    def bin_sort(self, fp: Footprints, n_per_view, cams, check=True, capacity=None) -> TileBins:
+    def bin_sort(self, fp: Footprints, n_per_view, cams, check=True, capacity=None, with_keys=False) -> TileBins:
+        """Bins and sorts the entries. The 64-bit (tile, depth) keys are written only with
+        `with_keys` (compositing needs pidx and the tile ranges alone)."""
         npv = A.int_array(n_per_view)
         carr = A.camera_array(cams)
         n_total = int(sum(n_per_view))
         tiles_total = sum(tiles_of(c) for c in cams)
         cap = self.capacity if capacity is None else capacity
         for _ in range(2):
-            bins = _alloc_bins(cap, n_total, tiles_total, self.device)
+            bins = _alloc_bins(cap, n_total, tiles_total, self.device, with_keys)
             ab = bins.abi()
             need = ctypes.c_size_t(0)
             A.check(A.lib().isogs_bin_sort(ctypes.byref(fp.abi()), npv, carr, len(cams), ctypes.byref(ab), None,
@@ -249,11 +253,26 @@ class Rasterizer:
 
     # -- convenience ------------------------------------------------------------------
     def render(self, scenes, cams, bg=(0.0, 0.0, 0.0), check=True):
-        """Full forward pass. Returns (list of [3, H, W] images, state for backward)."""
+        """Full forward pass. Returns (list of [3, H, W] images, state for backward).
+
+        Everything is queued before the one host synchronisation that `check` needs (the
+        capacity status); on overflow the capacity grows and the pass is redone. With
+        `persistent_fwd` set, compositing uses the longest-list-first persistent kernel
+        (same images bitwise)."""
         fp = self.project(scenes, cams)
         npv = [s.n for s in scenes]
-        bins = self.bin_sort(fp, npv, cams, check=check)
-        image, T, n_last = self.render_fwd(fp, npv, bins, cams, bg)
+        fwd = self.render_fwd_persistent if self.persistent_fwd else self.render_fwd
+        bins = self.bin_sort(fp, npv, cams, check=False)
+        out = fwd(fp, npv, bins, cams, bg)
+        if check:
+            st = int(bins.status.item())
+            if st == A.ISOGS_ERR_CAPACITY:
+                self.capacity = int(bins.n_entries() * self.headroom) + 4096
+                bins = self.bin_sort(fp, npv, cams, check=True)
+                out = fwd(fp, npv, bins, cams, bg)
+            elif st != A.ISOGS_OK:
+                raise A.IsoGSError(st, "bin_sort failed on the device")
+        image, T, n_last = out
         return split_images(image, cams), dict(fp=fp, bins=bins, image=image, T=T, n_last=n_last, npv=npv)
 
 

@@ -241,6 +241,18 @@ def workload_cameras(name: str, view_ids=None, width=None, height=None):
                          height or w["height"]) for i in ids]
 
 
+def crowded_projected(n, width, height, cx, cy, spread, seed=0, max_radius=6.0, depths=None):
+    """Binning-only footprints crowded around (cx, cy) (uniform within +-spread), so that
+    one tile holds many entries. `depths`: a set of values to draw from (exact ties), or
+    None for uniform depths in [0.5, 80]."""
+    rng = np.random.default_rng(seed)
+    u = cx + rng.uniform(-spread, spread, size=n)
+    v = cy + rng.uniform(-spread, spread, size=n)
+    r = rng.uniform(0.0, max_radius, size=n)
+    z = rng.uniform(0.5, 80.0, size=n) if depths is None else rng.choice(np.asarray(depths, np.float64), size=n)
+    return u.astype(np.float32), v.astype(np.float32), z.astype(np.float32), r.astype(np.float32)
+
+
 def random_projected(n, width, height, seed=0, max_radius=12.0, depth_ties=False):
     """Random per-Gaussian screen footprints (u, v, depth, radius) in FP32, for the
     binning stage alone: centres spread past the image borders, some radii zero-ish,

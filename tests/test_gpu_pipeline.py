@@ -116,6 +116,26 @@ def _bin_case(name):
         cams = [S.orbit_camera(1.0, 4.0, 1920, 1080)]
         projs = [O.project64(sc, c) for c in cams]
         return H.oracle_f32_footprints(projs, cams), cams
+    if name in ("crowd_wide_depth", "crowd_narrow_depth"):
+        # one tile with thousands of entries: the segment sort's multi-chunk path, with an
+        # even (wide depths) and an odd (eight tied depth values) number of digit passes
+        wide = name == "crowd_wide_depth"
+        n = 9000 if wide else 5000
+        u, v, z, r = S.crowded_projected(n, 96, 64, 40.0, 24.0, 7.5, seed=31 if wide else 32, max_radius=6.0,
+                                         depths=None if wide else [2.0 + k / 8 for k in range(8)])
+        return [H.synthetic_f32_footprints(u, v, z, r, 96, 64, seed=3)], [S.look_at_camera((0, 0, 3), width=96, height=64)]
+    if name == "segment_4096_4097":
+        # footprints inside one tile each: a segment of exactly 4096 entries (largest sorted
+        # in LDS) and one of 4097 (smallest sorted in chunks)
+        views, cams = [], []
+        for k, n in enumerate((4096, 4097)):
+            u, v, z, r = S.crowded_projected(n, 48, 32, 24.0, 8.0, 2.0, seed=40 + k, max_radius=0.5)
+            views.append(H.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
+            cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
+        return views, cams
+    if name == "single_tile":
+        u, v, z, r = S.random_projected(400, 16, 16, seed=50, max_radius=6.0, depth_ties=True)
+        return [H.synthetic_f32_footprints(u, v, z, r, 16, 16)], [S.look_at_camera((0, 0, 3), width=16, height=16)]
     if name == "empty_and_culled":
         sc = small_mix(500, 6, 0)
         sc.pos[2, :] = 50.0     # all behind a camera looking down -z from z=3 ... culled
@@ -127,7 +147,8 @@ def _bin_case(name):
     raise KeyError(name)
 
 
-BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled"]
+BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled",
+             "crowd_wide_depth", "crowd_narrow_depth", "segment_4096_4097", "single_tile"]
 
 
 @pytest.mark.parametrize("case", BIN_CASES)
@@ -138,7 +159,7 @@ def test_bin_sort_bit_exact(P, torch_cuda, case):
     R = P.Rasterizer()
     fp = H.upload_footprints(views, ob)
     npv = [v["u"].shape[0] for v in views]
-    bins = R.bin_sort(fp, npv, cams)
+    bins = R.bin_sort(fp, npv, cams, with_keys=True)
     torch_cuda.cuda.synchronize()
     cnt = bins.n_entries()
     assert cnt == ob.keys.shape[0]
@@ -146,6 +167,11 @@ def test_bin_sort_bit_exact(P, torch_cuda, case):
     np.testing.assert_array_equal(bins.pidx[:cnt].cpu().numpy().view(np.uint32), ob.pidx)
     np.testing.assert_array_equal(bins.ranges.cpu().numpy().view(np.uint32), ob.ranges)
     np.testing.assert_array_equal(bins.offsets.cpu().numpy().view(np.uint32), ob.offsets)
+    # without the optional keys the entry order is the same
+    nk = R.bin_sort(fp, npv, cams)
+    assert nk.keys is None
+    np.testing.assert_array_equal(nk.pidx[:cnt].cpu().numpy().view(np.uint32), ob.pidx)
+    np.testing.assert_array_equal(nk.ranges.cpu().numpy().view(np.uint32), ob.ranges)
 
 
 def test_bin_sort_capacity_overflow_reports_and_recovers(P, torch_cuda):
@@ -163,7 +189,7 @@ def test_bin_sort_capacity_overflow_reports_and_recovers(P, torch_cuda):
     # the render of an overflowed bin set leaves its outputs untouched
     img, T, nl = R.render_fwd(fp, [views[0]["u"].shape[0]], small, cams)
     # growing on demand gives the exact lists
-    ok = R.bin_sort(fp, [views[0]["u"].shape[0]], cams)
+    ok = R.bin_sort(fp, [views[0]["u"].shape[0]], cams, with_keys=True)
     assert ok.capacity >= ob.keys.shape[0]
     np.testing.assert_array_equal(ok.keys[:ok.n_entries()].cpu().numpy().view(np.uint64), ob.keys)
 
