@@ -3,20 +3,22 @@
 // The sort is split by key part. Entries are emitted in particle order, which is the tie
 // order of the (tile, depth) sort; a stable sort on the tile id alone therefore leaves
 // each tile's entries in emit order, and a stable sort of every tile's segment on depth
-// then yields exactly the stable (tile, depth) order. The global passes move 8 bytes per
-// entry over ceil(tile bits / 8) passes instead of 12 bytes over ceil((tile bits + 31) / 8),
-// and the depth sort runs per tile in LDS.
+// then yields exactly the stable (tile, depth) order. The global passes rank only the tile
+// bits (ceil(tile bits / 8) passes instead of ceil((tile bits + 31) / 8)), carrying the
+// particle index and the depth bits along so that the per-tile depth sort, which runs in
+// LDS, reads its keys sequentially instead of gathering them.
 //
 // Steps (all on the caller's stream, no host synchronisation):
 //   1. fill        zero tile ranges, radix histograms, tickets and look-back words
 //   2. scan        exclusive scan of per-particle tile counts -> emit offsets, total, status
-//   3. emit        one (tile id, particle index) pair per (particle, member tile)
+//   3. emit        one (tile id, particle index, depth bits) per (particle, member tile)
 //   4. histogram   digit counts of every tile-id pass in one read of the ids
 //   5. passes      stable LSD radix passes over the tile id, 8-bit digits, each a single
 //                  kernel with decoupled look-back
 //   6. finalize    tile ranges [start, end)
 //   7. segments    stable sort of each tile's segment on the depth bits (and the 64-bit
-//                  (tile, depth) keys, when the caller asks for them)
+//                  (tile, depth) keys, when the caller asks for them): one wave per short
+//                  segment, one workgroup per long one
 #include "common.h"
 #include <algorithm>
 
@@ -39,6 +41,26 @@ constexpr uint32_t kLbAggregate = 1u << 30;              // look-back word: tile
 constexpr uint32_t kLbInclusive = 2u << 30;              // look-back word: prefix through tile
 constexpr uint32_t kLbValue = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLbWindow = 8;                              // look-back words read per round trip
+
+// Splits the key bits [lo, hi) into the fewest passes of at most 8 bits, widths as equal as
+// possible (ballot ranking costs one ballot per digit bit, so no pass ranks unused bits).
+struct DigitSplit {
+    int passes, base, extra, lo;
+    __host__ __device__ DigitSplit(int lo_, int hi_) : lo(lo_) {
+        const int span = hi_ > lo_ ? hi_ - lo_ : 0;
+        passes = (span + kRadixBits - 1) / kRadixBits;
+        base = passes ? span / passes : 0;
+        extra = passes ? span % passes : 0;
+    }
+    __host__ __device__ int width(int p) const { return base + (p < extra ? 1 : 0); }
+    __host__ __device__ int shift(int p) const { return lo + p * base + (p < extra ? p : extra); }
+};
+
+// Digit of key k at (shift, bits).
+__device__ __forceinline__ uint32_t digit_at(uint32_t k, int shift, int bits) {
+    return (k >> shift) & ((1u << bits) - 1u);
+}
 
 // Inclusive scan over the 64 lanes of a wave.
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
@@ -51,16 +73,21 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
     return x;
 }
 
-// Exclusive scan over a 256-thread block; s_tmp holds 4 words. Returns the block total
+// Exclusive scan over a block of NW waves; s_tmp holds NW words. Returns the block total
 // in `total`. Contains __syncthreads.
+template <int NW = 4>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s_tmp, uint32_t& total) {
     const uint32_t w = threadIdx.x >> 6;
     const uint32_t inc = wave_inclusive_scan(x);
     if (lane_id() == kWave - 1) s_tmp[w] = inc;
     __syncthreads();
     uint32_t before = 0;
-    for (uint32_t j = 0; j < w; ++j) before += s_tmp[j];
-    total = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+    total = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        before += ((uint32_t)j < w) ? s_tmp[j] : 0u;
+        total += s_tmp[j];
+    }
     __syncthreads();
     return before + inc - x;
 }
@@ -138,8 +165,10 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
 __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ record,
                                                    const uint32_t* __restrict__ tile_count,
                                                    const uint32_t* __restrict__ offsets,
+                                                   const float* __restrict__ depth,
                                                    const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                   uint32_t* __restrict__ zbits) {
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     const int vi = view_of_block(pk, blockIdx.x);
@@ -153,6 +182,7 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
     if ((uint64_t)e0 + want > count) return;
     const float4 fp = record[2 * (size_t)i];
     const float r = record[2 * (size_t)i + 1].w;
+    const uint32_t z = __float_as_uint(depth[i]);
     int tx0, tx1, ty0, ty1;
     tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
     const float r2 = r * r;
@@ -164,38 +194,47 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
             const uint32_t e = e0 + j++;
             keys[e] = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
             vals[e] = i;
+            zbits[e] = z;
         }
     }
     for (; j < want; ++j) {
         keys[e0 + j] = 0xFFFFFFFFu;
         vals[e0 + j] = i;
+        zbits[e0 + j] = z;
     }
 }
 
 // Step 4: digit histograms of all tile-id passes in one sweep over the ids.
 __global__ void __launch_bounds__(256) sort_hist_kernel(const uint32_t* __restrict__ keys,
                                                         const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                        int passes, uint32_t* __restrict__ hist) {
+                                                        const DigitSplit split, uint32_t* __restrict__ hist) {
+    const int passes = split.passes;
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
     for (int p = 0; p < kMaxPasses; ++p) s_h[p][threadIdx.x] = 0u;
     __syncthreads();
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    // neighbouring entries mostly share their high digits: a wave whose lanes all hold the
-    // same digit adds once instead of 64 times to one LDS word
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < count; i0 += stride) {
-        const uint32_t i = i0 + threadIdx.x;
-        const bool ok = i < count;
-        const uint32_t c = ok ? keys[i] : 0u;
-        const uint64_t act = ballot64(ok);
-        for (int p = 0; p < passes; ++p) {
-            const uint32_t d = (c >> (p * kRadixBits)) & (kRadix - 1);
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-            if (ballot64(ok && d != d0) == 0) {
-                if (lane_id() == 0 && act) atomicAdd(&s_h[p][d0], (uint32_t)__popcll(act));
-            } else if (ok) {
-                atomicAdd(&s_h[p][d], 1u);
+    // eight loads per thread in flight per sweep step. Neighbouring entries mostly share
+    // their high digits: a wave whose lanes all hold the same digit adds once instead of 64
+    // times to one LDS word.
+    constexpr uint32_t kItems = 8;
+    const uint32_t step = gridDim.x * blockDim.x * kItems;
+    for (uint32_t b0 = blockIdx.x * blockDim.x * kItems; b0 < count; b0 += step) {
+        uint32_t c[kItems];
+#pragma unroll
+        for (uint32_t j = 0; j < kItems; ++j) c[j] = keys[min(b0 + j * blockDim.x + threadIdx.x, count - 1)];
+#pragma unroll
+        for (uint32_t j = 0; j < kItems; ++j) {
+            const bool ok = b0 + j * blockDim.x + threadIdx.x < count;
+            const uint64_t act = ballot64(ok);
+            for (int p = 0; p < passes; ++p) {
+                const uint32_t d = digit_at(c[j], split.shift(p), split.width(p));
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+                if (ballot64(ok && d != d0) == 0) {
+                    if (lane_id() == 0 && act) atomicAdd(&s_h[p][d0], (uint32_t)__popcll(act));
+                } else if (ok) {
+                    atomicAdd(&s_h[p][d], 1u);
+                }
             }
         }
     }
@@ -206,7 +245,7 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint32_t* __restri
     }
 }
 
-// Ranks up to ITEMS items per lane within the wave by 8-bit digit. Items are taken in
+// Ranks up to ITEMS items per lane within the wave by a digit of `bits` <= 8 bits. Items are taken in
 // rounds (item i of every lane in round i, lanes in order), so ranks follow the order
 // (round, lane). Lanes with equal digits are matched bit by bit with ballots; an item's
 // rank is the wave's count of its digit in earlier rounds plus the matching lanes below
@@ -214,24 +253,32 @@ __global__ void __launch_bounds__(256) sort_hist_kernel(const uint32_t* __restri
 // digit totals. Bit i of `valid` marks item i as present; `items` (uniform) bounds the
 // rounds.
 template <int ITEMS>
-__device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift, uint32_t valid, int items,
-                                          uint32_t* __restrict__ cnt, uint32_t (&rk)[ITEMS]) {
+__device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift, int bits, uint32_t valid,
+                                          int items, uint32_t* __restrict__ cnt, uint32_t (&rk)[ITEMS]) {
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        if (i >= items) break;
-        const uint32_t d = (k[i] >> shift) & (kRadix - 1);
-        const bool ok = (valid >> i) & 1u;
-        uint64_t m = ballot64(ok);
+        if (i < items) {
+            const uint32_t d = digit_at(k[i], shift, bits);
+            const bool ok = (valid >> i) & 1u;
+            const uint64_t okm = ballot64(ok);
+            uint32_t m_lo = (uint32_t)okm, m_hi = (uint32_t)(okm >> 32);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = ballot64(bit);
-            m &= bit ? bal : ~bal;
+            for (int b = 0; b < kRadixBits; ++b) {
+                if (b < bits) {
+                    // keep the lanes whose bit b equals this lane's: m &= ~(ballot ^ sign(bit))
+                    // (one three-input bitwise instruction per half)
+                    const uint32_t sx = (uint32_t)((int32_t)(d << (31 - b)) >> 31);   // bit b, sign-extended
+                    const uint64_t bal = ballot64(sx != 0u);
+                    m_lo &= ~((uint32_t)bal ^ sx);
+                    m_hi &= ~((uint32_t)(bal >> 32) ^ sx);
+                }
+            }
+            const uint64_t m = ((uint64_t)m_hi << 32) | m_lo;
+            const uint32_t below = rank_below(m);
+            const uint32_t prior = cnt[d];
+            rk[i] = prior + below;
+            if (ok && below == 0) cnt[d] = prior + (uint32_t)__popcll(m);
         }
-        const uint32_t below = rank_below(m);
-        const uint32_t prior = cnt[d];
-        rk[i] = prior + below;
-        if (ok && below == 0) cnt[d] = prior + (uint32_t)__popcll(m);
     }
 }
 
@@ -241,11 +288,12 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift,
 // tiles' words, then reorders the tile in LDS so the scatter writes contiguous runs per
 // digit.
 __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ count_p, uint64_t capacity, int shift,
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, const uint32_t* __restrict__ zin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t* __restrict__ zout,
+    const uint32_t* __restrict__ count_p, uint64_t capacity, int shift, int bits,
     const uint32_t* __restrict__ hist, uint32_t* __restrict__ lookback, uint32_t* __restrict__ ticket,
     int32_t* __restrict__ status) {
-    __shared__ uint32_t s_buf[kSortTile];   // tile reordered by digit: keys, then values
+    __shared__ uint32_t s_buf[kSortTile];   // tile reordered by digit: keys, values, depth bits
     __shared__ uint8_t s_dig[kSortTile];     // digit at each reordered position
     __shared__ uint32_t s_wcnt[4][kRadix];
     __shared__ uint32_t s_local[kRadix];
@@ -274,7 +322,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
         valid |= (uint32_t)ok << i;
         k[i] = ok ? kin[idx] : 0u;
     }
-    wave_rank<kSortItems>(k, shift, valid, kSortItems, s_wcnt[w], rk);
+    wave_rank<kSortItems>(k, shift, bits, valid, kSortItems, s_wcnt[w], rk);
     // values are needed only after the keys are placed: their loads overlap the look-back
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
@@ -295,23 +343,42 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t excl = 0;
     if (tile > 0) {
+        // look back over up to kLbWindow predecessors per round trip: every published
+        // word is consumed in order until an inclusive one; an unpublished word ends the
+        // round and is polled again
         int32_t j = (int32_t)tile - 1;
         uint32_t spins = 0;
-        while (j >= 0) {
-            const uint32_t word = __hip_atomic_load(&lb[(size_t)j * kRadix + t], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t flag = word & ~kLbValue;
-            if (flag == 0u) {
+        for (;;) {
+            uint32_t word[kLbWindow];
+#pragma unroll
+            for (int q = 0; q < kLbWindow; ++q)
+                word[q] = (j - q >= 0) ? __hip_atomic_load(&lb[(size_t)(j - q) * kRadix + t], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : kLbInclusive;
+            bool done = false, stalled = false;
+            int used = 0;
+#pragma unroll
+            for (int q = 0; q < kLbWindow; ++q) {
+                const uint32_t flag = word[q] & ~kLbValue;
+                if (!done && !stalled) {
+                    if (flag == 0u) {
+                        stalled = true;
+                    } else {
+                        excl += word[q] & kLbValue;
+                        ++used;
+                        done = flag == kLbInclusive;
+                    }
+                }
+            }
+            if (done) break;
+            j -= used;
+            if (used == 0) {
                 if (++spins > kSpinLimit) {
                     *status = kStatusDevice;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
-                continue;
             }
-            excl += word & kLbValue;
-            if (flag == kLbInclusive) break;
-            --j;
         }
         __hip_atomic_store(&lb[(size_t)tile * kRadix + t], kLbInclusive | (excl + mine), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -323,14 +390,14 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
     s_local[t] = lbase;
     __syncthreads();
 
-    // reorder in LDS by digit (stable), then write runs: keys first, then the values
-    // through the same buffer
+    // reorder in LDS by digit (stable), then write runs: keys first, then the values and
+    // the depth bits through the same buffer
     uint32_t lpos[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         lpos[i] = 0xFFFFFFFFu;
         if ((valid >> i) & 1u) {
-            const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+            const uint32_t d = digit_at(k[i], shift, bits);
             lpos[i] = s_local[d] + s_wcnt[w][d] + rk[i];
             s_buf[lpos[i]] = k[i];
         }
@@ -342,7 +409,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
         const uint32_t j = t + i * kSortThreads;
         if (j < n_here) {
             const uint32_t key = s_buf[j];
-            const uint32_t dd = (key >> shift) & (kRadix - 1);
+            const uint32_t dd = digit_at(key, shift, bits);
             s_dig[j] = (uint8_t)dd;
             const uint32_t dst = s_base[dd] + (j - s_local[dd]);
             if (dst < count) kout[dst] = key;
@@ -360,6 +427,26 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
             const uint32_t dd = s_dig[j];
             const uint32_t dst = s_base[dd] + (j - s_local[dd]);
             if (dst < count) vout[dst] = s_buf[j];
+        }
+    }
+    // the depth bits follow the same path (loaded late to keep registers free)
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t idx = wbase + i * kWave + lane;
+        v[i] = ((valid >> i) & 1u) ? zin[idx] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (lpos[i] != 0xFFFFFFFFu) s_buf[lpos[i]] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const uint32_t j = t + i * kSortThreads;
+        if (j < n_here) {
+            const uint32_t dd = s_dig[j];
+            const uint32_t dst = s_base[dd] + (j - s_local[dd]);
+            if (dst < count) zout[dst] = s_buf[j];
         }
     }
 }
@@ -422,7 +509,7 @@ __device__ __forceinline__ uint32_t digit_wave_prefix(SegShared& sh, uint32_t t)
 // each pass ranks by one 8-bit digit of the depth bits, reorders through LDS and reloads
 // in position order. Only the bits that differ within the segment are sorted on.
 __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, uint32_t start, uint32_t n,
-                                                 const float* __restrict__ depth, uint32_t* __restrict__ pidx,
+                                                 const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
                                                  uint64_t* __restrict__ keys64) {
     const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
     const int items = (int)((n + kSortThreads - 1) / kSortThreads);
@@ -430,27 +517,35 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
     uint32_t k[kSegItems], v[kSegItems], rk[kSegItems];
     uint32_t valid = 0;
     uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
+    // loads clamped into the segment rather than predicated, so that all of them are in
+    // flight at once
 #pragma unroll
     for (int i = 0; i < kSegItems; ++i) {
         const uint32_t p = wbase + (uint32_t)i * kWave + l;
-        const bool ok = i < items && p < n;
-        valid |= (uint32_t)ok << i;
-        v[i] = ok ? pidx[start + p] : 0u;
-        k[i] = ok ? __float_as_uint(depth[v[i]]) : 0u;
-        if (ok) {
-            k_or |= k[i];
-            k_and &= k[i];
-        }
+        valid |= (uint32_t)(i < items && p < n) << i;
+        v[i] = pidx[start + min(p, n - 1)];
+        k[i] = zs[start + min(p, n - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < kSegItems; ++i) {
+        const bool ok = (valid >> i) & 1u;
+        k_or |= ok ? k[i] : 0u;
+        k_and &= ok ? k[i] : 0xFFFFFFFFu;
     }
     uint32_t all_or, all_and;
     block_or_and(k_or, k_and, sh.tmp, all_or, all_and);
     const uint32_t diff = all_or ^ all_and;
-    const int lo = diff ? __builtin_ctz(diff) : 0, hi = diff ? 32 - __builtin_clz(diff) : 0;
-    for (int shift = lo; shift < hi; shift += kRadixBits) {
+    // uniform by construction; readfirstlane tells the compiler, so the digit loops branch
+    // on scalars
+    const int lo = __builtin_amdgcn_readfirstlane(diff ? __builtin_ctz(diff) : 0);
+    const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
+    const DigitSplit split(lo, hi);
+    for (int pass = 0; pass < split.passes; ++pass) {
+        const int shift = split.shift(pass), bits = split.width(pass);
 #pragma unroll
         for (int q = 0; q < 4; ++q) sh.wcnt[q][t] = 0u;
         __syncthreads();
-        wave_rank<kSegItems>(k, shift, valid, items, sh.wcnt[w], rk);
+        wave_rank<kSegItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
         __syncthreads();
         const uint32_t tot = digit_wave_prefix(sh, t);
         uint32_t all;
@@ -460,7 +555,7 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
 #pragma unroll
         for (int i = 0; i < kSegItems; ++i) {
             if ((valid >> i) & 1u) {
-                const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+                const uint32_t d = digit_at(k[i], shift, bits);
                 pos[i] = sh.local[d] + sh.wcnt[w][d] + rk[i];
                 sh.buf[pos[i]] = k[i];
             }
@@ -488,44 +583,67 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
     }
 }
 
-// Segment longer than kSegMax, sorted by one workgroup through global scratch: each pass
-// histograms the digit over the whole segment, then ranks chunk after chunk in order and
-// scatters every entry straight to its place. The ping-pong buffers are chosen so that the
-// last pass lands in pidx.
+// Segment longer than kSegMax, sorted by one workgroup through global scratch. A first
+// sweep copies (depth bits, particle index) to (sk0, sv) and reduces the differing bits;
+// each pass then scatters chunk after chunk straight to its place, counting the next
+// pass's digits on the way. Every sweep issues kSegItems independent loads per thread.
 __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile, uint32_t start, uint32_t n,
-                                                 const float* __restrict__ depth, uint32_t* __restrict__ pidx,
-                                                 uint64_t* __restrict__ keys64, uint32_t* __restrict__ sk0,
-                                                 uint32_t* __restrict__ sk1, uint32_t* __restrict__ sv) {
+                                                    const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
+                                                    uint64_t* __restrict__ keys64, uint32_t* __restrict__ sk0,
+                                                    uint32_t* __restrict__ sk1, uint32_t* __restrict__ sv) {
     const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
     uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
-    for (uint32_t p = t; p < n; p += kSortThreads) {
-        const uint32_t key = __float_as_uint(depth[pidx[start + p]]);
-        k_or |= key;
-        k_and &= key;
+    for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
+        uint32_t g[kSegItems], key[kSegItems];
+#pragma unroll
+        for (int i = 0; i < kSegItems; ++i) {
+            const uint32_t pc = min(c0 + (uint32_t)i * kSortThreads + t, n - 1);
+            g[i] = pidx[start + pc];
+            key[i] = zs[start + pc];
+        }
+#pragma unroll
+        for (int i = 0; i < kSegItems; ++i) {
+            const uint32_t p = c0 + (uint32_t)i * kSortThreads + t;
+            if (p < n) {
+                sk0[start + p] = key[i];
+                sv[start + p] = g[i];
+                k_or |= key[i];
+                k_and &= key[i];
+            }
+        }
     }
     uint32_t all_or, all_and;
-    block_or_and(k_or, k_and, sh.tmp, all_or, all_and);
+    block_or_and(k_or, k_and, sh.tmp, all_or, all_and);   // also orders the sweep's writes
     const uint32_t diff = all_or ^ all_and;
-    const int lo = diff ? __builtin_ctz(diff) : 0, hi = diff ? 32 - __builtin_clz(diff) : 0;
-    const int passes = (hi - lo + kRadixBits - 1) / kRadixBits;
-    // source of the first pass: (sk1, pidx) for an even pass count, (sk0, sv) for odd
-    uint32_t *src_k = (passes & 1) ? sk0 : sk1, *src_v = (passes & 1) ? sv : pidx;
-    uint32_t *dst_k = (passes & 1) ? sk1 : sk0, *dst_v = (passes & 1) ? pidx : sv;
-    for (uint32_t p = t; p < n; p += kSortThreads) {
-        const uint32_t g = pidx[start + p];
-        src_k[start + p] = __float_as_uint(depth[g]);
-        if (passes & 1) src_v[start + p] = g;
-    }
-    __syncthreads();
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = lo + pass * kRadixBits;
+    // uniform by construction; readfirstlane tells the compiler, so the digit loops branch
+    // on scalars
+    const int lo = __builtin_amdgcn_readfirstlane(diff ? __builtin_ctz(diff) : 0);
+    const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
+    const DigitSplit split(lo, hi);
+    const int passes = split.passes;
+    uint32_t *src_k = sk0, *src_v = sv, *dst_k = sk1, *dst_v = pidx;
+    if (passes > 0) {
+        // digit histogram of the first pass
         sh.local[t] = 0u;
         __syncthreads();
-        for (uint32_t p = t; p < n; p += kSortThreads)
-            atomicAdd(&sh.local[(src_k[start + p] >> shift) & (kRadix - 1)], 1u);
+        for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
+            uint32_t kk[kSegItems];
+#pragma unroll
+            for (int i = 0; i < kSegItems; ++i) kk[i] = src_k[start + min(c0 + (uint32_t)i * kSortThreads + t, n - 1)];
+#pragma unroll
+            for (int i = 0; i < kSegItems; ++i)
+                if (c0 + (uint32_t)i * kSortThreads + t < n) atomicAdd(&sh.local[digit_at(kk[i], split.shift(0), split.width(0))], 1u);
+        }
         __syncthreads();
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = split.shift(pass), bits = split.width(pass);
+        const bool has_next = pass + 1 < passes;
+        const int next_shift = has_next ? split.shift(pass + 1) : 0, next_bits = has_next ? split.width(pass + 1) : 0;
         uint32_t all;
-        sh.run[t] = block_exclusive_scan(sh.local[t], sh.tmp, all);
+        const uint32_t h = sh.local[t];
+        sh.run[t] = block_exclusive_scan(h, sh.tmp, all);
+        sh.local[t] = 0u;   // now the next pass's histogram
         for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
             const uint32_t cn = min(kSegMax, n - c0);
             const int items = (int)((cn + kSortThreads - 1) / kSortThreads);
@@ -538,22 +656,23 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
 #pragma unroll
             for (int i = 0; i < kSegItems; ++i) {
                 const uint32_t p = wbase + (uint32_t)i * kWave + l;
-                const bool ok = i < items && p < c0 + cn;
-                valid |= (uint32_t)ok << i;
-                k[i] = ok ? src_k[start + p] : 0u;
-                v[i] = ok ? src_v[start + p] : 0u;
+                valid |= (uint32_t)(i < items && p < c0 + cn) << i;
+                const uint32_t pc = min(p, n - 1);
+                k[i] = src_k[start + pc];
+                v[i] = src_v[start + pc];
             }
-            wave_rank<kSegItems>(k, shift, valid, items, sh.wcnt[w], rk);
+            wave_rank<kSegItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
             __syncthreads();
             const uint32_t tot = digit_wave_prefix(sh, t);
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < kSegItems; ++i) {
                 if (!((valid >> i) & 1u)) continue;
-                const uint32_t d = (k[i] >> shift) & (kRadix - 1);
+                const uint32_t d = digit_at(k[i], shift, bits);
                 const uint32_t o = sh.run[d] + sh.wcnt[w][d] + rk[i];
                 dst_k[start + o] = k[i];
                 dst_v[start + o] = v[i];
+                if (has_next) atomicAdd(&sh.local[digit_at(k[i], next_shift, next_bits)], 1u);
             }
             __syncthreads();
             sh.run[t] += tot;
@@ -566,29 +685,174 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
         dst_k = tk;
         dst_v = tv;
     }
-    // the last pass wrote (sk1, pidx); with no pass the keys are in sk1 and pidx unchanged
-    if (keys64)
-        for (uint32_t p = t; p < n; p += kSortThreads) keys64[start + p] = ((uint64_t)tile << 32) | sk1[start + p];
+    // sorted data in (src_k, src_v): (sk1, pidx) after an odd pass count, else (sk0, sv)
+    const bool in_place = src_v == pidx;
+    if (!in_place && passes == 0 && !keys64) return;   // order unchanged, pidx untouched
+    for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
+#pragma unroll
+        for (int i = 0; i < kSegItems; ++i) {
+            const uint32_t p = c0 + (uint32_t)i * kSortThreads + t;
+            if (p >= n) continue;
+            if (!in_place) pidx[start + p] = src_v[start + p];
+            if (keys64) keys64[start + p] = ((uint64_t)tile << 32) | src_k[start + p];
+        }
+    }
 }
 
-// Step 7: one workgroup per tile sorts the tile's segment on the depth bits, stably.
-__global__ void __launch_bounds__(kSortThreads) segment_sort_kernel(
-    const uint32_t* __restrict__ ranges, uint32_t tiles_total, const float* __restrict__ depth,
+// Wave-level segment sort, for segments of up to kWaveSegMax entries: one wave per tile,
+// items in registers (item i of lane l at position 64 i + l), each pass ranks by one 8-bit
+// digit with ballots, turns the wave's 256 digit counts into bases with a wave scan and
+// reorders through the wave's own LDS region. No workgroup barrier is involved: LDS
+// operations of one wave complete in order.
+constexpr int kWaveItems = 8;
+constexpr uint32_t kWaveSegMax = kWave * kWaveItems;
+
+struct WaveSegShared {
+    uint32_t buf[4][kWaveSegMax];
+    uint32_t cnt[4][kRadix];
+};
+
+__device__ __forceinline__ void wave_sort_segment(uint32_t* __restrict__ buf, uint32_t* __restrict__ cnt,
+                                                  uint32_t tile, uint32_t start, uint32_t n,
+                                                  const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
+                                                  uint64_t* __restrict__ keys64) {
+    const uint32_t l = lane_id();
+    const int items = (int)((n + kWave - 1) / kWave);
+    uint32_t k[kWaveItems], v[kWaveItems], rk[kWaveItems], pos[kWaveItems];
+    uint32_t valid = 0, k_or = 0u, k_and = 0xFFFFFFFFu;
+    // loads clamped into the segment rather than predicated, so that all of them are in
+    // flight at once
+#pragma unroll
+    for (int i = 0; i < kWaveItems; ++i) {
+        const uint32_t p = (uint32_t)i * kWave + l;
+        valid |= (uint32_t)(i < items && p < n) << i;
+        v[i] = pidx[start + min(p, n - 1)];
+        k[i] = zs[start + min(p, n - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < kWaveItems; ++i) {
+        const bool ok = (valid >> i) & 1u;
+        k_or |= ok ? k[i] : 0u;
+        k_and &= ok ? k[i] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        k_or |= __shfl_xor(k_or, o, kWave);
+        k_and &= __shfl_xor(k_and, o, kWave);
+    }
+    const uint32_t diff = k_or ^ k_and;
+    if (n <= kWave && diff) {
+        // one entry per lane: the rank is the number of smaller keys plus the number of
+        // equal keys at lower positions (about four instructions per entry)
+        const uint32_t key = k[0];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < n; ++j) {
+            const uint32_t kj = __builtin_amdgcn_readlane(key, (int)j);
+            rank += (kj < key || (kj == key && j < l)) ? 1u : 0u;
+        }
+        if (valid & 1u) {
+            pidx[start + rank] = v[0];
+            if (keys64) keys64[start + rank] = ((uint64_t)tile << 32) | key;
+        }
+        return;
+    }
+    // uniform by construction; readfirstlane tells the compiler, so the digit loops branch
+    // on scalars
+    const int lo = __builtin_amdgcn_readfirstlane(diff ? __builtin_ctz(diff) : 0);
+    const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
+    const DigitSplit split(lo, hi);
+    for (int pass = 0; pass < split.passes; ++pass) {
+        const int shift = split.shift(pass), bits = split.width(pass);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cnt[4 * l + q] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        wave_rank<kWaveItems>(k, shift, bits, valid, items, cnt, rk);
+        __builtin_amdgcn_wave_barrier();
+        // lane l owns digits 4l .. 4l+3: counts -> exclusive bases
+        const uint32_t c0 = cnt[4 * l], c1 = cnt[4 * l + 1], c2 = cnt[4 * l + 2], c3 = cnt[4 * l + 3];
+        const uint32_t sum = c0 + c1 + c2 + c3;
+        const uint32_t ex = wave_inclusive_scan(sum) - sum;
+        __builtin_amdgcn_wave_barrier();
+        cnt[4 * l] = ex;
+        cnt[4 * l + 1] = ex + c0;
+        cnt[4 * l + 2] = ex + c0 + c1;
+        cnt[4 * l + 3] = ex + c0 + c1 + c2;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < kWaveItems; ++i) {
+            if ((valid >> i) & 1u) {
+                pos[i] = cnt[digit_at(k[i], shift, bits)] + rk[i];
+                buf[pos[i]] = k[i];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < kWaveItems; ++i)
+            if ((valid >> i) & 1u) k[i] = buf[(uint32_t)i * kWave + l];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < kWaveItems; ++i)
+            if ((valid >> i) & 1u) buf[pos[i]] = v[i];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < kWaveItems; ++i)
+            if ((valid >> i) & 1u) v[i] = buf[(uint32_t)i * kWave + l];
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int i = 0; i < kWaveItems; ++i) {
+        if (!((valid >> i) & 1u)) continue;
+        const uint32_t p = (uint32_t)i * kWave + l;
+        if (hi > lo) pidx[start + p] = v[i];
+        if (keys64) keys64[start + p] = ((uint64_t)tile << 32) | k[i];
+    }
+}
+
+// Step 7a: one wave per tile sorts segments of up to kWaveSegMax entries and appends the
+// longer ones to a list for step 7b.
+__global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
+    const uint32_t* __restrict__ ranges, uint32_t tiles_total, const uint32_t* __restrict__ zs,
     uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p,
-    uint64_t capacity, const int32_t* __restrict__ status, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
-    uint32_t* __restrict__ sv) {
-    __shared__ SegShared sh;
+    uint64_t capacity, const int32_t* __restrict__ status, uint32_t* __restrict__ big_list,
+    uint32_t* __restrict__ big_count) {
+    __shared__ WaveSegShared sh;
     if (*status != kStatusOk) return;
     if ((uint64_t)*count_p > capacity) return;
-    const uint32_t tile = xcd_swizzle(blockIdx.x, gridDim.x);
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t tile = 4 * xcd_swizzle(blockIdx.x, gridDim.x) + w;
     if (tile >= tiles_total) return;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     if (end <= start) return;
     const uint32_t n = end - start;
-    if (n <= kSegMax)
-        segment_sort_lds(sh, tile, start, n, depth, pidx, keys64);
-    else
-        segment_sort_global(sh, tile, start, n, depth, pidx, keys64, sk0, sk1, sv);
+    if (n > kWaveSegMax) {
+        if (lane_id() == 0) big_list[atomicAdd(big_count, 1u)] = tile;
+        return;
+    }
+    wave_sort_segment(sh.buf[w], sh.cnt[w], tile, start, n, zs, pidx, keys64);
+}
+
+// Step 7b: a resident grid works through the list of long segments, one workgroup per
+// segment, with stable LSD radix passes: in LDS up to kSegMax entries, through the
+// workspace beyond.
+__global__ void __launch_bounds__(kSortThreads) segment_sort_big_kernel(
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
+    uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p, uint64_t capacity,
+    const int32_t* __restrict__ status, const uint32_t* __restrict__ big_list,
+    const uint32_t* __restrict__ big_count, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
+    uint32_t* __restrict__ sv) {
+    __shared__ SegShared sh;
+    if (*status != kStatusOk) return;
+    if ((uint64_t)*count_p > capacity) return;
+    const uint32_t nb = *big_count;
+    for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const uint32_t tile = big_list[i];
+        const uint32_t start = ranges[2 * tile], n = ranges[2 * tile + 1] - start;
+        if (n <= kSegMax)
+            segment_sort_lds(sh, tile, start, n, zs, pidx, keys64);
+        else
+            segment_sort_global(sh, tile, start, n, zs, pidx, keys64, sk0, sk1, sv);
+        __syncthreads();
+    }
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -603,21 +867,27 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     }
     p.n_total = (uint32_t)n;
     p.tiles_total = (uint32_t)tiles;
+    // 2^tile_bits > tiles: the sentinel id 0xFFFFFFFF, cut to the sorted bits, still sorts
+    // after every real tile id
     int tile_bits = 0;
-    while (tile_bits < 32 && (1ull << tile_bits) < tiles) ++tile_bits;
-    p.passes = (tile_bits + kRadixBits - 1) / kRadixBits;
+    while (tile_bits < 32 && (1ull << tile_bits) <= tiles) ++tile_bits;
+    p.passes = DigitSplit(0, tile_bits).passes;
+    p.tile_bits = tile_bits;
     p.sort_tiles = (uint32_t)((capacity + kSortTile - 1) / kSortTile);
     p.scan_blocks = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
     size_t off = 0;
     p.off_keys_a = off;     off = align256(off + capacity * 4);
     p.off_keys_b = off;     off = align256(off + capacity * 4);
     p.off_vals_alt = off;   off = align256(off + capacity * 4);
+    p.off_z_a = off;        off = align256(off + capacity * 4);
+    p.off_z_b = off;        off = align256(off + capacity * 4);
     // zero-initialised region: histograms, tickets, look-back words (contiguous)
     p.off_hist = off;       off += (size_t)kMaxPasses * kRadix * 4;
-    p.off_tickets = off;    off += (size_t)kMaxPasses * 4;
+    p.off_tickets = off;    off += (size_t)(kMaxPasses + 1) * 4;   // + the long-segment count
     p.off_lookback = off;   off = align256(off + (size_t)p.passes * p.sort_tiles * kRadix * 4);
     p.off_block_sums = off; off = align256(off + (size_t)(p.scan_blocks + 1) * 4);
     p.off_flags = off;      off = align256(off + 64);
+    p.off_big_list = off;   off = align256(off + (size_t)tiles * 4);
     p.bytes = off;
     return p;
 }
@@ -628,6 +898,8 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     uint32_t* keys_a = reinterpret_cast<uint32_t*>(base + plan.off_keys_a);
     uint32_t* keys_b = reinterpret_cast<uint32_t*>(base + plan.off_keys_b);
     uint32_t* vals_alt = reinterpret_cast<uint32_t*>(base + plan.off_vals_alt);
+    uint32_t* z_a = reinterpret_cast<uint32_t*>(base + plan.off_z_a);
+    uint32_t* z_b = reinterpret_cast<uint32_t*>(base + plan.off_z_b);
     uint32_t* hist = reinterpret_cast<uint32_t*>(base + plan.off_hist);
     uint32_t* tickets = reinterpret_cast<uint32_t*>(base + plan.off_tickets);
     uint32_t* lookback = reinterpret_cast<uint32_t*>(base + plan.off_lookback);
@@ -687,41 +959,58 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         if (blocks)
             hipLaunchKernelGGL(emit_kernel, dim3(blocks), dim3(256), 0, stream, pk,
                                reinterpret_cast<const float4*>(proj->record), proj->tile_count, bins->offsets,
-                               bins->count, plan.capacity, keys_a, v_emit);
+                               proj->depth, bins->count, plan.capacity, keys_a, v_emit, z_a);
     }
     if (plan.capacity == 0) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 
     // 4. histograms
     if (plan.passes) {
-        const unsigned hist_blocks = (unsigned)std::min<uint64_t>(512, (plan.capacity + 255) / 256);
+        const unsigned hist_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 2047) / 2048);
         hipLaunchKernelGGL(sort_hist_kernel, dim3(hist_blocks), dim3(256), 0, stream, keys_a, bins->count,
-                           plan.capacity, plan.passes, hist);
+                           plan.capacity, DigitSplit(0, plan.tile_bits), hist);
     }
     // 5. radix passes over the tile id
     const uint32_t* kin = keys_a;
     const uint32_t* vin = v_emit;
+    const uint32_t* zin = z_a;
     uint32_t* kout = keys_b;
     uint32_t* vout = v_other;
+    uint32_t* zout = z_b;
+    const DigitSplit tsplit(0, plan.tile_bits);
     for (int p = 0; p < plan.passes; ++p) {
-        hipLaunchKernelGGL(sort_pass_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, kout,
-                           vout, bins->count, plan.capacity, p * kRadixBits, hist + p * kRadix,
+        hipLaunchKernelGGL(sort_pass_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, zin,
+                           kout, vout, zout, bins->count, plan.capacity, tsplit.shift(p), tsplit.width(p),
+                           hist + p * kRadix,
                            lookback + (size_t)p * plan.sort_tiles * kRadix, tickets + p, bins->status);
         const uint32_t* tk = kin;
         const uint32_t* tv = vin;
+        const uint32_t* tz = zin;
         kin = kout;
         vin = vout;
+        zin = zout;
         kout = const_cast<uint32_t*>(tk);
         vout = const_cast<uint32_t*>(tv);
+        zout = const_cast<uint32_t*>(tz);
     }
     // 6. ranges
     const unsigned fin_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 255) / 256);
     hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks), dim3(256), 0, stream, kin, bins->count, plan.capacity,
                        plan.tiles_total, bins->ranges);
-    // 7. depth order within every tile (the tile-id arrays and vals_alt are scratch now)
-    if (plan.tiles_total)
-        hipLaunchKernelGGL(segment_sort_kernel, dim3(plan.tiles_total), dim3(kSortThreads), 0, stream, bins->ranges,
-                           plan.tiles_total, proj->depth, bins->pidx, bins->keys, bins->count, plan.capacity,
-                           bins->status, keys_a, keys_b, vals_alt);
+    // 7. depth order within every tile (zin: depth bits in the order of pidx; the tile-id
+    // arrays and vals_alt are scratch now)
+    if (plan.tiles_total) {
+        static int big_grid = 0;
+        if (!big_grid) big_grid = resident_blocks(reinterpret_cast<const void*>(segment_sort_big_kernel), kSortThreads);
+        if (!big_grid) return -1;
+        uint32_t* big_count = tickets + kMaxPasses;
+        uint32_t* big_list = reinterpret_cast<uint32_t*>(base + plan.off_big_list);
+        hipLaunchKernelGGL(segment_sort_small_kernel, dim3((plan.tiles_total + 3) / 4), dim3(kSortThreads), 0, stream,
+                           bins->ranges, plan.tiles_total, zin, bins->pidx, bins->keys, bins->count,
+                           plan.capacity, bins->status, big_list, big_count);
+        hipLaunchKernelGGL(segment_sort_big_kernel, dim3((unsigned)std::min<uint32_t>(plan.tiles_total, big_grid)),
+                           dim3(kSortThreads), 0, stream, bins->ranges, zin, bins->pidx, bins->keys,
+                           bins->count, plan.capacity, bins->status, big_list, big_count, keys_a, keys_b, vals_alt);
+    }
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -15,11 +15,12 @@ struct BinSortPlan {
     uint64_t capacity;
     uint32_t n_total;       // packed particles over all views
     uint32_t tiles_total;   // global tiles over all views
-    int passes;             // radix passes (8-bit digits) over the tile id
+    int passes;             // radix passes (digits of at most 8 bits) over the tile id
+    int tile_bits;          // bits of the largest global tile id
     uint32_t sort_tiles;    // 4096-entry sort tiles for `capacity`
     uint32_t scan_blocks;   // 2048-particle scan blocks
-    size_t off_keys_a, off_keys_b, off_vals_alt, off_hist, off_tickets, off_lookback, off_block_sums,
-        off_flags, bytes;
+    size_t off_keys_a, off_keys_b, off_vals_alt, off_z_a, off_z_b, off_hist, off_tickets, off_lookback, off_block_sums,
+        off_flags, off_big_list, bytes;
 };
 
 BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv, uint64_t capacity);

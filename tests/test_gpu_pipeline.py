@@ -124,15 +124,23 @@ def _bin_case(name):
         u, v, z, r = S.crowded_projected(n, 96, 64, 40.0, 24.0, 7.5, seed=31 if wide else 32, max_radius=6.0,
                                          depths=None if wide else [2.0 + k / 8 for k in range(8)])
         return [H.synthetic_f32_footprints(u, v, z, r, 96, 64, seed=3)], [S.look_at_camera((0, 0, 3), width=96, height=64)]
-    if name == "segment_4096_4097":
-        # footprints inside one tile each: a segment of exactly 4096 entries (largest sorted
-        # in LDS) and one of 4097 (smallest sorted in chunks)
+    if name == "segment_boundaries":
+        # footprints inside one tile each, one segment per view at the size limits of the
+        # segment sort's paths: 64 (rank by comparison in one wave), 65, 512 (largest
+        # sorted by one wave), 513, 4096 (largest radix-sorted in LDS), 4097, 8192 (largest
+        # bucketed in LDS) and 8193
         views, cams = [], []
-        for k, n in enumerate((4096, 4097)):
+        for k, n in enumerate((64, 65, 512, 513, 4096, 4097, 8192, 8193)):
             u, v, z, r = S.crowded_projected(n, 48, 32, 24.0, 8.0, 2.0, seed=40 + k, max_radius=0.5)
             views.append(H.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
         return views, cams
+    if name == "segment_ties_bucketed":
+        # one 3000-entry segment whose depths take 64 values: every bucket of the leading
+        # bits holds one value many times, so positions decide the order inside buckets
+        u, v, z, r = S.crowded_projected(3000, 48, 32, 24.0, 8.0, 2.0, seed=60, max_radius=0.5,
+                                         depths=[1.0 + k / 16 for k in range(64)])
+        return [H.synthetic_f32_footprints(u, v, z, r, 48, 32)], [S.look_at_camera((0, 0, 3), width=48, height=32)]
     if name == "single_tile":
         u, v, z, r = S.random_projected(400, 16, 16, seed=50, max_radius=6.0, depth_ties=True)
         return [H.synthetic_f32_footprints(u, v, z, r, 16, 16)], [S.look_at_camera((0, 0, 3), width=16, height=16)]
@@ -148,7 +156,7 @@ def _bin_case(name):
 
 
 BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled",
-             "crowd_wide_depth", "crowd_narrow_depth", "segment_4096_4097", "single_tile"]
+             "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_ties_bucketed", "single_tile"]
 
 
 @pytest.mark.parametrize("case", BIN_CASES)
