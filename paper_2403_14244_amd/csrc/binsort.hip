@@ -11,8 +11,9 @@
 // Steps (all on the caller's stream, no host synchronisation):
 //   1. fill        zero tile ranges, radix histograms, tickets and look-back words
 //   2. scan        exclusive scan of per-particle tile counts -> emit offsets, total, status
-//   3. emit        one (tile id, particle index, depth bits) per (particle, member tile)
-//   4. histogram   digit counts of every tile-id pass in one read of the ids
+//   3. emit        one (tile id, particle index, depth bits) per (particle, member tile),
+//                  counting the digits of every tile-id pass on the way
+//   4. histogram   sum of the per-workgroup digit counts
 //   5. passes      stable LSD radix passes over the tile id, 8-bit digits, each a single
 //                  kernel with decoupled look-back
 //   6. finalize    tile ranges [start, end)
@@ -162,87 +163,85 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
 // from its offset, tiles in row-major order. A particle writes no more entries than its
 // tile count says (the count may come from elsewhere); missing ones get the sentinel id
 // 0xFFFFFFFF, which sorts last and belongs to no tile.
-__global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ record,
+//
+// A resident grid walks the chunks of 256 particles. Each workgroup also counts the digits
+// of every tile-id pass in LDS and stores its counts as one row of `rows` (added to the
+// row when `accumulate`, for the later launches of a batch); step 4 sums the rows.
+constexpr int kEmitRows = 2048;   // most emit workgroups (rows of digit counts)
+
+__global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, uint32_t n_chunks,
+                                                   const float4* __restrict__ record,
                                                    const uint32_t* __restrict__ tile_count,
                                                    const uint32_t* __restrict__ offsets,
                                                    const float* __restrict__ depth,
                                                    const uint32_t* __restrict__ count_p, uint64_t capacity,
+                                                   const DigitSplit split, int accumulate,
                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                   uint32_t* __restrict__ zbits) {
-    const uint32_t count = *count_p;
-    if ((uint64_t)count > capacity) return;
-    const int vi = view_of_block(pk, blockIdx.x);
-    const ViewDesc& vd = pk.v[vi];
-    const uint32_t li = (blockIdx.x - pk.block_begin[vi]) * blockDim.x + threadIdx.x;
-    if (li >= vd.n) return;
-    const uint32_t i = vd.p_off + li;
-    const uint32_t want = tile_count[i];
-    if (want == 0) return;
-    const uint32_t e0 = offsets[i];
-    if ((uint64_t)e0 + want > count) return;
-    const float4 fp = record[2 * (size_t)i];
-    const float r = record[2 * (size_t)i + 1].w;
-    const uint32_t z = __float_as_uint(depth[i]);
-    int tx0, tx1, ty0, ty1;
-    tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
-    const float r2 = r * r;
-    const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
-    uint32_t j = 0;
-    for (int ty = ty0; ty <= ty1 && j < want; ++ty) {
-        for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
-            if (!tile_member(fp.x, fp.y, r2, tx, ty, w_lim, h_lim)) continue;
-            const uint32_t e = e0 + j++;
-            keys[e] = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
-            vals[e] = i;
-            zbits[e] = z;
-        }
-    }
-    for (; j < want; ++j) {
-        keys[e0 + j] = 0xFFFFFFFFu;
-        vals[e0 + j] = i;
-        zbits[e0 + j] = z;
-    }
-}
-
-// Step 4: digit histograms of all tile-id passes in one sweep over the ids.
-__global__ void __launch_bounds__(256) sort_hist_kernel(const uint32_t* __restrict__ keys,
-                                                        const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                        const DigitSplit split, uint32_t* __restrict__ hist) {
-    const int passes = split.passes;
+                                                   uint32_t* __restrict__ zbits, uint32_t* __restrict__ rows) {
     __shared__ uint32_t s_h[kMaxPasses][kRadix];
-    for (int p = 0; p < kMaxPasses; ++p) s_h[p][threadIdx.x] = 0u;
-    __syncthreads();
+    const uint32_t t = threadIdx.x;
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    // eight loads per thread in flight per sweep step. Neighbouring entries mostly share
-    // their high digits: a wave whose lanes all hold the same digit adds once instead of 64
-    // times to one LDS word.
-    constexpr uint32_t kItems = 8;
-    const uint32_t step = gridDim.x * blockDim.x * kItems;
-    for (uint32_t b0 = blockIdx.x * blockDim.x * kItems; b0 < count; b0 += step) {
-        uint32_t c[kItems];
-#pragma unroll
-        for (uint32_t j = 0; j < kItems; ++j) c[j] = keys[min(b0 + j * blockDim.x + threadIdx.x, count - 1)];
-#pragma unroll
-        for (uint32_t j = 0; j < kItems; ++j) {
-            const bool ok = b0 + j * blockDim.x + threadIdx.x < count;
-            const uint64_t act = ballot64(ok);
-            for (int p = 0; p < passes; ++p) {
-                const uint32_t d = digit_at(c[j], split.shift(p), split.width(p));
-                const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
-                if (ballot64(ok && d != d0) == 0) {
-                    if (lane_id() == 0 && act) atomicAdd(&s_h[p][d0], (uint32_t)__popcll(act));
-                } else if (ok) {
-                    atomicAdd(&s_h[p][d], 1u);
+    for (int p = 0; p < kMaxPasses; ++p) s_h[p][t] = 0u;
+    __syncthreads();
+    for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const int vi = view_of_block(pk, c);
+        const ViewDesc& vd = pk.v[vi];
+        const uint32_t first = vd.p_off + (c - pk.block_begin[vi]) * 256u;
+        const uint32_t last = min(first + 255u, vd.p_off + vd.n - 1u);
+        const uint32_t i = first + t;
+        const uint32_t want = i <= last ? tile_count[i] : 0u;
+        const uint32_t e0 = want ? offsets[i] : 0u;
+        if (want && (uint64_t)e0 + want <= count) {
+            const float4 fp = record[2 * (size_t)i];
+            const float r = record[2 * (size_t)i + 1].w;
+            const uint32_t z = __float_as_uint(depth[i]);
+            int tx0, tx1, ty0, ty1;
+            tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
+            const float r2 = r * r;
+            const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
+            uint32_t j = 0;
+            for (int ty = ty0; ty <= ty1 && j < want; ++ty) {
+                for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
+                    if (!tile_member(fp.x, fp.y, r2, tx, ty, w_lim, h_lim)) continue;
+                    const uint32_t e = e0 + j++;
+                    const uint32_t key = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
+                    keys[e] = key;
+                    vals[e] = i;
+                    zbits[e] = z;
+                    for (int p = 0; p < split.passes; ++p) atomicAdd(&s_h[p][digit_at(key, split.shift(p), split.width(p))], 1u);
                 }
+            }
+            for (; j < want; ++j) {
+                const uint32_t e = e0 + j;
+                keys[e] = 0xFFFFFFFFu;
+                vals[e] = i;
+                zbits[e] = z;
+                for (int p = 0; p < split.passes; ++p)
+                    atomicAdd(&s_h[p][digit_at(0xFFFFFFFFu, split.shift(p), split.width(p))], 1u);
             }
         }
     }
     __syncthreads();
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t h = s_h[p][threadIdx.x];
-        if (h) atomicAdd(&hist[p * kRadix + threadIdx.x], h);
-    }
+    uint32_t* row = rows + (size_t)blockIdx.x * (kMaxPasses * kRadix);
+    for (int p = 0; p < kMaxPasses; ++p) row[p * kRadix + t] = (accumulate ? row[p * kRadix + t] : 0u) + s_h[p][t];
+}
+
+// Step 4: digit histograms of all passes: the sum of the emit rows. Block (x, y) adds rows
+// y * kRowsPerBlock ... of columns x * 256 ... into the zeroed histogram.
+constexpr uint32_t kRowsPerBlock = 16;
+
+__global__ void __launch_bounds__(256) sum_rows_kernel(const uint32_t* __restrict__ rows, uint32_t n_rows,
+                                                       const uint32_t* __restrict__ count_p, uint64_t capacity,
+                                                       uint32_t* __restrict__ hist) {
+    if ((uint64_t)*count_p > capacity) return;
+    const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;   // < kMaxPasses * kRadix
+    const uint32_t r0 = blockIdx.y * kRowsPerBlock;
+    uint32_t acc = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kRowsPerBlock; ++q)
+        acc += (r0 + q < n_rows) ? rows[(size_t)(r0 + q) * (kMaxPasses * kRadix) + col] : 0u;
+    if (acc) atomicAdd(&hist[col], acc);
 }
 
 // Ranks up to ITEMS items per lane within the wave by a digit of `bits` <= 8 bits. Items are taken in
@@ -888,6 +887,7 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.off_block_sums = off; off = align256(off + (size_t)(p.scan_blocks + 1) * 4);
     p.off_flags = off;      off = align256(off + 64);
     p.off_big_list = off;   off = align256(off + (size_t)tiles * 4);
+    p.off_rows = off;       off = align256(off + (size_t)kEmitRows * kMaxPasses * kRadix * 4);
     p.bytes = off;
     return p;
 }
@@ -934,8 +934,14 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     uint32_t* v_emit = odd ? vals_alt : bins->pidx;
     uint32_t* v_other = odd ? bins->pidx : vals_alt;
 
-    // 3. emit, per group of views
+    // 3. emit (per group of views) with the digit counts of the tile passes; 4. their sum
+    static int emit_grid = 0;
+    if (!emit_grid) emit_grid = std::min(kEmitRows, resident_blocks(reinterpret_cast<const void*>(emit_kernel), 256));
+    if (!emit_grid) return -1;
+    uint32_t* rows = reinterpret_cast<uint32_t*>(base + plan.off_rows);
+    const DigitSplit tsplit(0, plan.tile_bits);
     uint32_t p_off = 0, tile_base = 0;
+    int launches = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         ViewPack pk{};
         pk.nv = min(kMaxViews, nv - v0);
@@ -956,19 +962,18 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
             tile_base += (uint32_t)(d.tiles_x * d.tiles_y);
         }
         pk.block_begin[pk.nv] = blocks;
-        if (blocks)
-            hipLaunchKernelGGL(emit_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                               reinterpret_cast<const float4*>(proj->record), proj->tile_count, bins->offsets,
-                               proj->depth, bins->count, plan.capacity, keys_a, v_emit, z_a);
+        if (!blocks) continue;
+        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)emit_grid), dim3(256), 0, stream, pk, blocks,
+                           reinterpret_cast<const float4*>(proj->record), proj->tile_count, bins->offsets,
+                           proj->depth, bins->count, plan.capacity, tsplit, launches > 0 ? 1 : 0, keys_a, v_emit, z_a,
+                           rows);
+        ++launches;
     }
     if (plan.capacity == 0) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+    if (plan.passes && launches)
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(kMaxPasses, (emit_grid + kRowsPerBlock - 1) / kRowsPerBlock),
+                           dim3(kRadix), 0, stream, rows, (uint32_t)emit_grid, bins->count, plan.capacity, hist);
 
-    // 4. histograms
-    if (plan.passes) {
-        const unsigned hist_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 2047) / 2048);
-        hipLaunchKernelGGL(sort_hist_kernel, dim3(hist_blocks), dim3(256), 0, stream, keys_a, bins->count,
-                           plan.capacity, DigitSplit(0, plan.tile_bits), hist);
-    }
     // 5. radix passes over the tile id
     const uint32_t* kin = keys_a;
     const uint32_t* vin = v_emit;
@@ -976,7 +981,6 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     uint32_t* kout = keys_b;
     uint32_t* vout = v_other;
     uint32_t* zout = z_b;
-    const DigitSplit tsplit(0, plan.tile_bits);
     for (int p = 0; p < plan.passes; ++p) {
         hipLaunchKernelGGL(sort_pass_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, zin,
                            kout, vout, zout, bins->count, plan.capacity, tsplit.shift(p), tsplit.width(p),

@@ -140,7 +140,7 @@ class Rasterizer:
         self.device = torch.device(device)
         self.headroom = headroom
         self.capacity = 0
-        self.persistent_fwd = False
+        self.persistent_fwd = True
         self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
 
     def _workspace(self, nbytes):
