@@ -9,13 +9,13 @@
 // LDS, reads its keys sequentially instead of gathering them.
 //
 // Steps (all on the caller's stream, no host synchronisation):
-//   1. fill        zero tile ranges, radix histograms, tickets and look-back words
+//   1. fill        zero tile ranges, radix histograms and counters
 //   2. scan        exclusive scan of per-particle tile counts -> emit offsets, total, status
 //   3. emit        one (tile id, particle index, depth bits) per (particle, member tile),
 //                  counting the digits of every tile-id pass on the way
 //   4. histogram   sum of the per-workgroup digit counts
-//   5. passes      stable LSD radix passes over the tile id, 8-bit digits, each a single
-//                  kernel with decoupled look-back
+//   5. passes      stable LSD radix passes over the tile id, digits of up to 9 bits, each
+//                  as count / scan / scatter kernels
 //   6. finalize    tile ranges [start, end)
 //   7. segments    stable sort of each tile's segment on the depth bits (and the 64-bit
 //                  (tile, depth) keys, when the caller asks for them): one wave per short
@@ -33,24 +33,23 @@ constexpr int kScanBlock = kScanThreads * kScanItems;   // particles per scan bl
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;    // entries per sort workgroup
-constexpr int kRadixBits = 8;
+constexpr int kRadixBits = 8;                 // digits of the per-tile depth sorts
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kTileRadixBits = 9;             // digits of the global tile-id passes
+constexpr int kTileRadix = 1 << kTileRadixBits;
 constexpr int kMaxPasses = 4;                             // tile ids have at most 32 bits
 constexpr int kSegItems = 16;
 constexpr uint32_t kSegMax = kSortThreads * kSegItems;   // longest segment sorted in LDS
-constexpr uint32_t kLbAggregate = 1u << 30;              // look-back word: tile's own count
-constexpr uint32_t kLbInclusive = 2u << 30;              // look-back word: prefix through tile
-constexpr uint32_t kLbValue = (1u << 30) - 1u;
-constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kLbWindow = 8;                              // look-back words read per round trip
+constexpr uint32_t kCountLimit = (1u << 30) - 1u;       // entries per batch must stay below
 
-// Splits the key bits [lo, hi) into the fewest passes of at most 8 bits, widths as equal as
-// possible (ballot ranking costs one ballot per digit bit, so no pass ranks unused bits).
+// Splits the key bits [lo, hi) into the fewest passes of at most `maxw` bits, widths as
+// equal as possible (ballot ranking costs one ballot per digit bit, so no pass ranks unused
+// bits).
 struct DigitSplit {
     int passes, base, extra, lo;
-    __host__ __device__ DigitSplit(int lo_, int hi_) : lo(lo_) {
+    __host__ __device__ DigitSplit(int lo_, int hi_, int maxw = kRadixBits) : lo(lo_) {
         const int span = hi_ > lo_ ? hi_ - lo_ : 0;
-        passes = (span + kRadixBits - 1) / kRadixBits;
+        passes = (span + maxw - 1) / maxw;
         base = passes ? span / passes : 0;
         extra = passes ? span % passes : 0;
     }
@@ -129,7 +128,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_top_kernel(uint32_t* __rest
         carry += total;
     }
     if (threadIdx.x == 0) {
-        const bool fits = carry <= capacity && carry < (uint64_t)kLbValue;
+        const bool fits = carry <= capacity && carry < (uint64_t)kCountLimit;
         *count = (uint32_t)(carry > 0xFFFFFFFFull ? 0xFFFFFFFFull : carry);
         *status = fits ? kStatusOk : kStatusCapacity;
     }
@@ -178,11 +177,14 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, uint32_t n
                                                    const DigitSplit split, int accumulate,
                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                    uint32_t* __restrict__ zbits, uint32_t* __restrict__ rows) {
-    __shared__ uint32_t s_h[kMaxPasses][kRadix];
+    __shared__ uint32_t s_h[kMaxPasses][kTileRadix];
     const uint32_t t = threadIdx.x;
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    for (int p = 0; p < kMaxPasses; ++p) s_h[p][t] = 0u;
+    for (int p = 0; p < kMaxPasses; ++p) {
+        s_h[p][t] = 0u;
+        s_h[p][t + 256] = 0u;
+    }
     __syncthreads();
     for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const int vi = view_of_block(pk, c);
@@ -223,8 +225,12 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, uint32_t n
         }
     }
     __syncthreads();
-    uint32_t* row = rows + (size_t)blockIdx.x * (kMaxPasses * kRadix);
-    for (int p = 0; p < kMaxPasses; ++p) row[p * kRadix + t] = (accumulate ? row[p * kRadix + t] : 0u) + s_h[p][t];
+    uint32_t* row = rows + (size_t)blockIdx.x * (kMaxPasses * kTileRadix);
+    for (int p = 0; p < kMaxPasses; ++p)
+        for (int h = 0; h < 2; ++h) {
+            const int d = t + 256 * h;
+            row[p * kTileRadix + d] = (accumulate ? row[p * kTileRadix + d] : 0u) + s_h[p][d];
+        }
 }
 
 // Step 4: digit histograms of all passes: the sum of the emit rows. Block (x, y) adds rows
@@ -235,23 +241,23 @@ __global__ void __launch_bounds__(256) sum_rows_kernel(const uint32_t* __restric
                                                        const uint32_t* __restrict__ count_p, uint64_t capacity,
                                                        uint32_t* __restrict__ hist) {
     if ((uint64_t)*count_p > capacity) return;
-    const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;   // < kMaxPasses * kRadix
+    const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;   // < kMaxPasses * kTileRadix
     const uint32_t r0 = blockIdx.y * kRowsPerBlock;
     uint32_t acc = 0;
 #pragma unroll
     for (uint32_t q = 0; q < kRowsPerBlock; ++q)
-        acc += (r0 + q < n_rows) ? rows[(size_t)(r0 + q) * (kMaxPasses * kRadix) + col] : 0u;
+        acc += (r0 + q < n_rows) ? rows[(size_t)(r0 + q) * (kMaxPasses * kTileRadix) + col] : 0u;
     if (acc) atomicAdd(&hist[col], acc);
 }
 
-// Ranks up to ITEMS items per lane within the wave by a digit of `bits` <= 8 bits. Items are taken in
+// Ranks up to ITEMS items per lane within the wave by a digit of `bits` <= MAXB bits. Items are taken in
 // rounds (item i of every lane in round i, lanes in order), so ranks follow the order
 // (round, lane). Lanes with equal digits are matched bit by bit with ballots; an item's
 // rank is the wave's count of its digit in earlier rounds plus the matching lanes below
 // it. `cnt` holds the wave's 256 digit counters (zero on entry) and ends with the wave's
 // digit totals. Bit i of `valid` marks item i as present; `items` (uniform) bounds the
 // rounds.
-template <int ITEMS>
+template <int ITEMS, int MAXB = kRadixBits>
 __device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift, int bits, uint32_t valid,
                                           int items, uint32_t* __restrict__ cnt, uint32_t (&rk)[ITEMS]) {
 #pragma unroll
@@ -262,7 +268,7 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift,
             const uint64_t okm = ballot64(ok);
             uint32_t m_lo = (uint32_t)okm, m_hi = (uint32_t)(okm >> 32);
 #pragma unroll
-            for (int b = 0; b < kRadixBits; ++b) {
+            for (int b = 0; b < MAXB; ++b) {
                 if (b < bits) {
                     // keep the lanes whose bit b equals this lane's: m &= ~(ballot ^ sign(bit))
                     // (one three-input bitwise instruction per half)
@@ -281,34 +287,97 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift,
     }
 }
 
-// Step 5: one stable LSD pass over the tile ids (digit at `shift`). Each workgroup takes
-// the next 4096-entry tile in ticket order, ranks its entries per digit within each wave,
-// publishes its digit counts and resolves its global offsets by looking back over earlier
-// tiles' words, then reorders the tile in LDS so the scatter writes contiguous runs per
-// digit.
-__global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, const uint32_t* __restrict__ zin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t* __restrict__ zout,
-    const uint32_t* __restrict__ count_p, uint64_t capacity, int shift, int bits,
-    const uint32_t* __restrict__ hist, uint32_t* __restrict__ lookback, uint32_t* __restrict__ ticket,
-    int32_t* __restrict__ status) {
-    __shared__ uint32_t s_buf[kSortTile];   // tile reordered by digit: keys, values, depth bits
-    __shared__ uint8_t s_dig[kSortTile];     // digit at each reordered position
-    __shared__ uint32_t s_wcnt[4][kRadix];
-    __shared__ uint32_t s_local[kRadix];
-    __shared__ uint32_t s_base[kRadix];
-    __shared__ uint32_t s_tmp[4];
-    __shared__ uint32_t s_ticket;
+// Step 5: stable LSD passes over the tile ids (digit of `bits` <= 9 bits at `shift`), each
+// in three kernels over 4096-entry sort tiles, with no waiting between workgroups:
+//   5a  count     each sort tile's digit counts, stored digit-major
+//   5b  scan      per digit, the exclusive prefix over the sort tiles
+//   5c  scatter   each sort tile ranks its entries per digit within each wave (ballots),
+//                 places them at digit base + earlier tiles' count + rank, reorders in LDS
+//                 so that the stores are contiguous runs per digit
+__global__ void __launch_bounds__(kSortThreads) tile_count_kernel(const uint32_t* __restrict__ kin,
+                                                                  const uint32_t* __restrict__ count_p,
+                                                                  uint64_t capacity, int shift, int bits,
+                                                                  uint32_t* __restrict__ tcount, uint32_t stride) {
+    __shared__ uint32_t s_h[kTileRadix];
+    const uint32_t count = *count_p;
+    if ((uint64_t)count > capacity) return;
+    const uint32_t tile = blockIdx.x, t = threadIdx.x;
+    if (tile * kSortTile >= count) return;
+    s_h[t] = 0u;
+    s_h[t + 256] = 0u;
+    __syncthreads();
+    uint32_t k[kSortItems];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) k[i] = kin[min(tile * kSortTile + i * kSortThreads + t, count - 1)];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        const bool ok = tile * kSortTile + i * kSortThreads + t < count;
+        const uint32_t d = digit_at(k[i], shift, bits);
+        // neighbouring entries mostly share a digit: then one add per wave
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const uint64_t act = ballot64(ok);
+        if (ballot64(ok && d != d0) == 0) {
+            if (lane_id() == 0 && act) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
+        } else if (ok) {
+            atomicAdd(&s_h[d], 1u);
+        }
+    }
+    __syncthreads();
+    tcount[(size_t)t * stride + tile] = s_h[t];
+    tcount[(size_t)(t + 256) * stride + tile] = s_h[t + 256];
+}
 
+__global__ void __launch_bounds__(256) tile_scan_kernel(uint32_t* __restrict__ tcount, uint32_t stride,
+                                                        const uint32_t* __restrict__ count_p, uint64_t capacity) {
+    __shared__ uint32_t s_tmp[4];
+    constexpr uint32_t kItems = 16;   // consecutive sort tiles per thread and chunk
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     const uint32_t ntiles = (count + kSortTile - 1) / kSortTile;
+    uint32_t* row = tcount + (size_t)blockIdx.x * stride;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < ntiles; c0 += 256 * kItems) {
+        const uint32_t i0 = c0 + threadIdx.x * kItems;
+        uint32_t x[kItems], sum = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kItems; ++q) {
+            x[q] = i0 + q < ntiles ? row[i0 + q] : 0u;
+            sum += x[q];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_exclusive_scan(sum, s_tmp, total);
+#pragma unroll
+        for (uint32_t q = 0; q < kItems; ++q) {
+            if (i0 + q < ntiles) row[i0 + q] = run;
+            run += x[q];
+        }
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, const uint32_t* __restrict__ zin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t* __restrict__ zout,
+    const uint32_t* __restrict__ count_p, uint64_t capacity, int shift, int bits,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ tcount, uint32_t stride) {
+    __shared__ uint32_t s_buf[kSortTile];   // tile reordered by digit: keys, values, depth bits
+    __shared__ uint16_t s_dig[kSortTile];    // digit at each reordered position
+    __shared__ uint32_t s_wcnt[4][kTileRadix];
+    __shared__ uint32_t s_local[kTileRadix];
+    __shared__ uint32_t s_base[kTileRadix];
+    __shared__ uint32_t s_tmp[4];
+
+    const uint32_t count = *count_p;
+    if ((uint64_t)count > capacity) return;
+    const uint32_t tile = blockIdx.x;
+    if (tile * kSortTile >= count) return;
     const uint32_t t = threadIdx.x, w = t >> 6, lane = t & 63;
-    if (t == 0) s_ticket = atomicAdd(ticket, 1u);
-    for (int k = 0; k < 4; ++k) s_wcnt[k][t] = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        s_wcnt[k][t] = 0u;
+        s_wcnt[k][t + 256] = 0u;
+    }
     __syncthreads();
-    const uint32_t tile = s_ticket;
-    if (tile >= ntiles) return;
 
     // load: wave w owns entries [tile*4096 + w*1024, +1024), item i of lane l at i*64 + l
     const uint32_t wbase = tile * kSortTile + w * (kSortTile / 4);
@@ -321,8 +390,11 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
         valid |= (uint32_t)ok << i;
         k[i] = ok ? kin[idx] : 0u;
     }
-    wave_rank<kSortItems>(k, shift, bits, valid, kSortItems, s_wcnt[w], rk);
-    // values are needed only after the keys are placed: their loads overlap the look-back
+    // this tile's start of digits 2t, 2t+1: digit base over all entries + earlier tiles' count
+    const uint32_t h0 = hist[2 * t], h1 = hist[2 * t + 1];
+    const uint32_t e0 = tcount[(size_t)(2 * t) * stride + tile], e1 = tcount[(size_t)(2 * t + 1) * stride + tile];
+    wave_rank<kSortItems, kTileRadixBits>(k, shift, bits, valid, kSortItems, s_wcnt[w], rk);
+    // values are needed only after the keys are placed: their loads overlap the scans
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t idx = wbase + i * kWave + lane;
@@ -330,63 +402,24 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
     }
     __syncthreads();
 
-    // thread t owns digit t: wave prefixes, tile total, look-back
-    const uint32_t c0 = s_wcnt[0][t], c1 = s_wcnt[1][t], c2 = s_wcnt[2][t], c3 = s_wcnt[3][t];
-    const uint32_t mine = c0 + c1 + c2 + c3;
-    s_wcnt[0][t] = 0u;
-    s_wcnt[1][t] = c0;
-    s_wcnt[2][t] = c0 + c1;
-    s_wcnt[3][t] = c0 + c1 + c2;
-    uint32_t* lb = lookback;  // this pass's region
-    __hip_atomic_store(&lb[(size_t)tile * kRadix + t], (tile == 0 ? kLbInclusive : kLbAggregate) | mine,
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t excl = 0;
-    if (tile > 0) {
-        // look back over up to kLbWindow predecessors per round trip: every published
-        // word is consumed in order until an inclusive one; an unpublished word ends the
-        // round and is polled again
-        int32_t j = (int32_t)tile - 1;
-        uint32_t spins = 0;
-        for (;;) {
-            uint32_t word[kLbWindow];
+    uint32_t mine[2];
 #pragma unroll
-            for (int q = 0; q < kLbWindow; ++q)
-                word[q] = (j - q >= 0) ? __hip_atomic_load(&lb[(size_t)(j - q) * kRadix + t], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : kLbInclusive;
-            bool done = false, stalled = false;
-            int used = 0;
-#pragma unroll
-            for (int q = 0; q < kLbWindow; ++q) {
-                const uint32_t flag = word[q] & ~kLbValue;
-                if (!done && !stalled) {
-                    if (flag == 0u) {
-                        stalled = true;
-                    } else {
-                        excl += word[q] & kLbValue;
-                        ++used;
-                        done = flag == kLbInclusive;
-                    }
-                }
-            }
-            if (done) break;
-            j -= used;
-            if (used == 0) {
-                if (++spins > kSpinLimit) {
-                    *status = kStatusDevice;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __hip_atomic_store(&lb[(size_t)tile * kRadix + t], kLbInclusive | (excl + mine), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t d = 2 * t + h;
+        const uint32_t c0 = s_wcnt[0][d], c1 = s_wcnt[1][d], c2 = s_wcnt[2][d], c3 = s_wcnt[3][d];
+        mine[h] = c0 + c1 + c2 + c3;
+        s_wcnt[0][d] = 0u;
+        s_wcnt[1][d] = c0;
+        s_wcnt[2][d] = c0 + c1;
+        s_wcnt[3][d] = c0 + c1 + c2;
     }
     uint32_t tot;
-    const uint32_t gbase = block_exclusive_scan(hist[t], s_tmp, tot);
-    const uint32_t lbase = block_exclusive_scan(mine, s_tmp, tot);
-    s_base[t] = gbase + excl;
-    s_local[t] = lbase;
+    const uint32_t gbase = block_exclusive_scan(h0 + h1, s_tmp, tot);
+    const uint32_t lbase = block_exclusive_scan(mine[0] + mine[1], s_tmp, tot);
+    s_base[2 * t] = gbase + e0;
+    s_base[2 * t + 1] = gbase + h0 + e1;
+    s_local[2 * t] = lbase;
+    s_local[2 * t + 1] = lbase + mine[0];
     __syncthreads();
 
     // reorder in LDS by digit (stable), then write runs: keys first, then the values and
@@ -409,7 +442,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_pass_kernel(
         if (j < n_here) {
             const uint32_t key = s_buf[j];
             const uint32_t dd = digit_at(key, shift, bits);
-            s_dig[j] = (uint8_t)dd;
+            s_dig[j] = (uint16_t)dd;
             const uint32_t dst = s_base[dd] + (j - s_local[dd]);
             if (dst < count) kout[dst] = key;
         }
@@ -870,7 +903,7 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     // after every real tile id
     int tile_bits = 0;
     while (tile_bits < 32 && (1ull << tile_bits) <= tiles) ++tile_bits;
-    p.passes = DigitSplit(0, tile_bits).passes;
+    p.passes = DigitSplit(0, tile_bits, kTileRadixBits).passes;
     p.tile_bits = tile_bits;
     p.sort_tiles = (uint32_t)((capacity + kSortTile - 1) / kSortTile);
     p.scan_blocks = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
@@ -880,14 +913,14 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.off_vals_alt = off;   off = align256(off + capacity * 4);
     p.off_z_a = off;        off = align256(off + capacity * 4);
     p.off_z_b = off;        off = align256(off + capacity * 4);
-    // zero-initialised region: histograms, tickets, look-back words (contiguous)
-    p.off_hist = off;       off += (size_t)kMaxPasses * kRadix * 4;
-    p.off_tickets = off;    off += (size_t)(kMaxPasses + 1) * 4;   // + the long-segment count
-    p.off_lookback = off;   off = align256(off + (size_t)p.passes * p.sort_tiles * kRadix * 4);
+    // zero-initialised region: histograms and the long-segment count (contiguous)
+    p.off_hist = off;       off += (size_t)kMaxPasses * kTileRadix * 4;
+    p.off_counters = off;   off = align256(off + 4 * 4);
     p.off_block_sums = off; off = align256(off + (size_t)(p.scan_blocks + 1) * 4);
     p.off_flags = off;      off = align256(off + 64);
     p.off_big_list = off;   off = align256(off + (size_t)tiles * 4);
-    p.off_rows = off;       off = align256(off + (size_t)kEmitRows * kMaxPasses * kRadix * 4);
+    p.off_tcount = off;     off = align256(off + (size_t)p.sort_tiles * kTileRadix * 4);
+    p.off_rows = off;       off = align256(off + (size_t)kEmitRows * kMaxPasses * kTileRadix * 4);
     p.bytes = off;
     return p;
 }
@@ -901,8 +934,8 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     uint32_t* z_a = reinterpret_cast<uint32_t*>(base + plan.off_z_a);
     uint32_t* z_b = reinterpret_cast<uint32_t*>(base + plan.off_z_b);
     uint32_t* hist = reinterpret_cast<uint32_t*>(base + plan.off_hist);
-    uint32_t* tickets = reinterpret_cast<uint32_t*>(base + plan.off_tickets);
-    uint32_t* lookback = reinterpret_cast<uint32_t*>(base + plan.off_lookback);
+    uint32_t* counters = reinterpret_cast<uint32_t*>(base + plan.off_counters);
+    uint32_t* tcount = reinterpret_cast<uint32_t*>(base + plan.off_tcount);
     uint32_t* block_sums = reinterpret_cast<uint32_t*>(base + plan.off_block_sums);
 
     // 1. zero ranges and the sort's bookkeeping
@@ -939,7 +972,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     if (!emit_grid) emit_grid = std::min(kEmitRows, resident_blocks(reinterpret_cast<const void*>(emit_kernel), 256));
     if (!emit_grid) return -1;
     uint32_t* rows = reinterpret_cast<uint32_t*>(base + plan.off_rows);
-    const DigitSplit tsplit(0, plan.tile_bits);
+    const DigitSplit tsplit(0, plan.tile_bits, kTileRadixBits);
     uint32_t p_off = 0, tile_base = 0;
     int launches = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
@@ -971,8 +1004,8 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     }
     if (plan.capacity == 0) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
     if (plan.passes && launches)
-        hipLaunchKernelGGL(sum_rows_kernel, dim3(kMaxPasses, (emit_grid + kRowsPerBlock - 1) / kRowsPerBlock),
-                           dim3(kRadix), 0, stream, rows, (uint32_t)emit_grid, bins->count, plan.capacity, hist);
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(kMaxPasses * kTileRadix / 256, (emit_grid + kRowsPerBlock - 1) / kRowsPerBlock),
+                           dim3(256), 0, stream, rows, (uint32_t)emit_grid, bins->count, plan.capacity, hist);
 
     // 5. radix passes over the tile id
     const uint32_t* kin = keys_a;
@@ -982,10 +1015,14 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     uint32_t* vout = v_other;
     uint32_t* zout = z_b;
     for (int p = 0; p < plan.passes; ++p) {
-        hipLaunchKernelGGL(sort_pass_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, zin,
-                           kout, vout, zout, bins->count, plan.capacity, tsplit.shift(p), tsplit.width(p),
-                           hist + p * kRadix,
-                           lookback + (size_t)p * plan.sort_tiles * kRadix, tickets + p, bins->status);
+        const int sh = tsplit.shift(p), wd = tsplit.width(p);
+        hipLaunchKernelGGL(tile_count_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, bins->count,
+                           plan.capacity, sh, wd, tcount, plan.sort_tiles);
+        hipLaunchKernelGGL(tile_scan_kernel, dim3(kTileRadix), dim3(256), 0, stream, tcount, plan.sort_tiles,
+                           bins->count, plan.capacity);
+        hipLaunchKernelGGL(sort_scatter_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, zin,
+                           kout, vout, zout, bins->count, plan.capacity, sh, wd, hist + p * kTileRadix, tcount,
+                           plan.sort_tiles);
         const uint32_t* tk = kin;
         const uint32_t* tv = vin;
         const uint32_t* tz = zin;
@@ -1006,7 +1043,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         static int big_grid = 0;
         if (!big_grid) big_grid = resident_blocks(reinterpret_cast<const void*>(segment_sort_big_kernel), kSortThreads);
         if (!big_grid) return -1;
-        uint32_t* big_count = tickets + kMaxPasses;
+        uint32_t* big_count = counters;
         uint32_t* big_list = reinterpret_cast<uint32_t*>(base + plan.off_big_list);
         hipLaunchKernelGGL(segment_sort_small_kernel, dim3((plan.tiles_total + 3) / 4), dim3(kSortThreads), 0, stream,
                            bins->ranges, plan.tiles_total, zin, bins->pidx, bins->keys, bins->count,
