@@ -75,8 +75,12 @@ __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& 
     n_last[vd.pix_off + pix] = last;
 }
 
+// Register budget of the one-workgroup-per-tile compositing kernel: six waves per SIMD (at
+// most 80 VGPRs, no spills) hide the staging gathers better than the default of five.
+constexpr int kFwdWavesPerSimd = 6;
+
 // One workgroup per tile, tiles in XCD-banded order.
-__global__ void __launch_bounds__(256) composite_fwd_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWavesPerSimd))) composite_fwd_kernel(
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
     float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
