@@ -255,8 +255,11 @@ class Rasterizer:
     def render(self, scenes, cams, bg=(0.0, 0.0, 0.0), check=True):
         """Full forward pass. Returns (list of [3, H, W] images, state for backward).
 
-        Everything is queued before the one host synchronisation that `check` needs (the
-        capacity status); on overflow the capacity grows and the pass is redone. With
+        `check=True`: everything is queued before the one host synchronisation that the
+        capacity status needs; on overflow the capacity grows and the pass is redone.
+        `check="deferred"`: once a capacity is known, nothing waits: the status is copied
+        to pinned host memory behind the launches and `verify(state)` reads it later (the
+        first call, with no capacity yet, still checks synchronously). With
         `persistent_fwd` set, compositing uses the longest-list-first persistent kernel
         (same images bitwise)."""
         fp = self.project(scenes, cams)
@@ -264,7 +267,15 @@ class Rasterizer:
         fwd = self.render_fwd_persistent if self.persistent_fwd else self.render_fwd
         bins = self.bin_sort(fp, npv, cams, check=False)
         out = fwd(fp, npv, bins, cams, bg)
-        if check:
+        pending = None
+        if check == "deferred" and self.capacity > 0:
+            pending = torch.empty(2, dtype=torch.int32, pin_memory=True)
+            pending[0:1].copy_(bins.status, non_blocking=True)
+            pending[1:2].copy_(bins.count, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream())
+            pending = (pending, ev)
+        elif check:
             st = int(bins.status.item())
             if st == A.ISOGS_ERR_CAPACITY:
                 self.capacity = int(bins.n_entries() * self.headroom) + 4096
@@ -273,7 +284,25 @@ class Rasterizer:
             elif st != A.ISOGS_OK:
                 raise A.IsoGSError(st, "bin_sort failed on the device")
         image, T, n_last = out
-        return split_images(image, cams), dict(fp=fp, bins=bins, image=image, T=T, n_last=n_last, npv=npv)
+        return split_images(image, cams), dict(fp=fp, bins=bins, image=image, T=T, n_last=n_last, npv=npv,
+                                               pending=pending)
+
+    def verify(self, state):
+        """Reads a deferred status (waiting for the forward launches if needed). On a
+        capacity overflow the capacity grows for the next call and IsoGSError is raised:
+        that pass's outputs are not valid."""
+        if state.get("pending") is None:
+            return
+        host, ev = state["pending"]
+        ev.synchronize()
+        st, count = int(host[0]), int(host[1])
+        state["pending"] = None
+        if st == A.ISOGS_ERR_CAPACITY:
+            self.capacity = int(count * self.headroom) + 4096
+            raise A.IsoGSError(st, f"entry capacity overflowed in the forward pass ({count} entries); "
+                                   f"capacity grown to {self.capacity}, repeat the pass")
+        if st != A.ISOGS_OK:
+            raise A.IsoGSError(st, "bin_sort failed on the device")
 
 
 def split_images(flat, cams):
@@ -297,7 +326,7 @@ class IsoGSRender(torch.autograd.Function):
         scene = GaussianScene(pos.contiguous(), scale.contiguous(), opacity.contiguous(), color.contiguous(),
                               int(sh_degree))
         scenes = [scene] * len(cams)
-        images, st = rasterizer.render(scenes, cams, bg, check=True)
+        images, st = rasterizer.render(scenes, cams, bg, check="deferred")
         ctx.rasterizer = rasterizer
         ctx.cams = cams
         ctx.bg = bg
@@ -308,6 +337,8 @@ class IsoGSRender(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         st = ctx.st
+        # the forward's capacity status, read here so that the forward never waits
+        ctx.rasterizer.verify(st)
         scenes = [ctx.scene] * len(ctx.cams)
         g = ctx.rasterizer.render_bwd(scenes, ctx.cams, st["fp"], st["bins"], ctx.bg,
                                       grad_out.contiguous().reshape(-1), st["T"], st["n_last"])[0]

@@ -345,3 +345,32 @@ def test_autograd_function_and_determinism(P, torch_cuda):
     ref = O.scene_grads(sc, cams, dCs)
     for name, gg in zip(("pos", "scale", "opacity", "color"), outs[0][1]):
         _grad_check(gg, ref[name], name, rel=5e-3, floor=1e-3)
+
+
+def test_autograd_deferred_capacity_check(P, torch_cuda):
+    """The autograd forward does not wait for the capacity status once a capacity is known;
+    an overflow is reported by the backward (IsoGSError, capacity grown) and the repeated
+    iteration matches a rasterizer that never overflowed."""
+    torch = torch_cuda
+    sc = _grad_scene(2, n=300, seed=5)
+    cams = [S.look_at_camera((0.1, 0.1, 3.0), width=48, height=40)]
+    note("autograd deferred capacity check")
+    target = torch.rand(1, 3, 40, 48, device="cuda")
+
+    def step(R):
+        params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+                  for a in (sc.pos, sc.scale, sc.opacity, sc.color)]
+        img = P.IsoGSRender.apply(*params, sc.sh_degree, cams, (0.0, 0.0, 0.0), R)
+        (img - target).abs().mean().backward()
+        return img.detach().cpu().numpy(), [p.grad.cpu().numpy() for p in params]
+
+    good = step(P.Rasterizer())
+    R = P.Rasterizer()
+    R.capacity = 10                      # known but far too small: the next forward overflows
+    with pytest.raises(P.IsoGSError):
+        step(R)
+    assert R.capacity > 10
+    again = step(R)
+    np.testing.assert_array_equal(again[0], good[0])
+    for a, b in zip(again[1], good[1]):
+        np.testing.assert_array_equal(a, b)
