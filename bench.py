@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--views", type=int, default=100)
     ap.add_argument("--batch-views", type=int, default=10)
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=4,
                     help="HIP streams the forward batches alternate over (sort of one batch overlaps "
                          "compositing of another)")
     ap.add_argument("--gaussians", type=int, default=1_000_000)

@@ -38,8 +38,10 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kTileRadixBits = 9;             // digits of the global tile-id passes
 constexpr int kTileRadix = 1 << kTileRadixBits;
 constexpr int kMaxPasses = 4;                             // tile ids have at most 32 bits
-constexpr int kSegItems = 16;
-constexpr uint32_t kSegMax = kSortThreads * kSegItems;   // longest segment sorted in LDS
+constexpr int kBigThreads = 512;                          // workgroup of the long-segment sort
+constexpr int kBigWaves = kBigThreads / kWave;
+constexpr int kBigItems = 8;
+constexpr uint32_t kSegMax = kBigThreads * kBigItems;    // longest segment sorted in LDS
 constexpr uint32_t kCountLimit = (1u << 30) - 1u;       // entries per batch must stay below
 
 // Splits the key bits [lo, hi) into the fewest passes of at most `maxw` bits, widths as
@@ -500,7 +502,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(const uint32_t* __restric
     }
 }
 
-// OR and AND of x over the workgroup (s_tmp: 8 words). Contains __syncthreads.
+// OR and AND of x over the workgroup (s_tmp: 2 * kBigWaves words). Contains __syncthreads.
 __device__ __forceinline__ void block_or_and(uint32_t x_or, uint32_t x_and, uint32_t* s_tmp, uint32_t& r_or,
                                              uint32_t& r_and) {
 #pragma unroll
@@ -511,30 +513,42 @@ __device__ __forceinline__ void block_or_and(uint32_t x_or, uint32_t x_and, uint
     const uint32_t w = threadIdx.x >> 6;
     if (lane_id() == 0) {
         s_tmp[w] = x_or;
-        s_tmp[4 + w] = x_and;
+        s_tmp[kBigWaves + w] = x_and;
     }
     __syncthreads();
-    r_or = s_tmp[0] | s_tmp[1] | s_tmp[2] | s_tmp[3];
-    r_and = s_tmp[4] & s_tmp[5] & s_tmp[6] & s_tmp[7];
+    r_or = 0u;
+    r_and = 0xFFFFFFFFu;
+#pragma unroll
+    for (int j = 0; j < kBigWaves; ++j) {
+        r_or |= s_tmp[j];
+        r_and &= s_tmp[kBigWaves + j];
+    }
     __syncthreads();
 }
 
 struct SegShared {
     uint32_t buf[kSegMax];        // segment reordered by digit: keys, then values
-    uint32_t wcnt[4][kRadix];
+    uint32_t wcnt[kBigWaves][kRadix];
     uint32_t local[kRadix];       // LDS path: digit bases; global path: digit histogram
     uint32_t run[kRadix];         // global path: next output position of each digit
-    uint32_t tmp[8];
+    uint32_t tmp[2 * kBigWaves];
 };
 
-// Thread t's digit: wave prefixes written back into wcnt, returns the total over waves.
-__device__ __forceinline__ uint32_t digit_wave_prefix(SegShared& sh, uint32_t t) {
-    const uint32_t c0 = sh.wcnt[0][t], c1 = sh.wcnt[1][t], c2 = sh.wcnt[2][t], c3 = sh.wcnt[3][t];
-    sh.wcnt[0][t] = 0u;
-    sh.wcnt[1][t] = c0;
-    sh.wcnt[2][t] = c0 + c1;
-    sh.wcnt[3][t] = c0 + c1 + c2;
-    return c0 + c1 + c2 + c3;
+__device__ __forceinline__ void zero_wcnt(SegShared& sh, uint32_t t) {
+#pragma unroll
+    for (int q = 0; q < kBigWaves * kRadix / kBigThreads; ++q) (&sh.wcnt[0][0])[q * kBigThreads + t] = 0u;
+}
+
+// Digit d (< kRadix): wave prefixes written back into wcnt, returns the total over waves.
+__device__ __forceinline__ uint32_t digit_wave_prefix(SegShared& sh, uint32_t d) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < kBigWaves; ++q) {
+        const uint32_t c = sh.wcnt[q][d];
+        sh.wcnt[q][d] = run;
+        run += c;
+    }
+    return run;
 }
 
 // Segment of n <= kSegMax entries sorted in LDS: items stay in registers between passes,
@@ -544,22 +558,22 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
                                                  const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
                                                  uint64_t* __restrict__ keys64) {
     const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
-    const int items = (int)((n + kSortThreads - 1) / kSortThreads);
+    const int items = (int)((n + kBigThreads - 1) / kBigThreads);
     const uint32_t wbase = w * kWave * (uint32_t)items;   // wave w owns positions [wbase, wbase + 64 items)
-    uint32_t k[kSegItems], v[kSegItems], rk[kSegItems];
+    uint32_t k[kBigItems], v[kBigItems], rk[kBigItems];
     uint32_t valid = 0;
     uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
     // loads clamped into the segment rather than predicated, so that all of them are in
     // flight at once
 #pragma unroll
-    for (int i = 0; i < kSegItems; ++i) {
+    for (int i = 0; i < kBigItems; ++i) {
         const uint32_t p = wbase + (uint32_t)i * kWave + l;
         valid |= (uint32_t)(i < items && p < n) << i;
         v[i] = pidx[start + min(p, n - 1)];
         k[i] = zs[start + min(p, n - 1)];
     }
 #pragma unroll
-    for (int i = 0; i < kSegItems; ++i) {
+    for (int i = 0; i < kBigItems; ++i) {
         const bool ok = (valid >> i) & 1u;
         k_or |= ok ? k[i] : 0u;
         k_and &= ok ? k[i] : 0xFFFFFFFFu;
@@ -574,18 +588,18 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
     const DigitSplit split(lo, hi);
     for (int pass = 0; pass < split.passes; ++pass) {
         const int shift = split.shift(pass), bits = split.width(pass);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sh.wcnt[q][t] = 0u;
+        zero_wcnt(sh, t);
         __syncthreads();
-        wave_rank<kSegItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
+        wave_rank<kBigItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
         __syncthreads();
-        const uint32_t tot = digit_wave_prefix(sh, t);
+        const uint32_t tot = t < kRadix ? digit_wave_prefix(sh, t) : 0u;
         uint32_t all;
-        sh.local[t] = block_exclusive_scan(tot, sh.tmp, all);
+        const uint32_t lb = block_exclusive_scan<kBigWaves>(tot, sh.tmp, all);
+        if (t < kRadix) sh.local[t] = lb;
         __syncthreads();
-        uint32_t pos[kSegItems];
+        uint32_t pos[kBigItems];
 #pragma unroll
-        for (int i = 0; i < kSegItems; ++i) {
+        for (int i = 0; i < kBigItems; ++i) {
             if ((valid >> i) & 1u) {
                 const uint32_t d = digit_at(k[i], shift, bits);
                 pos[i] = sh.local[d] + sh.wcnt[w][d] + rk[i];
@@ -594,20 +608,20 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kSegItems; ++i)
+        for (int i = 0; i < kBigItems; ++i)
             if ((valid >> i) & 1u) k[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kSegItems; ++i)
+        for (int i = 0; i < kBigItems; ++i)
             if ((valid >> i) & 1u) sh.buf[pos[i]] = v[i];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kSegItems; ++i)
+        for (int i = 0; i < kBigItems; ++i)
             if ((valid >> i) & 1u) v[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
     }
     // every read of the segment happened before block_or_and's barrier: in place is safe
 #pragma unroll
-    for (int i = 0; i < kSegItems; ++i) {
+    for (int i = 0; i < kBigItems; ++i) {
         if (!((valid >> i) & 1u)) continue;
         const uint32_t p = wbase + (uint32_t)i * kWave + l;
         pidx[start + p] = v[i];
@@ -618,7 +632,7 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
 // Segment longer than kSegMax, sorted by one workgroup through global scratch. A first
 // sweep copies (depth bits, particle index) to (sk0, sv) and reduces the differing bits;
 // each pass then scatters chunk after chunk straight to its place, counting the next
-// pass's digits on the way. Every sweep issues kSegItems independent loads per thread.
+// pass's digits on the way. Every sweep issues kBigItems independent loads per thread.
 __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile, uint32_t start, uint32_t n,
                                                     const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
                                                     uint64_t* __restrict__ keys64, uint32_t* __restrict__ sk0,
@@ -626,16 +640,16 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
     const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
     uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
     for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
-        uint32_t g[kSegItems], key[kSegItems];
+        uint32_t g[kBigItems], key[kBigItems];
 #pragma unroll
-        for (int i = 0; i < kSegItems; ++i) {
-            const uint32_t pc = min(c0 + (uint32_t)i * kSortThreads + t, n - 1);
+        for (int i = 0; i < kBigItems; ++i) {
+            const uint32_t pc = min(c0 + (uint32_t)i * kBigThreads + t, n - 1);
             g[i] = pidx[start + pc];
             key[i] = zs[start + pc];
         }
 #pragma unroll
-        for (int i = 0; i < kSegItems; ++i) {
-            const uint32_t p = c0 + (uint32_t)i * kSortThreads + t;
+        for (int i = 0; i < kBigItems; ++i) {
+            const uint32_t p = c0 + (uint32_t)i * kBigThreads + t;
             if (p < n) {
                 sk0[start + p] = key[i];
                 sv[start + p] = g[i];
@@ -656,15 +670,15 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
     uint32_t *src_k = sk0, *src_v = sv, *dst_k = sk1, *dst_v = pidx;
     if (passes > 0) {
         // digit histogram of the first pass
-        sh.local[t] = 0u;
+        if (t < kRadix) sh.local[t] = 0u;
         __syncthreads();
         for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
-            uint32_t kk[kSegItems];
+            uint32_t kk[kBigItems];
 #pragma unroll
-            for (int i = 0; i < kSegItems; ++i) kk[i] = src_k[start + min(c0 + (uint32_t)i * kSortThreads + t, n - 1)];
+            for (int i = 0; i < kBigItems; ++i) kk[i] = src_k[start + min(c0 + (uint32_t)i * kBigThreads + t, n - 1)];
 #pragma unroll
-            for (int i = 0; i < kSegItems; ++i)
-                if (c0 + (uint32_t)i * kSortThreads + t < n) atomicAdd(&sh.local[digit_at(kk[i], split.shift(0), split.width(0))], 1u);
+            for (int i = 0; i < kBigItems; ++i)
+                if (c0 + (uint32_t)i * kBigThreads + t < n) atomicAdd(&sh.local[digit_at(kk[i], split.shift(0), split.width(0))], 1u);
         }
         __syncthreads();
     }
@@ -673,32 +687,34 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
         const bool has_next = pass + 1 < passes;
         const int next_shift = has_next ? split.shift(pass + 1) : 0, next_bits = has_next ? split.width(pass + 1) : 0;
         uint32_t all;
-        const uint32_t h = sh.local[t];
-        sh.run[t] = block_exclusive_scan(h, sh.tmp, all);
-        sh.local[t] = 0u;   // now the next pass's histogram
+        const uint32_t h = t < kRadix ? sh.local[t] : 0u;
+        const uint32_t rb = block_exclusive_scan<kBigWaves>(h, sh.tmp, all);
+        if (t < kRadix) {
+            sh.run[t] = rb;
+            sh.local[t] = 0u;   // now the next pass's histogram
+        }
         for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
             const uint32_t cn = min(kSegMax, n - c0);
-            const int items = (int)((cn + kSortThreads - 1) / kSortThreads);
+            const int items = (int)((cn + kBigThreads - 1) / kBigThreads);
             const uint32_t wbase = c0 + w * kWave * (uint32_t)items;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) sh.wcnt[q][t] = 0u;
+            zero_wcnt(sh, t);
             __syncthreads();
-            uint32_t k[kSegItems], v[kSegItems], rk[kSegItems];
+            uint32_t k[kBigItems], v[kBigItems], rk[kBigItems];
             uint32_t valid = 0;
 #pragma unroll
-            for (int i = 0; i < kSegItems; ++i) {
+            for (int i = 0; i < kBigItems; ++i) {
                 const uint32_t p = wbase + (uint32_t)i * kWave + l;
                 valid |= (uint32_t)(i < items && p < c0 + cn) << i;
                 const uint32_t pc = min(p, n - 1);
                 k[i] = src_k[start + pc];
                 v[i] = src_v[start + pc];
             }
-            wave_rank<kSegItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
+            wave_rank<kBigItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
             __syncthreads();
-            const uint32_t tot = digit_wave_prefix(sh, t);
+            const uint32_t tot = t < kRadix ? digit_wave_prefix(sh, t) : 0u;
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < kSegItems; ++i) {
+            for (int i = 0; i < kBigItems; ++i) {
                 if (!((valid >> i) & 1u)) continue;
                 const uint32_t d = digit_at(k[i], shift, bits);
                 const uint32_t o = sh.run[d] + sh.wcnt[w][d] + rk[i];
@@ -707,7 +723,7 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
                 if (has_next) atomicAdd(&sh.local[digit_at(k[i], next_shift, next_bits)], 1u);
             }
             __syncthreads();
-            sh.run[t] += tot;
+            if (t < kRadix) sh.run[t] += tot;
         }
         __syncthreads();
         uint32_t* tk = src_k;
@@ -722,8 +738,8 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
     if (!in_place && passes == 0 && !keys64) return;   // order unchanged, pidx untouched
     for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
 #pragma unroll
-        for (int i = 0; i < kSegItems; ++i) {
-            const uint32_t p = c0 + (uint32_t)i * kSortThreads + t;
+        for (int i = 0; i < kBigItems; ++i) {
+            const uint32_t p = c0 + (uint32_t)i * kBigThreads + t;
             if (p >= n) continue;
             if (!in_place) pidx[start + p] = src_v[start + p];
             if (keys64) keys64[start + p] = ((uint64_t)tile << 32) | src_k[start + p];
@@ -866,7 +882,7 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
 // Step 7b: a resident grid works through the list of long segments, one workgroup per
 // segment, with stable LSD radix passes: in LDS up to kSegMax entries, through the
 // workspace beyond.
-__global__ void __launch_bounds__(kSortThreads) segment_sort_big_kernel(
+__global__ void __launch_bounds__(kBigThreads) segment_sort_big_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
     uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p, uint64_t capacity,
     const int32_t* __restrict__ status, const uint32_t* __restrict__ big_list,
@@ -1041,7 +1057,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     // arrays and vals_alt are scratch now)
     if (plan.tiles_total) {
         static int big_grid = 0;
-        if (!big_grid) big_grid = resident_blocks(reinterpret_cast<const void*>(segment_sort_big_kernel), kSortThreads);
+        if (!big_grid) big_grid = resident_blocks(reinterpret_cast<const void*>(segment_sort_big_kernel), kBigThreads);
         if (!big_grid) return -1;
         uint32_t* big_count = counters;
         uint32_t* big_list = reinterpret_cast<uint32_t*>(base + plan.off_big_list);
@@ -1049,7 +1065,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
                            bins->ranges, plan.tiles_total, zin, bins->pidx, bins->keys, bins->count,
                            plan.capacity, bins->status, big_list, big_count);
         hipLaunchKernelGGL(segment_sort_big_kernel, dim3((unsigned)std::min<uint32_t>(plan.tiles_total, big_grid)),
-                           dim3(kSortThreads), 0, stream, bins->ranges, zin, bins->pidx, bins->keys,
+                           dim3(kBigThreads), 0, stream, bins->ranges, zin, bins->pidx, bins->keys,
                            bins->count, plan.capacity, bins->status, big_list, big_count, keys_a, keys_b, vals_alt);
     }
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
