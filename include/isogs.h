@@ -154,17 +154,28 @@ int isogs_bin_sort(const isogs_projected* proj, const int32_t* n_per_view,
                    const isogs_camera* cams, int32_t n_views, const isogs_bins* bins,
                    void* ws, size_t* ws_bytes, void* stream);
 
+/* Compositing checkpoints, for isogs_render_bwd on long tile lists: at list positions
+ * k * ISOGS_CKPT_CHUNK (k >= 1) of a tile, each pixel's state before that entry - float4
+ * {T, accumulated r, g, b} - is stored at slot start / ISOGS_CKPT_CHUNK + k of the buffer
+ * (start: the tile's first entry), 256 float4 per slot in the tile's thread order. Slots
+ * of different tiles never overlap. A buffer for bins of a given capacity takes
+ * isogs_checkpoint_bytes(capacity) bytes (device memory, caller-owned). */
+#define ISOGS_CKPT_CHUNK 1024
+size_t isogs_checkpoint_bytes(uint64_t capacity);
+
 /* Front-to-back compositing (eq. 4) of every pixel over its tile's sorted entries.
  *   bg        host [3] background colour added as T_final * bg
  *   image     [sum 3 H_v W_v]  planar per view: [V][3][H][W]
  *   T_final   [sum H_v W_v]    transmittance left after the last composited entry
  *   n_last    [sum H_v W_v]    1 + tile-list position of the last contributing entry
  *                              (0 if none); the backward pass starts there
+ *   checkpoints  NULL, or a buffer of isogs_checkpoint_bytes(bins->capacity) bytes that
+ *                receives the compositing checkpoints (see above)
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_DEVICE. */
 int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
                      const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
                      const float* bg, float* image, float* T_final, uint32_t* n_last,
-                     void* stream);
+                     float* checkpoints, void* stream);
 
 /* Same outputs as isogs_render_fwd (bitwise), computed by a persistent grid - as many
  * workgroups as the GPU holds at once - that takes tiles from a global queue ordered
@@ -177,15 +188,20 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
 int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view,
                                 const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
                                 const float* bg, float* image, float* T_final, uint32_t* n_last,
-                                void* ws, size_t* ws_bytes, void* stream);
+                                float* checkpoints, void* ws, size_t* ws_bytes, void* stream);
 
 /* Gradients of a scalar loss L with respect to the particle parameters, given dL/dimage.
  * Walks each pixel's entries in reverse from n_last, recovering the transmittance before
  * each entry as T / (1 - alpha) (no per-entry state is stored by the forward pass), and
  * sums each entry's gradient over the tile's pixels with wavefront reductions in a fixed
- * order (no floating-point atomics: results are bitwise reproducible).
+ * order (no floating-point atomics: results are bitwise reproducible). With the forward's
+ * checkpoints, a tile whose list is longer than ISOGS_CKPT_CHUNK is walked as independent
+ * chunks on different workgroups, each starting from the checkpoint at its end (the light
+ * from behind a chunk is image - accumulated colour there).
  *   scenes, cams   the same arrays as given to isogs_project
+ *   image          the forward's image (may be NULL when checkpoints is NULL)
  *   dL_dimage      [sum 3 H_v W_v], same layout as image
+ *   checkpoints    NULL, or the buffer the forward filled for these bins
  *   grads          host array [V] of output buffers in scene layout; views whose scene
  *                  pointers (pos) are equal must pass equal grads entries: their
  *                  gradients are summed in view order. Outputs are overwritten.
@@ -197,8 +213,9 @@ int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_pe
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
 int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,
-                     const float* dL_dimage, const float* T_final, const uint32_t* n_last,
-                     const isogs_scene* grads, void* ws, size_t* ws_bytes, void* stream);
+                     const float* image, const float* dL_dimage, const float* T_final,
+                     const uint32_t* n_last, const float* checkpoints, const isogs_scene* grads,
+                     void* ws, size_t* ws_bytes, void* stream);
 
 /* Message describing the last error returned on the calling thread ("" if none). */
 const char* isogs_last_error(void);

@@ -144,9 +144,13 @@ int isogs_bin_sort(const isogs_projected* proj, const int32_t* n_per_view, const
     return ISOGS_OK;
 }
 
+size_t isogs_checkpoint_bytes(uint64_t capacity) {
+    return (size_t)(capacity / ISOGS_CKPT_CHUNK + 1) * 256 * 4 * sizeof(float);
+}
+
 int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                      const isogs_camera* cams, int32_t n_views, const float* bg, float* image, float* T_final,
-                     uint32_t* n_last, void* stream) {
+                     uint32_t* n_last, float* checkpoints, void* stream) {
     g_error[0] = 0;
     int rc;
     if ((rc = check_views(n_views))) return rc;
@@ -158,7 +162,7 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, con
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
-    if (isogs::launch_render_fwd(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
+    if (isogs::launch_render_fwd(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last, checkpoints,
                                  (hipStream_t)stream))
         return device_fail("isogs_render_fwd");
     return ISOGS_OK;
@@ -166,7 +170,8 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, con
 
 int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                                 const isogs_camera* cams, int32_t n_views, const float* bg, float* image,
-                                float* T_final, uint32_t* n_last, void* ws, size_t* ws_bytes, void* stream) {
+                                float* T_final, uint32_t* n_last, float* checkpoints, void* ws, size_t* ws_bytes,
+                                void* stream) {
     g_error[0] = 0;
     int rc;
     if ((rc = check_views(n_views))) return rc;
@@ -186,16 +191,16 @@ int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_pe
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
-    if (isogs::launch_render_fwd_persistent(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last, ws,
-                                            (hipStream_t)stream))
+    if (isogs::launch_render_fwd_persistent(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
+                                            checkpoints, ws, (hipStream_t)stream))
         return device_fail("isogs_render_fwd_persistent");
     return ISOGS_OK;
 }
 
 int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
-                     const isogs_projected* proj, const isogs_bins* bins, const float* bg, const float* dL_dimage,
-                     const float* T_final, const uint32_t* n_last, const isogs_scene* grads, void* ws,
-                     size_t* ws_bytes, void* stream) {
+                     const isogs_projected* proj, const isogs_bins* bins, const float* bg, const float* image,
+                     const float* dL_dimage, const float* T_final, const uint32_t* n_last, const float* checkpoints,
+                     const isogs_scene* grads, void* ws, size_t* ws_bytes, void* stream) {
     g_error[0] = 0;
     int rc;
     if ((rc = check_views(n_views))) return rc;
@@ -229,8 +234,9 @@ int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!bg || !dL_dimage || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "input buffer is NULL");
-    if (isogs::launch_render_bwd(scenes, cams, n_views, proj, bins, bg, dL_dimage, T_final, n_last, grads, ws,
-                                 (hipStream_t)stream))
+    if (checkpoints && !image) return fail(ISOGS_ERR_INVALID, "checkpoints given without the image");
+    if (isogs::launch_render_bwd(scenes, cams, n_views, proj, bins, bg, image, dL_dimage, T_final, n_last,
+                                 checkpoints, grads, ws, (hipStream_t)stream))
         return device_fail("isogs_render_bwd");
     return ISOGS_OK;
 }

@@ -94,12 +94,17 @@ __device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __res
 // Reverse walk of one tile (logical index within the launch) by a 256-thread workgroup,
 // one lane per pixel, each 16-lane row owning a 4x4 sub-block (the forward pixel layout).
 // Record of an entry: {du, dv, d(1/s^2), do} {dr, dg, db, 0}, at its emit position.
-// Contains __syncthreads.
+// With checkpoints (`ckpt` non-null) the workgroup walks only chunk `chunk` of the list,
+// positions [chunk * kCkptChunk, (chunk + 1) * kCkptChunk); a pixel whose last entry lies
+// beyond the chunk starts from the checkpoint at the chunk's end: T from there, and the
+// light from behind = image - colour accumulated before the chunk's end. Without
+// checkpoints the whole list is one chunk. Contains __syncthreads.
 __device__ __forceinline__ void composite_bwd_tile(
-    StagedBwd& sb, const RenderPack& pk, uint32_t logical, const float4* __restrict__ record,
+    StagedBwd& sb, const RenderPack& pk, uint32_t logical, uint32_t chunk, const float4* __restrict__ record,
     const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges,
-    float bg_r, float bg_g, float bg_b, const float* __restrict__ dL_dimage, const float* __restrict__ T_final,
-    const uint32_t* __restrict__ n_last, float4* __restrict__ rec) {
+    float bg_r, float bg_g, float bg_b, const float* __restrict__ image, const float* __restrict__ dL_dimage,
+    const float* __restrict__ T_final, const uint32_t* __restrict__ n_last, const float4* __restrict__ ckpt,
+    float4* __restrict__ rec) {
     int vi, tx, ty;
     locate_tile(pk, logical, vi, tx, ty);
     const ViewDesc& vd = pk.v[vi];
@@ -111,8 +116,13 @@ __device__ __forceinline__ void composite_bwd_tile(
     const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
     const uint32_t start = ranges[2 * gt], end = min(ranges[2 * gt + 1], pk.n_entries_cap);
     const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
+    const uint32_t len = end > start ? end - start : 0u;
+    // this workgroup's positions [c_lo, c_hi) of the list
+    const uint32_t c_lo = ckpt ? chunk * kCkptChunk : 0u;
+    const uint32_t c_hi = ckpt ? min(c_lo + kCkptChunk, len) : len;
 
     float T = 1.0f, dr = 0.0f, dg = 0.0f, db = 0.0f;
+    float Sr = 0.0f, Sg = 0.0f, Sb = 0.0f;
     uint32_t last = 0;
     if (inside) {
         const size_t hw = (size_t)vd.width * vd.height;
@@ -121,23 +131,35 @@ __device__ __forceinline__ void composite_bwd_tile(
         dr = dimg[pix];
         dg = dimg[hw + pix];
         db = dimg[2 * hw + pix];
-        T = T_final[vd.pix_off + pix];
         last = n_last[vd.pix_off + pix];
+        if (last > c_hi) {
+            // the pixel composited entries beyond this chunk: state at the chunk's end
+            const float4 s = ckpt[(size_t)ckpt_slot(start, c_hi / kCkptChunk) * 256 + t];
+            const float* im = image + (size_t)3 * vd.pix_off;
+            T = s.x;
+            Sr = im[pix] - s.y;
+            Sg = im[hw + pix] - s.z;
+            Sb = im[2 * hw + pix] - s.w;
+        } else {
+            // light arriving from behind the last entry: T_final bg
+            T = T_final[vd.pix_off + pix];
+            Sr = T * bg_r;
+            Sg = T * bg_g;
+            Sb = T * bg_b;
+        }
     }
-    // light arriving from behind the current entry: sum of later c alpha T, plus T_final bg
-    float Sr = T * bg_r, Sg = T * bg_g, Sb = T * bg_b;
 
     if (t < 16) sb.gmax[t] = 0u;
     __syncthreads();
-    if (last) atomicMax(&sb.gmax[sbk], last);
+    if (last > c_lo) atomicMax(&sb.gmax[sbk], min(last, c_hi));
     __syncthreads();
     uint32_t max_last = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) max_last = max(max_last, sb.gmax[k]);
-    max_last = min(max_last, end > start ? end - start : 0u);
+    max_last = max(max_last, c_lo);   // 1-based end of the walk inside [c_lo, c_hi]
 
-    // entries no pixel reached carry zero gradient
-    for (uint32_t e = start + max_last + t; e < end; e += 256) {
+    // entries of the chunk no pixel reached carry zero gradient
+    for (uint32_t e = start + max_last + t; e < start + c_hi; e += 256) {
         const uint32_t g = pidx[e];
         if (g < pk.n_particles) {
             const float4 f = record[2 * (size_t)g];
@@ -152,8 +174,8 @@ __device__ __forceinline__ void composite_bwd_tile(
 
     const uint32_t q8 = rev3(lane & 7u);
     const bool writer = (lane & 15u) < 8u && q8 < 7u;
-    for (uint32_t hi = start + max_last; hi > start;) {
-        const uint32_t nb = min((uint32_t)kBwdBatch, hi - start);
+    for (uint32_t hi = start + max_last; hi > start + c_lo;) {
+        const uint32_t nb = min((uint32_t)kBwdBatch, hi - start - c_lo);
         const uint32_t pos_hi = hi - start;
         uint32_t len;
         const uint32_t steps = stage_bwd(sb, record, pidx, offsets, pk.n_particles, hi, nb, pos_hi, tx, ty,
@@ -225,38 +247,66 @@ __device__ __forceinline__ void composite_bwd_tile(
     }
 }
 
-// One workgroup per tile, tiles in XCD-banded order.
-__global__ void __launch_bounds__(256) composite_bwd_kernel(
-    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
-    float bg_r, float bg_g, float bg_b, const float* __restrict__ dL_dimage, const float* __restrict__ T_final,
-    const uint32_t* __restrict__ n_last, float4* __restrict__ rec) {
-    __shared__ StagedBwd sb;
-    if (*status != kStatusOk) return;
-    composite_bwd_tile(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, offsets, ranges, bg_r, bg_g, bg_b,
-                       dL_dimage, T_final, n_last, rec);
+__global__ void __launch_bounds__(64) fill_u32_kernel_b(uint32_t* __restrict__ p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-// Persistent variant: a fixed grid takes tiles from the longest-list-first queue, so the
-// few tiles with very long lists start first instead of trailing the launch. Every
-// workgroup leaves once the counter passes the last item.
+// Work items of the tiles whose list is longer than one checkpoint chunk: one
+// (tile, chunk) pair per chunk, appended in any order.
+__global__ void __launch_bounds__(256) bwd_chunk_list_kernel(const uint32_t* __restrict__ ranges, uint32_t tile0,
+                                                             uint32_t n_tiles, uint32_t cap,
+                                                             uint32_t* __restrict__ heavy,
+                                                             uint32_t* __restrict__ heavy_count) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tiles) return;
+    const uint32_t s = ranges[2 * (tile0 + i)], e = min(ranges[2 * (tile0 + i) + 1], cap);
+    const uint32_t len = e > s ? e - s : 0u;
+    if (len <= kCkptChunk) return;
+    const uint32_t nch = (len + kCkptChunk - 1) / kCkptChunk;
+    const uint32_t base = atomicAdd(heavy_count, nch);
+    for (uint32_t c = 0; c < nch; ++c) {
+        heavy[2 * (base + c)] = i;
+        heavy[2 * (base + c) + 1] = c;
+    }
+}
+
+// A resident grid takes work items from one counter: first the chunks of the long tiles
+// (when checkpoints are given), then the tiles of the longest-list-first queue, skipping
+// the long ones. Every workgroup leaves once the counter passes the last item.
 __global__ void __launch_bounds__(256) composite_bwd_persistent_kernel(
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
-    float bg_r, float bg_g, float bg_b, const float* __restrict__ dL_dimage, const float* __restrict__ T_final,
-    const uint32_t* __restrict__ n_last, float4* __restrict__ rec, const uint32_t* __restrict__ order,
-    uint32_t n_items, uint32_t* __restrict__ counter) {
+    float bg_r, float bg_g, float bg_b, const float* __restrict__ image, const float* __restrict__ dL_dimage,
+    const float* __restrict__ T_final, const uint32_t* __restrict__ n_last, const float4* __restrict__ ckpt,
+    float4* __restrict__ rec, const uint32_t* __restrict__ order, uint32_t n_items,
+    const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count, uint32_t* __restrict__ counter) {
     __shared__ StagedBwd sb;
     __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
+    const uint32_t n_heavy = ckpt ? *heavy_count : 0u;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
         __syncthreads();
         const uint32_t item = s_item;
         __syncthreads();
-        if (item >= n_items) break;
-        composite_bwd_tile(sb, pk, order[item], record, pidx, offsets, ranges, bg_r, bg_g, bg_b, dL_dimage,
-                           T_final, n_last, rec);
+        uint32_t logical, chunk = 0;
+        if (item < n_heavy) {
+            logical = heavy[2 * item];
+            chunk = heavy[2 * item + 1];
+        } else {
+            const uint32_t j = item - n_heavy;
+            if (j >= n_items) break;
+            logical = order[j];
+            if (ckpt) {
+                int vi, tx, ty;
+                locate_tile(pk, logical, vi, tx, ty);
+                const uint32_t gt = pk.v[vi].tile_base + (uint32_t)(ty * pk.v[vi].tiles_x + tx);
+                const uint32_t s = ranges[2 * gt], e = min(ranges[2 * gt + 1], pk.n_entries_cap);
+                if (e > s && e - s > kCkptChunk) continue;   // walked as chunks above
+            }
+        }
+        composite_bwd_tile(sb, pk, logical, chunk, record, pidx, offsets, ranges, bg_r, bg_g, bg_b, image,
+                           dL_dimage, T_final, n_last, ckpt, rec);
     }
 }
 
@@ -421,24 +471,38 @@ __global__ void __launch_bounds__(256) grad_project_kernel(const GradPack pk, co
 
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Workspace: gradient records (32 B per entry of capacity), the tile queue, the chunk
+// item count and the chunk items (two words each; at most capacity / kCkptChunk + tiles).
+static size_t bwd_heavy_words(uint64_t capacity, uint32_t tiles) {
+    return 2 * ((size_t)(capacity / kCkptChunk) + tiles + 1);
+}
+
 size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv) {
-    return round256((size_t)capacity * 32) + tile_queue_words(max_group_tiles(cams, nv)) * 4 + 256;
+    const uint32_t tiles = max_group_tiles(cams, nv);
+    return round256((size_t)capacity * 32) + round256(tile_queue_words(tiles) * 4) + 256 +
+           bwd_heavy_words(capacity, tiles) * 4 + 256;
 }
 
 int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
                       const isogs_projected* proj, const isogs_bins* bins, const float* bg,
-                      const float* dL_dimage, const float* T_final, const uint32_t* n_last,
-                      const isogs_scene* grads, void* ws, hipStream_t stream) {
+                      const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
+                      const float* ckpt, const isogs_scene* grads, void* ws, hipStream_t stream) {
     static int grid_max = 0;
     if (!grid_max) grid_max = resident_blocks(reinterpret_cast<const void*>(composite_bwd_persistent_kernel), 256);
     if (!grid_max) return -1;
-    float4* rec = static_cast<float4*>(ws);
-    uint32_t* q = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + round256((size_t)bins->capacity * 32));
+    const uint32_t max_tiles = max_group_tiles(cams, nv);
+    char* base = static_cast<char*>(ws);
+    float4* rec = reinterpret_cast<float4*>(base);
+    base += round256((size_t)bins->capacity * 32);
+    uint32_t* q = reinterpret_cast<uint32_t*>(base);
+    base += round256(tile_queue_words(max_tiles) * 4);
+    uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base);
+    uint32_t* heavy = reinterpret_cast<uint32_t*>(base + 256);
     int32_t n_per_view[kMaxViews];
     int32_t n_all[4096];
     if (nv > 4096) return -1;
     for (int v = 0; v < nv; ++v) n_all[v] = scenes[v].n;
-    // 1. per-tile reverse compositing, longest lists first
+    // 1. reverse compositing: chunks of long tiles (with checkpoints), then tiles longest first
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         const int m = min(kMaxViews, nv - v0);
@@ -450,11 +514,16 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
         set_render_limits(pk, n_all, nv, bins->capacity);
         if (!blocks) continue;
         uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
+        if (ckpt) {
+            hipLaunchKernelGGL(fill_u32_kernel_b, dim3(1), dim3(64), 0, stream, heavy_count, 1u);
+            hipLaunchKernelGGL(bwd_chunk_list_kernel, dim3((blocks + 255) / 256), dim3(256), 0, stream, bins->ranges,
+                               tile0, blocks, pk.n_entries_cap, heavy, heavy_count);
+        }
         const unsigned grid = std::min<unsigned>(blocks, (unsigned)grid_max);
         hipLaunchKernelGGL(composite_bwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->offsets, bins->ranges,
-                           bins->status, bg[0], bg[1], bg[2], dL_dimage, T_final, n_last, rec, order, blocks,
-                           order - 1);
+                           bins->status, bg[0], bg[1], bg[2], image, dL_dimage, T_final, n_last,
+                           reinterpret_cast<const float4*>(ckpt), rec, order, blocks, heavy, heavy_count, order - 1);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     // 2. per scene: reduce records over its views (in view order) and chain to parameters

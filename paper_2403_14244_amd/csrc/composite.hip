@@ -30,7 +30,7 @@ __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& 
                                                const uint32_t* __restrict__ pidx,
                                                const uint32_t* __restrict__ ranges, float bg_r, float bg_g,
                                                float bg_b, float* __restrict__ image, float* __restrict__ T_final,
-                                               uint32_t* __restrict__ n_last) {
+                                               uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
     int vi, tx, ty;
     locate_tile(pk, logical, vi, tx, ty);
     const ViewDesc& vd = pk.v[vi];
@@ -48,6 +48,8 @@ __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& 
     bool done = !inside;
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         if (__syncthreads_and(done)) break;
+        if (ckpt && b0 > start && (b0 - start) % kCkptChunk == 0)
+            ckpt[(size_t)ckpt_slot(start, (b0 - start) / kCkptChunk) * 256 + t] = make_float4(T, cr, cg, cb);
         const uint32_t nb = min((uint32_t)kBatch, end - b0);
         const uint32_t steps = stage_batch_sub(sb, record, pidx, pk.n_particles, b0, nb, tx * kTile, ty * kTile,
                                                w_lim, h_lim);
@@ -84,11 +86,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWa
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
     float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
-    uint32_t* __restrict__ n_last) {
+    uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
     __shared__ StagedSub sb;
     if (*status != kStatusOk) return;
     composite_tile(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, ranges, bg_r, bg_g, bg_b, image,
-                   T_final, n_last);
+                   T_final, n_last, ckpt);
 }
 
 // Persistent variant: a fixed grid of workgroups takes tiles from a global queue ordered
@@ -98,7 +100,8 @@ __global__ void __launch_bounds__(256) composite_fwd_persistent_kernel(
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
     float* __restrict__ image, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
-    const uint32_t* __restrict__ order, uint32_t n_items, uint32_t* __restrict__ counter) {
+    float4* __restrict__ ckpt, const uint32_t* __restrict__ order, uint32_t n_items,
+    uint32_t* __restrict__ counter) {
     __shared__ StagedSub sb;
     __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(256) composite_fwd_persistent_kernel(
         const uint32_t item = s_item;
         __syncthreads();
         if (item >= n_items) break;
-        composite_tile(sb, pk, order[item], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last);
+        composite_tile(sb, pk, order[item], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
     }
 }
 
@@ -166,7 +169,7 @@ __global__ void __launch_bounds__(256) tile_class_scatter_kernel(const uint32_t*
 
 int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                       const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
-                      uint32_t* n_last, hipStream_t stream) {
+                      uint32_t* n_last, float* ckpt, hipStream_t stream) {
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         RenderPack pk{};
@@ -176,7 +179,8 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
         if (!blocks) continue;
         hipLaunchKernelGGL(composite_fwd_kernel, dim3(blocks), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges,
-                           bins->status, bg[0], bg[1], bg[2], image, T_final, n_last);
+                           bins->status, bg[0], bg[1], bg[2], image, T_final, n_last,
+                           reinterpret_cast<float4*>(ckpt));
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     return 0;
@@ -223,7 +227,7 @@ int resident_blocks(const void* kernel, int threads) {
 
 int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                                  const isogs_camera* cams, int32_t nv, const float* bg, float* image,
-                                 float* T_final, uint32_t* n_last, void* ws, hipStream_t stream) {
+                                 float* T_final, uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream) {
     static int grid_max = 0;
     if (!grid_max) grid_max = resident_blocks(reinterpret_cast<const void*>(composite_fwd_persistent_kernel), 256);
     if (!grid_max) return -1;
@@ -240,7 +244,8 @@ int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_p
         const unsigned grid = std::min<unsigned>(blocks, (unsigned)grid_max);
         hipLaunchKernelGGL(composite_fwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
-                           bg[0], bg[1], bg[2], image, T_final, n_last, order, blocks, order - 1);
+                           bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order,
+                           blocks, order - 1);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     return 0;

@@ -30,7 +30,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
 
 int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                       const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
-                      uint32_t* n_last, hipStream_t stream);
+                      uint32_t* n_last, float* ckpt, hipStream_t stream);
 
 size_t render_fwd_persistent_ws(const isogs_camera* cams, int32_t nv);
 
@@ -47,11 +47,11 @@ size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv);
 
 int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                                  const isogs_camera* cams, int32_t nv, const float* bg, float* image,
-                                 float* T_final, uint32_t* n_last, void* ws, hipStream_t stream);
+                                 float* T_final, uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream);
 
 int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
                       const isogs_projected* proj, const isogs_bins* bins, const float* bg,
-                      const float* dL_dimage, const float* T_final, const uint32_t* n_last,
-                      const isogs_scene* grads, void* ws, hipStream_t stream);
+                      const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
+                      const float* ckpt, const isogs_scene* grads, void* ws, hipStream_t stream);
 
 }  // namespace isogs

@@ -7,6 +7,18 @@
 namespace isogs {
 
 constexpr int kBatch = 256;   // forward: entries staged in LDS per round (one per thread)
+
+// Compositing checkpoints: at every kCkptChunk-th position of a tile's list (a multiple of
+// the forward batch) the forward can store each pixel's {T, r, g, b} before that entry, so
+// that the backward can walk the chunks of one long list on different workgroups. The
+// checkpoints of the tile whose list starts at global entry `start` occupy slots
+// start / kCkptChunk + k (k >= 1), which never overlap between tiles; a slot holds one
+// float4 per pixel (thread) of the tile.
+constexpr uint32_t kCkptChunk = 1024;
+static_assert(kCkptChunk % 256 == 0, "checkpoints sit on forward batch boundaries");
+static_assert(kCkptChunk == ISOGS_CKPT_CHUNK, "the header states the checkpoint spacing");
+
+__host__ __device__ inline uint32_t ckpt_slot(uint32_t start, uint32_t k) { return start / kCkptChunk + k; }
 constexpr int kDummy = kBatch; // staged slot of a zero-opacity record that pads the lists
 
 // Emit position of the entry (particle with footprint u, v, r; tile tx, ty): the

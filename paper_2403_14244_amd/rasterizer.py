@@ -186,7 +186,14 @@ class Rasterizer:
                 self.capacity = cap
         raise A.IsoGSError(A.ISOGS_ERR_CAPACITY, "bin_sort capacity still too small after growing")
 
-    def render_fwd(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0)):
+    def checkpoint_buffer(self, bins: TileBins) -> torch.Tensor:
+        """Device buffer for the compositing checkpoints of these bins (see render_bwd)."""
+        nbytes = int(A.lib().isogs_checkpoint_bytes(bins.capacity))
+        return torch.empty(nbytes // 4, dtype=_F32, device=self.device)
+
+    def render_fwd(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0), ckpt=None):
+        """Composites every view; with `ckpt` (from checkpoint_buffer) also stores the
+        checkpoints that let render_bwd split long tiles."""
         pix = sum(int(c.width) * int(c.height) for c in cams)
         image = torch.empty(3 * pix, dtype=_F32, device=self.device)
         T = torch.empty(pix, dtype=_F32, device=self.device)
@@ -194,11 +201,11 @@ class Rasterizer:
         bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
         A.check(A.lib().isogs_render_fwd(ctypes.byref(fp.abi()), A.int_array(n_per_view), ctypes.byref(bins.abi()),
                                          A.camera_array(cams), len(cams), bgc, _p(image), _p(T), _p(n_last),
-                                         _stream()))
+                                         _p(ckpt), _stream()))
         return image, T, n_last
 
     def render_fwd_persistent(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0),
-                              out=None):
+                              out=None, ckpt=None):
         """render_fwd through the persistent, longest-list-first kernel (same result).
         `out` optionally supplies (image, T_final, n_last) buffers."""
         pix = sum(int(c.width) * int(c.height) for c in cams)
@@ -212,7 +219,7 @@ class Rasterizer:
         npv = A.int_array(n_per_view)
         need = ctypes.c_size_t(0)
         args = (ctypes.byref(fp.abi()), npv, ctypes.byref(bins.abi()), carr, len(cams), bgc, _p(image), _p(T),
-                _p(n_last))
+                _p(n_last), _p(ckpt))
         A.check(A.lib().isogs_render_fwd_persistent(*args, None, ctypes.byref(need), _stream()))
         ws = self._workspace_q(need.value)
         have = ctypes.c_size_t(ws.numel())
@@ -224,9 +231,11 @@ class Rasterizer:
             self._wsq = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         return self._wsq
 
-    def render_bwd(self, scenes, cams, fp: Footprints, bins: TileBins, bg, dL_dimage, T_final, n_last, grads=None):
+    def render_bwd(self, scenes, cams, fp: Footprints, bins: TileBins, bg, dL_dimage, T_final, n_last, grads=None,
+                   image=None, ckpt=None):
         """Returns one GaussianScene of gradients per distinct scene (by pos pointer), in
-        order of first appearance; views of one scene are summed."""
+        order of first appearance; views of one scene are summed. With the forward's image
+        and checkpoints, long tiles are walked as chunks on several workgroups."""
         if grads is None:
             uniq = {}
             for s in scenes:
@@ -238,8 +247,8 @@ class Rasterizer:
         bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
         need = ctypes.c_size_t(0)
         ab = bins.abi()
-        args = (sc, A.camera_array(cams), len(cams), ctypes.byref(fp.abi()), ctypes.byref(ab), bgc,
-                _p(dL_dimage.contiguous()), _p(T_final), _p(n_last), gs)
+        args = (sc, A.camera_array(cams), len(cams), ctypes.byref(fp.abi()), ctypes.byref(ab), bgc, _p(image),
+                _p(dL_dimage.contiguous()), _p(T_final), _p(n_last), _p(ckpt), gs)
         A.check(A.lib().isogs_render_bwd(*args, None, ctypes.byref(need), _stream()))
         ws = self._workspace(need.value)
         have = ctypes.c_size_t(ws.numel())
@@ -252,7 +261,7 @@ class Rasterizer:
         return out
 
     # -- convenience ------------------------------------------------------------------
-    def render(self, scenes, cams, bg=(0.0, 0.0, 0.0), check=True):
+    def render(self, scenes, cams, bg=(0.0, 0.0, 0.0), check=True, checkpoints=False):
         """Full forward pass. Returns (list of [3, H, W] images, state for backward).
 
         `check=True`: everything is queued before the one host synchronisation that the
@@ -261,12 +270,14 @@ class Rasterizer:
         to pinned host memory behind the launches and `verify(state)` reads it later (the
         first call, with no capacity yet, still checks synchronously). With
         `persistent_fwd` set, compositing uses the longest-list-first persistent kernel
-        (same images bitwise)."""
+        (same images bitwise). `checkpoints` keeps the compositing checkpoints for the
+        backward in the state."""
         fp = self.project(scenes, cams)
         npv = [s.n for s in scenes]
         fwd = self.render_fwd_persistent if self.persistent_fwd else self.render_fwd
         bins = self.bin_sort(fp, npv, cams, check=False)
-        out = fwd(fp, npv, bins, cams, bg)
+        ckpt = self.checkpoint_buffer(bins) if checkpoints else None
+        out = fwd(fp, npv, bins, cams, bg, ckpt=ckpt)
         pending = None
         if check == "deferred" and self.capacity > 0:
             pending = torch.empty(2, dtype=torch.int32, pin_memory=True)
@@ -280,12 +291,13 @@ class Rasterizer:
             if st == A.ISOGS_ERR_CAPACITY:
                 self.capacity = int(bins.n_entries() * self.headroom) + 4096
                 bins = self.bin_sort(fp, npv, cams, check=True)
-                out = fwd(fp, npv, bins, cams, bg)
+                ckpt = self.checkpoint_buffer(bins) if checkpoints else None
+                out = fwd(fp, npv, bins, cams, bg, ckpt=ckpt)
             elif st != A.ISOGS_OK:
                 raise A.IsoGSError(st, "bin_sort failed on the device")
         image, T, n_last = out
         return split_images(image, cams), dict(fp=fp, bins=bins, image=image, T=T, n_last=n_last, npv=npv,
-                                               pending=pending)
+                                               pending=pending, ckpt=ckpt)
 
     def verify(self, state):
         """Reads a deferred status (waiting for the forward launches if needed). On a
@@ -326,7 +338,7 @@ class IsoGSRender(torch.autograd.Function):
         scene = GaussianScene(pos.contiguous(), scale.contiguous(), opacity.contiguous(), color.contiguous(),
                               int(sh_degree))
         scenes = [scene] * len(cams)
-        images, st = rasterizer.render(scenes, cams, bg, check="deferred")
+        images, st = rasterizer.render(scenes, cams, bg, check="deferred", checkpoints=True)
         ctx.rasterizer = rasterizer
         ctx.cams = cams
         ctx.bg = bg
@@ -341,5 +353,6 @@ class IsoGSRender(torch.autograd.Function):
         ctx.rasterizer.verify(st)
         scenes = [ctx.scene] * len(ctx.cams)
         g = ctx.rasterizer.render_bwd(scenes, ctx.cams, st["fp"], st["bins"], ctx.bg,
-                                      grad_out.contiguous().reshape(-1), st["T"], st["n_last"])[0]
+                                      grad_out.contiguous().reshape(-1), st["T"], st["n_last"],
+                                      image=st["image"], ckpt=st["ckpt"])[0]
         return g.pos, g.scale, g.opacity, g.color, None, None, None, None

@@ -20,7 +20,7 @@ def _abi():
 
 def header_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(isogs_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(isogs_\w+)\s*\(", text, re.M)))
 
 
 def test_header_declares_the_four_pipeline_calls():
@@ -114,8 +114,8 @@ def test_workspace_query_and_too_small_workspace():
     bins.capacity = 1000
     sc = (A.Scene * 1)()
     gs = (A.Scene * 1)()
-    assert L.isogs_render_bwd(sc, cams, 1, ctypes.byref(proj), ctypes.byref(bins), None, None, None, None, gs,
-                              None, ctypes.byref(need), None) == A.ISOGS_OK
+    assert L.isogs_render_bwd(sc, cams, 1, ctypes.byref(proj), ctypes.byref(bins), None, None, None, None, None,
+                              None, gs, None, ctypes.byref(need), None) == A.ISOGS_OK
     assert need.value >= 32 * 1000
 
 
