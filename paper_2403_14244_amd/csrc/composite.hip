@@ -5,10 +5,12 @@
 
 namespace isogs {
 
-// Composites one entry into a pixel's running state (branch-free; the dummy pad record
-// has log2(o) = -inf, so alpha = 0 and it changes nothing).
-__device__ __forceinline__ void composite_entry(const float4& f, const float4& c, float px, float py, uint32_t pos,
-                                                float& T, float& cr, float& cg, float& cb, uint32_t& last,
+// Composites one entry (staged slot j) into a pixel's running state (branch-free; the
+// dummy pad record has log2(o) = -inf, so alpha = 0 and it changes nothing). T loses the
+// weight it gives away, T - alpha T; `lastj` keeps the slot of the last entry used in the
+// current batch (slots only increase along a list).
+__device__ __forceinline__ void composite_entry(const float4& f, const float4& c, float px, float py, uint32_t j,
+                                                float& T, float& cr, float& cg, float& cb, uint32_t& lastj,
                                                 bool& done) {
     float g;
     float a = entry_alpha(px - f.x, py - f.y, f.z, f.w, g);
@@ -18,8 +20,8 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
     cr = fmaf(c.x, wgt, cr);
     cg = fmaf(c.y, wgt, cg);
     cb = fmaf(c.z, wgt, cb);
-    T = T * (1.0f - a);
-    last = use ? pos : last;
+    T = T - wgt;
+    lastj = use ? j : lastj;
     done = done || (T < kTMin);
 }
 
@@ -54,17 +56,19 @@ __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& 
         const uint32_t steps = stage_batch_sub(sb, record, pidx, pk.n_particles, b0, nb, tx * kTile, ty * kTile,
                                                w_lim, h_lim);
         const uint32_t pos0 = b0 - start + 1;   // 1-based list position of staged slot 0
+        uint32_t lastj = 0xFFFFFFFFu;
         for (uint32_t k = 0; k < steps; k += 4) {
             uint32_t j[4];
             list4_sub(sb, sbk, k, j);
             const float4 f0 = sb.fp[j[0]], f1 = sb.fp[j[1]], f2 = sb.fp[j[2]], f3 = sb.fp[j[3]];
             const float4 c0 = sb.col[j[0]], c1 = sb.col[j[1]], c2 = sb.col[j[2]], c3 = sb.col[j[3]];
-            composite_entry(f0, c0, px, py, pos0 + j[0], T, cr, cg, cb, last, done);
-            composite_entry(f1, c1, px, py, pos0 + j[1], T, cr, cg, cb, last, done);
-            composite_entry(f2, c2, px, py, pos0 + j[2], T, cr, cg, cb, last, done);
-            composite_entry(f3, c3, px, py, pos0 + j[3], T, cr, cg, cb, last, done);
+            composite_entry(f0, c0, px, py, j[0], T, cr, cg, cb, lastj, done);
+            composite_entry(f1, c1, px, py, j[1], T, cr, cg, cb, lastj, done);
+            composite_entry(f2, c2, px, py, j[2], T, cr, cg, cb, lastj, done);
+            composite_entry(f3, c3, px, py, j[3], T, cr, cg, cb, lastj, done);
             if (ballot64(!done) == 0) break;
         }
+        last = lastj != 0xFFFFFFFFu ? pos0 + lastj : last;
     }
     if (!inside) return;
     const size_t hw = (size_t)vd.width * vd.height;
