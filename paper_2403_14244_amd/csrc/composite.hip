@@ -8,7 +8,9 @@ namespace isogs {
 // Composites one entry (staged slot j) into a pixel's running state (branch-free; the
 // dummy pad record has log2(o) = -inf, so alpha = 0 and it changes nothing). T loses the
 // weight it gives away, T - alpha T; `lastj` keeps the slot of the last entry used in the
-// current batch (slots only increase along a list).
+// current batch (slots only increase along a list). TERM: the pixel stops after the entry
+// that takes T below kTMin.
+template <bool TERM>
 __device__ __forceinline__ void composite_entry(const float4& f, const float4& c, float px, float py, uint32_t j,
                                                 float& T, float& cr, float& cg, float& cb, uint32_t& lastj,
                                                 bool& done) {
@@ -22,63 +24,167 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
     cb = fmaf(c.z, wgt, cb);
     T = T - wgt;
     lastj = use ? j : lastj;
-    done = done || (T < kTMin);
+    if (TERM) done = done || (T < kTMin);
 }
 
-// Composites one tile (logical index within the launch) with a 256-thread workgroup, one
-// lane per pixel; each 16-lane row owns a 4x4 sub-block. Contains __syncthreads.
+// A lane's pixel in a tile, and the pixel's compositing state.
+struct TilePixel {
+    int width, height;
+    uint32_t pix_off;
+    int tx, ty, x, y;
+    bool inside;
+    float px, py, w_lim, h_lim;
+    uint32_t start, len, sbk;
+};
+
+struct PixelState {
+    float T, cr, cg, cb;
+    uint32_t last;   // 1-based tile-list position of the last entry used, 0 if none
+    bool done;
+};
+
+__device__ __forceinline__ TilePixel tile_pixel(const RenderPack& pk, uint32_t logical,
+                                                const uint32_t* __restrict__ ranges) {
+    TilePixel p;
+    int vi;
+    locate_tile(pk, logical, vi, p.tx, p.ty);
+    const ViewDesc& vd = pk.v[vi];
+    p.width = vd.width;
+    p.height = vd.height;
+    p.pix_off = vd.pix_off;
+    const uint32_t t = threadIdx.x;
+    p.x = p.tx * kTile + sub_x(t);
+    p.y = p.ty * kTile + sub_y(t);
+    p.inside = p.x < vd.width && p.y < vd.height;
+    p.px = (float)p.x + 0.5f;
+    p.py = (float)p.y + 0.5f;
+    p.w_lim = (float)vd.width - 0.5f;
+    p.h_lim = (float)vd.height - 0.5f;
+    const uint32_t gt = vd.tile_base + (uint32_t)(p.ty * vd.tiles_x + p.tx);
+    p.start = ranges[2 * gt];
+    const uint32_t end = min(ranges[2 * gt + 1], pk.n_entries_cap);
+    p.len = end > p.start ? end - p.start : 0u;
+    p.sbk = 4 * (t >> 6) + ((t >> 4) & 3u);   // this lane's sub-block
+    return p;
+}
+
+// Walks list positions [lo, hi) of the tile (lo a multiple of the batch) with a 256-thread
+// workgroup, one lane per pixel, each 16-lane row owning a 4x4 sub-block, and updates the
+// lanes' states. With `ckpt`, stores the checkpoints at chunk boundaries inside the range.
+// PIPE: software pipelining for a workgroup with few others beside it on its CU (more
+// registers): the LDS reads of the entries of step k + 4 and of the list words of step k + 8
+// are issued while step k is composited, and the global loads of the next batch while the
+// current one is walked, so that the walk does not wait on dependent round trips.
+// Contains __syncthreads.
+template <bool TERM, bool PIPE>
+__device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack& pk, const TilePixel& p,
+                                                const float4* __restrict__ record,
+                                                const uint32_t* __restrict__ pidx, uint32_t lo, uint32_t hi,
+                                                PixelState& s, float4* __restrict__ ckpt) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t end = p.start + hi;
+    auto batch_len = [end](uint32_t b) { return b < end ? min((uint32_t)kBatch, end - b) : 0u; };
+    uint32_t b0 = p.start + lo;
+    // PIPE also prefetches from global memory: the records of the next batch and the
+    // particle indices of the one after are loaded while the current batch is walked
+    EntryLoad cur{}, nxt{};
+    uint32_t g_next = 0xFFFFFFFFu;
+    if (PIPE) {
+        cur = load_entry(record, batch_pidx(pidx, b0, batch_len(b0)), pk.n_particles);
+        g_next = batch_pidx(pidx, b0 + kBatch, batch_len(b0 + kBatch));
+    }
+    for (; b0 < end; b0 += kBatch) {
+        if (__syncthreads_and(s.done)) break;
+        if (ckpt && b0 > p.start && (b0 - p.start) % kCkptChunk == 0)
+            ckpt[(size_t)ckpt_slot(p.start, (b0 - p.start) / kCkptChunk) * 256 + t] =
+                make_float4(s.T, s.cr, s.cg, s.cb);
+        uint32_t steps;
+        if (PIPE) {
+            nxt = load_entry(record, g_next, pk.n_particles);
+            g_next = batch_pidx(pidx, b0 + 2 * kBatch, batch_len(b0 + 2 * kBatch));
+            steps = stage_loaded(sb, cur, p.tx * kTile, p.ty * kTile, p.w_lim, p.h_lim);
+        } else {
+            steps = stage_batch_sub(sb, record, pidx, pk.n_particles, b0, batch_len(b0), p.tx * kTile,
+                                    p.ty * kTile, p.w_lim, p.h_lim);
+        }
+        const uint32_t pos0 = b0 - p.start + 1;   // 1-based list position of staged slot 0
+        const uint32_t len = sb.len[p.sbk];
+        uint32_t lastj = 0xFFFFFFFFu;
+        if (!PIPE) {
+            for (uint32_t k = 0; k < steps; k += 4) {
+                uint32_t j[4];
+                list4_sub(sb, p.sbk, k, len, j);
+                const float4 f0 = sb.fp[j[0]], f1 = sb.fp[j[1]], f2 = sb.fp[j[2]], f3 = sb.fp[j[3]];
+                const float4 c0 = sb.col[j[0]], c1 = sb.col[j[1]], c2 = sb.col[j[2]], c3 = sb.col[j[3]];
+                composite_entry<TERM>(f0, c0, p.px, p.py, j[0], s.T, s.cr, s.cg, s.cb, lastj, s.done);
+                composite_entry<TERM>(f1, c1, p.px, p.py, j[1], s.T, s.cr, s.cg, s.cb, lastj, s.done);
+                composite_entry<TERM>(f2, c2, p.px, p.py, j[2], s.T, s.cr, s.cg, s.cb, lastj, s.done);
+                composite_entry<TERM>(f3, c3, p.px, p.py, j[3], s.T, s.cr, s.cg, s.cb, lastj, s.done);
+                if (TERM && ballot64(!s.done) == 0) break;
+            }
+        } else {
+            uint32_t j[4], jn[4];
+            float4 f[4], c[4];
+            list4_sub(sb, p.sbk, 0, len, j);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                f[e] = sb.fp[j[e]];
+                c[e] = sb.col[j[e]];
+            }
+            list4_sub(sb, p.sbk, 4, len, jn);
+            for (uint32_t k = 0; k < steps; k += 4) {
+                float4 fn[4], cn[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    fn[e] = sb.fp[jn[e]];
+                    cn[e] = sb.col[jn[e]];
+                }
+                uint32_t jnn[4];
+                list4_sub(sb, p.sbk, k + 8, len, jnn);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    composite_entry<TERM>(f[e], c[e], p.px, p.py, j[e], s.T, s.cr, s.cg, s.cb, lastj, s.done);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    j[e] = jn[e];
+                    jn[e] = jnn[e];
+                    f[e] = fn[e];
+                    c[e] = cn[e];
+                }
+                if (TERM && ballot64(!s.done) == 0) break;
+            }
+        }
+        s.last = lastj != 0xFFFFFFFFu ? pos0 + lastj : s.last;
+        if (PIPE) cur = nxt;
+    }
+}
+
+__device__ __forceinline__ void write_pixel(const TilePixel& p, const PixelState& s, float bg_r, float bg_g,
+                                            float bg_b, float* __restrict__ image, float* __restrict__ T_final,
+                                            uint32_t* __restrict__ n_last) {
+    if (!p.inside) return;
+    const size_t hw = (size_t)p.width * p.height;
+    const size_t pix = (size_t)p.y * p.width + p.x;
+    float* img = image + (size_t)3 * p.pix_off;
+    img[pix] = fmaf(s.T, bg_r, s.cr);
+    img[hw + pix] = fmaf(s.T, bg_g, s.cg);
+    img[2 * hw + pix] = fmaf(s.T, bg_b, s.cb);
+    T_final[p.pix_off + pix] = s.T;
+    n_last[p.pix_off + pix] = s.last;
+}
+
+// Composites one whole tile (logical index within the launch). Contains __syncthreads.
+template <bool PIPE>
 __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& pk, uint32_t logical,
                                                const float4* __restrict__ record,
                                                const uint32_t* __restrict__ pidx,
                                                const uint32_t* __restrict__ ranges, float bg_r, float bg_g,
                                                float bg_b, float* __restrict__ image, float* __restrict__ T_final,
                                                uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
-    int vi, tx, ty;
-    locate_tile(pk, logical, vi, tx, ty);
-    const ViewDesc& vd = pk.v[vi];
-    const uint32_t t = threadIdx.x, w = t >> 6;
-    const int x = tx * kTile + sub_x(t), y = ty * kTile + sub_y(t);
-    const bool inside = x < vd.width && y < vd.height;
-    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
-    const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
-    const uint32_t start = ranges[2 * gt], end = min(ranges[2 * gt + 1], pk.n_entries_cap);
-    const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
-    const uint32_t sbk = 4 * w + ((t >> 4) & 3u);   // this lane's sub-block
-
-    float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-    uint32_t last = 0;
-    bool done = !inside;
-    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
-        if (__syncthreads_and(done)) break;
-        if (ckpt && b0 > start && (b0 - start) % kCkptChunk == 0)
-            ckpt[(size_t)ckpt_slot(start, (b0 - start) / kCkptChunk) * 256 + t] = make_float4(T, cr, cg, cb);
-        const uint32_t nb = min((uint32_t)kBatch, end - b0);
-        const uint32_t steps = stage_batch_sub(sb, record, pidx, pk.n_particles, b0, nb, tx * kTile, ty * kTile,
-                                               w_lim, h_lim);
-        const uint32_t pos0 = b0 - start + 1;   // 1-based list position of staged slot 0
-        uint32_t lastj = 0xFFFFFFFFu;
-        for (uint32_t k = 0; k < steps; k += 4) {
-            uint32_t j[4];
-            list4_sub(sb, sbk, k, j);
-            const float4 f0 = sb.fp[j[0]], f1 = sb.fp[j[1]], f2 = sb.fp[j[2]], f3 = sb.fp[j[3]];
-            const float4 c0 = sb.col[j[0]], c1 = sb.col[j[1]], c2 = sb.col[j[2]], c3 = sb.col[j[3]];
-            composite_entry(f0, c0, px, py, j[0], T, cr, cg, cb, lastj, done);
-            composite_entry(f1, c1, px, py, j[1], T, cr, cg, cb, lastj, done);
-            composite_entry(f2, c2, px, py, j[2], T, cr, cg, cb, lastj, done);
-            composite_entry(f3, c3, px, py, j[3], T, cr, cg, cb, lastj, done);
-            if (ballot64(!done) == 0) break;
-        }
-        last = lastj != 0xFFFFFFFFu ? pos0 + lastj : last;
-    }
-    if (!inside) return;
-    const size_t hw = (size_t)vd.width * vd.height;
-    const size_t pix = (size_t)y * vd.width + x;
-    float* img = image + (size_t)3 * vd.pix_off;
-    img[pix] = fmaf(T, bg_r, cr);
-    img[hw + pix] = fmaf(T, bg_g, cg);
-    img[2 * hw + pix] = fmaf(T, bg_b, cb);
-    T_final[vd.pix_off + pix] = T;
-    n_last[vd.pix_off + pix] = last;
+    const TilePixel p = tile_pixel(pk, logical, ranges);
+    PixelState s{1.0f, 0.0f, 0.0f, 0.0f, 0u, !p.inside};
+    composite_range<true, PIPE>(sb, pk, p, record, pidx, 0, p.len, s, ckpt);
+    write_pixel(p, s, bg_r, bg_g, bg_b, image, T_final, n_last);
 }
 
 // Register budget of the one-workgroup-per-tile compositing kernel: six waves per SIMD (at
@@ -93,7 +199,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWa
     uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
     __shared__ StagedSub sb;
     if (*status != kStatusOk) return;
-    composite_tile(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, ranges, bg_r, bg_g, bg_b, image,
+    composite_tile<false>(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, ranges, bg_r, bg_g, bg_b, image,
                    T_final, n_last, ckpt);
 }
 
@@ -115,7 +221,7 @@ __global__ void __launch_bounds__(256) composite_fwd_persistent_kernel(
         const uint32_t item = s_item;
         __syncthreads();
         if (item >= n_items) break;
-        composite_tile(sb, pk, order[item], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
+        composite_tile<true>(sb, pk, order[item], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
     }
 }
 

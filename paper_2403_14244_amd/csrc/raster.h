@@ -73,19 +73,39 @@ struct StagedSub {
     uint32_t len[16];           // padded list lengths (multiples of 4)
 };
 
-// Stages entries [first, first + n_in_batch) and builds the 16 sub-block lists. Returns the
-// number of list steps of the calling wave (the longest of its four rows' padded lists).
-// Contains __syncthreads.
-__device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4* __restrict__ record,
-                                                    const uint32_t* __restrict__ pidx, uint32_t n_particles,
-                                                    uint32_t first, uint32_t n_in_batch, int tile_x0, int tile_y0,
-                                                    float w_lim, float h_lim) {
+// One staged entry as loaded from global memory by its thread.
+struct EntryLoad {
+    bool ok;
+    float4 f, c;
+};
+
+// Particle index of this thread's entry of the batch at `first` (n_in_batch entries), or
+// none past the end.
+__device__ __forceinline__ uint32_t batch_pidx(const uint32_t* __restrict__ pidx, uint32_t first,
+                                               uint32_t n_in_batch) {
+    return threadIdx.x < n_in_batch ? pidx[first + threadIdx.x] : 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ EntryLoad load_entry(const float4* __restrict__ record, uint32_t g,
+                                                uint32_t n_particles) {
+    EntryLoad e{false, make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+    if (g < n_particles) {
+        e.ok = true;
+        e.f = record[2 * (size_t)g];
+        e.c = record[2 * (size_t)g + 1];
+    }
+    return e;
+}
+
+// Stages the loaded entries of a batch (one per thread) and builds the 16 sub-block lists.
+// Returns the number of list steps of the calling wave (the longest of its four rows'
+// padded lists). Contains __syncthreads.
+__device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad& e, int tile_x0, int tile_y0,
+                                                 float w_lim, float h_lim) {
     const uint32_t t = threadIdx.x, w = t >> 6;
     uint32_t mask = 0;
-    const uint32_t g = t < n_in_batch ? pidx[first + t] : 0xFFFFFFFFu;
-    if (g < n_particles) {
-        const float4 f = record[2 * (size_t)g];
-        const float4 c = record[2 * (size_t)g + 1];
+    if (e.ok) {
+        const float4 f = e.f, c = e.c;
         sb.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
         sb.col[t] = make_float4(c.x, c.y, c.z, f.w);
         const float r2 = c.w * c.w;
@@ -121,6 +141,7 @@ __device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4*
         const uint32_t n = sb.cnt[0][k] + sb.cnt[1][k] + sb.cnt[2][k] + sb.cnt[3][k];
         const uint32_t padded = (n + 3u) & ~3u;
         if (n + (t & 3u) < padded) sb.list[k][n + (t & 3u)] = (uint16_t)kDummy;
+        sb.list[k][padded + (t & 3u)] = (uint16_t)kDummy;   // four more: reads past the end
         if ((t & 3u) == 0) sb.len[k] = padded;
     }
     __syncthreads();
@@ -128,10 +149,20 @@ __device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4*
     return __builtin_amdgcn_readfirstlane(max(max(a, b), max(c, d)));
 }
 
-// Four consecutive entries of this lane's sub-block list from step k (dummies past its end).
-__device__ __forceinline__ void list4_sub(const StagedSub& sb, uint32_t sbk, uint32_t k, uint32_t j[4]) {
-    uint64_t q = 0x0100010001000100ull;   // four kDummy (256) indices
-    if (k < sb.len[sbk]) q = *reinterpret_cast<const uint64_t*>(&sb.list[sbk][k]);
+// Loads and stages entries [first, first + n_in_batch). Contains __syncthreads.
+__device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4* __restrict__ record,
+                                                    const uint32_t* __restrict__ pidx, uint32_t n_particles,
+                                                    uint32_t first, uint32_t n_in_batch, int tile_x0, int tile_y0,
+                                                    float w_lim, float h_lim) {
+    return stage_loaded(sb, load_entry(record, batch_pidx(pidx, first, n_in_batch), n_particles), tile_x0,
+                        tile_y0, w_lim, h_lim);
+}
+
+// Four consecutive entries of this lane's sub-block list (padded length `len`) from step k;
+// a step at or past the end reads the four dummies that follow the list.
+__device__ __forceinline__ void list4_sub(const StagedSub& sb, uint32_t sbk, uint32_t k, uint32_t len,
+                                          uint32_t j[4]) {
+    const uint64_t q = *reinterpret_cast<const uint64_t*>(&sb.list[sbk][min(k, len)]);
     j[0] = (uint32_t)q & 0xFFFFu;
     j[1] = (uint32_t)(q >> 16) & 0xFFFFu;
     j[2] = (uint32_t)(q >> 32) & 0xFFFFu;

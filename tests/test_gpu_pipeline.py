@@ -406,3 +406,42 @@ def test_render_bwd_chunked_long_lists(P, torch_cuda):
         r = _grad_check(a, ref[name], name)
         _grad_check(a, b.astype(np.float64), name, rel=1e-4, floor=1e-5)
         note(f"  {name}: max rel-to-max vs oracle {r:.2e}")
+
+
+@pytest.mark.parametrize("scale,opacity", [(0.06, (0.005, 0.03)), (0.25, (0.02, 0.08))])
+def test_persistent_forward_long_tiles(P, torch_cuda, scale, opacity):
+    """Tiles of thousands of entries: with faint particles no pixel stops, with denser ones
+    most pixels stop after their first thousand entries. The persistent kernel equals the
+    one-workgroup-per-tile kernel bitwise and both match the oracle."""
+    torch = torch_cuda
+    rng = np.random.default_rng(78)
+    base = S.uniform_cube_scene(6000, seed=78, log_scale_mean=math.log(scale), log_scale_std=0.3)
+    opac = rng.uniform(*opacity, base.pos.shape[1]).astype(np.float32)
+    sc = S.Scene(base.pos, base.scale, opac, base.color, 0)
+    cams = [S.look_at_camera((0.0, 0.0, 3.2), width=48, height=40)]
+    note(f"persistent forward, long tiles, opacity {opacity}")
+    R = P.Rasterizer()
+    g = P.GaussianScene.from_host(sc)
+    fp = R.project([g], cams)
+    b = R.bin_sort(fp, [g.n], cams)
+    lens = (b.ranges[:, 1] - b.ranges[:, 0]).cpu().numpy()
+    assert lens.max() > 3 * 1024
+    a = R.render_fwd(fp, [g.n], b, cams, (0.2, 0.1, 0.3))
+    c = R.render_fwd_persistent(fp, [g.n], b, cams, (0.2, 0.1, 0.3))
+    torch.cuda.synchronize()
+    for x, y in zip(a, c):
+        assert torch.equal(x, y)
+    nl_c = c[2].cpu().numpy()
+    ores = O.render_views([sc], cams, bg=(0.2, 0.1, 0.3), alpha_band=2.0 ** -12, term_band=2.0 ** -8)
+    # thousands of faint entries per pixel: many walks pass within the flag band of the
+    # 1/255 threshold somewhere, so only the unflagged pixels are held to 1e-4
+    d = np.abs(c[0].cpu().numpy().reshape(3, 40, 48).astype(np.float64) - ores[0][0]).max(axis=0)
+    flags = ores[3][0]
+    mx, nfl = float(d[~flags].max()), int(flags.sum())
+    assert mx <= IMG_TOL and (~flags).mean() > 0.5, (mx, nfl)
+    if flags.any():
+        assert d[flags].max() <= 0.01
+    stopped = c[1].cpu().numpy() < 1e-4
+    note(f"  max|d| {mx:.2e}, flagged {nfl}, n_last max {int(nl_c.max())}, stopped {stopped.mean():.2f}")
+    if scale > 0.1:
+        assert (nl_c[stopped] > 1024).mean() > 0.5   # most stops come after the first 1024 entries
