@@ -321,6 +321,8 @@ def main():
     Rt = P.Rasterizer(dev, headroom=1.1)
 
     def train_iter():
+        for q in params:
+            q.grad = None   # what an optimizer's zero_grad() does before each step
         img = P.IsoGSRender.apply(*params, gs.sh_degree, cam1, (0.0, 0.0, 0.0), Rt)
         loss = (img - target).abs().mean()
         loss.backward()

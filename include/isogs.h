@@ -29,7 +29,10 @@
  *     TX = ceil(W/16), TY = ceil(H/16)), pixels (sum of H_v * W_v).
  *   - Return codes: ISOGS_OK, or ISOGS_ERR_* below; isogs_last_error() then describes the
  *     failure. Data-dependent failures (entry capacity) cannot be known at launch time;
- *     they are reported through the device-side status word of isogs_bins.
+ *     they are reported through the device-side status word of isogs_bins. Every later
+ *     call that takes those bins reads the word on the device and, unless it is ISOGS_OK,
+ *     skips its work and leaves its outputs unwritten, so a caller may queue a whole
+ *     forward and backward pass before it reads the status.
  *   - Per-particle garbage (non-finite values, sigma <= 0, o < 1/255, depth <= near) is
  *     not an error: such a particle is culled (tile count 0).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).

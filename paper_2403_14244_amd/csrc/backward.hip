@@ -120,6 +120,7 @@ __device__ __forceinline__ void composite_bwd_tile(
     // this workgroup's positions [c_lo, c_hi) of the list
     const uint32_t c_lo = ckpt ? chunk * kCkptChunk : 0u;
     const uint32_t c_hi = ckpt ? min(c_lo + kCkptChunk, len) : len;
+    if (c_lo > c_hi) return;   // no such chunk (uniform over the workgroup)
 
     float T = 1.0f, dr = 0.0f, dg = 0.0f, db = 0.0f;
     float Sr = 0.0f, Sg = 0.0f, Sb = 0.0f;
@@ -255,15 +256,18 @@ __global__ void __launch_bounds__(64) fill_u32_kernel_b(uint32_t* __restrict__ p
 // (tile, chunk) pair per chunk, appended in any order.
 __global__ void __launch_bounds__(256) bwd_chunk_list_kernel(const uint32_t* __restrict__ ranges, uint32_t tile0,
                                                              uint32_t n_tiles, uint32_t cap,
+                                                             const int32_t* __restrict__ status,
                                                              uint32_t* __restrict__ heavy,
-                                                             uint32_t* __restrict__ heavy_count) {
+                                                             uint32_t* __restrict__ heavy_count,
+                                                             uint32_t heavy_max) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_tiles) return;
+    if (i >= n_tiles || *status != kStatusOk) return;
     const uint32_t s = ranges[2 * (tile0 + i)], e = min(ranges[2 * (tile0 + i) + 1], cap);
     const uint32_t len = e > s ? e - s : 0u;
     if (len <= kCkptChunk) return;
     const uint32_t nch = (len + kCkptChunk - 1) / kCkptChunk;
     const uint32_t base = atomicAdd(heavy_count, nch);
+    if (base + nch > heavy_max) return;   // cannot happen for ranges that partition the entries
     for (uint32_t c = 0; c < nch; ++c) {
         heavy[2 * (base + c)] = i;
         heavy[2 * (base + c) + 1] = c;
@@ -279,11 +283,12 @@ __global__ void __launch_bounds__(256) composite_bwd_persistent_kernel(
     float bg_r, float bg_g, float bg_b, const float* __restrict__ image, const float* __restrict__ dL_dimage,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_last, const float4* __restrict__ ckpt,
     float4* __restrict__ rec, const uint32_t* __restrict__ order, uint32_t n_items,
-    const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count, uint32_t* __restrict__ counter) {
+    const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count, uint32_t heavy_max,
+    uint32_t* __restrict__ counter) {
     __shared__ StagedBwd sb;
     __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
-    const uint32_t n_heavy = ckpt ? *heavy_count : 0u;
+    const uint32_t n_heavy = ckpt ? min(*heavy_count, heavy_max) : 0u;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
         __syncthreads();
@@ -293,6 +298,7 @@ __global__ void __launch_bounds__(256) composite_bwd_persistent_kernel(
         if (item < n_heavy) {
             logical = heavy[2 * item];
             chunk = heavy[2 * item + 1];
+            if (logical >= n_items) continue;
         } else {
             const uint32_t j = item - n_heavy;
             if (j >= n_items) break;
@@ -473,14 +479,14 @@ static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Workspace: gradient records (32 B per entry of capacity), the tile queue, the chunk
 // item count and the chunk items (two words each; at most capacity / kCkptChunk + tiles).
-static size_t bwd_heavy_words(uint64_t capacity, uint32_t tiles) {
-    return 2 * ((size_t)(capacity / kCkptChunk) + tiles + 1);
+static size_t bwd_heavy_items(uint64_t capacity, uint32_t tiles) {
+    return (size_t)(capacity / kCkptChunk) + tiles + 1;
 }
 
 size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv) {
     const uint32_t tiles = max_group_tiles(cams, nv);
     return round256((size_t)capacity * 32) + round256(tile_queue_words(tiles) * 4) + 256 +
-           bwd_heavy_words(capacity, tiles) * 4 + 256;
+           bwd_heavy_items(capacity, tiles) * 8 + 256;
 }
 
 int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
@@ -498,6 +504,7 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
     base += round256(tile_queue_words(max_tiles) * 4);
     uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base);
     uint32_t* heavy = reinterpret_cast<uint32_t*>(base + 256);
+    const uint32_t heavy_max = (uint32_t)bwd_heavy_items(bins->capacity, max_tiles);
     int32_t n_per_view[kMaxViews];
     int32_t n_all[4096];
     if (nv > 4096) return -1;
@@ -517,13 +524,14 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
         if (ckpt) {
             hipLaunchKernelGGL(fill_u32_kernel_b, dim3(1), dim3(64), 0, stream, heavy_count, 1u);
             hipLaunchKernelGGL(bwd_chunk_list_kernel, dim3((blocks + 255) / 256), dim3(256), 0, stream, bins->ranges,
-                               tile0, blocks, pk.n_entries_cap, heavy, heavy_count);
+                               tile0, blocks, pk.n_entries_cap, bins->status, heavy, heavy_count, heavy_max);
         }
         const unsigned grid = std::min<unsigned>(blocks, (unsigned)grid_max);
         hipLaunchKernelGGL(composite_bwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->offsets, bins->ranges,
                            bins->status, bg[0], bg[1], bg[2], image, dL_dimage, T_final, n_last,
-                           reinterpret_cast<const float4*>(ckpt), rec, order, blocks, heavy, heavy_count, order - 1);
+                           reinterpret_cast<const float4*>(ckpt), rec, order, blocks, heavy, heavy_count, heavy_max,
+                           order - 1);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     // 2. per scene: reduce records over its views (in view order) and chain to parameters

@@ -64,6 +64,10 @@ class GaussianScene:
         s.sh_degree = self.sh_degree
         return s
 
+    def empty_like(self) -> "GaussianScene":
+        return GaussianScene(torch.empty_like(self.pos), torch.empty_like(self.scale),
+                             torch.empty_like(self.opacity), torch.empty_like(self.color), self.sh_degree)
+
     def zeros_like(self) -> "GaussianScene":
         return GaussianScene(torch.zeros_like(self.pos), torch.zeros_like(self.scale),
                              torch.zeros_like(self.opacity), torch.zeros_like(self.color), self.sh_degree)
@@ -240,7 +244,7 @@ class Rasterizer:
             uniq = {}
             for s in scenes:
                 if s.pos.data_ptr() not in uniq:
-                    uniq[s.pos.data_ptr()] = s.zeros_like()
+                    uniq[s.pos.data_ptr()] = s.empty_like()   # the library overwrites every output
             grads = [uniq[s.pos.data_ptr()] for s in scenes]
         sc = (A.Scene * len(scenes))(*[s.abi() for s in scenes])
         gs = (A.Scene * len(scenes))(*[g.abi() for g in grads])
@@ -349,10 +353,12 @@ class IsoGSRender(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         st = ctx.st
-        # the forward's capacity status, read here so that the forward never waits
-        ctx.rasterizer.verify(st)
         scenes = [ctx.scene] * len(ctx.cams)
         g = ctx.rasterizer.render_bwd(scenes, ctx.cams, st["fp"], st["bins"], ctx.bg,
                                       grad_out.contiguous().reshape(-1), st["T"], st["n_last"],
                                       image=st["image"], ckpt=st["ckpt"])[0]
+        # the forward's capacity status is read only now, behind the queued backward, so
+        # that neither pass waits for the device (on an overflow every kernel after the
+        # sort skipped its work and this raises)
+        ctx.rasterizer.verify(st)
         return g.pos, g.scale, g.opacity, g.color, None, None, None, None
