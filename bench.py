@@ -227,7 +227,7 @@ def main():
                 ev[1].record(s)
                 bins = Rk.bin_sort(fp, [gs.n] * len(bc), bc, check=check)
                 ev[2].record(s)
-                Rk.render_fwd(fp, [gs.n] * len(bc), bins, bc)
+                Rk.render_fwd_ordered(fp, [gs.n] * len(bc), bins, bc)
                 ev[3].record(s)
             stage["project"].append((ev[0], ev[1]))
             stage["bin_sort"].append((ev[1], ev[2]))
@@ -249,7 +249,7 @@ def main():
         torch.cuda.synchronize()
         fp = R.project([gs] * len(batches[0]), batches[0])
         bins = R.bin_sort(fp, [gs.n] * len(batches[0]), batches[0], check=True)
-        R.render_fwd(fp, [gs.n] * len(batches[0]), bins, batches[0])
+        R.render_fwd_ordered(fp, [gs.n] * len(batches[0]), bins, batches[0])
         torch.cuda.synchronize()
         print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES, "views": len(batches[0]),
                           "entries": bins.n_entries(), "sources_digest": composite_sources_digest()}))
@@ -288,7 +288,7 @@ def main():
         bins = R.bin_sort(fp, [gs.n] * len(bc), bc, check=True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        _, T, n_last = R.render_fwd(fp, [gs.n] * len(bc), bins, bc)
+        _, T, n_last = R.render_fwd_ordered(fp, [gs.n] * len(bc), bins, bc)
         e1.record()
         iso.append((e0, e1))
         pairs += walk_pairs(T, n_last, bins.ranges, bc)
@@ -338,13 +338,13 @@ def main():
         torch.cuda.synchronize()
         return args.train_iters / (time.perf_counter() - t1)
 
-    # compositing of a single view is tail-bound by its longest tiles: the persistent,
-    # longest-first kernel is measured beside the one-workgroup-per-tile kernel
+    # compositing of a single view is tail-bound by its longest tiles: the longest-first
+    # launch is measured beside the spatial one-workgroup-per-tile launch
     it_by_kernel = {}
-    for persistent in (False, True):
-        Rt.persistent_fwd = persistent
-        it_by_kernel["persistent" if persistent else "per_tile"] = round(train_rate(), 2)
-    it_s = it_by_kernel["persistent"]   # the rasterizer's default for render()
+    for ordered in (False, True):
+        Rt.ordered_fwd = ordered
+        it_by_kernel["ordered" if ordered else "per_tile"] = round(train_rate(), 2)
+    it_s = it_by_kernel["ordered"]   # the rasterizer's default for render()
     log(f"fwd+bwd: {it_s:.1f} it/s ({it_by_kernel})")
 
     serving = None

@@ -180,18 +180,19 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
                      const float* bg, float* image, float* T_final, uint32_t* n_last,
                      float* checkpoints, void* stream);
 
-/* Same outputs as isogs_render_fwd (bitwise), computed by a persistent grid - as many
- * workgroups as the GPU holds at once - that takes tiles from a global queue ordered
- * longest entry list first, so that the few very long tiles of skewed scenes start early
- * instead of trailing the launch. Used by the serving loop for batches of mixed-resolution
- * requests.
+/* Same outputs as isogs_render_fwd (bitwise), with the tiles dispatched longest entry list
+ * first: a queue of the tiles sorted by list length is built on the device and workgroup b
+ * composites the tile at queue position b, so that the few very long tiles of skewed scenes
+ * start first instead of trailing the launch. Launches of few tiles (at most 24576 per group
+ * of 16 views) use a software-pipelined walk that shortens the longest tiles; larger ones a
+ * compact walk that keeps more workgroups resident. Used by the training and serving paths.
  *   ws, ws_bytes  workspace (query with ws == NULL): the queue, 4 bytes per tile of the
  *                 largest group of 16 views, plus bookkeeping
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
-int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view,
-                                const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
-                                const float* bg, float* image, float* T_final, uint32_t* n_last,
-                                float* checkpoints, void* ws, size_t* ws_bytes, void* stream);
+int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view,
+                             const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
+                             const float* bg, float* image, float* T_final, uint32_t* n_last,
+                             float* checkpoints, void* ws, size_t* ws_bytes, void* stream);
 
 /* Gradients of a scalar loss L with respect to the particle parameters, given dL/dimage.
  * Walks each pixel's entries in reverse from n_last, recovering the transmittance before
@@ -211,8 +212,10 @@ int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_pe
  *   ws, ws_bytes   workspace (query with ws == NULL, 256-byte aligned): 32 bytes per
  *                  entry of capacity - each entry's gradient record is stored at its emit
  *                  position, so a particle's records are contiguous - plus a tile queue of
- *                  4 bytes per tile of the largest group of 16 views (tiles are walked
- *                  longest entry list first by a persistent grid)
+ *                  4 bytes per tile of the largest group of 16 views (one workgroup per
+ *                  chunk of a long tile, then per tile, longest entry list first), and
+ *                  the chunk list, 8 bytes per ISOGS_CKPT_CHUNK entries of capacity and
+ *                  per tile
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
 int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t n_views,
                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,

@@ -17,7 +17,7 @@ ISOGS_ERR_CAPACITY = -2
 ISOGS_ERR_WORKSPACE = -3
 ISOGS_ERR_DEVICE = -4
 
-EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_persistent",
+EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
             "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_last_error", "isogs_version")
 
 
@@ -68,14 +68,14 @@ def lib():
                                      P(ctypes.c_size_t), vp]
         L.isogs_render_fwd.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera), ctypes.c_int32,
                                        P(ctypes.c_float), vp, vp, vp, vp, vp]
-        L.isogs_render_fwd_persistent.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera),
+        L.isogs_render_fwd_ordered.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera),
                                                   ctypes.c_int32, P(ctypes.c_float), vp, vp, vp, vp, vp,
                                                   P(ctypes.c_size_t), vp]
         L.isogs_render_bwd.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), P(Bins),
                                        P(ctypes.c_float), vp, vp, vp, vp, vp, P(Scene), vp, P(ctypes.c_size_t), vp]
         L.isogs_checkpoint_bytes.argtypes = [ctypes.c_uint64]
         L.isogs_checkpoint_bytes.restype = ctypes.c_size_t
-        for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_persistent",
+        for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
                      "isogs_render_bwd"):
             getattr(L, name).restype = ctypes.c_int
         L.isogs_last_error.restype = ctypes.c_char_p

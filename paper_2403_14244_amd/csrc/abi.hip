@@ -168,17 +168,17 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, con
     return ISOGS_OK;
 }
 
-int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
-                                const isogs_camera* cams, int32_t n_views, const float* bg, float* image,
-                                float* T_final, uint32_t* n_last, float* checkpoints, void* ws, size_t* ws_bytes,
-                                void* stream) {
+int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                             const isogs_camera* cams, int32_t n_views, const float* bg, float* image,
+                             float* T_final, uint32_t* n_last, float* checkpoints, void* ws, size_t* ws_bytes,
+                             void* stream) {
     g_error[0] = 0;
     int rc;
     if ((rc = check_views(n_views))) return rc;
     if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
     if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
     if ((rc = check_cameras(cams, n_views))) return rc;
-    const size_t need = isogs::render_fwd_persistent_ws(cams, n_views);
+    const size_t need = isogs::render_fwd_ordered_ws(cams, n_views);
     if (!ws) {
         *ws_bytes = need;
         return ISOGS_OK;
@@ -191,9 +191,9 @@ int isogs_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_pe
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
-    if (isogs::launch_render_fwd_persistent(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
-                                            checkpoints, ws, (hipStream_t)stream))
-        return device_fail("isogs_render_fwd_persistent");
+    if (isogs::launch_render_fwd_ordered(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
+                                         checkpoints, ws, (hipStream_t)stream))
+        return device_fail("isogs_render_fwd_ordered");
     return ISOGS_OK;
 }
 

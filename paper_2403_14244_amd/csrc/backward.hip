@@ -274,46 +274,38 @@ __global__ void __launch_bounds__(256) bwd_chunk_list_kernel(const uint32_t* __r
     }
 }
 
-// A resident grid takes work items from one counter: first the chunks of the long tiles
-// (when checkpoints are given), then the tiles of the longest-list-first queue, skipping
-// the long ones. Every workgroup leaves once the counter passes the last item.
-__global__ void __launch_bounds__(256) composite_bwd_persistent_kernel(
+// One workgroup per work item, in dispatch order: workgroups [0, heavy_slots) take the
+// chunks of the long tiles (when checkpoints are given; a workgroup past the device-side
+// count leaves at once), the others the tiles of the longest-list-first queue, skipping
+// the long ones.
+__global__ void __launch_bounds__(256) composite_bwd_ordered_kernel(
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
     float bg_r, float bg_g, float bg_b, const float* __restrict__ image, const float* __restrict__ dL_dimage,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_last, const float4* __restrict__ ckpt,
     float4* __restrict__ rec, const uint32_t* __restrict__ order, uint32_t n_items,
-    const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count, uint32_t heavy_max,
-    uint32_t* __restrict__ counter) {
+    const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count, uint32_t heavy_slots) {
     __shared__ StagedBwd sb;
-    __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
-    const uint32_t n_heavy = ckpt ? min(*heavy_count, heavy_max) : 0u;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t item = s_item;
-        __syncthreads();
-        uint32_t logical, chunk = 0;
-        if (item < n_heavy) {
-            logical = heavy[2 * item];
-            chunk = heavy[2 * item + 1];
-            if (logical >= n_items) continue;
-        } else {
-            const uint32_t j = item - n_heavy;
-            if (j >= n_items) break;
-            logical = order[j];
-            if (ckpt) {
-                int vi, tx, ty;
-                locate_tile(pk, logical, vi, tx, ty);
-                const uint32_t gt = pk.v[vi].tile_base + (uint32_t)(ty * pk.v[vi].tiles_x + tx);
-                const uint32_t s = ranges[2 * gt], e = min(ranges[2 * gt + 1], pk.n_entries_cap);
-                if (e > s && e - s > kCkptChunk) continue;   // walked as chunks above
-            }
+    const uint32_t b = blockIdx.x;
+    uint32_t logical, chunk = 0;
+    if (b < heavy_slots) {
+        if (b >= min(*heavy_count, heavy_slots)) return;
+        logical = heavy[2 * b];
+        chunk = heavy[2 * b + 1];
+        if (logical >= n_items) return;
+    } else {
+        logical = order[b - heavy_slots];
+        if (ckpt) {
+            int vi, tx, ty;
+            locate_tile(pk, logical, vi, tx, ty);
+            const uint32_t gt = pk.v[vi].tile_base + (uint32_t)(ty * pk.v[vi].tiles_x + tx);
+            const uint32_t s = ranges[2 * gt], e = min(ranges[2 * gt + 1], pk.n_entries_cap);
+            if (e > s && e - s > kCkptChunk) return;   // walked as chunks
         }
-        composite_bwd_tile(sb, pk, logical, chunk, record, pidx, offsets, ranges, bg_r, bg_g, bg_b, image,
-                           dL_dimage, T_final, n_last, ckpt, rec);
     }
+    composite_bwd_tile(sb, pk, logical, chunk, record, pidx, offsets, ranges, bg_r, bg_g, bg_b, image, dL_dimage,
+                       T_final, n_last, ckpt, rec);
 }
 
 // Gradient of each real SH basis polynomial (the forms used in the forward colour
@@ -493,9 +485,6 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
                       const isogs_projected* proj, const isogs_bins* bins, const float* bg,
                       const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
                       const float* ckpt, const isogs_scene* grads, void* ws, hipStream_t stream) {
-    static int grid_max = 0;
-    if (!grid_max) grid_max = resident_blocks(reinterpret_cast<const void*>(composite_bwd_persistent_kernel), 256);
-    if (!grid_max) return -1;
     const uint32_t max_tiles = max_group_tiles(cams, nv);
     char* base = static_cast<char*>(ws);
     float4* rec = reinterpret_cast<float4*>(base);
@@ -505,6 +494,10 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
     uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base);
     uint32_t* heavy = reinterpret_cast<uint32_t*>(base + 256);
     const uint32_t heavy_max = (uint32_t)bwd_heavy_items(bins->capacity, max_tiles);
+    // a tile longer than one chunk has fewer than 2 len / kCkptChunk chunks, so the chunks
+    // of ranges that partition the entries number fewer than 2 capacity / kCkptChunk
+    const uint32_t heavy_slots =
+        ckpt ? (uint32_t)std::min<uint64_t>(heavy_max, 2 * (bins->capacity / kCkptChunk) + 2) : 0u;
     int32_t n_per_view[kMaxViews];
     int32_t n_all[4096];
     if (nv > 4096) return -1;
@@ -526,12 +519,11 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
             hipLaunchKernelGGL(bwd_chunk_list_kernel, dim3((blocks + 255) / 256), dim3(256), 0, stream, bins->ranges,
                                tile0, blocks, pk.n_entries_cap, bins->status, heavy, heavy_count, heavy_max);
         }
-        const unsigned grid = std::min<unsigned>(blocks, (unsigned)grid_max);
-        hipLaunchKernelGGL(composite_bwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
+        hipLaunchKernelGGL(composite_bwd_ordered_kernel, dim3(heavy_slots + blocks), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->offsets, bins->ranges,
                            bins->status, bg[0], bg[1], bg[2], image, dL_dimage, T_final, n_last,
-                           reinterpret_cast<const float4*>(ckpt), rec, order, blocks, heavy, heavy_count, heavy_max,
-                           order - 1);
+                           reinterpret_cast<const float4*>(ckpt), rec, order, blocks, heavy, heavy_count,
+                           heavy_slots);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     // 2. per scene: reduce records over its views (in view order) and chain to parameters

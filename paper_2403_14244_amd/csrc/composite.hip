@@ -5,15 +5,14 @@
 
 namespace isogs {
 
-// Composites one entry (staged slot j) into a pixel's running state (branch-free; the
-// dummy pad record has log2(o) = -inf, so alpha = 0 and it changes nothing). T loses the
-// weight it gives away, T - alpha T; `lastj` keeps the slot of the last entry used in the
-// current batch (slots only increase along a list). TERM: the pixel stops after the entry
-// that takes T below kTMin.
+// Composites one staged entry into a pixel's running state (branch-free; the dummy pad
+// record has log2(o) = -inf, so alpha = 0 and it changes nothing). T loses the weight it
+// gives away, T - alpha T; `lastj` keeps the staged slot (carried in c.w) of the last entry
+// used in the current batch (slots only increase along a list). TERM: the pixel stops
+// after the entry that takes T below kTMin.
 template <bool TERM>
-__device__ __forceinline__ void composite_entry(const float4& f, const float4& c, float px, float py, uint32_t j,
-                                                float& T, float& cr, float& cg, float& cb, uint32_t& lastj,
-                                                bool& done) {
+__device__ __forceinline__ void composite_entry(const float4& f, const float4& c, float px, float py, float& T,
+                                                float& cr, float& cg, float& cb, uint32_t& lastj, bool& done) {
     float g;
     float a = entry_alpha(px - f.x, py - f.y, f.z, f.w, g);
     const bool use = (a >= kAlphaMin) && !done;
@@ -23,8 +22,24 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
     cg = fmaf(c.y, wgt, cg);
     cb = fmaf(c.z, wgt, cb);
     T = T - wgt;
-    lastj = use ? j : lastj;
+    lastj = use ? __float_as_uint(c.w) : lastj;
     if (TERM) done = done || (T < kTMin);
+}
+
+// The four entries of one list step: offsets -> staged records.
+struct Step4 {
+    float4 f[4], c[4];
+};
+
+__device__ __forceinline__ void load_step(const StagedSub& sb, const uint4& o, Step4& st) {
+    st.f[0] = staged_fp(sb, o.x);
+    st.f[1] = staged_fp(sb, o.y);
+    st.f[2] = staged_fp(sb, o.z);
+    st.f[3] = staged_fp(sb, o.w);
+    st.c[0] = staged_col(sb, o.x);
+    st.c[1] = staged_col(sb, o.y);
+    st.c[2] = staged_col(sb, o.z);
+    st.c[3] = staged_col(sb, o.w);
 }
 
 // A lane's pixel in a tile, and the pixel's compositing state.
@@ -110,51 +125,40 @@ __device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack&
         const uint32_t pos0 = b0 - p.start + 1;   // 1-based list position of staged slot 0
         const uint32_t len = sb.len[p.sbk];
         uint32_t lastj = 0xFFFFFFFFu;
+        auto composite_step = [&](const Step4& st) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                composite_entry<TERM>(st.f[e], st.c[e], p.px, p.py, s.T, s.cr, s.cg, s.cb, lastj, s.done);
+        };
         if (!PIPE) {
             for (uint32_t k = 0; k < steps; k += 4) {
-                uint32_t j[4];
-                list4_sub(sb, p.sbk, k, len, j);
-                const float4 f0 = sb.fp[j[0]], f1 = sb.fp[j[1]], f2 = sb.fp[j[2]], f3 = sb.fp[j[3]];
-                const float4 c0 = sb.col[j[0]], c1 = sb.col[j[1]], c2 = sb.col[j[2]], c3 = sb.col[j[3]];
-                composite_entry<TERM>(f0, c0, p.px, p.py, j[0], s.T, s.cr, s.cg, s.cb, lastj, s.done);
-                composite_entry<TERM>(f1, c1, p.px, p.py, j[1], s.T, s.cr, s.cg, s.cb, lastj, s.done);
-                composite_entry<TERM>(f2, c2, p.px, p.py, j[2], s.T, s.cr, s.cg, s.cb, lastj, s.done);
-                composite_entry<TERM>(f3, c3, p.px, p.py, j[3], s.T, s.cr, s.cg, s.cb, lastj, s.done);
+                Step4 st;
+                load_step(sb, list4_sub(sb, p.sbk, k, len), st);
+                composite_step(st);
                 if (TERM && ballot64(!s.done) == 0) break;
             }
         } else {
-            uint32_t j[4], jn[4];
-            float4 f[4], c[4];
-            list4_sub(sb, p.sbk, 0, len, j);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                f[e] = sb.fp[j[e]];
-                c[e] = sb.col[j[e]];
-            }
-            list4_sub(sb, p.sbk, 4, len, jn);
-            for (uint32_t k = 0; k < steps; k += 4) {
-                float4 fn[4], cn[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    fn[e] = sb.fp[jn[e]];
-                    cn[e] = sb.col[jn[e]];
-                }
-                uint32_t jnn[4];
-                list4_sub(sb, p.sbk, k + 8, len, jnn);
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    composite_entry<TERM>(f[e], c[e], p.px, p.py, j[e], s.T, s.cr, s.cg, s.cb, lastj, s.done);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    j[e] = jn[e];
-                    jn[e] = jnn[e];
-                    f[e] = fn[e];
-                    c[e] = cn[e];
-                }
+            // two register sets in turn, unrolled so that neither is copied: while one
+            // step is composited, the records of the next and the list words of the one
+            // after are in flight (the barriers keep the reads ahead of the arithmetic)
+            Step4 sa, sc;
+            uint4 o = list4_sub(sb, p.sbk, 0, len);
+            load_step(sb, o, sa);
+            o = list4_sub(sb, p.sbk, 4, len);
+            for (uint32_t k = 0; k < steps; k += 8) {
+                load_step(sb, o, sc);
+                o = list4_sub(sb, p.sbk, k + 8, len);
+                __builtin_amdgcn_sched_barrier(0);
+                composite_step(sa);
+                if (TERM && ballot64(!s.done) == 0) break;
+                load_step(sb, o, sa);
+                o = list4_sub(sb, p.sbk, k + 12, len);
+                __builtin_amdgcn_sched_barrier(0);
+                composite_step(sc);   // past the end of the lists: dummies only
                 if (TERM && ballot64(!s.done) == 0) break;
             }
         }
-        s.last = lastj != 0xFFFFFFFFu ? pos0 + lastj : s.last;
+        if (lastj != 0xFFFFFFFFu) s.last = pos0 + lastj;
         if (PIPE) cur = nxt;
     }
 }
@@ -203,27 +207,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWa
                    T_final, n_last, ckpt);
 }
 
-// Persistent variant: a fixed grid of workgroups takes tiles from a global queue ordered
-// longest list first, so a few very long tiles start early instead of trailing the launch.
-// Every workgroup leaves once the counter passes the last item.
-__global__ void __launch_bounds__(256) composite_fwd_persistent_kernel(
+// Longest list first: one workgroup per tile, the tiles taken in the order of a queue
+// sorted by list length, so that the dispatcher starts the long tiles of skewed scenes
+// first instead of leaving them to trail the launch. Two builds of the walk: with many
+// tiles the launch is throughput-bound and the compact one (six waves per SIMD) is faster;
+// with few, it is bound by its longest tiles and the software-pipelined one is.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWavesPerSimd)))
+composite_fwd_ordered_kernel(const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
+                             const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r,
+                             float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
+                             uint32_t* __restrict__ n_last, float4* __restrict__ ckpt,
+                             const uint32_t* __restrict__ order) {
+    __shared__ StagedSub sb;
+    if (*status != kStatusOk) return;
+    composite_tile<false>(sb, pk, order[blockIdx.x], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last,
+                          ckpt);
+}
+
+__global__ void __launch_bounds__(256) composite_fwd_ordered_pipe_kernel(
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
     float* __restrict__ image, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
-    float4* __restrict__ ckpt, const uint32_t* __restrict__ order, uint32_t n_items,
-    uint32_t* __restrict__ counter) {
+    float4* __restrict__ ckpt, const uint32_t* __restrict__ order) {
     __shared__ StagedSub sb;
-    __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t item = s_item;
-        __syncthreads();
-        if (item >= n_items) break;
-        composite_tile<true>(sb, pk, order[item], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
-    }
+    composite_tile<true>(sb, pk, order[blockIdx.x], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last,
+                         ckpt);
 }
+
+// Launches of at most this many tiles use the pipelined walk (measured crossover on the
+// 1M-particle 1080p views: between two and four views, 16320 and 32640 tiles).
+constexpr uint32_t kPipeTileLimit = 24576;
 
 __global__ void __launch_bounds__(128) fill_u32_kernel_c(uint32_t* __restrict__ p, uint32_t n) {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
@@ -296,7 +310,7 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
     return 0;
 }
 
-size_t render_fwd_persistent_ws(const isogs_camera* cams, int32_t nv) {
+size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv) {
     return tile_queue_words(max_group_tiles(cams, nv)) * 4 + 256;
 }
 
@@ -335,12 +349,9 @@ int resident_blocks(const void* kernel, int threads) {
     return cus * per_cu;
 }
 
-int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
-                                 const isogs_camera* cams, int32_t nv, const float* bg, float* image,
-                                 float* T_final, uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream) {
-    static int grid_max = 0;
-    if (!grid_max) grid_max = resident_blocks(reinterpret_cast<const void*>(composite_fwd_persistent_kernel), 256);
-    if (!grid_max) return -1;
+int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                              const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
+                              uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream) {
     uint32_t* q = static_cast<uint32_t*>(ws);
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
@@ -350,12 +361,15 @@ int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_p
         fill_render_pack(pk, cams, n_per_view, v0, nv, p_off, tile_base, pix_off, blocks);
         set_render_limits(pk, n_per_view, nv, bins->capacity);
         if (!blocks) continue;
-        uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
-        const unsigned grid = std::min<unsigned>(blocks, (unsigned)grid_max);
-        hipLaunchKernelGGL(composite_fwd_persistent_kernel, dim3(grid), dim3(256), 0, stream, pk,
-                           reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
-                           bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order,
-                           blocks, order - 1);
+        const uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
+        if (blocks <= kPipeTileLimit)
+            hipLaunchKernelGGL(composite_fwd_ordered_pipe_kernel, dim3(blocks), dim3(256), 0, stream, pk,
+                               reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
+                               bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order);
+        else
+            hipLaunchKernelGGL(composite_fwd_ordered_kernel, dim3(blocks), dim3(256), 0, stream, pk,
+                               reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
+                               bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     return 0;

@@ -32,7 +32,7 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
                       const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
                       uint32_t* n_last, float* ckpt, hipStream_t stream);
 
-size_t render_fwd_persistent_ws(const isogs_camera* cams, int32_t nv);
+size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv);
 
 // Longest-list-first tile queue of one launch group: words needed, the largest group, the
 // launch (returns the order array; the queue counter is the word before it).
@@ -45,9 +45,9 @@ int resident_blocks(const void* kernel, int threads);
 
 size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv);
 
-int launch_render_fwd_persistent(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
-                                 const isogs_camera* cams, int32_t nv, const float* bg, float* image,
-                                 float* T_final, uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream);
+int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                              const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
+                              uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream);
 
 int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
                       const isogs_projected* proj, const isogs_bins* bins, const float* bg,

@@ -65,10 +65,12 @@ __device__ __forceinline__ bool sub_block_touched(float u, float v, float r2, in
     return x_lo <= w_lim && y_lo <= h_lim && dx * dx + dy * dy <= r2;
 }
 
+constexpr uint32_t kSlotBytes = 16;   // one staged float4
+
 struct StagedSub {
     float4 fp[kBatch + 1];      // {u, v, q = log2(e)/s^2, log2(o)}
-    float4 col[kBatch + 1];     // {r, g, b, o}
-    uint16_t list[16][kBatch + 4];
+    float4 col[kBatch + 1];     // {r, g, b, slot bits}
+    uint32_t list[16][kBatch + 4];   // byte offsets (16 x staged slot) into fp and col
     uint32_t cnt[4][16];        // [loader wave][sub-block]
     uint32_t len[16];           // padded list lengths (multiples of 4)
 };
@@ -107,7 +109,7 @@ __device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad&
     if (e.ok) {
         const float4 f = e.f, c = e.c;
         sb.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
-        sb.col[t] = make_float4(c.x, c.y, c.z, f.w);
+        sb.col[t] = make_float4(c.x, c.y, c.z, __uint_as_float(t));   // w: the slot itself
         const float r2 = c.w * c.w;
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -115,7 +117,7 @@ __device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad&
     }
     if (t == 0) {
         sb.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
-        sb.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        sb.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float((uint32_t)kDummy));
     }
     uint64_t bal[16];
 #pragma unroll
@@ -132,7 +134,7 @@ __device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad&
         if ((mask >> k) & 1u) {
             uint32_t pos = rank_below(bal[k]);
             pos += (w > 0 ? sb.cnt[0][k] : 0u) + (w > 1 ? sb.cnt[1][k] : 0u) + (w > 2 ? sb.cnt[2][k] : 0u);
-            sb.list[k][pos] = (uint16_t)t;
+            sb.list[k][pos] = t * kSlotBytes;
         }
     }
     if (t < 64) {
@@ -140,8 +142,8 @@ __device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad&
         const uint32_t k = t >> 2;
         const uint32_t n = sb.cnt[0][k] + sb.cnt[1][k] + sb.cnt[2][k] + sb.cnt[3][k];
         const uint32_t padded = (n + 3u) & ~3u;
-        if (n + (t & 3u) < padded) sb.list[k][n + (t & 3u)] = (uint16_t)kDummy;
-        sb.list[k][padded + (t & 3u)] = (uint16_t)kDummy;   // four more: reads past the end
+        if (n + (t & 3u) < padded) sb.list[k][n + (t & 3u)] = kDummy * kSlotBytes;
+        sb.list[k][padded + (t & 3u)] = kDummy * kSlotBytes;   // four more: reads past the end
         if ((t & 3u) == 0) sb.len[k] = padded;
     }
     __syncthreads();
@@ -158,15 +160,18 @@ __device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4*
                         tile_y0, w_lim, h_lim);
 }
 
-// Four consecutive entries of this lane's sub-block list (padded length `len`) from step k;
-// a step at or past the end reads the four dummies that follow the list.
-__device__ __forceinline__ void list4_sub(const StagedSub& sb, uint32_t sbk, uint32_t k, uint32_t len,
-                                          uint32_t j[4]) {
-    const uint64_t q = *reinterpret_cast<const uint64_t*>(&sb.list[sbk][min(k, len)]);
-    j[0] = (uint32_t)q & 0xFFFFu;
-    j[1] = (uint32_t)(q >> 16) & 0xFFFFu;
-    j[2] = (uint32_t)(q >> 32) & 0xFFFFu;
-    j[3] = (uint32_t)(q >> 48);
+// Byte offsets of four consecutive entries of this lane's sub-block list (padded length
+// `len`) from step k; a step at or past the end reads the four dummies that follow the list.
+__device__ __forceinline__ uint4 list4_sub(const StagedSub& sb, uint32_t sbk, uint32_t k, uint32_t len) {
+    return *reinterpret_cast<const uint4*>(&sb.list[sbk][min(k, len)]);
+}
+
+// Staged record and colour of the entry at byte offset `off`.
+__device__ __forceinline__ float4 staged_fp(const StagedSub& sb, uint32_t off) {
+    return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sb.fp) + off);
+}
+__device__ __forceinline__ float4 staged_col(const StagedSub& sb, uint32_t off) {
+    return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sb.col) + off);
 }
 
 struct RenderPack {

@@ -144,7 +144,7 @@ class Rasterizer:
         self.device = torch.device(device)
         self.headroom = headroom
         self.capacity = 0
-        self.persistent_fwd = True
+        self.ordered_fwd = True
         self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
 
     def _workspace(self, nbytes):
@@ -208,9 +208,9 @@ class Rasterizer:
                                          _p(ckpt), _stream()))
         return image, T, n_last
 
-    def render_fwd_persistent(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0),
-                              out=None, ckpt=None):
-        """render_fwd through the persistent, longest-list-first kernel (same result).
+    def render_fwd_ordered(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0),
+                           out=None, ckpt=None):
+        """render_fwd with the tiles dispatched longest entry list first (same result).
         `out` optionally supplies (image, T_final, n_last) buffers."""
         pix = sum(int(c.width) * int(c.height) for c in cams)
         if out is None:
@@ -224,10 +224,10 @@ class Rasterizer:
         need = ctypes.c_size_t(0)
         args = (ctypes.byref(fp.abi()), npv, ctypes.byref(bins.abi()), carr, len(cams), bgc, _p(image), _p(T),
                 _p(n_last), _p(ckpt))
-        A.check(A.lib().isogs_render_fwd_persistent(*args, None, ctypes.byref(need), _stream()))
+        A.check(A.lib().isogs_render_fwd_ordered(*args, None, ctypes.byref(need), _stream()))
         ws = self._workspace_q(need.value)
         have = ctypes.c_size_t(ws.numel())
-        A.check(A.lib().isogs_render_fwd_persistent(*args, _p(ws), ctypes.byref(have), _stream()))
+        A.check(A.lib().isogs_render_fwd_ordered(*args, _p(ws), ctypes.byref(have), _stream()))
         return image, T, n_last
 
     def _workspace_q(self, nbytes):
@@ -273,12 +273,12 @@ class Rasterizer:
         `check="deferred"`: once a capacity is known, nothing waits: the status is copied
         to pinned host memory behind the launches and `verify(state)` reads it later (the
         first call, with no capacity yet, still checks synchronously). With
-        `persistent_fwd` set, compositing uses the longest-list-first persistent kernel
+        `ordered_fwd` set, compositing dispatches the tiles longest list first
         (same images bitwise). `checkpoints` keeps the compositing checkpoints for the
         backward in the state."""
         fp = self.project(scenes, cams)
         npv = [s.n for s in scenes]
-        fwd = self.render_fwd_persistent if self.persistent_fwd else self.render_fwd
+        fwd = self.render_fwd_ordered if self.ordered_fwd else self.render_fwd
         bins = self.bin_sort(fp, npv, cams, check=False)
         ckpt = self.checkpoint_buffer(bins) if checkpoints else None
         out = fwd(fp, npv, bins, cams, bg, ckpt=ckpt)

@@ -409,9 +409,9 @@ def test_render_bwd_chunked_long_lists(P, torch_cuda):
 
 
 @pytest.mark.parametrize("scale,opacity", [(0.06, (0.005, 0.03)), (0.25, (0.02, 0.08))])
-def test_persistent_forward_long_tiles(P, torch_cuda, scale, opacity):
+def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity):
     """Tiles of thousands of entries: with faint particles no pixel stops, with denser ones
-    most pixels stop after their first thousand entries. The persistent kernel equals the
+    most pixels stop after their first thousand entries. The longest-first launch equals the
     one-workgroup-per-tile kernel bitwise and both match the oracle."""
     torch = torch_cuda
     rng = np.random.default_rng(78)
@@ -419,7 +419,7 @@ def test_persistent_forward_long_tiles(P, torch_cuda, scale, opacity):
     opac = rng.uniform(*opacity, base.pos.shape[1]).astype(np.float32)
     sc = S.Scene(base.pos, base.scale, opac, base.color, 0)
     cams = [S.look_at_camera((0.0, 0.0, 3.2), width=48, height=40)]
-    note(f"persistent forward, long tiles, opacity {opacity}")
+    note(f"ordered forward, long tiles, opacity {opacity}")
     R = P.Rasterizer()
     g = P.GaussianScene.from_host(sc)
     fp = R.project([g], cams)
@@ -427,7 +427,7 @@ def test_persistent_forward_long_tiles(P, torch_cuda, scale, opacity):
     lens = (b.ranges[:, 1] - b.ranges[:, 0]).cpu().numpy()
     assert lens.max() > 3 * 1024
     a = R.render_fwd(fp, [g.n], b, cams, (0.2, 0.1, 0.3))
-    c = R.render_fwd_persistent(fp, [g.n], b, cams, (0.2, 0.1, 0.3))
+    c = R.render_fwd_ordered(fp, [g.n], b, cams, (0.2, 0.1, 0.3))
     torch.cuda.synchronize()
     for x, y in zip(a, c):
         assert torch.equal(x, y)

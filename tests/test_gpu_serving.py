@@ -1,4 +1,4 @@
-"""GPU checks of the serving path: the persistent longest-first compositing launch equals
+"""GPU checks of the serving path: the longest-list-first compositing launch equals
 the one-workgroup-per-tile launch bitwise, and every request served in a mixed,
 continuously batched stream gets exactly the image it gets when rendered alone."""
 import math
@@ -32,17 +32,26 @@ def _scenes():
             "cube": S.uniform_cube_scene(8000, seed=23, log_scale_mean=math.log(0.03))}
 
 
-def test_persistent_equals_per_tile_launch(P):
+@pytest.mark.parametrize("views", ["three_small", "sixteen_640"])
+def test_ordered_equals_per_tile_launch(P, views):
+    """Longest-list-first dispatch against the spatial one-workgroup-per-tile launch, bitwise:
+    three small views (pipelined walk) and sixteen 640x640 views (25600 tiles, above the
+    pipelined walk's limit: compact walk)."""
     import torch
-    note("persistent == per-tile")
-    sc = S.mixture_scene(100_000, seed=3)
-    cams = [S.orbit_camera(0.4 * i, 4.0, w, h) for i, (w, h) in enumerate([(640, 360), (512, 512), (333, 190)])]
+    note(f"ordered == per-tile ({views})")
+    if views == "three_small":
+        sc = S.mixture_scene(100_000, seed=3)
+        sizes = [(640, 360), (512, 512), (333, 190)]
+    else:
+        sc = S.mixture_scene(60_000, seed=4)
+        sizes = [(640, 640)] * 16
+    cams = [S.orbit_camera(0.4 * i, 4.0, w, h) for i, (w, h) in enumerate(sizes)]
     R = P.Rasterizer()
     g = P.GaussianScene.from_host(sc)
-    fp = R.project([g] * 3, cams)
-    b = R.bin_sort(fp, [g.n] * 3, cams)
-    a = R.render_fwd(fp, [g.n] * 3, b, cams, (0.1, 0.2, 0.3))
-    c = R.render_fwd_persistent(fp, [g.n] * 3, b, cams, (0.1, 0.2, 0.3))
+    fp = R.project([g] * len(cams), cams)
+    b = R.bin_sort(fp, [g.n] * len(cams), cams)
+    a = R.render_fwd(fp, [g.n] * len(cams), b, cams, (0.1, 0.2, 0.3))
+    c = R.render_fwd_ordered(fp, [g.n] * len(cams), b, cams, (0.1, 0.2, 0.3))
     torch.cuda.synchronize()
     for x, y in zip(a, c):
         assert torch.equal(x, y)
