@@ -180,19 +180,32 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
                      const float* bg, float* image, float* T_final, uint32_t* n_last,
                      float* checkpoints, void* stream);
 
+/* Flags of isogs_render_fwd_ordered. */
+#define ISOGS_FWD_WIDE 1u  /* wide walk for the longest tiles of small launches (see below) */
+
 /* Same outputs as isogs_render_fwd (bitwise), with the tiles dispatched longest entry list
  * first: a queue of the tiles sorted by list length is built on the device and workgroup b
  * composites the tile at queue position b, so that the few very long tiles of skewed scenes
  * start first instead of trailing the launch. Launches of few tiles (at most 24576 per group
  * of 16 views) use a software-pipelined walk that shortens the longest tiles; larger ones a
- * compact walk that keeps more workgroups resident. Used by the training and serving paths.
+ * compact walk that keeps more workgroups resident.
+ *   flags  0, or ISOGS_FWD_WIDE: in launches of at most 24576 tiles, the (at most 512)
+ *          tiles of at least 2048 entries are composited by four workgroups each, one per
+ *          8x8 quadrant, with four lanes per pixel that take the four entries of a list
+ *          step together (transmittance products scanned across the lanes, the stopping
+ *          entry found exactly, colour terms summed). Those tiles then agree with
+ *          isogs_render_fwd up to rounding (products and sums associated per step) instead
+ *          of bitwise, and which tiles take the wide walk depends on the whole launch; a
+ *          single 1080p view composites about twice as fast. Without the flag the result
+ *          of a view does not depend on the other views of the launch.
  *   ws, ws_bytes  workspace (query with ws == NULL): the queue, 4 bytes per tile of the
  *                 largest group of 16 views, plus bookkeeping
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
 int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view,
                              const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
                              const float* bg, float* image, float* T_final, uint32_t* n_last,
-                             float* checkpoints, void* ws, size_t* ws_bytes, void* stream);
+                             float* checkpoints, uint32_t flags, void* ws, size_t* ws_bytes,
+                             void* stream);
 
 /* Gradients of a scalar loss L with respect to the particle parameters, given dL/dimage.
  * Walks each pixel's entries in reverse from n_last, recovering the transmittance before

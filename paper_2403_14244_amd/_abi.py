@@ -17,6 +17,8 @@ ISOGS_ERR_CAPACITY = -2
 ISOGS_ERR_WORKSPACE = -3
 ISOGS_ERR_DEVICE = -4
 
+ISOGS_FWD_WIDE = 1
+
 EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
             "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_last_error", "isogs_version")
 
@@ -69,8 +71,8 @@ def lib():
         L.isogs_render_fwd.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera), ctypes.c_int32,
                                        P(ctypes.c_float), vp, vp, vp, vp, vp]
         L.isogs_render_fwd_ordered.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera),
-                                                  ctypes.c_int32, P(ctypes.c_float), vp, vp, vp, vp, vp,
-                                                  P(ctypes.c_size_t), vp]
+                                               ctypes.c_int32, P(ctypes.c_float), vp, vp, vp, vp, ctypes.c_uint32,
+                                               vp, P(ctypes.c_size_t), vp]
         L.isogs_render_bwd.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), P(Bins),
                                        P(ctypes.c_float), vp, vp, vp, vp, vp, P(Scene), vp, P(ctypes.c_size_t), vp]
         L.isogs_checkpoint_bytes.argtypes = [ctypes.c_uint64]

@@ -170,8 +170,8 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, con
 
 int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                              const isogs_camera* cams, int32_t n_views, const float* bg, float* image,
-                             float* T_final, uint32_t* n_last, float* checkpoints, void* ws, size_t* ws_bytes,
-                             void* stream) {
+                             float* T_final, uint32_t* n_last, float* checkpoints, uint32_t flags, void* ws,
+                             size_t* ws_bytes, void* stream) {
     g_error[0] = 0;
     int rc;
     if ((rc = check_views(n_views))) return rc;
@@ -191,8 +191,9 @@ int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_v
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (flags & ~ISOGS_FWD_WIDE) return fail(ISOGS_ERR_INVALID, "unknown flags %u", flags);
     if (isogs::launch_render_fwd_ordered(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
-                                         checkpoints, ws, (hipStream_t)stream))
+                                         checkpoints, flags, ws, (hipStream_t)stream))
         return device_fail("isogs_render_fwd_ordered");
     return ISOGS_OK;
 }

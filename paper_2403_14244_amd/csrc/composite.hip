@@ -207,6 +207,181 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWa
                    T_final, n_last, ckpt);
 }
 
+// ---- Wide walk for the longest tiles of small launches ------------------------------------
+// A launch of one or two views is bound by its few longest tiles: one wave walks a whole
+// list for its 64 pixels, one entry after another. The wide walk spreads such a tile over
+// four workgroups, one per 8x8 quadrant; wave w walks the list of the quadrant's sub-block
+// w with four lanes per pixel (lane l: pixel l / 4 of the 4x4 sub-block, entry l % 4 of
+// each four-entry list step). In a step the four lanes form the transmittance products
+// of the step's entries with a scan over the pixel's lanes, find the entry that takes T
+// below kTMin (the entries after it are not composited), and sum the four colour terms:
+// the result is the sequential one up to rounding (products and sums are associated per
+// step), at four times the lanes per pixel.
+
+struct StagedQuad {
+    float4 fp[kBatch + 1];
+    float4 col[kBatch + 1];        // {r, g, b, slot bits}
+    uint32_t list[4][kBatch + 4];  // byte offsets, per sub-block of the quadrant
+    uint32_t cnt[4][4];            // [loader wave][sub-block]
+    uint32_t len[4];
+};
+
+// Stages a batch for quadrant `quad` of the tile: records of all entries, lists of the
+// quadrant's four sub-blocks only. Returns the padded length of the calling wave's list
+// (wave w walks sub-block 4 quad + w). Contains __syncthreads.
+__device__ __forceinline__ uint32_t stage_quad(StagedQuad& sq, const EntryLoad& e, int quad, int tile_x0,
+                                               int tile_y0, float w_lim, float h_lim) {
+    const uint32_t t = threadIdx.x, w = t >> 6;
+    uint32_t mask = 0;
+    if (e.ok) {
+        const float4 f = e.f, c = e.c;
+        sq.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
+        sq.col[t] = make_float4(c.x, c.y, c.z, __uint_as_float(t));
+        const float r2 = c.w * c.w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (sub_block_touched(f.x, f.y, r2, 4 * quad + r, tile_x0, tile_y0, w_lim, h_lim)) mask |= 1u << r;
+    }
+    if (t == 0) {
+        sq.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
+        sq.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float((uint32_t)kDummy));
+    }
+    uint64_t bal[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bal[r] = ballot64((mask >> r) & 1u);
+    if (lane_id() < 4) {
+        const uint32_t r = lane_id();
+        sq.cnt[w][r] = (uint32_t)__popcll(r == 0 ? bal[0] : r == 1 ? bal[1] : r == 2 ? bal[2] : bal[3]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if ((mask >> r) & 1u) {
+            uint32_t pos = rank_below(bal[r]);
+            pos += (w > 0 ? sq.cnt[0][r] : 0u) + (w > 1 ? sq.cnt[1][r] : 0u) + (w > 2 ? sq.cnt[2][r] : 0u);
+            sq.list[r][pos] = t * kSlotBytes;
+        }
+    }
+    if (t < 16) {
+        const uint32_t r = t >> 2;
+        const uint32_t n = sq.cnt[0][r] + sq.cnt[1][r] + sq.cnt[2][r] + sq.cnt[3][r];
+        const uint32_t padded = (n + 3u) & ~3u;
+        if (n + (t & 3u) < padded) sq.list[r][n + (t & 3u)] = kDummy * kSlotBytes;
+        sq.list[r][padded + (t & 3u)] = kDummy * kSlotBytes;
+        if ((t & 3u) == 0) sq.len[r] = padded;
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(sq.len[w]);
+}
+
+// Composites quadrant `quad` of one tile with the wide walk. Contains __syncthreads.
+__device__ __forceinline__ void composite_quadrant(StagedQuad& sq, const RenderPack& pk, uint32_t logical, int quad,
+                                                   const float4* __restrict__ record,
+                                                   const uint32_t* __restrict__ pidx,
+                                                   const uint32_t* __restrict__ ranges, float bg_r, float bg_g,
+                                                   float bg_b, float* __restrict__ image,
+                                                   float* __restrict__ T_final, uint32_t* __restrict__ n_last,
+                                                   float4* __restrict__ ckpt) {
+    int vi, tx, ty;
+    locate_tile(pk, logical, vi, tx, ty);
+    const ViewDesc& vd = pk.v[vi];
+    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
+    const uint32_t e_idx = l & 3u;                  // entry of each list step
+    const uint32_t pp = l >> 2;                     // pixel of the sub-block
+    const uint32_t k = 4u * (uint32_t)quad + w;     // sub-block of the tile
+    const uint32_t t_px = 16u * k + pp;             // the pixel's thread in the one-workgroup layout
+    const int x = tx * kTile + (int)((k >> 2) & 1u) * 8 + (int)(k & 1u) * 4 + (int)(pp & 3u);
+    const int y = ty * kTile + (int)(k >> 3) * 8 + (int)((k & 3u) >> 1) * 4 + (int)(pp >> 2);
+    const bool inside = x < vd.width && y < vd.height;
+    const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+    const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
+    const uint32_t gt = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
+    const uint32_t start = ranges[2 * gt];
+    const uint32_t end = min(ranges[2 * gt + 1], pk.n_entries_cap);
+    const uint32_t len = end > start ? end - start : 0u;
+
+    float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+    uint32_t last = 0, lastp1 = 0;   // lastp1: staged slot + 1 of this lane's last entry used
+    bool done = !inside;
+    auto batch_len = [end](uint32_t b) { return b < end ? min((uint32_t)kBatch, end - b) : 0u; };
+    uint32_t b0 = start;
+    EntryLoad cur = load_entry(record, batch_pidx(pidx, b0, batch_len(b0)), pk.n_particles);
+    uint32_t g_next = batch_pidx(pidx, b0 + kBatch, batch_len(b0 + kBatch));
+    for (; b0 < end; b0 += kBatch) {
+        if (__syncthreads_and(done)) break;
+        if (ckpt && b0 > start && (b0 - start) % kCkptChunk == 0 && e_idx == 0)
+            ckpt[(size_t)ckpt_slot(start, (b0 - start) / kCkptChunk) * 256 + t_px] = make_float4(T, cr, cg, cb);
+        const EntryLoad nxt = load_entry(record, g_next, pk.n_particles);
+        g_next = batch_pidx(pidx, b0 + 2 * kBatch, batch_len(b0 + 2 * kBatch));
+        const uint32_t n = stage_quad(sq, cur, quad, tx * kTile, ty * kTile, w_lim, h_lim);
+        lastp1 = 0;
+        for (uint32_t s0 = 0; s0 < n; s0 += 4) {
+            const uint32_t off = sq.list[w][s0 + e_idx];
+            const float4 f = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sq.fp) + off);
+            const float4 c = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sq.col) + off);
+            float g;
+            float a = entry_alpha(px - f.x, py - f.y, f.z, f.w, g);
+            const bool use = a >= kAlphaMin;
+            a = use ? a : 0.0f;
+            const float om = 1.0f - a;
+            // products of (1 - alpha) over the pixel's lanes up to this one (quad scan). The
+            // cross-lane reads stay outside any condition: a read from a lane that a branch
+            // has switched off returns 0
+            float incl = om;
+            const float from1 = dpp<0x90>(incl);   // lane e - 1
+            incl = incl * (e_idx >= 1u ? from1 : 1.0f);
+            const float from2 = dpp<0x40>(incl);   // lane e - 2
+            incl = incl * (e_idx >= 2u ? from2 : 1.0f);
+            const float prev = dpp<0x90>(incl);
+            const float excl = e_idx >= 1u ? prev : 1.0f;
+            // the entry that takes T below kTMin is the last one composited
+            const bool cross = !done && use && (T * incl < kTMin);
+            const uint32_t nib = (uint32_t)(ballot64(cross) >> (l & 60u)) & 0xFu;
+            const bool muted = done || (nib & ((1u << e_idx) - 1u)) != 0u;
+            const float wgt = muted ? 0.0f : a * (T * excl);
+            float sr = wgt * c.x, sg = wgt * c.y, sb = wgt * c.z;
+            sr += dpp<0xB1>(sr);
+            sg += dpp<0xB1>(sg);
+            sb += dpp<0xB1>(sb);
+            sr += dpp<0x4E>(sr);
+            sg += dpp<0x4E>(sg);
+            sb += dpp<0x4E>(sb);
+            cr += sr;
+            cg += sg;
+            cb += sb;
+            float fac = muted ? 1.0f : om;
+            fac *= dpp<0xB1>(fac);
+            fac *= dpp<0x4E>(fac);
+            T = T * fac;
+            lastp1 = (use && !muted) ? __float_as_uint(c.w) + 1u : lastp1;
+            done = done || nib != 0u;
+            if (ballot64(!done) == 0) break;
+        }
+        // the pixel's last entry: the largest slot over its four lanes
+        uint32_t m = lastp1;
+        m = max(m, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m, 0xB1, 0xF, 0xF, false));
+        m = max(m, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m, 0x4E, 0xF, 0xF, false));
+        if (m) last = b0 - start + m;   // 1-based list position
+        cur = nxt;
+    }
+    if (inside && e_idx == 0) {
+        const size_t hw = (size_t)vd.width * vd.height;
+        const size_t pix = (size_t)y * vd.width + x;
+        float* img = image + (size_t)3 * vd.pix_off;
+        img[pix] = fmaf(T, bg_r, cr);
+        img[hw + pix] = fmaf(T, bg_g, cg);
+        img[2 * hw + pix] = fmaf(T, bg_b, cb);
+        T_final[vd.pix_off + pix] = T;
+        n_last[vd.pix_off + pix] = last;
+    }
+}
+
+// With the wide flag, tiles of at least 2^kWideMinLog2 entries (length classes above
+// kWideMinLog2) take the wide walk in small launches, at most kWideSlots of them (the
+// longest).
+constexpr int kWideMinLog2 = 11;
+constexpr uint32_t kWideSlots = 512;
+
 // Longest list first: one workgroup per tile, the tiles taken in the order of a queue
 // sorted by list length, so that the dispatcher starts the long tiles of skewed scenes
 // first instead of leaving them to trail the launch. Two builds of the walk: with many
@@ -349,9 +524,40 @@ int resident_blocks(const void* kernel, int threads) {
     return cus * per_cu;
 }
 
+// Small launches: workgroups [0, 4 wide_slots) take the quadrants of the longest tiles
+// (those of at least 2^kWideMinLog2 entries, counted from the queue's length classes; a
+// workgroup past their number leaves at once) with the wide walk, the others the
+// remaining tiles of the queue with the compact walk.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWavesPerSimd)))
+composite_fwd_ordered_wide_kernel(const RenderPack pk, const float4* __restrict__ record,
+                                  const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges,
+                                  const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
+                                  float* __restrict__ image, float* __restrict__ T_final,
+                                  uint32_t* __restrict__ n_last, float4* __restrict__ ckpt,
+                                  const uint32_t* __restrict__ order, const uint32_t* __restrict__ hist,
+                                  uint32_t wide_slots) {
+    static_assert(sizeof(StagedQuad) <= sizeof(StagedSub), "one LDS buffer serves both walks");
+    __shared__ __align__(16) unsigned char smem[sizeof(StagedSub)];
+    if (*status != kStatusOk) return;
+    uint32_t n_wide = 0;
+    for (int c = kWideMinLog2 + 1; c < kBuckets; ++c) n_wide += hist[c];
+    n_wide = min(n_wide, wide_slots);
+    const uint32_t b = blockIdx.x;
+    if (b < 4 * wide_slots) {
+        if ((b >> 2) >= n_wide) return;
+        composite_quadrant(*reinterpret_cast<StagedQuad*>(smem), pk, order[b >> 2], (int)(b & 3u), record, pidx,
+                           ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
+    } else {
+        const uint32_t j = b - 4 * wide_slots;
+        if (j < n_wide) return;
+        composite_tile<false>(*reinterpret_cast<StagedSub*>(smem), pk, order[j], record, pidx, ranges, bg_r, bg_g,
+                              bg_b, image, T_final, n_last, ckpt);
+    }
+}
+
 int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                               const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
-                              uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream) {
+                              uint32_t* n_last, float* ckpt, uint32_t flags, void* ws, hipStream_t stream) {
     uint32_t* q = static_cast<uint32_t*>(ws);
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
@@ -362,14 +568,21 @@ int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_
         set_render_limits(pk, n_per_view, nv, bins->capacity);
         if (!blocks) continue;
         const uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
-        if (blocks <= kPipeTileLimit)
+        if (blocks <= kPipeTileLimit && (flags & ISOGS_FWD_WIDE)) {
+            const uint32_t wide_slots = std::min<uint32_t>(blocks, kWideSlots);
+            hipLaunchKernelGGL(composite_fwd_ordered_wide_kernel, dim3(4 * wide_slots + blocks), dim3(256), 0, stream,
+                               pk, reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges,
+                               bins->status, bg[0], bg[1], bg[2], image, T_final, n_last,
+                               reinterpret_cast<float4*>(ckpt), order, q, wide_slots);
+        } else if (blocks <= kPipeTileLimit) {
             hipLaunchKernelGGL(composite_fwd_ordered_pipe_kernel, dim3(blocks), dim3(256), 0, stream, pk,
                                reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
                                bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order);
-        else
+        } else {
             hipLaunchKernelGGL(composite_fwd_ordered_kernel, dim3(blocks), dim3(256), 0, stream, pk,
                                reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
                                bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order);
+        }
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     return 0;

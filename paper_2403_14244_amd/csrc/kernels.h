@@ -47,7 +47,7 @@ size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv);
 
 int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                               const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
-                              uint32_t* n_last, float* ckpt, void* ws, hipStream_t stream);
+                              uint32_t* n_last, float* ckpt, uint32_t flags, void* ws, hipStream_t stream);
 
 int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
                       const isogs_projected* proj, const isogs_bins* bins, const float* bg,

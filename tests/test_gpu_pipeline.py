@@ -376,20 +376,22 @@ def test_autograd_deferred_capacity_check(P, torch_cuda):
         np.testing.assert_array_equal(a, b)
 
 
-def test_render_bwd_chunked_long_lists(P, torch_cuda):
-    """Tiles with thousands of faint entries: the forward stores checkpoints and the
-    backward walks each long list as chunks on separate workgroups; the gradients match the
-    FP64 oracle and the single-walk backward (no checkpoints)."""
+@pytest.mark.parametrize("wide", [False, True], ids=["sequential_fwd", "wide_fwd"])
+def test_render_bwd_chunked_long_lists(P, torch_cuda, wide):
+    """Tiles with thousands of faint entries: the forward (sequential or wide walk, the
+    latter being what training uses) stores checkpoints and the backward walks each long
+    list as chunks on separate workgroups; the gradients match the FP64 oracle and the
+    single-walk backward (no checkpoints)."""
     torch = torch_cuda
     rng = np.random.default_rng(77)
     base = S.uniform_cube_scene(6000, seed=77, log_scale_mean=math.log(0.06), log_scale_std=0.3)
     opac = rng.uniform(0.005, 0.03, base.pos.shape[1]).astype(np.float32)
     sc = S.Scene(base.pos, base.scale, opac, base.color, 0)
     cams = [S.look_at_camera((0.0, 0.0, 3.2), width=48, height=40)]
-    note("render_bwd chunked")
+    note(f"render_bwd chunked (wide forward: {wide})")
     R = P.Rasterizer()
     gs = P.GaussianScene.from_host(sc)
-    imgs, st = R.render([gs], cams, checkpoints=True)
+    imgs, st = R.render([gs], cams, checkpoints=True, wide=wide)
     lens = (st["bins"].ranges[:, 1] - st["bins"].ranges[:, 0]).cpu().numpy()
     assert lens.max() > 3 * 1024, int(lens.max())
     assert int(st["n_last"].max()) > 2048           # pixels keep compositing past two chunks
@@ -408,18 +410,21 @@ def test_render_bwd_chunked_long_lists(P, torch_cuda):
         note(f"  {name}: max rel-to-max vs oracle {r:.2e}")
 
 
+@pytest.mark.parametrize("wide", [False, True], ids=["pipelined", "wide"])
 @pytest.mark.parametrize("scale,opacity", [(0.06, (0.005, 0.03)), (0.25, (0.02, 0.08))])
-def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity):
+def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity, wide):
     """Tiles of thousands of entries: with faint particles no pixel stops, with denser ones
     most pixels stop after their first thousand entries. The longest-first launch equals the
-    one-workgroup-per-tile kernel bitwise and both match the oracle."""
+    one-workgroup-per-tile kernel bitwise (pipelined walk) or up to rounding (wide walk:
+    per-step products, so a stop decision can move only where T passes within rounding of
+    the threshold, a pixel the oracle flags), and both match the oracle."""
     torch = torch_cuda
     rng = np.random.default_rng(78)
     base = S.uniform_cube_scene(6000, seed=78, log_scale_mean=math.log(scale), log_scale_std=0.3)
     opac = rng.uniform(*opacity, base.pos.shape[1]).astype(np.float32)
     sc = S.Scene(base.pos, base.scale, opac, base.color, 0)
     cams = [S.look_at_camera((0.0, 0.0, 3.2), width=48, height=40)]
-    note(f"ordered forward, long tiles, opacity {opacity}")
+    note(f"ordered forward, long tiles, opacity {opacity}, wide={wide}")
     R = P.Rasterizer()
     g = P.GaussianScene.from_host(sc)
     fp = R.project([g], cams)
@@ -427,12 +432,22 @@ def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity):
     lens = (b.ranges[:, 1] - b.ranges[:, 0]).cpu().numpy()
     assert lens.max() > 3 * 1024
     a = R.render_fwd(fp, [g.n], b, cams, (0.2, 0.1, 0.3))
-    c = R.render_fwd_ordered(fp, [g.n], b, cams, (0.2, 0.1, 0.3))
+    c = R.render_fwd_ordered(fp, [g.n], b, cams, (0.2, 0.1, 0.3), wide=wide)
     torch.cuda.synchronize()
-    for x, y in zip(a, c):
-        assert torch.equal(x, y)
     nl_c = c[2].cpu().numpy()
     ores = O.render_views([sc], cams, bg=(0.2, 0.1, 0.3), alpha_band=2.0 ** -12, term_band=2.0 ** -8)
+    if not wide:
+        for x, y in zip(a, c):
+            assert torch.equal(x, y)
+    else:
+        fl = ores[3][0].reshape(-1)
+        dimg = np.abs(a[0].cpu().numpy().reshape(3, -1) - c[0].cpu().numpy().reshape(3, -1)).max(axis=0)
+        assert dimg[~fl].max() <= 2e-5 and dimg.max() <= 1e-4, (dimg[~fl].max(), dimg.max())
+        nl_a = a[2].cpu().numpy()
+        assert np.array_equal(nl_a[~fl], nl_c[~fl])
+        Ta, Tc = a[1].cpu().numpy(), c[1].cpu().numpy()
+        assert np.abs(Ta - Tc)[~fl].max() <= 1e-5
+        note(f"  wide vs sequential: max|d| {dimg.max():.2e}, n_last differs at {int((nl_a != nl_c).sum())} px")
     # thousands of faint entries per pixel: many walks pass within the flag band of the
     # 1/255 threshold somewhere, so only the unflagged pixels are held to 1e-4
     d = np.abs(c[0].cpu().numpy().reshape(3, 40, 48).astype(np.float64) - ores[0][0]).max(axis=0)
