@@ -157,13 +157,14 @@ int isogs_bin_sort(const isogs_projected* proj, const int32_t* n_per_view,
                    const isogs_camera* cams, int32_t n_views, const isogs_bins* bins,
                    void* ws, size_t* ws_bytes, void* stream);
 
-/* Compositing checkpoints, for isogs_render_bwd on long tile lists: at list positions
- * k * ISOGS_CKPT_CHUNK (k >= 1) of a tile, each pixel's state before that entry - float4
- * {T, accumulated r, g, b} - is stored at slot start / ISOGS_CKPT_CHUNK + k of the buffer
- * (start: the tile's first entry), 256 float4 per slot in the tile's thread order. Slots
- * of different tiles never overlap. A buffer for bins of a given capacity takes
- * isogs_checkpoint_bytes(capacity) bytes (device memory, caller-owned). */
-#define ISOGS_CKPT_CHUNK 1024
+/* Compositing checkpoints, for isogs_render_bwd on long tile lists (at least
+ * 2 * ISOGS_CKPT_CHUNK entries): at list positions k * ISOGS_CKPT_CHUNK (k >= 1) of such a
+ * tile, each pixel's state before that entry - float4 {T, accumulated r, g, b} - is stored
+ * at slot start / ISOGS_CKPT_CHUNK + k of the buffer (start: the tile's first entry), 256
+ * float4 per slot in the tile's thread order. Slots of different tiles never overlap. A
+ * buffer for bins of a given capacity takes isogs_checkpoint_bytes(capacity) bytes (device
+ * memory, caller-owned). */
+#define ISOGS_CKPT_CHUNK 256
 size_t isogs_checkpoint_bytes(uint64_t capacity);
 
 /* Front-to-back compositing (eq. 4) of every pixel over its tile's sorted entries.
@@ -212,7 +213,7 @@ int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_v
  * each entry as T / (1 - alpha) (no per-entry state is stored by the forward pass), and
  * sums each entry's gradient over the tile's pixels with wavefront reductions in a fixed
  * order (no floating-point atomics: results are bitwise reproducible). With the forward's
- * checkpoints, a tile whose list is longer than ISOGS_CKPT_CHUNK is walked as independent
+ * checkpoints, a tile of at least 2 * ISOGS_CKPT_CHUNK entries is walked as independent
  * chunks on different workgroups, each starting from the checkpoint at its end (the light
  * from behind a chunk is image - accumulated colour there).
  *   scenes, cams   the same arrays as given to isogs_project

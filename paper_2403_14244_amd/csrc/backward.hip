@@ -94,11 +94,12 @@ __device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __res
 // Reverse walk of one tile (logical index within the launch) by a 256-thread workgroup,
 // one lane per pixel, each 16-lane row owning a 4x4 sub-block (the forward pixel layout).
 // Record of an entry: {du, dv, d(1/s^2), do} {dr, dg, db, 0}, at its emit position.
-// With checkpoints (`ckpt` non-null) the workgroup walks only chunk `chunk` of the list,
-// positions [chunk * kCkptChunk, (chunk + 1) * kCkptChunk); a pixel whose last entry lies
-// beyond the chunk starts from the checkpoint at the chunk's end: T from there, and the
-// light from behind = image - colour accumulated before the chunk's end. Without
-// checkpoints the whole list is one chunk. Contains __syncthreads.
+// With checkpoints (`ckpt` non-null) and a list of at least kChunkedMin entries, the
+// workgroup walks only chunk `chunk` of the list, positions [chunk * kCkptChunk,
+// (chunk + 1) * kCkptChunk); a pixel whose last entry lies beyond the chunk starts from the
+// checkpoint at the chunk's end: T from there, and the light from behind = image - colour
+// accumulated before the chunk's end. Shorter lists, and every list without checkpoints,
+// are one chunk. Contains __syncthreads.
 __device__ __forceinline__ void composite_bwd_tile(
     StagedBwd& sb, const RenderPack& pk, uint32_t logical, uint32_t chunk, const float4* __restrict__ record,
     const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges,
@@ -118,8 +119,9 @@ __device__ __forceinline__ void composite_bwd_tile(
     const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
     const uint32_t len = end > start ? end - start : 0u;
     // this workgroup's positions [c_lo, c_hi) of the list
-    const uint32_t c_lo = ckpt ? chunk * kCkptChunk : 0u;
-    const uint32_t c_hi = ckpt ? min(c_lo + kCkptChunk, len) : len;
+    const bool chunked = ckpt && chunked_list(len);
+    const uint32_t c_lo = chunked ? chunk * kCkptChunk : 0u;
+    const uint32_t c_hi = chunked ? min(c_lo + kCkptChunk, len) : len;
     if (c_lo > c_hi) return;   // no such chunk (uniform over the workgroup)
 
     float T = 1.0f, dr = 0.0f, dg = 0.0f, db = 0.0f;
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(256) bwd_chunk_list_kernel(const uint32_t* __r
     if (i >= n_tiles || *status != kStatusOk) return;
     const uint32_t s = ranges[2 * (tile0 + i)], e = min(ranges[2 * (tile0 + i) + 1], cap);
     const uint32_t len = e > s ? e - s : 0u;
-    if (len <= kCkptChunk) return;
+    if (!chunked_list(len)) return;
     const uint32_t nch = (len + kCkptChunk - 1) / kCkptChunk;
     const uint32_t base = atomicAdd(heavy_count, nch);
     if (base + nch > heavy_max) return;   // cannot happen for ranges that partition the entries
@@ -274,35 +276,38 @@ __global__ void __launch_bounds__(256) bwd_chunk_list_kernel(const uint32_t* __r
     }
 }
 
-// One workgroup per work item, in dispatch order: workgroups [0, heavy_slots) take the
-// chunks of the long tiles (when checkpoints are given; a workgroup past the device-side
-// count leaves at once), the others the tiles of the longest-list-first queue, skipping
-// the long ones.
+// One workgroup per work item, in dispatch order. With checkpoints: workgroups
+// [0, n_chunks) take the chunks of the long tiles (listed by bwd_chunk_list_kernel), the
+// next ones the other tiles in longest-list-first order (they follow the long ones in the
+// queue, whose length classes tell how many those are); a workgroup past the last item
+// leaves at once. Without: workgroup b walks the tile at queue position b whole.
 __global__ void __launch_bounds__(256) composite_bwd_ordered_kernel(
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
     float bg_r, float bg_g, float bg_b, const float* __restrict__ image, const float* __restrict__ dL_dimage,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_last, const float4* __restrict__ ckpt,
-    float4* __restrict__ rec, const uint32_t* __restrict__ order, uint32_t n_items,
-    const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count, uint32_t heavy_slots) {
+    float4* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ hist,
+    uint32_t n_items, const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count,
+    uint32_t heavy_max) {
     __shared__ StagedBwd sb;
     if (*status != kStatusOk) return;
     const uint32_t b = blockIdx.x;
     uint32_t logical, chunk = 0;
-    if (b < heavy_slots) {
-        if (b >= min(*heavy_count, heavy_slots)) return;
-        logical = heavy[2 * b];
-        chunk = heavy[2 * b + 1];
-        if (logical >= n_items) return;
-    } else {
-        logical = order[b - heavy_slots];
-        if (ckpt) {
-            int vi, tx, ty;
-            locate_tile(pk, logical, vi, tx, ty);
-            const uint32_t gt = pk.v[vi].tile_base + (uint32_t)(ty * pk.v[vi].tiles_x + tx);
-            const uint32_t s = ranges[2 * gt], e = min(ranges[2 * gt + 1], pk.n_entries_cap);
-            if (e > s && e - s > kCkptChunk) return;   // walked as chunks
+    if (ckpt) {
+        const uint32_t n_heavy = min(*heavy_count, heavy_max);
+        if (b < n_heavy) {
+            logical = heavy[2 * b];
+            chunk = heavy[2 * b + 1];
+            if (logical >= n_items) return;
+        } else {
+            uint32_t n_long = 0;
+            for (int c = kChunkedClass; c < kBuckets; ++c) n_long += hist[c];
+            const uint32_t j = n_long + (b - n_heavy);
+            if (j >= n_items) return;
+            logical = order[j];
         }
+    } else {
+        logical = order[b];
     }
     composite_bwd_tile(sb, pk, logical, chunk, record, pidx, offsets, ranges, bg_r, bg_g, bg_b, image, dL_dimage,
                        T_final, n_last, ckpt, rec);
@@ -494,10 +499,10 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
     uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base);
     uint32_t* heavy = reinterpret_cast<uint32_t*>(base + 256);
     const uint32_t heavy_max = (uint32_t)bwd_heavy_items(bins->capacity, max_tiles);
-    // a tile longer than one chunk has fewer than 2 len / kCkptChunk chunks, so the chunks
-    // of ranges that partition the entries number fewer than 2 capacity / kCkptChunk
-    const uint32_t heavy_slots =
-        ckpt ? (uint32_t)std::min<uint64_t>(heavy_max, 2 * (bins->capacity / kCkptChunk) + 2) : 0u;
+    // a long tile of len entries has ceil(len / kCkptChunk) chunks, at most len / kCkptChunk
+    // more items than tiles; over ranges that partition the entries, at most
+    // capacity / kCkptChunk more in all
+    const uint32_t extra_items = ckpt ? (uint32_t)(bins->capacity / kCkptChunk) + 1u : 0u;
     int32_t n_per_view[kMaxViews];
     int32_t n_all[4096];
     if (nv > 4096) return -1;
@@ -519,11 +524,11 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
             hipLaunchKernelGGL(bwd_chunk_list_kernel, dim3((blocks + 255) / 256), dim3(256), 0, stream, bins->ranges,
                                tile0, blocks, pk.n_entries_cap, bins->status, heavy, heavy_count, heavy_max);
         }
-        hipLaunchKernelGGL(composite_bwd_ordered_kernel, dim3(heavy_slots + blocks), dim3(256), 0, stream, pk,
+        hipLaunchKernelGGL(composite_bwd_ordered_kernel, dim3(blocks + extra_items), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->offsets, bins->ranges,
                            bins->status, bg[0], bg[1], bg[2], image, dL_dimage, T_final, n_last,
-                           reinterpret_cast<const float4*>(ckpt), rec, order, blocks, heavy, heavy_count,
-                           heavy_slots);
+                           reinterpret_cast<const float4*>(ckpt), rec, order, q, blocks, heavy, heavy_count,
+                           heavy_max);
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }
     // 2. per scene: reduce records over its views (in view order) and chain to parameters

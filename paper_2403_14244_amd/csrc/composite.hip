@@ -110,7 +110,7 @@ __device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack&
     }
     for (; b0 < end; b0 += kBatch) {
         if (__syncthreads_and(s.done)) break;
-        if (ckpt && b0 > p.start && (b0 - p.start) % kCkptChunk == 0)
+        if (ckpt && chunked_list(p.len) && b0 > p.start && (b0 - p.start) % kCkptChunk == 0)
             ckpt[(size_t)ckpt_slot(p.start, (b0 - p.start) / kCkptChunk) * 256 + t] =
                 make_float4(s.T, s.cr, s.cg, s.cb);
         uint32_t steps;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void composite_quadrant(StagedQuad& sq, const RenderP
     uint32_t g_next = batch_pidx(pidx, b0 + kBatch, batch_len(b0 + kBatch));
     for (; b0 < end; b0 += kBatch) {
         if (__syncthreads_and(done)) break;
-        if (ckpt && b0 > start && (b0 - start) % kCkptChunk == 0 && e_idx == 0)
+        if (ckpt && chunked_list(len) && b0 > start && (b0 - start) % kCkptChunk == 0 && e_idx == 0)
             ckpt[(size_t)ckpt_slot(start, (b0 - start) / kCkptChunk) * 256 + t_px] = make_float4(T, cr, cg, cb);
         const EntryLoad nxt = load_entry(record, g_next, pk.n_particles);
         g_next = batch_pidx(pidx, b0 + 2 * kBatch, batch_len(b0 + 2 * kBatch));
@@ -418,7 +418,6 @@ __global__ void __launch_bounds__(128) fill_u32_kernel_c(uint32_t* __restrict__ 
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-constexpr int kBuckets = 33;   // list length classes: 0, then 32 - clz(length)
 
 __device__ __forceinline__ uint32_t length_bucket(const uint32_t* ranges, uint32_t gt, uint32_t cap) {
     const uint32_t s = ranges[2 * gt], e = min(ranges[2 * gt + 1], cap);

@@ -8,17 +8,26 @@ namespace isogs {
 
 constexpr int kBatch = 256;   // forward: entries staged in LDS per round (one per thread)
 
-// Compositing checkpoints: at every kCkptChunk-th position of a tile's list (a multiple of
-// the forward batch) the forward can store each pixel's {T, r, g, b} before that entry, so
-// that the backward can walk the chunks of one long list on different workgroups. The
+// Compositing checkpoints: at every kCkptChunk-th position of a long tile list (a multiple
+// of the forward batch) the forward can store each pixel's {T, r, g, b} before that entry,
+// so that the backward can walk the chunks of the list on different workgroups. The
 // checkpoints of the tile whose list starts at global entry `start` occupy slots
 // start / kCkptChunk + k (k >= 1), which never overlap between tiles; a slot holds one
-// float4 per pixel (thread) of the tile.
-constexpr uint32_t kCkptChunk = 1024;
+// float4 per pixel (thread) of the tile. Lists of at least kChunkedMin entries (length
+// class kChunkedClass and up, the class being the bit length) are the long ones.
+constexpr uint32_t kCkptChunk = 256;
+constexpr uint32_t kChunkedMin = 2 * kCkptChunk;
+constexpr int kChunkedClass = 10;
 static_assert(kCkptChunk % 256 == 0, "checkpoints sit on forward batch boundaries");
 static_assert(kCkptChunk == ISOGS_CKPT_CHUNK, "the header states the checkpoint spacing");
+static_assert((1u << (kChunkedClass - 1)) == kChunkedMin, "class of the shortest chunked list");
 
 __host__ __device__ inline uint32_t ckpt_slot(uint32_t start, uint32_t k) { return start / kCkptChunk + k; }
+__host__ __device__ inline bool chunked_list(uint32_t len) { return len >= kChunkedMin; }
+
+// Longest-list-first tile queues: list length classes 0, then 32 - clz(length); a queue
+// starts with its class histogram (kBuckets words).
+constexpr int kBuckets = 33;
 constexpr int kDummy = kBatch; // staged slot of a zero-opacity record that pads the lists
 
 // Emit position of the entry (particle with footprint u, v, r; tile tx, ty): the
