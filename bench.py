@@ -302,7 +302,7 @@ def main():
     # record (32 B); per pixel the image (12 B), final transmittance (4 B) and last index
     # (4 B); per tile its range (8 B)
     comp_bytes = ent_per_launch * 36 + pix_per_launch * 20 + tiles_per_launch * 8
-    roof = dict(kernel="composite_fwd_kernel", bound="alu",
+    roof = dict(kernel="composite_fwd_ordered_kernel", bound="alu",
                 achieved=flops / (comp_ms * 1e-3) / 1e12, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
                 traffic=measured_traffic(comp_bytes), launch_ms=comp_ms, launch_ms_alone=iso_ms,
                 pairs_per_launch=pairs_per_launch,
