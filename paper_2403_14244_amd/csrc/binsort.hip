@@ -9,15 +9,14 @@
 // LDS, reads its keys sequentially instead of gathering them.
 //
 // Steps (all on the caller's stream, no host synchronisation):
-//   1. fill        zero tile ranges, radix histograms and counters
+//   1. fill        zero tile ranges and counters
 //   2. scan        exclusive scan of per-particle tile counts -> emit offsets, total, status
-//   3. emit        one (tile id, particle index, depth bits) per (particle, member tile),
-//                  counting the digits of every tile-id pass on the way
-//   4. histogram   sum of the per-workgroup digit counts
-//   5. passes      stable LSD radix passes over the tile id, digits of up to 9 bits, each
-//                  as count / scan / scatter kernels
-//   6. finalize    tile ranges [start, end)
-//   7. segments    stable sort of each tile's segment on the depth bits (and the 64-bit
+//   3. emit        one (tile id, particle index, depth bits) per (particle, member tile)
+//   4. passes      stable LSD radix passes over the tile id, digits of up to 9 bits, each
+//                  as count / scan / scatter kernels; the per-digit scan over the sort tiles
+//                  also yields each digit's total, from which the scatter forms the bases
+//   5. finalize    tile ranges [start, end)
+//   6. segments    stable sort of each tile's segment on the depth bits (and the 64-bit
 //                  (tile, depth) keys, when the caller asks for them): one wave per short
 //                  segment, one workgroup per long one
 #include "common.h"
@@ -163,93 +162,49 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
 // Step 3: one entry per (particle, member tile); entries of a particle are consecutive
 // from its offset, tiles in row-major order. A particle writes no more entries than its
 // tile count says (the count may come from elsewhere); missing ones get the sentinel id
-// 0xFFFFFFFF, which sorts last and belongs to no tile.
-//
-// A resident grid walks the chunks of 256 particles. Each workgroup also counts the digits
-// of every tile-id pass in LDS and stores its counts as one row of `rows` (added to the
-// row when `accumulate`, for the later launches of a batch); step 4 sums the rows.
-constexpr int kEmitRows = 2048;   // most emit workgroups (rows of digit counts)
-
-__global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, uint32_t n_chunks,
-                                                   const float4* __restrict__ record,
+// 0xFFFFFFFF, which sorts last and belongs to no tile. One workgroup per chunk of 256
+// particles of a view.
+__global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ record,
                                                    const uint32_t* __restrict__ tile_count,
                                                    const uint32_t* __restrict__ offsets,
                                                    const float* __restrict__ depth,
                                                    const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                   const DigitSplit split, int accumulate,
                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                   uint32_t* __restrict__ zbits, uint32_t* __restrict__ rows) {
-    __shared__ uint32_t s_h[kMaxPasses][kTileRadix];
-    const uint32_t t = threadIdx.x;
+                                                   uint32_t* __restrict__ zbits) {
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    for (int p = 0; p < kMaxPasses; ++p) {
-        s_h[p][t] = 0u;
-        s_h[p][t + 256] = 0u;
-    }
-    __syncthreads();
-    for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-        const int vi = view_of_block(pk, c);
-        const ViewDesc& vd = pk.v[vi];
-        const uint32_t first = vd.p_off + (c - pk.block_begin[vi]) * 256u;
-        const uint32_t last = min(first + 255u, vd.p_off + vd.n - 1u);
-        const uint32_t i = first + t;
-        const uint32_t want = i <= last ? tile_count[i] : 0u;
-        const uint32_t e0 = want ? offsets[i] : 0u;
-        if (want && (uint64_t)e0 + want <= count) {
-            const float4 fp = record[2 * (size_t)i];
-            const float r = record[2 * (size_t)i + 1].w;
-            const uint32_t z = __float_as_uint(depth[i]);
-            int tx0, tx1, ty0, ty1;
-            tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
-            const float r2 = r * r;
-            const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
-            uint32_t j = 0;
-            for (int ty = ty0; ty <= ty1 && j < want; ++ty) {
-                for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
-                    if (!tile_member(fp.x, fp.y, r2, tx, ty, w_lim, h_lim)) continue;
-                    const uint32_t e = e0 + j++;
-                    const uint32_t key = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
-                    keys[e] = key;
-                    vals[e] = i;
-                    zbits[e] = z;
-                    for (int p = 0; p < split.passes; ++p) atomicAdd(&s_h[p][digit_at(key, split.shift(p), split.width(p))], 1u);
-                }
-            }
-            for (; j < want; ++j) {
-                const uint32_t e = e0 + j;
-                keys[e] = 0xFFFFFFFFu;
-                vals[e] = i;
-                zbits[e] = z;
-                for (int p = 0; p < split.passes; ++p)
-                    atomicAdd(&s_h[p][digit_at(0xFFFFFFFFu, split.shift(p), split.width(p))], 1u);
-            }
+    const uint32_t c = blockIdx.x;
+    const int vi = view_of_block(pk, c);
+    const ViewDesc& vd = pk.v[vi];
+    const uint32_t first = vd.p_off + (c - pk.block_begin[vi]) * 256u;
+    const uint32_t last = min(first + 255u, vd.p_off + vd.n - 1u);
+    const uint32_t i = first + threadIdx.x;
+    const uint32_t want = i <= last ? tile_count[i] : 0u;
+    const uint32_t e0 = want ? offsets[i] : 0u;
+    if (!want || (uint64_t)e0 + want > count) return;
+    const float4 fp = record[2 * (size_t)i];
+    const float r = record[2 * (size_t)i + 1].w;
+    const uint32_t z = __float_as_uint(depth[i]);
+    int tx0, tx1, ty0, ty1;
+    tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
+    const float r2 = r * r;
+    const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
+    uint32_t j = 0;
+    for (int ty = ty0; ty <= ty1 && j < want; ++ty) {
+        for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
+            if (!tile_member(fp.x, fp.y, r2, tx, ty, w_lim, h_lim)) continue;
+            const uint32_t e = e0 + j++;
+            keys[e] = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
+            vals[e] = i;
+            zbits[e] = z;
         }
     }
-    __syncthreads();
-    uint32_t* row = rows + (size_t)blockIdx.x * (kMaxPasses * kTileRadix);
-    for (int p = 0; p < kMaxPasses; ++p)
-        for (int h = 0; h < 2; ++h) {
-            const int d = t + 256 * h;
-            row[p * kTileRadix + d] = (accumulate ? row[p * kTileRadix + d] : 0u) + s_h[p][d];
-        }
-}
-
-// Step 4: digit histograms of all passes: the sum of the emit rows. Block (x, y) adds rows
-// y * kRowsPerBlock ... of columns x * 256 ... into the zeroed histogram.
-constexpr uint32_t kRowsPerBlock = 16;
-
-__global__ void __launch_bounds__(256) sum_rows_kernel(const uint32_t* __restrict__ rows, uint32_t n_rows,
-                                                       const uint32_t* __restrict__ count_p, uint64_t capacity,
-                                                       uint32_t* __restrict__ hist) {
-    if ((uint64_t)*count_p > capacity) return;
-    const uint32_t col = blockIdx.x * blockDim.x + threadIdx.x;   // < kMaxPasses * kTileRadix
-    const uint32_t r0 = blockIdx.y * kRowsPerBlock;
-    uint32_t acc = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < kRowsPerBlock; ++q)
-        acc += (r0 + q < n_rows) ? rows[(size_t)(r0 + q) * (kMaxPasses * kTileRadix) + col] : 0u;
-    if (acc) atomicAdd(&hist[col], acc);
+    for (; j < want; ++j) {
+        const uint32_t e = e0 + j;
+        keys[e] = 0xFFFFFFFFu;
+        vals[e] = i;
+        zbits[e] = z;
+    }
 }
 
 // Ranks up to ITEMS items per lane within the wave by a digit of `bits` <= MAXB bits. Items are taken in
@@ -289,11 +244,11 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift,
     }
 }
 
-// Step 5: stable LSD passes over the tile ids (digit of `bits` <= 9 bits at `shift`), each
+// Step 4: stable LSD passes over the tile ids (digit of `bits` <= 9 bits at `shift`), each
 // in three kernels over 4096-entry sort tiles, with no waiting between workgroups:
-//   5a  count     each sort tile's digit counts, stored digit-major
-//   5b  scan      per digit, the exclusive prefix over the sort tiles
-//   5c  scatter   each sort tile ranks its entries per digit within each wave (ballots),
+//   4a  count     each sort tile's digit counts, stored digit-major
+//   4b  scan      per digit, the exclusive prefix over the sort tiles and the total
+//   4c  scatter   each sort tile ranks its entries per digit within each wave (ballots),
 //                 places them at digit base + earlier tiles' count + rank, reorders in LDS
 //                 so that the stores are contiguous runs per digit
 __global__ void __launch_bounds__(kSortThreads) tile_count_kernel(const uint32_t* __restrict__ kin,
@@ -330,7 +285,8 @@ __global__ void __launch_bounds__(kSortThreads) tile_count_kernel(const uint32_t
 }
 
 __global__ void __launch_bounds__(256) tile_scan_kernel(uint32_t* __restrict__ tcount, uint32_t stride,
-                                                        const uint32_t* __restrict__ count_p, uint64_t capacity) {
+                                                        const uint32_t* __restrict__ count_p, uint64_t capacity,
+                                                        uint32_t* __restrict__ hist) {
     __shared__ uint32_t s_tmp[4];
     constexpr uint32_t kItems = 16;   // consecutive sort tiles per thread and chunk
     const uint32_t count = *count_p;
@@ -355,6 +311,7 @@ __global__ void __launch_bounds__(256) tile_scan_kernel(uint32_t* __restrict__ t
         }
         carry += total;
     }
+    if (threadIdx.x == 0) hist[blockIdx.x] = carry;   // this digit's count over all entries
 }
 
 __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
@@ -485,7 +442,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
     }
 }
 
-// Step 6: tile ranges from the sorted tile ids.
+// Step 5: tile ranges from the sorted tile ids.
 __global__ void __launch_bounds__(256) finalize_kernel(const uint32_t* __restrict__ keys,
                                                        const uint32_t* __restrict__ count_p, uint64_t capacity,
                                                        uint32_t tiles_total, uint32_t* __restrict__ ranges) {
@@ -856,8 +813,8 @@ __device__ __forceinline__ void wave_sort_segment(uint32_t* __restrict__ buf, ui
     }
 }
 
-// Step 7a: one wave per tile sorts segments of up to kWaveSegMax entries and appends the
-// longer ones to a list for step 7b.
+// Step 6a: one wave per tile sorts segments of up to kWaveSegMax entries and appends the
+// longer ones to a list for step 6b.
 __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     const uint32_t* __restrict__ ranges, uint32_t tiles_total, const uint32_t* __restrict__ zs,
     uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p,
@@ -879,7 +836,7 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     wave_sort_segment(sh.buf[w], sh.cnt[w], tile, start, n, zs, pidx, keys64);
 }
 
-// Step 7b: a resident grid works through the list of long segments, one workgroup per
+// Step 6b: a resident grid works through the list of long segments, one workgroup per
 // segment, with stable LSD radix passes: in LDS up to kSegMax entries, through the
 // workspace beyond.
 __global__ void __launch_bounds__(kBigThreads) segment_sort_big_kernel(
@@ -936,7 +893,6 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.off_flags = off;      off = align256(off + 64);
     p.off_big_list = off;   off = align256(off + (size_t)tiles * 4);
     p.off_tcount = off;     off = align256(off + (size_t)p.sort_tiles * kTileRadix * 4);
-    p.off_rows = off;       off = align256(off + (size_t)kEmitRows * kMaxPasses * kTileRadix * 4);
     p.bytes = off;
     return p;
 }
@@ -983,14 +939,9 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     uint32_t* v_emit = odd ? vals_alt : bins->pidx;
     uint32_t* v_other = odd ? bins->pidx : vals_alt;
 
-    // 3. emit (per group of views) with the digit counts of the tile passes; 4. their sum
-    static int emit_grid = 0;
-    if (!emit_grid) emit_grid = std::min(kEmitRows, resident_blocks(reinterpret_cast<const void*>(emit_kernel), 256));
-    if (!emit_grid) return -1;
-    uint32_t* rows = reinterpret_cast<uint32_t*>(base + plan.off_rows);
+    // 3. emit (per group of views)
     const DigitSplit tsplit(0, plan.tile_bits, kTileRadixBits);
     uint32_t p_off = 0, tile_base = 0;
-    int launches = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         ViewPack pk{};
         pk.nv = min(kMaxViews, nv - v0);
@@ -1012,18 +963,13 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         }
         pk.block_begin[pk.nv] = blocks;
         if (!blocks) continue;
-        hipLaunchKernelGGL(emit_kernel, dim3((unsigned)emit_grid), dim3(256), 0, stream, pk, blocks,
+        hipLaunchKernelGGL(emit_kernel, dim3(blocks), dim3(256), 0, stream, pk,
                            reinterpret_cast<const float4*>(proj->record), proj->tile_count, bins->offsets,
-                           proj->depth, bins->count, plan.capacity, tsplit, launches > 0 ? 1 : 0, keys_a, v_emit, z_a,
-                           rows);
-        ++launches;
+                           proj->depth, bins->count, plan.capacity, keys_a, v_emit, z_a);
     }
     if (plan.capacity == 0) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
-    if (plan.passes && launches)
-        hipLaunchKernelGGL(sum_rows_kernel, dim3(kMaxPasses * kTileRadix / 256, (emit_grid + kRowsPerBlock - 1) / kRowsPerBlock),
-                           dim3(256), 0, stream, rows, (uint32_t)emit_grid, bins->count, plan.capacity, hist);
 
-    // 5. radix passes over the tile id
+    // 4. radix passes over the tile id
     const uint32_t* kin = keys_a;
     const uint32_t* vin = v_emit;
     const uint32_t* zin = z_a;
@@ -1035,7 +981,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         hipLaunchKernelGGL(tile_count_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, bins->count,
                            plan.capacity, sh, wd, tcount, plan.sort_tiles);
         hipLaunchKernelGGL(tile_scan_kernel, dim3(kTileRadix), dim3(256), 0, stream, tcount, plan.sort_tiles,
-                           bins->count, plan.capacity);
+                           bins->count, plan.capacity, hist + p * kTileRadix);
         hipLaunchKernelGGL(sort_scatter_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, zin,
                            kout, vout, zout, bins->count, plan.capacity, sh, wd, hist + p * kTileRadix, tcount,
                            plan.sort_tiles);
@@ -1049,11 +995,11 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         vout = const_cast<uint32_t*>(tv);
         zout = const_cast<uint32_t*>(tz);
     }
-    // 6. ranges
+    // 5. ranges
     const unsigned fin_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 255) / 256);
     hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks), dim3(256), 0, stream, kin, bins->count, plan.capacity,
                        plan.tiles_total, bins->ranges);
-    // 7. depth order within every tile (zin: depth bits in the order of pidx; the tile-id
+    // 6. depth order within every tile (zin: depth bits in the order of pidx; the tile-id
     // arrays and vals_alt are scratch now)
     if (plan.tiles_total) {
         static int big_grid = 0;

@@ -20,7 +20,7 @@ struct BinSortPlan {
     uint32_t sort_tiles;    // 4096-entry sort tiles for `capacity`
     uint32_t scan_blocks;   // 2048-particle scan blocks
     size_t off_keys_a, off_keys_b, off_vals_alt, off_z_a, off_z_b, off_hist, off_counters, off_block_sums,
-        off_flags, off_big_list, off_tcount, off_rows, bytes;
+        off_flags, off_big_list, off_tcount, bytes;
 };
 
 BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv, uint64_t capacity);
