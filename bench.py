@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of the request trace of the serving measurement (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="skip the 500k 4x720p training step and the 6M 4K stress fwd+bwd")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one copy kernel of known size, then one forward call")
     return ap.parse_args()
@@ -148,6 +150,93 @@ def serving_benchmark(args, dev):
     st["capacity_overflows"] = ex.overflows
     st.pop("pool_bytes", None)
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+
+
+def training_workload(dev, iters=20):
+    """The training step as the workload states it: 500k Gaussians, targets rendered from the
+    ground truth at views 0, 25, 50, 75 of the orbit at 1280x720, parameters from a jittered
+    copy, L1 loss through the autograd function; iterations per second."""
+    import torch
+    import scenegen as S
+    import paper_2403_14244_amd as P
+    gt = S.mixture_scene(500_000, seed=0)
+    init = S.jitter_scene(gt, seed=1)
+    cams = S.workload_cameras("mix500k_720p_x4")
+    R = P.Rasterizer(dev, headroom=1.1)
+    targets = torch.stack(R.render([P.GaussianScene.from_host(gt, dev)] * len(cams), cams)[0])
+    params = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).requires_grad_(True)
+              for a in (init.pos, init.scale, init.opacity, init.color)]
+
+    def step():
+        for q in params:
+            q.grad = None
+        img = P.IsoGSRender.apply(*params, init.sh_degree, cams, (0.0, 0.0, 0.0), R)
+        loss = (img - targets).abs().mean()
+        loss.backward()
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    return {"workload": "mix500k_720p_x4", "iters_per_s": round(1.0 / dt, 2), "ms_per_iter": round(dt * 1e3, 3),
+            "views": len(cams), "width": 1280, "height": 720, "gaussians": 500_000}
+
+
+def stress_workload(dev, iters=3):
+    """6M Gaussians (70% in 16 tight clusters), SH3, 8 views at 3840x2160: forward and
+    backward against L1 targets of the ground truth, parameters from a jittered copy; ms per
+    iteration, and the tile list lengths that skew the load."""
+    import torch
+    import scenegen as S
+    import paper_2403_14244_amd as P
+    gt = S.stress_scene(6_000_000, seed=5)
+    init = S.jitter_scene(gt, seed=1)
+    cams = S.workload_cameras("stress6m_4k_x8")
+    R = P.Rasterizer(dev, headroom=1.1)
+    imgs, st = R.render([P.GaussianScene.from_host(gt, dev)] * len(cams), cams)
+    targets = torch.stack(imgs)
+    lens = (st["bins"].ranges[:, 1] - st["bins"].ranges[:, 0]).long()
+    nz = lens[lens > 0].float()
+    hist = torch.bincount(torch.floor(torch.log2(nz)).long(), minlength=18).tolist()
+    lists = {"tiles": int(lens.numel()), "occupied": int(nz.numel()), "entries": int(lens.sum()),
+             "mean": round(float(nz.mean()), 1), "p50": int(nz.median()), "p99": int(torch.quantile(nz, 0.99)),
+             "max": int(nz.max()), "log2_histogram": {f"[{1 << i},{2 << i})": c for i, c in enumerate(hist) if c}}
+    del imgs, st
+    params = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).requires_grad_(True)
+              for a in (init.pos, init.scale, init.opacity, init.color)]
+
+    def step():
+        for q in params:
+            q.grad = None
+        img = P.IsoGSRender.apply(*params, init.sh_degree, cams, (0.0, 0.0, 0.0), R)
+        loss = (img - targets).abs().mean()
+        loss.backward()
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    # the forward alone (projection, bin sort, compositing) of the same 8 views
+    g_init = P.GaussianScene(*(q.detach() for q in params), init.sh_degree)
+    fwd = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        R.render([g_init] * len(cams), cams, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        fwd.append(e0.elapsed_time(e1))
+    return {"workload": "stress6m_4k_x8", "fwd_bwd_ms_per_iter": round(dt * 1e3, 2),
+            "fwd_ms": round(sorted(fwd)[1], 2), "views": len(cams), "width": 3840, "height": 2160,
+            "gaussians": 6_000_000, "mpix_per_s_fwd": round(len(cams) * 3840 * 2160 / (sorted(fwd)[1] * 1e-3) / 1e6, 1),
+            "tile_lists": lists}
 
 
 def cpu_baseline(scene, cam, budget_s):
@@ -347,6 +436,19 @@ def main():
     it_s = it_by_kernel["ordered"]   # the rasterizer's default for render()
     log(f"fwd+bwd: {it_s:.1f} it/s ({it_by_kernel})")
 
+    extra = {}
+    if not args.no_extra_workloads:
+        del Rt, params
+        torch.cuda.empty_cache()
+        log("training workload (500k, 4 x 1280x720) ...")
+        extra["training_500k_720p_x4"] = training_workload(dev)
+        log(f"training workload: {extra['training_500k_720p_x4']}")
+        torch.cuda.empty_cache()
+        log("stress workload (6M, 8 x 3840x2160) ...")
+        extra["stress_6m_4k_x8"] = stress_workload(dev)
+        log(f"stress workload: {extra['stress_6m_4k_x8']}")
+        torch.cuda.empty_cache()
+
     serving = None
     if args.serve_seconds > 0:
         log("serving ...")
@@ -369,6 +471,7 @@ def main():
         "roofline": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
         "stage_us_per_view": {k: round(v * 1e3 / args.views, 1) for k, v in stage_ms.items()},
         "serving": serving,
+        **extra,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
