@@ -86,12 +86,13 @@ __device__ __forceinline__ TilePixel tile_pixel(const RenderPack& pk, uint32_t l
 // Walks list positions [lo, hi) of the tile (lo a multiple of the batch) with a 256-thread
 // workgroup, one lane per pixel, each 16-lane row owning a 4x4 sub-block, and updates the
 // lanes' states. With `ckpt`, stores the checkpoints at chunk boundaries inside the range.
-// PIPE: software pipelining for a workgroup with few others beside it on its CU (more
-// registers): the LDS reads of the entries of step k + 4 and of the list words of step k + 8
-// are issued while step k is composited, and the global loads of the next batch while the
-// current one is walked, so that the walk does not wait on dependent round trips.
+// PIPE: the global loads of the next batch are issued while the current one is walked.
+// PL (default PIPE): software-pipelined LDS reads as well, for a workgroup with few others
+// beside it on its CU (more registers): the reads of the entries of step k + 4 and of the
+// list words of step k + 8 are issued while step k is composited, so that the walk does not
+// wait on dependent round trips.
 // Contains __syncthreads.
-template <bool TERM, bool PIPE>
+template <bool TERM, bool PIPE, bool PL = PIPE>
 __device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack& pk, const TilePixel& p,
                                                 const float4* __restrict__ record,
                                                 const uint32_t* __restrict__ pidx, uint32_t lo, uint32_t hi,
@@ -130,7 +131,7 @@ __device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack&
             for (int e = 0; e < 4; ++e)
                 composite_entry<TERM>(st.f[e], st.c[e], p.px, p.py, s.T, s.cr, s.cg, s.cb, lastj, s.done);
         };
-        if (!PIPE) {
+        if (!PL) {
             for (uint32_t k = 0; k < steps; k += 4) {
                 Step4 st;
                 load_step(sb, list4_sub(sb, p.sbk, k, len), st);
@@ -178,7 +179,7 @@ __device__ __forceinline__ void write_pixel(const TilePixel& p, const PixelState
 }
 
 // Composites one whole tile (logical index within the launch). Contains __syncthreads.
-template <bool PIPE>
+template <bool PIPE, bool PL = PIPE>
 __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& pk, uint32_t logical,
                                                const float4* __restrict__ record,
                                                const uint32_t* __restrict__ pidx,
@@ -187,16 +188,19 @@ __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& 
                                                uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
     const TilePixel p = tile_pixel(pk, logical, ranges);
     PixelState s{1.0f, 0.0f, 0.0f, 0.0f, 0u, !p.inside};
-    composite_range<true, PIPE>(sb, pk, p, record, pidx, 0, p.len, s, ckpt);
+    composite_range<true, PIPE, PL>(sb, pk, p, record, pidx, 0, p.len, s, ckpt);
     write_pixel(p, s, bg_r, bg_g, bg_b, image, T_final, n_last);
 }
 
-// Register budget of the one-workgroup-per-tile compositing kernel: six waves per SIMD (at
-// most 80 VGPRs, no spills) hide the staging gathers better than the default of five.
-constexpr int kFwdWavesPerSimd = 6;
+// Register budgets: the compact walk of large launches, six waves per SIMD (80 VGPRs), as
+// many resident workgroups as LDS allows hiding the staging gathers; the walk of the
+// remaining tiles of small launches also prefetches the next batch from global memory,
+// five waves per SIMD (at most 102 VGPRs).
+constexpr int kCompactWavesPerSimd = 6;
+constexpr int kPrefetchWavesPerSimd = 5;
 
 // One workgroup per tile, tiles in XCD-banded order.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWavesPerSimd))) composite_fwd_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompactWavesPerSimd))) composite_fwd_kernel(
     const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
     const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
     float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
@@ -204,7 +208,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWa
     __shared__ StagedSub sb;
     if (*status != kStatusOk) return;
     composite_tile<false>(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, ranges, bg_r, bg_g, bg_b, image,
-                   T_final, n_last, ckpt);
+                          T_final, n_last, ckpt);
 }
 
 // ---- Wide walk for the longest tiles of small launches ------------------------------------
@@ -385,9 +389,10 @@ constexpr uint32_t kWideSlots = 512;
 // Longest list first: one workgroup per tile, the tiles taken in the order of a queue
 // sorted by list length, so that the dispatcher starts the long tiles of skewed scenes
 // first instead of leaving them to trail the launch. Two builds of the walk: with many
-// tiles the launch is throughput-bound and the compact one (six waves per SIMD) is faster;
-// with few, it is bound by its longest tiles and the software-pipelined one is.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWavesPerSimd)))
+// tiles the launch is throughput-bound and the compact one is faster; with few, it is bound
+// by its longest tiles and the fully pipelined one is.
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompactWavesPerSimd)))
 composite_fwd_ordered_kernel(const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
                              const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r,
                              float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
@@ -526,8 +531,8 @@ int resident_blocks(const void* kernel, int threads) {
 // Small launches: workgroups [0, 4 wide_slots) take the quadrants of the longest tiles
 // (those of at least 2^kWideMinLog2 entries, counted from the queue's length classes; a
 // workgroup past their number leaves at once) with the wide walk, the others the
-// remaining tiles of the queue with the compact walk.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kFwdWavesPerSimd)))
+// remaining tiles of the queue with the walk that prefetches the next batch.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPrefetchWavesPerSimd)))
 composite_fwd_ordered_wide_kernel(const RenderPack pk, const float4* __restrict__ record,
                                   const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges,
                                   const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
@@ -549,8 +554,8 @@ composite_fwd_ordered_wide_kernel(const RenderPack pk, const float4* __restrict_
     } else {
         const uint32_t j = b - 4 * wide_slots;
         if (j < n_wide) return;
-        composite_tile<false>(*reinterpret_cast<StagedSub*>(smem), pk, order[j], record, pidx, ranges, bg_r, bg_g,
-                              bg_b, image, T_final, n_last, ckpt);
+        composite_tile<true, false>(*reinterpret_cast<StagedSub*>(smem), pk, order[j], record, pidx, ranges, bg_r,
+                                    bg_g, bg_b, image, T_final, n_last, ckpt);
     }
 }
 
