@@ -24,7 +24,7 @@ constexpr int kBwdDummy = kBwdBatch;   // staged slot of the zero-opacity pad re
 // One batch of a tile's entries in LDS, back to front, with the 16 sub-block lists.
 struct StagedBwd {
     float4 fp[kBwdBatch + 1];            // {u, v, q = log2(e)/s^2, log2(o)}
-    float4 col[kBwdBatch + 1];           // {r, g, b, o}
+    float4 col[kBwdBatch + 1];           // {r, g, b, 1/o}
     uint16_t list[16][kBwdBatch + 4];    // per sub-block, staged slots in walk order
     uint32_t slot[kBwdBatch];            // emit position of each staged entry
     uint8_t mask[4][kBwdBatch];          // [wave] which of its sub-blocks listed the entry
@@ -52,7 +52,7 @@ __device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __res
         const float4 c = record[2 * (size_t)g + 1];
         if (w == 0) {
             sb.fp[l] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
-            sb.col[l] = make_float4(c.x, c.y, c.z, f.w);
+            sb.col[l] = make_float4(c.x, c.y, c.z, __builtin_amdgcn_rcpf(f.w));   // once per entry
         } else if (w == 1) {
             sb.slot[l] = emit_slot(offsets[g], f.x, f.y, c.w, tx, ty, tiles_x, tiles_y, w_lim, h_lim);
         }
@@ -219,7 +219,7 @@ __device__ __forceinline__ void composite_bwd_tile(
                 gv[0] = 2.0f * kk * inv_s2 * dx;
                 gv[1] = 2.0f * kk * inv_s2 * dy;
                 gv[2] = -kk * fmaf(dx, dx, dy * dy);
-                gv[3] = kk * __builtin_amdgcn_rcpf(c.w);
+                gv[3] = kk * c.w;
                 gv[4] = dr * wgt;
                 gv[5] = dg * wgt;
                 gv[6] = db * wgt;
