@@ -127,10 +127,10 @@ def _bin_case(name):
     if name == "segment_boundaries":
         # footprints inside one tile each, one segment per view at the size limits of the
         # segment sort's paths: 64 (rank by comparison in one wave), 65, 512 (largest
-        # sorted by one wave), 513, 4096 (largest radix-sorted in LDS), 4097, 8192 (largest
-        # bucketed in LDS) and 8193
+        # sorted by one wave), 513, 1024, 1025, 4096 (largest radix-sorted in LDS by a
+        # workgroup), 4097 (through the workspace), 8192 and 8193
         views, cams = [], []
-        for k, n in enumerate((64, 65, 512, 513, 4096, 4097, 8192, 8193)):
+        for k, n in enumerate((64, 65, 512, 513, 1024, 1025, 4096, 4097, 8192, 8193)):
             u, v, z, r = S.crowded_projected(n, 48, 32, 24.0, 8.0, 2.0, seed=40 + k, max_radius=0.5)
             views.append(H.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
