@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of the request trace of the serving measurement (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-inflight", type=int, default=2,
+                    help="batches in flight at once (one HIP stream each)")
     ap.add_argument("--no-extra-workloads", action="store_true",
                     help="skip the 500k 4x720p training step and the 6M 4K stress fwd+bwd")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -137,11 +139,11 @@ def serving_benchmark(args, dev):
     n = max(1, int(args.serve_seconds * args.serve_rate))
     warm = poisson_trace(100, args.serve_rate, list(scenes), res, seed=3)
     reqs = poisson_trace(n, args.serve_rate, list(scenes), res, seed=4, start_id=1000)
-    ex = GpuExecutor(scenes, dev)
+    ex = GpuExecutor(scenes, dev, n_streams=args.serve_inflight)
     ex.calibrate(warm + reqs)
-    Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=2).run(warm)
+    Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=args.serve_inflight).run(warm)
     torch.cuda.synchronize()
-    srv = Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=2)
+    srv = Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=args.serve_inflight)
     st = srv.run(reqs)
     sel = [r.latency * 1e3 for r in reqs if r.scene == "mix1m" and r.cam.width == 1920]
     st["p99_ms_1080p_1m"] = float(np.percentile(sel, 99)) if sel else None
