@@ -14,6 +14,8 @@
  *   isogs_project    particles -> screen footprints and per-particle tile counts
  *   isogs_bin_sort   footprints -> (tile, depth)-sorted entry lists per 16x16 tile
  *   isogs_render_fwd entry lists -> image, final transmittance, last contributor
+ *                    (isogs_render_fwd_ordered: the same with the tiles dispatched
+ *                    longest list first)
  *   isogs_render_bwd dL/dimage -> dL/d(particle parameters), for back-propagation
  *                    (the optimisation mode of Section 3, "Optimization")
  *
