@@ -192,15 +192,14 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
  * start first instead of trailing the launch. Launches of few tiles (at most 24576 per group
  * of 16 views) use a software-pipelined walk that shortens the longest tiles; larger ones a
  * compact walk that keeps more workgroups resident.
- *   flags  0, or ISOGS_FWD_WIDE: in launches of at most 24576 tiles, the (at most 512)
- *          tiles of at least 2048 entries are composited by four workgroups each, one per
- *          8x8 quadrant, with four lanes per pixel that take the four entries of a list
- *          step together (transmittance products scanned across the lanes, the stopping
- *          entry found exactly, colour terms summed). Those tiles then agree with
- *          isogs_render_fwd up to rounding (products and sums associated per step) instead
- *          of bitwise, and which tiles take the wide walk depends on the whole launch; a
- *          single 1080p view composites about twice as fast. Without the flag the result
- *          of a view does not depend on the other views of the launch.
+ *   flags  0, or ISOGS_FWD_WIDE: every tile of at least 2048 entries is composited by
+ *          four workgroups, one per 8x8 quadrant, with four lanes per pixel that take the
+ *          four entries of a list step together (transmittance products scanned across
+ *          the lanes, the stopping entry found exactly, colour terms summed). Those tiles
+ *          then agree with isogs_render_fwd up to rounding (products and sums associated
+ *          per step) instead of bitwise; a single 1080p view composites about twice as
+ *          fast. With or without the flag, a view's result does not depend on the other
+ *          views of the launch.
  *   ws, ws_bytes  workspace (query with ws == NULL): the queue, 4 bytes per tile of the
  *                 largest group of 16 views, plus bookkeeping
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */

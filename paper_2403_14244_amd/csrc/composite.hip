@@ -380,11 +380,10 @@ __device__ __forceinline__ void composite_quadrant(StagedQuad& sq, const RenderP
     }
 }
 
-// With the wide flag, tiles of at least 2^kWideMinLog2 entries (length classes above
-// kWideMinLog2) take the wide walk in small launches, at most kWideSlots of them (the
-// longest).
+// With the wide flag, every tile of at least 2^kWideMinLog2 entries (length classes above
+// kWideMinLog2) takes the wide walk: a decision of the tile alone, so a view's result does
+// not depend on the other views of the launch.
 constexpr int kWideMinLog2 = 11;
-constexpr uint32_t kWideSlots = 512;
 
 // Longest list first: one workgroup per tile, the tiles taken in the order of a queue
 // sorted by list length, so that the dispatcher starts the long tiles of skewed scenes
@@ -528,10 +527,11 @@ int resident_blocks(const void* kernel, int threads) {
     return cus * per_cu;
 }
 
-// Small launches: workgroups [0, 4 wide_slots) take the quadrants of the longest tiles
-// (those of at least 2^kWideMinLog2 entries, counted from the queue's length classes; a
-// workgroup past their number leaves at once) with the wide walk, the others the
-// remaining tiles of the queue with the walk that prefetches the next batch.
+// Workgroups [0, 4 wide_slots) take the quadrants of the long tiles (those of at least
+// 2^kWideMinLog2 entries: the first ones of the queue, counted from its length classes;
+// wide_slots bounds their number, and a workgroup past it leaves at once) with the wide
+// walk, the others the remaining tiles of the queue with the walk that prefetches the next
+// batch.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPrefetchWavesPerSimd)))
 composite_fwd_ordered_wide_kernel(const RenderPack pk, const float4* __restrict__ record,
                                   const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges,
@@ -572,8 +572,10 @@ int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_
         set_render_limits(pk, n_per_view, nv, bins->capacity);
         if (!blocks) continue;
         const uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
-        if (blocks <= kPipeTileLimit && (flags & ISOGS_FWD_WIDE)) {
-            const uint32_t wide_slots = std::min<uint32_t>(blocks, kWideSlots);
+        if (flags & ISOGS_FWD_WIDE) {
+            // a long tile holds at least 2^kWideMinLog2 of the group's entries
+            const uint32_t wide_slots =
+                (uint32_t)std::min<uint64_t>(blocks, (uint64_t)pk.n_entries_cap / (1u << kWideMinLog2) + 1);
             hipLaunchKernelGGL(composite_fwd_ordered_wide_kernel, dim3(4 * wide_slots + blocks), dim3(256), 0, stream,
                                pk, reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges,
                                bins->status, bg[0], bg[1], bg[2], image, T_final, n_last,

@@ -5,7 +5,9 @@ views. A batch is formed whenever an execution slot is free, from every request 
 arrived and fits the memory pool; requests that arrive while batches are running are
 admitted as soon as a slot and pool memory free up, and up to `max_inflight` batches run
 concurrently on separate HIP streams, so their work overlaps on the device. Each batch is
-one projection (grouped by scene), one bin sort and one longest-list-first compositing launch.
+one projection (grouped by scene), one bin sort and one longest-list-first compositing launch
+(tiles of at least 2048 entries with the wide walk, a decision of each tile alone, so a
+request's image does not depend on the batch it ran in).
 
 The scheduler is written against a small executor interface so that its admission,
 batching and statistics logic also runs on the CPU with a simulated executor and a
@@ -271,7 +273,7 @@ class GpuExecutor(Executor):
         with torch.cuda.stream(s):
             fp = R.project(scenes, cams)
             bins = R.bin_sort(fp, npv, cams, check=False, capacity=cap)
-            img, T, nl = R.render_fwd_ordered(fp, npv, bins, cams)
+            img, T, nl = R.render_fwd_ordered(fp, npv, bins, cams, wide=True)
             status = torch.empty(2, dtype=torch.int32, pin_memory=True)
             status[0:1].copy_(bins.status, non_blocking=True)
             status[1:2].copy_(bins.count, non_blocking=True)
@@ -295,7 +297,7 @@ class GpuExecutor(Executor):
             with torch.cuda.stream(self.streams[h["si"]]):
                 bins = R.bin_sort(h["fp"], h["npv"], h["cams"], check=True,
                                   capacity=int(count * self.headroom) + 4096)
-                img, _, _ = R.render_fwd_ordered(h["fp"], h["npv"], bins, h["cams"])
+                img, _, _ = R.render_fwd_ordered(h["fp"], h["npv"], bins, h["cams"], wide=True)
             self.streams[h["si"]].synchronize()
         for r, im in zip(h["batch"], split_images(img, h["cams"])):
             r.result = im

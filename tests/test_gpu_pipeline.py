@@ -438,6 +438,35 @@ def test_render_bwd_checkpoints_all_list_lengths(P, torch_cuda):
         _grad_check(a, b.astype(np.float64), name, rel=1e-4, floor=1e-5)
 
 
+def test_wide_forward_independent_of_launch(P, torch_cuda):
+    """The wide walk is chosen per tile: a view with tiles of thousands of entries gives
+    the same outputs, bitwise, composited alone and as the first of sixteen views in a
+    launch of 25,000+ tiles."""
+    torch = torch_cuda
+    rng = np.random.default_rng(80)
+    base = S.uniform_cube_scene(6000, seed=80, log_scale_mean=math.log(0.06), log_scale_std=0.3)
+    opac = rng.uniform(0.01, 0.05, base.pos.shape[1]).astype(np.float32)
+    sc = S.Scene(base.pos, base.scale, opac, base.color, 0)
+    cam0 = S.look_at_camera((0.0, 0.0, 3.2), width=48, height=40)
+    cams = [cam0] + [S.orbit_camera(0.3 * i, 4.0, 656, 656) for i in range(15)]
+    note("wide forward: alone vs in a 16-view launch")
+    R = P.Rasterizer()
+    g = P.GaussianScene.from_host(sc)
+    outs = []
+    for cc in ([cam0], cams):
+        fp = R.project([g] * len(cc), cc)
+        b = R.bin_sort(fp, [g.n] * len(cc), cc)
+        lens = (b.ranges[:, 1] - b.ranges[:, 0]).cpu().numpy()
+        assert lens[:9].max() > 3 * 1024
+        outs.append(R.render_fwd_ordered(fp, [g.n] * len(cc), b, cc, (0.2, 0.1, 0.3), wide=True))
+    torch.cuda.synchronize()
+    n0 = 48 * 40
+    assert sum(((int(c.width) + 15) // 16) * ((int(c.height) + 15) // 16) for c in cams) > 24576
+    assert torch.equal(outs[0][0], outs[1][0][:3 * n0])
+    assert torch.equal(outs[0][1], outs[1][1][:n0])
+    assert torch.equal(outs[0][2], outs[1][2][:n0])
+
+
 @pytest.mark.parametrize("wide", [False, True], ids=["pipelined", "wide"])
 @pytest.mark.parametrize("scale,opacity", [(0.06, (0.005, 0.03)), (0.25, (0.02, 0.08))])
 def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity, wide):

@@ -80,7 +80,7 @@ def test_served_images_equal_alone_and_in_mix(P):
     assert st["requests"] == 40 and st["mean_batch"] > 1.0
     R = P.Rasterizer()
     for r in reqs:
-        alone, _ = R.render([dev[r.scene]], [r.cam])
+        alone, _ = R.render([dev[r.scene]], [r.cam], wide=True)   # the serving walk
         assert torch.equal(alone[0], r.result), r.rid
     # and a few against the oracle (end to end, FP64)
     for r in reqs[:3]:
