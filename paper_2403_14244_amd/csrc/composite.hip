@@ -503,14 +503,14 @@ uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv) {
     return most;
 }
 
-size_t tile_queue_words(uint32_t n_tiles) { return 2 * kBuckets + 1 + (size_t)n_tiles; }
+size_t tile_queue_words(uint32_t n_tiles) { return 2 * kBuckets + (size_t)n_tiles; }
 
 uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0, uint32_t n_tiles, uint32_t cap,
                             hipStream_t stream) {
     uint32_t* hist = q;
     uint32_t* cursor = q + kBuckets;
-    uint32_t* order = q + 2 * kBuckets + 1;
-    hipLaunchKernelGGL(fill_u32_kernel_c, dim3(1), dim3(128), 0, stream, q, (uint32_t)(2 * kBuckets + 1));
+    uint32_t* order = q + 2 * kBuckets;
+    hipLaunchKernelGGL(fill_u32_kernel_c, dim3(1), dim3(128), 0, stream, q, (uint32_t)(2 * kBuckets));
     const unsigned hb = std::min<unsigned>(256u, (n_tiles + 255u) / 256u);
     hipLaunchKernelGGL(tile_class_hist_kernel, dim3(hb), dim3(256), 0, stream, ranges, tile0, n_tiles, cap, hist);
     hipLaunchKernelGGL(tile_class_scatter_kernel, dim3((n_tiles + 255u) / 256u), dim3(256), 0, stream, ranges, tile0,

@@ -35,7 +35,8 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
 size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv);
 
 // Longest-list-first tile queue of one launch group: words needed, the largest group, the
-// launch (returns the order array; the queue counter is the word before it).
+// launch. The queue holds the length-class histogram (its first kBuckets words, read by
+// the compositing kernels), the class cursors, and the order array (returned).
 size_t tile_queue_words(uint32_t n_tiles);
 uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv);
 uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0, uint32_t n_tiles, uint32_t cap,
