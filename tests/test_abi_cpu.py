@@ -128,3 +128,24 @@ def test_negative_view_particle_counts_rejected():
     proj = A.Projected()
     assert L.isogs_bin_sort(ctypes.byref(proj), A.int_array([-3]), cams, 1, ctypes.byref(bins), None,
                             ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+
+
+def test_ordered_forward_rejects_unknown_flags():
+    """Every argument is well formed except ``flags``: the call must fail before any launch."""
+    A = _abi()
+    L = A.lib()
+    cams = A.camera_array([_cam(64, 48)])
+    npv = A.int_array([10])
+    fake = 1 << 20                      # 256-byte aligned addresses that are never dereferenced
+    proj = A.Projected(fake, fake, fake)
+    bins = A.Bins(fake, fake, fake, fake, 100, fake, fake)
+    bg = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    need = ctypes.c_size_t(0)
+    assert L.isogs_render_fwd_ordered(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, None, None,
+                                      None, None, 0, None, ctypes.byref(need), None) == A.ISOGS_OK
+    out = ctypes.c_void_p(fake)
+    for flags in (2, 1 << 31, A.ISOGS_FWD_WIDE | 4):
+        assert L.isogs_render_fwd_ordered(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, out, out,
+                                          out, None, flags, ctypes.c_void_p(fake), ctypes.byref(need),
+                                          None) == A.ISOGS_ERR_INVALID
+        assert b"flags" in L.isogs_last_error()
