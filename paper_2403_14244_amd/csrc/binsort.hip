@@ -251,6 +251,10 @@ __device__ __forceinline__ void wave_rank(const uint32_t (&k)[ITEMS], int shift,
 //   4c  scatter   each sort tile ranks its entries per digit within each wave (ballots),
 //                 places them at digit base + earlier tiles' count + rank, reorders in LDS
 //                 so that the stores are contiguous runs per digit
+// Count and scatter give each XCD a contiguous range of sort tiles (xcd_swizzle over the
+// tiles in use): neighbouring sort tiles write neighbouring words of the digit-major counts
+// and, for a digit, adjacent pieces of its output run, so the partial cache lines they
+// leave are completed in one L2 instead of being written back separately from several.
 __global__ void __launch_bounds__(kSortThreads) tile_count_kernel(const uint32_t* __restrict__ kin,
                                                                   const uint32_t* __restrict__ count_p,
                                                                   uint64_t capacity, int shift, int bits,
@@ -258,8 +262,9 @@ __global__ void __launch_bounds__(kSortThreads) tile_count_kernel(const uint32_t
     __shared__ uint32_t s_h[kTileRadix];
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    const uint32_t tile = blockIdx.x, t = threadIdx.x;
-    if (tile * kSortTile >= count) return;
+    const uint32_t n_tiles = (count + kSortTile - 1) / kSortTile;
+    if (blockIdx.x >= n_tiles) return;
+    const uint32_t tile = xcd_swizzle(blockIdx.x, n_tiles), t = threadIdx.x;
     s_h[t] = 0u;
     s_h[t + 256] = 0u;
     __syncthreads();
@@ -328,8 +333,9 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
 
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    const uint32_t tile = blockIdx.x;
-    if (tile * kSortTile >= count) return;
+    const uint32_t n_tiles = (count + kSortTile - 1) / kSortTile;
+    if (blockIdx.x >= n_tiles) return;
+    const uint32_t tile = xcd_swizzle(blockIdx.x, n_tiles);
     const uint32_t t = threadIdx.x, w = t >> 6, lane = t & 63;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -813,13 +819,20 @@ __device__ __forceinline__ void wave_sort_segment(uint32_t* __restrict__ buf, ui
     }
 }
 
+// The long segments are listed for step 6b in kLongLists lists, tile t in list t mod
+// kLongLists, each with its own counter on its own 128-byte line: appends to one device-wide
+// counter are serialised in memory (the XCDs' L2s are not coherent), while appends to
+// different lines proceed in parallel.
+constexpr uint32_t kLongLists = 64;
+constexpr uint32_t kLongCounterStride = 32;   // words: one counter per 128-byte line
+
 // Step 6a: one wave per tile sorts segments of up to kWaveSegMax entries and appends the
-// longer ones to a list for step 6b.
+// longer ones to the lists for step 6b.
 __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     const uint32_t* __restrict__ ranges, uint32_t tiles_total, const uint32_t* __restrict__ zs,
     uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p,
-    uint64_t capacity, const int32_t* __restrict__ status, uint32_t* __restrict__ big_list,
-    uint32_t* __restrict__ big_count) {
+    uint64_t capacity, const int32_t* __restrict__ status, uint32_t* __restrict__ long_lists,
+    uint32_t* __restrict__ long_counts) {
     __shared__ WaveSegShared sh;
     if (*status != kStatusOk) return;
     if ((uint64_t)*count_p > capacity) return;
@@ -830,27 +843,44 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     if (end <= start) return;
     const uint32_t n = end - start;
     if (n > kWaveSegMax) {
-        if (lane_id() == 0) big_list[atomicAdd(big_count, 1u)] = tile;
+        if (lane_id() == 0) {
+            const uint32_t j = tile % kLongLists, per = (tiles_total + kLongLists - 1) / kLongLists;
+            long_lists[j * per + atomicAdd(&long_counts[j * kLongCounterStride], 1u)] = tile;
+        }
         return;
     }
     wave_sort_segment(sh.buf[w], sh.cnt[w], tile, start, n, zs, pidx, keys64);
 }
 
-// Step 6b: a resident grid works through the list of long segments, one workgroup per
-// segment, with stable LSD radix passes: in LDS up to kSegMax entries, through the
-// workspace beyond.
-__global__ void __launch_bounds__(kBigThreads) segment_sort_big_kernel(
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
-    uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p, uint64_t capacity,
-    const int32_t* __restrict__ status, const uint32_t* __restrict__ big_list,
-    const uint32_t* __restrict__ big_count, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
+// Step 6b: a resident grid of G workgroups sorts the listed long segments, workgroup g
+// taking items g, g + G, g + 2G, ... of the lists read one after another, one segment at a
+// time, with stable LSD radix passes: in LDS up to kSegMax entries, through the workspace
+// beyond. The sort is bound by the latency of its barriers and ballot chains, not by
+// bytes, so the kernel is held to 64 VGPRs: four workgroups per CU instead of two.
+__global__ void __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(8))) segment_sort_big_kernel(
+    const uint32_t* __restrict__ ranges, uint32_t tiles_total, const uint32_t* __restrict__ zs,
+    uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p,
+    uint64_t capacity, const int32_t* __restrict__ status, const uint32_t* __restrict__ long_lists,
+    const uint32_t* __restrict__ long_counts, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
     uint32_t* __restrict__ sv) {
     __shared__ SegShared sh;
+    __shared__ uint32_t s_first[kLongLists + 1];   // index of each list's first item in the sequence
     if (*status != kStatusOk) return;
     if ((uint64_t)*count_p > capacity) return;
-    const uint32_t nb = *big_count;
-    for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
-        const uint32_t tile = big_list[i];
+    const uint32_t t = threadIdx.x;
+    if (t < kWave) {
+        static_assert(kLongLists == kWave, "one lane per list");
+        const uint32_t c = long_counts[t * kLongCounterStride];
+        const uint32_t incl = wave_inclusive_scan(c);
+        s_first[t + 1] = incl;
+        if (t == 0) s_first[0] = 0u;
+    }
+    __syncthreads();
+    const uint32_t total = s_first[kLongLists], per = (tiles_total + kLongLists - 1) / kLongLists;
+    uint32_t j = 0;
+    for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
+        while (s_first[j + 1] <= i) ++j;   // items ascend, so the list index only grows
+        const uint32_t tile = long_lists[j * per + (i - s_first[j])];
         const uint32_t start = ranges[2 * tile], n = ranges[2 * tile + 1] - start;
         if (n <= kSegMax)
             segment_sort_lds(sh, tile, start, n, zs, pidx, keys64);
@@ -886,12 +916,11 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.off_vals_alt = off;   off = align256(off + capacity * 4);
     p.off_z_a = off;        off = align256(off + capacity * 4);
     p.off_z_b = off;        off = align256(off + capacity * 4);
-    // zero-initialised region: histograms and the long-segment count (contiguous)
+    // zero-initialised region: the digit totals of the passes and the long-segment counts
     p.off_hist = off;       off += (size_t)kMaxPasses * kTileRadix * 4;
-    p.off_counters = off;   off = align256(off + 4 * 4);
+    p.off_long_counts = off; off = align256(off + (size_t)kLongLists * kLongCounterStride * 4);
     p.off_block_sums = off; off = align256(off + (size_t)(p.scan_blocks + 1) * 4);
-    p.off_flags = off;      off = align256(off + 64);
-    p.off_big_list = off;   off = align256(off + (size_t)tiles * 4);
+    p.off_long_lists = off; off = align256(off + (size_t)(tiles + kLongLists) * 4);
     p.off_tcount = off;     off = align256(off + (size_t)p.sort_tiles * kTileRadix * 4);
     p.bytes = off;
     return p;
@@ -906,7 +935,6 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
     uint32_t* z_a = reinterpret_cast<uint32_t*>(base + plan.off_z_a);
     uint32_t* z_b = reinterpret_cast<uint32_t*>(base + plan.off_z_b);
     uint32_t* hist = reinterpret_cast<uint32_t*>(base + plan.off_hist);
-    uint32_t* counters = reinterpret_cast<uint32_t*>(base + plan.off_counters);
     uint32_t* tcount = reinterpret_cast<uint32_t*>(base + plan.off_tcount);
     uint32_t* block_sums = reinterpret_cast<uint32_t*>(base + plan.off_block_sums);
 
@@ -1005,14 +1033,15 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         static int big_grid = 0;
         if (!big_grid) big_grid = resident_blocks(reinterpret_cast<const void*>(segment_sort_big_kernel), kBigThreads);
         if (!big_grid) return -1;
-        uint32_t* big_count = counters;
-        uint32_t* big_list = reinterpret_cast<uint32_t*>(base + plan.off_big_list);
+        uint32_t* long_counts = reinterpret_cast<uint32_t*>(base + plan.off_long_counts);
+        uint32_t* long_lists = reinterpret_cast<uint32_t*>(base + plan.off_long_lists);
         hipLaunchKernelGGL(segment_sort_small_kernel, dim3((plan.tiles_total + 3) / 4), dim3(kSortThreads), 0, stream,
                            bins->ranges, plan.tiles_total, zin, bins->pidx, bins->keys, bins->count,
-                           plan.capacity, bins->status, big_list, big_count);
+                           plan.capacity, bins->status, long_lists, long_counts);
         hipLaunchKernelGGL(segment_sort_big_kernel, dim3((unsigned)std::min<uint32_t>(plan.tiles_total, big_grid)),
-                           dim3(kBigThreads), 0, stream, bins->ranges, zin, bins->pidx, bins->keys,
-                           bins->count, plan.capacity, bins->status, big_list, big_count, keys_a, keys_b, vals_alt);
+                           dim3(kBigThreads), 0, stream, bins->ranges, plan.tiles_total, zin, bins->pidx,
+                           bins->keys, bins->count, plan.capacity, bins->status, long_lists, long_counts, keys_a,
+                           keys_b, vals_alt);
     }
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }

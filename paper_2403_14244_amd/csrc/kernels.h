@@ -15,12 +15,12 @@ struct BinSortPlan {
     uint64_t capacity;
     uint32_t n_total;       // packed particles over all views
     uint32_t tiles_total;   // global tiles over all views
-    int passes;             // radix passes (digits of at most 8 bits) over the tile id
+    int passes;             // radix passes (digits of at most 9 bits) over the tile id
     int tile_bits;          // bits of the largest global tile id
     uint32_t sort_tiles;    // 4096-entry sort tiles for `capacity`
     uint32_t scan_blocks;   // 2048-particle scan blocks
-    size_t off_keys_a, off_keys_b, off_vals_alt, off_z_a, off_z_b, off_hist, off_counters, off_block_sums,
-        off_flags, off_big_list, off_tcount, bytes;
+    size_t off_keys_a, off_keys_b, off_vals_alt, off_z_a, off_z_b, off_hist, off_long_counts,
+        off_block_sums, off_long_lists, off_tcount, bytes;
 };
 
 BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv, uint64_t capacity);
