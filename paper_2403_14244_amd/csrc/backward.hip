@@ -259,21 +259,43 @@ __global__ void __launch_bounds__(64) fill_u32_kernel_b(uint32_t* __restrict__ p
 }
 
 // Work items of the tiles whose list is longer than one checkpoint chunk: one
-// (tile, chunk) pair per chunk, appended in any order.
+// (tile, chunk) pair per chunk, appended in any order, with one device-wide add per
+// workgroup (adds to one counter from many XCDs are serialised in memory).
 __global__ void __launch_bounds__(256) bwd_chunk_list_kernel(const uint32_t* __restrict__ ranges, uint32_t tile0,
                                                              uint32_t n_tiles, uint32_t cap,
                                                              const int32_t* __restrict__ status,
                                                              uint32_t* __restrict__ heavy,
                                                              uint32_t* __restrict__ heavy_count,
                                                              uint32_t heavy_max) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_tiles || *status != kStatusOk) return;
-    const uint32_t s = ranges[2 * (tile0 + i)], e = min(ranges[2 * (tile0 + i) + 1], cap);
-    const uint32_t len = e > s ? e - s : 0u;
-    if (!chunked_list(len)) return;
-    const uint32_t nch = (len + kCkptChunk - 1) / kCkptChunk;
-    const uint32_t base = atomicAdd(heavy_count, nch);
-    if (base + nch > heavy_max) return;   // cannot happen for ranges that partition the entries
+    __shared__ uint32_t s_wave[4];
+    __shared__ uint32_t s_base;
+    if (*status != kStatusOk) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    uint32_t nch = 0;
+    if (i < n_tiles) {
+        const uint32_t s = ranges[2 * (tile0 + i)], e = min(ranges[2 * (tile0 + i) + 1], cap);
+        const uint32_t len = e > s ? e - s : 0u;
+        if (chunked_list(len)) nch = (len + kCkptChunk - 1) / kCkptChunk;
+    }
+    uint32_t incl = nch;
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wave[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t c = s_wave[q];
+        before += q < w ? c : 0u;
+        total += c;
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(heavy_count, total) : 0u;
+    __syncthreads();
+    const uint32_t base = s_base + before + incl - nch;
+    if (!nch || base + nch > heavy_max) return;   // the bound holds for ranges that partition the entries
     for (uint32_t c = 0; c < nch; ++c) {
         heavy[2 * (base + c)] = i;
         heavy[2 * (base + c) + 1] = c;
