@@ -6,3 +6,4 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` an
 from .isogs64 import *  # noqa: F401,F403
 from .isogs64 import (ALPHA_MIN, ALPHA_MAX, T_MIN, TILE, RADIUS_GROW, RADIUS_PAD,  # noqa: F401
                       ALPHA_FLAG_REL, TERM_FLAG_REL)
+from . import field2d64  # noqa: F401  (2D kernel-sum representation of Section 3)

@@ -26,6 +26,7 @@ __all__ = [
     "Scene", "Camera", "look_at_camera", "orbit_camera", "uniform_cube_scene",
     "mixture_scene", "stress_scene", "jitter_scene", "subset_scene",
     "WORKLOADS", "workload_scene", "workload_cameras", "random_projected",
+    "field2d_target", "field2d_init",
 ]
 
 
@@ -265,3 +266,50 @@ def random_projected(n, width, height, seed=0, max_radius=12.0, depth_ties=False
     if depth_ties:
         z = rng.choice(np.array([1.0, 1.5, 2.0, 2.0000002]), size=n)
     return u.astype(np.float32), v.astype(np.float32), z.astype(np.float32), r.astype(np.float32)
+
+
+# --------------------------------------------------------------------------------------
+# 2D image fitting (the paper's 2D experiment): a procedural target image and a random
+# initial set of particles. Draws only; the kernel sum itself lives elsewhere.
+# --------------------------------------------------------------------------------------
+
+def field2d_target(width=512, height=512, seed=20) -> np.ndarray:
+    """Procedural RGB target [3][H][W] in [0, 1] (a stand-in for the paper's images, which
+    are not available): a linear colour ramp, 12 filled discs of random colour and radius
+    16-80 px, and a band of sinusoidal stripes. Draws: ramp direction and end colours,
+    then per disc centre, radius, colour, then the band's row range, period and phase."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64) + 0.5
+    ang = rng.uniform(0.0, 2.0 * math.pi)
+    c0, c1 = rng.uniform(0.0, 1.0, 3), rng.uniform(0.0, 1.0, 3)
+    t = ((xx - width / 2) * math.cos(ang) + (yy - height / 2) * math.sin(ang)) / max(width, height) + 0.5
+    t = t.clip(0.0, 1.0)
+    img = c0[:, None, None] * (1.0 - t) + c1[:, None, None] * t
+    for _ in range(12):
+        cx, cy = rng.uniform(0, width), rng.uniform(0, height)
+        rad = rng.uniform(16.0, 80.0)
+        col = rng.uniform(0.0, 1.0, 3)
+        m = (xx - cx) ** 2 + (yy - cy) ** 2 < rad * rad
+        img[:, m] = col[:, None]
+    y0 = rng.uniform(0.6, 0.8) * height
+    y1 = y0 + rng.uniform(0.08, 0.15) * height
+    period, phase = rng.uniform(6.0, 20.0), rng.uniform(0.0, 2.0 * math.pi)
+    band = (yy >= y0) & (yy < y1)
+    stripes = 0.5 + 0.5 * np.sin(2.0 * math.pi * xx / period + phase)
+    img[:, band] = stripes[band][None, :]
+    return img.astype(np.float32)
+
+
+def field2d_init(target: np.ndarray, K: int, seed=21):
+    """Random initial particles for fitting `target` [3][H][W] (the paper's random
+    initialisation): centres uniform over the image, scale half the width of one cell of
+    a K-cell partition of the image, amplitude the target colour of the pixel under the
+    centre. Returns (mu [2][K], sigma [K], amp [3][K]) in FP32."""
+    rng = np.random.default_rng(seed)
+    _, H, W = target.shape
+    mu = np.stack([rng.uniform(0.0, W, K), rng.uniform(0.0, H, K)])
+    sigma = np.full(K, 0.5 * math.sqrt(W * H / K))
+    ix = np.clip(mu[0].astype(np.int64), 0, W - 1)
+    iy = np.clip(mu[1].astype(np.int64), 0, H - 1)
+    amp = target[:, iy, ix].astype(np.float64)
+    return mu.astype(np.float32), sigma.astype(np.float32), amp.astype(np.float32)
