@@ -18,6 +18,8 @@
  *                    longest list first)
  *   isogs_render_bwd dL/dimage -> dL/d(particle parameters), for back-propagation
  *                    (the optimisation mode of Section 3, "Optimization")
+ * and, for the 2D kernel-sum representation of Section 3 (no compositing),
+ * isogs_field2d_bin / isogs_field2d_fwd / isogs_field2d_bwd on the same bins.
  *
  * Conventions shared by every call:
  *   - Every buffer pointer is DEVICE memory owned by the caller, except the arrays of
@@ -237,6 +239,57 @@ int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_
                      const float* image, const float* dL_dimage, const float* T_final,
                      const uint32_t* n_last, const float* checkpoints, const isogs_scene* grads,
                      void* ws, size_t* ws_bytes, void* stream);
+
+/* ---- 2D kernel-sum representation (Section 3, "Our Method") --------------------------
+ * An image signal represented by K weighted isotropic kernels, with no compositing:
+ *   f_c(x) = sum over k with |x - mu_k| < D of A_kc exp(-|x - mu_k|^2 / sigma_k^2)
+ * (the reconstruction equation of Section 3, the support region of eq. 2, the kernel of
+ * eq. 8), for pixel centres x = (i + 1/2, j + 1/2), x right and y down, channels
+ * c = 0, 1, 2. The support test is strict and taken in FP32 one operation at a time:
+ * dx = x - mu_x, dy likewise, include iff dx*dx + dy*dy < D*D. A particle with a
+ * non-finite parameter or sigma <= 0 contributes nothing and gets zero gradients.
+ * The calls reuse the splatting path's footprints, bins and sort: every particle is a
+ * disk of radius D (record {mu_x, mu_y, 1/sigma^2, 0, A_0, A_1, A_2, D}, depth 1), so each
+ * tile's list keeps particle order and every pixel's sum is taken in that fixed order. */
+typedef struct {
+    float* mu;      /* [2][K] centres, pixels */
+    float* sigma;   /* [K] scales sigma > 0, pixels */
+    float* amp;     /* [3][K] amplitudes A_k (the particle's colour) */
+    int32_t K;
+} isogs_field2d;
+
+/* Footprints and tile lists of a 2D signal on a width x height image with support D.
+ *   field       host struct of device arrays (read only here)
+ *   fp          output footprints: record [K][8] (32-byte aligned), depth [K], tile_count [K]
+ *   bins        as for isogs_bin_sort: one view of ceil(W/16) * ceil(H/16) tiles
+ *   ws, ws_bytes  the isogs_bin_sort workspace of this capacity and one view (query with
+ *                 ws == NULL)
+ * Errors: ISOGS_ERR_INVALID (NULL arrays with K > 0, K < 0, width/height <= 0, D not
+ * finite or <= 0), ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE; capacity overflow is reported
+ * in *bins->status on the device. */
+int isogs_field2d_bin(const isogs_field2d* field, int32_t width, int32_t height, float support,
+                      const isogs_projected* fp, const isogs_bins* bins, void* ws, size_t* ws_bytes,
+                      void* stream);
+
+/* The image [3][H][W] of the signal binned by isogs_field2d_bin (same width, height, D):
+ * one workgroup per tile, one lane per pixel, kernels added in list (particle) order.
+ * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_DEVICE. */
+int isogs_field2d_fwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width,
+                      int32_t height, float support, float* image, void* stream);
+
+/* Gradients of a loss with respect to mu, sigma and A, given dL/dimage [3][H][W]:
+ *   dL/dA_kc  = sum_x w_c(x) g_k(x),  with w = dL/dimage and g_k the kernel of particle k
+ *   dL/dmu_k  = sum_x (sum_c w_c A_kc) g_k(x) 2 (x - mu_k) / sigma_k^2
+ *   dL/dsigma = sum_x (sum_c w_c A_kc) g_k(x) 2 |x - mu_k|^2 / sigma_k^3
+ * Each (tile, particle) entry's six sums over the tile's pixels are formed in a fixed
+ * order and stored at its emit position; each particle then adds its entries in
+ * row-major tile order (bitwise reproducible, no atomics).
+ *   grads       host struct of device OUTPUT arrays of the field's shapes (overwritten)
+ *   ws, ws_bytes  32 bytes per entry of capacity (query with ws == NULL, 256-byte aligned)
+ * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
+int isogs_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width,
+                      int32_t height, float support, const float* dL_dimage, const isogs_field2d* grads,
+                      void* ws, size_t* ws_bytes, void* stream);
 
 /* Message describing the last error returned on the calling thread ("" if none). */
 const char* isogs_last_error(void);

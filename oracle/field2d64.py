@@ -20,7 +20,7 @@ pixels. Readings where the paper is silent:
   time (dx = x - mu_x, dy likewise, d2 = dx*dx + dy*dy, include iff d2 < D*D), the same
   decision the GPU takes on the same FP32 inputs; everything else is FP64;
 * a particle with a non-finite parameter or sigma <= 0 contributes nothing (and gets
-  zero gradients);
+  zero gradients), and so does one whose 1/sigma^2 overflows in FP32 (sigma < ~1e-19);
 * the loss of the paper's fit is read as its L1 term, mean |f - target| over channels
   and pixels (the SSIM term is not on this path); its gradient is
   sign(f - target) / numel with sign(0) = 0.
@@ -53,7 +53,10 @@ def _valid(mu, sigma, amp):
     mu = np.asarray(mu, dtype=np.float32)
     sigma = np.asarray(sigma, dtype=np.float32)
     amp = np.asarray(amp, dtype=np.float32)
-    ok = np.isfinite(mu).all(axis=0) & np.isfinite(sigma) & (sigma > 0) & np.isfinite(amp).all(axis=0)
+    with np.errstate(over="ignore", divide="ignore", invalid="ignore"):
+        inv_s2 = np.float32(1.0) / (sigma * sigma)   # FP32: a scale whose 1/sigma^2 overflows is invalid
+    ok = (np.isfinite(mu).all(axis=0) & np.isfinite(sigma) & (sigma > 0) & np.isfinite(amp).all(axis=0)
+          & np.isfinite(inv_s2))
     return mu, sigma, amp, ok
 
 

@@ -20,7 +20,8 @@ ISOGS_ERR_DEVICE = -4
 ISOGS_FWD_WIDE = 1
 
 EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
-            "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_last_error", "isogs_version")
+            "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_field2d_bin", "isogs_field2d_fwd",
+            "isogs_field2d_bwd", "isogs_last_error", "isogs_version")
 
 
 class Scene(ctypes.Structure):
@@ -42,6 +43,11 @@ class Bins(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("pidx", ctypes.c_void_p), ("ranges", ctypes.c_void_p),
                 ("offsets", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("count", ctypes.c_void_p),
                 ("status", ctypes.c_void_p)]
+
+
+class Field2D(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("amp", ctypes.c_void_p),
+                ("K", ctypes.c_int32)]
 
 
 class IsoGSError(RuntimeError):
@@ -75,10 +81,16 @@ def lib():
                                                vp, P(ctypes.c_size_t), vp]
         L.isogs_render_bwd.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), P(Bins),
                                        P(ctypes.c_float), vp, vp, vp, vp, vp, P(Scene), vp, P(ctypes.c_size_t), vp]
+        L.isogs_field2d_bin.argtypes = [P(Field2D), ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P(Projected),
+                                        P(Bins), vp, P(ctypes.c_size_t), vp]
+        L.isogs_field2d_fwd.argtypes = [P(Projected), ctypes.c_int32, P(Bins), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_float, vp, vp]
+        L.isogs_field2d_bwd.argtypes = [P(Projected), ctypes.c_int32, P(Bins), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_float, vp, P(Field2D), vp, P(ctypes.c_size_t), vp]
         L.isogs_checkpoint_bytes.argtypes = [ctypes.c_uint64]
         L.isogs_checkpoint_bytes.restype = ctypes.c_size_t
         for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
-                     "isogs_render_bwd"):
+                     "isogs_render_bwd", "isogs_field2d_bin", "isogs_field2d_fwd", "isogs_field2d_bwd"):
             getattr(L, name).restype = ctypes.c_int
         L.isogs_last_error.restype = ctypes.c_char_p
         L.isogs_last_error.argtypes = []

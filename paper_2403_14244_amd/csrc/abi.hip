@@ -91,6 +91,17 @@ int check_scene(const isogs_scene& s, int v, bool grads) {
     return ISOGS_OK;
 }
 
+int check_field2d_sizes(int32_t K, int32_t width, int32_t height, float support, uint64_t* tiles) {
+    if (K < 0) return fail(ISOGS_ERR_INVALID, "K < 0");
+    if (width <= 0 || height <= 0) return fail(ISOGS_ERR_INVALID, "width and height must be positive");
+    if (!(support > 0.0f) || !isfinite(support)) return fail(ISOGS_ERR_INVALID, "support must be finite and > 0");
+    const uint64_t t = (uint64_t)((width + 15) / 16) * (uint64_t)((height + 15) / 16);
+    if (t >= (1ull << 31) || (uint64_t)width * (uint64_t)height >= (1ull << 32))
+        return fail(ISOGS_ERR_INVALID, "image too large");
+    *tiles = t;
+    return ISOGS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -239,6 +250,73 @@ int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_
     if (isogs::launch_render_bwd(scenes, cams, n_views, proj, bins, bg, image, dL_dimage, T_final, n_last,
                                  checkpoints, grads, ws, (hipStream_t)stream))
         return device_fail("isogs_render_bwd");
+    return ISOGS_OK;
+}
+
+int isogs_field2d_bin(const isogs_field2d* field, int32_t width, int32_t height, float support,
+                      const isogs_projected* fp, const isogs_bins* bins, void* ws, size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if (!field) return fail(ISOGS_ERR_INVALID, "field is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    uint64_t tiles;
+    if ((rc = check_field2d_sizes(field->K, width, height, support, &tiles))) return rc;
+    const isogs::BinSortPlan plan = isogs::plan_field2d_bin(field->K, width, height, bins->capacity);
+    if (!ws) {
+        *ws_bytes = plan.bytes;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < plan.bytes)
+        return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, plan.bytes);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (field->K > 0 && (!field->mu || !field->sigma || !field->amp))
+        return fail(ISOGS_ERR_INVALID, "field parameter buffer is NULL");
+    if ((rc = check_projected(fp, (uint64_t)field->K))) return rc;
+    if ((rc = check_bins(bins, (uint64_t)field->K, tiles))) return rc;
+    if (isogs::launch_field2d_bin(plan, field, width, height, support, fp, bins, ws, (hipStream_t)stream))
+        return device_fail("isogs_field2d_bin");
+    return ISOGS_OK;
+}
+
+int isogs_field2d_fwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width, int32_t height,
+                      float support, float* image, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    uint64_t tiles;
+    if ((rc = check_field2d_sizes(K, width, height, support, &tiles))) return rc;
+    if ((rc = check_projected(fp, (uint64_t)K))) return rc;
+    if ((rc = check_bins(bins, (uint64_t)K, tiles))) return rc;
+    if (!image) return fail(ISOGS_ERR_INVALID, "image is NULL");
+    if (isogs::launch_field2d_fwd(fp, bins, width, height, support, image, (hipStream_t)stream))
+        return device_fail("isogs_field2d_fwd");
+    return ISOGS_OK;
+}
+
+int isogs_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width, int32_t height,
+                      float support, const float* dL_dimage, const isogs_field2d* grads, void* ws, size_t* ws_bytes,
+                      void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    uint64_t tiles;
+    if ((rc = check_field2d_sizes(K, width, height, support, &tiles))) return rc;
+    const size_t need = isogs::field2d_bwd_ws(bins->capacity);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if ((rc = check_projected(fp, (uint64_t)K))) return rc;
+    if ((rc = check_bins(bins, (uint64_t)K, tiles))) return rc;
+    if (!dL_dimage) return fail(ISOGS_ERR_INVALID, "dL_dimage is NULL");
+    if (!grads || grads->K != K) return fail(ISOGS_ERR_INVALID, "grads must describe K particles");
+    if (K > 0 && (!grads->mu || !grads->sigma || !grads->amp))
+        return fail(ISOGS_ERR_INVALID, "grads buffer is NULL");
+    if (isogs::launch_field2d_bwd(fp, K, bins, width, height, support, dL_dimage, grads, ws, (hipStream_t)stream))
+        return device_fail("isogs_field2d_bwd");
     return ISOGS_OK;
 }
 

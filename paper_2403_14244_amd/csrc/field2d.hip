@@ -1,0 +1,278 @@
+// The 2D kernel-sum representation of the paper's Section 3 ("Our Method"): an image
+// signal as a sum of weighted isotropic kernels (eq. 8) within a support radius (eq. 2),
+// with no compositing. It reuses the splatting path's binning and sort: each particle is
+// written as a disk of radius D with depth 1, so the stable (tile, depth) sort leaves every
+// tile's list in particle order, and every pixel adds its kernels in that fixed order.
+#include "common.h"
+#include "kernels.h"
+#include "raster.h"
+
+namespace isogs {
+
+namespace {
+
+constexpr int kFieldBwdBatch = 64;   // entries staged per step of the backward walk
+
+__device__ __forceinline__ bool bins_ok(const uint32_t* count_p, uint64_t capacity, const int32_t* status) {
+    return *status == kStatusOk && (uint64_t)*count_p <= capacity;
+}
+
+// Footprint record of every particle, in the layout of the splatting records:
+// {mu_x, mu_y, 1/sigma^2, 0} {A_0, A_1, A_2, D}, depth 1 and the member-tile count of the
+// disk of radius D (the exact FP32 tile test of the binning). A particle with a
+// non-finite parameter or sigma <= 0 gets an all-zero record and no tiles.
+__global__ void __launch_bounds__(256) field2d_footprint_kernel(const float* __restrict__ mu,
+                                                                const float* __restrict__ sigma,
+                                                                const float* __restrict__ amp, uint32_t K,
+                                                                int width, int height, float support,
+                                                                float4* __restrict__ record,
+                                                                float* __restrict__ depth,
+                                                                uint32_t* __restrict__ tile_count) {
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= K) return;
+    const float mx = mu[k], my = mu[K + k], s = sigma[k];
+    const float a0 = amp[k], a1 = amp[K + k], a2 = amp[2 * (size_t)K + k];
+    const bool ok = isfinite(mx) && isfinite(my) && isfinite(s) && s > 0.0f && isfinite(a0) && isfinite(a1) &&
+                    isfinite(a2) && isfinite(1.0f / (s * s));
+    float4 fp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float4 cr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint32_t cnt = 0;
+    if (ok) {
+        fp = make_float4(mx, my, 1.0f / (s * s), 0.0f);
+        cr = make_float4(a0, a1, a2, support);
+        int tx0, tx1, ty0, ty1;
+        const int TX = (width + kTile - 1) / kTile, TY = (height + kTile - 1) / kTile;
+        tile_box(mx, my, support, TX, TY, tx0, tx1, ty0, ty1);
+        const float r2 = support * support;
+        const float w_lim = (float)width - 0.5f, h_lim = (float)height - 0.5f;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) cnt += tile_member(mx, my, r2, tx, ty, w_lim, h_lim) ? 1u : 0u;
+    }
+    record[2 * (size_t)k] = fp;
+    record[2 * (size_t)k + 1] = cr;
+    depth[k] = 1.0f;
+    tile_count[k] = cnt;
+}
+
+// One workgroup per tile, one lane per pixel. The tile's list is staged through LDS 256
+// entries at a time; every lane adds A exp(-d^2/sigma^2) of each staged entry whose support
+// holds its pixel centre, in list order. The support decision d2 < D*D is computed one
+// rounded operation at a time (the library is built without contraction), as the oracle
+// takes it.
+__global__ void __launch_bounds__(kTilePixels) field2d_fwd_kernel(
+    const float4* __restrict__ record, const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ count_p, uint64_t capacity, const int32_t* __restrict__ status, int width,
+    int height, int tiles_x, float support, float* __restrict__ image) {
+    __shared__ float4 s_pos[kTilePixels];   // {mu_x, mu_y, log2(e)/sigma^2, -}
+    __shared__ float4 s_amp[kTilePixels];   // {A_0, A_1, A_2, -}
+    if (!bins_ok(count_p, capacity, status)) return;
+    const uint32_t tile = xcd_swizzle(blockIdx.x, gridDim.x), t = threadIdx.x;
+    const int px = (int)(tile % (uint32_t)tiles_x) * kTile + (int)(t & 15u);
+    const int py = (int)(tile / (uint32_t)tiles_x) * kTile + (int)(t >> 4);
+    const float x = (float)px + 0.5f, y = (float)py + 0.5f;
+    const float D2 = support * support;
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    for (uint32_t b = start; b < end; b += kTilePixels) {
+        const uint32_t n = min((uint32_t)kTilePixels, end - b);
+        if (t < n) {
+            const uint32_t g = pidx[b + t];
+            const float4 fp = record[2 * (size_t)g];
+            s_pos[t] = make_float4(fp.x, fp.y, fp.z * kLog2e, 0.0f);
+            s_amp[t] = record[2 * (size_t)g + 1];
+        }
+        __syncthreads();
+        for (uint32_t j = 0; j < n; ++j) {
+            const float4 e = s_pos[j];
+            const float dx = x - e.x, dy = y - e.y;
+            const float dx2 = dx * dx, dy2 = dy * dy;
+            const float d2 = dx2 + dy2;
+            if (d2 < D2) {
+                const float g = __builtin_amdgcn_exp2f(-d2 * e.z);
+                const float4 a = s_amp[j];
+                c0 = fmaf(a.x, g, c0);
+                c1 = fmaf(a.y, g, c1);
+                c2 = fmaf(a.z, g, c2);
+            }
+        }
+        __syncthreads();
+    }
+    if (px < width && py < height) {
+        const size_t hw = (size_t)width * height, o = (size_t)py * width + px;
+        image[o] = c0;
+        image[hw + o] = c1;
+        image[2 * hw + o] = c2;
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// One workgroup per tile. For each staged entry every lane forms the six derivative terms
+// of its pixel (A_0..A_2, mu_x, mu_y, sigma); the workgroup sums them over the tile's
+// pixels in a fixed order (a butterfly within each wave, then the four waves in order)
+// and writes them as the entry's record {dmu_x, dmu_y, dsigma, 0} {dA_0, dA_1, dA_2, 0}
+// at its emit position. Lanes of pixels outside the image carry dL/dimage = 0.
+__global__ void __launch_bounds__(kTilePixels) field2d_bwd_kernel(
+    const float4* __restrict__ record, const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges,
+    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ count_p, uint64_t capacity,
+    const int32_t* __restrict__ status, int width, int height, int tiles_x, int tiles_y, float support,
+    const float* __restrict__ dL_dimage, float4* __restrict__ rec) {
+    __shared__ float4 s_pos[kFieldBwdBatch];   // {mu_x, mu_y, 1/sigma^2, log2(e)/sigma^2}
+    __shared__ float4 s_amp[kFieldBwdBatch];
+    __shared__ uint32_t s_slot[kFieldBwdBatch];
+    __shared__ float s_part[kTilePixels / kWave][kFieldBwdBatch][6];
+    if (!bins_ok(count_p, capacity, status)) return;
+    const uint32_t tile = xcd_swizzle(blockIdx.x, gridDim.x), t = threadIdx.x;
+    const uint32_t w = t >> 6, lane = t & 63u;
+    const int tx = (int)(tile % (uint32_t)tiles_x), ty = (int)(tile / (uint32_t)tiles_x);
+    const int px = tx * kTile + (int)(t & 15u), py = ty * kTile + (int)(t >> 4);
+    const float x = (float)px + 0.5f, y = (float)py + 0.5f;
+    const float D2 = support * support;
+    const float w_lim = (float)width - 0.5f, h_lim = (float)height - 0.5f;
+    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+    if (px < width && py < height) {
+        const size_t hw = (size_t)width * height, o = (size_t)py * width + px;
+        w0 = dL_dimage[o];
+        w1 = dL_dimage[hw + o];
+        w2 = dL_dimage[2 * hw + o];
+    }
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    for (uint32_t b = start; b < end; b += kFieldBwdBatch) {
+        const uint32_t n = min((uint32_t)kFieldBwdBatch, end - b);
+        if (t < n) {
+            const uint32_t g = pidx[b + t];
+            const float4 fp = record[2 * (size_t)g];
+            const float4 cr = record[2 * (size_t)g + 1];
+            s_pos[t] = make_float4(fp.x, fp.y, fp.z, fp.z * kLog2e);
+            s_amp[t] = cr;
+            s_slot[t] = emit_slot(offsets[g], fp.x, fp.y, cr.w, tx, ty, tiles_x, tiles_y, w_lim, h_lim);
+        }
+        __syncthreads();
+        for (uint32_t j = 0; j < n; ++j) {
+            const float4 e = s_pos[j];
+            const float dx = x - e.x, dy = y - e.y;
+            const float dx2 = dx * dx, dy2 = dy * dy;
+            const float d2 = dx2 + dy2;
+            float v[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            if (d2 < D2) {
+                const float g = __builtin_amdgcn_exp2f(-d2 * e.w);
+                const float4 a = s_amp[j];
+                v[0] = w0 * g;
+                v[1] = w1 * g;
+                v[2] = w2 * g;
+                // dL/dg times 2/sigma^2: the common factor of the centre and scale terms
+                const float k2 = 2.0f * (w0 * a.x + w1 * a.y + w2 * a.z) * g * e.z;
+                v[3] = k2 * dx;
+                v[4] = k2 * dy;
+                v[5] = k2 * d2 * sqrtf(e.z);
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[q] = wave_sum(v[q]);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) s_part[w][j][q] = v[q];
+            }
+        }
+        __syncthreads();
+        if (t < n) {
+            float r[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                r[q] = ((s_part[0][t][q] + s_part[1][t][q]) + s_part[2][t][q]) + s_part[3][t][q];
+            const uint32_t slot = s_slot[t];
+            rec[2 * (size_t)slot] = make_float4(r[3], r[4], r[5], 0.0f);
+            rec[2 * (size_t)slot + 1] = make_float4(r[0], r[1], r[2], 0.0f);
+        }
+        __syncthreads();
+    }
+}
+
+// Per particle: the sum of its entries' records in emit order (row-major tiles), written
+// as its gradients; a particle with no tiles gets zeros.
+__global__ void __launch_bounds__(256) field2d_grad_reduce_kernel(
+    const float4* __restrict__ rec, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ tile_count,
+    const uint32_t* __restrict__ count_p, uint64_t capacity, const int32_t* __restrict__ status, uint32_t K,
+    float* __restrict__ g_mu, float* __restrict__ g_sigma, float* __restrict__ g_amp) {
+    const uint32_t k = blockIdx.x * 256u + threadIdx.x;
+    if (k >= K || !bins_ok(count_p, capacity, status)) return;
+    const uint32_t e0 = offsets[k], cnt = tile_count[k];
+    float a[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t j = 0; j < cnt; ++j) {
+        const float4 p = rec[2 * (size_t)(e0 + j)];
+        const float4 q = rec[2 * (size_t)(e0 + j) + 1];
+        a[0] += p.x;
+        a[1] += p.y;
+        a[2] += p.z;
+        a[3] += q.x;
+        a[4] += q.y;
+        a[5] += q.z;
+    }
+    g_mu[k] = a[0];
+    g_mu[K + k] = a[1];
+    g_sigma[k] = a[2];
+    g_amp[k] = a[3];
+    g_amp[K + k] = a[4];
+    g_amp[2 * (size_t)K + k] = a[5];
+}
+
+isogs_camera field_camera(int32_t width, int32_t height) {
+    isogs_camera c{};
+    c.width = width;
+    c.height = height;
+    return c;
+}
+
+}  // namespace
+
+BinSortPlan plan_field2d_bin(int32_t K, int32_t width, int32_t height, uint64_t capacity) {
+    const isogs_camera cam = field_camera(width, height);
+    return plan_bin_sort(&K, &cam, 1, capacity);
+}
+
+int launch_field2d_bin(const BinSortPlan& plan, const isogs_field2d* f, int32_t width, int32_t height,
+                       float support, const isogs_projected* fp, const isogs_bins* bins, void* ws,
+                       hipStream_t stream) {
+    const uint32_t K = (uint32_t)f->K;
+    if (K)
+        hipLaunchKernelGGL(field2d_footprint_kernel, dim3((K + 255) / 256), dim3(256), 0, stream, f->mu, f->sigma,
+                           f->amp, K, width, height, support, reinterpret_cast<float4*>(fp->record), fp->depth,
+                           fp->tile_count);
+    if (hipPeekAtLastError() != hipSuccess) return -1;
+    const isogs_camera cam = field_camera(width, height);
+    const int32_t n = f->K;
+    return launch_bin_sort(plan, fp, &n, &cam, 1, bins, ws, stream);
+}
+
+int launch_field2d_fwd(const isogs_projected* fp, const isogs_bins* bins, int32_t width, int32_t height,
+                       float support, float* image, hipStream_t stream) {
+    const int tx = (width + kTile - 1) / kTile, ty = (height + kTile - 1) / kTile;
+    hipLaunchKernelGGL(field2d_fwd_kernel, dim3((unsigned)(tx * ty)), dim3(kTilePixels), 0, stream,
+                       reinterpret_cast<const float4*>(fp->record), bins->pidx, bins->ranges, bins->count,
+                       bins->capacity, bins->status, width, height, tx, support, image);
+    return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+}
+
+size_t field2d_bwd_ws(uint64_t capacity) { return (size_t)capacity * 32; }
+
+int launch_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width, int32_t height,
+                       float support, const float* dL_dimage, const isogs_field2d* grads, void* ws,
+                       hipStream_t stream) {
+    const int tx = (width + kTile - 1) / kTile, ty = (height + kTile - 1) / kTile;
+    float4* rec = static_cast<float4*>(ws);
+    if (bins->capacity)
+        hipLaunchKernelGGL(field2d_bwd_kernel, dim3((unsigned)(tx * ty)), dim3(kTilePixels), 0, stream,
+                           reinterpret_cast<const float4*>(fp->record), bins->pidx, bins->ranges, bins->offsets,
+                           bins->count, bins->capacity, bins->status, width, height, tx, ty, support, dL_dimage,
+                           rec);
+    if (K > 0)
+        hipLaunchKernelGGL(field2d_grad_reduce_kernel, dim3(((uint32_t)K + 255) / 256), dim3(256), 0, stream, rec,
+                           bins->offsets, fp->tile_count, bins->count, bins->capacity, bins->status, (uint32_t)K,
+                           grads->mu, grads->sigma, grads->amp);
+    return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace isogs

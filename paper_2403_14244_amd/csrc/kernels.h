@@ -55,4 +55,16 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
                       const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
                       const float* ckpt, const isogs_scene* grads, void* ws, hipStream_t stream);
 
+// The 2D kernel-sum representation (no compositing) on the same footprints and bins.
+BinSortPlan plan_field2d_bin(int32_t K, int32_t width, int32_t height, uint64_t capacity);
+int launch_field2d_bin(const BinSortPlan& plan, const isogs_field2d* f, int32_t width, int32_t height,
+                       float support, const isogs_projected* fp, const isogs_bins* bins, void* ws,
+                       hipStream_t stream);
+int launch_field2d_fwd(const isogs_projected* fp, const isogs_bins* bins, int32_t width, int32_t height,
+                       float support, float* image, hipStream_t stream);
+size_t field2d_bwd_ws(uint64_t capacity);
+int launch_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width, int32_t height,
+                       float support, const float* dL_dimage, const isogs_field2d* grads, void* ws,
+                       hipStream_t stream);
+
 }  // namespace isogs

@@ -1,0 +1,132 @@
+"""Torch-facing binding of the 2D kernel-sum representation (the paper's Section 3).
+
+An RGB image is represented by K weighted isotropic kernels,
+f_c(x) = sum over |x - mu_k| < D of A_kc exp(-|x - mu_k|^2 / sigma_k^2), with no
+compositing. Binning, rendering and gradients run in the library's HIP kernels
+(``isogs_field2d_bin`` / ``_fwd`` / ``_bwd`` of include/isogs.h); this module allocates
+buffers and marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi as A
+from .rasterizer import Footprints, TileBins, _alloc_bins, _p, _stream
+
+_F32 = torch.float32
+
+
+def _field(mu, sigma, amp) -> A.Field2D:
+    f = A.Field2D()
+    f.mu, f.sigma, f.amp = _p(mu), _p(sigma), _p(amp)
+    f.K = int(sigma.shape[0])
+    return f
+
+
+def _check_params(mu, sigma, amp):
+    K = int(sigma.shape[0])
+    for name, x, shape in (("mu", mu, (2, K)), ("sigma", sigma, (K,)), ("amp", amp, (3, K))):
+        if tuple(x.shape) != shape or x.dtype != _F32 or not x.is_contiguous() or not x.is_cuda:
+            raise ValueError(f"{name}: need a contiguous CUDA float32 tensor of shape {shape}")
+
+
+class Field2DRenderer:
+    """Bins, renders and differentiates a 2D kernel-sum signal on a fixed image size and
+    support radius, keeping the entry capacity and the workspaces between calls. The
+    capacity grows on demand: a binning that overflows is repeated once with the exact
+    count plus headroom (one host synchronisation)."""
+
+    def __init__(self, width, height, support, device="cuda", headroom=1.25):
+        self.width, self.height, self.support = int(width), int(height), float(support)
+        self.device = torch.device(device)
+        self.headroom = headroom
+        self.capacity = 0
+        self.tiles = ((self.width + 15) // 16) * ((self.height + 15) // 16)
+        self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+        self._wsb = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    @staticmethod
+    def _grow(buf, nbytes):
+        return buf if buf.numel() >= nbytes else torch.empty(int(nbytes), dtype=torch.uint8, device=buf.device)
+
+    def bin(self, mu, sigma, amp, check=True):
+        """Footprints and tile lists of the particles. With `check`, reads the device status
+        (one synchronisation) and grows the capacity on overflow."""
+        _check_params(mu, sigma, amp)
+        K = int(sigma.shape[0])
+        fp = Footprints.empty(K, self.device)
+        f = _field(mu, sigma, amp)
+        cap = self.capacity
+        for _ in range(2):
+            bins = _alloc_bins(cap, K, self.tiles, self.device)
+            ab = bins.abi()
+            need = ctypes.c_size_t(0)
+            args = (ctypes.byref(f), self.width, self.height, self.support, ctypes.byref(fp.abi()), ctypes.byref(ab))
+            A.check(A.lib().isogs_field2d_bin(*args, None, ctypes.byref(need), _stream()))
+            self._ws = self._grow(self._ws, need.value)
+            have = ctypes.c_size_t(self._ws.numel())
+            A.check(A.lib().isogs_field2d_bin(*args, _p(self._ws), ctypes.byref(have), _stream()))
+            if not check:
+                return fp, bins
+            st = int(bins.status.item())
+            if st == A.ISOGS_OK:
+                return fp, bins
+            if st != A.ISOGS_ERR_CAPACITY:
+                raise A.IsoGSError(st, "isogs_field2d_bin failed on the device")
+            cap = self.capacity = int(bins.n_entries() * self.headroom) + 4096
+        raise A.IsoGSError(A.ISOGS_ERR_CAPACITY, "field2d capacity still too small after growing")
+
+    def render(self, fp: Footprints, bins: TileBins, K: int, out=None):
+        """The image [3, H, W]."""
+        image = torch.empty((3, self.height, self.width), dtype=_F32, device=self.device) if out is None else out
+        A.check(A.lib().isogs_field2d_fwd(ctypes.byref(fp.abi()), int(K), ctypes.byref(bins.abi()), self.width,
+                                          self.height, self.support, _p(image), _stream()))
+        return image
+
+    def grads(self, fp: Footprints, bins: TileBins, K: int, dL_dimage):
+        """(dL/dmu [2, K], dL/dsigma [K], dL/dA [3, K]) for dL/dimage [3, H, W]."""
+        gmu = torch.empty((2, K), dtype=_F32, device=self.device)
+        gsig = torch.empty(K, dtype=_F32, device=self.device)
+        gamp = torch.empty((3, K), dtype=_F32, device=self.device)
+        g = _field(gmu, gsig, gamp)
+        dl = dL_dimage.contiguous()
+        need = ctypes.c_size_t(0)
+        args = (ctypes.byref(fp.abi()), int(K), ctypes.byref(bins.abi()), self.width, self.height, self.support,
+                _p(dl), ctypes.byref(g))
+        A.check(A.lib().isogs_field2d_bwd(*args, None, ctypes.byref(need), _stream()))
+        self._wsb = self._grow(self._wsb, max(need.value, 1))
+        have = ctypes.c_size_t(self._wsb.numel())
+        A.check(A.lib().isogs_field2d_bwd(*args, _p(self._wsb), ctypes.byref(have), _stream()))
+        return gmu, gsig, gamp
+
+
+class Field2DRender(torch.autograd.Function):
+    """Differentiable image of a 2D kernel-sum signal: forward(mu, sigma, amp, renderer)
+    -> [3, H, W]; gradients flow to mu [2, K], sigma [K] and amp [3, K].
+
+    Once the renderer has a capacity, the forward queues binning and rendering without
+    waiting; the capacity status is read in the backward (or by `verify`), and an
+    overflow there raises IsoGSError after growing the capacity, so the caller repeats
+    the step."""
+
+    @staticmethod
+    def forward(ctx, mu, sigma, amp, renderer):
+        mu, sigma, amp = mu.contiguous(), sigma.contiguous(), amp.contiguous()
+        fp, bins = renderer.bin(mu, sigma, amp, check=renderer.capacity == 0)
+        image = renderer.render(fp, bins, int(sigma.shape[0]))
+        ctx.renderer, ctx.fp, ctx.bins, ctx.K = renderer, fp, bins, int(sigma.shape[0])
+        return image
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        r = ctx.renderer
+        gmu, gsig, gamp = r.grads(ctx.fp, ctx.bins, ctx.K, grad_out)
+        st = int(ctx.bins.status.item())
+        if st == A.ISOGS_ERR_CAPACITY:
+            r.capacity = int(ctx.bins.n_entries() * r.headroom) + 4096
+            raise A.IsoGSError(st, f"field2d entry capacity overflowed; grown to {r.capacity}, repeat the step")
+        if st != A.ISOGS_OK:
+            raise A.IsoGSError(st, "isogs_field2d_bin failed on the device")
+        return gmu, gsig, gamp, None

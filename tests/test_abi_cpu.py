@@ -149,3 +149,37 @@ def test_ordered_forward_rejects_unknown_flags():
                                           out, None, flags, ctypes.c_void_p(fake), ctypes.byref(need),
                                           None) == A.ISOGS_ERR_INVALID
         assert b"flags" in L.isogs_last_error()
+
+
+def test_field2d_invalid_arguments_and_workspace_query():
+    A = _abi()
+    L = A.lib()
+    f = A.Field2D()
+    f.K = 10
+    proj = A.Projected()
+    bins = A.Bins()
+    bins.capacity = 1000
+    need = ctypes.c_size_t(0)
+    # NULL parameter arrays are only checked once a workspace is given; the query works
+    assert L.isogs_field2d_bin(ctypes.byref(f), 64, 48, 5.0, ctypes.byref(proj), ctypes.byref(bins), None,
+                               ctypes.byref(need), None) == A.ISOGS_OK
+    assert need.value >= 1000 * 12
+    for w, h, d in ((0, 48, 5.0), (64, -1, 5.0), (64, 48, 0.0), (64, 48, float("nan")), (64, 48, float("inf"))):
+        assert L.isogs_field2d_bin(ctypes.byref(f), w, h, d, ctypes.byref(proj), ctypes.byref(bins), None,
+                                   ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    f.K = -1
+    assert L.isogs_field2d_bin(ctypes.byref(f), 64, 48, 5.0, ctypes.byref(proj), ctypes.byref(bins), None,
+                               ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    f.K = 10
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.isogs_field2d_bin(ctypes.byref(f), 64, 48, 5.0, ctypes.byref(proj), ctypes.byref(bins), fake,
+                               ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    assert b"NULL" in L.isogs_last_error()
+    # backward workspace: 32 bytes per entry of capacity
+    g = A.Field2D()
+    g.K = 10
+    assert L.isogs_field2d_bwd(ctypes.byref(proj), 10, ctypes.byref(bins), 64, 48, 5.0, None, ctypes.byref(g),
+                               None, ctypes.byref(need), None) == A.ISOGS_OK
+    assert need.value == 32 * 1000
+    assert L.isogs_field2d_fwd(ctypes.byref(proj), 10, ctypes.byref(bins), 64, 48, 5.0, None,
+                               None) == A.ISOGS_ERR_INVALID
