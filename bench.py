@@ -241,6 +241,65 @@ def stress_workload(dev, iters=3):
             "tile_lists": lists}
 
 
+def field2d_workload(dev, iters=100):
+    """The paper's 2D experiment on a synthetic stand-in: fit 2000 weighted isotropic kernels
+    (random initialisation) to a procedural 512x512 RGB image with the L1 loss and Adam, at
+    support radii D = 15 and 50 px. One iteration: binning, kernel sum, loss, gradients,
+    optimizer step. Also the two kernels' times alone (HIP events on their stream)."""
+    import torch
+    import scenegen as S
+    import paper_2403_14244_amd as P
+    tgt_np = S.field2d_target(512, 512)
+    mu0, s0, a0 = S.field2d_init(tgt_np, 2000)
+    tgt = torch.from_numpy(tgt_np).to(dev)
+    res = {"workload": "field2d_fit512_k2000", "width": 512, "height": 512, "particles": 2000}
+    for D in (15.0, 50.0):
+        R = P.Field2DRenderer(512, 512, D, device=dev)
+        mu, s, a = (torch.from_numpy(x.copy()).to(dev).requires_grad_(True) for x in (mu0, s0, a0))
+        opt = torch.optim.Adam([mu, s, a], lr=0.02)
+
+        def step():
+            opt.zero_grad(set_to_none=True)
+            img = P.Field2DRender.apply(mu, s, a, R)
+            loss = (img - tgt).abs().mean()
+            loss.backward()
+            opt.step()
+            with torch.no_grad():
+                s.clamp_(min=0.3)
+            return loss
+
+        l0 = float(step().detach())
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            loss = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / iters
+        with torch.no_grad():
+            fp, bins = R.bin(mu.detach(), s.detach(), a.detach())
+            w = torch.sign(R.render(fp, bins, 2000) - tgt) / tgt.numel()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            for _ in range(20):
+                R.render(fp, bins, 2000)
+            ev[1].record()
+            for _ in range(20):
+                R.grads(fp, bins, 2000, w)
+            ev[2].record()
+            torch.cuda.synchronize()
+        entries = bins.n_entries()
+        fwd_us = ev[0].elapsed_time(ev[1]) * 1e3 / 20
+        res[f"d{int(D)}"] = {"iters_per_s": round(1.0 / dt, 1), "ms_per_iter": round(dt * 1e3, 3),
+                             "s_per_2000_iters": round(2000 * dt, 2), "l1_first": round(l0, 5),
+                             "l1_after": round(float(loss), 5), "entries": entries,
+                             "fwd_kernel_us": round(fwd_us, 2),
+                             "bwd_kernels_us": round(ev[1].elapsed_time(ev[2]) * 1e3 / 20, 2),
+                             "fwd_pairs_per_s": round(entries * 256 / (fwd_us * 1e-6), 1)}
+    return res
+
+
 def cpu_baseline(scene, cam, budget_s):
     """FP64 oracle on one view: full projection and binning, then compositing of tiles in a
     seeded random order until the time budget is spent, extrapolated to the full frame."""
@@ -266,12 +325,24 @@ def cpu_baseline(scene, cam, budget_s):
             pix += len(O.tile_pixels(tx, ty, cam.width, cam.height)[0])
             if t_render + (t2 - t0) > budget_s:
                 break
+        # the 2D fit: one iteration (kernel sum, L1 gradient, parameter gradients) per radius
+        import scenegen as S
+        from oracle import field2d64 as F2
+        tgt = S.field2d_target(512, 512)
+        mu, sg, amp = S.field2d_init(tgt, 2000)
+        f2 = {}
+        for D in (15.0, 50.0):
+            ts = time.perf_counter()
+            _, w = F2.l1_loss64(F2.render_field64(mu, sg, amp, 512, 512, D), tgt)
+            F2.field_grads64(mu, sg, amp, 512, 512, D, w)
+            f2[f"d{int(D)}_s_per_iter"] = round(time.perf_counter() - ts, 3)
     total_pix = cam.width * cam.height
     per_view = (t1 - t0) + (t2 - t1) + t_render * (total_pix / pix)
     return dict(value=total_pix / per_view / 1e6, unit="Mpix/s", cores=1, kind="oracle",
                 sample=f"1 view of 1920x1080 / 1M Gaussians: FP64 projection and binning of all "
                        f"particles ({t1 - t0:.1f}s + {t2 - t1:.1f}s), compositing of {done_tiles} random "
-                       f"tiles ({pix} px, {t_render:.1f}s) extrapolated to the full frame; one thread")
+                       f"tiles ({pix} px, {t_render:.1f}s) extrapolated to the full frame; one thread",
+                field2d_fit512_k2000=f2)
 
 
 def main():
@@ -450,6 +521,9 @@ def main():
         extra["stress_6m_4k_x8"] = stress_workload(dev)
         log(f"stress workload: {extra['stress_6m_4k_x8']}")
         torch.cuda.empty_cache()
+        log("2D fit (2000 kernels, 512x512) ...")
+        extra["field2d_fit512_k2000"] = field2d_workload(dev)
+        log(f"2D fit: {extra['field2d_fit512_k2000']}")
 
     serving = None
     if args.serve_seconds > 0:

@@ -105,17 +105,15 @@ __global__ void __launch_bounds__(kTilePixels) field2d_fwd_kernel(
     }
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-// One workgroup per tile. For each staged entry every lane forms the six derivative terms
-// of its pixel (A_0..A_2, mu_x, mu_y, sigma); the workgroup sums them over the tile's
-// pixels in a fixed order (a butterfly within each wave, then the four waves in order)
-// and writes them as the entry's record {dmu_x, dmu_y, dsigma, 0} {dA_0, dA_1, dA_2, 0}
-// at its emit position. Lanes of pixels outside the image carry dL/dimage = 0.
+// One workgroup per tile; wave w owns the tile's pixels [64 w, 64 w + 64) and the tile's
+// list is staged 64 entries at a time. A batch of E entries is spread over the wave's
+// lanes entry-major: with E' the power of two >= E, lane l takes entry l mod E' and every
+// (64 / E')-th of the wave's pixels from l / E' on, so each lane accumulates the six
+// derivative terms (A_0..A_2, mu_x, mu_y, sigma) of one entry over E' pixels in
+// registers; the lanes sharing an entry are then summed by a butterfly over the high lane
+// bits and the four waves in order. Every sum has a fixed order, so the records are
+// bitwise reproducible. Each entry's record {dmu_x, dmu_y, dsigma, 0} {dA_0, dA_1, dA_2, 0}
+// is written at its emit position. Pixels outside the image carry dL/dimage = 0.
 __global__ void __launch_bounds__(kTilePixels) field2d_bwd_kernel(
     const float4* __restrict__ record, const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges,
     const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ count_p, uint64_t capacity,
@@ -124,22 +122,28 @@ __global__ void __launch_bounds__(kTilePixels) field2d_bwd_kernel(
     __shared__ float4 s_pos[kFieldBwdBatch];   // {mu_x, mu_y, 1/sigma^2, log2(e)/sigma^2}
     __shared__ float4 s_amp[kFieldBwdBatch];
     __shared__ uint32_t s_slot[kFieldBwdBatch];
+    __shared__ float s_w[3][kTilePixels];      // dL/dimage of the tile's pixels
     __shared__ float s_part[kTilePixels / kWave][kFieldBwdBatch][6];
     if (!bins_ok(count_p, capacity, status)) return;
     const uint32_t tile = xcd_swizzle(blockIdx.x, gridDim.x), t = threadIdx.x;
     const uint32_t w = t >> 6, lane = t & 63u;
     const int tx = (int)(tile % (uint32_t)tiles_x), ty = (int)(tile / (uint32_t)tiles_x);
-    const int px = tx * kTile + (int)(t & 15u), py = ty * kTile + (int)(t >> 4);
-    const float x = (float)px + 0.5f, y = (float)py + 0.5f;
     const float D2 = support * support;
     const float w_lim = (float)width - 0.5f, h_lim = (float)height - 0.5f;
-    float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
-    if (px < width && py < height) {
-        const size_t hw = (size_t)width * height, o = (size_t)py * width + px;
-        w0 = dL_dimage[o];
-        w1 = dL_dimage[hw + o];
-        w2 = dL_dimage[2 * hw + o];
+    {
+        const int px = tx * kTile + (int)(t & 15u), py = ty * kTile + (int)(t >> 4);
+        float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+        if (px < width && py < height) {
+            const size_t hw = (size_t)width * height, o = (size_t)py * width + px;
+            w0 = dL_dimage[o];
+            w1 = dL_dimage[hw + o];
+            w2 = dL_dimage[2 * hw + o];
+        }
+        s_w[0][t] = w0;
+        s_w[1][t] = w1;
+        s_w[2][t] = w2;
     }
+    const float x0 = (float)(tx * kTile) + 0.5f, y0 = (float)(ty * kTile) + 0.5f;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     for (uint32_t b = start; b < end; b += kFieldBwdBatch) {
         const uint32_t n = min((uint32_t)kFieldBwdBatch, end - b);
@@ -152,30 +156,41 @@ __global__ void __launch_bounds__(kTilePixels) field2d_bwd_kernel(
             s_slot[t] = emit_slot(offsets[g], fp.x, fp.y, cr.w, tx, ty, tiles_x, tiles_y, w_lim, h_lim);
         }
         __syncthreads();
-        for (uint32_t j = 0; j < n; ++j) {
-            const float4 e = s_pos[j];
-            const float dx = x - e.x, dy = y - e.y;
+        // E' = the power of two >= n (uniform), lg = log2(E')
+        const uint32_t lg = n > 1 ? 32u - (uint32_t)__builtin_clz(n - 1u) : 0u;
+        const uint32_t ep = 1u << lg, e = lane & (ep - 1u), slice = lane >> lg, step = kWave >> lg;
+        const bool valid = e < n;
+        float4 ent = make_float4(0.0f, 0.0f, 0.0f, 0.0f), amp = ent;
+        if (valid) {
+            ent = s_pos[e];
+            amp = s_amp[e];
+        }
+        const float inv_s = sqrtf(ent.z);
+        float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (uint32_t k = 0; k < ep; ++k) {
+            const uint32_t pix = w * kWave + slice + k * step;   // pixel of the tile, row-major
+            const float x = x0 + (float)(pix & 15u), y = y0 + (float)(pix >> 4);
+            const float dx = x - ent.x, dy = y - ent.y;
             const float dx2 = dx * dx, dy2 = dy * dy;
             const float d2 = dx2 + dy2;
-            float v[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            if (d2 < D2) {
-                const float g = __builtin_amdgcn_exp2f(-d2 * e.w);
-                const float4 a = s_amp[j];
-                v[0] = w0 * g;
-                v[1] = w1 * g;
-                v[2] = w2 * g;
-                // dL/dg times 2/sigma^2: the common factor of the centre and scale terms
-                const float k2 = 2.0f * (w0 * a.x + w1 * a.y + w2 * a.z) * g * e.z;
-                v[3] = k2 * dx;
-                v[4] = k2 * dy;
-                v[5] = k2 * d2 * sqrtf(e.z);
-            }
+            const float g = (valid && d2 < D2) ? __builtin_amdgcn_exp2f(-d2 * ent.w) : 0.0f;
+            const float c0 = s_w[0][pix], c1 = s_w[1][pix], c2 = s_w[2][pix];
+            acc[0] = fmaf(c0, g, acc[0]);
+            acc[1] = fmaf(c1, g, acc[1]);
+            acc[2] = fmaf(c2, g, acc[2]);
+            // dL/dg times 2/sigma^2: the common factor of the centre and scale terms
+            const float k2 = 2.0f * (c0 * amp.x + c1 * amp.y + c2 * amp.z) * g * ent.z;
+            acc[3] = fmaf(k2, dx, acc[3]);
+            acc[4] = fmaf(k2, dy, acc[4]);
+            acc[5] = fmaf(k2 * d2, inv_s, acc[5]);
+        }
+        for (uint32_t o = ep; o < (uint32_t)kWave; o <<= 1) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) v[q] = wave_sum(v[q]);
-            if (lane == 0) {
+            for (int q = 0; q < 6; ++q) acc[q] += __shfl_xor(acc[q], (int)o, kWave);
+        }
+        if (valid && slice == 0) {
 #pragma unroll
-                for (int q = 0; q < 6; ++q) s_part[w][j][q] = v[q];
-            }
+            for (int q = 0; q < 6; ++q) s_part[w][e][q] = acc[q];
         }
         __syncthreads();
         if (t < n) {
