@@ -19,7 +19,8 @@
  *   isogs_render_bwd dL/dimage -> dL/d(particle parameters), for back-propagation
  *                    (the optimisation mode of Section 3, "Optimization")
  * and, for the 2D kernel-sum representation of Section 3 (no compositing),
- * isogs_field2d_bin / isogs_field2d_fwd / isogs_field2d_bwd on the same bins.
+ * isogs_field2d_bin / isogs_field2d_fwd / isogs_field2d_bwd on the same bins, and the
+ * SSIM term of the loss, isogs_ssim_fwd / isogs_ssim_bwd.
  *
  * Conventions shared by every call:
  *   - Every buffer pointer is DEVICE memory owned by the caller, except the arrays of
@@ -290,6 +291,32 @@ int isogs_field2d_fwd(const isogs_projected* fp, int32_t K, const isogs_bins* bi
 int isogs_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width,
                       int32_t height, float support, const float* dL_dimage, const isogs_field2d* grads,
                       void* ws, size_t* ws_bytes, void* stream);
+
+/* ---- SSIM term of the loss (Section 3) -----------------------------------------------
+ * The paper's loss adds lambda times an SSIM term to the L1 error (lambda = 0.2); read as
+ * lambda (1 - SSIM). SSIM is the structural similarity of Wang et al. (2004): per channel,
+ * local statistics under an 11 x 11 Gaussian window of standard deviation 1.5 normalised
+ * to sum 1, the image counted as zero outside its borders (no renormalisation),
+ * C1 = 0.01^2, C2 = 0.03^2 (dynamic range 1),
+ *   S = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2)),
+ * and the reported value is the mean of S over channels and pixels.
+ *   image, target  device [channels][height][width] (any number of planes: views and
+ *                  colour channels alike)
+ *   ssim           device [1]: the mean, written by the forward (block sums added in
+ *                  FP64 in a fixed order: reproducible)
+ *   ws, ws_bytes   workspace (query with ws == NULL, 256-byte aligned): the three
+ *                  derivative maps of S (12 bytes per pixel and channel) and the block
+ *                  sums; the backward reads what the forward left there
+ * Errors: ISOGS_ERR_INVALID (sizes <= 0, more than 2^31 values or 65535 planes, NULL
+ * buffers), ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
+int isogs_ssim_fwd(const float* image, const float* target, int32_t channels, int32_t height,
+                   int32_t width, float* ssim, void* ws, size_t* ws_bytes, void* stream);
+
+/* dL/dimage = dL/dSSIM * dSSIM/dimage for the same image, target and workspace as the
+ * forward (the target is constant); dL_dssim is a device scalar. Output overwritten. */
+int isogs_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height,
+                   int32_t width, const float* dL_dssim, const void* ws, size_t ws_bytes,
+                   float* dL_dimage, void* stream);
 
 /* Message describing the last error returned on the calling thread ("" if none). */
 const char* isogs_last_error(void);

@@ -320,4 +320,39 @@ int isogs_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bi
     return ISOGS_OK;
 }
 
+int isogs_ssim_fwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                   float* ssim, void* ws, size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (channels <= 0 || height <= 0 || width <= 0) return fail(ISOGS_ERR_INVALID, "sizes must be positive");
+    if ((uint64_t)channels * (uint64_t)height * (uint64_t)width >= (1ull << 31) || channels > 65535)
+        return fail(ISOGS_ERR_INVALID, "image too large");
+    const size_t need = isogs::ssim_ws_bytes(channels, height, width);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!image || !target || !ssim) return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (isogs::launch_ssim_fwd(image, target, channels, height, width, ssim, ws, (hipStream_t)stream))
+        return device_fail("isogs_ssim_fwd");
+    return ISOGS_OK;
+}
+
+int isogs_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                   const float* dL_dssim, const void* ws, size_t ws_bytes, float* dL_dimage, void* stream) {
+    g_error[0] = 0;
+    if (channels <= 0 || height <= 0 || width <= 0) return fail(ISOGS_ERR_INVALID, "sizes must be positive");
+    if ((uint64_t)channels * (uint64_t)height * (uint64_t)width >= (1ull << 31) || channels > 65535)
+        return fail(ISOGS_ERR_INVALID, "image too large");
+    const size_t need = isogs::ssim_ws_bytes(channels, height, width);
+    if (!ws || ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "the forward's workspace of %zu bytes is needed", need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!image || !target || !dL_dssim || !dL_dimage) return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (isogs::launch_ssim_bwd(image, target, channels, height, width, dL_dssim, ws, dL_dimage, (hipStream_t)stream))
+        return device_fail("isogs_ssim_bwd");
+    return ISOGS_OK;
+}
+
 }  // extern "C"

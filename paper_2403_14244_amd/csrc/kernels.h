@@ -67,4 +67,12 @@ int launch_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* b
                        float support, const float* dL_dimage, const isogs_field2d* grads, void* ws,
                        hipStream_t stream);
 
+// The SSIM term of the loss: forward (mean SSIM and the derivative maps kept in the
+// workspace) and backward.
+size_t ssim_ws_bytes(int32_t channels, int32_t height, int32_t width);
+int launch_ssim_fwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                    float* ssim, void* ws, hipStream_t stream);
+int launch_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                    const float* dL_dssim, const void* ws, float* dL_dimage, hipStream_t stream);
+
 }  // namespace isogs

@@ -183,3 +183,17 @@ def test_field2d_invalid_arguments_and_workspace_query():
     assert need.value == 32 * 1000
     assert L.isogs_field2d_fwd(ctypes.byref(proj), 10, ctypes.byref(bins), 64, 48, 5.0, None,
                                None) == A.ISOGS_ERR_INVALID
+
+
+def test_ssim_invalid_arguments_and_workspace_query():
+    A = _abi()
+    L = A.lib()
+    need = ctypes.c_size_t(0)
+    assert L.isogs_ssim_fwd(None, None, 3, 48, 64, None, None, ctypes.byref(need), None) == A.ISOGS_OK
+    assert need.value >= 12 * 3 * 48 * 64
+    for c, h, w in ((0, 48, 64), (3, 0, 64), (3, 48, -2), (70000, 4, 4)):
+        assert L.isogs_ssim_fwd(None, None, c, h, w, None, None, ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    fake = ctypes.c_void_p(1 << 20)
+    small = ctypes.c_size_t(16)
+    assert L.isogs_ssim_fwd(fake, fake, 3, 48, 64, fake, fake, ctypes.byref(small), None) == A.ISOGS_ERR_WORKSPACE
+    assert L.isogs_ssim_bwd(fake, fake, 3, 48, 64, fake, None, 0, fake, None) == A.ISOGS_ERR_WORKSPACE
