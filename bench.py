@@ -350,8 +350,9 @@ def cpu_baseline(scene, cam, budget_s):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(rendering and serving shard by view/request; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (rendering and "
+              "serving would shard by view and request, training by views with one gradient all-reduce)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import scenegen as S

@@ -19,8 +19,9 @@
  *   isogs_render_bwd dL/dimage -> dL/d(particle parameters), for back-propagation
  *                    (the optimisation mode of Section 3, "Optimization")
  * and, for the 2D kernel-sum representation of Section 3 (no compositing),
- * isogs_field2d_bin / isogs_field2d_fwd / isogs_field2d_bwd on the same bins, and the
- * SSIM term of the loss, isogs_ssim_fwd / isogs_ssim_bwd.
+ * isogs_field2d_bin / isogs_field2d_fwd / isogs_field2d_bwd on the same bins, with its
+ * quadtree initialisation and multiscale edits (isogs_field2d_tree_init / _prune /
+ * _split), and the SSIM term of the loss, isogs_ssim_fwd / isogs_ssim_bwd.
  *
  * Conventions shared by every call:
  *   - Every buffer pointer is DEVICE memory owned by the caller, except the arrays of
@@ -291,6 +292,43 @@ int isogs_field2d_fwd(const isogs_projected* fp, int32_t K, const isogs_bins* bi
 int isogs_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bins, int32_t width,
                       int32_t height, float support, const float* dL_dimage, const isogs_field2d* grads,
                       void* ws, size_t* ws_bytes, void* stream);
+
+/* Quadtree initialisation of a 2D signal (Section 3, "Initial with Tree Structure"): the
+ * leaves of a quadtree over `target` [3][height][width] become particles with the mean
+ * colour of their pixels as amplitude, half the cell width as sigma and the centre of the
+ * cell's in-image rectangle as mu. The tree starts from a grid of root cells of side
+ * `root` (a power of two; border cells clipped to the image); a cell of side s splits into
+ * its in-image quadrants when its colour variance (the mean over channels of the
+ * population variance of its pixels, in FP64) exceeds tau and s/2 >= min_side. Levels
+ * grow one at a time; a level whose splits would let the leaf count exceed K splits no
+ * cell. Leaves are numbered by level (root first), row-major within a level.
+ *   out    host struct of device arrays of capacity out->K >= K (row stride out->K)
+ *   count  device int32: the number of particles written (<= K)
+ *   ws, ws_bytes  workspace (query with ws == NULL, 256-byte aligned)
+ * Errors: ISOGS_ERR_INVALID (sizes, root not a power of two >= min_side >= 1, tau not
+ * finite or < 0, K below the number of root cells, NULL buffers), ISOGS_ERR_WORKSPACE,
+ * ISOGS_ERR_DEVICE. */
+int isogs_field2d_tree_init(const float* target, int32_t height, int32_t width, int32_t root,
+                            int32_t min_side, float tau, int32_t K, const isogs_field2d* out,
+                            int32_t* count, void* ws, size_t* ws_bytes, void* stream);
+
+/* Multiscale edits (Section 2, "Multiscale": isotropic kernels are easily deleted or
+ * divided according to their scale), order-preserving:
+ *   prune  keeps the particles whose largest amplitude magnitude max_c |A_kc| >= amp_min
+ *          (and drops those with a non-finite parameter or sigma <= 0);
+ *   split  replaces every particle with sigma > sigma_max, in place, by four of scale
+ *          sigma/2 centred at mu + (-h, -h), (+h, -h), (-h, +h), (+h, +h), h = sigma/2
+ *          (one FP32 rounding each), with its amplitude; copies the others.
+ *   in     host struct of device arrays (in->K particles)
+ *   out    host struct of device arrays of capacity out->K (row stride out->K); outputs
+ *          past the capacity are not written
+ *   count  device int32: the number of outputs (may exceed the capacity)
+ *   ws, ws_bytes  workspace (query with ws == NULL, 256-byte aligned)
+ * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
+int isogs_field2d_prune(const isogs_field2d* in, float amp_min, const isogs_field2d* out,
+                        int32_t* count, void* ws, size_t* ws_bytes, void* stream);
+int isogs_field2d_split(const isogs_field2d* in, float sigma_max, const isogs_field2d* out,
+                        int32_t* count, void* ws, size_t* ws_bytes, void* stream);
 
 /* ---- SSIM term of the loss (Section 3) -----------------------------------------------
  * The paper's loss adds lambda times an SSIM term to the L1 error (lambda = 0.2); read as

@@ -10,8 +10,9 @@ the image: a leaf cell carries the average colour of its pixels and a scale of h
 cell width. It does not say when a cell splits or how the particle count is bounded;
 the readings here:
 
-* the image is covered by a grid of square root cells of side `root` pixels (cells at
-  the right and bottom borders are clipped to the image); a cell of side `side` splits
+* the image is covered by a grid of square root cells of side `root` pixels (a power of
+  two; cells at the right and bottom borders are clipped to the image; the budget K
+  allows at least one particle per root cell); a cell of side `side` splits
   into its four quadrants (side / 2, quadrants outside the image dropped) when its colour
   variance exceeds `tau` and side / 2 >= `min_side`. The colour variance is the mean over
   the channels of the population variance of the cell's in-image pixels;
@@ -25,7 +26,7 @@ the readings here:
   amplitude = the mean colour of its pixels (FP64, rounded to FP32).
 
 Multiscale edits (Section 2: isotropic kernels are easily divided or deleted according
-to their scale; SURVEY-style readings):
+to their scale; the readings):
 
 * prune: drop particles whose largest amplitude magnitude max_c |A_kc| is below
   `amp_min` (FP32 comparison), and particles with a non-finite parameter or sigma <= 0;
@@ -53,9 +54,11 @@ def quadtree_init64(target, K, root=64, min_side=2, tau=1e-3, return_stats=False
     """Particles (mu [2][n], sigma [n], amp [3][n]) of the quadtree leaves of `target`
     [3][H][W]; with `return_stats`, also the colour variance of every visited cell, per
     level (for the tests' margin checks)."""
+    assert root >= 1 and root & (root - 1) == 0 and min_side >= 1, "root must be a power of two"
     img = np.asarray(target, dtype=np.float64)
     C, H, W = img.shape
     cells = [(x, y) for y in range(0, H, root) for x in range(0, W, root)]
+    assert K >= len(cells), "the budget must allow one particle per root cell"
     side = root
     leaves = []          # (x0, y0, side, mean colour)
     seen = []

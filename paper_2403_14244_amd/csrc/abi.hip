@@ -355,4 +355,63 @@ int isogs_ssim_bwd(const float* image, const float* target, int32_t channels, in
     return ISOGS_OK;
 }
 
+int isogs_field2d_tree_init(const float* target, int32_t height, int32_t width, int32_t root, int32_t min_side,
+                            float tau, int32_t K, const isogs_field2d* out, int32_t* count, void* ws, size_t* ws_bytes,
+                            void* stream) {
+    g_error[0] = 0;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (height <= 0 || width <= 0) return fail(ISOGS_ERR_INVALID, "width and height must be positive");
+    if ((uint64_t)width * (uint64_t)height * 3 >= (1ull << 31)) return fail(ISOGS_ERR_INVALID, "image too large");
+    uint64_t roots = 0;
+    if (!isogs::tree_levels_ok(width, height, root, min_side, &roots))
+        return fail(ISOGS_ERR_INVALID, "root must be a power of two >= min_side >= 1");
+    if (!(tau >= 0.0f) || !isfinite(tau)) return fail(ISOGS_ERR_INVALID, "tau must be finite and >= 0");
+    if (K <= 0 || (uint64_t)K < roots) return fail(ISOGS_ERR_INVALID, "K must allow one particle per root cell");
+    const size_t need = isogs::tree_init_ws(width, height, root, min_side);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!target || !out || !count || !out->mu || !out->sigma || !out->amp)
+        return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (out->K < K) return fail(ISOGS_ERR_INVALID, "out must hold K particles");
+    isogs_field2d o = *out;
+    o.K = K;
+    if (isogs::launch_tree_init(target, width, height, root, min_side, tau, K, &o, count, ws, (hipStream_t)stream))
+        return device_fail("isogs_field2d_tree_init");
+    return ISOGS_OK;
+}
+
+static int field2d_edit(int mode, const char* name, const isogs_field2d* in, float thr, const isogs_field2d* out,
+                        int32_t* count, void* ws, size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!in || in->K < 0) return fail(ISOGS_ERR_INVALID, "in must describe K >= 0 particles");
+    if (isnan(thr)) return fail(ISOGS_ERR_INVALID, "threshold is NaN");
+    const size_t need = isogs::edit_ws(in->K);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!out || !count || out->K < 0) return fail(ISOGS_ERR_INVALID, "out or count is NULL");
+    if (in->K > 0 && (!in->mu || !in->sigma || !in->amp)) return fail(ISOGS_ERR_INVALID, "in buffer is NULL");
+    if (out->K > 0 && (!out->mu || !out->sigma || !out->amp)) return fail(ISOGS_ERR_INVALID, "out buffer is NULL");
+    if (isogs::launch_edit(mode, thr, in, out, out->K, count, ws, (hipStream_t)stream)) return device_fail(name);
+    return ISOGS_OK;
+}
+
+int isogs_field2d_prune(const isogs_field2d* in, float amp_min, const isogs_field2d* out, int32_t* count, void* ws,
+                        size_t* ws_bytes, void* stream) {
+    return field2d_edit(0, "isogs_field2d_prune", in, amp_min, out, count, ws, ws_bytes, stream);
+}
+
+int isogs_field2d_split(const isogs_field2d* in, float sigma_max, const isogs_field2d* out, int32_t* count, void* ws,
+                        size_t* ws_bytes, void* stream) {
+    return field2d_edit(1, "isogs_field2d_split", in, sigma_max, out, count, ws, ws_bytes, stream);
+}
+
 }  // extern "C"

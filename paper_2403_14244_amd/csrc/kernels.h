@@ -75,4 +75,14 @@ int launch_ssim_fwd(const float* image, const float* target, int32_t channels, i
 int launch_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
                     const float* dL_dssim, const void* ws, float* dL_dimage, hipStream_t stream);
 
+// Quadtree initialisation, prune and split of 2D particles.
+int tree_levels_ok(int32_t width, int32_t height, int32_t root, int32_t min_side, uint64_t* root_cells);
+size_t tree_init_ws(int32_t width, int32_t height, int32_t root, int32_t min_side);
+int launch_tree_init(const float* target, int32_t width, int32_t height, int32_t root, int32_t min_side, float tau,
+                     int32_t K, const isogs_field2d* out, int32_t* count, void* ws, hipStream_t stream);
+size_t edit_ws(int32_t K);
+// mode 0: prune (keep max |A| >= thr), mode 1: split (sigma > thr into four)
+int launch_edit(int mode, float thr, const isogs_field2d* in, const isogs_field2d* out, int32_t cap, int32_t* count,
+                void* ws, hipStream_t stream);
+
 }  // namespace isogs

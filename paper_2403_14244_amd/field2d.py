@@ -102,6 +102,58 @@ class Field2DRenderer:
         return gmu, gsig, gamp
 
 
+def _alloc_params(cap, device):
+    return (torch.empty((2, cap), dtype=_F32, device=device), torch.empty(cap, dtype=_F32, device=device),
+            torch.empty((3, cap), dtype=_F32, device=device))
+
+
+def tree_init(target, K, root=64, min_side=2, tau=1e-3):
+    """Quadtree initialisation (isogs_field2d_tree_init) of particles for `target` [3, H, W]:
+    returns (mu [2, n], sigma [n], amp [3, n]), n <= K (one host synchronisation for n)."""
+    target = target.contiguous()
+    if target.dim() != 3 or target.shape[0] != 3 or target.dtype != _F32 or not target.is_cuda:
+        raise ValueError("target: need a CUDA float32 tensor [3, H, W]")
+    H, W = int(target.shape[1]), int(target.shape[2])
+    out = _alloc_params(int(K), target.device)
+    count = torch.zeros(1, dtype=torch.int32, device=target.device)
+    fo = _field(*out)
+    need = ctypes.c_size_t(0)
+    args = (_p(target), H, W, int(root), int(min_side), float(tau), int(K), ctypes.byref(fo), _p(count))
+    A.check(A.lib().isogs_field2d_tree_init(*args, None, ctypes.byref(need), _stream()))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device=target.device)
+    have = ctypes.c_size_t(ws.numel())
+    A.check(A.lib().isogs_field2d_tree_init(*args, _p(ws), ctypes.byref(have), _stream()))
+    n = int(count.item())
+    return out[0][:, :n].contiguous(), out[1][:n].contiguous(), out[2][:, :n].contiguous()
+
+
+def _edit(fn, mu, sigma, amp, thr, factor):
+    _check_params(mu, sigma, amp)
+    K = int(sigma.shape[0])
+    cap = max(1, factor * K)
+    out = _alloc_params(cap, mu.device)
+    count = torch.zeros(1, dtype=torch.int32, device=mu.device)
+    fi, fo = _field(mu, sigma, amp), _field(*out)
+    need = ctypes.c_size_t(0)
+    A.check(fn(ctypes.byref(fi), float(thr), ctypes.byref(fo), _p(count), None, ctypes.byref(need), _stream()))
+    ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=mu.device)
+    have = ctypes.c_size_t(ws.numel())
+    A.check(fn(ctypes.byref(fi), float(thr), ctypes.byref(fo), _p(count), _p(ws), ctypes.byref(have), _stream()))
+    n = int(count.item())
+    return out[0][:, :n].contiguous(), out[1][:n].contiguous(), out[2][:, :n].contiguous()
+
+
+def prune(mu, sigma, amp, amp_min):
+    """Drops particles whose max_c |A_kc| < amp_min (isogs_field2d_prune), keeping order."""
+    return _edit(A.lib().isogs_field2d_prune, mu, sigma, amp, amp_min, 1)
+
+
+def split(mu, sigma, amp, sigma_max):
+    """Replaces every particle with sigma > sigma_max by four of half its scale
+    (isogs_field2d_split), in place in the order."""
+    return _edit(A.lib().isogs_field2d_split, mu, sigma, amp, sigma_max, 4)
+
+
 class Field2DRender(torch.autograd.Function):
     """Differentiable image of a 2D kernel-sum signal: forward(mu, sigma, amp, renderer)
     -> [3, H, W]; gradients flow to mu [2, K], sigma [K] and amp [3, K].

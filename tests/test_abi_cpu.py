@@ -197,3 +197,27 @@ def test_ssim_invalid_arguments_and_workspace_query():
     small = ctypes.c_size_t(16)
     assert L.isogs_ssim_fwd(fake, fake, 3, 48, 64, fake, fake, ctypes.byref(small), None) == A.ISOGS_ERR_WORKSPACE
     assert L.isogs_ssim_bwd(fake, fake, 3, 48, 64, fake, None, 0, fake, None) == A.ISOGS_ERR_WORKSPACE
+
+
+def test_tree_init_and_edits_invalid_arguments():
+    A = _abi()
+    L = A.lib()
+    need = ctypes.c_size_t(0)
+    out = A.Field2D()
+    out.K = 100
+    assert L.isogs_field2d_tree_init(None, 64, 64, 16, 2, 1e-3, 100, ctypes.byref(out), None, None,
+                                     ctypes.byref(need), None) == A.ISOGS_OK and need.value > 0
+    for root, ms, tau, K in ((24, 2, 1e-3, 100), (16, 32, 1e-3, 100), (16, 0, 1e-3, 100), (16, 2, -1.0, 100),
+                             (16, 2, float("nan"), 100), (16, 2, 1e-3, 15)):
+        assert L.isogs_field2d_tree_init(None, 64, 64, root, ms, tau, K, ctypes.byref(out), None, None,
+                                         ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    fi = A.Field2D()
+    fi.K = -1
+    for fn in (L.isogs_field2d_prune, L.isogs_field2d_split):
+        assert fn(ctypes.byref(fi), 0.1, ctypes.byref(out), None, None, ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    fi.K = 1000
+    assert L.isogs_field2d_split(ctypes.byref(fi), 0.1, ctypes.byref(out), None, None, ctypes.byref(need),
+                                 None) == A.ISOGS_OK
+    assert need.value >= 4 * 4
+    assert L.isogs_field2d_split(ctypes.byref(fi), float("nan"), ctypes.byref(out), None, None, ctypes.byref(need),
+                                 None) == A.ISOGS_ERR_INVALID
