@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-inflight", type=int, default=2,
                     help="batches in flight at once (one HIP stream each)")
+    ap.add_argument("--only-field2d", action="store_true",
+                    help="run only the 2D fit (2000 kernels, 512x512) and print its JSON object")
     ap.add_argument("--no-extra-workloads", action="store_true",
                     help="skip the 500k 4x720p training step and the 6M 4K stress fwd+bwd")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -319,7 +321,7 @@ def field2d_workload(dev, iters=100):
         fwd_us = ev[0].elapsed_time(ev[1]) * 1e3 / 20
         res[f"d{int(D)}"] = {"iters_per_s": round(1.0 / dt, 1), "ms_per_iter": round(dt * 1e3, 3),
                              "s_per_2000_iters": round(2000 * dt, 2), "loss": "0.8 L1 + 0.2 (1 - SSIM)",
-                             "loss_first": round(l0, 5), "loss_after": round(float(loss), 5), "entries": entries,
+                             "loss_first": round(l0, 5), "loss_after": round(float(loss.detach()), 5), "entries": entries,
                              "fwd_kernel_us": round(fwd_us, 2),
                              "bwd_kernels_us": round(ev[1].elapsed_time(ev[2]) * 1e3 / 20, 2),
                              "fwd_pairs_per_s": round(entries * 256 / (fwd_us * 1e-6), 1),
@@ -384,6 +386,9 @@ def main():
     import torch
     import scenegen as S
     import paper_2403_14244_amd as P
+    if args.only_field2d:
+        print(json.dumps(field2d_workload("cuda")), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -9,6 +9,7 @@ buffers and marshals arguments.
 from __future__ import annotations
 
 import ctypes
+import math
 
 import torch
 
@@ -34,9 +35,10 @@ def _check_params(mu, sigma, amp):
 
 class Field2DRenderer:
     """Bins, renders and differentiates a 2D kernel-sum signal on a fixed image size and
-    support radius, keeping the entry capacity and the workspaces between calls. The
-    capacity grows on demand: a binning that overflows is repeated once with the exact
-    count plus headroom (one host synchronisation)."""
+    support radius, keeping the workspaces between calls. Every particle's support disk
+    meets at most (ceil(2D/16) + 1)^2 tiles, so the entry capacity is sized from that
+    bound (plus a margin of one tile per axis) and binning cannot overflow; an explicit
+    smaller `capacity` is grown on demand (one host synchronisation)."""
 
     def __init__(self, width, height, support, device="cuda", headroom=1.25):
         self.width, self.height, self.support = int(width), int(height), float(support)
@@ -51,14 +53,22 @@ class Field2DRenderer:
     def _grow(buf, nbytes):
         return buf if buf.numel() >= nbytes else torch.empty(int(nbytes), dtype=torch.uint8, device=buf.device)
 
-    def bin(self, mu, sigma, amp, check=True):
+    def tiles_bound(self) -> int:
+        return (math.ceil(2.0 * self.support / 16.0) + 2) ** 2
+
+    def bin(self, mu, sigma, amp, check=True, capacity=None):
         """Footprints and tile lists of the particles. With `check`, reads the device status
-        (one synchronisation) and grows the capacity on overflow."""
+        (one synchronisation) and grows the capacity on overflow; without it nothing
+        waits (safe at the default capacity, which no binning can exceed)."""
         _check_params(mu, sigma, amp)
         K = int(sigma.shape[0])
         fp = Footprints.empty(K, self.device)
         f = _field(mu, sigma, amp)
-        cap = self.capacity
+        if capacity is None:
+            self.capacity = max(self.capacity, K * self.tiles_bound())
+            cap = self.capacity
+        else:
+            cap = int(capacity)
         for _ in range(2):
             bins = _alloc_bins(cap, K, self.tiles, self.device)
             ab = bins.abi()
@@ -75,7 +85,8 @@ class Field2DRenderer:
                 return fp, bins
             if st != A.ISOGS_ERR_CAPACITY:
                 raise A.IsoGSError(st, "isogs_field2d_bin failed on the device")
-            cap = self.capacity = int(bins.n_entries() * self.headroom) + 4096
+            cap = int(bins.n_entries() * self.headroom) + 4096
+            self.capacity = max(self.capacity, cap)
         raise A.IsoGSError(A.ISOGS_ERR_CAPACITY, "field2d capacity still too small after growing")
 
     def render(self, fp: Footprints, bins: TileBins, K: int, out=None):
@@ -156,29 +167,18 @@ def split(mu, sigma, amp, sigma_max):
 
 class Field2DRender(torch.autograd.Function):
     """Differentiable image of a 2D kernel-sum signal: forward(mu, sigma, amp, renderer)
-    -> [3, H, W]; gradients flow to mu [2, K], sigma [K] and amp [3, K].
-
-    Once the renderer has a capacity, the forward queues binning and rendering without
-    waiting; the capacity status is read in the backward (or by `verify`), and an
-    overflow there raises IsoGSError after growing the capacity, so the caller repeats
-    the step."""
+    -> [3, H, W]; gradients flow to mu [2, K], sigma [K] and amp [3, K]. Nothing waits on
+    the host: the renderer's capacity bound rules out an overflow."""
 
     @staticmethod
     def forward(ctx, mu, sigma, amp, renderer):
         mu, sigma, amp = mu.contiguous(), sigma.contiguous(), amp.contiguous()
-        fp, bins = renderer.bin(mu, sigma, amp, check=renderer.capacity == 0)
+        fp, bins = renderer.bin(mu, sigma, amp, check=False)
         image = renderer.render(fp, bins, int(sigma.shape[0]))
         ctx.renderer, ctx.fp, ctx.bins, ctx.K = renderer, fp, bins, int(sigma.shape[0])
         return image
 
     @staticmethod
     def backward(ctx, grad_out):
-        r = ctx.renderer
-        gmu, gsig, gamp = r.grads(ctx.fp, ctx.bins, ctx.K, grad_out)
-        st = int(ctx.bins.status.item())
-        if st == A.ISOGS_ERR_CAPACITY:
-            r.capacity = int(ctx.bins.n_entries() * r.headroom) + 4096
-            raise A.IsoGSError(st, f"field2d entry capacity overflowed; grown to {r.capacity}, repeat the step")
-        if st != A.ISOGS_OK:
-            raise A.IsoGSError(st, "isogs_field2d_bin failed on the device")
+        gmu, gsig, gamp = ctx.renderer.grads(ctx.fp, ctx.bins, ctx.K, grad_out)
         return gmu, gsig, gamp, None

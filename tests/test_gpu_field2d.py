@@ -173,9 +173,11 @@ def test_field2d_capacity_overflow_recovers(P, torch_cuda):
     mu, s, a, W, H, D = _case("random_ragged")
     note("field2d capacity overflow")
     R = P.Field2DRenderer(W, H, D)
-    R.capacity = 16                      # far too small: the first binning overflows
-    fp, bins = R.bin(*_upload(torch_cuda, mu, s, a))
+    # far too small: the first binning overflows, the second runs with the exact count
+    fp, bins = R.bin(*_upload(torch_cuda, mu, s, a), capacity=16)
     ob = O.bin_sort_ref([F.field_footprints_f32(mu, s, a, W, H, D)])
-    assert R.capacity > ob.keys.shape[0] and bins.n_entries() == ob.keys.shape[0]
+    assert bins.capacity > ob.keys.shape[0] and bins.n_entries() == ob.keys.shape[0]
+    # the default capacity bounds every binning: at most (ceil(2D/16) + 1)^2 tiles a particle
+    assert int(ob.tile_count.max()) <= (int(np.ceil(2 * D / 16)) + 1) ** 2 < R.tiles_bound()
     img = R.render(fp, bins, s.shape[0]).cpu().numpy()
     assert np.abs(img - F.render_field64(mu, s, a, W, H, D)).max() <= IMG_TOL
