@@ -175,7 +175,7 @@ def training_workload(dev, iters=20):
         for q in params:
             q.grad = None
         img = P.IsoGSRender.apply(*params, init.sh_degree, cams, (0.0, 0.0, 0.0), R)
-        loss = (img - targets).abs().mean()
+        loss = P.l1_loss(img, targets)
         loss.backward()
 
     for _ in range(3):
@@ -217,7 +217,7 @@ def stress_workload(dev, iters=3):
         for q in params:
             q.grad = None
         img = P.IsoGSRender.apply(*params, init.sh_degree, cams, (0.0, 0.0, 0.0), R)
-        loss = (img - targets).abs().mean()
+        loss = P.l1_loss(img, targets)
         loss.backward()
 
     step()
@@ -521,7 +521,7 @@ def main():
         for q in params:
             q.grad = None   # what an optimizer's zero_grad() does before each step
         img = P.IsoGSRender.apply(*params, gs.sh_degree, cam1, (0.0, 0.0, 0.0), Rt)
-        loss = (img - target).abs().mean()
+        loss = P.l1_loss(img, target)
         loss.backward()
         return loss
 

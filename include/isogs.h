@@ -21,7 +21,7 @@
  * and, for the 2D kernel-sum representation of Section 3 (no compositing),
  * isogs_field2d_bin / isogs_field2d_fwd / isogs_field2d_bwd on the same bins, with its
  * quadtree initialisation and multiscale edits (isogs_field2d_tree_init / _prune /
- * _split), and the SSIM term of the loss, isogs_ssim_fwd / isogs_ssim_bwd.
+ * _split), and the loss terms, isogs_ssim_fwd / _bwd and isogs_l1_fwd / _bwd.
  *
  * Conventions shared by every call:
  *   - Every buffer pointer is DEVICE memory owned by the caller, except the arrays of
@@ -355,6 +355,17 @@ int isogs_ssim_fwd(const float* image, const float* target, int32_t channels, in
 int isogs_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height,
                    int32_t width, const float* dL_dssim, const void* ws, size_t ws_bytes,
                    float* dL_dimage, void* stream);
+
+/* The L1 term of the loss (Section 3): loss = mean |image - target| over n values (FP32
+ * per element, block sums added in FP64 in a fixed order), and its gradient
+ * dL/dimage = dL/dloss * sign(image - target) / n with sign(0) = 0. `loss` and `dL_dloss`
+ * are device scalars; ws holds one FP64 partial sum per 4096 values (query with
+ * ws == NULL). Errors: ISOGS_ERR_INVALID (n < 0 or >= 2^40, NULL buffers),
+ * ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
+int isogs_l1_fwd(const float* image, const float* target, int64_t n, float* loss, void* ws,
+                 size_t* ws_bytes, void* stream);
+int isogs_l1_bwd(const float* image, const float* target, int64_t n, const float* dL_dloss,
+                 float* dL_dimage, void* stream);
 
 /* Message describing the last error returned on the calling thread ("" if none). */
 const char* isogs_last_error(void);

@@ -11,8 +11,8 @@ _lib()
 from .rasterizer import (GaussianScene, Footprints, TileBins, Rasterizer, IsoGSRender,  # noqa: E402,F401
                          split_images, tiles_of)
 from .field2d import Field2DRenderer, Field2DRender, tree_init, prune, split  # noqa: E402,F401
-from .loss import SSIM, ssim, l1_ssim_loss  # noqa: E402,F401
+from .loss import SSIM, L1, ssim, l1_loss, l1_ssim_loss  # noqa: E402,F401
 
 __all__ = ["GaussianScene", "Footprints", "TileBins", "Rasterizer", "IsoGSRender", "IsoGSError",
-           "split_images", "tiles_of", "Field2DRenderer", "Field2DRender", "SSIM", "ssim", "l1_ssim_loss",
+           "split_images", "tiles_of", "Field2DRenderer", "Field2DRender", "SSIM", "L1", "ssim", "l1_loss", "l1_ssim_loss",
            "tree_init", "prune", "split"]

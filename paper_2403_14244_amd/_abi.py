@@ -22,7 +22,8 @@ ISOGS_FWD_WIDE = 1
 EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
             "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_field2d_bin", "isogs_field2d_fwd",
             "isogs_field2d_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune", "isogs_field2d_split",
-            "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_last_error", "isogs_version")
+            "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_last_error",
+            "isogs_version")
 
 
 class Scene(ctypes.Structure):
@@ -93,6 +94,8 @@ def lib():
                                               vp]
         for name in ("isogs_field2d_prune", "isogs_field2d_split"):
             getattr(L, name).argtypes = [P(Field2D), ctypes.c_float, P(Field2D), vp, vp, P(ctypes.c_size_t), vp]
+        L.isogs_l1_fwd.argtypes = [vp, vp, ctypes.c_int64, vp, vp, P(ctypes.c_size_t), vp]
+        L.isogs_l1_bwd.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp]
         L.isogs_ssim_fwd.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
                                      P(ctypes.c_size_t), vp]
         L.isogs_ssim_bwd.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_size_t,
@@ -102,7 +105,7 @@ def lib():
         for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
                      "isogs_render_bwd", "isogs_field2d_bin", "isogs_field2d_fwd", "isogs_field2d_bwd",
                      "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune",
-                     "isogs_field2d_split"):
+                     "isogs_field2d_split", "isogs_l1_fwd", "isogs_l1_bwd"):
             getattr(L, name).restype = ctypes.c_int
         L.isogs_last_error.restype = ctypes.c_char_p
         L.isogs_last_error.argtypes = []

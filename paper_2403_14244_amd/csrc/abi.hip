@@ -414,4 +414,31 @@ int isogs_field2d_split(const isogs_field2d* in, float sigma_max, const isogs_fi
     return field2d_edit(1, "isogs_field2d_split", in, sigma_max, out, count, ws, ws_bytes, stream);
 }
 
+int isogs_l1_fwd(const float* image, const float* target, int64_t n, float* loss, void* ws, size_t* ws_bytes,
+                 void* stream) {
+    g_error[0] = 0;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (n < 0 || (uint64_t)n >= (1ull << 40)) return fail(ISOGS_ERR_INVALID, "n must be in [0, 2^40)");
+    const size_t need = isogs::l1_ws_bytes((uint64_t)n);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!loss || (n > 0 && (!image || !target))) return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (isogs::launch_l1_fwd(image, target, (uint64_t)n, loss, ws, (hipStream_t)stream)) return device_fail("isogs_l1_fwd");
+    return ISOGS_OK;
+}
+
+int isogs_l1_bwd(const float* image, const float* target, int64_t n, const float* dL_dloss, float* dL_dimage,
+                 void* stream) {
+    g_error[0] = 0;
+    if (n < 0 || (uint64_t)n >= (1ull << 40)) return fail(ISOGS_ERR_INVALID, "n must be in [0, 2^40)");
+    if (!dL_dloss || (n > 0 && (!image || !target || !dL_dimage))) return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (isogs::launch_l1_bwd(image, target, (uint64_t)n, dL_dloss, dL_dimage, (hipStream_t)stream))
+        return device_fail("isogs_l1_bwd");
+    return ISOGS_OK;
+}
+
 }  // extern "C"

@@ -85,4 +85,10 @@ size_t edit_ws(int32_t K);
 int launch_edit(int mode, float thr, const isogs_field2d* in, const isogs_field2d* out, int32_t cap, int32_t* count,
                 void* ws, hipStream_t stream);
 
+// The L1 term of the loss: mean |image - target| and its gradient.
+size_t l1_ws_bytes(uint64_t n);
+int launch_l1_fwd(const float* image, const float* target, uint64_t n, float* loss, void* ws, hipStream_t stream);
+int launch_l1_bwd(const float* image, const float* target, uint64_t n, const float* dL_dloss, float* dL_dimage,
+                  hipStream_t stream);
+
 }  // namespace isogs

@@ -1,4 +1,6 @@
-// The SSIM term of the paper's loss (Section 3): mean structural similarity of a rendered
+// The loss of the paper (Section 3): the SSIM term and the L1 term.
+//
+// SSIM: mean structural similarity of a rendered
 // image and its target under an 11 x 11 Gaussian window (sigma 1.5, zero outside the
 // image), C1 = 0.01^2, C2 = 0.03^2, and its gradient with respect to the rendered image.
 //
@@ -13,6 +15,8 @@
 // dSSIM/dx = (G*dS/dm1 + 2 x G*dS/de11 + y G*dS/de12) / N.
 #include "common.h"
 #include "kernels.h"
+
+#include <algorithm>
 
 namespace isogs {
 
@@ -232,6 +236,86 @@ int launch_ssim_bwd(const float* image, const float* target, int32_t channels, i
                        image, target, width, height, tx, make_window(),
                        reinterpret_cast<const float*>(base + L.off_m1), reinterpret_cast<const float*>(base + L.off_e11),
                        reinterpret_cast<const float*>(base + L.off_e12), dL_dssim, inv_n, dL_dimage);
+    return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace isogs
+
+// ---- L1 term of the loss -------------------------------------------------------------
+// mean |image - target|: block b sums its contiguous chunk of kL1Chunk values (FP32 per
+// lane, then FP64 across the block's lanes in a fixed order); one workgroup adds the block
+// sums in FP64 in block order. The backward writes g sign(image - target) / n, sign(0) = 0.
+namespace isogs {
+
+namespace {
+
+constexpr int kL1Threads = 256, kL1PerThread = 16;
+constexpr uint32_t kL1Chunk = kL1Threads * kL1PerThread;
+
+__global__ void __launch_bounds__(kL1Threads) l1_partial_kernel(const float* __restrict__ image,
+                                                                const float* __restrict__ target, uint64_t n,
+                                                                double* __restrict__ block_sum) {
+    __shared__ double s_w[kL1Threads / kWave];
+    const uint64_t base = (uint64_t)blockIdx.x * kL1Chunk;
+    float a = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kL1PerThread; ++i) {
+        const uint64_t k = base + (uint64_t)i * kL1Threads + threadIdx.x;
+        if (k < n) a += fabsf(image[k] - target[k]);
+    }
+    double d = (double)a;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, kWave);
+    if ((threadIdx.x & 63u) == 0) s_w[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = ((s_w[0] + s_w[1]) + s_w[2]) + s_w[3];
+}
+
+__global__ void __launch_bounds__(256) l1_final_kernel(const double* __restrict__ block_sum, uint32_t n_blocks,
+                                                       double inv_n, float* __restrict__ loss) {
+    __shared__ double s_run[256];
+    const uint32_t t = threadIdx.x, per = (n_blocks + 255u) / 256u;
+    double a = 0.0;
+    for (uint32_t i = t * per; i < min(n_blocks, (t + 1u) * per); ++i) a += block_sum[i];
+    s_run[t] = a;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < 256; ++i) tot += s_run[i];
+        *loss = (float)(tot * inv_n);
+    }
+}
+
+__global__ void __launch_bounds__(kL1Threads) l1_grad_kernel(const float* __restrict__ image,
+                                                             const float* __restrict__ target, uint64_t n,
+                                                             const float* __restrict__ dL_dloss, float inv_n,
+                                                             float* __restrict__ dL_dimage) {
+    const float g = *dL_dloss * inv_n;
+    for (uint64_t k = (uint64_t)blockIdx.x * kL1Threads + threadIdx.x; k < n; k += (uint64_t)gridDim.x * kL1Threads) {
+        const float d = image[k] - target[k];
+        dL_dimage[k] = d > 0.0f ? g : (d < 0.0f ? -g : 0.0f);
+    }
+}
+
+}  // namespace
+
+size_t l1_ws_bytes(uint64_t n) { return ((n + kL1Chunk - 1) / kL1Chunk + 1) * sizeof(double); }
+
+int launch_l1_fwd(const float* image, const float* target, uint64_t n, float* loss, void* ws, hipStream_t stream) {
+    const uint32_t nb = (uint32_t)((n + kL1Chunk - 1) / kL1Chunk);
+    double* blocks = static_cast<double*>(ws);
+    if (nb)
+        hipLaunchKernelGGL(l1_partial_kernel, dim3(nb), dim3(kL1Threads), 0, stream, image, target, n, blocks);
+    hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, stream, blocks, nb, n ? 1.0 / (double)n : 0.0, loss);
+    return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_l1_bwd(const float* image, const float* target, uint64_t n, const float* dL_dloss, float* dL_dimage,
+                  hipStream_t stream) {
+    if (!n) return 0;
+    const uint64_t blocks = std::min<uint64_t>((n + kL1Threads - 1) / kL1Threads, 8192);
+    hipLaunchKernelGGL(l1_grad_kernel, dim3((unsigned)blocks), dim3(kL1Threads), 0, stream, image, target, n, dL_dloss,
+                       (float)(1.0 / (double)n), dL_dimage);
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -1,9 +1,9 @@
 """The paper's loss (Section 3): (1 - lambda) L1 + lambda (1 - SSIM), lambda = 0.2.
 
-SSIM and its gradient run in the library's HIP kernels (``isogs_ssim_fwd`` /
-``isogs_ssim_bwd`` of include/isogs.h: 11 x 11 Gaussian window, sigma 1.5, zero outside
-the image, C1 = 0.01^2, C2 = 0.03^2); the L1 term is torch's. This module marshals
-arguments only.
+Both terms and their gradients run in the library's HIP kernels (``isogs_l1_fwd`` /
+``_bwd`` and ``isogs_ssim_fwd`` / ``_bwd`` of include/isogs.h; SSIM: 11 x 11 Gaussian
+window, sigma 1.5, zero outside the image, C1 = 0.01^2, C2 = 0.03^2). This module
+marshals arguments only.
 """
 from __future__ import annotations
 
@@ -57,10 +57,42 @@ class SSIM(torch.autograd.Function):
         return dimg, None
 
 
+class L1(torch.autograd.Function):
+    """mean |image - target| (target constant), two kernels forward, one backward."""
+
+    @staticmethod
+    def forward(ctx, image, target):
+        image, target = image.contiguous(), target.contiguous()
+        if image.shape != target.shape or image.dtype != torch.float32 or not image.is_cuda:
+            raise ValueError("image and target: CUDA float32 tensors of one shape")
+        n = image.numel()
+        need = ctypes.c_size_t(0)
+        A.check(A.lib().isogs_l1_fwd(None, None, n, None, None, ctypes.byref(need), _stream()))
+        ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=image.device)
+        out = torch.empty(1, dtype=torch.float32, device=image.device)
+        have = ctypes.c_size_t(ws.numel())
+        A.check(A.lib().isogs_l1_fwd(_p(image), _p(target), n, _p(out), _p(ws), ctypes.byref(have), _stream()))
+        ctx.save_for_backward(image, target)
+        return out[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        image, target = ctx.saved_tensors
+        g = grad_out.reshape(1).to(torch.float32).contiguous()
+        dimg = torch.empty_like(image)
+        A.check(A.lib().isogs_l1_bwd(_p(image), _p(target), image.numel(), _p(g), _p(dimg), _stream()))
+        return dimg, None
+
+
 def ssim(image, target):
     return SSIM.apply(image, target)
 
 
+def l1_loss(image, target):
+    """mean |image - target|, differentiable in `image`."""
+    return L1.apply(image, target)
+
+
 def l1_ssim_loss(image, target, lam=LAMBDA):
     """(1 - lam) mean|image - target| + lam (1 - SSIM(image, target))."""
-    return (1.0 - lam) * (image - target).abs().mean() + lam * (1.0 - ssim(image, target))
+    return (1.0 - lam) * l1_loss(image, target) + lam * (1.0 - ssim(image, target))

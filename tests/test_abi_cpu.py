@@ -221,3 +221,13 @@ def test_tree_init_and_edits_invalid_arguments():
     assert need.value >= 4 * 4
     assert L.isogs_field2d_split(ctypes.byref(fi), float("nan"), ctypes.byref(out), None, None, ctypes.byref(need),
                                  None) == A.ISOGS_ERR_INVALID
+
+
+def test_l1_invalid_arguments_and_workspace_query():
+    A = _abi()
+    L = A.lib()
+    need = ctypes.c_size_t(0)
+    assert L.isogs_l1_fwd(None, None, 10_000, None, None, ctypes.byref(need), None) == A.ISOGS_OK
+    assert need.value >= 8 * 3
+    assert L.isogs_l1_fwd(None, None, -1, None, None, ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    assert L.isogs_l1_bwd(None, None, 5, None, None, None) == A.ISOGS_ERR_INVALID

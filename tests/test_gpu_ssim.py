@@ -87,3 +87,21 @@ def test_loss_matches_oracle_and_is_deterministic(P, torch_cuda):
     assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
     tol = 1e-3 * np.abs(gref) + 1e-3 * np.abs(gref).max()
     assert np.all(np.abs(outs[0][1] - gref) <= tol)
+
+
+@pytest.mark.parametrize("n_shape", [(3, 1080, 1920), (1, 1, 4097), (2, 3, 5)])
+def test_l1_matches_oracle(P, torch_cuda, n_shape):
+    # the L1 term: mean |x - y| to FP32 rounding of the per-lane sums, gradient
+    # sign(x - y) / n exactly (sign(0) = 0 where clipping made the values equal)
+    from oracle import field2d64 as F
+    torch = torch_cuda
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0, 1, n_shape).astype(np.float32)
+    y = np.clip(x + rng.normal(0, 0.3, n_shape), 0, 1).astype(np.float32)
+    note(f"l1 {n_shape}")
+    ref, gref = F.l1_loss64(x, y)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    loss = P.l1_loss(xt, torch.from_numpy(y).cuda())
+    (loss * 2.0).backward()
+    assert abs(float(loss) - ref) <= 1e-6 * max(1.0, ref)
+    np.testing.assert_array_equal(xt.grad.cpu().numpy(), (2.0 * gref).astype(np.float32))
