@@ -141,6 +141,17 @@ def _bin_case(name):
         u, v, z, r = S.crowded_projected(3000, 48, 32, 24.0, 8.0, 2.0, seed=60, max_radius=0.5,
                                          depths=[1.0 + k / 16 for k in range(64)])
         return [H.synthetic_f32_footprints(u, v, z, r, 48, 32)], [S.look_at_camera((0, 0, 3), width=48, height=32)]
+    if name == "all_tiles_long":
+        # every tile of a 208x200 view holds more than 512 entries, so each of the 64 lists
+        # of long segments receives two or three tiles (tile ids equal modulo 64)
+        rng = np.random.default_rng(70)
+        n = 30_000
+        u = rng.uniform(0, 208, n).astype(np.float32)
+        v = rng.uniform(0, 200, n).astype(np.float32)
+        z = rng.uniform(0.5, 9.0, n).astype(np.float32)
+        r = rng.uniform(12.0, 20.0, n).astype(np.float32)
+        cam = S.look_at_camera((0, 0, 3), width=208, height=200)
+        return [H.synthetic_f32_footprints(u, v, z, r, 208, 200, seed=5)], [cam]
     if name == "single_tile":
         u, v, z, r = S.random_projected(400, 16, 16, seed=50, max_radius=6.0, depth_ties=True)
         return [H.synthetic_f32_footprints(u, v, z, r, 16, 16)], [S.look_at_camera((0, 0, 3), width=16, height=16)]
@@ -156,7 +167,8 @@ def _bin_case(name):
 
 
 BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled",
-             "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_ties_bucketed", "single_tile"]
+             "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_ties_bucketed", "single_tile",
+             "all_tiles_long"]
 
 
 @pytest.mark.parametrize("case", BIN_CASES)
