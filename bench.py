@@ -250,7 +250,7 @@ def field2d_workload(dev, iters=100):
     binning, kernel sum, loss, gradients, optimizer step. Also the kernel sum's and its
     backward's times alone (HIP events on their stream), and the same number of
     iterations from the quadtree initialisation (at most 2000 leaves) instead of the
-    random one."""
+    random one, and the rate of the step captured once in a HIP graph and replayed."""
     import torch
     import scenegen as S
     import paper_2403_14244_amd as P
@@ -319,12 +319,44 @@ def field2d_workload(dev, iters=100):
             torch.cuda.synchronize()
         entries = bins.n_entries()
         fwd_us = ev[0].elapsed_time(ev[1]) * 1e3 / 20
+        # the same step captured once in a HIP graph and replayed (no host work per step)
+        gparams = [torch.from_numpy(x.copy()).to(dev).requires_grad_(True) for x in (mu0, s0, a0)]
+        gopt = torch.optim.Adam(gparams, lr=0.02, capturable=True)
+        Rg = P.Field2DRenderer(512, 512, D, device=dev)
+
+        def gstep():
+            gopt.zero_grad(set_to_none=True)
+            gl = P.l1_ssim_loss(P.Field2DRender.apply(*gparams, Rg), tgt)
+            gl.backward()
+            gopt.step()
+            with torch.no_grad():
+                gparams[1].clamp_(min=0.3)
+            return gl
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                gstep()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gloss = gstep()
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(iters):
+            graph.replay()
+        torch.cuda.synchronize()
+        gdt = (time.perf_counter() - t0) / iters
         res[f"d{int(D)}"] = {"iters_per_s": round(1.0 / dt, 1), "ms_per_iter": round(dt * 1e3, 3),
                              "s_per_2000_iters": round(2000 * dt, 2), "loss": "0.8 L1 + 0.2 (1 - SSIM)",
                              "loss_first": round(l0, 5), "loss_after": round(float(loss.detach()), 5), "entries": entries,
                              "fwd_kernel_us": round(fwd_us, 2),
                              "bwd_kernels_us": round(ev[1].elapsed_time(ev[2]) * 1e3 / 20, 2),
                              "fwd_pairs_per_s": round(entries * 256 / (fwd_us * 1e-6), 1),
+                             "graph_iters_per_s": round(1.0 / gdt, 1),
+                             "graph_loss_after": round(float(gloss.detach()), 5),
                              "tree_init_loss_first": round(tree_first, 5),
                              "tree_init_loss_after": round(tree_after, 5)}
     return res

@@ -181,3 +181,50 @@ def test_field2d_capacity_overflow_recovers(P, torch_cuda):
     assert int(ob.tile_count.max()) <= (int(np.ceil(2 * D / 16)) + 1) ** 2 < R.tiles_bound()
     img = R.render(fp, bins, s.shape[0]).cpu().numpy()
     assert np.abs(img - F.render_field64(mu, s, a, W, H, D)).max() <= IMG_TOL
+
+
+def test_field2d_fit_step_replays_in_a_hip_graph(P, torch_cuda):
+    # the whole step (binning, kernel sum, L1 + SSIM loss, gradients, Adam) captured once
+    # and replayed: every replay, with eager work and synchronisations in between, must
+    # leave the parameters bitwise where the same steps taken eagerly leave them
+    torch = torch_cuda
+    tgt_np = S.field2d_target(128, 128, seed=6)
+    mu0, s0, a0 = S.field2d_init(tgt_np, 300, seed=7)
+    tgt = torch.from_numpy(tgt_np).cuda()
+    note("field2d fit step in a HIP graph: K=300, 128x128, D=12")
+
+    def make():
+        params = [torch.from_numpy(x.copy()).cuda().requires_grad_(True) for x in (mu0, s0, a0)]
+        opt = torch.optim.Adam(params, lr=0.02, capturable=True)
+        R = P.Field2DRenderer(128, 128, 12.0)
+
+        def step():
+            opt.zero_grad(set_to_none=True)
+            loss = P.l1_ssim_loss(P.Field2DRender.apply(*params, R), tgt)
+            loss.backward()
+            opt.step()
+            with torch.no_grad():
+                params[1].clamp_(min=0.3)
+            return loss
+        return params, step
+
+    eager_params, eager_step = make()
+    graph_params, graph_step = make()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(3):            # warm-up: workspaces, capacity, optimizer state
+            eager_step()
+            graph_step()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        static_loss = graph_step()
+    for i in range(4):
+        g.replay()
+        eager_loss = eager_step()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+        assert float(static_loss) == float(eager_loss), f"replay {i}: loss differs"
+        for a, b in zip(graph_params, eager_params):
+            assert torch.equal(a, b), f"replay {i}: parameters differ"
