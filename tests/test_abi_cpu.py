@@ -1,6 +1,8 @@
 """Host-side checks of the C ABI: the library loads, exports what include/isogs.h
 declares, and rejects invalid arguments before touching a device. No GPU needed."""
 import ctypes
+import subprocess
+import sys
 import os
 import re
 
@@ -49,13 +51,47 @@ def test_header_constants_match_the_oracle():
     assert val("ISOGS_T_MIN") == O.T_MIN
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
     A = _abi()
     assert ctypes.sizeof(A.Camera) == 4 * (9 + 3 + 3 + 4) + 8
     assert ctypes.sizeof(A.Scene) == 4 * 8 + 8
     assert ctypes.sizeof(A.Projected) == 3 * 8
     assert ctypes.sizeof(A.Bins) == 7 * 8
     assert A.Bins.capacity.offset == 32
+    # sizes and field offsets as a C compiler lays the header's structs out
+    structs = {"isogs_scene": A.Scene, "isogs_camera": A.Camera, "isogs_projected": A.Projected,
+               "isogs_bins": A.Bins, "isogs_field2d": A.Field2D}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in ct._fields_:
+            cf = "near_z" if fname == "near_z" else fname
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, ct in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(ct), cname
+        for fname, _ in ct._fields_:
+            assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # the package copied without libisogs.so: importing it raises, no fallback path exists
+    import shutil
+    pkg = tmp_path / "paper_2403_14244_amd"
+    pkg.mkdir()
+    src = os.path.join(os.path.dirname(HEADER), "..", "paper_2403_14244_amd")
+    for f in os.listdir(src):
+        if f.endswith(".py"):
+            shutil.copy(os.path.join(src, f), pkg / f)
+    r = subprocess.run([sys.executable, "-c", "import paper_2403_14244_amd"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0 and "libisogs.so is missing" in r.stderr
 
 
 def _cam(w=64, h=48):
