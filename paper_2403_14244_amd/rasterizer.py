@@ -94,7 +94,7 @@ class Footprints:
 @dataclass
 class TileBins:
     """Output of bin_sort. Entry arrays hold `capacity` slots; `count` and `status` live
-    on the device."""
+    on the device, as the two adjacent words of one allocation (read back together)."""
     keys: torch.Tensor | None    # [capacity] int64 (uint64 on the device); None: not requested
     pidx: torch.Tensor           # [capacity] int32
     ranges: torch.Tensor         # [T, 2] int32
@@ -127,12 +127,12 @@ def tiles_of(cam) -> int:
 
 def _alloc_bins(capacity, n_total, tiles_total, device, with_keys=False) -> TileBins:
     cap = max(int(capacity), 1)
+    words = torch.zeros(2, dtype=torch.int32, device=device)   # {count, status}: one fill, one read-back
     return TileBins(keys=torch.empty(cap, dtype=torch.int64, device=device) if with_keys else None,
                     pidx=torch.empty(cap, dtype=torch.int32, device=device),
                     ranges=torch.empty((tiles_total, 2), dtype=torch.int32, device=device),
                     offsets=torch.empty(max(n_total, 1), dtype=torch.int32, device=device)[:n_total],
-                    count=torch.zeros(1, dtype=torch.int32, device=device),
-                    status=torch.zeros(1, dtype=torch.int32, device=device), capacity=cap)
+                    count=words[0:1], status=words[1:2], capacity=cap)
 
 
 class Rasterizer:
@@ -291,8 +291,8 @@ class Rasterizer:
         pending = None
         if check == "deferred" and self.capacity > 0:
             pending = torch.empty(2, dtype=torch.int32, pin_memory=True)
-            pending[0:1].copy_(bins.status, non_blocking=True)
-            pending[1:2].copy_(bins.count, non_blocking=True)
+            # count and status are adjacent words of one allocation (_alloc_bins): one copy
+            pending.copy_(bins.count.as_strided((2,), (1,)), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(torch.cuda.current_stream())
             pending = (pending, ev)
@@ -317,7 +317,7 @@ class Rasterizer:
             return
         host, ev = state["pending"]
         ev.synchronize()
-        st, count = int(host[0]), int(host[1])
+        count, st = int(host[0]), int(host[1])   # {count, status}
         state["pending"] = None
         if st == A.ISOGS_ERR_CAPACITY:
             self.capacity = int(count * self.headroom) + 4096

@@ -274,9 +274,8 @@ class GpuExecutor(Executor):
             fp = R.project(scenes, cams)
             bins = R.bin_sort(fp, npv, cams, check=False, capacity=cap)
             img, T, nl = R.render_fwd_ordered(fp, npv, bins, cams, wide=True)
-            status = torch.empty(2, dtype=torch.int32, pin_memory=True)
-            status[0:1].copy_(bins.status, non_blocking=True)
-            status[1:2].copy_(bins.count, non_blocking=True)
+            status = torch.empty(2, dtype=torch.int32, pin_memory=True)   # {count, status}
+            status.copy_(bins.count.as_strided((2,), (1,)), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
         return dict(si=si, batch=batch, ev=ev, fp=fp, bins=bins, img=img, status=status, npv=npv, cams=cams,
@@ -288,7 +287,7 @@ class GpuExecutor(Executor):
     def finish(self, h):
         torch = self.torch
         from .rasterizer import split_images
-        st, count = int(h["status"][0]), int(h["status"][1])
+        count, st = int(h["status"][0]), int(h["status"][1])
         R = self.rasters[h["si"]]
         img = h["img"]
         if st != 0:
