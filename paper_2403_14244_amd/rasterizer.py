@@ -348,21 +348,30 @@ class IsoGSRender(torch.autograd.Function):
         scene = GaussianScene(pos.contiguous(), scale.contiguous(), opacity.contiguous(), color.contiguous(),
                               int(sh_degree))
         scenes = [scene] * len(cams)
+        if len({(int(c.width), int(c.height)) for c in cams}) != 1:
+            raise ValueError("IsoGSRender: every camera must have the same size")
         images, st = rasterizer.render(scenes, cams, bg, check="deferred", checkpoints=True, wide=True)
         ctx.rasterizer = rasterizer
         ctx.cams = cams
         ctx.bg = bg
         ctx.scene = scene
         ctx.st = st
-        return torch.stack(images)
+        # the views are packed back to back in one buffer: the batch is a view of it, no
+        # copy. The backward reads the same buffer (checkpointed tiles restart from it), so
+        # it is saved as an output: autograd then refuses a backward after an in-place
+        # change of the returned images.
+        out = st.pop("image").view(len(cams), 3, int(cams[0].height), int(cams[0].width))
+        ctx.save_for_backward(out)
+        return out
 
     @staticmethod
     def backward(ctx, grad_out):
         st = ctx.st
+        (image,) = ctx.saved_tensors
         scenes = [ctx.scene] * len(ctx.cams)
         g = ctx.rasterizer.render_bwd(scenes, ctx.cams, st["fp"], st["bins"], ctx.bg,
                                       grad_out.contiguous().reshape(-1), st["T"], st["n_last"],
-                                      image=st["image"], ckpt=st["ckpt"])[0]
+                                      image=image.reshape(-1), ckpt=st["ckpt"])[0]
         # the forward's capacity status is read only now, behind the queued backward, so
         # that neither pass waits for the device (on an overflow every kernel after the
         # sort skipped its work and this raises)

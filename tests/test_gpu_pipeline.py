@@ -359,6 +359,27 @@ def test_autograd_function_and_determinism(P, torch_cuda):
         _grad_check(gg, ref[name], name, rel=5e-3, floor=1e-3)
 
 
+def test_autograd_output_guarded_against_inplace_changes(P, torch_cuda):
+    """The batch returned by the autograd forward is the render buffer itself (no copy),
+    which the backward reads; an in-place change of it must make the backward fail
+    rather than use the changed image."""
+    torch = torch_cuda
+    sc = _grad_scene(2, n=300, seed=5)
+    cams = [S.look_at_camera((0.1, 0.1, 3.0), width=48, height=40)]
+    note("autograd output in-place guard")
+    params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+              for a in (sc.pos, sc.scale, sc.opacity, sc.color)]
+    img = P.IsoGSRender.apply(*params, sc.sh_degree, cams, (0.0, 0.0, 0.0), P.Rasterizer())
+    assert img.shape == (1, 3, 40, 48)
+    with torch.no_grad():
+        img.mul_(2.0)
+    with pytest.raises(RuntimeError):
+        img.sum().backward()
+    with pytest.raises(ValueError):
+        P.IsoGSRender.apply(*params, sc.sh_degree, [cams[0], S.look_at_camera((0, 0, 3), width=32, height=40)],
+                            (0.0, 0.0, 0.0), P.Rasterizer())
+
+
 def test_autograd_deferred_capacity_check(P, torch_cuda):
     """The autograd forward does not wait for the capacity status once a capacity is known;
     an overflow is reported by the backward (IsoGSError, capacity grown) and the repeated
