@@ -5,7 +5,6 @@ Both sides read the same FP32 parameters. Binning is integer work and must be bi
 images must match to max-abs 1e-4 (the support decision is taken in FP32 on both sides,
 so no pixel is flagged); gradients to |d| <= 1e-3 |g| + 1e-4 max|g| per group.
 """
-import math
 import sys
 
 import numpy as np
