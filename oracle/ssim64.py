@@ -36,7 +36,6 @@ and FP64 central differences of the gradient.
 """
 from __future__ import annotations
 
-
 import numpy as np
 from scipy.ndimage import correlate1d
 
