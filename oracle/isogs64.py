@@ -156,7 +156,9 @@ def project64(scene, cam) -> Projected64:
     screen scale s = f sigma / z (isotropic footprint, Section 2 "View Dependency");
     rgb = max(0, c_0 + sum_{l>=1} c_lm Y_lm(d)), d = (mu - eye)/|mu - eye|.
     A particle is invisible when any input is non-finite, sigma <= 0, o < 1/255 (it can
-    never reach alpha >= 1/255) or z <= near.
+    never reach alpha >= 1/255), z <= near, or its footprint has no normal FP32 form (the
+    centre, 1/s^2 or the binning radius overflows, or 1/s^2 falls below the smallest normal
+    FP32 value).
     Binning radius r = s sqrt(ln(255 o)) (1 + 2^-10) + 2^-6: alpha = o exp(-d^2/s^2) >= 1/255
     exactly when d <= s sqrt(ln(255 o)); the small growth makes the FP32 tile test a
     superset of that disk.
@@ -192,6 +194,14 @@ def project64(scene, cam) -> Projected64:
         visible &= np.isfinite(u) & np.isfinite(v) & np.isfinite(s) & (s > 0) & np.isfinite(rgb).all(axis=0)
         radius = np.where(visible, s * np.sqrt(np.log(np.where(visible, 255.0 * o, 1.0)))
                           * RADIUS_GROW + RADIUS_PAD, 0.0)
+        # a footprint must be representable in FP32 (the stored form of every footprint):
+        # 1/s^2 finite and at least the smallest normal FP32 value, the binning radius
+        # finite, else it is culled
+        inv32 = np.where(visible, 1.0 / np.where(visible, s * s, 1.0), 1.0).astype(np.float32)
+        visible &= (np.isfinite(inv32) & (inv32 >= np.finfo(np.float32).tiny)
+                    & np.isfinite(radius.astype(np.float32)) & np.isfinite(u.astype(np.float32))
+                    & np.isfinite(v.astype(np.float32)))
+        radius = np.where(visible, radius, 0.0)
     return Projected64(u=u, v=v, z=z, s=s, opacity=o, rgb=rgb, radius=radius, visible=visible,
                        p=p, dirs=dirs, dist=dist, rgb_raw=rgb_raw)
 
@@ -328,7 +338,8 @@ def bin_sort_ref(views):
 # Compositing (eq. 4) with the isotropic kernel (eq. 8).
 # --------------------------------------------------------------------------------------
 
-def composite_pixels(px, py, seq, u, v, s, o, rgb, bg, trace=False, alpha_band=None, term_band=None):
+def composite_pixels(px, py, seq, u, v, s, o, rgb, bg, trace=False, alpha_band=None, term_band=None,
+                     pos_err=None, z32=None):
     """Front-to-back compositing of one particle sequence at a set of pixel centres.
 
     For every pixel (px, py) independently, walking ``seq`` (particle indices in depth
@@ -341,6 +352,16 @@ def composite_pixels(px, py, seq, u, v, s, o, rgb, bg, trace=False, alpha_band=N
     decision margins used for flagging: a pixel is near a decision when some entry's
     alpha lies within a relative ``alpha_band`` of 1/255, or some T after an entry lies
     within a relative ``term_band`` of 1e-4.
+
+    When the footprints an implementation composites are themselves roundings of these
+    ones (an end-to-end comparison), ``pos_err`` [n] bounds each particle's footprint
+    centre error in pixels and ``z32`` [n] gives the FP32 depths that order the lists. An
+    entry's alpha band then grows by the relative change of exp(-d^2/s^2) that a shift of
+    the centre by pos_err in x and y can cause, (2 (|dx| + |dy|) e + 2 e^2) / s^2; the
+    band of T grows by what those alpha changes do to T, the sum over the composited
+    entries of alpha/(1 - alpha) times that growth; and a pixel is also near a decision
+    when two consecutive composited entries have FP32 depths at most one ulp apart (their
+    order may differ). Without them the flags are as described above.
     """
     alpha_band = ALPHA_FLAG_REL if alpha_band is None else alpha_band
     term_band = TERM_FLAG_REL if term_band is None else term_band
@@ -353,6 +374,9 @@ def composite_pixels(px, py, seq, u, v, s, o, rgb, bg, trace=False, alpha_band=N
     done = np.zeros(P, dtype=bool)
     near_alpha = np.zeros(P, dtype=bool)
     near_term = np.zeros(P, dtype=bool)
+    t_band = np.full(P, float(term_band))
+    zb = None if z32 is None else np.asarray(z32, dtype=np.float32).view(np.int32).astype(np.int64)
+    prev_z = np.full(P, -(1 << 40), dtype=np.int64)
     rec = [] if trace else None
     for pos, g in enumerate(seq):
         if done.all():
@@ -363,14 +387,23 @@ def composite_pixels(px, py, seq, u, v, s, o, rgb, bg, trace=False, alpha_band=N
         G = np.exp(-d2 / (s[g] * s[g]))
         a = np.minimum(ALPHA_MAX, o[g] * G)
         live = ~done
-        near_alpha |= live & (np.abs(a * 255.0 - 1.0) <= alpha_band)
+        grow = 0.0
+        if pos_err is not None:
+            e = float(pos_err[g])
+            grow = (2.0 * (np.abs(dx) + np.abs(dy)) * e + 2.0 * e * e) / (s[g] * s[g])
+        near_alpha |= live & (np.abs(a * 255.0 - 1.0) <= alpha_band + grow)
         use = live & (a >= ALPHA_MIN)
         if not use.any():
             continue
         w = np.where(use, a * T, 0.0)
         C = C + rgb[:, g][:, None] * w[None, :]
         T_new = np.where(use, T * (1.0 - a), T)
-        near_term |= use & (np.abs(T_new / T_MIN - 1.0) <= term_band)
+        if pos_err is not None:
+            t_band = t_band + np.where(use, a / (1.0 - a) * grow, 0.0)
+        near_term |= use & (np.abs(T_new / T_MIN - 1.0) <= t_band)
+        if zb is not None:
+            near_alpha |= use & (np.abs(zb[g] - prev_z) <= 1)
+            prev_z = np.where(use, zb[g], prev_z)
         if trace:
             rec.append((pos, g, np.where(use, a, 0.0), T.copy(), use.copy(), G))
         T = T_new
@@ -387,6 +420,139 @@ def composite_pixels(px, py, seq, u, v, s, o, rgb, bg, trace=False, alpha_band=N
 # passes through such a band are flagged and compared against a looser bound.
 ALPHA_FLAG_REL = 2.0 ** -14
 TERM_FLAG_REL = 2.0 ** -10
+
+
+def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=None, term_band=None,
+                   pos_err=None, z32=None, slack=1e-5, max_branch=12):
+    """Every result one pixel can validly take when an FP32 walk and this FP64 walk may
+    take a discrete decision differently ("several results are correct").
+
+    The walk of eq. 4 decides, per entry, whether alpha >= 1/255 (the compact support of
+    eq. 2) and whether T has fallen below 1e-4 (stop after this entry). When the FP64
+    value of such a decision lies within its band of the threshold (the bands and their
+    growth with ``pos_err`` as in ``composite_pixels``), an FP32 implementation may take
+    either side, and both results are correct. With ``z32``, two consecutive entries that
+    may composite and whose FP32 depths are at most one ulp apart may also be taken in
+    either order.
+
+    Each such alpha decision and order is taken both ways, except alpha decisions whose
+    largest possible effect on the colour, 2 M (1/255)(1 + band) T_max (T_max: the
+    transmittance before the entry with every in-band entry left out, M the largest
+    colour or background magnitude), summed over the decisions left out, stays below
+    ``slack``: those keep the FP64 side, and the change of T they could cause widens the
+    band of every later stop decision. Along each combination the stop decisions are
+    taken both ways inside the band: the walk may stop at every in-band entry up to the
+    first entry whose T is clearly below 1e-4, where it must stop (or run to the end of
+    the list).
+
+    Returns (outcomes, resolved): outcomes is a list of (C [3], T_final, n_last) with
+    n_last the 1-based position of the last composited entry in the (possibly reordered)
+    list; resolved is False, with no outcomes, when more than ``max_branch`` decisions
+    would have to be taken both ways. Pinned by closed forms of eq. 4 for pixels with one
+    in-band alpha, T or order decision, and by agreement with ``composite_pixels`` where
+    nothing is in band.
+    """
+    alpha_band = ALPHA_FLAG_REL if alpha_band is None else alpha_band
+    term_band = TERM_FLAG_REL if term_band is None else term_band
+    seq = np.asarray(seq, dtype=np.int64)
+    bgv = np.asarray(bg, dtype=np.float64)
+    n = seq.shape[0]
+    if n == 0:
+        return [(bgv.copy(), 1.0, 0)], True
+    dx = float(px) - u[seq]
+    dy = float(py) - v[seq]
+    d2 = dx * dx + dy * dy
+    s2 = s[seq] * s[seq]
+    a = np.minimum(ALPHA_MAX, o[seq] * np.exp(-d2 / s2))
+    grow = np.zeros(n)
+    if pos_err is not None:
+        e = np.asarray(pos_err, dtype=np.float64)[seq]
+        grow = (2.0 * (np.abs(dx) + np.abs(dy)) * e + 2.0 * e * e) / s2
+    ok = a >= ALPHA_MIN
+    in_band = np.abs(a * 255.0 - 1.0) <= alpha_band + grow
+    # transmittance before each entry, largest over every branch: in-band entries left out
+    kept = np.where(ok & ~in_band, 1.0 - a, 1.0)
+    T_max = np.concatenate([[1.0], np.cumprod(kept)[:-1]])
+    M = max(1.0, float(np.abs(rgb[:, seq]).max()), float(np.abs(bgv).max()))
+    effect = 2.0 * M * (1.0 / 255.0) * (1.0 + alpha_band + grow) * T_max
+    cand = np.nonzero(in_band)[0]
+    cand = cand[np.argsort(-effect[cand], kind="stable")]
+    left = float(effect[cand].sum())
+    branch = []
+    for k in cand:
+        if left <= slack:
+            break
+        branch.append(int(k))
+        left -= float(effect[k])
+    fixed = np.zeros(n, dtype=bool)
+    fixed[cand] = True
+    fixed[branch] = False          # in-band decisions kept on the FP64 side
+    swaps = []
+    if z32 is not None:
+        zb = np.asarray(z32, dtype=np.float32).view(np.int32).astype(np.int64)[seq]
+        maybe = np.nonzero(ok | in_band)[0]
+        for i0, i1 in zip(maybe[:-1], maybe[1:]):
+            if abs(int(zb[i1]) - int(zb[i0])) <= 1:
+                swaps.append((int(i0), int(i1)))
+    if len(branch) + len(swaps) > max_branch:
+        return [], False
+    ratio_a = a / (1.0 - a)
+    outcomes = []
+    seen = set()
+    nb = len(branch)
+    for bits in range(1 << (nb + len(swaps))):
+        inc = ok.copy()
+        for j, k in enumerate(branch):
+            if (bits >> j) & 1:
+                inc[k] = not ok[k]
+        perm = np.arange(n)
+        for j, (i0, i1) in enumerate(swaps):
+            if (bits >> (nb + j)) & 1:
+                perm[i0], perm[i1] = perm[i1], perm[i0]
+        ap, incp = a[perm], inc[perm]
+        f = np.where(incp, 1.0 - ap, 1.0)
+        T_after = np.cumprod(f)
+        T_before = np.concatenate([[1.0], T_after[:-1]])
+        w = np.where(incp, ap * T_before, 0.0)
+        C_cum = np.cumsum(rgb[:, seq[perm]] * w[None, :], axis=1)
+        # band of each stop decision: rounding band, plus what the alpha uncertainty of the
+        # composited entries and the flips kept on the FP64 side can do to T
+        t_band = (term_band + np.cumsum(np.where(incp, ratio_a[perm] * grow[perm], 0.0))
+                  + np.cumsum(np.where(fixed[perm], ratio_a[perm], 0.0)))
+        stops = []
+        for k in np.nonzero(incp)[0]:
+            r = T_after[k] / T_MIN
+            if abs(r - 1.0) <= t_band[k]:
+                stops.append(int(k))
+            elif r < 1.0:
+                stops.append(int(k))
+                break
+        else:
+            stops.append(-1)       # runs to the end of the list
+        for k in stops:
+            if k < 0:
+                used = np.nonzero(incp)[0]
+                Cf = C_cum[:, -1] + T_after[-1] * bgv
+                out = (Cf, float(T_after[-1]), int(used[-1]) + 1 if used.size else 0)
+            else:
+                out = (C_cum[:, k] + T_after[k] * bgv, float(T_after[k]), k + 1)
+            key = tuple(np.round(out[0], 12)) + (round(out[1], 12), out[2])
+            if key not in seen:
+                seen.add(key)
+                outcomes.append(out)
+    return outcomes, True
+
+
+def footprint_uncertainty(proj: Projected64):
+    """Bounds for comparing against footprints that are FP32 roundings of these: each
+    particle's centre error, 1.5 FP32 ulps of its larger coordinate (an implementation's
+    own rounding within one ulp of this oracle's, which is within half an ulp of the FP64
+    value), and the oracle's FP32 depths. For ``composite_pixels`` / ``pixel_outcomes``."""
+    u32 = np.where(proj.visible, proj.u, 0.0).astype(np.float32)
+    v32 = np.where(proj.visible, proj.v, 0.0).astype(np.float32)
+    ulp = np.maximum(np.spacing(np.abs(u32)), np.spacing(np.abs(v32))).astype(np.float64)
+    z32 = np.where(proj.visible, proj.z, 1.0).astype(np.float32)
+    return 1.5 * ulp, z32
 
 
 def depth_order(proj: Projected64):
@@ -425,7 +591,8 @@ def tile_pixels(tx, ty, width, height):
 
 
 def render64_tiled(u, v, s, o, rgb, bins: Bins, view_id, width, height, bg=(0.0, 0.0, 0.0),
-                   tiles=None, pidx_offset=0, with_flags=False, alpha_band=None, term_band=None):
+                   tiles=None, pidx_offset=0, with_flags=False, alpha_band=None, term_band=None,
+                   pos_err=None, z32=None):
     """Per-tile rendering of one view: each pixel walks its tile's sorted entry list.
 
     u, v, s, o, rgb are per-particle arrays of this view (upcast to FP64); ``bins`` comes
@@ -446,7 +613,7 @@ def render64_tiled(u, v, s, o, rgb, bins: Bins, view_id, width, height, bg=(0.0,
         seq = bins.pidx[a:b].astype(np.int64) - pidx_offset
         X, Y = tile_pixels(tx, ty, width, height)
         C, T, n, tr = composite_pixels(X + 0.5, Y + 0.5, seq, u, v, s, o, rgb, bg, trace=True,
-                                       alpha_band=alpha_band, term_band=term_band)
+                                       alpha_band=alpha_band, term_band=term_band, pos_err=pos_err, z32=z32)
         img[:, Y, X] = C
         Tf[Y, X] = T
         nl[Y, X] = n
@@ -610,19 +777,23 @@ def f32_views(projs, cams):
     return out
 
 
-def render_views(scenes, cams, bg=(0.0, 0.0, 0.0), tiles=None, alpha_band=None, term_band=None):
+def render_views(scenes, cams, bg=(0.0, 0.0, 0.0), tiles=None, alpha_band=None, term_band=None,
+                 rounded=False):
     """Projects, bins and renders each (scene, camera) pair with the tiled oracle.
 
-    Footprints are FP64; binning takes its decisions on their FP32 roundings.
+    Footprints are FP64; binning takes its decisions on their FP32 roundings. With
+    ``rounded`` the flags also cover what FP32 footprints computed elsewhere may change
+    (``footprint_uncertainty``).
     Returns (images list, T_final list, n_last list, flags list, projections, bins)."""
     projs = [project64(sc, cam) for sc, cam in zip(scenes, cams)]
     bins = bin_sort_ref(f32_views(projs, cams))
     imgs, Ts, nls, fls = [], [], [], []
     off = 0
     for vi, (pr, cam) in enumerate(zip(projs, cams)):
+        pe, z32 = footprint_uncertainty(pr) if rounded else (None, None)
         img, Tf, nl, fl = render64_tiled(pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bins, vi, cam.width,
                                          cam.height, bg, tiles=tiles, pidx_offset=off, with_flags=True,
-                                         alpha_band=alpha_band, term_band=term_band)
+                                         alpha_band=alpha_band, term_band=term_band, pos_err=pe, z32=z32)
         imgs.append(img)
         Ts.append(Tf)
         nls.append(nl)

@@ -97,8 +97,13 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4*
         const double u64 = f * px / pz + (double)pv.cx;
         const double v64 = f * py / pz + (double)pv.cy;
         const double s64 = f * (double)sigma / pz;
-        const bool vis = param_ok && pz > (double)pv.near_z && isfinite(u64) && isfinite(v64) && isfinite(s64) &&
-                         s64 > 0.0;
+        // the stored footprint must have a normal FP32 form: centre, 1/s^2 and radius
+        // finite, 1/s^2 at least the smallest normal value (a denormal may be flushed)
+        const float u = (float)u64, v = (float)v64;
+        const float inv_s2 = (float)(1.0 / (s64 * s64));
+        const float r = (float)(s64 * root * (1.0 + 0x1p-10) + 0x1p-6);
+        const bool vis = param_ok && pz > (double)pv.near_z && isfinite(u) && isfinite(v) && isfinite(s64) &&
+                         s64 > 0.0 && isfinite(inv_s2) && inv_s2 >= 0x1p-126f && isfinite(r);
         float4 fp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float4 cr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float z32 = 1.0f;
@@ -117,10 +122,8 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4*
                 for (int k = 1; k < K; ++k) acc = fmaf(coef[3 * k + ch], Y[k], acc);
                 rgb[ch] = fmaxf(acc, 0.0f);
             }
-            const float u = (float)u64, v = (float)v64;
-            const float r = (float)(s64 * root * (1.0 + 0x1p-10) + 0x1p-6);
             z32 = (float)pz;
-            fp = make_float4(u, v, (float)(1.0 / (s64 * s64)), opa);
+            fp = make_float4(u, v, inv_s2, opa);
             cr = make_float4(rgb[0], rgb[1], rgb[2], r);
             int tx0, tx1, ty0, ty1;
             const int TX = (pv.width + kTile - 1) / kTile, TY = (pv.height + kTile - 1) / kTile;

@@ -140,6 +140,20 @@ def test_culling_rules():
     assert bins.tile_count.tolist()[1:] == [0] * 7 and bins.tile_count[0] > 0
 
 
+def test_culling_of_footprints_without_fp32_form():
+    """Catches: a footprint stored with 1/s^2 = inf (0 * inf = NaN in any later product)
+    or a denormal 1/s^2 (flushed to 0 by some FP32 units: a kernel of constant value) or an
+    infinite binning radius. With f = 100 and z = 5, sigma = 1e-22 gives s = 2e-21 px
+    (1/s^2 = 2.5e41 overflows FP32) and sigma = 1e19 gives s = 2e20 px (1/s^2 = 2.5e-41,
+    below the smallest normal FP32 value); both are culled, while sigma = 1e-17
+    (1/s^2 = 2.5e31) and sigma = 1e17 (1/s^2 = 2.5e-37, normal) stay visible."""
+    cam = axis_camera()
+    sc = make_scene([[0, 0, 5]] * 4, [1e-22, 1e19, 1e-17, 1e17], [0.5] * 4, [(1, 1, 1)] * 4)
+    pr = O.project64(sc, cam)
+    assert pr.visible.tolist() == [False, False, True, True]
+    assert (pr.radius[:2] == 0).all()
+
+
 # ---------------------------------------------------------------------------------------
 # eq. 4: compositing
 # ---------------------------------------------------------------------------------------
