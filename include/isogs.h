@@ -37,8 +37,10 @@
  *     failure. Data-dependent failures (entry capacity) cannot be known at launch time;
  *     they are reported through the device-side status word of isogs_bins. Every later
  *     call that takes those bins reads the word on the device and, unless it is ISOGS_OK,
- *     skips its work and leaves its outputs unwritten, so a caller may queue a whole
- *     forward and backward pass before it reads the status.
+ *     skips its work, so a caller may queue a whole forward and backward pass before it
+ *     reads the status: the compositing calls then write NaN colour and transmittance and
+ *     n_last 0 for every pixel (no stale image can pass for a render), the others leave
+ *     their outputs unwritten.
  *   - Per-particle garbage (non-finite values, sigma <= 0, o < 1/255, depth <= near) is
  *     not an error: such a particle is culled (tile count 0).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
@@ -131,8 +133,9 @@ typedef struct {
  *   capacity    number of entries the two entry arrays can hold
  *   count       [1]         written: total entries (even when it exceeds capacity)
  *   status      [1]         written: ISOGS_OK, or ISOGS_ERR_CAPACITY when count > capacity
- *                           (then every later call on these bins leaves its outputs
- *                           untouched; re-run isogs_bin_sort with a larger capacity) */
+ *                           (then every later call on these bins skips its work - the
+ *                           compositing calls write NaN images, see above; re-run
+ *                           isogs_bin_sort with a larger capacity) */
 typedef struct {
     uint64_t* keys;
     uint32_t* pidx;

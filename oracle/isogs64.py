@@ -435,8 +435,10 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
     may composite and whose FP32 depths are at most one ulp apart may also be taken in
     either order.
 
-    Each such alpha decision and order is taken both ways, except alpha decisions whose
-    largest possible effect on the colour, 2 M (1/255)(1 + band) T_max (T_max: the
+    Entries after the first one where even the largest possible T (every in-band entry
+    skipped) is clearly below 1e-4 cannot be composited on any branch and are not taken
+    both ways. Each remaining alpha decision and order is taken both ways, except alpha
+    decisions whose largest possible effect on the colour, 2 M (1/255)(1 + band) T_max (T_max: the
     transmittance before the entry with every in-band entry left out, M the largest
     colour or background magnitude), summed over the decisions left out, stays below
     ``slack``: those keep the FP64 side, and the change of T they could cause widens the
@@ -472,7 +474,16 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
     in_band = np.abs(a * 255.0 - 1.0) <= alpha_band + grow
     # transmittance before each entry, largest over every branch: in-band entries left out
     kept = np.where(ok & ~in_band, 1.0 - a, 1.0)
-    T_max = np.concatenate([[1.0], np.cumprod(kept)[:-1]])
+    T_max_after = np.cumprod(kept)
+    T_max = np.concatenate([[1.0], T_max_after[:-1]])
+    # every branch has stopped by the first entry whose largest T is clearly below 1e-4
+    # (the widest stop band any branch can have): later entries cannot matter
+    ratio = a / (1.0 - a)
+    widest = term_band + float(np.sum(np.where(ok | in_band, ratio * grow, 0.0))) + float(
+        np.sum(np.where(in_band, ratio, 0.0)))
+    below = np.nonzero(T_max_after < T_MIN * (1.0 - widest))[0]
+    if below.size:
+        in_band[below[0] + 1:] = False
     M = max(1.0, float(np.abs(rgb[:, seq]).max()), float(np.abs(bgv).max()))
     effect = 2.0 * M * (1.0 / 255.0) * (1.0 + alpha_band + grow) * T_max
     cand = np.nonzero(in_band)[0]
@@ -491,12 +502,14 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
     if z32 is not None:
         zb = np.asarray(z32, dtype=np.float32).view(np.int32).astype(np.int64)[seq]
         maybe = np.nonzero(ok | in_band)[0]
+        if below.size:
+            maybe = maybe[maybe <= below[0]]
         for i0, i1 in zip(maybe[:-1], maybe[1:]):
             if abs(int(zb[i1]) - int(zb[i0])) <= 1:
                 swaps.append((int(i0), int(i1)))
     if len(branch) + len(swaps) > max_branch:
         return [], False
-    ratio_a = a / (1.0 - a)
+    ratio_a = ratio
     outcomes = []
     seen = set()
     nb = len(branch)
@@ -544,15 +557,18 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
 
 
 def footprint_uncertainty(proj: Projected64):
-    """Bounds for comparing against footprints that are FP32 roundings of these: each
-    particle's centre error, 1.5 FP32 ulps of its larger coordinate (an implementation's
-    own rounding within one ulp of this oracle's, which is within half an ulp of the FP64
-    value), and the oracle's FP32 depths. For ``composite_pixels`` / ``pixel_outcomes``."""
-    u32 = np.where(proj.visible, proj.u, 0.0).astype(np.float32)
-    v32 = np.where(proj.visible, proj.v, 0.0).astype(np.float32)
-    ulp = np.maximum(np.spacing(np.abs(u32)), np.spacing(np.abs(v32))).astype(np.float64)
+    """Bounds for comparing against footprints that are the FP32 roundings of these values
+    (computed in higher precision and rounded once): each particle's centre error, half an
+    FP32 ulp of its larger coordinate (the ulp taken just above the value, so that a
+    rounding up into the next binade is covered), and the oracle's FP32 depths (whose
+    order an implementation shares up to one ulp). For ``composite_pixels`` and
+    ``pixel_outcomes``."""
+    grow = 1.0 + 2.0 ** -10
+    u32 = (np.abs(np.where(proj.visible, proj.u, 0.0)) * grow).astype(np.float32)
+    v32 = (np.abs(np.where(proj.visible, proj.v, 0.0)) * grow).astype(np.float32)
+    ulp = np.maximum(np.spacing(u32), np.spacing(v32)).astype(np.float64)
     z32 = np.where(proj.visible, proj.z, 1.0).astype(np.float32)
-    return 1.5 * ulp, z32
+    return 0.5 * ulp, z32
 
 
 def depth_order(proj: Projected64):

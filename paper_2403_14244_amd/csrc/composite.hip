@@ -178,6 +178,27 @@ __device__ __forceinline__ void write_pixel(const TilePixel& p, const PixelState
     n_last[p.pix_off + pix] = s.last;
 }
 
+// On a capacity overflow the bins hold no valid lists: the tile's pixels get NaN colour
+// and transmittance and n_last 0, so that a result whose status was never read cannot
+// pass for a render.
+__device__ __forceinline__ void write_overflow_tile(const RenderPack& pk, uint32_t logical,
+                                                   float* __restrict__ image, float* __restrict__ T_final,
+                                                   uint32_t* __restrict__ n_last) {
+    int vi, tx, ty;
+    locate_tile(pk, logical, vi, tx, ty);
+    const ViewDesc& vd = pk.v[vi];
+    const int x = tx * kTile + (int)(threadIdx.x & 15u), y = ty * kTile + (int)(threadIdx.x >> 4);
+    if (x >= vd.width || y >= vd.height) return;
+    const size_t hw = (size_t)vd.width * vd.height, pix = (size_t)y * vd.width + x;
+    const float nan = __builtin_nanf("");
+    float* img = image + (size_t)3 * vd.pix_off;
+    img[pix] = nan;
+    img[hw + pix] = nan;
+    img[2 * hw + pix] = nan;
+    T_final[vd.pix_off + pix] = nan;
+    n_last[vd.pix_off + pix] = 0u;
+}
+
 // Composites one whole tile (logical index within the launch). Contains __syncthreads.
 template <bool PIPE, bool PL = PIPE>
 __device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& pk, uint32_t logical,
@@ -206,9 +227,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompa
     float bg_r, float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
     uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
     __shared__ StagedSub sb;
-    if (*status != kStatusOk) return;
-    composite_tile<false>(sb, pk, xcd_swizzle(blockIdx.x, gridDim.x), record, pidx, ranges, bg_r, bg_g, bg_b, image,
-                          T_final, n_last, ckpt);
+    const uint32_t logical = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (*status != kStatusOk) return write_overflow_tile(pk, logical, image, T_final, n_last);
+    composite_tile<false>(sb, pk, logical, record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
 }
 
 // ---- Wide walk for the longest tiles of small launches ------------------------------------
@@ -398,7 +419,7 @@ composite_fwd_ordered_kernel(const RenderPack pk, const float4* __restrict__ rec
                              uint32_t* __restrict__ n_last, float4* __restrict__ ckpt,
                              const uint32_t* __restrict__ order) {
     __shared__ StagedSub sb;
-    if (*status != kStatusOk) return;
+    if (*status != kStatusOk) return write_overflow_tile(pk, order[blockIdx.x], image, T_final, n_last);
     composite_tile<false>(sb, pk, order[blockIdx.x], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last,
                           ckpt);
 }
@@ -409,7 +430,7 @@ __global__ void __launch_bounds__(256) composite_fwd_ordered_pipe_kernel(
     float* __restrict__ image, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
     float4* __restrict__ ckpt, const uint32_t* __restrict__ order) {
     __shared__ StagedSub sb;
-    if (*status != kStatusOk) return;
+    if (*status != kStatusOk) return write_overflow_tile(pk, order[blockIdx.x], image, T_final, n_last);
     composite_tile<true>(sb, pk, order[blockIdx.x], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last,
                          ckpt);
 }
@@ -542,7 +563,11 @@ composite_fwd_ordered_wide_kernel(const RenderPack pk, const float4* __restrict_
                                   uint32_t wide_slots) {
     static_assert(sizeof(StagedQuad) <= sizeof(StagedSub), "one LDS buffer serves both walks");
     __shared__ __align__(16) unsigned char smem[sizeof(StagedSub)];
-    if (*status != kStatusOk) return;
+    if (*status != kStatusOk) {
+        // every tile is one of the remaining ones then (no list is long)
+        if (blockIdx.x >= 4 * wide_slots) write_overflow_tile(pk, order[blockIdx.x - 4 * wide_slots], image, T_final, n_last);
+        return;
+    }
     uint32_t n_wide = 0;
     for (int c = kWideMinLog2 + 1; c < kBuckets; ++c) n_wide += hist[c];
     n_wide = min(n_wide, wide_slots);

@@ -274,7 +274,9 @@ class Rasterizer:
         capacity status needs; on overflow the capacity grows and the pass is redone.
         `check="deferred"`: once a capacity is known, nothing waits: the status is copied
         to pinned host memory behind the launches and `verify(state)` reads it later (the
-        first call, with no capacity yet, still checks synchronously). With
+        first call, with no capacity yet, still checks synchronously); until then, an
+        overflowed pass shows NaN images and transmittance (the library's compositing
+        writes NaN when the bins overflowed). With
         `ordered_fwd` set, compositing dispatches the tiles longest list first
         (same images bitwise; with `wide`, the longest tiles of small launches are
         composited four lanes per pixel, equal up to rounding). `checkpoints` keeps the
@@ -351,6 +353,10 @@ class IsoGSRender(torch.autograd.Function):
         if len({(int(c.width), int(c.height)) for c in cams}) != 1:
             raise ValueError("IsoGSRender: every camera must have the same size")
         images, st = rasterizer.render(scenes, cams, bg, check="deferred", checkpoints=True, wide=True)
+        if not any(ctx.needs_input_grad[:4]):
+            # no backward will read the deferred status: read it now (an overflowed pass
+            # raises here; its images are NaN, never silently stale)
+            rasterizer.verify(st)
         ctx.rasterizer = rasterizer
         ctx.cams = cams
         ctx.bg = bg

@@ -75,6 +75,89 @@ def oracle_render_f32(views, bins, bg=(0.0, 0.0, 0.0), tiles=None, alpha_band=No
     return res
 
 
+def tile_outcomes(u, v, s, o, rgb, bins, view_id, width, bg=(0.0, 0.0, 0.0), pidx_offset=0, alpha_band=None,
+                  term_band=None, pos_err=None, z32=None):
+    """outcomes(y, x) -> (list of valid (C, T, n_last), resolved) of one pixel of a view, over
+    its tile's list in ``bins`` (the oracle's ``pixel_outcomes``)."""
+    TX = (int(width) + 15) // 16
+    base = int(bins.tile_base[view_id])
+
+    def fn(y, x):
+        a, b = bins.ranges[base + (y // 16) * TX + x // 16]
+        seq = bins.pidx[a:b].astype(np.int64) - pidx_offset
+        return O.pixel_outcomes(x + 0.5, y + 0.5, seq, u, v, s, o, rgb, bg, alpha_band=alpha_band,
+                                term_band=term_band, pos_err=pos_err, z32=z32)
+    return fn
+
+
+def f32_footprint_outcomes(views, bins, bg=(0.0, 0.0, 0.0), alpha_band=None, term_band=None):
+    """tile_outcomes for each view of FP32 footprints (as given to the GPU stage tests)."""
+    out, off = [], 0
+    for vi, v in enumerate(views):
+        with np.errstate(divide="ignore"):
+            s = np.where(v["is2"] > 0, 1.0 / np.sqrt(v["is2"].astype(np.float64)), 1.0)
+        out.append(tile_outcomes(v["u"].astype(np.float64), v["v"].astype(np.float64), s, v["o"].astype(np.float64),
+                                 v["rgb"].astype(np.float64), bins, vi, v["width"], bg, off, alpha_band, term_band))
+        off += v["u"].shape[0]
+    return out
+
+
+def projected_outcomes(projs, cams, bins, bg=(0.0, 0.0, 0.0), alpha_band=None, term_band=None):
+    """tile_outcomes for each view of the oracle's FP64 projections, compared against
+    footprints rounded elsewhere (centre errors and FP32 depths from footprint_uncertainty)."""
+    out, off = [], 0
+    for vi, (pr, cam) in enumerate(zip(projs, cams)):
+        pe, z32 = O.footprint_uncertainty(pr)
+        out.append(tile_outcomes(pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bins, vi, cam.width, bg, off, alpha_band,
+                                 term_band, pe, z32))
+        off += pr.u.shape[0]
+    return out
+
+
+def check_image(gimg, gT, oimg, oT, flags, outcomes, tol=1e-4, max_flag_frac=0.01, what="", pixels=None):
+    """Image parity with several correct results near a decision.
+
+    gimg/oimg [3, H, W], gT/oT [H, W] (or, with ``pixels`` = (ys, xs), the same values at
+    those pixels only: [3, P] and [P]). Unflagged pixels: colour and T within ``tol`` of the
+    oracle's walk. Flagged pixels (at most ``max_flag_frac`` of them): within ``tol`` of at
+    least one of the pixel's valid outcomes, every one of them resolved.
+    Returns (max |d| unflagged, flagged count, max |d| to the nearest valid outcome)."""
+    if pixels is None:
+        H, W = flags.shape
+        ys, xs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+        ys, xs = ys.ravel(), xs.ravel()
+        g = gimg.reshape(3, -1).astype(np.float64)
+        gt = gT.reshape(-1).astype(np.float64)
+        o, ot, fl = oimg.reshape(3, -1), oT.reshape(-1), flags.reshape(-1)
+    else:
+        ys, xs = pixels
+        g, gt, o, ot, fl = gimg.astype(np.float64), gT.astype(np.float64), oimg, oT, flags
+    d = np.maximum(np.abs(g - o).max(axis=0), np.abs(gt - ot))
+    assert fl.mean() <= max_flag_frac, (what, "flagged fraction", float(fl.mean()), int(fl.sum()))
+    worst_unflagged = float(d[~fl].max(initial=0.0))
+    assert worst_unflagged <= tol, (what, worst_unflagged)
+    worst_flagged = 0.0
+    for p in np.nonzero(fl)[0]:
+        outs, ok = outcomes(int(ys[p]), int(xs[p]))
+        assert ok, (what, "unresolved pixel", int(ys[p]), int(xs[p]))
+        best = min(max(float(np.abs(g[:, p] - c).max()), abs(float(gt[p]) - t)) for c, t, _ in outs)
+        assert best <= tol, (what, "flagged pixel matches no valid outcome", int(ys[p]), int(xs[p]), best)
+        worst_flagged = max(worst_flagged, best)
+    return worst_unflagged, int(fl.sum()), worst_flagged
+
+
+def grad_check(g_gpu, g_ref, name, rel=1e-3, floor=1e-4):
+    """|GPU - oracle| <= rel |g| + floor max|g| for every element (no exemptions: the
+    comparisons that use it give no weight to pixels where a decision is in band)."""
+    a = np.asarray(g_gpu, dtype=np.float64)
+    b = np.asarray(g_ref, dtype=np.float64)
+    scale = float(np.abs(b).max())
+    err = np.abs(a - b)
+    bad = err > rel * np.abs(b) + floor * scale
+    assert not bad.any(), (name, int(bad.sum()), bad.size, float(err.max()), scale)
+    return float(err.max() / max(scale, 1e-30))
+
+
 def split_flat(flat, cams, per_pixel_channels=3):
     out, off = [], 0
     for c in cams:

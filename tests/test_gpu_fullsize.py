@@ -18,8 +18,18 @@ import pytest
 
 import oracle as O
 import scenegen as S
+from tests import _helpers as H
 
 pytestmark = pytest.mark.gpu
+
+# Flagged-pixel caps of the sampled tiles (each flagged pixel is still held to 1e-4 of one
+# of its valid outcomes). The sample is dominated by the longest lists, whose pixels stop
+# only after compositing dozens of faint entries: the band of the stop decision then
+# carries the alpha uncertainty of all of them (oracle.composite_pixels), and the oracle
+# flags 4-9% of those pixels at 1080p (measured on the CPU: 8.6%, 4.4% and 7.8% for views
+# 0, 3 and 7) and 1.2% of the stress tiles' pixels.
+FLAG_CAP_1080P = 0.12
+FLAG_CAP_STRESS = 0.03
 
 
 def note(msg):
@@ -37,7 +47,9 @@ def P():
 
 def oracle_tile(pr, vw, tx, ty, W, H, bg=(0.0, 0.0, 0.0)):
     """One tile, composited by the oracle: members by the FP32 disk test on the oracle's own
-    FP32 footprints, ordered by (depth bits, index), eq. 4 per pixel in FP64."""
+    FP32 footprints, ordered by (depth bits, index), eq. 4 per pixel in FP64, with the flags
+    widened by what the GPU's own FP32 footprints may change. Returns the list, the
+    pixels, C, T, the flags and the pixels' valid-outcome function."""
     cand = np.nonzero(vw["r"] > 0)[0]
     m = O.tile_member_f32(vw["u"][cand], vw["v"][cand], vw["r"][cand], np.full(cand.shape, tx),
                           np.full(cand.shape, ty), W, H)
@@ -45,28 +57,34 @@ def oracle_tile(pr, vw, tx, ty, W, H, bg=(0.0, 0.0, 0.0)):
     zb = vw["z"][idx].view(np.uint32)
     seq = idx[np.lexsort((idx, zb))]
     X, Y = O.tile_pixels(tx, ty, W, H)
+    pe, z32 = O.footprint_uncertainty(pr)
     C, T, nl, tr = O.composite_pixels(X + 0.5, Y + 0.5, seq, pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bg, trace=True,
-                                      alpha_band=2.0 ** -12, term_band=2.0 ** -8)
-    return seq, X, Y, C, T, tr["near_alpha"] | tr["near_term"]
+                                      pos_err=pe, z32=z32)
+
+    def outcomes(y, x):
+        return O.pixel_outcomes(x + 0.5, y + 0.5, seq, pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bg, pos_err=pe, z32=z32)
+    return seq, X, Y, C, T, tr["near_alpha"] | tr["near_term"], outcomes
 
 
-def check_tiles(img, gpu_pidx, ranges, tile_base, pr, vw, W, H, tiles, p_off, tol=1e-4):
+def check_tiles(img, gT, gpu_pidx, ranges, tile_base, pr, vw, W, H, tiles, p_off, tol=1e-4, max_flag_frac=0.01):
+    """Sampled tiles of one view: lists against the oracle's, every pixel within 1e-4 of the
+    oracle's walk or, where flagged, of one of its valid outcomes; at most `max_flag_frac`
+    of the sampled pixels flagged."""
     TX = (W + 15) // 16
-    worst, flagged, npx, exact_lists = 0.0, 0, 0, 0
+    worst, worst_fl, flagged, npx, exact_lists = 0.0, 0.0, 0, 0, 0
     for tx, ty in tiles:
-        seq, X, Y, C, T, fl = oracle_tile(pr, vw, tx, ty, W, H)
+        seq, X, Y, C, T, fl, outcomes = oracle_tile(pr, vw, tx, ty, W, H)
         a, b = ranges[tile_base + ty * TX + tx]
         glist = gpu_pidx[a:b].astype(np.int64) - p_off
         exact_lists += int(np.array_equal(glist, seq))
-        g = img[:, Y, X].astype(np.float64)
-        d = np.abs(g - C).max(axis=0)
-        assert d[~fl].max(initial=0.0) <= tol, (tx, ty, float(d[~fl].max()))
-        if fl.any():
-            assert d[fl].max() <= 0.01
-        worst = max(worst, float(d[~fl].max(initial=0.0)))
-        flagged += int(fl.sum())
+        # the flagged fraction is bounded over the whole sample below
+        mx, nfl, mf = H.check_image(img[:, Y, X], gT[Y, X], C, T, fl, outcomes, tol=tol, max_flag_frac=1.0,
+                                    what=f"tile ({tx}, {ty})", pixels=(Y, X))
+        worst, worst_fl = max(worst, mx), max(worst_fl, mf)
+        flagged += nfl
         npx += X.shape[0]
-    return worst, flagged, npx, exact_lists
+    assert flagged <= max_flag_frac * npx, (flagged, npx)
+    return worst, flagged, npx, exact_lists, worst_fl
 
 
 def pick_tiles(ranges, tile_base, TX, TY, n_heavy, n_rand, seed):
@@ -89,6 +107,7 @@ def test_mix1m_1080p_batch_sampled_tiles(P):
     ranges = st["bins"].ranges.cpu().numpy().view(np.uint32)
     gpidx = st["bins"].pidx.cpu().numpy().view(np.uint32)
     foot = st["fp"].record.cpu().numpy()
+    gT = st["T"].cpu().numpy().reshape(10, 1080, 1920)
     TX, TY = (1920 + 15) // 16, (1080 + 15) // 16
     for vi in (0, 3, 7):
         pr = O.project64(scene, cams[vi])
@@ -98,10 +117,10 @@ def test_mix1m_1080p_batch_sampled_tiles(P):
         same = (foot[p_off:p_off + scene.n, 0] == vw["u"]) & (foot[p_off:p_off + scene.n, 1] == vw["v"])
         assert same[pr.visible].mean() > 0.999
         tiles, lens = pick_tiles(ranges, vi * TX * TY, TX, TY, 4, 8, vi)
-        worst, flagged, npx, exact = check_tiles(imgs[vi].cpu().numpy(), gpidx, ranges, vi * TX * TY, pr, vw,
-                                                 1920, 1080, tiles, p_off)
+        worst, flagged, npx, exact, wf = check_tiles(imgs[vi].cpu().numpy(), gT[vi], gpidx, ranges, vi * TX * TY, pr,
+                                                     vw, 1920, 1080, tiles, p_off, max_flag_frac=FLAG_CAP_1080P)
         note(f"  view {vi}: {len(tiles)} tiles (max list {lens.max()}), max|d| {worst:.2e}, "
-             f"flagged {flagged}/{npx}, identical lists {exact}/{len(tiles)}")
+             f"flagged {flagged}/{npx} (nearest valid outcome within {wf:.2e}), identical lists {exact}/{len(tiles)}")
         assert exact >= len(tiles) - 1
 
 
@@ -109,52 +128,84 @@ def _crop_camera(cam, x0, y0, w, h):
     return cam.shifted(x0, y0, w, h)
 
 
+def _tile_seq(vw, tx, ty, W, H):
+    cand = np.nonzero(vw["r"] > 0)[0]
+    m = O.tile_member_f32(vw["u"][cand], vw["v"][cand], vw["r"][cand], np.full(cand.shape, tx),
+                          np.full(cand.shape, ty), W, H)
+    idx = cand[m]
+    return idx[np.lexsort((idx, vw["z"][idx].view(np.uint32)))]
+
+
 def test_training_workload_full_size_and_fd_subset(P):
-    """500k Gaussians, 4 views at 1280x720, L1 loss through the autograd function."""
+    """500k Gaussians, 4 views at 1280x720, L1 loss through the autograd function.
+
+    Gradients of 24 sampled particles are recomputed by the oracle over every tile they
+    touch, from its own renders of the jittered scene and of the ground truth (the
+    targets). The L1 loss gives no weight to the pixels of those tiles where the oracle
+    flags a decision (in either render) or where the two renders lie within 1e-3 of each
+    other (where the sign of C - target may differ between the sides); every sampled
+    gradient must then be within 1e-3 |g| + 1e-4 max|g|. The 64-particle 32x32 subset is
+    checked the same way against FP64 central differences."""
     import torch
     note("training workload: full size + 64-Gaussian FD subset")
     gt = S.mixture_scene(500_000, seed=0)
     init = S.jitter_scene(gt, seed=1)
     cams = S.workload_cameras("mix500k_720p_x4")
+    rng = np.random.default_rng(0)
+    projs = [O.project64(init, c) for c in cams]
+    vws = O.f32_views(projs, cams)
+    gprojs = [O.project64(gt, c) for c in cams]
+    gvws = O.f32_views(gprojs, cams)
+    vis_all = np.nonzero(np.all([p.visible for p in projs], axis=0))[0]
+    sample = rng.choice(vis_all, 24, replace=False)
+    W0, H0 = cams[0].width, cams[0].height
+    mask = np.ones((len(cams), 3, H0, W0))
+    per_view = []
+    n_px = n_masked = 0
+    for vi, (pr, vw, gpr, gvw, cam) in enumerate(zip(projs, vws, gprojs, gvws, cams)):
+        tiles = set()
+        for p in sample:
+            gi, ty, tx = O.member_tiles(vw["u"][p:p + 1], vw["v"][p:p + 1], vw["r"][p:p + 1], W0, H0)
+            tiles.update(zip(tx.tolist(), ty.tolist()))
+        pe, z32 = O.footprint_uncertainty(pr)
+        gpe, gz32 = O.footprint_uncertainty(gpr)
+        items = []
+        for tx, ty in sorted(tiles):
+            seq = _tile_seq(vw, tx, ty, W0, H0)
+            X, Y = O.tile_pixels(tx, ty, W0, H0)
+            C, _, _, tr = O.composite_pixels(X + 0.5, Y + 0.5, seq, pr.u, pr.v, pr.s, pr.opacity, pr.rgb,
+                                             (0.0, 0.0, 0.0), trace=True, pos_err=pe, z32=z32)
+            gseq = _tile_seq(gvw, tx, ty, W0, H0)
+            Cg, _, _, gtr = O.composite_pixels(X + 0.5, Y + 0.5, gseq, gpr.u, gpr.v, gpr.s, gpr.opacity, gpr.rgb,
+                                               (0.0, 0.0, 0.0), trace=True, pos_err=gpe, z32=gz32)
+            keep = ~(tr["near_alpha"] | tr["near_term"] | gtr["near_alpha"] | gtr["near_term"])
+            m = keep[None, :] & (np.abs(C - Cg) > 1e-3)
+            mask[vi][:, Y, X] = m
+            n_px += m.size
+            n_masked += int((~m).sum())
+            items.append((seq, X, Y, np.where(m, np.sign(C - Cg), 0.0)))
+        per_view.append(items)
+    assert n_masked <= 0.07 * n_px, (n_masked, n_px)   # 4.6% measured on the CPU
     R = P.Rasterizer()
     targets = torch.stack(R.render([P.GaussianScene.from_host(gt)] * 4, cams)[0])
     params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
               for a in (init.pos, init.scale, init.opacity, init.color)]
+    Mt = torch.from_numpy(mask.astype(np.float32)).cuda()
     img = P.IsoGSRender.apply(*params, 3, cams, (0.0, 0.0, 0.0), R)
-    loss = (img - targets).abs().mean()
+    loss = ((img - targets).abs() * Mt).sum() / img.numel()
     loss.backward()
     torch.cuda.synchronize()
     grads = [p.grad.cpu().numpy().astype(np.float64) for p in params]
     assert np.isfinite(loss.item()) and loss.item() > 0
     assert all(np.isfinite(gg).all() for gg in grads)
-    # sampled particles: the oracle gradient over every tile each one touches, all 4 views
-    C = img.detach().cpu().numpy().astype(np.float64)
-    Tg = targets.cpu().numpy().astype(np.float64)
-    dC = np.sign(C - Tg) / C.size
-    rng = np.random.default_rng(0)
-    projs = [O.project64(init, c) for c in cams]
-    vws = O.f32_views(projs, cams)
-    vis_all = np.nonzero(np.all([p.visible for p in projs], axis=0))[0]
-    sample = rng.choice(vis_all, 24, replace=False)
+    N = float(img.numel())
     ref = {k: np.zeros_like(v) for k, v in zip(("pos", "scale", "opacity", "color"), grads)}
-    for vi, (pr, vw, cam) in enumerate(zip(projs, vws, cams)):
-        W, H = cam.width, cam.height
-        TX, TY = (W + 15) // 16, (H + 15) // 16
+    for vi, (pr, cam) in enumerate(zip(projs, cams)):
         sg = dict(du=np.zeros(init.n), dv=np.zeros(init.n), ds=np.zeros(init.n), do=np.zeros(init.n),
                   drgb=np.zeros((3, init.n)))
-        tiles = set()
-        for p in sample:
-            gi, ty, tx = O.member_tiles(vw["u"][p:p + 1], vw["v"][p:p + 1], vw["r"][p:p + 1], W, H)
-            tiles.update(zip(tx.tolist(), ty.tolist()))
-        for tx, ty in tiles:
-            cand = np.nonzero(vw["r"] > 0)[0]
-            m = O.tile_member_f32(vw["u"][cand], vw["v"][cand], vw["r"][cand], np.full(cand.shape, tx),
-                                  np.full(cand.shape, ty), W, H)
-            idx = cand[m]
-            seq = idx[np.lexsort((idx, vw["z"][idx].view(np.uint32)))]
-            X, Y = O.tile_pixels(tx, ty, W, H)
+        for seq, X, Y, sgn in per_view[vi]:
             res = O.composite_backward_pixels(X + 0.5, Y + 0.5, seq, pr.u, pr.v, pr.s, pr.opacity, pr.rgb,
-                                              (0.0, 0.0, 0.0), dC[vi][:, Y, X])
+                                              (0.0, 0.0, 0.0), sgn / N)
             for gidx in sample:
                 if int(gidx) in res:
                     a = res[int(gidx)]
@@ -169,10 +220,8 @@ def test_training_workload_full_size_and_fd_subset(P):
     for name, gg in zip(("pos", "scale", "opacity", "color"), grads):
         a = gg[..., sample] if gg.ndim == 2 else gg[sample]
         b = ref[name][..., sample] if gg.ndim == 2 else ref[name][sample]
-        scale = np.abs(b).max()
-        bad = np.abs(a - b) > 5e-3 * np.abs(b) + 1e-3 * scale
-        note(f"  {name}: max |d|/max|g| {np.abs(a - b).max() / max(scale, 1e-30):.2e}, outside {int(bad.sum())}/{bad.size}")
-        assert bad.mean() <= 0.05, name
+        r = H.grad_check(a, b, name)
+        note(f"  {name}: max |d|/max|g| {r:.2e} over {b.size} sampled values")
 
     # 64-Gaussian 32x32 subset of view 0: GPU gradients vs FP64 finite differences
     cam0 = cams[0]
@@ -190,22 +239,28 @@ def test_training_workload_full_size_and_fd_subset(P):
     keep = np.argsort(-wsum)[:64]
     sub = S.subset_scene(init, keep)
     tgt = rng.uniform(0, 1, (3, 32, 32))
+    sub64 = S.Scene(sub.pos.astype(np.float64), sub.scale.astype(np.float64), sub.opacity.astype(np.float64),
+                    sub.color.astype(np.float64), 3)
+    C0 = O.render64_untiled(O.project64(sub64, crop), 32, 32)[0]
+    sflags = O.render_views([sub], [crop], rounded=True)[3][0]
+    Msub = (~sflags)[None] & (np.abs(C0 - tgt) > 1e-3)
+    assert Msub.mean() > 0.9
+    W_l1 = Msub * np.sign(C0 - tgt) / C0.size
     sub_params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
                   for a in (sub.pos, sub.scale, sub.opacity, sub.color)]
     out = P.IsoGSRender.apply(*sub_params, 3, [crop], (0.0, 0.0, 0.0), P.Rasterizer())
-    lsub = (out[0] - torch.from_numpy(tgt).float().cuda()).abs().mean()
+    lsub = ((out[0] - torch.from_numpy(tgt).float().cuda()).abs()
+            * torch.from_numpy(Msub.astype(np.float32)).cuda()).sum() / C0.size
     lsub.backward()
     torch.cuda.synchronize()
     g_gpu = {k: p.grad.cpu().numpy().astype(np.float64) for k, p in zip(("pos", "scale", "opacity", "color"), sub_params)}
-    C0 = O.render64_untiled(O.project64(sub, crop), 32, 32)[0]
-    W_l1 = np.sign(C0 - tgt) / C0.size
-    sub64 = S.Scene(sub.pos.astype(np.float64), sub.scale.astype(np.float64), sub.opacity.astype(np.float64),
-                    sub.color.astype(np.float64), 3)
     ref_an = O.scene_grads(sub64, [crop], [W_l1])
     sig0 = O.decision_signature(O.project64(sub64, crop), 32, 32)
-    checked = agree = 0
+    checked = 0
+    worst = 0.0
     for name in ("pos", "scale", "opacity", "color"):
         arr = getattr(sub64, name)
+        scale = np.abs(ref_an[name]).max()
         for idx in list(np.ndindex(arr.shape))[::3]:
             h = 1e-6 * max(1.0, abs(arr[idx]))
             vals, same = [], True
@@ -219,11 +274,12 @@ def test_training_workload_full_size_and_fd_subset(P):
                 continue
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - ref_an[name][idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx)
-            scale = np.abs(ref_an[name]).max()
             checked += 1
-            agree += abs(g_gpu[name][idx] - fd) <= 5e-3 * abs(fd) + 1e-3 * scale
-    note(f"  FD subset: {agree}/{checked} GPU gradients within tolerance of central differences")
-    assert checked > 100 and agree >= 0.97 * checked
+            err = abs(g_gpu[name][idx] - fd)
+            worst = max(worst, err / max(scale, 1e-30))
+            assert err <= 1e-3 * abs(fd) + 1e-4 * scale, (name, idx, g_gpu[name][idx], fd, scale)
+    note(f"  FD subset: all {checked} GPU gradients within 1e-3 |fd| + 1e-4 max|g| (worst {worst:.2e} of max)")
+    assert checked > 100
 
 
 def test_stress_6m_4k_sampled_tiles(P):
@@ -237,14 +293,16 @@ def test_stress_6m_4k_sampled_tiles(P):
     torch.cuda.synchronize()
     ranges = st["bins"].ranges.cpu().numpy().view(np.uint32)
     gpidx = st["bins"].pidx.cpu().numpy().view(np.uint32)
+    gT = st["T"].cpu().numpy().reshape(2, 2160, 3840)
     TX, TY = (3840 + 15) // 16, (2160 + 15) // 16
     pr = O.project64(scene, cams[1])
     vw = O.f32_views([pr], [cams[1]])[0]
     tiles, lens = pick_tiles(ranges, TX * TY, TX, TY, 2, 4, 1)
-    worst, flagged, npx, exact = check_tiles(imgs[1].cpu().numpy(), gpidx, ranges, TX * TY, pr, vw, 3840, 2160,
-                                             tiles, scene.n)
+    worst, flagged, npx, exact, wf = check_tiles(imgs[1].cpu().numpy(), gT[1], gpidx, ranges, TX * TY, pr, vw, 3840,
+                                                 2160, tiles, scene.n, max_flag_frac=FLAG_CAP_STRESS)
     nz = lens[lens > 0]
     note(f"  lists: max {lens.max()}, median {int(np.median(nz))}, p99 {int(np.percentile(nz, 99))}; "
-         f"max|d| {worst:.2e}, flagged {flagged}/{npx}, identical lists {exact}/{len(tiles)}")
+         f"max|d| {worst:.2e}, flagged {flagged}/{npx} (nearest valid outcome within {wf:.2e}), "
+         f"identical lists {exact}/{len(tiles)}")
     assert lens.max() > 100 * np.median(nz)
     assert exact >= len(tiles) - 1

@@ -3,9 +3,15 @@
 Stage tests give both sides identical FP32 inputs produced by the oracle, so:
   * binning and sorting must be bit-exact (integer work);
   * compositing must match to max-abs 1e-4 on every pixel whose FP64 walk does not pass
-    within a hair of a discrete decision (alpha = 1/255, T = 1e-4) - such pixels are
-    counted, must be rare, and are held to the size of one skipped entry instead;
+    within rounding of a discrete decision (alpha = 1/255, T = 1e-4); such pixels are
+    flagged, must be rare, and must match one of the results the oracle gets by taking
+    each in-band decision both ways, to the same 1e-4;
+  * gradients must match to 1e-3 |g| + 1e-4 max|g| for every parameter; the upstream
+    gradient gives no weight to flagged pixels, where the two sides may legitimately
+    walk different entries;
   * projection must match the FP64 values to within FP32 rounding.
+End-to-end tests (GPU footprints from the particle parameters) widen the flag bands by
+what the footprints' own FP32 rounding can change (oracle.footprint_uncertainty).
 """
 import math
 import sys
@@ -51,6 +57,7 @@ def small_mix(n=20_000, seed=3, deg=3):
 PROJECT_CASES = {
     "cube10k_256": lambda: ([S.workload_scene("cube10k_256")], S.workload_cameras("cube10k_256")),
     "mix20k_deg3_321x203": lambda: ([small_mix()], [S.orbit_camera(0.7, 4.0, 321, 203)]),
+    "mix20k_deg1_1920x1080": lambda: ([small_mix(deg=1)], [S.orbit_camera(1.3, 4.0, 1920, 1080)]),
     "batch_mixed": lambda: ([S.workload_scene("cube10k_256"), small_mix(5000, 4, 2)],
                             [S.workload_cameras("cube10k_256")[0], S.orbit_camera(2.0, 3.5, 100, 60)]),
 }
@@ -77,10 +84,15 @@ def test_project_matches_oracle(P, torch_cuda, case):
         vis = pr.visible
         assert ((foot[sl, 3] > 0) == vis).all()
         assert vis.sum() > 0.3 * n
-        # u, v, z: FP64 computation rounded once -> within one FP32 ulp of the oracle
-        for k, arr, ref in (("u", foot[sl, 0], vw["u"]), ("v", foot[sl, 1], vw["v"]), ("z", z[sl], vw["z"])):
-            d = np.abs(arr[vis].astype(np.float64) - ref[vis].astype(np.float64))
-            assert (d <= ulp32(ref[vis])).all(), (k, d.max())
+        # u, v: FP64 computation rounded once -> within half an FP32 ulp of the FP64 value,
+        # the bound the end-to-end comparisons assume (oracle.footprint_uncertainty)
+        pe, _ = O.footprint_uncertainty(pr)
+        for k, arr, ref in (("u", foot[sl, 0], pr.u), ("v", foot[sl, 1], pr.v)):
+            d = np.abs(arr[vis].astype(np.float64) - ref[vis])
+            assert (d <= pe[vis]).all(), (k, float((d / pe[vis]).max()))
+        # z: within one ulp of the oracle's FP32 depth (the order the comparisons allow for)
+        d = np.abs(z[sl][vis].astype(np.float64) - vw["z"][vis].astype(np.float64))
+        assert (d <= ulp32(vw["z"][vis])).all(), ("z", d.max())
         np.testing.assert_allclose(foot[sl, 2][vis], vw["is2"][vis], rtol=2 ** -21)
         np.testing.assert_array_equal(foot[sl, 3][vis], vw["o"][vis])
         np.testing.assert_allclose(colr[sl, :3][vis].T, vw["rgb"][:, vis], atol=1e-5)
@@ -206,24 +218,19 @@ def test_bin_sort_capacity_overflow_reports_and_recovers(P, torch_cuda):
     assert small.n_entries() == ob.keys.shape[0]
     with pytest.raises(P.IsoGSError):
         small.verify()
-    # the render of an overflowed bin set leaves its outputs untouched
-    img, T, nl = R.render_fwd(fp, [views[0]["u"].shape[0]], small, cams)
+    # the render of an overflowed bin set marks every pixel invalid (NaN colour and T,
+    # n_last 0), in both the spatial and the longest-first launches
+    for out in (R.render_fwd(fp, [views[0]["u"].shape[0]], small, cams),
+                R.render_fwd_ordered(fp, [views[0]["u"].shape[0]], small, cams),
+                R.render_fwd_ordered(fp, [views[0]["u"].shape[0]], small, cams, wide=True)):
+        img, T, nl = out
+        assert bool(torch_cuda.isnan(img).all()) and bool(torch_cuda.isnan(T).all()) and int(nl.abs().sum()) == 0
     # growing on demand gives the exact lists
     ok = R.bin_sort(fp, [views[0]["u"].shape[0]], cams, with_keys=True)
     assert ok.capacity >= ob.keys.shape[0]
     np.testing.assert_array_equal(ok.keys[:ok.n_entries()].cpu().numpy().view(np.uint64), ob.keys)
 
 
-def _check_image(gimg, oimg, flags, tol=IMG_TOL, what=""):
-    d = np.abs(gimg.astype(np.float64) - oimg).max(axis=0)
-    unflagged = ~flags
-    assert d[unflagged].max() <= tol, (what, float(d[unflagged].max()))
-    # a flagged pixel differs by at most one entry near the 1/255 threshold or the tail
-    # left after the termination threshold
-    assert flags.mean() < 1e-2, (what, int(flags.sum()))
-    if flags.any():
-        assert d[flags].max() <= 0.01, (what, float(d[flags].max()))
-    return float(d[unflagged].max()), int(flags.sum())
 
 
 RENDER_CASES = ["cube10k_256", "mix_batch_3views", "dense_termination"]
@@ -254,10 +261,10 @@ def test_render_fwd_matches_oracle(P, torch_cuda, case):
     gT = H.split_flat(T.cpu().numpy(), cams, 1)
     gn = H.split_flat(nl.cpu().numpy(), cams, 1)
     ref = H.oracle_render_f32(views, ob, bg)
+    outs = H.f32_footprint_outcomes(views, ob, bg)
     for k, (oimg, oT, onl, ofl) in enumerate(ref):
-        mx, nfl = _check_image(gi[k], oimg, ofl, what=f"{case} view {k}")
-        note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl}")
-        assert np.abs(gT[k][~ofl] - oT[~ofl]).max() <= IMG_TOL
+        mx, nfl, mf = H.check_image(gi[k], gT[k], oimg, oT, ofl, outs[k], what=f"{case} view {k}")
+        note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl} (nearest valid outcome within {mf:.2e})")
         np.testing.assert_array_equal(gn[k][~ofl], onl[~ofl])
     if case == "dense_termination":
         assert (ref[0][1] < O.T_MIN).mean() > 0.2
@@ -272,6 +279,19 @@ def _e2e_scenes(name):
     raise KeyError(name)
 
 
+def check_end_to_end(scenes, cams, imgs, T, bg=(0.0, 0.0, 0.0), what="", max_flag_frac=0.01):
+    """GPU images (list of [3, H, W]) and packed T_final against the oracle's end-to-end
+    render, flags widened by the footprints' FP32 rounding. Returns the oracle's flags."""
+    ores = O.render_views(scenes, cams, bg=bg, rounded=True)
+    outs = H.projected_outcomes(ores[4], cams, ores[5], bg)
+    gT = H.split_flat(T.cpu().numpy(), cams, 1)
+    for k in range(len(cams)):
+        mx, nfl, mf = H.check_image(imgs[k].cpu().numpy(), gT[k], ores[0][k], ores[1][k], ores[3][k], outs[k],
+                                    what=f"{what} view {k}", max_flag_frac=max_flag_frac)
+        note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl} (nearest valid outcome within {mf:.2e})")
+    return ores
+
+
 @pytest.mark.parametrize("case", ["cube10k_256", "mix50k_deg3_480x270"])
 def test_end_to_end_matches_oracle(P, torch_cuda, case):
     """Whole pipeline from particle parameters: GPU FP32 footprints vs the FP64 oracle."""
@@ -281,10 +301,7 @@ def test_end_to_end_matches_oracle(P, torch_cuda, case):
     gsc = [P.GaussianScene.from_host(s) for s in scenes]
     imgs, st = R.render(gsc, cams, bg=(0.0, 0.0, 0.0))
     torch_cuda.cuda.synchronize()
-    ores = O.render_views(scenes, cams, alpha_band=2.0 ** -12, term_band=2.0 ** -8)
-    for k in range(len(cams)):
-        mx, nfl = _check_image(imgs[k].cpu().numpy(), ores[0][k], ores[3][k], what=f"{case} view {k}")
-        note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl}")
+    check_end_to_end(scenes, cams, imgs, st["T"], what=case)
 
 
 def _grad_scene(deg, n=400, seed=12):
@@ -299,25 +316,35 @@ def _grad_scene(deg, n=400, seed=12):
     return sc
 
 
-def _grad_check(g_gpu, g_ref, name, rel=2e-3, floor=2e-4):
-    a = g_gpu.astype(np.float64)
-    b = g_ref.astype(np.float64)
-    scale = np.abs(b).max()
-    bad = np.abs(a - b) > rel * np.abs(b) + floor * scale
-    # a few particles may sit on a discrete decision in FP32 but not FP64
-    assert bad.mean() <= 0.01, (name, int(bad.sum()), bad.size, float(np.abs(a - b).max()), float(scale))
-    return float(np.abs(a - b).max() / max(scale, 1e-30))
+def unflagged_weights(scenes, cams, rng, bg=(0.0, 0.0, 0.0), max_flag_frac=0.01):
+    """Random upstream gradients dL/dC, zero at every pixel the oracle flags end to end
+    (where the GPU may take a decision the other way): gradients are then compared with no
+    exemption. Returns the per-view weights (FP32) and the oracle's render."""
+    ores = O.render_views(scenes, cams, bg=bg, rounded=True)
+    Ws = []
+    for c, fl in zip(cams, ores[3]):
+        assert fl.mean() <= max_flag_frac, float(fl.mean())
+        Ws.append((rng.normal(size=(3, c.height, c.width)) * ~fl[None]).astype(np.float32))
+    return Ws, ores
 
 
-@pytest.mark.parametrize("deg", [0, 3])
+def _grads_vs_oracle(g, ref, what=""):
+    for name in ("pos", "scale", "opacity", "color"):
+        r = H.grad_check(getattr(g, name).cpu().numpy() if not isinstance(g, dict) else g[name], ref[name],
+                         f"{what} {name}")
+        note(f"  {name}: max |d| / max|g| {r:.2e}")
+
+
+@pytest.mark.parametrize("deg", [0, 1, 3])
 def test_render_bwd_matches_oracle(P, torch_cuda, deg):
-    """Backward pass through the ABI vs the FP64 oracle gradient of L = <W, C>."""
+    """Backward pass through the ABI vs the FP64 oracle gradient of L = <W, C>, every
+    parameter within 1e-3 |g| + 1e-4 max|g|."""
     torch = torch_cuda
     sc = _grad_scene(deg)
     cams = [S.look_at_camera((0.3, 0.2, 3.0), width=72, height=56),
             S.look_at_camera((-0.4, 0.1, 2.8), width=64, height=64)]
     rng = np.random.default_rng(deg)
-    Ws = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    Ws, _ = unflagged_weights([sc, sc], cams, rng)
     note(f"render_bwd deg {deg}")
     R = P.Rasterizer()
     gs = P.GaussianScene.from_host(sc)
@@ -326,37 +353,42 @@ def test_render_bwd_matches_oracle(P, torch_cuda, deg):
     g = R.render_bwd([gs, gs], cams, st["fp"], st["bins"], (0.0, 0.0, 0.0), dL, st["T"], st["n_last"])[0]
     torch.cuda.synchronize()
     ref = O.scene_grads(sc, cams, [w.astype(np.float64) for w in Ws])
-    for name in ("pos", "scale", "opacity", "color"):
-        r = _grad_check(getattr(g, name).cpu().numpy(), ref[name], name)
-        note(f"  {name}: max rel-to-max {r:.2e}")
+    _grads_vs_oracle(g, ref, f"deg {deg}")
 
 
 def test_autograd_function_and_determinism(P, torch_cuda):
+    """The autograd function with an L1 loss: bitwise repeatable, and its gradients equal
+    the oracle's L1 gradient. The loss weights out the pixels the oracle flags and those
+    whose colour lies within 1e-3 of the target (where the sign of C - target could differ
+    between the two sides)."""
     torch = torch_cuda
     sc = _grad_scene(2, n=300, seed=5)
     cams = [S.look_at_camera((0.1, 0.1, 3.0), width=48, height=40) for _ in range(2)]
     cams[1] = S.look_at_camera((-0.3, 0.2, 2.9), width=48, height=40)
     note("autograd + determinism")
     R = P.Rasterizer()
-    target = torch.rand(2, 3, 40, 48, device="cuda")
+    t = np.random.default_rng(7).uniform(0, 1, (2, 3, 40, 48))
+    ores = O.render_views([sc, sc], cams, rounded=True)
+    M = np.stack([np.broadcast_to(~ores[3][k][None], (3, 40, 48)) & (np.abs(ores[0][k] - t[k]) > 1e-3)
+                  for k in range(2)])
+    assert M.mean() > 0.95
+    target = torch.from_numpy(t.astype(np.float32)).cuda()
+    mask = torch.from_numpy(M.astype(np.float32)).cuda()
     outs = []
     for rep in range(2):
         params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
                   for a in (sc.pos, sc.scale, sc.opacity, sc.color)]
         img = P.IsoGSRender.apply(*params, sc.sh_degree, cams, (0.0, 0.0, 0.0), R)
-        loss = (img - target).abs().mean()
+        loss = ((img - target).abs() * mask).sum() / img.numel()
         loss.backward()
         outs.append((img.detach().cpu().numpy(), [p.grad.cpu().numpy() for p in params]))
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     for a, b in zip(outs[0][1], outs[1][1]):
         np.testing.assert_array_equal(a, b)
     # the L1 gradient through the oracle
-    t = target.cpu().numpy().astype(np.float64)
-    ores = O.render_views([sc, sc], cams)
-    dCs = [np.sign(ores[0][k] - t[k]) / t.size for k in range(2)]
+    dCs = [M[k] * np.sign(ores[0][k] - t[k]) / t.size for k in range(2)]
     ref = O.scene_grads(sc, cams, dCs)
-    for name, gg in zip(("pos", "scale", "opacity", "color"), outs[0][1]):
-        _grad_check(gg, ref[name], name, rel=5e-3, floor=1e-3)
+    _grads_vs_oracle(dict(zip(("pos", "scale", "opacity", "color"), outs[0][1])), ref, "autograd L1")
 
 
 def test_autograd_output_guarded_against_inplace_changes(P, torch_cuda):
@@ -428,19 +460,16 @@ def test_render_bwd_chunked_long_lists(P, torch_cuda, wide):
     lens = (st["bins"].ranges[:, 1] - st["bins"].ranges[:, 0]).cpu().numpy()
     assert lens.max() > 3 * 1024, int(lens.max())
     assert int(st["n_last"].max()) > 2048           # pixels keep compositing over many chunks
-    W = rng.normal(size=(3, 40, 48)).astype(np.float32)
+    Ws, _ = unflagged_weights([sc], cams, rng)
+    W = Ws[0]
     dL = torch.from_numpy(W.ravel().copy()).cuda()
     args = ([gs], cams, st["fp"], st["bins"], (0.0, 0.0, 0.0), dL, st["T"], st["n_last"])
     g_chunk = R.render_bwd(*args, image=st["image"], ckpt=st["ckpt"])[0]
     g_whole = R.render_bwd(*args)[0]
     torch.cuda.synchronize()
     ref = O.scene_grads(sc, cams, [W.astype(np.float64)])
-    for name in ("pos", "scale", "opacity", "color"):
-        a = getattr(g_chunk, name).cpu().numpy()
-        b = getattr(g_whole, name).cpu().numpy()
-        r = _grad_check(a, ref[name], name)
-        _grad_check(a, b.astype(np.float64), name, rel=1e-4, floor=1e-5)
-        note(f"  {name}: max rel-to-max vs oracle {r:.2e}")
+    _grads_vs_oracle(g_chunk, ref, "chunked")
+    _grads_vs_oracle(g_whole, ref, "whole lists")
 
 
 def test_render_bwd_checkpoints_all_list_lengths(P, torch_cuda):
@@ -465,10 +494,11 @@ def test_render_bwd_checkpoints_all_list_lengths(P, torch_cuda):
     g_chunk = R.render_bwd(*args, image=st["image"], ckpt=st["ckpt"])[0]
     g_whole = R.render_bwd(*args)[0]
     torch.cuda.synchronize()
+    # the same forward decisions on both sides: the walks differ only in how T is
+    # recovered (from a checkpoint at most 256 entries back, or by division along the
+    # whole list), i.e. by rounding
     for name in ("pos", "scale", "opacity", "color"):
-        a = getattr(g_chunk, name).cpu().numpy()
-        b = getattr(g_whole, name).cpu().numpy()
-        _grad_check(a, b.astype(np.float64), name, rel=1e-4, floor=1e-5)
+        H.grad_check(getattr(g_chunk, name).cpu().numpy(), getattr(g_whole, name).cpu().numpy(), name)
 
 
 def test_wide_forward_independent_of_launch(P, torch_cuda):
@@ -525,7 +555,7 @@ def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity, wide):
     c = R.render_fwd_ordered(fp, [g.n], b, cams, (0.2, 0.1, 0.3), wide=wide)
     torch.cuda.synchronize()
     nl_c = c[2].cpu().numpy()
-    ores = O.render_views([sc], cams, bg=(0.2, 0.1, 0.3), alpha_band=2.0 ** -12, term_band=2.0 ** -8)
+    ores = O.render_views([sc], cams, bg=(0.2, 0.1, 0.3), rounded=True)
     if not wide:
         for x, y in zip(a, c):
             assert torch.equal(x, y)
@@ -538,15 +568,131 @@ def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity, wide):
         Ta, Tc = a[1].cpu().numpy(), c[1].cpu().numpy()
         assert np.abs(Ta - Tc)[~fl].max() <= 1e-5
         note(f"  wide vs sequential: max|d| {dimg.max():.2e}, n_last differs at {int((nl_a != nl_c).sum())} px")
-    # thousands of faint entries per pixel: many walks pass within the flag band of the
-    # 1/255 threshold somewhere, so only the unflagged pixels are held to 1e-4
-    d = np.abs(c[0].cpu().numpy().reshape(3, 40, 48).astype(np.float64) - ores[0][0]).max(axis=0)
-    flags = ores[3][0]
-    mx, nfl = float(d[~flags].max()), int(flags.sum())
-    assert mx <= IMG_TOL and (~flags).mean() > 0.5, (mx, nfl)
-    if flags.any():
-        assert d[flags].max() <= 0.01
+    # the denser case stops most pixels after a thousand entries or more, where T carries
+    # the most rounding: up to 6% of its pixels are flagged (4.6% measured), each held to
+    # one of its valid outcomes
+    outs = H.projected_outcomes(ores[4], cams, ores[5], (0.2, 0.1, 0.3))
+    mx, nfl, mf = H.check_image(c[0].cpu().numpy().reshape(3, 40, 48), c[1].cpu().numpy().reshape(40, 48),
+                                ores[0][0], ores[1][0], ores[3][0], outs[0], max_flag_frac=0.06,
+                                what=f"long tiles wide={wide}")
     stopped = c[1].cpu().numpy() < 1e-4
-    note(f"  max|d| {mx:.2e}, flagged {nfl}, n_last max {int(nl_c.max())}, stopped {stopped.mean():.2f}")
+    note(f"  max|d| {mx:.2e}, flagged {nfl} (nearest valid outcome within {mf:.2e}), n_last max {int(nl_c.max())}, "
+         f"stopped {stopped.mean():.2f}")
     if scale > 0.1:
         assert (nl_c[stopped] > 1024).mean() > 0.5   # most stops come after the first 1024 entries
+
+
+def _invalid_scene():
+    """Valid particles in front of the camera, interleaved with every kind of invalid one:
+    non-finite position, scale, opacity or colour; scale <= 0; opacity below 1/255; depth at
+    or behind the near plane; footprints with no normal FP32 form (1/s^2 overflowing or
+    below the smallest normal)."""
+    sc = S.uniform_cube_scene(400, seed=31, log_scale_mean=math.log(0.05), log_scale_std=0.3)
+    sc = S.Scene(sc.pos.copy(), sc.scale.copy(), sc.opacity.copy(), sc.color.copy(), 0)
+    bad = {}
+    kinds = ["pos_nan", "pos_inf", "scale_zero", "scale_neg", "scale_nan", "scale_inf", "opa_low", "opa_nan",
+             "color_nan", "color_inf", "behind_near", "behind_camera", "inv_s2_overflow", "inv_s2_denormal"]
+    for j, k in enumerate(kinds):
+        i = 7 + 13 * j
+        bad[k] = i
+        if k == "pos_nan":
+            sc.pos[0, i] = np.nan
+        elif k == "pos_inf":
+            sc.pos[1, i] = np.inf
+        elif k == "scale_zero":
+            sc.scale[i] = 0.0
+        elif k == "scale_neg":
+            sc.scale[i] = -0.05
+        elif k == "scale_nan":
+            sc.scale[i] = np.nan
+        elif k == "scale_inf":
+            sc.scale[i] = np.inf
+        elif k == "opa_low":
+            sc.opacity[i] = np.float32(1.0 / 256.0)
+        elif k == "opa_nan":
+            sc.opacity[i] = np.nan
+        elif k == "color_nan":
+            sc.color[1, i] = np.nan
+        elif k == "color_inf":
+            sc.color[2, i] = -np.inf
+        elif k == "behind_near":
+            sc.pos[:, i] = (0.0, 0.0, 3.0 - 0.1)     # depth 0.1 <= near 0.2 for the camera at z = 3
+        elif k == "behind_camera":
+            sc.pos[:, i] = (0.0, 0.0, 4.0)
+        elif k == "inv_s2_overflow":
+            sc.scale[i] = np.float32(1e-22)
+        elif k == "inv_s2_denormal":
+            sc.scale[i] = np.float32(1e19)
+    return sc, bad
+
+
+def test_invalid_particles_culled_like_the_oracle(P, torch_cuda):
+    """Per-particle garbage is culled, not an error: each invalid particle gets an all-zero
+    record and no tile, exactly where the oracle finds it invisible, and the image of the
+    remaining ones matches the oracle end to end."""
+    sc, bad = _invalid_scene()
+    cam = S.look_at_camera((0.0, 0.0, 3.0), width=96, height=80)
+    note(f"invalid particles: {sorted(bad)}")
+    R = P.Rasterizer()
+    g = P.GaussianScene.from_host(sc)
+    fp = R.project([g], [cam])
+    torch_cuda.cuda.synchronize()
+    rec = fp.record.cpu().numpy()
+    tc = fp.tile_count.cpu().numpy()
+    pr = O.project64(sc, cam)
+    for k, i in bad.items():
+        assert not pr.visible[i], k
+    assert pr.visible.sum() > 300
+    culled = ~pr.visible
+    assert (rec[culled] == 0).all() and (tc[culled] == 0).all()
+    assert (rec[pr.visible, 3] > 0).all()
+    imgs, st = R.render([g], [cam], bg=(0.1, 0.0, 0.2))
+    torch_cuda.cuda.synchronize()
+    check_end_to_end([sc], [cam], imgs, st["T"], bg=(0.1, 0.0, 0.2), what="invalid particles")
+    # and their gradients are exactly zero
+    rng = np.random.default_rng(1)
+    Ws, _ = unflagged_weights([sc], [cam], rng, bg=(0.1, 0.0, 0.2))
+    dL = torch_cuda.from_numpy(Ws[0].ravel().copy()).cuda()
+    gr = R.render_bwd([g], [cam], st["fp"], st["bins"], (0.1, 0.0, 0.2), dL, st["T"], st["n_last"])[0]
+    torch_cuda.cuda.synchronize()
+    for name in ("pos", "scale", "opacity", "color"):
+        a = getattr(gr, name).cpu().numpy()
+        assert (a[..., culled] == 0).all(), name
+    ref = O.scene_grads(sc, [cam], [Ws[0].astype(np.float64)], bg=(0.1, 0.0, 0.2))
+    vis = pr.visible
+    for name in ("pos", "scale", "opacity", "color"):
+        a = getattr(gr, name).cpu().numpy()
+        H.grad_check(a[..., vis], ref[name][..., vis], name)
+
+
+def test_twenty_views_in_one_call(P, torch_cuda):
+    """A call of 20 views (two launch groups of at most 16 views) of two scenes taken in
+    turn, at two sizes: forward end to end against the oracle for every view, and the
+    backward's per-scene gradients - views of one scene summed across both groups - against
+    the oracle's."""
+    torch = torch_cuda
+    scA = _grad_scene(1, n=500, seed=40)
+    scB = _grad_scene(0, n=300, seed=41)
+    cams = [S.look_at_camera((0.6 * math.sin(0.31 * i), 0.2 * math.cos(0.7 * i), 3.0 + 0.05 * i),
+                             width=56 if i % 3 else 40, height=40 if i % 3 else 48) for i in range(20)]
+    scenes = [scA if i % 2 == 0 else scB for i in range(20)]
+    note("20 views in one call, two scenes")
+    R = P.Rasterizer()
+    gA, gB = P.GaussianScene.from_host(scA), P.GaussianScene.from_host(scB)
+    gsc = [gA if i % 2 == 0 else gB for i in range(20)]
+    imgs, st = R.render(gsc, cams)
+    torch.cuda.synchronize()
+    check_end_to_end(scenes, cams, imgs, st["T"], what="20 views")
+    rng = np.random.default_rng(20)
+    Ws = []
+    for i in range(20):
+        w, _ = unflagged_weights([scenes[i]], [cams[i]], rng)
+        Ws.append(w[0])
+    dL = torch.from_numpy(np.concatenate([w.ravel() for w in Ws])).cuda()
+    grads = R.render_bwd(gsc, cams, st["fp"], st["bins"], (0.0, 0.0, 0.0), dL, st["T"], st["n_last"])
+    torch.cuda.synchronize()
+    assert len(grads) == 2
+    for g, sc, par in ((grads[0], scA, 0), (grads[1], scB, 1)):
+        idx = [i for i in range(20) if i % 2 == par]
+        ref = O.scene_grads(sc, [cams[i] for i in idx], [Ws[i].astype(np.float64) for i in idx])
+        _grads_vs_oracle(g, ref, f"scene {'AB'[par]}")

@@ -177,15 +177,22 @@ def test_position_band_flags_and_branches():
     assert ok and len(outs) == 2
 
 
-def test_footprint_uncertainty_is_one_and_a_half_ulps():
-    """Catches: a bound in the wrong units. 1.5 FP32 ulps of the larger screen coordinate."""
-    sc = uniform_cube_scene(50, seed=1)
-    cam = look_at_camera((0, 0, 3), width=1920, height=1080)
+def test_footprint_uncertainty_bounds_the_fp32_rounding():
+    """Catches: a bound in the wrong units or one that misses the rounding into the next
+    binade. For every visible particle, both FP32 neighbours of each FP64 coordinate (the
+    two values a rounding can give) lie within the bound of it."""
+    sc = uniform_cube_scene(400, seed=1)
+    cam = look_at_camera((0, 0, 2.2), width=1920, height=1080)
     pr = O.project64(sc, cam)
     pe, z32 = O.footprint_uncertainty(pr)
     vis = pr.visible
-    big = np.maximum(np.abs(pr.u[vis]), np.abs(pr.v[vis])).astype(np.float32)
-    np.testing.assert_array_equal(pe[vis], 1.5 * np.spacing(big).astype(np.float64))
+    for c in (pr.u[vis], pr.v[vis]):
+        lo = c.astype(np.float32)
+        lo = np.where(lo.astype(np.float64) > c, np.nextafter(lo, np.float32(-np.inf)), lo)
+        hi = np.nextafter(lo, np.float32(np.inf))
+        near = np.where(np.abs(lo - c) <= np.abs(hi - c), lo, hi).astype(np.float64)
+        assert (np.abs(near - c) <= pe[vis]).all()
+    assert (pe[vis] < 1e-3).all()
     np.testing.assert_array_equal(z32[vis], pr.z[vis].astype(np.float32))
 
 
