@@ -18,7 +18,7 @@ import pytest
 
 import oracle as O
 import scenegen as S
-from tests import _helpers as H
+from tests import _helpers as TH
 
 pytestmark = pytest.mark.gpu
 
@@ -78,7 +78,7 @@ def check_tiles(img, gT, gpu_pidx, ranges, tile_base, pr, vw, W, H, tiles, p_off
         glist = gpu_pidx[a:b].astype(np.int64) - p_off
         exact_lists += int(np.array_equal(glist, seq))
         # the flagged fraction is bounded over the whole sample below
-        mx, nfl, mf = H.check_image(img[:, Y, X], gT[Y, X], C, T, fl, outcomes, tol=tol, max_flag_frac=1.0,
+        mx, nfl, mf = TH.check_image(img[:, Y, X], gT[Y, X], C, T, fl, outcomes, tol=tol, max_flag_frac=1.0,
                                     what=f"tile ({tx}, {ty})", pixels=(Y, X))
         worst, worst_fl = max(worst, mx), max(worst_fl, mf)
         flagged += nfl
@@ -220,7 +220,7 @@ def test_training_workload_full_size_and_fd_subset(P):
     for name, gg in zip(("pos", "scale", "opacity", "color"), grads):
         a = gg[..., sample] if gg.ndim == 2 else gg[sample]
         b = ref[name][..., sample] if gg.ndim == 2 else ref[name][sample]
-        r = H.grad_check(a, b, name)
+        r = TH.grad_check(a, b, name)
         note(f"  {name}: max |d|/max|g| {r:.2e} over {b.size} sampled values")
 
     # 64-Gaussian 32x32 subset of view 0: GPU gradients vs FP64 finite differences

@@ -21,7 +21,7 @@ import pytest
 
 import oracle as O
 import scenegen as S
-from tests import _helpers as H
+from tests import _helpers as TH
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +75,7 @@ def test_project_matches_oracle(P, torch_cuda, case):
     z = fp.depth.cpu().numpy()
     tc = fp.tile_count.cpu().numpy()
     projs = [O.project64(s, c) for s, c in zip(scenes, cams)]
-    views = H.oracle_f32_footprints(projs, cams)
+    views = TH.oracle_f32_footprints(projs, cams)
     ob = O.bin_sort_ref(O.f32_views(projs, cams))
     off = 0
     for pr, vw in zip(projs, views):
@@ -108,26 +108,26 @@ def _bin_case(name):
     if name == "cube10k_256":
         sc, cams = [S.workload_scene("cube10k_256")], S.workload_cameras("cube10k_256")
         projs = [O.project64(s, c) for s, c in zip(sc, cams)]
-        return H.oracle_f32_footprints(projs, cams), cams
+        return TH.oracle_f32_footprints(projs, cams), cams
     if name == "mix_batch_3views":
         sc = small_mix(30_000, 5, 3)
         cams = [S.orbit_camera(0.3 * i, 4.0, w, h) for i, (w, h) in enumerate([(256, 256), (333, 190), (64, 48)])]
         projs = [O.project64(sc, c) for c in cams]
-        return H.oracle_f32_footprints(projs, cams), cams
+        return TH.oracle_f32_footprints(projs, cams), cams
     if name in ("random_ties", "random_wide"):
         ties = name == "random_ties"
         views, cams = [], []
         for k, (w, h) in enumerate([(200, 120), (47, 33)]):
             u, v, z, r = S.random_projected(3000, w, h, seed=20 + k, max_radius=40.0 if not ties else 10.0,
                                             depth_ties=ties)
-            views.append(H.synthetic_f32_footprints(u, v, z, r, w, h, seed=k))
+            views.append(TH.synthetic_f32_footprints(u, v, z, r, w, h, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=w, height=h))
         return views, cams
     if name == "mix200k_1080p":
         sc = S.mixture_scene(200_000, seed=7)
         cams = [S.orbit_camera(1.0, 4.0, 1920, 1080)]
         projs = [O.project64(sc, c) for c in cams]
-        return H.oracle_f32_footprints(projs, cams), cams
+        return TH.oracle_f32_footprints(projs, cams), cams
     if name in ("crowd_wide_depth", "crowd_narrow_depth"):
         # one tile with thousands of entries: the segment sort's multi-chunk path, with an
         # even (wide depths) and an odd (eight tied depth values) number of digit passes
@@ -135,7 +135,7 @@ def _bin_case(name):
         n = 9000 if wide else 5000
         u, v, z, r = S.crowded_projected(n, 96, 64, 40.0, 24.0, 7.5, seed=31 if wide else 32, max_radius=6.0,
                                          depths=None if wide else [2.0 + k / 8 for k in range(8)])
-        return [H.synthetic_f32_footprints(u, v, z, r, 96, 64, seed=3)], [S.look_at_camera((0, 0, 3), width=96, height=64)]
+        return [TH.synthetic_f32_footprints(u, v, z, r, 96, 64, seed=3)], [S.look_at_camera((0, 0, 3), width=96, height=64)]
     if name == "segment_boundaries":
         # footprints inside one tile each, one segment per view at the size limits of the
         # segment sort's paths: 64 (rank by comparison in one wave), 65, 512 (largest
@@ -144,7 +144,7 @@ def _bin_case(name):
         views, cams = [], []
         for k, n in enumerate((64, 65, 512, 513, 1024, 1025, 4096, 4097, 8192, 8193)):
             u, v, z, r = S.crowded_projected(n, 48, 32, 24.0, 8.0, 2.0, seed=40 + k, max_radius=0.5)
-            views.append(H.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
+            views.append(TH.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
         return views, cams
     if name == "segment_ties_bucketed":
@@ -152,7 +152,7 @@ def _bin_case(name):
         # bits holds one value many times, so positions decide the order inside buckets
         u, v, z, r = S.crowded_projected(3000, 48, 32, 24.0, 8.0, 2.0, seed=60, max_radius=0.5,
                                          depths=[1.0 + k / 16 for k in range(64)])
-        return [H.synthetic_f32_footprints(u, v, z, r, 48, 32)], [S.look_at_camera((0, 0, 3), width=48, height=32)]
+        return [TH.synthetic_f32_footprints(u, v, z, r, 48, 32)], [S.look_at_camera((0, 0, 3), width=48, height=32)]
     if name == "all_tiles_long":
         # every tile of a 208x200 view holds more than 512 entries, so each of the 64 lists
         # of long segments receives two or three tiles (tile ids equal modulo 64)
@@ -163,17 +163,17 @@ def _bin_case(name):
         z = rng.uniform(0.5, 9.0, n).astype(np.float32)
         r = rng.uniform(12.0, 20.0, n).astype(np.float32)
         cam = S.look_at_camera((0, 0, 3), width=208, height=200)
-        return [H.synthetic_f32_footprints(u, v, z, r, 208, 200, seed=5)], [cam]
+        return [TH.synthetic_f32_footprints(u, v, z, r, 208, 200, seed=5)], [cam]
     if name == "single_tile":
         u, v, z, r = S.random_projected(400, 16, 16, seed=50, max_radius=6.0, depth_ties=True)
-        return [H.synthetic_f32_footprints(u, v, z, r, 16, 16)], [S.look_at_camera((0, 0, 3), width=16, height=16)]
+        return [TH.synthetic_f32_footprints(u, v, z, r, 16, 16)], [S.look_at_camera((0, 0, 3), width=16, height=16)]
     if name == "empty_and_culled":
         sc = small_mix(500, 6, 0)
         sc.pos[2, :] = 50.0     # all behind a camera looking down -z from z=3 ... culled
         cams = [S.look_at_camera((0, 0, 3), width=40, height=40), S.look_at_camera((0, 0, 3), width=16, height=16)]
         projs = [O.project64(sc, cams[0])]
-        views = H.oracle_f32_footprints(projs, cams[:1])
-        empty = H.synthetic_f32_footprints(*(np.zeros(0, np.float32),) * 4, 16, 16)
+        views = TH.oracle_f32_footprints(projs, cams[:1])
+        empty = TH.synthetic_f32_footprints(*(np.zeros(0, np.float32),) * 4, 16, 16)
         return views + [empty], cams
     raise KeyError(name)
 
@@ -189,7 +189,7 @@ def test_bin_sort_bit_exact(P, torch_cuda, case):
     ob = O.bin_sort_ref(views)
     note(f"bin_sort {case}: {ob.keys.shape[0]} entries")
     R = P.Rasterizer()
-    fp = H.upload_footprints(views, ob)
+    fp = TH.upload_footprints(views, ob)
     npv = [v["u"].shape[0] for v in views]
     bins = R.bin_sort(fp, npv, cams, with_keys=True)
     torch_cuda.cuda.synchronize()
@@ -211,7 +211,7 @@ def test_bin_sort_capacity_overflow_reports_and_recovers(P, torch_cuda):
     ob = O.bin_sort_ref(views)
     note("bin_sort capacity overflow")
     R = P.Rasterizer()
-    fp = H.upload_footprints(views, ob)
+    fp = TH.upload_footprints(views, ob)
     small = R.bin_sort(fp, [views[0]["u"].shape[0]], cams, check=False, capacity=1000)
     torch_cuda.cuda.synchronize()
     assert int(small.status.item()) == P._abi.ISOGS_ERR_CAPACITY
@@ -242,7 +242,7 @@ def _render_case(name):
         sc.opacity[:] = np.float32(0.85)
         cams = [S.look_at_camera((0, 0, 3), width=96, height=80)]
         projs = [O.project64(sc, cams[0])]
-        return H.oracle_f32_footprints(projs, cams), cams
+        return TH.oracle_f32_footprints(projs, cams), cams
     return _bin_case(name)
 
 
@@ -253,17 +253,17 @@ def test_render_fwd_matches_oracle(P, torch_cuda, case):
     bg = (0.1, 0.3, 0.2)
     note(f"render_fwd {case}: {ob.keys.shape[0]} entries")
     R = P.Rasterizer()
-    fp = H.upload_footprints(views, ob)
-    gb = H.upload_bins(ob)
+    fp = TH.upload_footprints(views, ob)
+    gb = TH.upload_bins(ob)
     img, T, nl = R.render_fwd(fp, [v["u"].shape[0] for v in views], gb, cams, bg)
     torch_cuda.cuda.synchronize()
-    gi = H.split_flat(img.cpu().numpy(), cams)
-    gT = H.split_flat(T.cpu().numpy(), cams, 1)
-    gn = H.split_flat(nl.cpu().numpy(), cams, 1)
-    ref = H.oracle_render_f32(views, ob, bg)
-    outs = H.f32_footprint_outcomes(views, ob, bg)
+    gi = TH.split_flat(img.cpu().numpy(), cams)
+    gT = TH.split_flat(T.cpu().numpy(), cams, 1)
+    gn = TH.split_flat(nl.cpu().numpy(), cams, 1)
+    ref = TH.oracle_render_f32(views, ob, bg)
+    outs = TH.f32_footprint_outcomes(views, ob, bg)
     for k, (oimg, oT, onl, ofl) in enumerate(ref):
-        mx, nfl, mf = H.check_image(gi[k], gT[k], oimg, oT, ofl, outs[k], what=f"{case} view {k}")
+        mx, nfl, mf = TH.check_image(gi[k], gT[k], oimg, oT, ofl, outs[k], what=f"{case} view {k}")
         note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl} (nearest valid outcome within {mf:.2e})")
         np.testing.assert_array_equal(gn[k][~ofl], onl[~ofl])
     if case == "dense_termination":
@@ -283,10 +283,10 @@ def check_end_to_end(scenes, cams, imgs, T, bg=(0.0, 0.0, 0.0), what="", max_fla
     """GPU images (list of [3, H, W]) and packed T_final against the oracle's end-to-end
     render, flags widened by the footprints' FP32 rounding. Returns the oracle's flags."""
     ores = O.render_views(scenes, cams, bg=bg, rounded=True)
-    outs = H.projected_outcomes(ores[4], cams, ores[5], bg)
-    gT = H.split_flat(T.cpu().numpy(), cams, 1)
+    outs = TH.projected_outcomes(ores[4], cams, ores[5], bg)
+    gT = TH.split_flat(T.cpu().numpy(), cams, 1)
     for k in range(len(cams)):
-        mx, nfl, mf = H.check_image(imgs[k].cpu().numpy(), gT[k], ores[0][k], ores[1][k], ores[3][k], outs[k],
+        mx, nfl, mf = TH.check_image(imgs[k].cpu().numpy(), gT[k], ores[0][k], ores[1][k], ores[3][k], outs[k],
                                     what=f"{what} view {k}", max_flag_frac=max_flag_frac)
         note(f"  view {k}: max|d| {mx:.2e}, flagged {nfl} (nearest valid outcome within {mf:.2e})")
     return ores
@@ -330,7 +330,7 @@ def unflagged_weights(scenes, cams, rng, bg=(0.0, 0.0, 0.0), max_flag_frac=0.01)
 
 def _grads_vs_oracle(g, ref, what=""):
     for name in ("pos", "scale", "opacity", "color"):
-        r = H.grad_check(getattr(g, name).cpu().numpy() if not isinstance(g, dict) else g[name], ref[name],
+        r = TH.grad_check(getattr(g, name).cpu().numpy() if not isinstance(g, dict) else g[name], ref[name],
                          f"{what} {name}")
         note(f"  {name}: max |d| / max|g| {r:.2e}")
 
@@ -498,7 +498,7 @@ def test_render_bwd_checkpoints_all_list_lengths(P, torch_cuda):
     # recovered (from a checkpoint at most 256 entries back, or by division along the
     # whole list), i.e. by rounding
     for name in ("pos", "scale", "opacity", "color"):
-        H.grad_check(getattr(g_chunk, name).cpu().numpy(), getattr(g_whole, name).cpu().numpy(), name)
+        TH.grad_check(getattr(g_chunk, name).cpu().numpy(), getattr(g_whole, name).cpu().numpy(), name)
 
 
 def test_wide_forward_independent_of_launch(P, torch_cuda):
@@ -571,8 +571,8 @@ def test_ordered_forward_long_tiles(P, torch_cuda, scale, opacity, wide):
     # the denser case stops most pixels after a thousand entries or more, where T carries
     # the most rounding: up to 6% of its pixels are flagged (4.6% measured), each held to
     # one of its valid outcomes
-    outs = H.projected_outcomes(ores[4], cams, ores[5], (0.2, 0.1, 0.3))
-    mx, nfl, mf = H.check_image(c[0].cpu().numpy().reshape(3, 40, 48), c[1].cpu().numpy().reshape(40, 48),
+    outs = TH.projected_outcomes(ores[4], cams, ores[5], (0.2, 0.1, 0.3))
+    mx, nfl, mf = TH.check_image(c[0].cpu().numpy().reshape(3, 40, 48), c[1].cpu().numpy().reshape(40, 48),
                                 ores[0][0], ores[1][0], ores[3][0], outs[0], max_flag_frac=0.06,
                                 what=f"long tiles wide={wide}")
     stopped = c[1].cpu().numpy() < 1e-4
@@ -662,7 +662,7 @@ def test_invalid_particles_culled_like_the_oracle(P, torch_cuda):
     vis = pr.visible
     for name in ("pos", "scale", "opacity", "color"):
         a = getattr(gr, name).cpu().numpy()
-        H.grad_check(a[..., vis], ref[name][..., vis], name)
+        TH.grad_check(a[..., vis], ref[name][..., vis], name)
 
 
 def test_twenty_views_in_one_call(P, torch_cuda):

@@ -84,10 +84,10 @@ def test_served_images_equal_alone_and_in_mix(P):
         assert torch.equal(alone[0], r.result), r.rid
     # and a few against the oracle (end to end, FP64; near a decision, one of the valid
     # results)
-    from tests import _helpers as H
+    from tests import _helpers as TH
     for r in reqs[:3]:
         ores = O.render_views([host[r.scene]], [r.cam], rounded=True)
-        outs = H.projected_outcomes(ores[4], [r.cam], ores[5])
+        outs = TH.projected_outcomes(ores[4], [r.cam], ores[5])
         img = r.result.cpu().numpy()
         ok_px = ~ores[3][0]
         d = np.abs(img.astype(np.float64) - ores[0][0]).max(axis=0)
