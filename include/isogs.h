@@ -166,6 +166,27 @@ int isogs_bin_sort(const isogs_projected* proj, const int32_t* n_per_view,
                    const isogs_camera* cams, int32_t n_views, const isogs_bins* bins,
                    void* ws, size_t* ws_bytes, void* stream);
 
+/* isogs_bin_sort for callers that cannot allocate device memory or hand over a workspace:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid allocation. The
+ * same kernels and outputs as isogs_bin_sort (bit for bit), with the scratch taken from a
+ * static device array of ISOGS_STATIC_SCRATCH_BYTES that the library holds on each GPU it
+ * runs on until the process ends (its address is looked up once per device, on the first
+ * call with that device current). The caller still owns and passes proj and bins.
+ *   - Limit: the call needs the scratch isogs_bin_sort reports for the same arguments
+ *     (about 20 bytes per entry of capacity plus 2 KB per 4096 entries and 4 bytes per
+ *     tile); above ISOGS_STATIC_SCRATCH_BYTES it returns ISOGS_ERR_WORKSPACE and launches
+ *     nothing (128 MiB: about 6M entries, three 1080p views of a 1M-particle scene).
+ *   - No hipMalloc, hipFree or allocating library call is made; the bookkeeping that must
+ *     start at zero is cleared by a kernel on `stream` at every call.
+ *   - Every call on one GPU shares that GPU's array, which keeps the last call's contents:
+ *     calls that overlap on one GPU (other streams, other host threads) race and must be
+ *     serialised by the caller.
+ * Errors: as isogs_bin_sort, plus ISOGS_ERR_DEVICE if the array's address cannot be found. */
+#define ISOGS_STATIC_SCRATCH_BYTES (128u << 20)
+int isogs_bin_sort_static(const isogs_projected* proj, const int32_t* n_per_view,
+                          const isogs_camera* cams, int32_t n_views, const isogs_bins* bins,
+                          void* stream);
+
 /* Compositing checkpoints, for isogs_render_bwd on long tile lists (at least
  * 2 * ISOGS_CKPT_CHUNK entries): at list positions k * ISOGS_CKPT_CHUNK (k >= 1) of such a
  * tile, each pixel's state before that entry - float4 {T, accumulated r, g, b} - is stored

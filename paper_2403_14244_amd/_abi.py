@@ -18,8 +18,9 @@ ISOGS_ERR_WORKSPACE = -3
 ISOGS_ERR_DEVICE = -4
 
 ISOGS_FWD_WIDE = 1
+ISOGS_STATIC_SCRATCH_BYTES = 128 << 20
 
-EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
+EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_render_fwd", "isogs_render_fwd_ordered",
             "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_field2d_bin", "isogs_field2d_fwd",
             "isogs_field2d_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune", "isogs_field2d_split",
             "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_last_error",
@@ -76,6 +77,8 @@ def lib():
         L.isogs_project.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), vp]
         L.isogs_bin_sort.argtypes = [P(Projected), P(ctypes.c_int32), P(Camera), ctypes.c_int32, P(Bins), vp,
                                      P(ctypes.c_size_t), vp]
+        L.isogs_bin_sort_static.argtypes = [P(Projected), P(ctypes.c_int32), P(Camera), ctypes.c_int32, P(Bins),
+                                            vp]
         L.isogs_render_fwd.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera), ctypes.c_int32,
                                        P(ctypes.c_float), vp, vp, vp, vp, vp]
         L.isogs_render_fwd_ordered.argtypes = [P(Projected), P(ctypes.c_int32), P(Bins), P(Camera),
@@ -102,7 +105,7 @@ def lib():
                                      vp, vp]
         L.isogs_checkpoint_bytes.argtypes = [ctypes.c_uint64]
         L.isogs_checkpoint_bytes.restype = ctypes.c_size_t
-        for name in ("isogs_project", "isogs_bin_sort", "isogs_render_fwd", "isogs_render_fwd_ordered",
+        for name in ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_render_fwd", "isogs_render_fwd_ordered",
                      "isogs_render_bwd", "isogs_field2d_bin", "isogs_field2d_fwd", "isogs_field2d_bwd",
                      "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune",
                      "isogs_field2d_split", "isogs_l1_fwd", "isogs_l1_bwd"):

@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation, workspace sizing and dispatch.
 #include <math.h>
+#include <mutex>
 #include <stdarg.h>
 #include <stdio.h>
 
@@ -438,6 +439,76 @@ int isogs_l1_bwd(const float* image, const float* target, int64_t n, const float
     if (!dL_dloss || (n > 0 && (!image || !target || !dL_dimage))) return fail(ISOGS_ERR_INVALID, "buffer is NULL");
     if (isogs::launch_l1_bwd(image, target, (uint64_t)n, dL_dloss, dL_dimage, (hipStream_t)stream))
         return device_fail("isogs_l1_bwd");
+    return ISOGS_OK;
+}
+
+}  // extern "C"
+
+// ---- Bin sort without a caller workspace ---------------------------------------------------
+// The scratch of isogs_bin_sort_static lives in a file-scope device array, one copy per GPU,
+// held until the process ends. Host code never passes the array's name to a kernel (on the
+// host it only stands in for the symbol): its device address is looked up once per device
+// with hipGetSymbolAddress and cached.
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)ISOGS_STATIC_SCRATCH_BYTES;
+static_assert(kStaticScratchBytes % 256 == 0, "the scratch holds 256-byte aligned sections");
+
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (the current device's), or NULL with the error set.
+void* device_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        fail(ISOGS_ERR_DEVICE, "isogs_bin_sort_static: no current device (or device index >= %d)", kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(ISOGS_ERR_DEVICE, "isogs_bin_sort_static: hipGetSymbolAddress failed on device %d: %s", dev,
+                 hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int isogs_bin_sort_static(const isogs_projected* proj, const int32_t* n_per_view, const isogs_camera* cams,
+                          int32_t n_views, const isogs_bins* bins, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    uint64_t n, tiles;
+    if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    const isogs::BinSortPlan plan = isogs::plan_bin_sort(n_per_view, cams, n_views, bins->capacity);
+    if (plan.bytes > kStaticScratchBytes)
+        return fail(ISOGS_ERR_WORKSPACE,
+                    "isogs_bin_sort_static: %zu bytes of scratch needed for capacity %llu and %llu tiles, "
+                    "the static scratch holds %zu",
+                    plan.bytes, (unsigned long long)bins->capacity, (unsigned long long)tiles, kStaticScratchBytes);
+    if ((rc = check_projected(proj, n))) return rc;
+    if ((rc = check_bins(bins, n, tiles))) return rc;
+    void* ws = device_scratch();
+    if (!ws) return ISOGS_ERR_DEVICE;
+    if (isogs::launch_bin_sort(plan, proj, n_per_view, cams, n_views, bins, ws, (hipStream_t)stream))
+        return device_fail("isogs_bin_sort_static");
     return ISOGS_OK;
 }
 

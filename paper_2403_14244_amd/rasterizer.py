@@ -190,6 +190,16 @@ class Rasterizer:
                 self.capacity = cap
         raise A.IsoGSError(A.ISOGS_ERR_CAPACITY, "bin_sort capacity still too small after growing")
 
+    def bin_sort_static(self, fp: Footprints, n_per_view, cams, capacity, with_keys=False) -> TileBins:
+        """bin_sort through isogs_bin_sort_static: the library's scratch is its static
+        per-GPU array, so the only allocations are the output bins made here (a caller
+        that cannot allocate passes bins it made beforehand to the C call). No capacity
+        retry: the status is left on the device for the caller."""
+        bins = _alloc_bins(capacity, int(sum(n_per_view)), sum(tiles_of(c) for c in cams), self.device, with_keys)
+        A.check(A.lib().isogs_bin_sort_static(ctypes.byref(fp.abi()), A.int_array(n_per_view), A.camera_array(cams),
+                                              len(cams), ctypes.byref(bins.abi()), _stream()))
+        return bins
+
     def checkpoint_buffer(self, bins: TileBins) -> torch.Tensor:
         """Device buffer for the compositing checkpoints of these bins (see render_bwd)."""
         nbytes = int(A.lib().isogs_checkpoint_bytes(bins.capacity))

@@ -267,3 +267,35 @@ def test_l1_invalid_arguments_and_workspace_query():
     assert need.value >= 8 * 3
     assert L.isogs_l1_fwd(None, None, -1, None, None, ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
     assert L.isogs_l1_bwd(None, None, 5, None, None, None) == A.ISOGS_ERR_INVALID
+
+
+def test_static_bin_sort_rejects_oversize_and_bad_arguments_without_a_device():
+    """isogs_bin_sort_static checks its arguments and the size of its static scratch before
+    it looks up the array on a device."""
+    A = _abi()
+    L = A.lib()
+    cams = A.camera_array([_cam(64, 48)])
+    npv = A.int_array([100])
+    bins = A.Bins()
+    proj = A.Projected()
+    # the scratch a workspace call would need for this capacity exceeds the static array
+    bins.capacity = (A.ISOGS_STATIC_SCRATCH_BYTES // 20) + 1
+    need = ctypes.c_size_t(0)
+    assert L.isogs_bin_sort(ctypes.byref(proj), npv, cams, 1, ctypes.byref(bins), None, ctypes.byref(need),
+                            None) == A.ISOGS_OK
+    assert need.value > A.ISOGS_STATIC_SCRATCH_BYTES
+    assert L.isogs_bin_sort_static(ctypes.byref(proj), npv, cams, 1, ctypes.byref(bins), None) == A.ISOGS_ERR_WORKSPACE
+    assert b"static scratch" in L.isogs_last_error()
+    assert L.isogs_bin_sort_static(ctypes.byref(proj), npv, cams, 0, ctypes.byref(bins), None) == A.ISOGS_ERR_INVALID
+    assert L.isogs_bin_sort_static(ctypes.byref(proj), None, cams, 1, ctypes.byref(bins), None) == A.ISOGS_ERR_INVALID
+    assert L.isogs_bin_sort_static(ctypes.byref(proj), npv, cams, 1, None, None) == A.ISOGS_ERR_INVALID
+    # within the limit, NULL buffers are still rejected before any device call
+    bins.capacity = 1000
+    assert L.isogs_bin_sort_static(ctypes.byref(proj), npv, cams, 1, ctypes.byref(bins), None) == A.ISOGS_ERR_INVALID
+
+
+def test_header_states_the_static_scratch_size():
+    A = _abi()
+    text = open(HEADER).read()
+    m = re.search(r"#define ISOGS_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and (int(m.group(1)) << int(m.group(2))) == A.ISOGS_STATIC_SCRATCH_BYTES
