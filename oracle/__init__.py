@@ -9,3 +9,4 @@ from .isogs64 import (ALPHA_MIN, ALPHA_MAX, T_MIN, TILE, RADIUS_GROW, RADIUS_PAD
 from . import field2d64  # noqa: F401  (2D kernel-sum representation of Section 3)
 from . import ssim64  # noqa: F401  (SSIM term of the loss)
 from . import tree2d64  # noqa: F401  (quadtree initialisation, prune and split of 2D particles)
+from . import aniso64  # noqa: F401  (anisotropic variant: eq. 5-7)

@@ -454,13 +454,10 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
     in-band alpha, T or order decision, and by agreement with ``composite_pixels`` where
     nothing is in band.
     """
-    alpha_band = ALPHA_FLAG_REL if alpha_band is None else alpha_band
-    term_band = TERM_FLAG_REL if term_band is None else term_band
     seq = np.asarray(seq, dtype=np.int64)
-    bgv = np.asarray(bg, dtype=np.float64)
     n = seq.shape[0]
     if n == 0:
-        return [(bgv.copy(), 1.0, 0)], True
+        return [(np.asarray(bg, dtype=np.float64).copy(), 1.0, 0)], True
     dx = float(px) - u[seq]
     dy = float(py) - v[seq]
     d2 = dx * dx + dy * dy
@@ -470,6 +467,24 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
     if pos_err is not None:
         e = np.asarray(pos_err, dtype=np.float64)[seq]
         grow = (2.0 * (np.abs(dx) + np.abs(dy)) * e + 2.0 * e * e) / s2
+    zs = None if z32 is None else np.asarray(z32, dtype=np.float32)[seq]
+    return walk_outcomes(a, grow, rgb[:, seq], bg, alpha_band, term_band, zs, slack, max_branch)
+
+
+def walk_outcomes(a, grow, rgb_seq, bg=(0.0, 0.0, 0.0), alpha_band=None, term_band=None, z32_seq=None, slack=1e-5,
+                  max_branch=12):
+    """The valid results of one pixel's walk (see ``pixel_outcomes``) from the alpha of each
+    entry of its list in list order (clamped, before the 1/255 test), the growth of each
+    entry's alpha band, the entries' colours [3, n] and, optionally, their FP32 depths.
+    Shared by the kernels whose alpha is computed differently (isotropic, anisotropic)."""
+    alpha_band = ALPHA_FLAG_REL if alpha_band is None else alpha_band
+    term_band = TERM_FLAG_REL if term_band is None else term_band
+    bgv = np.asarray(bg, dtype=np.float64)
+    a = np.asarray(a, dtype=np.float64)
+    grow = np.asarray(grow, dtype=np.float64)
+    n = a.shape[0]
+    if n == 0:
+        return [(bgv.copy(), 1.0, 0)], True
     ok = a >= ALPHA_MIN
     in_band = np.abs(a * 255.0 - 1.0) <= alpha_band + grow
     # transmittance before each entry, largest over every branch: in-band entries left out
@@ -484,7 +499,7 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
     below = np.nonzero(T_max_after < T_MIN * (1.0 - widest))[0]
     if below.size:
         in_band[below[0] + 1:] = False
-    M = max(1.0, float(np.abs(rgb[:, seq]).max()), float(np.abs(bgv).max()))
+    M = max(1.0, float(np.abs(rgb_seq).max()), float(np.abs(bgv).max()))
     effect = 2.0 * M * (1.0 / 255.0) * (1.0 + alpha_band + grow) * T_max
     cand = np.nonzero(in_band)[0]
     cand = cand[np.argsort(-effect[cand], kind="stable")]
@@ -499,8 +514,8 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
     fixed[cand] = True
     fixed[branch] = False          # in-band decisions kept on the FP64 side
     swaps = []
-    if z32 is not None:
-        zb = np.asarray(z32, dtype=np.float32).view(np.int32).astype(np.int64)[seq]
+    if z32_seq is not None:
+        zb = np.asarray(z32_seq, dtype=np.float32).view(np.int32).astype(np.int64)
         maybe = np.nonzero(ok | in_band)[0]
         if below.size:
             maybe = maybe[maybe <= below[0]]
@@ -527,7 +542,7 @@ def pixel_outcomes(px, py, seq, u, v, s, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=
         T_after = np.cumprod(f)
         T_before = np.concatenate([[1.0], T_after[:-1]])
         w = np.where(incp, ap * T_before, 0.0)
-        C_cum = np.cumsum(rgb[:, seq[perm]] * w[None, :], axis=1)
+        C_cum = np.cumsum(rgb_seq[:, perm] * w[None, :], axis=1)
         # band of each stop decision: rounding band, plus what the alpha uncertainty of the
         # composited entries and the flips kept on the FP64 side can do to T
         t_band = (term_band + np.cumsum(np.where(incp, ratio_a[perm] * grow[perm], 0.0))

@@ -26,7 +26,7 @@ __all__ = [
     "Scene", "Camera", "look_at_camera", "orbit_camera", "uniform_cube_scene",
     "mixture_scene", "stress_scene", "jitter_scene", "subset_scene",
     "WORKLOADS", "workload_scene", "workload_cameras", "random_projected",
-    "field2d_target", "field2d_init",
+    "field2d_target", "field2d_init", "AnisoScene", "aniso_from_iso", "aniso_mixture_scene",
 ]
 
 
@@ -184,6 +184,51 @@ def stress_scene(n=6_000_000, seed=5, sh_degree=3) -> Scene:
     opacity = _sigmoid(rng.normal(0.0, 1.0, size=n))
     color = _sh_coeffs(rng, n, sh_degree)
     return _pack(pos, log_scale, opacity, color, sh_degree)
+
+
+@dataclass
+class AnisoScene:
+    """Particles with a full covariance (the anisotropic variant): pos [3, N], rot [4, N]
+    quaternions (w, x, y, z; not necessarily unit), scale [3, N] linear per-axis scales,
+    opacity [N], color [3K, N] as in Scene. FP32."""
+    pos: np.ndarray
+    rot: np.ndarray
+    scale: np.ndarray
+    opacity: np.ndarray
+    color: np.ndarray
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.opacity.shape[0])
+
+
+def aniso_from_iso(scene: Scene) -> AnisoScene:
+    """The same particles as anisotropic ones: identity rotation, the scale on all three
+    axes (so the covariance is sigma^2 I)."""
+    n = scene.n
+    rot = np.zeros((4, n), dtype=np.float32)
+    rot[0] = 1.0
+    return AnisoScene(pos=scene.pos.copy(), rot=rot, scale=np.ascontiguousarray(np.repeat(scene.scale[None], 3, 0)),
+                      opacity=scene.opacity.copy(), color=scene.color.copy(), sh_degree=scene.sh_degree)
+
+
+def aniso_mixture_scene(n=1_000_000, seed=0, log_scale_mean=math.log(0.005), log_scale_std=0.5,
+                        axis_log_std=0.5, sh_degree=3) -> AnisoScene:
+    """The mixture layout of mixture_scene with a random orientation per particle
+    (quaternion of four N(0, 1) draws) and per-axis scales exp(b + N(0, axis_log_std)) around
+    a per-particle log-scale b ~ N(log_scale_mean, log_scale_std). Draw order: positions,
+    b, opacity, colour, quaternions, per-axis offsets."""
+    rng = np.random.default_rng(seed)
+    pos = _mixture_points(rng, n)
+    b = rng.normal(log_scale_mean, log_scale_std, size=n)
+    opacity = _sigmoid(rng.normal(0.0, 1.0, size=n))
+    color = _sh_coeffs(rng, n, sh_degree)
+    q = rng.normal(0.0, 1.0, size=(4, n))
+    axis = rng.normal(0.0, axis_log_std, size=(3, n))
+    return AnisoScene(pos=np.ascontiguousarray(pos.T.astype(np.float32)), rot=q.astype(np.float32),
+                      scale=np.exp(b[None, :] + axis).astype(np.float32), opacity=opacity.astype(np.float32),
+                      color=np.ascontiguousarray(color.astype(np.float32)), sh_degree=int(sh_degree))
 
 
 def jitter_scene(scene: Scene, seed=1, pos_std=0.01, log_scale_std=0.2) -> Scene:
