@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--train-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of the request trace of the serving measurement (0 skips it)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -243,6 +243,84 @@ def stress_workload(dev, iters=3):
             "tile_lists": lists}
 
 
+def aniso_workload(dev, scene_iso, cams, batch_views=10, fwd_views=20, train_iters=10):
+    """The paper's comparison of isotropic and anisotropic kernels (Table 1, Table 2, the
+    "about 100X" of the abstract and Section 3) on this library's own kernels, both
+    families built from the same walks: the isotropic scene of the benchmark, the same
+    particles as anisotropic ones (identity rotation, sigma on every axis: each particle's
+    full sigma^2 J J^T footprint) and an anisotropic scene of the same layout with random
+    orientations and per-axis scales. Per variant: forward Mpix/s over `fwd_views` orbit
+    views at 1080p in calls of `batch_views` (one stream), entries per view, and fwd+bwd
+    iterations/s at one 1080p view with the L1 loss through the autograd function."""
+    import torch
+    import scenegen as S
+    import paper_2403_14244_amd as P
+    n = scene_iso.n
+    variants = {"iso": scene_iso, "aniso_same_particles": S.aniso_from_iso(scene_iso),
+                "aniso_random": S.aniso_mixture_scene(n, seed=0)}
+    views = cams[:fwd_views]
+    batches = [views[i:i + batch_views] for i in range(0, len(views), batch_views)]
+    W, H = int(views[0].width), int(views[0].height)
+    target = torch.rand(1, 3, H, W, device=dev)
+    out = {}
+    for name, sc in variants.items():
+        an = name != "iso"
+        R = (P.AnisoRasterizer if an else P.Rasterizer)(dev, headroom=1.1)
+        g = (P.AnisoGaussianScene if an else P.GaussianScene).from_host(sc, dev)
+
+        def fwd(check):
+            ents = []
+            for bc in batches:
+                fp = R.project([g] * len(bc), bc)
+                bins = R.bin_sort(fp, [g.n] * len(bc), bc, check=check)
+                R.render_fwd_ordered(fp, [g.n] * len(bc), bins, bc)
+                ents.append(bins)
+            return ents
+
+        fwd(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            bins_all = fwd(False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        for b in bins_all:
+            b.verify()
+        entries = sum(b.n_entries() for b in bins_all) / len(views)
+        params = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).requires_grad_(True)
+                  for a in ((sc.pos, sc.rot, sc.scale, sc.opacity, sc.color) if an else
+                            (sc.pos, sc.scale, sc.opacity, sc.color))]
+        fn = P.AnisoGSRender if an else P.IsoGSRender
+        Rt = (P.AnisoRasterizer if an else P.Rasterizer)(dev, headroom=1.1)
+
+        def step():
+            for q in params:
+                q.grad = None
+            img = fn.apply(*params, sc.sh_degree, views[:1], (0.0, 0.0, 0.0), Rt)
+            P.l1_loss(img, target).backward()
+
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(train_iters):
+            step()
+        torch.cuda.synchronize()
+        it = train_iters / (time.perf_counter() - t0)
+        out[name] = {"fwd_mpix_per_s": round(len(views) * W * H / dt / 1e6, 1),
+                     "fwd_ms_per_view": round(dt * 1e3 / len(views), 3), "entries_per_view": round(entries),
+                     "fwd_bwd_iters_per_s": round(it, 1)}
+        del R, Rt, params, g, bins_all
+        torch.cuda.empty_cache()
+    iso = out["iso"]
+    for k in ("aniso_same_particles", "aniso_random"):
+        out[k]["iso_speedup_fwd"] = round(iso["fwd_mpix_per_s"] / out[k]["fwd_mpix_per_s"], 3)
+        out[k]["iso_speedup_fwd_bwd"] = round(iso["fwd_bwd_iters_per_s"] / out[k]["fwd_bwd_iters_per_s"], 3)
+    out["workload"] = f"mix1m_1080p: {len(views)} orbit views, calls of {batch_views}; fwd+bwd at 1 view, L1"
+    return out
+
+
 def field2d_workload(dev, iters=100):
     """The paper's 2D experiment on a synthetic stand-in: fit 2000 weighted isotropic kernels
     (random initialisation) to a procedural 512x512 RGB image with the paper's loss,
@@ -362,11 +440,58 @@ def field2d_workload(dev, iters=100):
     return res
 
 
-def cpu_baseline(scene, cam, budget_s):
-    """FP64 oracle on one view: full projection and binning, then compositing of tiles in a
-    seeded random order until the time budget is spent, extrapolated to the full frame."""
+_CPU = {}
+
+
+def _cpu_workers():
+    """Host cores this process may use, at most 16 (the CPU share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _cpu_tiles(args):
+    """Worker: composites its tiles with the FP64 oracle until the deadline."""
     import oracle as O
+    tiles, deadline = args
+    pr, bins, cam = _CPU["pr"], _CPU["bins"], _CPU["cam"]
+    done, pix = 0, 0
+    for k in tiles:
+        if time.perf_counter() > deadline:
+            break
+        TXc = (cam.width + 15) // 16
+        tx, ty = int(k) % TXc, int(k) // TXc
+        O.render64_tiled(pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bins, 0, cam.width, cam.height, tiles=[(tx, ty)])
+        done += 1
+        pix += len(O.tile_pixels(tx, ty, cam.width, cam.height)[0])
+    return done, pix
+
+
+def _cpu_rows(args):
+    """Worker: the untiled oracle (every pixel over every visible particle) on some rows."""
+    import oracle as O
+    key, rows = args
+    pr, cam = _CPU[key]
+    O.render64_untiled(pr, cam.width, cam.height, rows=rows)
+    return len(rows) * cam.width
+
+
+def cpu_baseline(scene, cam, budget_s):
+    """The FP64 oracle on the host's cores (a pool of worker processes, one BLAS thread
+    each): one view of the benchmark workload - full projection and binning of all
+    particles, then the tiled compositing of seeded-random tiles until the time budget is
+    spent, extrapolated to the full frame; also the untiled definition (every pixel over
+    every visible particle) on the 10k-particle 256x256 workload's full frame and on a 64x64
+    centre crop of the benchmark view, and one iteration of the 2D fit."""
+    import multiprocessing as mp
+    import oracle as O
+    import scenegen as S
     from threadpoolctl import threadpool_limits
+    workers = _cpu_workers()
+    ctx = mp.get_context("fork")
+    out = {}
     with threadpool_limits(1):
         t0 = time.perf_counter()
         pr = O.project64(scene, cam)
@@ -375,20 +500,25 @@ def cpu_baseline(scene, cam, budget_s):
         t2 = time.perf_counter()
         TX, TY = O.tile_grid(cam.width, cam.height)
         order = np.random.default_rng(0).permutation(TX * TY)
-        done_tiles, pix = 0, 0
-        t_render = 0.0
-        for k in order:
-            tx, ty = int(k % TX), int(k // TX)
+        _CPU.update(pr=pr, bins=bins, cam=cam)
+        # untiled legs: the 10k-particle 256x256 frame and a 64x64 crop of this view
+        c1_scene, c1_cam = S.workload_scene("cube10k_256"), S.workload_cameras("cube10k_256")[0]
+        _CPU["cube"] = (O.project64(c1_scene, c1_cam), c1_cam)
+        crop = cam.shifted(cam.width // 2 - 32, cam.height // 2 - 32, 64, 64)
+        _CPU["crop"] = (O.project64(scene, crop), crop)
+        with ctx.Pool(workers) as pool:
+            deadline = time.perf_counter() + budget_s
             ts = time.perf_counter()
-            O.render64_tiled(pr.u, pr.v, pr.s, pr.opacity, pr.rgb, bins, 0, cam.width, cam.height,
-                             tiles=[(tx, ty)])
-            t_render += time.perf_counter() - ts
-            done_tiles += 1
-            pix += len(O.tile_pixels(tx, ty, cam.width, cam.height)[0])
-            if t_render + (t2 - t0) > budget_s:
-                break
-        # the 2D fit: one iteration (kernel sum, L1 gradient, parameter gradients) per radius
-        import scenegen as S
+            res = pool.map(_cpu_tiles, [(order[w::workers], deadline) for w in range(workers)])
+            t_render = time.perf_counter() - ts
+            done_tiles, pix = sum(r[0] for r in res), sum(r[1] for r in res)
+            legs = {}
+            for key in ("cube", "crop"):
+                H = _CPU[key][1].height
+                ts = time.perf_counter()
+                npx = sum(pool.map(_cpu_rows, [(key, np.arange(w, H, workers)) for w in range(workers)]))
+                legs[key] = (npx, time.perf_counter() - ts)
+        # the 2D fit: one iteration (kernel sum, loss gradient, parameter gradients) per radius
         from oracle import field2d64 as F2
         from oracle import ssim64 as Q2
         tgt = S.field2d_target(512, 512)
@@ -400,12 +530,21 @@ def cpu_baseline(scene, cam, budget_s):
             F2.field_grads64(mu, sg, amp, 512, 512, D, w)
             f2[f"d{int(D)}_s_per_iter"] = round(time.perf_counter() - ts, 3)
     total_pix = cam.width * cam.height
-    per_view = (t1 - t0) + (t2 - t1) + t_render * (total_pix / pix)
-    return dict(value=total_pix / per_view / 1e6, unit="Mpix/s", cores=1, kind="oracle",
-                sample=f"1 view of 1920x1080 / 1M Gaussians: FP64 projection and binning of all "
-                       f"particles ({t1 - t0:.1f}s + {t2 - t1:.1f}s), compositing of {done_tiles} random "
-                       f"tiles ({pix} px, {t_render:.1f}s) extrapolated to the full frame; one thread",
-                field2d_fit512_k2000=f2)
+    per_view = (t1 - t0) + (t2 - t1) + t_render * (total_pix / max(pix, 1))
+    out = dict(value=total_pix / per_view / 1e6, unit="Mpix/s", cores=workers, kind="oracle",
+               sample=f"1 view of 1920x1080 / 1M Gaussians: FP64 projection and binning of all particles "
+                      f"({t1 - t0:.1f}s + {t2 - t1:.1f}s, one process), tiled compositing of {done_tiles} random "
+                      f"tiles ({pix} px) in {t_render:.1f}s on {workers} worker processes, extrapolated to the "
+                      f"full frame",
+               os_cpu_count=os.cpu_count(),
+               untiled_cube10k_256_full_frame={"mpix_per_s": round(legs["cube"][0] / legs["cube"][1] / 1e6, 5),
+                                               "s": round(legs["cube"][1], 2), "pixels": legs["cube"][0],
+                                               "pairs": int(_CPU["cube"][0].visible.sum()) * legs["cube"][0]},
+               untiled_mix1m_1080p_crop64={"mpix_per_s": round(legs["crop"][0] / legs["crop"][1] / 1e6, 6),
+                                           "s": round(legs["crop"][1], 2), "pixels": legs["crop"][0]},
+               field2d_fit512_k2000=f2)
+    _CPU.clear()
+    return out
 
 
 def main():
@@ -422,12 +561,19 @@ def main():
         print(json.dumps(field2d_workload("cuda")), flush=True)
         return
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     t = time.perf_counter()
     scene = S.mixture_scene(args.gaussians, seed=0)
     cams = [S.orbit_camera(2.0 * math.pi * i / args.views, 4.0, args.width, args.height) for i in range(args.views)]
     log(f"scene generated in {time.perf_counter() - t:.1f}s")
+    cpu = None
+    if not args.no_cpu_baseline and not args.pmc_probe:
+        # before the GPU is touched: the oracle's worker processes fork from this one
+        log(f"cpu baseline ({_cpu_workers()} worker processes) ...")
+        cpu = cpu_baseline(scene, cams[0], args.cpu_seconds)
+        cpu["value"] = round(cpu["value"], 5)
+        log(f"cpu baseline: {cpu}")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
     gs = P.GaussianScene.from_host(scene, dev)
     R = P.Rasterizer(dev, headroom=1.1)
     B = args.batch_views
@@ -588,6 +734,10 @@ def main():
         extra["stress_6m_4k_x8"] = stress_workload(dev)
         log(f"stress workload: {extra['stress_6m_4k_x8']}")
         torch.cuda.empty_cache()
+        log("iso vs aniso (1M, 1080p) ...")
+        extra["iso_vs_aniso"] = aniso_workload(dev, scene, cams)
+        log(f"iso vs aniso: {extra['iso_vs_aniso']}")
+        torch.cuda.empty_cache()
         log("2D fit (2000 kernels, 512x512) ...")
         extra["field2d_fit512_k2000"] = field2d_workload(dev)
         log(f"2D fit: {extra['field2d_fit512_k2000']}")
@@ -616,10 +766,8 @@ def main():
         "serving": serving,
         **extra,
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(scene, cams[0], args.cpu_seconds)
-        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 5)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -266,6 +266,76 @@ int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_
                      const uint32_t* n_last, const float* checkpoints, const isogs_scene* grads,
                      void* ws, size_t* ws_bytes, void* stream);
 
+/* ---- Anisotropic variant (Section 1: eq. 5, eq. 6, eq. 7) ----------------------------
+ * The kernels the paper sets its isotropic ones against, on the same pipeline: a particle
+ * carries a rotation and three scales, its covariance is Sigma = R S S^T R^T (eq. 6), its
+ * screen covariance Sigma_2D = J V Sigma V^T J^T (eq. 7: V the camera rotation, J the
+ * Jacobian of the pinhole map at the centre, no low-pass term), and the screen kernel is
+ * eq. 5 with Sigma_2D, g = exp(-(A dx^2 + 2 B dx dy + C dy^2)) where [[A, B], [B, C]] =
+ * Sigma_2D^-1 (the conic) and (dx, dy) = pixel centre - projected centre (no factor 1/2,
+ * as in eq. 8). alpha = min(0.99, o g) and everything after it - the 1/255 support, the
+ * compositing of eq. 4, the stop at T < 1e-4, 16x16 tiles, the depth order - is the
+ * isotropic path's. With Sigma = sigma^2 I the footprint is the full projection
+ * sigma^2 J J^T of an isotropic particle (on the optical axis, the circle of scale
+ * f sigma / z that isogs_project uses).
+ *
+ * A scene (device memory, structure of arrays, FP32):
+ *   pos      [3][n]   centres
+ *   rot      [4][n]   quaternions (w, x, y, z), any non-zero length (normalised inside)
+ *   scale    [3][n]   linear per-axis scales > 0
+ *   opacity  [n], color [3K][n]  as in isogs_scene
+ * In isogs_aniso_render_bwd the same struct describes gradient OUTPUT buffers. */
+typedef struct {
+    const float* pos;
+    const float* rot;
+    const float* scale;
+    const float* opacity;
+    const float* color;
+    int32_t n;
+    int32_t sh_degree;
+} isogs_aniso_scene;
+
+/* Anisotropic footprints, packed over views like isogs_projected:
+ *   fp.record  [N][8]  {u, v, A, o, r, g, b, radius} (32-byte aligned); radius is the
+ *                      radius of the disk around the support ellipse A dx^2 + 2 B dx dy +
+ *                      C dy^2 <= ln(255 o), sqrt(lambda_max(Sigma_2D) ln(255 o)) (1 + 2^-10)
+ *                      + 2^-6 pixels; a culled particle has an all-zero record
+ *   fp.depth, fp.tile_count  as in isogs_projected
+ *   conic      [N][2]  {B, C} (8-byte aligned)
+ * fp has the isotropic record's layout where binning reads it (centre, radius, depth,
+ * tile count): isogs_bin_sort and isogs_bin_sort_static take &fp unchanged. */
+typedef struct {
+    isogs_projected fp;
+    float* conic;
+} isogs_aniso_projected;
+
+/* Projects every particle of every view: centre, conic and binning radius of eq. 7 (FP64
+ * inside, rounded once to FP32), colour as isogs_project, member-tile count. A particle
+ * is culled when a parameter is non-finite, a scale <= 0, |q| = 0, o < 1/255, depth <=
+ * near_z, det Sigma_2D <= 0, or its footprint has no normal FP32 form (centre, conic or
+ * radius overflowing, A or C below the smallest normal FP32 value).
+ * Errors: as isogs_project (rot must be non-NULL with n > 0; conic 8-byte aligned). */
+int isogs_aniso_project(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t n_views,
+                        const isogs_aniso_projected* out, void* stream);
+
+/* isogs_render_fwd_ordered for anisotropic footprints binned by isogs_bin_sort(&proj->fp):
+ * the same outputs, workspace, checkpoints and flags (ISOGS_FWD_WIDE). */
+int isogs_aniso_render_fwd(const isogs_aniso_projected* proj, const int32_t* n_per_view,
+                           const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,
+                           const float* bg, float* image, float* T_final, uint32_t* n_last,
+                           float* checkpoints, uint32_t flags, void* ws, size_t* ws_bytes,
+                           void* stream);
+
+/* isogs_render_bwd for the anisotropic family: gradients of the centre, the quaternion
+ * (through its normalisation), the three scales, the opacity and the colour coefficients.
+ * The workspace holds 48 bytes per entry of capacity (each entry's nine gradient sums)
+ * instead of 32; everything else as isogs_render_bwd. */
+int isogs_aniso_render_bwd(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t n_views,
+                           const isogs_aniso_projected* proj, const isogs_bins* bins, const float* bg,
+                           const float* image, const float* dL_dimage, const float* T_final,
+                           const uint32_t* n_last, const float* checkpoints,
+                           const isogs_aniso_scene* grads, void* ws, size_t* ws_bytes, void* stream);
+
 /* ---- 2D kernel-sum representation (Section 3, "Our Method") --------------------------
  * An image signal represented by K weighted isotropic kernels, with no compositing:
  *   f_c(x) = sum over k with |x - mu_k| < D of A_kc exp(-|x - mu_k|^2 / sigma_k^2)

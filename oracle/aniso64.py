@@ -162,8 +162,17 @@ def kernel_exponent(dx, dy, conic_g):
     return A * dx * dx + 2.0 * B * dx * dy + C * dy * dy
 
 
+def centre_growth(dx, dy, conic_g, e):
+    """Largest change of Q = d^T M d (M the conic) when the centre moves by at most e in x
+    and in y: 2 (|(M d)_x| + |(M d)_y|) e + (|A| + 2 |B| + |C|) e^2. For a circle M = I / s^2
+    this is the isotropic walk's bound (2 (|dx| + |dy|) e + 2 e^2) / s^2."""
+    A, B, C = conic_g
+    return (2.0 * (np.abs(A * dx + B * dy) + np.abs(B * dx + C * dy)) * e
+            + (abs(A) + 2.0 * abs(B) + abs(C)) * e * e)
+
+
 def composite_pixels_aniso(px, py, seq, u, v, conic, o, rgb, bg, trace=False, alpha_band=None, term_band=None,
-                           q_err=None):
+                           q_err=None, pos_err=None, z32=None):
     """Front-to-back compositing (eq. 4) of one particle sequence at a set of pixel centres
     with the kernel of eq. 5: G = exp(-(A dx^2 + 2 B dx dy + C dy^2)), alpha = min(0.99, o G),
     an entry is skipped when alpha < 1/255, C += c alpha T, T *= 1 - alpha, the pixel stops
@@ -173,7 +182,13 @@ def composite_pixels_aniso(px, py, seq, u, v, conic, o, rgb, bg, trace=False, al
     exponent evaluated in lower precision) of 1/255, or some T after an entry within a
     relative ``term_band`` (grown by what those alpha uncertainties can do to T) of 1e-4.
     Pinned: equal to the isotropic walk for circular conics, tiled == untiled, finite
-    differences of its gradients."""
+    differences of its gradients.
+
+    For footprints that are the FP32 roundings of these (an end-to-end comparison),
+    ``pos_err`` [n] bounds each centre's error (the alpha band grows by ``centre_growth``,
+    and the band of T by what that does to T, as in ``isogs64.composite_pixels``) and
+    ``z32`` [n] gives the FP32 depths: two consecutive composited entries at most one ulp
+    apart flag the pixel (their order may differ)."""
     alpha_band = I.ALPHA_FLAG_REL if alpha_band is None else alpha_band
     term_band = I.TERM_FLAG_REL if term_band is None else term_band
     px = np.asarray(px, dtype=np.float64)
@@ -186,6 +201,8 @@ def composite_pixels_aniso(px, py, seq, u, v, conic, o, rgb, bg, trace=False, al
     near_alpha = np.zeros(P, dtype=bool)
     near_term = np.zeros(P, dtype=bool)
     t_band = np.full(P, float(term_band))
+    zb = None if z32 is None else np.asarray(z32, dtype=np.float32).view(np.int32).astype(np.int64)
+    prev_z = np.full(P, -(1 << 40), dtype=np.int64)
     rec = [] if trace else None
     for pos, g in enumerate(seq):
         if done.all():
@@ -200,6 +217,8 @@ def composite_pixels_aniso(px, py, seq, u, v, conic, o, rgb, bg, trace=False, al
         if q_err is not None:
             A, B, Cc = conic[:, g]
             grow = q_err * (abs(A) * dx * dx + 2.0 * abs(B) * np.abs(dx * dy) + abs(Cc) * dy * dy)
+        if pos_err is not None:
+            grow = grow + centre_growth(dx, dy, conic[:, g], float(pos_err[g]))
         near_alpha |= live & (np.abs(a * 255.0 - 1.0) <= alpha_band + grow)
         use = live & (a >= I.ALPHA_MIN)
         if not use.any():
@@ -209,6 +228,9 @@ def composite_pixels_aniso(px, py, seq, u, v, conic, o, rgb, bg, trace=False, al
         T_new = np.where(use, T * (1.0 - a), T)
         t_band = t_band + np.where(use, a / (1.0 - a) * grow, 0.0)
         near_term |= use & (np.abs(T_new / I.T_MIN - 1.0) <= t_band)
+        if zb is not None:
+            near_alpha |= use & (np.abs(zb[g] - prev_z) <= 1)
+            prev_z = np.where(use, zb[g], prev_z)
         if trace:
             rec.append((pos, g, np.where(use, a, 0.0), T.copy(), use.copy(), G))
         T = T_new
@@ -221,9 +243,10 @@ def composite_pixels_aniso(px, py, seq, u, v, conic, o, rgb, bg, trace=False, al
 
 
 def pixel_outcomes_aniso(px, py, seq, u, v, conic, o, rgb, bg=(0.0, 0.0, 0.0), alpha_band=None, term_band=None,
-                         q_err=None, slack=1e-5, max_branch=12):
+                         q_err=None, slack=1e-5, max_branch=12, pos_err=None, z32=None):
     """Every valid result of one pixel near a decision (``isogs64.pixel_outcomes``) for the
-    kernel of eq. 5, the alpha bands grown as in ``composite_pixels_aniso``."""
+    kernel of eq. 5, the alpha bands grown as in ``composite_pixels_aniso`` (with ``z32``, the
+    order of two entries one FP32 ulp apart in depth is also taken both ways)."""
     seq = np.asarray(seq, dtype=np.int64)
     dx = float(px) - u[seq]
     dy = float(py) - v[seq]
@@ -233,7 +256,10 @@ def pixel_outcomes_aniso(px, py, seq, u, v, conic, o, rgb, bg=(0.0, 0.0, 0.0), a
     grow = np.zeros(seq.shape[0])
     if q_err is not None:
         grow = q_err * (np.abs(cg[0]) * dx * dx + 2.0 * np.abs(cg[1] * dx * dy) + np.abs(cg[2]) * dy * dy)
-    return I.walk_outcomes(a, grow, rgb[:, seq], bg, alpha_band, term_band, None, slack, max_branch)
+    if pos_err is not None:
+        grow = grow + centre_growth(dx, dy, cg, np.asarray(pos_err, dtype=np.float64)[seq])
+    zs = None if z32 is None else np.asarray(z32, dtype=np.float32)[seq]
+    return I.walk_outcomes(a, grow, rgb[:, seq], bg, alpha_band, term_band, zs, slack, max_branch)
 
 
 def f32_views_aniso(projs, cams):
@@ -263,7 +289,7 @@ def render_aniso_untiled(proj: AnisoProjected64, width, height, bg=(0.0, 0.0, 0.
 
 
 def render_aniso_tiled(u, v, conic, o, rgb, bins, view_id, width, height, bg=(0.0, 0.0, 0.0), pidx_offset=0,
-                       q_err=None, tiles=None):
+                       q_err=None, tiles=None, pos_err=None, z32=None):
     """Per-tile rendering of one view over the lists of ``isogs64.bin_sort_ref``. Returns
     image [3, H, W], T_final [H, W], n_last [H, W] and the flags [H, W]."""
     TX, TY = I.tile_grid(width, height)
@@ -278,7 +304,7 @@ def render_aniso_tiled(u, v, conic, o, rgb, bins, view_id, width, height, bg=(0.
         seq = bins.pidx[a:b].astype(np.int64) - pidx_offset
         X, Y = I.tile_pixels(tx, ty, width, height)
         C, T, n, tr = composite_pixels_aniso(X + 0.5, Y + 0.5, seq, u, v, conic, o, rgb, bg, trace=True,
-                                             q_err=q_err)
+                                             q_err=q_err, pos_err=pos_err, z32=z32)
         img[:, Y, X] = C
         Tf[Y, X] = T
         nl[Y, X] = n
@@ -286,16 +312,19 @@ def render_aniso_tiled(u, v, conic, o, rgb, bins, view_id, width, height, bg=(0.
     return img, Tf, nl, flags
 
 
-def render_aniso_views(scenes, cams, bg=(0.0, 0.0, 0.0), q_err=None):
+def render_aniso_views(scenes, cams, bg=(0.0, 0.0, 0.0), q_err=None, rounded=False, tiles=None):
     """Projects, bins and renders each (scene, camera) pair with the tiled oracle. Returns
-    (images, T_final, n_last, flags, projections, bins), lists over the views."""
+    (images, T_final, n_last, flags, projections, bins), lists over the views. ``rounded``:
+    the flags allow for footprints rounded once to FP32 elsewhere (centre errors and FP32
+    depths from ``isogs64.footprint_uncertainty``)."""
     projs = [project_aniso64(sc, cam) for sc, cam in zip(scenes, cams)]
     bins = I.bin_sort_ref(f32_views_aniso(projs, cams))
     out = ([], [], [], [])
     off = 0
     for vi, (pr, cam) in enumerate(zip(projs, cams)):
+        pe, z32 = I.footprint_uncertainty(pr) if rounded else (None, None)
         res = render_aniso_tiled(pr.u, pr.v, pr.conic, pr.opacity, pr.rgb, bins, vi, cam.width, cam.height, bg,
-                                 pidx_offset=off, q_err=q_err)
+                                 pidx_offset=off, q_err=q_err, tiles=tiles, pos_err=pe, z32=z32)
         for lst, x in zip(out, res):
             lst.append(x)
         off += pr.u.shape[0]

@@ -23,8 +23,8 @@ ISOGS_STATIC_SCRATCH_BYTES = 128 << 20
 EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_render_fwd", "isogs_render_fwd_ordered",
             "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_field2d_bin", "isogs_field2d_fwd",
             "isogs_field2d_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune", "isogs_field2d_split",
-            "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_last_error",
-            "isogs_version")
+            "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_aniso_project",
+            "isogs_aniso_render_fwd", "isogs_aniso_render_bwd", "isogs_last_error", "isogs_version")
 
 
 class Scene(ctypes.Structure):
@@ -40,6 +40,16 @@ class Camera(ctypes.Structure):
 
 class Projected(ctypes.Structure):
     _fields_ = [("record", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("tile_count", ctypes.c_void_p)]
+
+
+class AnisoScene(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("color", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32)]
+
+
+class AnisoProjected(ctypes.Structure):
+    _fields_ = [("fp", Projected), ("conic", ctypes.c_void_p)]
 
 
 class Bins(ctypes.Structure):
@@ -86,6 +96,13 @@ def lib():
                                                vp, P(ctypes.c_size_t), vp]
         L.isogs_render_bwd.argtypes = [P(Scene), P(Camera), ctypes.c_int32, P(Projected), P(Bins),
                                        P(ctypes.c_float), vp, vp, vp, vp, vp, P(Scene), vp, P(ctypes.c_size_t), vp]
+        L.isogs_aniso_project.argtypes = [P(AnisoScene), P(Camera), ctypes.c_int32, P(AnisoProjected), vp]
+        L.isogs_aniso_render_fwd.argtypes = [P(AnisoProjected), P(ctypes.c_int32), P(Bins), P(Camera),
+                                             ctypes.c_int32, P(ctypes.c_float), vp, vp, vp, vp, ctypes.c_uint32,
+                                             vp, P(ctypes.c_size_t), vp]
+        L.isogs_aniso_render_bwd.argtypes = [P(AnisoScene), P(Camera), ctypes.c_int32, P(AnisoProjected), P(Bins),
+                                             P(ctypes.c_float), vp, vp, vp, vp, vp, P(AnisoScene), vp,
+                                             P(ctypes.c_size_t), vp]
         L.isogs_field2d_bin.argtypes = [P(Field2D), ctypes.c_int32, ctypes.c_int32, ctypes.c_float, P(Projected),
                                         P(Bins), vp, P(ctypes.c_size_t), vp]
         L.isogs_field2d_fwd.argtypes = [P(Projected), ctypes.c_int32, P(Bins), ctypes.c_int32, ctypes.c_int32,
@@ -108,7 +125,8 @@ def lib():
         for name in ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_render_fwd", "isogs_render_fwd_ordered",
                      "isogs_render_bwd", "isogs_field2d_bin", "isogs_field2d_fwd", "isogs_field2d_bwd",
                      "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune",
-                     "isogs_field2d_split", "isogs_l1_fwd", "isogs_l1_bwd"):
+                     "isogs_field2d_split", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_aniso_project",
+                     "isogs_aniso_render_fwd", "isogs_aniso_render_bwd"):
             getattr(L, name).restype = ctypes.c_int
         L.isogs_last_error.restype = ctypes.c_char_p
         L.isogs_last_error.argtypes = []

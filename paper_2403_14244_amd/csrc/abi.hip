@@ -92,6 +92,25 @@ int check_scene(const isogs_scene& s, int v, bool grads) {
     return ISOGS_OK;
 }
 
+int check_aniso_scene(const isogs_aniso_scene& s, int v, bool grads) {
+    const char* what = grads ? "grads" : "scene";
+    if (s.n < 0) return fail(ISOGS_ERR_INVALID, "%s %d: n < 0", what, v);
+    if (s.sh_degree < 0 || s.sh_degree > ISOGS_MAX_SH_DEGREE)
+        return fail(ISOGS_ERR_INVALID, "%s %d: sh_degree %d outside 0..3", what, v, s.sh_degree);
+    if (s.n > 0 && (!s.pos || !s.rot || !s.scale || !s.opacity || !s.color))
+        return fail(ISOGS_ERR_INVALID, "%s %d: NULL parameter buffer", what, v);
+    return ISOGS_OK;
+}
+
+int check_aniso_projected(const isogs_aniso_projected* p, uint64_t n) {
+    if (!p) return fail(ISOGS_ERR_INVALID, "projected is NULL");
+    int rc = check_projected(&p->fp, n);
+    if (rc) return rc;
+    if (n && !p->conic) return fail(ISOGS_ERR_INVALID, "projected conic is NULL");
+    if ((uintptr_t)p->conic & 7) return fail(ISOGS_ERR_INVALID, "projected conic must be 8-byte aligned");
+    return ISOGS_OK;
+}
+
 int check_field2d_sizes(int32_t K, int32_t width, int32_t height, float support, uint64_t* tiles) {
     if (K < 0) return fail(ISOGS_ERR_INVALID, "K < 0");
     if (width <= 0 || height <= 0) return fail(ISOGS_ERR_INVALID, "width and height must be positive");
@@ -204,7 +223,7 @@ int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_v
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
     if (flags & ~ISOGS_FWD_WIDE) return fail(ISOGS_ERR_INVALID, "unknown flags %u", flags);
-    if (isogs::launch_render_fwd_ordered(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
+    if (isogs::launch_render_fwd_ordered(proj, nullptr, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
                                          checkpoints, flags, ws, (hipStream_t)stream))
         return device_fail("isogs_render_fwd_ordered");
     return ISOGS_OK;
@@ -221,7 +240,7 @@ int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_
     if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
     if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
     if ((rc = check_cameras(cams, n_views))) return rc;
-    const size_t need = isogs::render_bwd_ws(bins->capacity, cams, n_views);
+    const size_t need = isogs::render_bwd_ws(bins->capacity, cams, n_views, false);
     if (!ws) {
         *ws_bytes = need;
         return ISOGS_OK;
@@ -251,6 +270,106 @@ int isogs_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_
     if (isogs::launch_render_bwd(scenes, cams, n_views, proj, bins, bg, image, dL_dimage, T_final, n_last,
                                  checkpoints, grads, ws, (hipStream_t)stream))
         return device_fail("isogs_render_bwd");
+    return ISOGS_OK;
+}
+
+int isogs_aniso_project(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t n_views,
+                        const isogs_aniso_projected* out, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!scenes) return fail(ISOGS_ERR_INVALID, "scenes is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    int32_t npv[kMaxBatchViews];
+    for (int v = 0; v < n_views; ++v) {
+        if ((rc = check_aniso_scene(scenes[v], v, false))) return rc;
+        npv[v] = scenes[v].n;
+    }
+    uint64_t n;
+    if ((rc = check_totals(npv, cams, n_views, &n, nullptr, nullptr))) return rc;
+    if ((rc = check_aniso_projected(out, n))) return rc;
+    if (isogs::launch_aniso_project(scenes, cams, n_views, out, (hipStream_t)stream))
+        return device_fail("isogs_aniso_project");
+    return ISOGS_OK;
+}
+
+int isogs_aniso_render_fwd(const isogs_aniso_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
+                           const isogs_camera* cams, int32_t n_views, const float* bg, float* image, float* T_final,
+                           uint32_t* n_last, float* checkpoints, uint32_t flags, void* ws, size_t* ws_bytes,
+                           void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    const size_t need = isogs::render_fwd_ordered_ws(cams, n_views);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!bg) return fail(ISOGS_ERR_INVALID, "bg is NULL");
+    uint64_t n, tiles;
+    if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
+    if ((rc = check_aniso_projected(proj, n))) return rc;
+    if ((rc = check_bins(bins, n, tiles))) return rc;
+    if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (flags & ~ISOGS_FWD_WIDE) return fail(ISOGS_ERR_INVALID, "unknown flags %u", flags);
+    // a NULL conic selects the isotropic walk: give the anisotropic one a valid address
+    // even when there is no particle
+    static float no_conic[2];
+    const float* conic = proj->conic ? proj->conic : no_conic;
+    if (isogs::launch_render_fwd_ordered(&proj->fp, conic, n_per_view, bins, cams, n_views, bg, image, T_final,
+                                         n_last, checkpoints, flags, ws, (hipStream_t)stream))
+        return device_fail("isogs_aniso_render_fwd");
+    return ISOGS_OK;
+}
+
+int isogs_aniso_render_bwd(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t n_views,
+                           const isogs_aniso_projected* proj, const isogs_bins* bins, const float* bg,
+                           const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
+                           const float* checkpoints, const isogs_aniso_scene* grads, void* ws, size_t* ws_bytes,
+                           void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if ((rc = check_views(n_views))) return rc;
+    if (!scenes || !grads) return fail(ISOGS_ERR_INVALID, "scenes or grads is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    if ((rc = check_cameras(cams, n_views))) return rc;
+    const size_t need = isogs::render_bwd_ws(bins->capacity, cams, n_views, true);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    int32_t npv[kMaxBatchViews];
+    for (int v = 0; v < n_views; ++v) {
+        if ((rc = check_aniso_scene(scenes[v], v, false))) return rc;
+        if ((rc = check_aniso_scene(grads[v], v, true))) return rc;
+        if (grads[v].n != scenes[v].n || grads[v].sh_degree != scenes[v].sh_degree)
+            return fail(ISOGS_ERR_INVALID, "view %d: grads must match the scene's n and sh_degree", v);
+        npv[v] = scenes[v].n;
+    }
+    for (int v = 0; v < n_views; ++v)
+        for (int u = 0; u < v; ++u)
+            if (scenes[u].pos == scenes[v].pos &&
+                (grads[u].pos != grads[v].pos || scenes[u].n != scenes[v].n || scenes[u].rot != scenes[v].rot ||
+                 scenes[u].scale != scenes[v].scale || scenes[u].sh_degree != scenes[v].sh_degree ||
+                 scenes[u].color != scenes[v].color))
+                return fail(ISOGS_ERR_INVALID, "views %d and %d share a scene but not its grads buffers", u, v);
+    uint64_t n, tiles;
+    if ((rc = check_totals(npv, cams, n_views, &n, &tiles, nullptr))) return rc;
+    if ((rc = check_aniso_projected(proj, n))) return rc;
+    if ((rc = check_bins(bins, n, tiles))) return rc;
+    if (!bg || !dL_dimage || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "input buffer is NULL");
+    if (checkpoints && !image) return fail(ISOGS_ERR_INVALID, "checkpoints given without the image");
+    if (isogs::launch_aniso_render_bwd(scenes, cams, n_views, proj, bins, bg, image, dL_dimage, T_final, n_last,
+                                       checkpoints, grads, ws, (hipStream_t)stream))
+        return device_fail("isogs_aniso_render_bwd");
     return ISOGS_OK;
 }
 

@@ -21,14 +21,28 @@ constexpr int kBwdBatch = 48;
 static_assert(kBwdBatch <= kWave, "one staged entry per lane");
 constexpr int kBwdDummy = kBwdBatch;   // staged slot of the zero-opacity pad record
 
+// Per-entry gradient sums over a tile's pixels (dx = x - u, dy = y - v; k = dL/dalpha
+// times the kernel value below the clamp, i.e. -dL/d(exponent); w = alpha T):
+//   isotropic (7):    2 k dx / s^2, 2 k dy / s^2, -k d^2, k / o, dr w, dg w, db w
+//   anisotropic (9):  k dx, k dy, k dx^2, k dx dy, k dy^2, k / o, dr w, dg w, db w
+// (the anisotropic centre and conic gradients are these sums times the entry's conic,
+// applied per particle). A record holds them in kRecVec4<AN> float4s at the entry's emit
+// position.
+template <bool AN>
+constexpr int kGradTerms = AN ? 9 : 7;
+template <bool AN>
+constexpr int kRecVec4 = AN ? 3 : 2;
+
 // One batch of a tile's entries in LDS, back to front, with the 16 sub-block lists.
-struct StagedBwd {
-    float4 fp[kBwdBatch + 1];            // {u, v, q = log2(e)/s^2, log2(o)}
+template <bool AN>
+struct StagedBwdT {
+    float4 fp[kBwdBatch + 1];            // staged kernel (staged_kernel: {u, v, q or nA, log2(o)})
     float4 col[kBwdBatch + 1];           // {r, g, b, 1/o}
+    float2 cn[AN ? kBwdBatch + 1 : 1];   // anisotropic: {nB2, nC}
     uint16_t list[16][kBwdBatch + 4];    // per sub-block, staged slots in walk order
     uint32_t slot[kBwdBatch];            // emit position of each staged entry
     uint8_t mask[4][kBwdBatch];          // [wave] which of its sub-blocks listed the entry
-    float part[16][7][kBwdBatch];        // per-sub-block gradient sums of each entry
+    float part[16][kGradTerms<AN>][kBwdBatch];   // per-sub-block gradient sums of each entry
     uint32_t gmax[16];                   // largest n_last of each sub-block
 };
 
@@ -39,8 +53,9 @@ struct StagedBwd {
 // disk touches the sub-block and its position is at most the sub-block's largest n_last
 // (no later entry was composited there). Returns the number of list steps of the calling
 // wave; `len` receives the padded length of this lane's row list. Contains __syncthreads.
-__device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __restrict__ record,
-                                              const uint32_t* __restrict__ pidx,
+template <bool AN>
+__device__ __forceinline__ uint32_t stage_bwd(StagedBwdT<AN>& sb, const float4* __restrict__ record,
+                                              const float2* __restrict__ conic, const uint32_t* __restrict__ pidx,
                                               const uint32_t* __restrict__ offsets, uint32_t n_particles,
                                               uint32_t hi, uint32_t nb, uint32_t pos_hi, int tx, int ty,
                                               int tiles_x, int tiles_y, float w_lim, float h_lim, uint32_t& len) {
@@ -51,10 +66,12 @@ __device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __res
         const float4 f = record[2 * (size_t)g];
         const float4 c = record[2 * (size_t)g + 1];
         if (w == 0) {
-            sb.fp[l] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
+            sb.fp[l] = staged_kernel<AN>(f);
             sb.col[l] = make_float4(c.x, c.y, c.z, __builtin_amdgcn_rcpf(f.w));   // once per entry
         } else if (w == 1) {
             sb.slot[l] = emit_slot(offsets[g], f.x, f.y, c.w, tx, ty, tiles_x, tiles_y, w_lim, h_lim);
+        } else if (AN && w == 2) {
+            sb.cn[l] = staged_conic(conic[g]);
         }
         const float r2 = c.w * c.w;
         const uint32_t pos1 = pos_hi - l;
@@ -70,6 +87,7 @@ __device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __res
     if (t == 0) {
         sb.fp[kBwdDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
         sb.col[kBwdDummy] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (AN) sb.cn[kBwdDummy] = make_float2(0.0f, 0.0f);
     }
     if (l < (uint32_t)kBwdBatch) sb.mask[w][l] = (uint8_t)mask;
     uint64_t bal[4];
@@ -96,16 +114,17 @@ __device__ __forceinline__ uint32_t stage_bwd(StagedBwd& sb, const float4* __res
 
 // Reverse walk of one tile (logical index within the launch) by a 256-thread workgroup,
 // one lane per pixel, each 16-lane row owning a 4x4 sub-block (the forward pixel layout).
-// Record of an entry: {du, dv, d(1/s^2), do} {dr, dg, db, 0}, at its emit position.
+// Record of an entry: its gradient sums (kGradTerms), at its emit position.
 // With checkpoints (`ckpt` non-null) and a list of at least kChunkedMin entries, the
 // workgroup walks only chunk `chunk` of the list, positions [chunk * kCkptChunk,
 // (chunk + 1) * kCkptChunk); a pixel whose last entry lies beyond the chunk starts from the
 // checkpoint at the chunk's end: T from there, and the light from behind = image - colour
 // accumulated before the chunk's end. Shorter lists, and every list without checkpoints,
 // are one chunk. Contains __syncthreads.
+template <bool AN>
 __device__ __forceinline__ void composite_bwd_tile(
-    StagedBwd& sb, const RenderPack& pk, uint32_t logical, uint32_t chunk, const float4* __restrict__ record,
-    const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges,
+    StagedBwdT<AN>& sb, const RenderPack& pk, uint32_t logical, uint32_t chunk, const float4* __restrict__ record,
+    const float2* __restrict__ conic, const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges,
     float bg_r, float bg_g, float bg_b, const float* __restrict__ image, const float* __restrict__ dL_dimage,
     const float* __restrict__ T_final, const uint32_t* __restrict__ n_last, const float4* __restrict__ ckpt,
     float4* __restrict__ rec) {
@@ -172,19 +191,21 @@ __device__ __forceinline__ void composite_bwd_tile(
             const float r = record[2 * (size_t)g + 1].w;
             const uint32_t slot = emit_slot(offsets[g], f.x, f.y, r, tx, ty, vd.tiles_x, vd.tiles_y, w_lim, h_lim);
             if (slot < pk.n_entries_cap) {
-                rec[2 * (size_t)slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                rec[2 * (size_t)slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+                for (int q = 0; q < kRecVec4<AN>; ++q)
+                    rec[kRecVec4<AN> * (size_t)slot + q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         }
     }
 
     const uint32_t q8 = rev3(lane & 7u);
-    const bool writer = (lane & 15u) < 8u && q8 < 7u;
+    const bool writer = (lane & 15u) < 8u && q8 < (uint32_t)kGradTerms<AN>;
+    const bool writer9 = AN && (lane & 15u) == 8u;   // the ninth sum
     for (uint32_t hi = start + max_last; hi > start + c_lo;) {
         const uint32_t nb = min((uint32_t)kBwdBatch, hi - start - c_lo);
         const uint32_t pos_hi = hi - start;
         uint32_t len;
-        const uint32_t steps = stage_bwd(sb, record, pidx, offsets, pk.n_particles, hi, nb, pos_hi, tx, ty,
+        const uint32_t steps = stage_bwd(sb, record, conic, pidx, offsets, pk.n_particles, hi, nb, pos_hi, tx, ty,
                                          vd.tiles_x, vd.tiles_y, w_lim, h_lim, len);
         for (uint32_t k = 0; k < steps; k += 4) {
             constexpr uint64_t kD = (uint64_t)kBwdDummy;
@@ -196,9 +217,10 @@ __device__ __forceinline__ void composite_bwd_tile(
                 const uint32_t pos1 = pos_hi - j;            // 1-based list position
                 const float4 f = sb.fp[j];
                 const float4 c = sb.col[j];
+                const float2 kc = AN ? sb.cn[j] : make_float2(0.0f, 0.0f);
                 const float dx = px - f.x, dy = py - f.y;
                 float ga;
-                float a = entry_alpha(dx, dy, f.z, f.w, ga);
+                float a = staged_alpha<AN>(dx, dy, f, kc, ga);
                 // an entry this pixel composited in the forward pass (same decision); the
                 // pad record has alpha 0
                 const bool use = (pos1 <= last) && (a >= kAlphaMin);
@@ -214,40 +236,67 @@ __device__ __forceinline__ void composite_bwd_tile(
                 // alpha = o exp(-d^2 / s^2) below the clamp: d/du = 2 alpha dx / s^2,
                 // d/d(1/s^2) = -alpha d^2, d/do = alpha / o
                 const float kk = (use && ga < kAlphaMax) ? dLda * ga : 0.0f;
-                const float inv_s2 = f.z * (1.0f / kLog2e);
-                float gv[8];
-                gv[0] = 2.0f * kk * inv_s2 * dx;
-                gv[1] = 2.0f * kk * inv_s2 * dy;
-                gv[2] = -kk * fmaf(dx, dx, dy * dy);
-                gv[3] = kk * c.w;
-                gv[4] = dr * wgt;
-                gv[5] = dg * wgt;
-                gv[6] = db * wgt;
-                gv[7] = 0.0f;
-                const float red = (ballot64(use) != 0) ? row_sum8(gv, lane) : 0.0f;
+                float gv[8], g9 = 0.0f;
+                if (!AN) {
+                    const float inv_s2 = f.z * (1.0f / kLog2e);
+                    gv[0] = 2.0f * kk * inv_s2 * dx;
+                    gv[1] = 2.0f * kk * inv_s2 * dy;
+                    gv[2] = -kk * fmaf(dx, dx, dy * dy);
+                    gv[3] = kk * c.w;
+                    gv[4] = dr * wgt;
+                    gv[5] = dg * wgt;
+                    gv[6] = db * wgt;
+                    gv[7] = 0.0f;
+                } else {
+                    // alpha = o exp(-Q) below the clamp: dL/du = k (2 A dx + 2 B dy),
+                    // dL/dA = -k dx^2, ...: the conic enters per particle
+                    const float kx = kk * dx, ky = kk * dy;
+                    gv[0] = kx;
+                    gv[1] = ky;
+                    gv[2] = kx * dx;
+                    gv[3] = kx * dy;
+                    gv[4] = ky * dy;
+                    gv[5] = kk * c.w;
+                    gv[6] = dr * wgt;
+                    gv[7] = dg * wgt;
+                    g9 = db * wgt;
+                }
+                const bool any = ballot64(use) != 0;
+                const float red = any ? row_sum8(gv, lane) : 0.0f;
                 if (writer && j != kBwdDummy) sb.part[sbk][q8][j] = red;
+                if (AN) {
+                    // the ninth sum over the row: butterfly (quad swaps, row rotations)
+                    float r9 = g9;
+                    if (any) {
+                        r9 += dpp<0xB1>(r9);
+                        r9 += dpp<0x4E>(r9);
+                        r9 += dpp<0x124>(r9);
+                        r9 += dpp<0x128>(r9);
+                    }
+                    if (writer9 && j != kBwdDummy) sb.part[sbk][kGradTerms<AN> - 1][j] = r9;
+                }
             }
         }
         __syncthreads();
-        // combine: the sub-blocks that listed an entry, in fixed order; waves 0 and 1 write
-        // the two halves of each record
+        // combine: the sub-blocks that listed an entry, in fixed order; wave w writes
+        // float4 w of each record (sums 4w .. 4w + 3)
         const uint32_t l = lane;
-        if (w < 2 && l < nb) {
+        if (w < (uint32_t)kRecVec4<AN> && l < nb) {
             const uint32_t m = (uint32_t)sb.mask[0][l] | ((uint32_t)sb.mask[1][l] << 4) |
                                ((uint32_t)sb.mask[2][l] << 8) | ((uint32_t)sb.mask[3][l] << 12);
             const int q0 = 4 * (int)w;
-            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+            float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 if ((m >> k) & 1u) {
-                    s0 += sb.part[k][q0][l];
-                    s1 += sb.part[k][q0 + 1][l];
-                    s2 += sb.part[k][q0 + 2][l];
-                    if (w == 0) s3 += sb.part[k][3][l];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (q0 + e < kGradTerms<AN>) s4[e] += sb.part[k][q0 + e][l];
                 }
             }
             const uint32_t slot = sb.slot[l];
-            if (slot < pk.n_entries_cap) rec[2 * (size_t)slot + w] = make_float4(s0, s1, s2, s3);
+            if (slot < pk.n_entries_cap)
+                rec[kRecVec4<AN> * (size_t)slot + w] = make_float4(s4[0], s4[1], s4[2], s4[3]);
         }
         __syncthreads();
         hi -= nb;
@@ -307,20 +356,40 @@ __global__ void __launch_bounds__(256) bwd_chunk_list_kernel(const uint32_t* __r
 // next ones the other tiles in longest-list-first order (they follow the long ones in the
 // queue, whose length classes tell how many those are); a workgroup past the last item
 // leaves at once. Without: workgroup b walks the tile at queue position b whole.
-__global__ void __launch_bounds__(256) composite_bwd_ordered_kernel(
-    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
-    const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status,
-    float bg_r, float bg_g, float bg_b, const float* __restrict__ image, const float* __restrict__ dL_dimage,
-    const float* __restrict__ T_final, const uint32_t* __restrict__ n_last, const float4* __restrict__ ckpt,
-    float4* __restrict__ rec, const uint32_t* __restrict__ order, const uint32_t* __restrict__ hist,
-    uint32_t n_items, const uint32_t* __restrict__ heavy, const uint32_t* __restrict__ heavy_count,
-    uint32_t heavy_max) {
-    __shared__ StagedBwd sb;
-    if (*status != kStatusOk) return;
+struct BwdArgs {
+    const float4* record;
+    const float2* conic;     // anisotropic family: {B, C} per record
+    const uint32_t* pidx;
+    const uint32_t* offsets;
+    const uint32_t* ranges;
+    const int32_t* status;
+    float bg_r, bg_g, bg_b;
+    const float* image;
+    const float* dL_dimage;
+    const float* T_final;
+    const uint32_t* n_last;
+    const float4* ckpt;
+    float4* rec;
+    const uint32_t* order;
+    const uint32_t* hist;
+    uint32_t n_items;
+    const uint32_t* heavy;
+    const uint32_t* heavy_count;
+    uint32_t heavy_max;
+};
+
+template <bool AN>
+__device__ __forceinline__ void bwd_ordered(StagedBwdT<AN>& sb, const RenderPack& pk, const BwdArgs& A) {
+    const float4* __restrict__ ckpt = A.ckpt;
+    const uint32_t* __restrict__ heavy = A.heavy;
+    const uint32_t* __restrict__ order = A.order;
+    const uint32_t* __restrict__ hist = A.hist;
+    const uint32_t n_items = A.n_items, heavy_max = A.heavy_max;
+    if (*A.status != kStatusOk) return;
     const uint32_t b = blockIdx.x;
     uint32_t logical, chunk = 0;
     if (ckpt) {
-        const uint32_t n_heavy = min(*heavy_count, heavy_max);
+        const uint32_t n_heavy = min(*A.heavy_count, heavy_max);
         if (b < n_heavy) {
             logical = heavy[2 * b];
             chunk = heavy[2 * b + 1];
@@ -335,8 +404,19 @@ __global__ void __launch_bounds__(256) composite_bwd_ordered_kernel(
     } else {
         logical = order[b];
     }
-    composite_bwd_tile(sb, pk, logical, chunk, record, pidx, offsets, ranges, bg_r, bg_g, bg_b, image, dL_dimage,
-                       T_final, n_last, ckpt, rec);
+    composite_bwd_tile(sb, pk, logical, chunk, A.record, A.conic, A.pidx, A.offsets, A.ranges, A.bg_r, A.bg_g, A.bg_b,
+                       A.image, A.dL_dimage, A.T_final, A.n_last, ckpt, A.rec);
+}
+
+__global__ void __launch_bounds__(256) composite_bwd_ordered_kernel(const RenderPack pk, const BwdArgs a) {
+    __shared__ StagedBwdT<false> sb;
+    bwd_ordered(sb, pk, a);
+}
+
+// The anisotropic family (eq. 5 kernels).
+__global__ void __launch_bounds__(256) aniso_bwd_ordered_kernel(const RenderPack pk, const BwdArgs a) {
+    __shared__ StagedBwdT<true> sb;
+    bwd_ordered(sb, pk, a);
 }
 
 // Gradient of each real SH basis polynomial (the forms used in the forward colour
@@ -373,6 +453,41 @@ struct GradView {
     uint32_t p_off;
     float R[9], t[3], eye[3], f, cx, cy;
 };
+
+// Colour of one view, rgb = max(0, c_0 + sum_k c_k Y_k(d)) with d = (mu - eye)/|mu - eye|:
+// adds the view's gradient (drgb, zero where the colour was clamped) to the coefficients'
+// and to the centre's (through the direction's tangential part).
+template <int DEG>
+__device__ __forceinline__ void color_backward(const float* coef, const float drgb[3], const float eye[3], float mx,
+                                               float my, float mz, float* gcol, float& gmx, float& gmy, float& gmz) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const float ex = mx - eye[0], ey = my - eye[1], ez = mz - eye[2];
+    const float inv_dist = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+    const float dxn = ex * inv_dist, dyn = ey * inv_dist, dzn = ez * inv_dist;
+    float Y[16], gx[16], gy[16], gz[16];
+    sh_eval_grad(DEG, dxn, dyn, dzn, Y, gx, gy, gz);
+    float wdx = 0.0f, wdy = 0.0f, wdz = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float raw = coef[ch];
+#pragma unroll
+        for (int k = 1; k < K; ++k) raw = fmaf(coef[3 * k + ch], Y[k], raw);
+        const float d = (raw > 0.0f) ? drgb[ch] : 0.0f;
+        gcol[ch] += d;
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            gcol[3 * k + ch] += d * Y[k];
+            const float wk = d * coef[3 * k + ch];
+            wdx = fmaf(wk, gx[k], wdx);
+            wdy = fmaf(wk, gy[k], wdy);
+            wdz = fmaf(wk, gz[k], wdz);
+        }
+    }
+    const float radial = wdx * dxn + wdy * dyn + wdz * dzn;
+    gmx += (wdx - radial * dxn) * inv_dist;
+    gmy += (wdy - radial * dyn) * inv_dist;
+    gmz += (wdz - radial * dzn) * inv_dist;
+}
 
 struct GradPack {
     int32_t nv;            // views of this scene in this launch, in view order
@@ -451,33 +566,7 @@ __global__ void __launch_bounds__(256) grad_project_kernel(const GradPack pk, co
         gmx += gv.R[0] * gpx + gv.R[3] * gpy + gv.R[6] * gpz;
         gmy += gv.R[1] * gpx + gv.R[4] * gpy + gv.R[7] * gpz;
         gmz += gv.R[2] * gpx + gv.R[5] * gpy + gv.R[8] * gpz;
-        // colour: rgb = max(0, c_0 + sum_k c_k Y_k(d)), d = (mu - eye)/|mu - eye|
-        const float ex = mx - gv.eye[0], ey = my - gv.eye[1], ez = mz - gv.eye[2];
-        const float inv_dist = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
-        const float dxn = ex * inv_dist, dyn = ey * inv_dist, dzn = ez * inv_dist;
-        float Y[16], gx[16], gy[16], gz[16];
-        sh_eval_grad(DEG, dxn, dyn, dzn, Y, gx, gy, gz);
-        float wdx = 0.0f, wdy = 0.0f, wdz = 0.0f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float raw = coef[ch];
-#pragma unroll
-            for (int k = 1; k < K; ++k) raw = fmaf(coef[3 * k + ch], Y[k], raw);
-            const float d = (raw > 0.0f) ? drgb[ch] : 0.0f;
-            gcol[ch] += d;
-#pragma unroll
-            for (int k = 1; k < K; ++k) {
-                gcol[3 * k + ch] += d * Y[k];
-                const float wk = d * coef[3 * k + ch];
-                wdx = fmaf(wk, gx[k], wdx);
-                wdy = fmaf(wk, gy[k], wdy);
-                wdz = fmaf(wk, gz[k], wdz);
-            }
-        }
-        const float radial = wdx * dxn + wdy * dyn + wdz * dzn;
-        gmx += (wdx - radial * dxn) * inv_dist;
-        gmy += (wdy - radial * dyn) * inv_dist;
-        gmz += (wdz - radial * dzn) * inv_dist;
+        color_backward<DEG>(coef, drgb, gv.eye, mx, my, mz, gcol, gmx, gmy, gmz);
     }
     if (pk.accumulate) {
         pk.g_pos[i] += gmx;
@@ -498,28 +587,265 @@ __global__ void __launch_bounds__(256) grad_project_kernel(const GradPack pk, co
     }
 }
 
+// ---- Anisotropic chain rule (eq. 5-7) ------------------------------------------------------
+struct AnisoGradPack {
+    int32_t nv;            // views of this scene in this launch, in view order
+    int32_t accumulate;    // add to the outputs (a previous launch covered earlier views)
+    const float* pos;
+    const float* rot;
+    const float* scale;
+    const float* opacity;
+    const float* color;
+    uint32_t n;
+    int32_t sh_degree;
+    float* g_pos;
+    float* g_rot;
+    float* g_scale;
+    float* g_opacity;
+    float* g_color;
+    GradView v[kMaxViews];
+};
+
+// Rotation matrix of the unit quaternion (w, x, y, z), row-major.
+__device__ __forceinline__ void quat_rot(double w, double x, double y, double z, double R[9]) {
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z);       R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);       R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);       R[7] = 2.0 * (y * z + w * x);       R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// One thread per particle of one scene. Per view: the entry records of the particle are
+// summed in emit order (FP32, fixed order), turned into the gradients of the footprint
+// centre (u, v), the conic (A, B, C), the opacity and the colour, and chained in FP64
+// through Sigma_2D = T Sigma T^T (T = J V, eq. 7; conic = Sigma_2D^-1) to the centre and,
+// accumulated over the views, to Sigma = R S S^T R^T (eq. 6), hence to the quaternion
+// (through its normalisation) and the three scales.
+template <int DEG>
+__global__ void __launch_bounds__(256) aniso_grad_project_kernel(const AnisoGradPack pk, const float4* __restrict__ rec,
+                                                                 const float4* __restrict__ record,
+                                                                 const float2* __restrict__ conic,
+                                                                 const uint32_t* __restrict__ tile_count,
+                                                                 const uint32_t* __restrict__ offsets,
+                                                                 const uint32_t* __restrict__ count_p,
+                                                                 const int32_t* __restrict__ status) {
+    if (*status != kStatusOk) return;
+    const uint32_t n_entries = *count_p;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pk.n) return;
+    const uint32_t n = pk.n;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const float mx = pk.pos[i], my = pk.pos[n + i], mz = pk.pos[2 * n + i];
+    const double qw = pk.rot[i], qx = pk.rot[n + i], qy = pk.rot[2 * n + i], qz = pk.rot[3 * n + i];
+    const double sc[3] = {(double)pk.scale[i], (double)pk.scale[n + i], (double)pk.scale[2 * n + i]};
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double hw = qw / qn, hx = qx / qn, hy = qy / qn, hz = qz / qn;
+    double Rq[9];
+    quat_rot(hw, hx, hy, hz, Rq);
+    // Sigma = R diag(s^2) R^T
+    double Sig[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc += Rq[3 * a + c] * sc[c] * sc[c] * Rq[3 * b + c];
+            Sig[3 * a + b] = acc;
+        }
+
+    float gmx = 0.0f, gmy = 0.0f, gmz = 0.0f, gop = 0.0f;
+    double GS[9];   // dL/dSigma, summed over the views
+#pragma unroll
+    for (int k = 0; k < 9; ++k) GS[k] = 0.0;
+    double gmu64[3] = {0.0, 0.0, 0.0};
+    bool any = false;
+    float gcol[3 * K];
+    float coef[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) {
+        gcol[k] = 0.0f;
+        coef[k] = pk.color[(size_t)k * n + i];
+    }
+
+    for (int vv = 0; vv < pk.nv; ++vv) {
+        const GradView& gv = pk.v[vv];
+        const uint32_t pi = gv.p_off + i;
+        const uint32_t cnt = tile_count[pi];
+        if (cnt == 0) continue;
+        const uint32_t e0 = offsets[pi];
+        if ((uint64_t)e0 + cnt > n_entries) continue;
+        any = true;
+        float S[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) S[k] = 0.0f;
+        for (uint32_t e = e0; e < e0 + cnt; ++e) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const float4 r = rec[3 * (size_t)e + q];
+                S[4 * q] += r.x;
+                S[4 * q + 1] += r.y;
+                S[4 * q + 2] += r.z;
+                S[4 * q + 3] += r.w;
+            }
+        }
+        gop += S[5];
+        const double A = (double)record[2 * (size_t)pi].z;
+        const float2 bc = conic[pi];
+        const double B = (double)bc.x, C = (double)bc.y;
+        // sums k dx, k dy, k dx^2, k dx dy, k dy^2 -> gradients of u, v and the conic
+        const double du = 2.0 * (A * S[0] + B * S[1]), dv = 2.0 * (B * S[0] + C * S[1]);
+        const double dA = -(double)S[2], dB = -2.0 * (double)S[3], dC = -(double)S[4];
+        // dL/dSigma_2D = -Ci Gc Ci, Ci = [[A, B], [B, C]], Gc = [[dA, dB/2], [dB/2, dC]]
+        const double m00 = A * dA + B * 0.5 * dB, m01 = A * 0.5 * dB + B * dC;
+        const double m10 = B * dA + C * 0.5 * dB, m11 = B * 0.5 * dB + C * dC;
+        const double G00 = -(m00 * A + m01 * B), G01 = -(m00 * B + m01 * C), G11 = -(m10 * B + m11 * C);
+        // camera-space centre and T = J V
+        double V[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) V[k] = (double)gv.R[k];
+        const double px = V[0] * mx + V[1] * my + V[2] * mz + (double)gv.t[0];
+        const double py = V[3] * mx + V[4] * my + V[5] * mz + (double)gv.t[1];
+        const double pz = V[6] * mx + V[7] * my + V[8] * mz + (double)gv.t[2];
+        const double f = (double)gv.f, iz = 1.0 / pz;
+        const double J00 = f * iz, J02 = -f * px * iz * iz, J12 = -f * py * iz * iz;
+        double T[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T[c] = J00 * V[c] + J02 * V[6 + c];
+            T[3 + c] = J00 * V[3 + c] + J12 * V[6 + c];
+        }
+        // dL/dSigma += T^T G T
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                GS[3 * a + b] += T[a] * (G00 * T[b] + G01 * T[3 + b]) + T[3 + a] * (G01 * T[b] + G11 * T[3 + b]);
+        // dL/dT = 2 G T Sigma, dL/dJ = dL/dT V^T
+        double TS[6];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                TS[3 * r + c] = T[3 * r] * Sig[c] + T[3 * r + 1] * Sig[3 + c] + T[3 * r + 2] * Sig[6 + c];
+        double GT[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            GT[c] = 2.0 * (G00 * TS[c] + G01 * TS[3 + c]);
+            GT[3 + c] = 2.0 * (G01 * TS[c] + G11 * TS[3 + c]);
+        }
+        double GJ[6];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                GJ[3 * r + c] = GT[3 * r] * V[3 * c] + GT[3 * r + 1] * V[3 * c + 1] + GT[3 * r + 2] * V[3 * c + 2];
+        // J = [[f/z, 0, -f p_x/z^2], [0, f/z, -f p_y/z^2]]; u = f p_x / z + cx, v likewise
+        const double iz2 = iz * iz;
+        double dpx = -GJ[2] * f * iz2 + du * f * iz;
+        double dpy = -GJ[5] * f * iz2 + dv * f * iz;
+        double dpz = -(GJ[0] + GJ[4]) * f * iz2 + 2.0 * f * (GJ[2] * px + GJ[5] * py) * iz2 * iz -
+                     (du * f * px + dv * f * py) * iz2;
+        gmu64[0] += V[0] * dpx + V[3] * dpy + V[6] * dpz;
+        gmu64[1] += V[1] * dpx + V[4] * dpy + V[7] * dpz;
+        gmu64[2] += V[2] * dpx + V[5] * dpy + V[8] * dpz;
+        const float drgb[3] = {S[6], S[7], S[8]};
+        color_backward<DEG>(coef, drgb, gv.eye, mx, my, mz, gcol, gmx, gmy, gmz);
+    }
+    float grot[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gsc[3] = {0.0f, 0.0f, 0.0f};
+    if (any) {
+        // Sigma = R diag(s^2) R^T: dL/dR = 2 GS R diag(s^2), dL/ds_b = 2 s_b (R^T GS R)_bb
+        double GR[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                GR[3 * a + b] = 2.0 * (GS[3 * a] * Rq[b] + GS[3 * a + 1] * Rq[3 + b] + GS[3 * a + 2] * Rq[6 + b]) *
+                                sc[b] * sc[b];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc += Rq[3 * a + b] * GS[3 * a + c] * Rq[3 * c + b];
+            gsc[b] = (float)(2.0 * sc[b] * acc);
+        }
+        // dR/d(w, x, y, z) of the rotation formula, at the unit quaternion
+        const double w = hw, x = hx, y = hy, z = hz;
+        const double dRw[9] = {0.0, -2 * z, 2 * y, 2 * z, 0.0, -2 * x, -2 * y, 2 * x, 0.0};
+        const double dRx[9] = {0.0, 2 * y, 2 * z, 2 * y, -4 * x, -2 * w, 2 * z, 2 * w, -4 * x};
+        const double dRy[9] = {-4 * y, 2 * x, 2 * w, 2 * x, 0.0, 2 * z, -2 * w, 2 * z, -4 * y};
+        const double dRz[9] = {-4 * z, -2 * w, 2 * x, 2 * w, -4 * z, 2 * y, 2 * x, 2 * y, 0.0};
+        double dq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            dq[0] += GR[k] * dRw[k];
+            dq[1] += GR[k] * dRx[k];
+            dq[2] += GR[k] * dRy[k];
+            dq[3] += GR[k] * dRz[k];
+        }
+        // through the normalisation q / |q|
+        const double radial = hw * dq[0] + hx * dq[1] + hy * dq[2] + hz * dq[3];
+        grot[0] = (float)((dq[0] - hw * radial) / qn);
+        grot[1] = (float)((dq[1] - hx * radial) / qn);
+        grot[2] = (float)((dq[2] - hy * radial) / qn);
+        grot[3] = (float)((dq[3] - hz * radial) / qn);
+        gmx += (float)gmu64[0];
+        gmy += (float)gmu64[1];
+        gmz += (float)gmu64[2];
+    }
+    if (pk.accumulate) {
+        pk.g_pos[i] += gmx;
+        pk.g_pos[n + i] += gmy;
+        pk.g_pos[2 * n + i] += gmz;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pk.g_rot[(size_t)k * n + i] += grot[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pk.g_scale[(size_t)k * n + i] += gsc[k];
+        pk.g_opacity[i] += gop;
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) pk.g_color[(size_t)k * n + i] += gcol[k];
+    } else {
+        pk.g_pos[i] = gmx;
+        pk.g_pos[n + i] = gmy;
+        pk.g_pos[2 * n + i] = gmz;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pk.g_rot[(size_t)k * n + i] = grot[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) pk.g_scale[(size_t)k * n + i] = gsc[k];
+        pk.g_opacity[i] = gop;
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) pk.g_color[(size_t)k * n + i] = gcol[k];
+    }
+}
+
 static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Workspace: gradient records (32 B per entry of capacity), the tile queue, the chunk
-// item count and the chunk items (two words each; at most capacity / kCkptChunk + tiles).
+// Workspace: gradient records (32 B per entry of capacity, 48 B for the anisotropic
+// family), the tile queue, the chunk item count and the chunk items (two words each; at
+// most capacity / kCkptChunk + tiles).
 static size_t bwd_heavy_items(uint64_t capacity, uint32_t tiles) {
     return (size_t)(capacity / kCkptChunk) + tiles + 1;
 }
 
-size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv) {
+static size_t rec_bytes(bool an) { return an ? 48 : 32; }
+
+size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv, bool an) {
     const uint32_t tiles = max_group_tiles(cams, nv);
-    return round256((size_t)capacity * 32) + round256(tile_queue_words(tiles) * 4) + 256 +
+    return round256((size_t)capacity * rec_bytes(an)) + round256(tile_queue_words(tiles) * 4) + 256 +
            bwd_heavy_items(capacity, tiles) * 8 + 256;
 }
 
-int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
-                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,
-                      const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
-                      const float* ckpt, const isogs_scene* grads, void* ws, hipStream_t stream) {
+// Reverse compositing of every view into the entry records (both families): chunks of
+// long tiles (with checkpoints), then tiles longest first. Returns the records.
+static float4* launch_composite_bwd(bool an, const int32_t* n_all, const isogs_camera* cams, int32_t nv,
+                                    const isogs_projected* proj, const float* conic, const isogs_bins* bins,
+                                    const float* bg, const float* image, const float* dL_dimage,
+                                    const float* T_final, const uint32_t* n_last, const float* ckpt, void* ws,
+                                    hipStream_t stream) {
     const uint32_t max_tiles = max_group_tiles(cams, nv);
     char* base = static_cast<char*>(ws);
     float4* rec = reinterpret_cast<float4*>(base);
-    base += round256((size_t)bins->capacity * 32);
+    base += round256((size_t)bins->capacity * rec_bytes(an));
     uint32_t* q = reinterpret_cast<uint32_t*>(base);
     base += round256(tile_queue_words(max_tiles) * 4);
     uint32_t* heavy_count = reinterpret_cast<uint32_t*>(base);
@@ -529,19 +855,13 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
     // more items than tiles; over ranges that partition the entries, at most
     // capacity / kCkptChunk more in all
     const uint32_t extra_items = ckpt ? (uint32_t)(bins->capacity / kCkptChunk) + 1u : 0u;
-    int32_t n_per_view[kMaxViews];
-    int32_t n_all[4096];
-    if (nv > 4096) return -1;
-    for (int v = 0; v < nv; ++v) n_all[v] = scenes[v].n;
-    // 1. reverse compositing: chunks of long tiles (with checkpoints), then tiles longest first
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         const int m = min(kMaxViews, nv - v0);
-        for (int j = 0; j < m; ++j) n_per_view[j] = scenes[v0 + j].n;
         RenderPack pk{};
         uint32_t blocks;
         const uint32_t tile0 = tile_base;
-        fill_render_pack(pk, cams + v0, n_per_view, 0, m, p_off, tile_base, pix_off, blocks);
+        fill_render_pack(pk, cams + v0, n_all + v0, 0, m, p_off, tile_base, pix_off, blocks);
         set_render_limits(pk, n_all, nv, bins->capacity);
         if (!blocks) continue;
         uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
@@ -550,36 +870,69 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
             hipLaunchKernelGGL(bwd_chunk_list_kernel, dim3((blocks + 255) / 256), dim3(256), 0, stream, bins->ranges,
                                tile0, blocks, pk.n_entries_cap, bins->status, heavy, heavy_count, heavy_max);
         }
-        hipLaunchKernelGGL(composite_bwd_ordered_kernel, dim3(blocks + extra_items), dim3(256), 0, stream, pk,
-                           reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->offsets, bins->ranges,
-                           bins->status, bg[0], bg[1], bg[2], image, dL_dimage, T_final, n_last,
-                           reinterpret_cast<const float4*>(ckpt), rec, order, q, blocks, heavy, heavy_count,
-                           heavy_max);
-        if (hipPeekAtLastError() != hipSuccess) return -1;
+        const BwdArgs a{reinterpret_cast<const float4*>(proj->record), reinterpret_cast<const float2*>(conic),
+                        bins->pidx, bins->offsets, bins->ranges, bins->status, bg[0], bg[1], bg[2], image, dL_dimage,
+                        T_final, n_last, reinterpret_cast<const float4*>(ckpt), rec, order, q, blocks, heavy,
+                        heavy_count, heavy_max};
+        hipLaunchKernelGGL(an ? aniso_bwd_ordered_kernel : composite_bwd_ordered_kernel, dim3(blocks + extra_items),
+                           dim3(256), 0, stream, pk, a);
+        if (hipPeekAtLastError() != hipSuccess) return nullptr;
     }
-    // 2. per scene: reduce records over its views (in view order) and chain to parameters
-    uint32_t view_off[4096];
-    if (nv > 4096) return -1;
-    {
-        uint32_t o = 0;
-        for (int v = 0; v < nv; ++v) {
-            view_off[v] = o;
-            o += (uint32_t)scenes[v].n;
-        }
-    }
+    return rec;
+}
+
+// Views grouped by scene (equal position buffers), in view order; calls fn(first view of
+// the scene, views[], count) for each scene.
+template <typename Fn>
+static void for_each_scene(const float* const* pos, int32_t nv, Fn fn) {
     bool handled[4096] = {false};
     for (int v = 0; v < nv; ++v) {
         if (handled[v]) continue;
-        const isogs_scene& sc = scenes[v];
         int pending[4096];
         int np = 0;
         for (int u = v; u < nv; ++u)
-            if (!handled[u] && scenes[u].pos == sc.pos) {
+            if (!handled[u] && pos[u] == pos[v]) {
                 handled[u] = true;
                 pending[np++] = u;
             }
+        fn(v, pending, np);
+    }
+}
+
+static void fill_grad_view(GradView& g, const isogs_camera& c, uint32_t p_off) {
+    g.p_off = p_off;
+    for (int k = 0; k < 9; ++k) g.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) g.t[k] = c.t[k], g.eye[k] = c.eye[k];
+    g.f = c.f;
+    g.cx = c.cx;
+    g.cy = c.cy;
+}
+
+int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
+                      const isogs_projected* proj, const isogs_bins* bins, const float* bg,
+                      const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
+                      const float* ckpt, const isogs_scene* grads, void* ws, hipStream_t stream) {
+    if (nv > 4096) return -1;
+    int32_t n_all[4096];
+    uint32_t view_off[4096];
+    const float* pos[4096];
+    uint32_t o = 0;
+    for (int v = 0; v < nv; ++v) {
+        n_all[v] = scenes[v].n;
+        view_off[v] = o;
+        o += (uint32_t)scenes[v].n;
+        pos[v] = scenes[v].pos;
+    }
+    // 1. reverse compositing
+    const float4* rec = launch_composite_bwd(false, n_all, cams, nv, proj, nullptr, bins, bg, image, dL_dimage, T_final,
+                                             n_last, ckpt, ws, stream);
+    if (!rec) return -1;
+    // 2. per scene: reduce records over its views (in view order) and chain to parameters
+    int rc = 0;
+    for_each_scene(pos, nv, [&](int v, const int* pending, int np) {
+        const isogs_scene& sc = scenes[v];
         const isogs_scene& gs = grads[v];
-        for (int b0 = 0; b0 < np; b0 += kMaxViews) {
+        for (int b0 = 0; b0 < np && !rc; b0 += kMaxViews) {
             GradPack gp{};
             gp.nv = min(kMaxViews, np - b0);
             gp.accumulate = b0 > 0;
@@ -593,31 +946,78 @@ int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32
             gp.g_scale = const_cast<float*>(gs.scale);
             gp.g_opacity = const_cast<float*>(gs.opacity);
             gp.g_color = const_cast<float*>(gs.color);
-            for (int j = 0; j < gp.nv; ++j) {
-                const int u = pending[b0 + j];
-                const isogs_camera& c = cams[u];
-                GradView& g = gp.v[j];
-                g.p_off = view_off[u];
-                for (int k = 0; k < 9; ++k) g.R[k] = c.R[k];
-                for (int k = 0; k < 3; ++k) g.t[k] = c.t[k], g.eye[k] = c.eye[k];
-                g.f = c.f;
-                g.cx = c.cx;
-                g.cy = c.cy;
-            }
+            for (int j = 0; j < gp.nv; ++j) fill_grad_view(gp.v[j], cams[pending[b0 + j]], view_off[pending[b0 + j]]);
             if (sc.n > 0) {
                 const dim3 grid((sc.n + 255) / 256);
-                const float4* r = rec;
                 switch (sc.sh_degree) {
-                    case 0: hipLaunchKernelGGL(grad_project_kernel<0>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
-                    case 1: hipLaunchKernelGGL(grad_project_kernel<1>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
-                    case 2: hipLaunchKernelGGL(grad_project_kernel<2>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
-                    default: hipLaunchKernelGGL(grad_project_kernel<3>, grid, dim3(256), 0, stream, gp, r, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                    case 0: hipLaunchKernelGGL(grad_project_kernel<0>, grid, dim3(256), 0, stream, gp, rec, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                    case 1: hipLaunchKernelGGL(grad_project_kernel<1>, grid, dim3(256), 0, stream, gp, rec, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                    case 2: hipLaunchKernelGGL(grad_project_kernel<2>, grid, dim3(256), 0, stream, gp, rec, proj->tile_count, bins->offsets, bins->count, bins->status); break;
+                    default: hipLaunchKernelGGL(grad_project_kernel<3>, grid, dim3(256), 0, stream, gp, rec, proj->tile_count, bins->offsets, bins->count, bins->status); break;
                 }
             }
-            if (hipPeekAtLastError() != hipSuccess) return -1;
+            if (hipPeekAtLastError() != hipSuccess) rc = -1;
         }
+    });
+    return rc;
+}
+
+int launch_aniso_render_bwd(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t nv,
+                            const isogs_aniso_projected* proj, const isogs_bins* bins, const float* bg,
+                            const float* image, const float* dL_dimage, const float* T_final,
+                            const uint32_t* n_last, const float* ckpt, const isogs_aniso_scene* grads, void* ws,
+                            hipStream_t stream) {
+    if (nv > 4096) return -1;
+    int32_t n_all[4096];
+    uint32_t view_off[4096];
+    const float* pos[4096];
+    uint32_t o = 0;
+    for (int v = 0; v < nv; ++v) {
+        n_all[v] = scenes[v].n;
+        view_off[v] = o;
+        o += (uint32_t)scenes[v].n;
+        pos[v] = scenes[v].pos;
     }
-    return 0;
+    const float4* rec = launch_composite_bwd(true, n_all, cams, nv, &proj->fp, proj->conic, bins, bg, image, dL_dimage,
+                                             T_final, n_last, ckpt, ws, stream);
+    if (!rec) return -1;
+    int rc = 0;
+    for_each_scene(pos, nv, [&](int v, const int* pending, int np) {
+        const isogs_aniso_scene& sc = scenes[v];
+        const isogs_aniso_scene& gs = grads[v];
+        for (int b0 = 0; b0 < np && !rc; b0 += kMaxViews) {
+            AnisoGradPack gp{};
+            gp.nv = min(kMaxViews, np - b0);
+            gp.accumulate = b0 > 0;
+            gp.pos = sc.pos;
+            gp.rot = sc.rot;
+            gp.scale = sc.scale;
+            gp.opacity = sc.opacity;
+            gp.color = sc.color;
+            gp.n = (uint32_t)sc.n;
+            gp.sh_degree = sc.sh_degree;
+            gp.g_pos = const_cast<float*>(gs.pos);
+            gp.g_rot = const_cast<float*>(gs.rot);
+            gp.g_scale = const_cast<float*>(gs.scale);
+            gp.g_opacity = const_cast<float*>(gs.opacity);
+            gp.g_color = const_cast<float*>(gs.color);
+            for (int j = 0; j < gp.nv; ++j) fill_grad_view(gp.v[j], cams[pending[b0 + j]], view_off[pending[b0 + j]]);
+            if (sc.n > 0) {
+                const dim3 grid((sc.n + 255) / 256);
+                const float4* r = reinterpret_cast<const float4*>(proj->fp.record);
+                const float2* k = reinterpret_cast<const float2*>(proj->conic);
+                const uint32_t* tc = proj->fp.tile_count;
+                switch (sc.sh_degree) {
+                    case 0: hipLaunchKernelGGL(aniso_grad_project_kernel<0>, grid, dim3(256), 0, stream, gp, rec, r, k, tc, bins->offsets, bins->count, bins->status); break;
+                    case 1: hipLaunchKernelGGL(aniso_grad_project_kernel<1>, grid, dim3(256), 0, stream, gp, rec, r, k, tc, bins->offsets, bins->count, bins->status); break;
+                    case 2: hipLaunchKernelGGL(aniso_grad_project_kernel<2>, grid, dim3(256), 0, stream, gp, rec, r, k, tc, bins->offsets, bins->count, bins->status); break;
+                    default: hipLaunchKernelGGL(aniso_grad_project_kernel<3>, grid, dim3(256), 0, stream, gp, rec, r, k, tc, bins->offsets, bins->count, bins->status); break;
+                }
+            }
+            if (hipPeekAtLastError() != hipSuccess) rc = -1;
+        }
+    });
+    return rc;
 }
 
 }  // namespace isogs

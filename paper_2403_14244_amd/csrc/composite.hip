@@ -10,11 +10,12 @@ namespace isogs {
 // gives away, T - alpha T; `lastj` keeps the staged slot (carried in c.w) of the last entry
 // used in the current batch (slots only increase along a list). TERM: the pixel stops
 // after the entry that takes T below kTMin.
-template <bool TERM>
-__device__ __forceinline__ void composite_entry(const float4& f, const float4& c, float px, float py, float& T,
-                                                float& cr, float& cg, float& cb, uint32_t& lastj, bool& done) {
+template <bool TERM, bool AN>
+__device__ __forceinline__ void composite_entry(const float4& f, const float4& c, const float2& k, float px, float py,
+                                                float& T, float& cr, float& cg, float& cb, uint32_t& lastj,
+                                                bool& done) {
     float g;
-    float a = entry_alpha(px - f.x, py - f.y, f.z, f.w, g);
+    float a = staged_alpha<AN>(px - f.x, py - f.y, f, k, g);
     const bool use = (a >= kAlphaMin) && !done;
     a = use ? a : 0.0f;
     const float wgt = a * T;
@@ -26,12 +27,14 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
     if (TERM) done = done || (T < kTMin);
 }
 
-// The four entries of one list step: offsets -> staged records.
+// The four entries of one list step: offsets -> staged records (k: conics, anisotropic).
 struct Step4 {
     float4 f[4], c[4];
+    float2 k[4];
 };
 
-__device__ __forceinline__ void load_step(const StagedSub& sb, const uint4& o, Step4& st) {
+template <bool AN>
+__device__ __forceinline__ void load_step(const StagedSubT<AN>& sb, const uint4& o, Step4& st) {
     st.f[0] = staged_fp(sb, o.x);
     st.f[1] = staged_fp(sb, o.y);
     st.f[2] = staged_fp(sb, o.z);
@@ -40,6 +43,10 @@ __device__ __forceinline__ void load_step(const StagedSub& sb, const uint4& o, S
     st.c[1] = staged_col(sb, o.y);
     st.c[2] = staged_col(sb, o.z);
     st.c[3] = staged_col(sb, o.w);
+    st.k[0] = staged_cn(sb, o.x);
+    st.k[1] = staged_cn(sb, o.y);
+    st.k[2] = staged_cn(sb, o.z);
+    st.k[3] = staged_cn(sb, o.w);
 }
 
 // A lane's pixel in a tile, and the pixel's compositing state.
@@ -92,9 +99,9 @@ __device__ __forceinline__ TilePixel tile_pixel(const RenderPack& pk, uint32_t l
 // list words of step k + 8 are issued while step k is composited, so that the walk does not
 // wait on dependent round trips.
 // Contains __syncthreads.
-template <bool TERM, bool PIPE, bool PL = PIPE>
-__device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack& pk, const TilePixel& p,
-                                                const float4* __restrict__ record,
+template <bool TERM, bool PIPE, bool PL, bool AN>
+__device__ __forceinline__ void composite_range(StagedSubT<AN>& sb, const RenderPack& pk, const TilePixel& p,
+                                                const float4* __restrict__ record, const float2* __restrict__ conic,
                                                 const uint32_t* __restrict__ pidx, uint32_t lo, uint32_t hi,
                                                 PixelState& s, float4* __restrict__ ckpt) {
     const uint32_t t = threadIdx.x;
@@ -106,7 +113,7 @@ __device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack&
     EntryLoad cur{}, nxt{};
     uint32_t g_next = 0xFFFFFFFFu;
     if (PIPE) {
-        cur = load_entry(record, batch_pidx(pidx, b0, batch_len(b0)), pk.n_particles);
+        cur = load_entry<AN>(record, batch_pidx(pidx, b0, batch_len(b0)), pk.n_particles, conic);
         g_next = batch_pidx(pidx, b0 + kBatch, batch_len(b0 + kBatch));
     }
     for (; b0 < end; b0 += kBatch) {
@@ -116,11 +123,11 @@ __device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack&
                 make_float4(s.T, s.cr, s.cg, s.cb);
         uint32_t steps;
         if (PIPE) {
-            nxt = load_entry(record, g_next, pk.n_particles);
+            nxt = load_entry<AN>(record, g_next, pk.n_particles, conic);
             g_next = batch_pidx(pidx, b0 + 2 * kBatch, batch_len(b0 + 2 * kBatch));
             steps = stage_loaded(sb, cur, p.tx * kTile, p.ty * kTile, p.w_lim, p.h_lim);
         } else {
-            steps = stage_batch_sub(sb, record, pidx, pk.n_particles, b0, batch_len(b0), p.tx * kTile,
+            steps = stage_batch_sub(sb, record, conic, pidx, pk.n_particles, b0, batch_len(b0), p.tx * kTile,
                                     p.ty * kTile, p.w_lim, p.h_lim);
         }
         const uint32_t pos0 = b0 - p.start + 1;   // 1-based list position of staged slot 0
@@ -129,7 +136,8 @@ __device__ __forceinline__ void composite_range(StagedSub& sb, const RenderPack&
         auto composite_step = [&](const Step4& st) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                composite_entry<TERM>(st.f[e], st.c[e], p.px, p.py, s.T, s.cr, s.cg, s.cb, lastj, s.done);
+                composite_entry<TERM, AN>(st.f[e], st.c[e], st.k[e], p.px, p.py, s.T, s.cr, s.cg, s.cb, lastj,
+                                          s.done);
         };
         if (!PL) {
             for (uint32_t k = 0; k < steps; k += 4) {
@@ -200,16 +208,16 @@ __device__ __forceinline__ void write_overflow_tile(const RenderPack& pk, uint32
 }
 
 // Composites one whole tile (logical index within the launch). Contains __syncthreads.
-template <bool PIPE, bool PL = PIPE>
-__device__ __forceinline__ void composite_tile(StagedSub& sb, const RenderPack& pk, uint32_t logical,
-                                               const float4* __restrict__ record,
+template <bool PIPE, bool PL, bool AN>
+__device__ __forceinline__ void composite_tile(StagedSubT<AN>& sb, const RenderPack& pk, uint32_t logical,
+                                               const float4* __restrict__ record, const float2* __restrict__ conic,
                                                const uint32_t* __restrict__ pidx,
                                                const uint32_t* __restrict__ ranges, float bg_r, float bg_g,
                                                float bg_b, float* __restrict__ image, float* __restrict__ T_final,
                                                uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
     const TilePixel p = tile_pixel(pk, logical, ranges);
     PixelState s{1.0f, 0.0f, 0.0f, 0.0f, 0u, !p.inside};
-    composite_range<true, PIPE, PL>(sb, pk, p, record, pidx, 0, p.len, s, ckpt);
+    composite_range<true, PIPE, PL, AN>(sb, pk, p, record, conic, pidx, 0, p.len, s, ckpt);
     write_pixel(p, s, bg_r, bg_g, bg_b, image, T_final, n_last);
 }
 
@@ -229,7 +237,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompa
     __shared__ StagedSub sb;
     const uint32_t logical = xcd_swizzle(blockIdx.x, gridDim.x);
     if (*status != kStatusOk) return write_overflow_tile(pk, logical, image, T_final, n_last);
-    composite_tile<false>(sb, pk, logical, record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
+    composite_tile<false, false, false>(sb, pk, logical, record, nullptr, pidx, ranges, bg_r, bg_g, bg_b, image,
+                                        T_final, n_last, ckpt);
 }
 
 // ---- Wide walk for the longest tiles of small launches ------------------------------------
@@ -243,9 +252,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompa
 // the result is the sequential one up to rounding (products and sums are associated per
 // step), at four times the lanes per pixel.
 
-struct StagedQuad {
+template <bool AN>
+struct StagedQuadT {
     float4 fp[kBatch + 1];
     float4 col[kBatch + 1];        // {r, g, b, slot bits}
+    float2 cn[AN ? kBatch + 1 : 1];
     uint32_t list[4][kBatch + 4];  // byte offsets, per sub-block of the quadrant
     uint32_t cnt[4][4];            // [loader wave][sub-block]
     uint32_t len[4];
@@ -254,13 +265,15 @@ struct StagedQuad {
 // Stages a batch for quadrant `quad` of the tile: records of all entries, lists of the
 // quadrant's four sub-blocks only. Returns the padded length of the calling wave's list
 // (wave w walks sub-block 4 quad + w). Contains __syncthreads.
-__device__ __forceinline__ uint32_t stage_quad(StagedQuad& sq, const EntryLoad& e, int quad, int tile_x0,
+template <bool AN>
+__device__ __forceinline__ uint32_t stage_quad(StagedQuadT<AN>& sq, const EntryLoad& e, int quad, int tile_x0,
                                                int tile_y0, float w_lim, float h_lim) {
     const uint32_t t = threadIdx.x, w = t >> 6;
     uint32_t mask = 0;
     if (e.ok) {
         const float4 f = e.f, c = e.c;
-        sq.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
+        sq.fp[t] = staged_kernel<AN>(f);
+        if (AN) sq.cn[t] = staged_conic(e.k);
         sq.col[t] = make_float4(c.x, c.y, c.z, __uint_as_float(t));
         const float r2 = c.w * c.w;
 #pragma unroll
@@ -269,6 +282,7 @@ __device__ __forceinline__ uint32_t stage_quad(StagedQuad& sq, const EntryLoad& 
     }
     if (t == 0) {
         sq.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
+        if (AN) sq.cn[kDummy] = make_float2(0.0f, 0.0f);
         sq.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float((uint32_t)kDummy));
     }
     uint64_t bal[4];
@@ -300,8 +314,10 @@ __device__ __forceinline__ uint32_t stage_quad(StagedQuad& sq, const EntryLoad& 
 }
 
 // Composites quadrant `quad` of one tile with the wide walk. Contains __syncthreads.
-__device__ __forceinline__ void composite_quadrant(StagedQuad& sq, const RenderPack& pk, uint32_t logical, int quad,
-                                                   const float4* __restrict__ record,
+template <bool AN>
+__device__ __forceinline__ void composite_quadrant(StagedQuadT<AN>& sq, const RenderPack& pk, uint32_t logical,
+                                                   int quad, const float4* __restrict__ record,
+                                                   const float2* __restrict__ conic,
                                                    const uint32_t* __restrict__ pidx,
                                                    const uint32_t* __restrict__ ranges, float bg_r, float bg_g,
                                                    float bg_b, float* __restrict__ image,
@@ -330,13 +346,13 @@ __device__ __forceinline__ void composite_quadrant(StagedQuad& sq, const RenderP
     bool done = !inside;
     auto batch_len = [end](uint32_t b) { return b < end ? min((uint32_t)kBatch, end - b) : 0u; };
     uint32_t b0 = start;
-    EntryLoad cur = load_entry(record, batch_pidx(pidx, b0, batch_len(b0)), pk.n_particles);
+    EntryLoad cur = load_entry<AN>(record, batch_pidx(pidx, b0, batch_len(b0)), pk.n_particles, conic);
     uint32_t g_next = batch_pidx(pidx, b0 + kBatch, batch_len(b0 + kBatch));
     for (; b0 < end; b0 += kBatch) {
         if (__syncthreads_and(done)) break;
         if (ckpt && chunked_list(len) && b0 > start && (b0 - start) % kCkptChunk == 0 && e_idx == 0)
             ckpt[(size_t)ckpt_slot(start, (b0 - start) / kCkptChunk) * 256 + t_px] = make_float4(T, cr, cg, cb);
-        const EntryLoad nxt = load_entry(record, g_next, pk.n_particles);
+        const EntryLoad nxt = load_entry<AN>(record, g_next, pk.n_particles, conic);
         g_next = batch_pidx(pidx, b0 + 2 * kBatch, batch_len(b0 + 2 * kBatch));
         const uint32_t n = stage_quad(sq, cur, quad, tx * kTile, ty * kTile, w_lim, h_lim);
         lastp1 = 0;
@@ -344,8 +360,10 @@ __device__ __forceinline__ void composite_quadrant(StagedQuad& sq, const RenderP
             const uint32_t off = sq.list[w][s0 + e_idx];
             const float4 f = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sq.fp) + off);
             const float4 c = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sq.col) + off);
+            float2 kc = make_float2(0.0f, 0.0f);
+            if (AN) kc = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(sq.cn) + (off >> 1));
             float g;
-            float a = entry_alpha(px - f.x, py - f.y, f.z, f.w, g);
+            float a = staged_alpha<AN>(px - f.x, py - f.y, f, kc, g);
             const bool use = a >= kAlphaMin;
             a = use ? a : 0.0f;
             const float om = 1.0f - a;
@@ -412,27 +430,56 @@ constexpr int kWideMinLog2 = 11;
 // tiles the launch is throughput-bound and the compact one is faster; with few, it is bound
 // by its longest tiles and the fully pipelined one is.
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompactWavesPerSimd)))
-composite_fwd_ordered_kernel(const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
-                             const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r,
-                             float bg_g, float bg_b, float* __restrict__ image, float* __restrict__ T_final,
-                             uint32_t* __restrict__ n_last, float4* __restrict__ ckpt,
-                             const uint32_t* __restrict__ order) {
-    __shared__ StagedSub sb;
-    if (*status != kStatusOk) return write_overflow_tile(pk, order[blockIdx.x], image, T_final, n_last);
-    composite_tile<false>(sb, pk, order[blockIdx.x], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last,
-                          ckpt);
+// Arguments of the longest-first compositing kernels (both kernel families).
+struct OrderedArgs {
+    const float4* record;
+    const float2* conic;      // anisotropic family: {B, C} per record
+    const uint32_t* pidx;
+    const uint32_t* ranges;
+    const int32_t* status;
+    float bg_r, bg_g, bg_b;
+    float* image;
+    float* T_final;
+    uint32_t* n_last;
+    float4* ckpt;
+    const uint32_t* order;
+    const uint32_t* hist;
+    uint32_t wide_slots;
+};
+
+template <bool PIPE, bool AN>
+__device__ __forceinline__ void ordered_tile(StagedSubT<AN>& sb, const RenderPack& pk, const OrderedArgs& a) {
+    if (*a.status != kStatusOk) return write_overflow_tile(pk, a.order[blockIdx.x], a.image, a.T_final, a.n_last);
+    composite_tile<PIPE, PIPE, AN>(sb, pk, a.order[blockIdx.x], a.record, a.conic, a.pidx, a.ranges, a.bg_r, a.bg_g,
+                                   a.bg_b, a.image, a.T_final, a.n_last, a.ckpt);
 }
 
-__global__ void __launch_bounds__(256) composite_fwd_ordered_pipe_kernel(
-    const RenderPack pk, const float4* __restrict__ record, const uint32_t* __restrict__ pidx,
-    const uint32_t* __restrict__ ranges, const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
-    float* __restrict__ image, float* __restrict__ T_final, uint32_t* __restrict__ n_last,
-    float4* __restrict__ ckpt, const uint32_t* __restrict__ order) {
-    __shared__ StagedSub sb;
-    if (*status != kStatusOk) return write_overflow_tile(pk, order[blockIdx.x], image, T_final, n_last);
-    composite_tile<true>(sb, pk, order[blockIdx.x], record, pidx, ranges, bg_r, bg_g, bg_b, image, T_final, n_last,
-                         ckpt);
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompactWavesPerSimd)))
+composite_fwd_ordered_kernel(const RenderPack pk, const OrderedArgs a) {
+    __shared__ StagedSubT<false> sb;
+    ordered_tile<false>(sb, pk, a);
+}
+
+__global__ void __launch_bounds__(256) composite_fwd_ordered_pipe_kernel(const RenderPack pk, const OrderedArgs a) {
+    __shared__ StagedSubT<false> sb;
+    ordered_tile<true>(sb, pk, a);
+}
+
+// The anisotropic family (eq. 5 kernels): the same walks with the conic staged beside each
+// record. Its larger staging (27.5 KB) fits five workgroups per CU, so the compact walk
+// gets the registers of five waves per SIMD.
+constexpr int kAnisoCompactWavesPerSimd = 5;
+constexpr int kAnisoWideWavesPerSimd = 4;
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAnisoCompactWavesPerSimd)))
+aniso_fwd_ordered_kernel(const RenderPack pk, const OrderedArgs a) {
+    __shared__ StagedSubT<true> sb;
+    ordered_tile<false>(sb, pk, a);
+}
+
+__global__ void __launch_bounds__(256) aniso_fwd_ordered_pipe_kernel(const RenderPack pk, const OrderedArgs a) {
+    __shared__ StagedSubT<true> sb;
+    ordered_tile<true>(sb, pk, a);
 }
 
 // Launches of at most this many tiles use the pipelined walk (measured crossover on the
@@ -553,40 +600,50 @@ int resident_blocks(const void* kernel, int threads) {
 // wide_slots bounds their number, and a workgroup past it leaves at once) with the wide
 // walk, the others the remaining tiles of the queue with the walk that prefetches the next
 // batch.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPrefetchWavesPerSimd)))
-composite_fwd_ordered_wide_kernel(const RenderPack pk, const float4* __restrict__ record,
-                                  const uint32_t* __restrict__ pidx, const uint32_t* __restrict__ ranges,
-                                  const int32_t* __restrict__ status, float bg_r, float bg_g, float bg_b,
-                                  float* __restrict__ image, float* __restrict__ T_final,
-                                  uint32_t* __restrict__ n_last, float4* __restrict__ ckpt,
-                                  const uint32_t* __restrict__ order, const uint32_t* __restrict__ hist,
-                                  uint32_t wide_slots) {
-    static_assert(sizeof(StagedQuad) <= sizeof(StagedSub), "one LDS buffer serves both walks");
-    __shared__ __align__(16) unsigned char smem[sizeof(StagedSub)];
-    if (*status != kStatusOk) {
+template <bool AN>
+__device__ __forceinline__ void ordered_wide(unsigned char* smem, const RenderPack& pk, const OrderedArgs& a) {
+    static_assert(sizeof(StagedQuadT<AN>) <= sizeof(StagedSubT<AN>), "one LDS buffer serves both walks");
+    const uint32_t wide_slots = a.wide_slots;
+    if (*a.status != kStatusOk) {
         // every tile is one of the remaining ones then (no list is long)
-        if (blockIdx.x >= 4 * wide_slots) write_overflow_tile(pk, order[blockIdx.x - 4 * wide_slots], image, T_final, n_last);
+        if (blockIdx.x >= 4 * wide_slots)
+            write_overflow_tile(pk, a.order[blockIdx.x - 4 * wide_slots], a.image, a.T_final, a.n_last);
         return;
     }
     uint32_t n_wide = 0;
-    for (int c = kWideMinLog2 + 1; c < kBuckets; ++c) n_wide += hist[c];
+    for (int c = kWideMinLog2 + 1; c < kBuckets; ++c) n_wide += a.hist[c];
     n_wide = min(n_wide, wide_slots);
     const uint32_t b = blockIdx.x;
     if (b < 4 * wide_slots) {
         if ((b >> 2) >= n_wide) return;
-        composite_quadrant(*reinterpret_cast<StagedQuad*>(smem), pk, order[b >> 2], (int)(b & 3u), record, pidx,
-                           ranges, bg_r, bg_g, bg_b, image, T_final, n_last, ckpt);
+        composite_quadrant(*reinterpret_cast<StagedQuadT<AN>*>(smem), pk, a.order[b >> 2], (int)(b & 3u), a.record,
+                           a.conic, a.pidx, a.ranges, a.bg_r, a.bg_g, a.bg_b, a.image, a.T_final, a.n_last, a.ckpt);
     } else {
         const uint32_t j = b - 4 * wide_slots;
         if (j < n_wide) return;
-        composite_tile<true, false>(*reinterpret_cast<StagedSub*>(smem), pk, order[j], record, pidx, ranges, bg_r,
-                                    bg_g, bg_b, image, T_final, n_last, ckpt);
+        composite_tile<true, false, AN>(*reinterpret_cast<StagedSubT<AN>*>(smem), pk, a.order[j], a.record, a.conic,
+                                        a.pidx, a.ranges, a.bg_r, a.bg_g, a.bg_b, a.image, a.T_final, a.n_last,
+                                        a.ckpt);
     }
 }
 
-int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
-                              const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
-                              uint32_t* n_last, float* ckpt, uint32_t flags, void* ws, hipStream_t stream) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPrefetchWavesPerSimd)))
+composite_fwd_ordered_wide_kernel(const RenderPack pk, const OrderedArgs a) {
+    __shared__ __align__(16) unsigned char smem[sizeof(StagedSubT<false>)];
+    ordered_wide<false>(smem, pk, a);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAnisoWideWavesPerSimd)))
+aniso_fwd_ordered_wide_kernel(const RenderPack pk, const OrderedArgs a) {
+    __shared__ __align__(16) unsigned char smem[sizeof(StagedSubT<true>)];
+    ordered_wide<true>(smem, pk, a);
+}
+
+int launch_render_fwd_ordered(const isogs_projected* proj, const float* conic, const int32_t* n_per_view,
+                              const isogs_bins* bins, const isogs_camera* cams, int32_t nv, const float* bg,
+                              float* image, float* T_final, uint32_t* n_last, float* ckpt, uint32_t flags, void* ws,
+                              hipStream_t stream) {
+    const bool an = conic != nullptr;
     uint32_t* q = static_cast<uint32_t*>(ws);
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
@@ -597,22 +654,20 @@ int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_
         set_render_limits(pk, n_per_view, nv, bins->capacity);
         if (!blocks) continue;
         const uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
+        OrderedArgs a{reinterpret_cast<const float4*>(proj->record), reinterpret_cast<const float2*>(conic),
+                      bins->pidx, bins->ranges, bins->status, bg[0], bg[1], bg[2], image, T_final, n_last,
+                      reinterpret_cast<float4*>(ckpt), order, q, 0u};
         if (flags & ISOGS_FWD_WIDE) {
             // a long tile holds at least 2^kWideMinLog2 of the group's entries
-            const uint32_t wide_slots =
-                (uint32_t)std::min<uint64_t>(blocks, (uint64_t)pk.n_entries_cap / (1u << kWideMinLog2) + 1);
-            hipLaunchKernelGGL(composite_fwd_ordered_wide_kernel, dim3(4 * wide_slots + blocks), dim3(256), 0, stream,
-                               pk, reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges,
-                               bins->status, bg[0], bg[1], bg[2], image, T_final, n_last,
-                               reinterpret_cast<float4*>(ckpt), order, q, wide_slots);
+            a.wide_slots = (uint32_t)std::min<uint64_t>(blocks, (uint64_t)pk.n_entries_cap / (1u << kWideMinLog2) + 1);
+            hipLaunchKernelGGL(an ? aniso_fwd_ordered_wide_kernel : composite_fwd_ordered_wide_kernel,
+                               dim3(4 * a.wide_slots + blocks), dim3(256), 0, stream, pk, a);
         } else if (blocks <= kPipeTileLimit) {
-            hipLaunchKernelGGL(composite_fwd_ordered_pipe_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                               reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
-                               bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order);
+            hipLaunchKernelGGL(an ? aniso_fwd_ordered_pipe_kernel : composite_fwd_ordered_pipe_kernel, dim3(blocks),
+                               dim3(256), 0, stream, pk, a);
         } else {
-            hipLaunchKernelGGL(composite_fwd_ordered_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                               reinterpret_cast<const float4*>(proj->record), bins->pidx, bins->ranges, bins->status,
-                               bg[0], bg[1], bg[2], image, T_final, n_last, reinterpret_cast<float4*>(ckpt), order);
+            hipLaunchKernelGGL(an ? aniso_fwd_ordered_kernel : composite_fwd_ordered_kernel, dim3(blocks), dim3(256), 0,
+                               stream, pk, a);
         }
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }

@@ -44,16 +44,29 @@ uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0,
 // Workgroups of `threads` threads of `kernel` resident on the whole GPU at once.
 int resident_blocks(const void* kernel, int threads);
 
-size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv);
+// an: the anisotropic family (48-byte entry records instead of 32)
+size_t render_bwd_ws(uint64_t capacity, const isogs_camera* cams, int32_t nv, bool an);
 
-int launch_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
-                              const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
-                              uint32_t* n_last, float* ckpt, uint32_t flags, void* ws, hipStream_t stream);
+// conic: NULL for the isotropic family; the {B, C} array of anisotropic footprints.
+int launch_render_fwd_ordered(const isogs_projected* proj, const float* conic, const int32_t* n_per_view,
+                              const isogs_bins* bins, const isogs_camera* cams, int32_t nv, const float* bg,
+                              float* image, float* T_final, uint32_t* n_last, float* ckpt, uint32_t flags, void* ws,
+                              hipStream_t stream);
 
 int launch_render_bwd(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv,
                       const isogs_projected* proj, const isogs_bins* bins, const float* bg,
                       const float* image, const float* dL_dimage, const float* T_final, const uint32_t* n_last,
                       const float* ckpt, const isogs_scene* grads, void* ws, hipStream_t stream);
+
+// The anisotropic family (eq. 5-7): projection to conic footprints, and the backward
+// (the forward is launch_render_fwd_ordered with the conic array).
+int launch_aniso_project(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t nv,
+                         const isogs_aniso_projected* out, hipStream_t stream);
+int launch_aniso_render_bwd(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t nv,
+                            const isogs_aniso_projected* proj, const isogs_bins* bins, const float* bg,
+                            const float* image, const float* dL_dimage, const float* T_final,
+                            const uint32_t* n_last, const float* ckpt, const isogs_aniso_scene* grads, void* ws,
+                            hipStream_t stream);
 
 // The 2D kernel-sum representation (no compositing) on the same footprints and bins.
 BinSortPlan plan_field2d_bin(int32_t K, int32_t width, int32_t height, uint64_t capacity);

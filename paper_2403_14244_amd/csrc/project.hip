@@ -198,4 +198,199 @@ int launch_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t 
     return 0;
 }
 
+// ---- Anisotropic footprints (eq. 5-7) ------------------------------------------------------
+
+struct AnisoProjPack {
+    const float* pos;
+    const float* rot;
+    const float* scale;
+    const float* opacity;
+    const float* color;
+    uint32_t n;
+    int32_t nv;
+    ProjCam c[kMaxViews];
+};
+
+// One thread per particle, every view of the launch. Sigma = R diag(s^2) R^T (eq. 6) is
+// formed once per particle; per view, Sigma_2D = T Sigma T^T with T = J V (eq. 7), its
+// inverse (the conic), the larger eigenvalue (the binning radius) - all in FP64, the
+// stored footprint rounded once to FP32.
+template <int DEG>
+__global__ void __launch_bounds__(256) aniso_project_kernel(const AnisoProjPack pk, float4* __restrict__ record,
+                                                            float2* __restrict__ conic, float* __restrict__ depth,
+                                                            uint32_t* __restrict__ tile_count) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pk.n) return;
+    const uint32_t n = pk.n;
+    const float mx = pk.pos[i], my = pk.pos[n + i], mz = pk.pos[2 * n + i];
+    const float q0 = pk.rot[i], q1 = pk.rot[n + i], q2 = pk.rot[2 * n + i], q3 = pk.rot[3 * n + i];
+    const float s0 = pk.scale[i], s1 = pk.scale[n + i], s2 = pk.scale[2 * n + i];
+    const float opa = pk.opacity[i];
+    float coef[3 * K];
+    bool finite_in = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(q0) && isfinite(q1) && isfinite(q2) &&
+                     isfinite(q3) && isfinite(s0) && isfinite(s1) && isfinite(s2) && isfinite(opa);
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) {
+        coef[k] = pk.color[(size_t)k * n + i];
+        finite_in = finite_in && isfinite(coef[k]);
+    }
+    const double qw = q0, qx = q1, qy = q2, qz = q3;
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const bool param_ok = finite_in && s0 > 0.0f && s1 > 0.0f && s2 > 0.0f && qn > 0.0 &&
+                          (double)opa >= 1.0 / 255.0;
+    const double root = param_ok ? sqrt(log(255.0 * (double)opa)) : 0.0;
+    // Sigma (symmetric): S00 S01 S02 S11 S12 S22
+    double Sg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (param_ok) {
+        const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+        const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                             2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                             2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+        const double d[3] = {(double)s0 * s0, (double)s1 * s1, (double)s2 * s2};
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b)
+                Sg[k++] = R[3 * a] * d[0] * R[3 * b] + R[3 * a + 1] * d[1] * R[3 * b + 1] + R[3 * a + 2] * d[2] * R[3 * b + 2];
+    }
+
+    for (int vi = 0; vi < pk.nv; ++vi) {
+        const ProjCam& pv = pk.c[vi];
+        const uint32_t o = pv.p_off + i;
+        double V[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) V[k] = (double)pv.R[k];
+        const double px = V[0] * mx + V[1] * my + V[2] * mz + (double)pv.t[0];
+        const double py = V[3] * mx + V[4] * my + V[5] * mz + (double)pv.t[1];
+        const double pz = V[6] * mx + V[7] * my + V[8] * mz + (double)pv.t[2];
+        const double f = (double)pv.f;
+        const double u64 = f * px / pz + (double)pv.cx;
+        const double v64 = f * py / pz + (double)pv.cy;
+        // T = J V, J = [[f/z, 0, -f p_x/z^2], [0, f/z, -f p_y/z^2]]
+        const double j0 = f / pz, j2 = -f * px / (pz * pz), j5 = -f * py / (pz * pz);
+        double T0[3], T1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T0[c] = j0 * V[c] + j2 * V[6 + c];
+            T1[c] = j0 * V[3 + c] + j5 * V[6 + c];
+        }
+        // Sigma_2D = [[a, b], [b, c]] = T Sigma T^T
+        double ST0[3], ST1[3];
+        ST0[0] = Sg[0] * T0[0] + Sg[1] * T0[1] + Sg[2] * T0[2];
+        ST0[1] = Sg[1] * T0[0] + Sg[3] * T0[1] + Sg[4] * T0[2];
+        ST0[2] = Sg[2] * T0[0] + Sg[4] * T0[1] + Sg[5] * T0[2];
+        ST1[0] = Sg[0] * T1[0] + Sg[1] * T1[1] + Sg[2] * T1[2];
+        ST1[1] = Sg[1] * T1[0] + Sg[3] * T1[1] + Sg[4] * T1[2];
+        ST1[2] = Sg[2] * T1[0] + Sg[4] * T1[1] + Sg[5] * T1[2];
+        const double a = T0[0] * ST0[0] + T0[1] * ST0[1] + T0[2] * ST0[2];
+        const double b = T0[0] * ST1[0] + T0[1] * ST1[1] + T0[2] * ST1[2];
+        const double c = T1[0] * ST1[0] + T1[1] * ST1[1] + T1[2] * ST1[2];
+        const double det = a * c - b * b;
+        const double lam = 0.5 * (a + c) + sqrt(0.25 * (a - c) * (a - c) + b * b);
+        const float u = (float)u64, v = (float)v64;
+        const float A = (float)(c / det), B = (float)(-b / det), C = (float)(a / det);
+        const float r = (float)(sqrt(lam) * root * (1.0 + 0x1p-10) + 0x1p-6);
+        const bool vis = param_ok && pz > (double)pv.near_z && isfinite(u) && isfinite(v) && isfinite(det) &&
+                         det > 0.0 && isfinite(A) && isfinite(B) && isfinite(C) && A >= 0x1p-126f &&
+                         C >= 0x1p-126f && isfinite(r);
+        float4 fp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float4 cr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float2 bc = make_float2(0.0f, 0.0f);
+        float z32 = 1.0f;
+        uint32_t cnt = 0;
+        if (vis) {
+            const float ex = mx - pv.eye[0], ey = my - pv.eye[1], ez = mz - pv.eye[2];
+            const float inv = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+            float Y[16];
+            sh_eval(DEG, ex * inv, ey * inv, ez * inv, Y);
+            float rgb[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = coef[ch];
+#pragma unroll
+                for (int k = 1; k < K; ++k) acc = fmaf(coef[3 * k + ch], Y[k], acc);
+                rgb[ch] = fmaxf(acc, 0.0f);
+            }
+            z32 = (float)pz;
+            fp = make_float4(u, v, A, opa);
+            cr = make_float4(rgb[0], rgb[1], rgb[2], r);
+            bc = make_float2(B, C);
+            int tx0, tx1, ty0, ty1;
+            const int TX = (pv.width + kTile - 1) / kTile, TY = (pv.height + kTile - 1) / kTile;
+            tile_box(u, v, r, TX, TY, tx0, tx1, ty0, ty1);
+            const float r2 = r * r;
+            const float w_lim = (float)pv.width - 0.5f, h_lim = (float)pv.height - 0.5f;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) cnt += tile_member(u, v, r2, tx, ty, w_lim, h_lim) ? 1u : 0u;
+        }
+        record[2 * (size_t)o] = fp;
+        record[2 * (size_t)o + 1] = cr;
+        conic[o] = bc;
+        depth[o] = z32;
+        tile_count[o] = cnt;
+    }
+}
+
+static void fill_proj_cam(ProjCam& c, const isogs_camera& cam, uint32_t p_off) {
+    for (int k = 0; k < 9; ++k) c.R[k] = cam.R[k];
+    for (int k = 0; k < 3; ++k) c.t[k] = cam.t[k], c.eye[k] = cam.eye[k];
+    c.f = cam.f;
+    c.cx = cam.cx;
+    c.cy = cam.cy;
+    c.near_z = cam.near_z;
+    c.width = cam.width;
+    c.height = cam.height;
+    c.p_off = p_off;
+}
+
+int launch_aniso_project(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t nv,
+                         const isogs_aniso_projected* out, hipStream_t stream) {
+    uint32_t off[4096];
+    if (nv > 4096) return -1;
+    uint32_t p = 0;
+    for (int v = 0; v < nv; ++v) {
+        off[v] = p;
+        p += (uint32_t)scenes[v].n;
+    }
+    bool done[4096] = {false};
+    for (int v = 0; v < nv; ++v) {
+        if (done[v]) continue;
+        const isogs_aniso_scene& sc = scenes[v];
+        AnisoProjPack pk{};
+        pk.pos = sc.pos;
+        pk.rot = sc.rot;
+        pk.scale = sc.scale;
+        pk.opacity = sc.opacity;
+        pk.color = sc.color;
+        pk.n = (uint32_t)sc.n;
+        auto flush = [&]() -> int {
+            if (pk.nv == 0 || pk.n == 0) return 0;
+            const dim3 grid((pk.n + 255) / 256);
+            float4* rec = reinterpret_cast<float4*>(out->fp.record);
+            float2* cn = reinterpret_cast<float2*>(out->conic);
+            switch (sc.sh_degree) {
+                case 0: hipLaunchKernelGGL(aniso_project_kernel<0>, grid, dim3(256), 0, stream, pk, rec, cn, out->fp.depth, out->fp.tile_count); break;
+                case 1: hipLaunchKernelGGL(aniso_project_kernel<1>, grid, dim3(256), 0, stream, pk, rec, cn, out->fp.depth, out->fp.tile_count); break;
+                case 2: hipLaunchKernelGGL(aniso_project_kernel<2>, grid, dim3(256), 0, stream, pk, rec, cn, out->fp.depth, out->fp.tile_count); break;
+                default: hipLaunchKernelGGL(aniso_project_kernel<3>, grid, dim3(256), 0, stream, pk, rec, cn, out->fp.depth, out->fp.tile_count); break;
+            }
+            pk.nv = 0;
+            return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+        };
+        for (int u = v; u < nv; ++u) {
+            const isogs_aniso_scene& su = scenes[u];
+            if (done[u] || su.pos != sc.pos || su.rot != sc.rot || su.scale != sc.scale || su.opacity != sc.opacity ||
+                su.color != sc.color || su.n != sc.n || su.sh_degree != sc.sh_degree)
+                continue;
+            done[u] = true;
+            fill_proj_cam(pk.c[pk.nv++], cams[u], off[u]);
+            if (pk.nv == kMaxViews && flush()) return -1;
+        }
+        if (flush()) return -1;
+    }
+    return 0;
+}
+
 }  // namespace isogs

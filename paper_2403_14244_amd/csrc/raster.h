@@ -76,19 +76,51 @@ __device__ __forceinline__ bool sub_block_touched(float u, float v, float r2, in
 
 constexpr uint32_t kSlotBytes = 16;   // one staged float4
 
-struct StagedSub {
-    float4 fp[kBatch + 1];      // {u, v, q = log2(e)/s^2, log2(o)}
-    float4 col[kBatch + 1];     // {r, g, b, slot bits}
+// The walks serve two kernel families, chosen by the template flag AN: the isotropic
+// kernel of eq. 8 (a circle, one scalar 1/s^2 per entry) and the anisotropic kernel of
+// eq. 5 (an ellipse: the conic A, B, C of the screen covariance of eq. 7). Staged per entry:
+//   isotropic    fp {u, v, q = log2(e)/s^2, log2(o)}
+//   anisotropic  fp {u, v, nA = -A log2(e), log2(o)}, cn {nB2 = -2 B log2(e), nC = -C log2(e)}
+// and col {r, g, b, slot bits}. Both families share the footprint record's layout for
+// what binning reads (centre, radius), so they share the bin sort.
+template <bool AN>
+struct StagedSubT {
+    float4 fp[kBatch + 1];
+    float4 col[kBatch + 1];
+    float2 cn[AN ? kBatch + 1 : 1];
     uint32_t list[16][kBatch + 4];   // byte offsets (16 x staged slot) into fp and col
     uint32_t cnt[4][16];        // [loader wave][sub-block]
     uint32_t len[16];           // padded list lengths (multiples of 4)
 };
+using StagedSub = StagedSubT<false>;
 
-// One staged entry as loaded from global memory by its thread.
+// One staged entry as loaded from global memory by its thread (k: the conic's B, C).
 struct EntryLoad {
     bool ok;
     float4 f, c;
+    float2 k;
 };
+
+// Staged form of an entry's kernel parameters (see StagedSubT).
+template <bool AN>
+__device__ __forceinline__ float4 staged_kernel(const float4& f) {
+    return make_float4(f.x, f.y, (AN ? -f.z : f.z) * kLog2e, __builtin_amdgcn_logf(f.w));
+}
+__device__ __forceinline__ float2 staged_conic(const float2& k) {
+    return make_float2(-2.0f * k.x * kLog2e, -k.y * kLog2e);
+}
+
+// alpha of a staged entry at pixel offset (dx, dy): the isotropic kernel (entry_alpha) or
+// the anisotropic one, min(0.99, o exp(-(A dx^2 + 2 B dx dy + C dy^2))) evaluated as
+// exp2(log2(o) + dx (nA dx + nB2 dy) + nC dy^2). `g` returns the value before the clamp.
+template <bool AN>
+__device__ __forceinline__ float staged_alpha(float dx, float dy, const float4& f, const float2& k, float& g) {
+    if (!AN) return entry_alpha(dx, dy, f.z, f.w, g);
+    const float t = fmaf(k.x, dy, f.z * dx);
+    const float s = fmaf(k.y * dy, dy, f.w);
+    g = __builtin_amdgcn_exp2f(fmaf(dx, t, s));
+    return fminf(kAlphaMax, g);
+}
 
 // Particle index of this thread's entry of the batch at `first` (n_in_batch entries), or
 // none past the end.
@@ -97,13 +129,15 @@ __device__ __forceinline__ uint32_t batch_pidx(const uint32_t* __restrict__ pidx
     return threadIdx.x < n_in_batch ? pidx[first + threadIdx.x] : 0xFFFFFFFFu;
 }
 
+template <bool AN = false>
 __device__ __forceinline__ EntryLoad load_entry(const float4* __restrict__ record, uint32_t g,
-                                                uint32_t n_particles) {
-    EntryLoad e{false, make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+                                                uint32_t n_particles, const float2* __restrict__ conic = nullptr) {
+    EntryLoad e{false, make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f), make_float2(0.f, 0.f)};
     if (g < n_particles) {
         e.ok = true;
         e.f = record[2 * (size_t)g];
         e.c = record[2 * (size_t)g + 1];
+        if (AN) e.k = conic[g];
     }
     return e;
 }
@@ -111,13 +145,15 @@ __device__ __forceinline__ EntryLoad load_entry(const float4* __restrict__ recor
 // Stages the loaded entries of a batch (one per thread) and builds the 16 sub-block lists.
 // Returns the number of list steps of the calling wave (the longest of its four rows'
 // padded lists). Contains __syncthreads.
-__device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad& e, int tile_x0, int tile_y0,
+template <bool AN>
+__device__ __forceinline__ uint32_t stage_loaded(StagedSubT<AN>& sb, const EntryLoad& e, int tile_x0, int tile_y0,
                                                  float w_lim, float h_lim) {
     const uint32_t t = threadIdx.x, w = t >> 6;
     uint32_t mask = 0;
     if (e.ok) {
         const float4 f = e.f, c = e.c;
-        sb.fp[t] = make_float4(f.x, f.y, f.z * kLog2e, __builtin_amdgcn_logf(f.w));
+        sb.fp[t] = staged_kernel<AN>(f);
+        if (AN) sb.cn[t] = staged_conic(e.k);
         sb.col[t] = make_float4(c.x, c.y, c.z, __uint_as_float(t));   // w: the slot itself
         const float r2 = c.w * c.w;
 #pragma unroll
@@ -126,6 +162,7 @@ __device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad&
     }
     if (t == 0) {
         sb.fp[kDummy] = make_float4(0.0f, 0.0f, 0.0f, -__builtin_inff());
+        if (AN) sb.cn[kDummy] = make_float2(0.0f, 0.0f);
         sb.col[kDummy] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float((uint32_t)kDummy));
     }
     uint64_t bal[16];
@@ -161,26 +198,36 @@ __device__ __forceinline__ uint32_t stage_loaded(StagedSub& sb, const EntryLoad&
 }
 
 // Loads and stages entries [first, first + n_in_batch). Contains __syncthreads.
-__device__ __forceinline__ uint32_t stage_batch_sub(StagedSub& sb, const float4* __restrict__ record,
+template <bool AN>
+__device__ __forceinline__ uint32_t stage_batch_sub(StagedSubT<AN>& sb, const float4* __restrict__ record,
+                                                    const float2* __restrict__ conic,
                                                     const uint32_t* __restrict__ pidx, uint32_t n_particles,
                                                     uint32_t first, uint32_t n_in_batch, int tile_x0, int tile_y0,
                                                     float w_lim, float h_lim) {
-    return stage_loaded(sb, load_entry(record, batch_pidx(pidx, first, n_in_batch), n_particles), tile_x0,
-                        tile_y0, w_lim, h_lim);
+    return stage_loaded(sb, load_entry<AN>(record, batch_pidx(pidx, first, n_in_batch), n_particles, conic),
+                        tile_x0, tile_y0, w_lim, h_lim);
 }
 
 // Byte offsets of four consecutive entries of this lane's sub-block list (padded length
 // `len`) from step k; a step at or past the end reads the four dummies that follow the list.
-__device__ __forceinline__ uint4 list4_sub(const StagedSub& sb, uint32_t sbk, uint32_t k, uint32_t len) {
+template <bool AN>
+__device__ __forceinline__ uint4 list4_sub(const StagedSubT<AN>& sb, uint32_t sbk, uint32_t k, uint32_t len) {
     return *reinterpret_cast<const uint4*>(&sb.list[sbk][min(k, len)]);
 }
 
-// Staged record and colour of the entry at byte offset `off`.
-__device__ __forceinline__ float4 staged_fp(const StagedSub& sb, uint32_t off) {
+// Staged record, colour and conic of the entry at byte offset `off` (16 bytes per slot).
+template <bool AN>
+__device__ __forceinline__ float4 staged_fp(const StagedSubT<AN>& sb, uint32_t off) {
     return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sb.fp) + off);
 }
-__device__ __forceinline__ float4 staged_col(const StagedSub& sb, uint32_t off) {
+template <bool AN>
+__device__ __forceinline__ float4 staged_col(const StagedSubT<AN>& sb, uint32_t off) {
     return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(sb.col) + off);
+}
+template <bool AN>
+__device__ __forceinline__ float2 staged_cn(const StagedSubT<AN>& sb, uint32_t off) {
+    if (!AN) return make_float2(0.0f, 0.0f);
+    return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(sb.cn) + (off >> 1));
 }
 
 struct RenderPack {

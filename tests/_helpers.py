@@ -167,3 +167,60 @@ def split_flat(flat, cams, per_pixel_channels=3):
                    else a.reshape(c.height, c.width))
         off += n
     return out
+
+
+# ---- anisotropic family ---------------------------------------------------------------------
+
+def oracle_f32_aniso_footprints(projs, cams):
+    """Per-view FP32 anisotropic footprints from the oracle's FP64 projection: the binning
+    inputs of ``aniso64.f32_views_aniso`` plus the conic, opacity and colour."""
+    out = []
+    for pr, vw in zip(projs, O.aniso64.f32_views_aniso(projs, cams)):
+        vis = pr.visible
+        conic = np.array([np.where(vis, x, 0.0) for x in pr.conic]).astype(np.float32)
+        out.append(dict(u=vw["u"], v=vw["v"], z=vw["z"], r=vw["r"], conic=conic,
+                        o=np.where(vis, pr.opacity, 0.0).astype(np.float32),
+                        rgb=np.where(vis[None, :], pr.rgb, 0.0).astype(np.float32),
+                        width=vw["width"], height=vw["height"]))
+    return out
+
+
+def upload_aniso_footprints(views, bins, device="cuda"):
+    """Packs per-view FP32 anisotropic footprints (+ the oracle's tile counts) into device
+    AnisoFootprints: record {u, v, A, o, r, g, b, radius} and conic {B, C}."""
+    import torch
+    from paper_2403_14244_amd import AnisoFootprints, Footprints
+    rec = np.concatenate([np.stack([v["u"], v["v"], v["conic"][0], v["o"], v["rgb"][0], v["rgb"][1], v["rgb"][2],
+                                    v["r"]], 1) for v in views]).astype(np.float32)
+    bc = np.concatenate([np.stack([v["conic"][1], v["conic"][2]], 1) for v in views]).astype(np.float32)
+    z = np.concatenate([v["z"] for v in views]).astype(np.float32)
+    tc = bins.tile_count.astype(np.int64).astype(np.int32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return AnisoFootprints(Footprints(t(rec), t(z), t(tc)), t(bc))
+
+
+def oracle_aniso_render_f32(views, bins, bg=(0.0, 0.0, 0.0), q_err=None):
+    """The oracle's tiled anisotropic render of FP32 footprints (upcast to FP64), per view."""
+    res, off = [], 0
+    for vi, v in enumerate(views):
+        f64 = lambda a: np.asarray(a, dtype=np.float64)
+        res.append(O.aniso64.render_aniso_tiled(f64(v["u"]), f64(v["v"]), f64(v["conic"]), f64(v["o"]),
+                                                f64(v["rgb"]), bins, vi, v["width"], v["height"], bg,
+                                                pidx_offset=off, q_err=q_err))
+        off += v["u"].shape[0]
+    return res
+
+
+def aniso_outcomes(u, v, conic, o, rgb, bins, view_id, width, bg=(0.0, 0.0, 0.0), pidx_offset=0, q_err=None,
+                   pos_err=None, z32=None):
+    """outcomes(y, x) -> (valid results, resolved) of one pixel over its tile's list, for the
+    anisotropic kernel (``aniso64.pixel_outcomes_aniso``)."""
+    TX = (int(width) + 15) // 16
+    base = int(bins.tile_base[view_id])
+
+    def fn(y, x):
+        a, b = bins.ranges[base + (y // 16) * TX + x // 16]
+        seq = bins.pidx[a:b].astype(np.int64) - pidx_offset
+        return O.aniso64.pixel_outcomes_aniso(x + 0.5, y + 0.5, seq, u, v, conic, o, rgb, bg, q_err=q_err,
+                                              pos_err=pos_err, z32=z32)
+    return fn

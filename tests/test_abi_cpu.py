@@ -60,7 +60,8 @@ def test_struct_layouts_match_header(tmp_path):
     assert A.Bins.capacity.offset == 32
     # sizes and field offsets as a C compiler lays the header's structs out
     structs = {"isogs_scene": A.Scene, "isogs_camera": A.Camera, "isogs_projected": A.Projected,
-               "isogs_bins": A.Bins, "isogs_field2d": A.Field2D}
+               "isogs_bins": A.Bins, "isogs_field2d": A.Field2D, "isogs_aniso_scene": A.AnisoScene,
+               "isogs_aniso_projected": A.AnisoProjected}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, ct in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -299,3 +300,44 @@ def test_header_states_the_static_scratch_size():
     text = open(HEADER).read()
     m = re.search(r"#define ISOGS_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
     assert m and (int(m.group(1)) << int(m.group(2))) == A.ISOGS_STATIC_SCRATCH_BYTES
+
+
+def test_aniso_invalid_arguments_are_rejected_without_a_device():
+    """The anisotropic calls validate like the isotropic ones, before any launch."""
+    A = _abi()
+    L = A.lib()
+    cams = A.camera_array([_cam()])
+    sc = (A.AnisoScene * 1)()
+    sc[0].n = 4
+    sc[0].sh_degree = 0
+    proj = A.AnisoProjected()
+    assert L.isogs_aniso_project(sc, cams, 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    assert b"NULL" in L.isogs_last_error()
+    sc[0].sh_degree = 5
+    assert L.isogs_aniso_project(sc, cams, 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    assert b"sh_degree" in L.isogs_last_error()
+    # buffers given, but the conic misaligned
+    sc[0].sh_degree = 0
+    for f in ("pos", "rot", "scale", "opacity", "color"):
+        setattr(sc[0], f, 4096)
+    proj.fp.record, proj.fp.depth, proj.fp.tile_count, proj.conic = 4096, 4096, 4096, 4100
+    assert L.isogs_aniso_project(sc, cams, 1, ctypes.byref(proj), None) == A.ISOGS_ERR_INVALID
+    assert b"conic" in L.isogs_last_error()
+    # workspace queries answer without a device; the backward's records are 48 bytes
+    bins = A.Bins()
+    bins.capacity = 1000
+    need_iso, need_an = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    npv = A.int_array([4])
+    bg = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    assert L.isogs_aniso_render_fwd(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, None, None, None, None,
+                                    0, None, ctypes.byref(need_an), None) == A.ISOGS_OK
+    assert need_an.value > 0
+    iso = (A.Scene * 1)()
+    iso[0].n = 4
+    assert L.isogs_render_bwd(iso, cams, 1, None, ctypes.byref(bins), bg, None, None, None, None, None, iso, None,
+                              ctypes.byref(need_iso), None) == A.ISOGS_OK
+    assert L.isogs_aniso_render_bwd(sc, cams, 1, ctypes.byref(proj), ctypes.byref(bins), bg, None, None, None, None,
+                                    None, sc, None, ctypes.byref(need_an), None) == A.ISOGS_OK
+    assert need_an.value - need_iso.value >= 1000 * 16
+    assert L.isogs_aniso_render_fwd(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, None, None, None, None,
+                                    2, None, ctypes.byref(need_an), None) == A.ISOGS_OK   # query ignores flags
