@@ -10,3 +10,5 @@ from . import field2d64  # noqa: F401  (2D kernel-sum representation of Section 
 from . import ssim64  # noqa: F401  (SSIM term of the loss)
 from . import tree2d64  # noqa: F401  (quadtree initialisation, prune and split of 2D particles)
 from . import aniso64  # noqa: F401  (anisotropic variant: eq. 5-7)
+from . import octree64  # noqa: F401  (octree initialisation of 3D particles, merge of 2D particles)
+from . import field2d_aniso64  # noqa: F401  (2D kernel sum with anisotropic kernels)

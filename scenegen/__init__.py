@@ -26,7 +26,7 @@ __all__ = [
     "Scene", "Camera", "look_at_camera", "orbit_camera", "uniform_cube_scene",
     "mixture_scene", "stress_scene", "jitter_scene", "subset_scene",
     "WORKLOADS", "workload_scene", "workload_cameras", "random_projected",
-    "field2d_target", "field2d_init", "AnisoScene", "aniso_from_iso", "aniso_mixture_scene",
+    "field2d_target", "field2d_init", "AnisoScene", "aniso_from_iso", "aniso_mixture_scene", "point_cloud",
 ]
 
 
@@ -155,6 +155,29 @@ def _mixture_points(rng, n):
     ps = s_centres[s_assign] + s_radii[s_assign, None] * nrm
     pos = np.concatenate([pc, ps], axis=0)
     return pos[rng.permutation(n)]
+
+
+def point_cloud(n=200_000, seed=30, extent=1.0, n_clusters=24):
+    """A coloured point cloud (the stand-in for the points a 3D reconstruction starts
+    from): clusters of isotropic normal points (centres U[-extent/2, extent/2]^3, std
+    U[0.03, 0.25] extent) plus 25% uniform in the cube [-extent, extent]^3; every cluster
+    has a base colour U[0,1]^3, its points that colour plus N(0, 0.04) clipped to [0, 1],
+    the uniform points U[0,1]^3. Returns (points [3, n], colours [3, n]), FP32."""
+    rng = np.random.default_rng(seed)
+    n_u = n // 4
+    n_c = n - n_u
+    centres = rng.uniform(-0.5 * extent, 0.5 * extent, size=(n_clusters, 3))
+    stds = rng.uniform(0.03, 0.25, size=n_clusters) * extent
+    base = rng.uniform(0.0, 1.0, size=(n_clusters, 3))
+    assign = rng.integers(0, n_clusters, size=n_c)
+    pc = centres[assign] + rng.normal(size=(n_c, 3)) * stds[assign, None]
+    cc = np.clip(base[assign] + rng.normal(0.0, 0.04, size=(n_c, 3)), 0.0, 1.0)
+    pu = rng.uniform(-extent, extent, size=(n_u, 3))
+    cu = rng.uniform(0.0, 1.0, size=(n_u, 3))
+    order = rng.permutation(n)
+    pos = np.concatenate([pc, pu])[order]
+    col = np.concatenate([cc, cu])[order]
+    return np.ascontiguousarray(pos.T.astype(np.float32)), np.ascontiguousarray(col.T.astype(np.float32))
 
 
 def mixture_scene(n=1_000_000, seed=0, log_scale_mean=math.log(0.005), log_scale_std=0.5,
