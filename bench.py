@@ -27,8 +27,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# the forward's four streams and the serving slots' streams each on a hardware queue of
+# their own (HIP's default pool of 4 per process would make some share one and run in
+# turn); set before the HIP runtime starts
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed instructions: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz
+# published FP32 vector peak (packed FMA), and without packed instructions (this build emits
+# none): 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3
 VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
@@ -57,17 +64,28 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-inflight", type=int, default=2,
                     help="batches in flight at once (one HIP stream each)")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="warm-up requests before the measured trace")
+    ap.add_argument("--serve-sweep", default="1000,3000",
+                    help="extra arrival rates (req/s), 500 requests each, for the batch size and latency at load")
+    ap.add_argument("--only-serving", action="store_true", help="run only the serving measurement")
     ap.add_argument("--only-field2d", action="store_true",
                     help="run only the 2D fit (2000 kernels, 512x512) and print its JSON object")
     ap.add_argument("--no-extra-workloads", action="store_true",
                     help="skip the 500k 4x720p training step and the 6M 4K stress fwd+bwd")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: one copy kernel of known size, then one forward call")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the solo per-stage measurement (the phase the roofline figures come from), "
+                         "for a kernel trace of exactly those launches")
     return ap.parse_args()
 
 
 COPY_BYTES = 512 << 20
 FLOPS_PER_PAIR = 9   # dx, dy, dx^2 + dy^2 (3), times -log2(e)/s^2, exp, times o, clamp
+# reverse walk, per (pixel, entry) pair: alpha as above (9), T before the entry (2), its weight
+# (1), dC/dalpha per channel and its dot with dL/dC (14), light from behind (6), colour
+# gradient (3), kernel and opacity gradients (9)
+BWD_FLOPS_PER_PAIR = 44
 
 
 def composite_sources_digest():
@@ -112,6 +130,77 @@ def walk_pairs(T, n_last, ranges, cams, tile_base0=0):
     return total
 
 
+def bwd_pairs(n_last):
+    """(pixel, entry) pairs of the reverse walk: every pixel walks back from its last
+    contributing entry."""
+    return int(n_last.long().sum().item())
+
+
+def solo_stages(R, gs, batches, dL_seed=7):
+    """Every stage of the benchmark call alone on one stream, with HIP events on that
+    stream around each library call: projection, bin sort, longest-first compositing (with
+    checkpoints) and the backward pass (random dL/dimage), per batch of views. Returns the
+    mean time per call of each stage (ms), and the work of the compositing walks."""
+    import torch
+    st = {k: [] for k in ("project", "bin_sort", "render_fwd", "render_bwd")}
+    fwd_pairs = bwd_p = entries = 0
+    gen = torch.Generator(device=gs.pos.device)
+    gen.manual_seed(dL_seed)
+    for bc in batches:
+        npv = [gs.n] * len(bc)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        fp = R.project([gs] * len(bc), bc)
+        ev[1].record()
+        bins = R.bin_sort(fp, npv, bc, check=False)
+        ev[2].record()
+        ck = R.checkpoint_buffer(bins)
+        img, T, n_last = R.render_fwd_ordered(fp, npv, bins, bc, ckpt=ck)
+        ev[3].record()
+        dL = torch.randn(img.shape, device=img.device, generator=gen)
+        e_b0, e_b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e_b0.record()
+        R.render_bwd([gs] * len(bc), bc, fp, bins, (0.0, 0.0, 0.0), dL, T, n_last, image=img, ckpt=ck)
+        e_b1.record()
+        torch.cuda.synchronize()
+        bins.verify()
+        st["project"].append(ev[0].elapsed_time(ev[1]))
+        st["bin_sort"].append(ev[1].elapsed_time(ev[2]))
+        st["render_fwd"].append(ev[2].elapsed_time(ev[3]))
+        st["render_bwd"].append(e_b0.elapsed_time(e_b1))
+        fwd_pairs += walk_pairs(T, n_last, bins.ranges, bc)
+        bwd_p += bwd_pairs(n_last)
+        entries += bins.n_entries()
+        del ck, dL, img, T, n_last, bins, fp
+    nb = len(batches)
+    return ({k: float(np.mean(v)) for k, v in st.items()}, fwd_pairs / nb, bwd_p / nb, entries / nb)
+
+
+def stage_rooflines(ms, fwd_pairs, bwd_pairs_, entries, n, views, pixels, tiles, sh_degree):
+    """Per-stage figures of one call from its solo time: algorithmic work (bytes or flops per
+    unit as stated in the design notes), achieved rate and its fraction of the published
+    peaks (HBM 8 TB/s; FP32 157.3 TFLOP/s, 78.6 without packed instructions)."""
+    K = (sh_degree + 1) ** 2
+    out = {}
+    proj_b = n * (20 + 12 * K) + n * views * 40
+    sort_b = entries * 24
+    fwd_b = entries * 36 + pixels * 20 + tiles * 8
+    for name, alg_b in (("project", proj_b), ("bin_sort", sort_b)):
+        gbs = alg_b / (ms[name] * 1e-3) / 1e9
+        out[name] = {"us": round(ms[name] * 1e3, 1), "bound": "hbm", "alg_bytes": int(alg_b),
+                     "alg_gbs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    for name, pairs, fpp, alg_b in (("render_fwd", fwd_pairs, FLOPS_PER_PAIR, fwd_b),
+                                    ("render_bwd", bwd_pairs_, BWD_FLOPS_PER_PAIR, None)):
+        tf = pairs * fpp / (ms[name] * 1e-3) / 1e12
+        out[name] = {"us": round(ms[name] * 1e3, 1), "bound": "alu", "pairs": int(pairs), "flops_per_pair": fpp,
+                     "tflops": round(tf, 3), "frac_fp32_peak": round(tf / FP32_PEAK_TFLOPS, 4),
+                     "frac_nonpacked": round(tf / VALU_PEAK_TFLOPS, 4)}
+        if alg_b:
+            out[name]["alg_bytes"] = int(alg_b)
+            out[name]["alg_gbs"] = round(alg_b / (ms[name] * 1e-3) / 1e9, 1)
+    return out
+
+
 def poisson_trace(n, rate_hz, scene_names, resolutions, seed=4, radius=4.0, start_id=0):
     """Serving requests: exponential inter-arrival times (mean 1/rate), a uniformly chosen
     resident scene, an orbit camera at a uniform angle and a uniformly chosen resolution."""
@@ -139,21 +228,67 @@ def serving_benchmark(args, dev):
     scenes = {k: P.GaussianScene.from_host(S.mixture_scene(n, seed=sd), dev) for k, (n, sd) in sizes.items()}
     res = [(512, 512), (1280, 720), (1920, 1080)]
     n = max(1, int(args.serve_seconds * args.serve_rate))
-    warm = poisson_trace(100, args.serve_rate, list(scenes), res, seed=3)
-    reqs = poisson_trace(n, args.serve_rate, list(scenes), res, seed=4, start_id=1000)
-    ex = GpuExecutor(scenes, dev, n_streams=args.serve_inflight)
-    ex.calibrate(warm + reqs)
+    warm = poisson_trace(args.serve_warmup, args.serve_rate, list(scenes), res, seed=3)
+    reqs = poisson_trace(n, args.serve_rate, list(scenes), res, seed=4, start_id=1_000_000)
+    rates = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
+    sweeps = {r: poisson_trace(500, r, list(scenes), res, seed=5 + k, start_id=2_000_000 + 1000 * k)
+              for k, r in enumerate(rates)}
+    ex = GpuExecutor(scenes, dev, n_streams=args.serve_inflight, record_spans=True)
+    ex.calibrate(warm + reqs + [q for v in sweeps.values() for q in v])
     Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=args.serve_inflight).run(warm)
     torch.cuda.synchronize()
+    ex.spans.clear()
     srv = Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=args.serve_inflight)
     st = srv.run(reqs)
+    ov = ex.device_overlap()
     sel = [r.latency * 1e3 for r in reqs if r.scene == "mix1m" and r.cam.width == 1920]
     st["p99_ms_1080p_1m"] = float(np.percentile(sel, 99)) if sel else None
     st["rate_hz"] = args.serve_rate
+    st["warmup_requests"] = len(warm)
     st["scenes"] = {k: v[0] for k, v in sizes.items()}
     st["capacity_overflows"] = ex.overflows
+    st["device_overlap"] = {"overlapping_batch_pairs": ov["overlapping_pairs"],
+                            "ms_two_batches_on_device": round(ov["overlap_ms"], 2),
+                            "ms_device_busy": round(ov["busy_ms"], 2)}
     st.pop("pool_bytes", None)
+    sweep_out = {}
+    for r, trace in sweeps.items():
+        ex.spans.clear()
+        s2 = Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=args.serve_inflight).run(trace)
+        o2 = ex.device_overlap()
+        sweep_out[f"{int(r)}_req_per_s"] = {"requests": s2["requests"], "mean_batch": round(s2["mean_batch"], 3),
+                                            "p50_ms": round(s2["p50_ms"], 3), "p99_ms": round(s2["p99_ms"], 3),
+                                            "mpix_per_s": round(s2["mpix_per_s"], 1),
+                                            "overlapping_batch_pairs": o2["overlapping_pairs"]}
+    st["rate_sweep"] = sweep_out
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+
+
+def cube_workload(dev, iters=200):
+    """The small forward workload: 10,000 particles uniform in the cube, one 256x256 view from
+    distance 3 (RGB). Forward Mpix/s over `iters` renders, and each stage's solo time."""
+    import torch
+    import scenegen as S
+    import paper_2403_14244_amd as P
+    scene = S.workload_scene("cube10k_256")
+    cams = S.workload_cameras("cube10k_256")
+    gs = P.GaussianScene.from_host(scene, dev)
+    R = P.Rasterizer(dev, headroom=1.1)
+    for _ in range(5):
+        R.render([gs], cams, check=False)
+    R.render([gs], cams, check=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        R.render([gs], cams, check=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / iters
+    solo_stages(R, gs, [cams])
+    ms, fwd_pairs, bwd_p, entries = solo_stages(R, gs, [cams] * 20)
+    return {"workload": "cube10k_256", "gaussians": 10_000, "width": 256, "height": 256,
+            "fwd_mpix_per_s": round(256 * 256 / dt / 1e6, 1), "fwd_us_per_render": round(dt * 1e6, 1),
+            "entries": int(entries), "walk_pairs": int(fwd_pairs),
+            "stage_us_solo": {k: round(v * 1e3, 1) for k, v in ms.items()}}
 
 
 def training_workload(dev, iters=20):
@@ -547,6 +682,30 @@ def cpu_baseline(scene, cam, budget_s):
     return out
 
 
+def roofline_phase(R, gs, batches, args):
+    """Solo stage times and the roofline of the dominant kernel (compositing)."""
+    solo_stages(R, gs, batches[:1])       # warm: workspaces sized, code loaded
+    ms, fwd_pairs, bwd_p, entries = solo_stages(R, gs, batches)
+    B = len(batches[0])
+    pixels = B * args.width * args.height
+    tiles = B * ((args.width + 15) // 16) * ((args.height + 15) // 16)
+    stages = stage_rooflines(ms, fwd_pairs, bwd_p, entries, gs.n, B, pixels, tiles, gs.sh_degree)
+    fwd = stages["render_fwd"]
+    comp_bytes = entries * 36 + pixels * 20 + tiles * 8
+    achieved = fwd_pairs * FLOPS_PER_PAIR / (ms["render_fwd"] * 1e-3) / 1e12
+    roof = dict(kernel="composite_fwd_ordered_kernel", bound="alu", achieved=achieved, peak=FP32_PEAK_TFLOPS,
+                unit="TFLOP/s", frac=achieved / FP32_PEAK_TFLOPS, traffic=measured_traffic(comp_bytes),
+                frac_nonpacked=achieved / VALU_PEAK_TFLOPS, nonpacked_peak=round(VALU_PEAK_TFLOPS, 2),
+                launch_ms=ms["render_fwd"], launches=len(batches), measured="solo launches, HIP events on the "
+                "launch stream (isogs_render_fwd_ordered: the tile queue's two small kernels and the compositing "
+                "kernel)", pairs_per_launch=fwd_pairs, flops_per_pair=FLOPS_PER_PAIR, alg_bytes_per_launch=comp_bytes,
+                hbm_gbs_alg=comp_bytes / (ms["render_fwd"] * 1e-3) / 1e9, views_per_launch=B)
+    log(f"solo stages per {B}-view call: " + ", ".join(f"{k} {v['us']} us" for k, v in stages.items()))
+    log(f"composite: {ms['render_fwd'] * 1e3:.0f} us/launch alone, {fwd_pairs:.3e} pairs, {achieved:.2f} TFLOP/s "
+        f"({roof['frac']:.3f} of {FP32_PEAK_TFLOPS}, {roof['frac_nonpacked']:.3f} of {VALU_PEAK_TFLOPS:.1f})")
+    return roof, stages
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -559,6 +718,10 @@ def main():
     import paper_2403_14244_amd as P
     if args.only_field2d:
         print(json.dumps(field2d_workload("cuda")), flush=True)
+        return
+    if args.only_serving:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": serving_benchmark(args, torch.device("cuda:0"))}), flush=True)
         return
 
     t = time.perf_counter()
@@ -615,19 +778,22 @@ def main():
         return stage, bins_all
 
     if args.pmc_probe:
-        fp = R.project([gs] * len(batches[0]), batches[0])
-        R.bin_sort(fp, [gs.n] * len(batches[0]), batches[0], check=True)
+        solo_stages(R, gs, batches[:1])       # sizes the capacity and workspaces
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)                      # plain copy: COPY_BYTES read + COPY_BYTES written
         torch.cuda.synchronize()
-        fp = R.project([gs] * len(batches[0]), batches[0])
-        bins = R.bin_sort(fp, [gs.n] * len(batches[0]), batches[0], check=True)
-        R.render_fwd_ordered(fp, [gs.n] * len(batches[0]), bins, batches[0])
-        torch.cuda.synchronize()
+        # one call of every stage, as the roofline phase makes it (fwd with checkpoints, bwd)
+        ms, fwd_pairs, bwd_p, entries = solo_stages(R, gs, batches[:1])
         print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES, "views": len(batches[0]),
-                          "entries": bins.n_entries(), "sources_digest": composite_sources_digest()}))
+                          "entries": entries, "sources_digest": composite_sources_digest()}))
+        return
+
+    if args.roofline_only:
+        roof, stages_solo = roofline_phase(R, gs, batches, args)
+        print(json.dumps({"roofline": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
+                          "stages_solo_per_call": stages_solo}), flush=True)
         return
 
     for _ in range(max(args.warmup, 1)):
@@ -652,41 +818,10 @@ def main():
     stage_ms = {k: sum(a.elapsed_time(b) for st in stages for a, b in st[k]) / args.steps for k in stages[0]}
     log(f"forward: {ms_step:.2f} ms/step, {mpix:.1f} Mpix/s, stages {stage_ms}")
 
-    # dominant kernel: compositing (one launch per batch of views). Its binding roof is the
-    # FP32 VALU: work = evaluated (pixel, entry) pairs of the plain tiled walk x 9 flops.
-    n_comp = args.steps * len(batches)
-    comp_ms = stage_ms["render_fwd"] * args.steps / n_comp
-    pairs = 0
-    iso = []
-    for bc in batches:
-        fp = R.project([gs] * len(bc), bc)
-        bins = R.bin_sort(fp, [gs.n] * len(bc), bc, check=True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        _, T, n_last = R.render_fwd_ordered(fp, [gs.n] * len(bc), bins, bc)
-        e1.record()
-        iso.append((e0, e1))
-        pairs += walk_pairs(T, n_last, bins.ranges, bc)
-    iso_ms = sum(a.elapsed_time(b) for a, b in iso) / len(iso)
-    pairs_per_launch = pairs / len(batches)
-    flops = pairs_per_launch * FLOPS_PER_PAIR
-    pix_per_launch = B * args.width * args.height
-    ent_per_launch = float(np.mean(entries))
-    tiles_per_launch = B * ((args.width + 15) // 16) * ((args.height + 15) // 16)
-    # algorithmic bytes of one launch: per entry its particle index (4 B) and footprint
-    # record (32 B); per pixel the image (12 B), final transmittance (4 B) and last index
-    # (4 B); per tile its range (8 B)
-    comp_bytes = ent_per_launch * 36 + pix_per_launch * 20 + tiles_per_launch * 8
-    roof = dict(kernel="composite_fwd_ordered_kernel", bound="alu",
-                achieved=flops / (comp_ms * 1e-3) / 1e12, peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                traffic=measured_traffic(comp_bytes), launch_ms=comp_ms, launch_ms_alone=iso_ms,
-                pairs_per_launch=pairs_per_launch,
-                flops_per_pair=FLOPS_PER_PAIR, alg_bytes_per_launch=comp_bytes,
-                hbm_gbs_alg=comp_bytes / (comp_ms * 1e-3) / 1e9)
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    log(f"composite: {comp_ms * 1e3:.0f} us/launch in the timed region ({iso_ms * 1e3:.0f} us alone), "
-        f"{pairs_per_launch:.3e} pairs, "
-        f"{roof['achieved']:.2f} TFLOP/s ({roof['frac']:.3f} of {VALU_PEAK_TFLOPS:.1f})")
+    # per-stage rooflines from solo launches (nothing else on the GPU), one call per batch;
+    # the dominant kernel is compositing, bound by the FP32 VALU: work = evaluated (pixel,
+    # entry) pairs of the plain tiled walk x 9 flops
+    roof, stages_solo = roofline_phase(R, gs, batches, args)
 
     # fwd+bwd iterations per second: one 1080p view, L1 loss, autograd
     cam1 = [cams[0]]
@@ -726,6 +861,9 @@ def main():
     if not args.no_extra_workloads:
         del Rt, params
         torch.cuda.empty_cache()
+        log("cube10k_256 forward ...")
+        extra["cube10k_256"] = cube_workload(dev)
+        log(f"cube10k_256: {extra['cube10k_256']}")
         log("training workload (500k, 4 x 1280x720) ...")
         extra["training_500k_720p_x4"] = training_workload(dev)
         log(f"training workload: {extra['training_500k_720p_x4']}")
@@ -758,11 +896,12 @@ def main():
                    "width": args.width, "height": args.height, "sh_degree": 3, "views_per_call": B,
                    "streams": len(streams)},
         "stage_ms_per_step": {k: round(v, 3) for k, v in stage_ms.items()},
-        "entries_per_view": round(ent_per_launch / B),
+        "entries_per_view": round(float(np.mean(entries)) / B),
         "fwd_bwd_iters_per_s": round(it_s, 2),
         "fwd_bwd_iters_per_s_by_fwd_kernel": it_by_kernel,
         "roofline": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
-        "stage_us_per_view": {k: round(v * 1e3 / args.views, 1) for k, v in stage_ms.items()},
+        "stages_solo_per_call": stages_solo,
+        "stage_span_us_per_view_overlapped": {k: round(v * 1e3 / args.views, 1) for k, v in stage_ms.items()},
         "serving": serving,
         **extra,
     }

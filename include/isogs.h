@@ -387,6 +387,47 @@ int isogs_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* bi
                       int32_t height, float support, const float* dL_dimage, const isogs_field2d* grads,
                       void* ws, size_t* ws_bytes, void* stream);
 
+/* The 2D kernel sum with anisotropic kernels, the variant the paper times its isotropic
+ * kernels against (Table 2, the settings (D, K) of the 2D fit): particle k has centre mu_k,
+ * rotation angle theta_k, scales s1_k, s2_k > 0 and amplitude A_k, and the kernel of eq. 5
+ * with the 2D form of eq. 6, Sigma = R(theta) diag(s1^2, s2^2) R(theta)^T,
+ *   f_c(x) = sum over |x - mu_k| < D of A_kc exp(-(x - mu_k)^T Sigma_k^-1 (x - mu_k)),
+ * the support, pixel grid, order of the sum and binning being those of the isotropic calls
+ * above. The conic Sigma^-1 = [[P00, P01], [P01, P11]] is formed in FP64 and rounded once;
+ * the exponent is evaluated in FP32. A particle with a non-finite parameter, a scale <= 0
+ * or a conic entry overflowing contributes nothing and gets zero gradients. */
+typedef struct {
+    float* mu;      /* [2][K] centres, pixels */
+    float* theta;   /* [K] rotation angles, radians */
+    float* scale;   /* [2][K] scales s1, s2 > 0, pixels */
+    float* amp;     /* [3][K] amplitudes */
+    int32_t K;
+} isogs_field2d_aniso;
+
+/* Footprints and tile lists: fp as for isogs_field2d_bin with {mu_x, mu_y, P00, P01} in
+ * the record's first half, conic_c [K] (device) receives P11.
+ * Errors: as isogs_field2d_bin (conic_c NULL with K > 0 is invalid). */
+int isogs_field2d_aniso_bin(const isogs_field2d_aniso* field, int32_t width, int32_t height,
+                            float support, const isogs_projected* fp, float* conic_c,
+                            const isogs_bins* bins, void* ws, size_t* ws_bytes, void* stream);
+
+/* The image [3][H][W] of the binned anisotropic signal. Errors: as isogs_field2d_fwd. */
+int isogs_field2d_aniso_fwd(const isogs_projected* fp, const float* conic_c, int32_t K,
+                            const isogs_bins* bins, int32_t width, int32_t height, float support,
+                            float* image, void* stream);
+
+/* Gradients for dL/dimage [3][H][W]: per entry the eight sums over its tile's pixels
+ * (the amplitude terms, t dx, t dy, t dx^2, t dx dy, t dy^2 with t = (sum_c w_c A_c) g),
+ * stored at the entry's emit position; per particle their sum in emit order, chained in
+ * FP64 to mu, theta and the scales. `field` is the binned signal (for theta and the
+ * scales); grads: device OUTPUT arrays of its shapes. ws: 32 bytes per entry of capacity.
+ * Errors: as isogs_field2d_bwd. */
+int isogs_field2d_aniso_bwd(const isogs_field2d_aniso* field, const isogs_projected* fp,
+                            const float* conic_c, const isogs_bins* bins, int32_t width,
+                            int32_t height, float support, const float* dL_dimage,
+                            const isogs_field2d_aniso* grads, void* ws, size_t* ws_bytes,
+                            void* stream);
+
 /* Quadtree initialisation of a 2D signal (Section 3, "Initial with Tree Structure"): the
  * leaves of a quadtree over `target` [3][height][width] become particles with the mean
  * colour of their pixels as amplitude, half the cell width as sigma and the centre of the
@@ -424,6 +465,71 @@ int isogs_field2d_prune(const isogs_field2d* in, float amp_min, const isogs_fiel
 int isogs_field2d_split(const isogs_field2d* in, float sigma_max, const isogs_field2d* out,
                         int32_t* count, void* ws, size_t* ws_bytes, void* stream);
 
+/* Merge (Section 2, "Multiscale": isotropic kernels are easily merged or divided according
+ * to their scale; Section 3, "Optimization"), the inverse of the split: particles with
+ * sigma <= sigma_max (finite parameters, sigma > 0, centre inside the width x height image)
+ * are grouped by the square cell of edge `cell` holding their centre (floor(mu / cell), in
+ * FP64); every group of two or more particles becomes one that keeps the kernels' mass per
+ * channel (pi A sigma^2): sigma_m^2 = sum sigma_k^2, mu_m and A_m the sigma_k^2-weighted
+ * means; it takes the place of the group's first member, the other particles keep their
+ * order. The four children of a split merge back into their parent. Group sums are FP64
+ * (their terms may be added in any order: the merged values can differ in their last FP64
+ * bits between calls, rounded to FP32 they practically never do); membership and order are
+ * exact.
+ *   in, out, count  as isogs_field2d_prune (count: outputs, <= in->K)
+ *   ws, ws_bytes    workspace (query with ws == NULL, 256-byte aligned): 56 bytes per cell
+ *                   of the width x height grid plus the scan's block sums
+ * Errors: ISOGS_ERR_INVALID (sizes, cell not finite or <= 0, a grid of more than 2^26 cells,
+ * NULL buffers), ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
+int isogs_field2d_merge(const isogs_field2d* in, int32_t width, int32_t height, float cell,
+                        float sigma_max, const isogs_field2d* out, int32_t* count, void* ws,
+                        size_t* ws_bytes, void* stream);
+
+/* ---- Octree initialisation of 3D particles (Section 3, "Initial with Tree Structure") -
+ * The 3D counterpart of isogs_field2d_tree_init: an octree over a coloured point cloud (the
+ * points a reconstruction starts from), every leaf cell a particle with the mean colour of
+ * its points and a scale of half the cell width.
+ *   - The domain is a grid of roots[0] x roots[1] x roots[2] cubic root cells of edge
+ *     root_side with corner lo; the tree has `levels` levels, level l having cells of edge
+ *     root_side / 2^l; a point belongs to the finest cell floor((p - lo) / h) per axis (FP64,
+ *     h the finest edge) and is ignored outside the grid.
+ *   - Statistics are exact integers: each colour channel clamped to [0, 1] and quantised to
+ *     q = rint(65535 c); a cell keeps its point count and the sums of q and q^2 per channel
+ *     (coarser cells add their eight children), so they do not depend on the order points
+ *     are added in. Its colour variance, in FP64 from those integers,
+ *     (1/3) sum_ch (S2/n - (S1/n)^2), is compared with tau * 65535^2.
+ *   - A cell with no point never splits and carries no particle; a non-empty cell of a
+ *     level below the last splits into its octants when its variance exceeds tau. Levels
+ *     grow one at a time; a level whose splits would let the particle count (leaves so far,
+ *     the level's non-empty cells that do not split, the non-empty children of those that
+ *     do) exceed K splits no cell.
+ *   - Leaves are numbered level by level, x fastest, then y, then z; particle: centre = the
+ *     cell centre lo + (i + 1/2) edge (FP64, rounded), scale = edge / 2, opacity = `opacity`,
+ *     colour = the mean quantised colour / 65535 as coefficient 0 (the scene's higher
+ *     coefficients are set to 0).
+ *   points, colors  device [3][n_points] each (FP32)
+ *   out    host struct of device arrays with capacity out->n >= K (the row stride), any
+ *          sh_degree; at most K particles are written
+ *   count  device int32: the number of leaves (above K only when the non-empty root cells
+ *          alone exceed it; particles past K are not written)
+ *   ws, ws_bytes  workspace (query with ws == NULL, 256-byte aligned): 58 bytes per cell of
+ *          all levels and the scan's block sums
+ * Errors: ISOGS_ERR_INVALID (n_points < 0, levels outside 1..12, a root count < 1,
+ * root_side or lo not finite, root_side <= 0, 2^28 cells or more, K < 1, out->n < K, tau
+ * not finite or < 0, opacity outside (0, 1), NULL buffers), ISOGS_ERR_WORKSPACE,
+ * ISOGS_ERR_DEVICE. */
+typedef struct {
+    float lo[3];
+    float root_side;
+    int32_t roots[3];
+    int32_t levels;
+} isogs_octree_grid;
+
+int isogs_octree_init(const float* points, const float* colors, int32_t n_points,
+                      const isogs_octree_grid* grid, float tau, int32_t K, float opacity,
+                      const isogs_scene* out, int32_t* count, void* ws, size_t* ws_bytes,
+                      void* stream);
+
 /* ---- SSIM term of the loss (Section 3) -----------------------------------------------
  * The paper's loss adds lambda times an SSIM term to the L1 error (lambda = 0.2); read as
  * lambda (1 - SSIM). SSIM is the structural similarity of Wang et al. (2004): per channel,
@@ -448,6 +554,22 @@ int isogs_ssim_fwd(const float* image, const float* target, int32_t channels, in
  * forward (the target is constant); dL_dssim is a device scalar. Output overwritten. */
 int isogs_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height,
                    int32_t width, const float* dL_dssim, const void* ws, size_t ws_bytes,
+                   float* dL_dimage, void* stream);
+
+/* The paper's loss (Section 3), (1 - lambda) L1 + lambda (1 - SSIM) with the two terms as
+ * defined for isogs_l1_fwd and isogs_ssim_fwd (lambda = 0.2 in the paper; the sign of the
+ * SSIM term read so that the loss falls as the images agree).
+ *   loss      device [2]: written, {the loss, the mean SSIM}; the L1 mean is added in FP64
+ *             from fixed-order block sums, as isogs_l1_fwd does
+ *   ws, ws_bytes  workspace (query with ws == NULL, 256-byte aligned): the SSIM workspace
+ *             plus the L1 block sums; isogs_loss_bwd reads what the forward left there
+ * isogs_loss_bwd writes dL/dimage = dL_dloss ((1 - lambda) sign(image - target) / n -
+ * lambda dSSIM/dimage) in one kernel (dL_dloss a device scalar; sign(0) = 0).
+ * Errors: as isogs_ssim_fwd / _bwd, and ISOGS_ERR_INVALID for lambda outside [0, 1]. */
+int isogs_loss_fwd(const float* image, const float* target, int32_t channels, int32_t height,
+                   int32_t width, float lambda, float* loss, void* ws, size_t* ws_bytes, void* stream);
+int isogs_loss_bwd(const float* image, const float* target, int32_t channels, int32_t height,
+                   int32_t width, float lambda, const float* dL_dloss, const void* ws, size_t ws_bytes,
                    float* dL_dimage, void* stream);
 
 /* The L1 term of the loss (Section 3): loss = mean |image - target| over n values (FP32

@@ -10,10 +10,11 @@ _lib()
 
 from .rasterizer import (GaussianScene, Footprints, TileBins, Rasterizer, IsoGSRender,  # noqa: E402,F401
                          split_images, tiles_of)
-from .field2d import Field2DRenderer, Field2DRender, tree_init, prune, split  # noqa: E402,F401
+from .field2d import (Field2DRenderer, Field2DRender, Field2DAnisoRenderer, Field2DAnisoRender,  # noqa: E402,F401
+                      tree_init, prune, split, merge, octree_init)
 from .loss import SSIM, L1, ssim, l1_loss, l1_ssim_loss  # noqa: E402,F401
 from .aniso import AnisoGaussianScene, AnisoFootprints, AnisoRasterizer, AnisoGSRender  # noqa: E402,F401
 
 __all__ = ["GaussianScene", "Footprints", "TileBins", "Rasterizer", "IsoGSRender", "IsoGSError",
            "split_images", "tiles_of", "Field2DRenderer", "Field2DRender", "SSIM", "L1", "ssim", "l1_loss", "l1_ssim_loss",
-           "tree_init", "prune", "split", "AnisoGaussianScene", "AnisoFootprints", "AnisoRasterizer", "AnisoGSRender"]
+           "tree_init", "prune", "split", "merge", "octree_init", "Field2DAnisoRenderer", "Field2DAnisoRender", "AnisoGaussianScene", "AnisoFootprints", "AnisoRasterizer", "AnisoGSRender"]

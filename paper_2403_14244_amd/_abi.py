@@ -24,7 +24,9 @@ EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_r
             "isogs_render_bwd", "isogs_checkpoint_bytes", "isogs_field2d_bin", "isogs_field2d_fwd",
             "isogs_field2d_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune", "isogs_field2d_split",
             "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_aniso_project",
-            "isogs_aniso_render_fwd", "isogs_aniso_render_bwd", "isogs_last_error", "isogs_version")
+            "isogs_aniso_render_fwd", "isogs_aniso_render_bwd", "isogs_loss_fwd", "isogs_loss_bwd",
+            "isogs_field2d_merge", "isogs_octree_init", "isogs_field2d_aniso_bin", "isogs_field2d_aniso_fwd",
+            "isogs_field2d_aniso_bwd", "isogs_last_error", "isogs_version")
 
 
 class Scene(ctypes.Structure):
@@ -61,6 +63,16 @@ class Bins(ctypes.Structure):
 class Field2D(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("amp", ctypes.c_void_p),
                 ("K", ctypes.c_int32)]
+
+
+class Field2DAniso(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_void_p), ("theta", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("amp", ctypes.c_void_p), ("K", ctypes.c_int32)]
+
+
+class OctreeGrid(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float * 3), ("root_side", ctypes.c_float), ("roots", ctypes.c_int32 * 3),
+                ("levels", ctypes.c_int32)]
 
 
 class IsoGSError(RuntimeError):
@@ -120,13 +132,30 @@ def lib():
                                      P(ctypes.c_size_t), vp]
         L.isogs_ssim_bwd.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, ctypes.c_size_t,
                                      vp, vp]
+        L.isogs_loss_fwd.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, vp, vp,
+                                     P(ctypes.c_size_t), vp]
+        L.isogs_loss_bwd.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, vp, vp,
+                                     ctypes.c_size_t, vp, vp]
+        L.isogs_field2d_merge.argtypes = [P(Field2D), ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                          P(Field2D), vp, vp, P(ctypes.c_size_t), vp]
+        L.isogs_octree_init.argtypes = [vp, vp, ctypes.c_int32, P(OctreeGrid), ctypes.c_float, ctypes.c_int32,
+                                        ctypes.c_float, P(Scene), vp, vp, P(ctypes.c_size_t), vp]
+        L.isogs_field2d_aniso_bin.argtypes = [P(Field2DAniso), ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                              P(Projected), vp, P(Bins), vp, P(ctypes.c_size_t), vp]
+        L.isogs_field2d_aniso_fwd.argtypes = [P(Projected), vp, ctypes.c_int32, P(Bins), ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_float, vp, vp]
+        L.isogs_field2d_aniso_bwd.argtypes = [P(Field2DAniso), P(Projected), vp, P(Bins), ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_float, vp, P(Field2DAniso), vp,
+                                              P(ctypes.c_size_t), vp]
         L.isogs_checkpoint_bytes.argtypes = [ctypes.c_uint64]
         L.isogs_checkpoint_bytes.restype = ctypes.c_size_t
         for name in ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_render_fwd", "isogs_render_fwd_ordered",
                      "isogs_render_bwd", "isogs_field2d_bin", "isogs_field2d_fwd", "isogs_field2d_bwd",
                      "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_field2d_tree_init", "isogs_field2d_prune",
                      "isogs_field2d_split", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_aniso_project",
-                     "isogs_aniso_render_fwd", "isogs_aniso_render_bwd"):
+                     "isogs_aniso_render_fwd", "isogs_aniso_render_bwd", "isogs_loss_fwd", "isogs_loss_bwd",
+                     "isogs_field2d_merge", "isogs_octree_init", "isogs_field2d_aniso_bin",
+                     "isogs_field2d_aniso_fwd", "isogs_field2d_aniso_bwd"):
             getattr(L, name).restype = ctypes.c_int
         L.isogs_last_error.restype = ctypes.c_char_p
         L.isogs_last_error.argtypes = []

@@ -475,6 +475,172 @@ int isogs_ssim_bwd(const float* image, const float* target, int32_t channels, in
     return ISOGS_OK;
 }
 
+int isogs_field2d_aniso_bin(const isogs_field2d_aniso* field, int32_t width, int32_t height, float support,
+                            const isogs_projected* fp, float* conic_c, const isogs_bins* bins, void* ws,
+                            size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if (!field) return fail(ISOGS_ERR_INVALID, "field is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    uint64_t tiles;
+    if ((rc = check_field2d_sizes(field->K, width, height, support, &tiles))) return rc;
+    const isogs::BinSortPlan plan = isogs::plan_field2d_bin(field->K, width, height, bins->capacity);
+    if (!ws) {
+        *ws_bytes = plan.bytes;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < plan.bytes)
+        return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, plan.bytes);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (field->K > 0 && (!field->mu || !field->theta || !field->scale || !field->amp || !conic_c))
+        return fail(ISOGS_ERR_INVALID, "field parameter buffer or conic_c is NULL");
+    if ((rc = check_projected(fp, (uint64_t)field->K))) return rc;
+    if ((rc = check_bins(bins, (uint64_t)field->K, tiles))) return rc;
+    if (isogs::launch_field2d_aniso_bin(plan, field, width, height, support, fp, conic_c, bins, ws,
+                                        (hipStream_t)stream))
+        return device_fail("isogs_field2d_aniso_bin");
+    return ISOGS_OK;
+}
+
+int isogs_field2d_aniso_fwd(const isogs_projected* fp, const float* conic_c, int32_t K, const isogs_bins* bins,
+                            int32_t width, int32_t height, float support, float* image, void* stream) {
+    g_error[0] = 0;
+    int rc;
+    uint64_t tiles;
+    if ((rc = check_field2d_sizes(K, width, height, support, &tiles))) return rc;
+    if ((rc = check_projected(fp, (uint64_t)K))) return rc;
+    if ((rc = check_bins(bins, (uint64_t)K, tiles))) return rc;
+    if (!image || (K > 0 && !conic_c)) return fail(ISOGS_ERR_INVALID, "image or conic_c is NULL");
+    if (isogs::launch_field2d_aniso_fwd(fp, conic_c, bins, width, height, support, image, (hipStream_t)stream))
+        return device_fail("isogs_field2d_aniso_fwd");
+    return ISOGS_OK;
+}
+
+int isogs_field2d_aniso_bwd(const isogs_field2d_aniso* field, const isogs_projected* fp, const float* conic_c,
+                            const isogs_bins* bins, int32_t width, int32_t height, float support,
+                            const float* dL_dimage, const isogs_field2d_aniso* grads, void* ws, size_t* ws_bytes,
+                            void* stream) {
+    g_error[0] = 0;
+    int rc;
+    if (!field || !grads) return fail(ISOGS_ERR_INVALID, "field or grads is NULL");
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!bins) return fail(ISOGS_ERR_INVALID, "bins is NULL");
+    uint64_t tiles;
+    if ((rc = check_field2d_sizes(field->K, width, height, support, &tiles))) return rc;
+    const size_t need = isogs::field2d_bwd_ws(bins->capacity);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if ((rc = check_projected(fp, (uint64_t)field->K))) return rc;
+    if ((rc = check_bins(bins, (uint64_t)field->K, tiles))) return rc;
+    if (!dL_dimage) return fail(ISOGS_ERR_INVALID, "dL_dimage is NULL");
+    if (grads->K != field->K) return fail(ISOGS_ERR_INVALID, "grads must describe K particles");
+    if (field->K > 0 && (!field->theta || !field->scale || !conic_c || !grads->mu || !grads->theta ||
+                         !grads->scale || !grads->amp))
+        return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (isogs::launch_field2d_aniso_bwd(field, fp, conic_c, bins, width, height, support, dL_dimage, grads, ws,
+                                        (hipStream_t)stream))
+        return device_fail("isogs_field2d_aniso_bwd");
+    return ISOGS_OK;
+}
+
+int isogs_field2d_merge(const isogs_field2d* in, int32_t width, int32_t height, float cell, float sigma_max,
+                        const isogs_field2d* out, int32_t* count, void* ws, size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!in || !out) return fail(ISOGS_ERR_INVALID, "in or out is NULL");
+    if (in->K < 0 || out->K < 0) return fail(ISOGS_ERR_INVALID, "K < 0");
+    if (width <= 0 || height <= 0) return fail(ISOGS_ERR_INVALID, "width and height must be positive");
+    if (!(cell > 0.0f) || !isfinite(cell)) return fail(ISOGS_ERR_INVALID, "cell must be finite and > 0");
+    if (!isogs::merge_cells_ok(width, height, cell)) return fail(ISOGS_ERR_INVALID, "the cell grid is too large");
+    const size_t need = isogs::merge_ws(in->K, width, height, cell);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!count) return fail(ISOGS_ERR_INVALID, "count is NULL");
+    if (in->K > 0 && (!in->mu || !in->sigma || !in->amp)) return fail(ISOGS_ERR_INVALID, "input buffer is NULL");
+    if (out->K > 0 && (!out->mu || !out->sigma || !out->amp)) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (isogs::launch_merge(in, width, height, cell, sigma_max, out, count, ws, (hipStream_t)stream))
+        return device_fail("isogs_field2d_merge");
+    return ISOGS_OK;
+}
+
+int isogs_octree_init(const float* points, const float* colors, int32_t n_points, const isogs_octree_grid* grid,
+                      float tau, int32_t K, float opacity, const isogs_scene* out, int32_t* count, void* ws,
+                      size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (!grid) return fail(ISOGS_ERR_INVALID, "grid is NULL");
+    if (!isogs::octree_grid_ok(grid))
+        return fail(ISOGS_ERR_INVALID, "octree grid: levels 1..12, roots >= 1, finite lo, root_side > 0, < 2^28 cells");
+    const size_t need = isogs::octree_init_ws(grid);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (n_points < 0) return fail(ISOGS_ERR_INVALID, "n_points < 0");
+    if (n_points > 0 && (!points || !colors)) return fail(ISOGS_ERR_INVALID, "points or colors is NULL");
+    if (!(tau >= 0.0f) || !isfinite(tau)) return fail(ISOGS_ERR_INVALID, "tau must be finite and >= 0");
+    if (!(opacity > 0.0f && opacity < 1.0f)) return fail(ISOGS_ERR_INVALID, "opacity must be in (0, 1)");
+    if (K < 1) return fail(ISOGS_ERR_INVALID, "K must be >= 1");
+    if (!out || out->n < K) return fail(ISOGS_ERR_INVALID, "out must hold K particles");
+    if (out->sh_degree < 0 || out->sh_degree > ISOGS_MAX_SH_DEGREE)
+        return fail(ISOGS_ERR_INVALID, "out sh_degree outside 0..3");
+    if (!out->pos || !out->scale || !out->opacity || !out->color || !count)
+        return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (isogs::launch_octree_init(points, colors, n_points, grid, tau, K, opacity, out, count, ws, (hipStream_t)stream))
+        return device_fail("isogs_octree_init");
+    return ISOGS_OK;
+}
+
+int isogs_loss_fwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                   float lambda, float* loss, void* ws, size_t* ws_bytes, void* stream) {
+    g_error[0] = 0;
+    if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
+    if (channels <= 0 || height <= 0 || width <= 0) return fail(ISOGS_ERR_INVALID, "sizes must be positive");
+    if ((uint64_t)channels * (uint64_t)height * (uint64_t)width >= (1ull << 31) || channels > 65535)
+        return fail(ISOGS_ERR_INVALID, "image too large");
+    if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(ISOGS_ERR_INVALID, "lambda must be in [0, 1]");
+    const size_t need = isogs::loss_ws_bytes(channels, height, width);
+    if (!ws) {
+        *ws_bytes = need;
+        return ISOGS_OK;
+    }
+    if (*ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!image || !target || !loss) return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (isogs::launch_loss_fwd(image, target, channels, height, width, lambda, loss, ws, (hipStream_t)stream))
+        return device_fail("isogs_loss_fwd");
+    return ISOGS_OK;
+}
+
+int isogs_loss_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                   float lambda, const float* dL_dloss, const void* ws, size_t ws_bytes, float* dL_dimage,
+                   void* stream) {
+    g_error[0] = 0;
+    if (channels <= 0 || height <= 0 || width <= 0) return fail(ISOGS_ERR_INVALID, "sizes must be positive");
+    if ((uint64_t)channels * (uint64_t)height * (uint64_t)width >= (1ull << 31) || channels > 65535)
+        return fail(ISOGS_ERR_INVALID, "image too large");
+    if (!(lambda >= 0.0f && lambda <= 1.0f)) return fail(ISOGS_ERR_INVALID, "lambda must be in [0, 1]");
+    const size_t need = isogs::loss_ws_bytes(channels, height, width);
+    if (!ws || ws_bytes < need) return fail(ISOGS_ERR_WORKSPACE, "the forward's workspace of %zu bytes is needed", need);
+    if ((uintptr_t)ws & 255) return fail(ISOGS_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (!image || !target || !dL_dloss || !dL_dimage) return fail(ISOGS_ERR_INVALID, "buffer is NULL");
+    if (isogs::launch_loss_bwd(image, target, channels, height, width, lambda, dL_dloss, ws, dL_dimage,
+                               (hipStream_t)stream))
+        return device_fail("isogs_loss_bwd");
+    return ISOGS_OK;
+}
+
 int isogs_field2d_tree_init(const float* target, int32_t height, int32_t width, int32_t root, int32_t min_side,
                             float tau, int32_t K, const isogs_field2d* out, int32_t* count, void* ws, size_t* ws_bytes,
                             void* stream) {

@@ -39,8 +39,10 @@ size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv);
 // the compositing kernels), the class cursors, and the order array (returned).
 size_t tile_queue_words(uint32_t n_tiles);
 uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv);
+// banded: the XCD-banded order of large compact launches (each XCD a contiguous band of
+// tiles, longest first within it); otherwise one global longest-first order.
 uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0, uint32_t n_tiles, uint32_t cap,
-                            hipStream_t stream);
+                            hipStream_t stream, bool banded = false);
 // Workgroups of `threads` threads of `kernel` resident on the whole GPU at once.
 int resident_blocks(const void* kernel, int threads);
 
@@ -80,6 +82,15 @@ int launch_field2d_bwd(const isogs_projected* fp, int32_t K, const isogs_bins* b
                        float support, const float* dL_dimage, const isogs_field2d* grads, void* ws,
                        hipStream_t stream);
 
+int launch_field2d_aniso_bin(const BinSortPlan& plan, const isogs_field2d_aniso* f, int32_t width, int32_t height,
+                             float support, const isogs_projected* fp, float* conic_c, const isogs_bins* bins,
+                             void* ws, hipStream_t stream);
+int launch_field2d_aniso_fwd(const isogs_projected* fp, const float* conic_c, const isogs_bins* bins, int32_t width,
+                             int32_t height, float support, float* image, hipStream_t stream);
+int launch_field2d_aniso_bwd(const isogs_field2d_aniso* f, const isogs_projected* fp, const float* conic_c,
+                             const isogs_bins* bins, int32_t width, int32_t height, float support,
+                             const float* dL_dimage, const isogs_field2d_aniso* grads, void* ws, hipStream_t stream);
+
 // The SSIM term of the loss: forward (mean SSIM and the derivative maps kept in the
 // workspace) and backward.
 size_t ssim_ws_bytes(int32_t channels, int32_t height, int32_t width);
@@ -87,6 +98,18 @@ int launch_ssim_fwd(const float* image, const float* target, int32_t channels, i
                     float* ssim, void* ws, hipStream_t stream);
 int launch_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
                     const float* dL_dssim, const void* ws, float* dL_dimage, hipStream_t stream);
+
+int launch_ssim_bwd_weighted(const float* image, const float* target, int32_t channels, int32_t height,
+                             int32_t width, const float* dL_dssim, const void* ws, float ssim_w, float l1_w,
+                             float* dL_dimage, hipStream_t stream);
+// The paper's combined loss (1 - lambda) L1 + lambda (1 - SSIM): loss[0] the value, loss[1]
+// the SSIM mean; the backward is one fused kernel.
+size_t loss_ws_bytes(int32_t channels, int32_t height, int32_t width);
+int launch_loss_fwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                    float lambda, float* loss, void* ws, hipStream_t stream);
+int launch_loss_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                    float lambda, const float* dL_dloss, const void* ws, float* dL_dimage, hipStream_t stream);
+uint32_t launch_l1_partial(const float* image, const float* target, uint64_t n, double* blocks, hipStream_t stream);
 
 // Quadtree initialisation, prune and split of 2D particles.
 int tree_levels_ok(int32_t width, int32_t height, int32_t root, int32_t min_side, uint64_t* root_cells);
@@ -97,6 +120,17 @@ size_t edit_ws(int32_t K);
 // mode 0: prune (keep max |A| >= thr), mode 1: split (sigma > thr into four)
 int launch_edit(int mode, float thr, const isogs_field2d* in, const isogs_field2d* out, int32_t cap, int32_t* count,
                 void* ws, hipStream_t stream);
+
+// Octree initialisation of 3D particles from a coloured point cloud; merge of 2D particles.
+int octree_grid_ok(const isogs_octree_grid* g);
+size_t octree_init_ws(const isogs_octree_grid* g);
+int launch_octree_init(const float* points, const float* colors, int32_t P, const isogs_octree_grid* grid, float tau,
+                       int32_t K, float opacity, const isogs_scene* out, int32_t* count, void* ws,
+                       hipStream_t stream);
+int merge_cells_ok(int32_t width, int32_t height, float cell);
+size_t merge_ws(int32_t K, int32_t width, int32_t height, float cell);
+int launch_merge(const isogs_field2d* in, int32_t width, int32_t height, float cell, float sigma_max,
+                 const isogs_field2d* out, int32_t* count, void* ws, hipStream_t stream);
 
 // The L1 term of the loss: mean |image - target| and its gradient.
 size_t l1_ws_bytes(uint64_t n);

@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(kTilePixels) ssim_bwd_kernel(const float* __re
                                                                const float* __restrict__ d_e11,
                                                                const float* __restrict__ d_e12,
                                                                const float* __restrict__ dL_dssim, float inv_n,
+                                                               float ssim_w, float l1_w,
                                                                float* __restrict__ dL_dimage) {
     __shared__ SsimBwdShared sh;
     const uint32_t t = threadIdx.x, tile = blockIdx.x, ch = blockIdx.y;
@@ -170,8 +171,35 @@ __global__ void __launch_bounds__(kTilePixels) ssim_bwd_kernel(const float* __re
         for (int q = 0; q < 3; ++q) b[q] = fmaf(g, sh.h[q][r + k][c], b[q]);
     }
     const size_t o = ch * plane + (size_t)py * width + px;
-    const float scale = *dL_dssim * inv_n;
-    dL_dimage[o] = scale * (b[0] + 2.0f * image[o] * b[1] + target[o] * b[2]);
+    // dL/dimage = ssim_w g dSSIM/dimage (+ l1_w g sign(image - target) / n for the paper's
+    // combined loss), g = dL_dssim[0]
+    const float g = *dL_dssim;
+    const float scale = ssim_w * g * inv_n;
+    float out = scale * (b[0] + 2.0f * image[o] * b[1] + target[o] * b[2]);
+    if (l1_w != 0.0f) {
+        const float gl = l1_w * g * inv_n, d = image[o] - target[o];
+        out += d > 0.0f ? gl : (d < 0.0f ? -gl : 0.0f);
+    }
+    dL_dimage[o] = out;
+}
+
+// The paper's loss (1 - lambda) L1 + lambda (1 - SSIM) from the SSIM mean and the L1 block
+// sums (added in block order in FP64, as l1_final_kernel does).
+__global__ void __launch_bounds__(256) loss_combine_kernel(const double* __restrict__ l1_blocks, uint32_t n_blocks,
+                                                           double inv_n, const float* __restrict__ ssim, double lam,
+                                                           float* __restrict__ loss) {
+    __shared__ double s_run[256];
+    const uint32_t t = threadIdx.x, per = (n_blocks + 255u) / 256u;
+    double a = 0.0;
+    for (uint32_t i = t * per; i < min(n_blocks, (t + 1u) * per); ++i) a += l1_blocks[i];
+    s_run[t] = a;
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < 256; ++i) tot += s_run[i];
+        loss[0] = (float)((1.0 - lam) * (tot * inv_n) + lam * (1.0 - (double)*ssim));
+        loss[1] = *ssim;
+    }
 }
 
 Window make_window() {
@@ -187,7 +215,7 @@ Window make_window() {
 }
 
 struct SsimWs {
-    size_t off_m1, off_e11, off_e12, off_blocks, bytes;
+    size_t off_m1, off_e11, off_e12, off_blocks, off_l1, off_scalar, bytes;
 };
 
 SsimWs ssim_layout(int32_t channels, int32_t height, int32_t width) {
@@ -200,6 +228,9 @@ SsimWs ssim_layout(int32_t channels, int32_t height, int32_t width) {
     w.off_e12 = w.off_e11 + a256(n * 4);
     w.off_blocks = w.off_e12 + a256(n * 4);
     w.bytes = w.off_blocks + a256(blocks * 8);
+    // the combined loss also keeps the L1 block sums and the SSIM mean
+    w.off_l1 = w.bytes;
+    w.off_scalar = w.off_l1 + a256(l1_ws_bytes(n));
     return w;
 }
 
@@ -228,6 +259,38 @@ int launch_ssim_fwd(const float* image, const float* target, int32_t channels, i
 
 int launch_ssim_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
                     const float* dL_dssim, const void* ws, float* dL_dimage, hipStream_t stream) {
+    return launch_ssim_bwd_weighted(image, target, channels, height, width, dL_dssim, ws, 1.0f, 0.0f, dL_dimage,
+                                    stream);
+}
+
+size_t loss_ws_bytes(int32_t channels, int32_t height, int32_t width) {
+    return ssim_layout(channels, height, width).off_scalar + 256;
+}
+
+int launch_loss_fwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                    float lambda, float* loss, void* ws, hipStream_t stream) {
+    const SsimWs L = ssim_layout(channels, height, width);
+    char* base = static_cast<char*>(ws);
+    float* ssim = reinterpret_cast<float*>(base + L.off_scalar);
+    if (launch_ssim_fwd(image, target, channels, height, width, ssim, ws, stream)) return -1;
+    const uint64_t n = (uint64_t)channels * height * width;
+    double* l1b = reinterpret_cast<double*>(base + L.off_l1);
+    const uint32_t nb = launch_l1_partial(image, target, n, l1b, stream);
+    hipLaunchKernelGGL(loss_combine_kernel, dim3(1), dim3(256), 0, stream, l1b, nb, 1.0 / (double)n, ssim,
+                       (double)lambda, loss);
+    return hipPeekAtLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_loss_bwd(const float* image, const float* target, int32_t channels, int32_t height, int32_t width,
+                    float lambda, const float* dL_dloss, const void* ws, float* dL_dimage, hipStream_t stream) {
+    // d/dimage [(1 - lambda) L1 + lambda (1 - SSIM)] = (1 - lambda) dL1 - lambda dSSIM
+    return launch_ssim_bwd_weighted(image, target, channels, height, width, dL_dloss, ws, -lambda, 1.0f - lambda,
+                                    dL_dimage, stream);
+}
+
+int launch_ssim_bwd_weighted(const float* image, const float* target, int32_t channels, int32_t height,
+                             int32_t width, const float* dL_dssim, const void* ws, float ssim_w, float l1_w,
+                             float* dL_dimage, hipStream_t stream) {
     const SsimWs L = ssim_layout(channels, height, width);
     const char* base = static_cast<const char*>(ws);
     const int tx = (width + kTile - 1) / kTile, ty = (height + kTile - 1) / kTile;
@@ -235,7 +298,7 @@ int launch_ssim_bwd(const float* image, const float* target, int32_t channels, i
     hipLaunchKernelGGL(ssim_bwd_kernel, dim3((unsigned)(tx * ty), (unsigned)channels), dim3(kTilePixels), 0, stream,
                        image, target, width, height, tx, make_window(),
                        reinterpret_cast<const float*>(base + L.off_m1), reinterpret_cast<const float*>(base + L.off_e11),
-                       reinterpret_cast<const float*>(base + L.off_e12), dL_dssim, inv_n, dL_dimage);
+                       reinterpret_cast<const float*>(base + L.off_e12), dL_dssim, inv_n, ssim_w, l1_w, dL_dimage);
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -301,11 +364,17 @@ __global__ void __launch_bounds__(kL1Threads) l1_grad_kernel(const float* __rest
 
 size_t l1_ws_bytes(uint64_t n) { return ((n + kL1Chunk - 1) / kL1Chunk + 1) * sizeof(double); }
 
-int launch_l1_fwd(const float* image, const float* target, uint64_t n, float* loss, void* ws, hipStream_t stream) {
+uint32_t launch_l1_partial(const float* image, const float* target, uint64_t n, double* blocks,
+                           hipStream_t stream) {
     const uint32_t nb = (uint32_t)((n + kL1Chunk - 1) / kL1Chunk);
-    double* blocks = static_cast<double*>(ws);
     if (nb)
         hipLaunchKernelGGL(l1_partial_kernel, dim3(nb), dim3(kL1Threads), 0, stream, image, target, n, blocks);
+    return nb;
+}
+
+int launch_l1_fwd(const float* image, const float* target, uint64_t n, float* loss, void* ws, hipStream_t stream) {
+    double* blocks = static_cast<double*>(ws);
+    const uint32_t nb = launch_l1_partial(image, target, n, blocks, stream);
     hipLaunchKernelGGL(l1_final_kernel, dim3(1), dim3(256), 0, stream, blocks, nb, n ? 1.0 / (double)n : 0.0, loss);
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }

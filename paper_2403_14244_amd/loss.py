@@ -84,6 +84,38 @@ class L1(torch.autograd.Function):
         return dimg, None
 
 
+class L1SSIMLoss(torch.autograd.Function):
+    """(1 - lam) mean|image - target| + lam (1 - SSIM(image, target)) in the library: one
+    forward call (both terms and their combination), one fused gradient kernel."""
+
+    @staticmethod
+    def forward(ctx, image, target, lam):
+        image, target = image.contiguous(), target.contiguous()
+        if image.shape != target.shape:
+            raise ValueError("image and target must have the same shape")
+        C, H, W = _planes(image)
+        need = ctypes.c_size_t(0)
+        A.check(A.lib().isogs_loss_fwd(None, None, C, H, W, float(lam), None, None, ctypes.byref(need), _stream()))
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=image.device)
+        out = torch.empty(2, dtype=torch.float32, device=image.device)
+        have = ctypes.c_size_t(ws.numel())
+        A.check(A.lib().isogs_loss_fwd(_p(image), _p(target), C, H, W, float(lam), _p(out), _p(ws),
+                                       ctypes.byref(have), _stream()))
+        ctx.save_for_backward(image, target)
+        ctx.ws, ctx.dims, ctx.lam = ws, (C, H, W), float(lam)
+        return out[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        image, target = ctx.saved_tensors
+        C, H, W = ctx.dims
+        g = grad_out.reshape(1).to(torch.float32).contiguous()
+        dimg = torch.empty_like(image)
+        A.check(A.lib().isogs_loss_bwd(_p(image), _p(target), C, H, W, ctx.lam, _p(g), _p(ctx.ws), ctx.ws.numel(),
+                                       _p(dimg), _stream()))
+        return dimg, None, None
+
+
 def ssim(image, target):
     return SSIM.apply(image, target)
 
@@ -94,5 +126,6 @@ def l1_loss(image, target):
 
 
 def l1_ssim_loss(image, target, lam=LAMBDA):
-    """(1 - lam) mean|image - target| + lam (1 - SSIM(image, target))."""
-    return (1.0 - lam) * l1_loss(image, target) + lam * (1.0 - ssim(image, target))
+    """(1 - lam) mean|image - target| + lam (1 - SSIM(image, target)), value and gradient
+    formed in the library (isogs_loss_fwd / _bwd)."""
+    return L1SSIMLoss.apply(image, target, lam)

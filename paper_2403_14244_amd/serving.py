@@ -219,15 +219,21 @@ class SimulatedExecutor(Executor):
 class GpuExecutor(Executor):
     """Runs batches through the C ABI on `n_streams` HIP streams (default priority)."""
 
-    def __init__(self, scenes: dict, device="cuda", n_streams=2, headroom=1.3):
+    def __init__(self, scenes: dict, device="cuda", n_streams=2, headroom=1.3, record_spans=False):
         import torch
         from .rasterizer import Rasterizer
         self.torch = torch
+        # with record_spans, each batch's device span (events before its first and after
+        # its last launch, on its stream) is kept for device_overlap()
+        self.record_spans = record_spans
+        self.spans = []
         self.scenes = scenes                    # name -> GaussianScene (resident)
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
         self.busy = [False] * n_streams
         self.rasters = [Rasterizer(self.device) for _ in range(n_streams)]
+        # one pinned {count, status} word pair per slot, reused: a slot runs one batch at a time
+        self.status_host = [torch.empty(2, dtype=torch.int32, pin_memory=True) for _ in range(n_streams)]
         self.headroom = headroom
         self.entries_per_view = {}              # (scene, W, H) -> entries seen
         self.overflows = 0
@@ -270,14 +276,20 @@ class GpuExecutor(Executor):
         scenes = [self.scenes[r.scene] for r in batch]
         npv = [g.n for g in scenes]
         cap = int(sum(self._entries(r) for r in batch) * self.headroom) + 4096
+        ev0 = None
+        if self.record_spans:
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev0.record(s)
         with torch.cuda.stream(s):
             fp = R.project(scenes, cams)
             bins = R.bin_sort(fp, npv, cams, check=False, capacity=cap)
             img, T, nl = R.render_fwd_ordered(fp, npv, bins, cams, wide=True)
-            status = torch.empty(2, dtype=torch.int32, pin_memory=True)   # {count, status}
+            status = self.status_host[si]   # {count, status}
             status.copy_(bins.count.as_strided((2,), (1,)), non_blocking=True)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=self.record_spans)
             ev.record(s)
+        if self.record_spans:
+            self.spans.append((si, ev0, ev))
         return dict(si=si, batch=batch, ev=ev, fp=fp, bins=bins, img=img, status=status, npv=npv, cams=cams,
                     scenes=scenes)
 
@@ -301,3 +313,24 @@ class GpuExecutor(Executor):
         for r, im in zip(h["batch"], split_images(img, h["cams"])):
             r.result = im
         self.busy[h["si"]] = False
+
+    def device_overlap(self):
+        """From the recorded device spans (after the batches completed): the number of batch
+        pairs on different streams whose spans intersect, the time with at least two batches
+        on the device and the time with at least one (milliseconds)."""
+        if not self.spans:
+            return dict(batches=0, overlapping_pairs=0, overlap_ms=0.0, busy_ms=0.0)
+        self.torch.cuda.synchronize()
+        ref = self.spans[0][1]
+        iv = [(si, ref.elapsed_time(a), ref.elapsed_time(b)) for si, a, b in self.spans]
+        pairs = sum(1 for i in range(len(iv)) for j in range(i + 1, len(iv))
+                    if iv[i][0] != iv[j][0] and iv[i][1] < iv[j][2] and iv[j][1] < iv[i][2])
+        pts = sorted([(a, 1) for _, a, _ in iv] + [(b, -1) for _, _, b in iv])
+        depth, last, two, one = 0, None, 0.0, 0.0
+        for t, d in pts:
+            if last is not None:
+                two += (t - last) if depth >= 2 else 0.0
+                one += (t - last) if depth >= 1 else 0.0
+            depth += d
+            last = t
+        return dict(batches=len(iv), overlapping_pairs=pairs, overlap_ms=two, busy_ms=one)

@@ -3,6 +3,12 @@ import sys
 
 import pytest
 
+# HIP maps streams onto a per-process pool of hardware queues (4 by default); past that,
+# streams share queues and their work runs one after another. The GPU tests create a few
+# streams per test (serving slots, overlap checks): eight queues keep them apart. Set
+# before the HIP runtime starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

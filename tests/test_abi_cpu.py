@@ -61,7 +61,8 @@ def test_struct_layouts_match_header(tmp_path):
     # sizes and field offsets as a C compiler lays the header's structs out
     structs = {"isogs_scene": A.Scene, "isogs_camera": A.Camera, "isogs_projected": A.Projected,
                "isogs_bins": A.Bins, "isogs_field2d": A.Field2D, "isogs_aniso_scene": A.AnisoScene,
-               "isogs_aniso_projected": A.AnisoProjected}
+               "isogs_aniso_projected": A.AnisoProjected, "isogs_octree_grid": A.OctreeGrid,
+               "isogs_field2d_aniso": A.Field2DAniso}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, ct in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -341,3 +342,44 @@ def test_aniso_invalid_arguments_are_rejected_without_a_device():
     assert need_an.value - need_iso.value >= 1000 * 16
     assert L.isogs_aniso_render_fwd(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, None, None, None, None,
                                     2, None, ctypes.byref(need_an), None) == A.ISOGS_OK   # query ignores flags
+
+
+def test_tree_and_loss_calls_validate_without_a_device():
+    """Octree initialisation, merge and the combined loss reject bad arguments and answer
+    workspace queries before touching a device."""
+    A = _abi()
+    L = A.lib()
+    g = A.OctreeGrid()
+    g.lo[:] = [-1.0, -1.0, -1.0]
+    g.root_side = 0.5
+    g.roots[:] = [4, 4, 4]
+    g.levels = 6
+    need = ctypes.c_size_t(0)
+    out = A.Scene()
+    assert L.isogs_octree_init(None, None, 0, ctypes.byref(g), 1e-3, 10, 0.5, ctypes.byref(out), None, None,
+                               ctypes.byref(need), None) == A.ISOGS_OK
+    cells = sum((4 << l) ** 3 for l in range(6))
+    assert need.value >= cells * 58
+    g.levels = 13
+    assert L.isogs_octree_init(None, None, 0, ctypes.byref(g), 1e-3, 10, 0.5, ctypes.byref(out), None, None,
+                               ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    g.levels = 6
+    g.root_side = -1.0
+    assert L.isogs_octree_init(None, None, 0, ctypes.byref(g), 1e-3, 10, 0.5, ctypes.byref(out), None, None,
+                               ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    g.root_side = 0.5
+    ws = ctypes.create_string_buffer(need.value + 256)
+    aligned = (ctypes.addressof(ws) + 255) & ~255
+    have = ctypes.c_size_t(need.value)
+    out.n = 5    # capacity below K
+    assert L.isogs_octree_init(None, None, 0, ctypes.byref(g), 1e-3, 10, 0.5, ctypes.byref(out), None, aligned,
+                               ctypes.byref(have), None) == A.ISOGS_ERR_INVALID
+    assert b"K" in L.isogs_last_error()
+    fi, fo = A.Field2D(), A.Field2D()
+    assert L.isogs_field2d_merge(ctypes.byref(fi), 64, 64, 0.0, 1.0, ctypes.byref(fo), None, None,
+                                 ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    assert L.isogs_field2d_merge(ctypes.byref(fi), 64, 64, 4.0, 1.0, ctypes.byref(fo), None, None,
+                                 ctypes.byref(need), None) == A.ISOGS_OK
+    assert need.value >= 16 * 16 * 56
+    assert L.isogs_loss_fwd(None, None, 3, 8, 8, 1.5, None, None, ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
+    assert L.isogs_loss_fwd(None, None, 3, 8, 8, 0.2, None, None, ctypes.byref(need), None) == A.ISOGS_OK

@@ -73,9 +73,14 @@ def test_ssim_and_gradient_match_oracle(P, torch_cuda, case):
     assert np.all(np.abs(g - gref) <= tol)
 
 
-def test_loss_matches_oracle_and_is_deterministic(P, torch_cuda):
+@pytest.mark.parametrize("case", ["noise_ragged", "tiny_planes", "target512"])
+def test_loss_matches_oracle_and_is_deterministic(P, torch_cuda, case):
+    """The paper's combined loss, value and gradient formed in the library (one forward
+    call, one fused gradient kernel): against the FP64 oracle, bitwise repeatable, and
+    with lambda = 0 the L1 term's gradient exactly."""
     torch = torch_cuda
-    x, y = _pair("noise_ragged")
+    x, y = _pair(case)
+    note(f"l1 + ssim loss {case}: {x.shape}")
     lref, gref = Q.l1_ssim_loss64(x, y)
     outs = []
     for _ in range(2):
@@ -87,6 +92,10 @@ def test_loss_matches_oracle_and_is_deterministic(P, torch_cuda):
     assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
     tol = 1e-3 * np.abs(gref) + 1e-3 * np.abs(gref).max()
     assert np.all(np.abs(outs[0][1] - gref) <= tol)
+    xt = torch.from_numpy(x).cuda().requires_grad_(True)
+    P.l1_ssim_loss(xt, torch.from_numpy(y).cuda(), lam=0.0).backward()
+    d = x.astype(np.float64) - y.astype(np.float64)
+    np.testing.assert_array_equal(xt.grad.cpu().numpy(), (np.sign(d) * np.float32(1.0 / d.size)).astype(np.float32))
 
 
 @pytest.mark.parametrize("n_shape", [(3, 1080, 1920), (1, 1, 4097), (2, 3, 5)])
