@@ -217,7 +217,12 @@ class SimulatedExecutor(Executor):
 
 
 class GpuExecutor(Executor):
-    """Runs batches through the C ABI on `n_streams` HIP streams (default priority)."""
+    """Runs batches through the C ABI on `n_streams` HIP streams (default priority).
+
+    Batches of different slots overlap on the device only where their streams sit on
+    different hardware queues: HIP gives each process a pool of GPU_MAX_HW_QUEUES of them
+    (4 by default) shared by every stream the process creates, torch's own included; run
+    with 8 (set before the HIP runtime starts) to keep the slots apart."""
 
     def __init__(self, scenes: dict, device="cuda", n_streams=2, headroom=1.3, record_spans=False):
         import torch

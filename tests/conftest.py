@@ -7,7 +7,8 @@ import pytest
 # streams share queues and their work runs one after another. The GPU tests create a few
 # streams per test (serving slots, overlap checks): eight queues keep them apart. Set
 # before the HIP runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
