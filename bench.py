@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--serve-inflight", type=int, default=2,
                     help="batches in flight at once (one HIP stream each)")
     ap.add_argument("--serve-warmup", type=int, default=100, help="warm-up requests before the measured trace")
-    ap.add_argument("--serve-sweep", default="1000,3000",
+    ap.add_argument("--serve-sweep", default="1000,3000,10000",
                     help="extra arrival rates (req/s), 500 requests each, for the batch size and latency at load")
     ap.add_argument("--only-serving", action="store_true", help="run only the serving measurement")
     ap.add_argument("--only-field2d", action="store_true",
@@ -145,6 +145,9 @@ def solo_stages(R, gs, batches, dL_seed=7):
     import torch
     st = {k: [] for k in ("project", "bin_sort", "render_fwd", "render_bwd")}
     fwd_pairs = bwd_p = entries = 0
+    for bc in batches:
+        # entry capacity sized with a checked bin sort (grows only): the timed calls then fit
+        R.bin_sort(R.project([gs] * len(bc), bc), [gs.n] * len(bc), bc, check=True)
     gen = torch.Generator(device=gs.pos.device)
     gen.manual_seed(dL_seed)
     for bc in batches:
@@ -260,7 +263,9 @@ def serving_benchmark(args, dev):
         sweep_out[f"{int(r)}_req_per_s"] = {"requests": s2["requests"], "mean_batch": round(s2["mean_batch"], 3),
                                             "p50_ms": round(s2["p50_ms"], 3), "p99_ms": round(s2["p99_ms"], 3),
                                             "mpix_per_s": round(s2["mpix_per_s"], 1),
-                                            "overlapping_batch_pairs": o2["overlapping_pairs"]}
+                                            "overlapping_batch_pairs": o2["overlapping_pairs"],
+                                            "ms_two_batches_on_device": round(o2["overlap_ms"], 2),
+                                            "ms_device_busy": round(o2["busy_ms"], 2)}
     st["rate_sweep"] = sweep_out
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
 
@@ -772,7 +777,7 @@ def main():
     cams = [S.orbit_camera(2.0 * math.pi * i / args.views, 4.0, args.width, args.height) for i in range(args.views)]
     log(f"scene generated in {time.perf_counter() - t:.1f}s")
     cpu = None
-    if not args.no_cpu_baseline and not args.pmc_probe:
+    if not args.no_cpu_baseline and not args.pmc_probe and not args.roofline_only:
         # before the GPU is touched: the oracle's worker processes fork from this one
         log(f"cpu baseline ({_cpu_workers()} worker processes) ...")
         cpu = cpu_baseline(scene, cams[0], args.cpu_seconds)

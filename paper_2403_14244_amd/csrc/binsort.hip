@@ -58,6 +58,16 @@ struct DigitSplit {
     __host__ __device__ int shift(int p) const { return lo + p * base + (p < extra ? p : extra); }
 };
 
+// The segment sorts rank fixed 8-bit digits, [lo, lo + 8 passes) covering the differing
+// bits [lo, hi): bits at and above hi are equal within the segment, so ranking them too
+// leaves the order unchanged, and a compile-time width keeps the ballot chain free of
+// per-bit conditions (their masks otherwise take scalar registers the kernel runs short of).
+struct Split8 {
+    int passes, lo;
+    __device__ Split8(int lo_, int hi_) : passes(hi_ > lo_ ? (hi_ - lo_ + kRadixBits - 1) / kRadixBits : 0), lo(lo_) {}
+    __device__ int shift(int p) const { return lo + p * kRadixBits; }
+};
+
 // Digit of key k at (shift, bits).
 __device__ __forceinline__ uint32_t digit_at(uint32_t k, int shift, int bits) {
     return (k >> shift) & ((1u << bits) - 1u);
@@ -548,9 +558,9 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
     // on scalars
     const int lo = __builtin_amdgcn_readfirstlane(diff ? __builtin_ctz(diff) : 0);
     const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
-    const DigitSplit split(lo, hi);
+    const Split8 split(lo, hi);
     for (int pass = 0; pass < split.passes; ++pass) {
-        const int shift = split.shift(pass), bits = split.width(pass);
+        const int shift = split.shift(pass), bits = kRadixBits;
         zero_wcnt(sh, t);
         __syncthreads();
         wave_rank<kBigItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
@@ -628,7 +638,7 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
     // on scalars
     const int lo = __builtin_amdgcn_readfirstlane(diff ? __builtin_ctz(diff) : 0);
     const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
-    const DigitSplit split(lo, hi);
+    const Split8 split(lo, hi);
     const int passes = split.passes;
     uint32_t *src_k = sk0, *src_v = sv, *dst_k = sk1, *dst_v = pidx;
     if (passes > 0) {
@@ -641,14 +651,14 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
             for (int i = 0; i < kBigItems; ++i) kk[i] = src_k[start + min(c0 + (uint32_t)i * kBigThreads + t, n - 1)];
 #pragma unroll
             for (int i = 0; i < kBigItems; ++i)
-                if (c0 + (uint32_t)i * kBigThreads + t < n) atomicAdd(&sh.local[digit_at(kk[i], split.shift(0), split.width(0))], 1u);
+                if (c0 + (uint32_t)i * kBigThreads + t < n) atomicAdd(&sh.local[digit_at(kk[i], split.shift(0), kRadixBits)], 1u);
         }
         __syncthreads();
     }
     for (int pass = 0; pass < passes; ++pass) {
-        const int shift = split.shift(pass), bits = split.width(pass);
+        const int shift = split.shift(pass), bits = kRadixBits;
         const bool has_next = pass + 1 < passes;
-        const int next_shift = has_next ? split.shift(pass + 1) : 0, next_bits = has_next ? split.width(pass + 1) : 0;
+        const int next_shift = has_next ? split.shift(pass + 1) : 0, next_bits = kRadixBits;
         uint32_t all;
         const uint32_t h = t < kRadix ? sh.local[t] : 0u;
         const uint32_t rb = block_exclusive_scan<kBigWaves>(h, sh.tmp, all);
@@ -771,9 +781,9 @@ __device__ __forceinline__ void wave_sort_segment(uint32_t* __restrict__ buf, ui
     // on scalars
     const int lo = __builtin_amdgcn_readfirstlane(diff ? __builtin_ctz(diff) : 0);
     const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
-    const DigitSplit split(lo, hi);
+    const Split8 split(lo, hi);
     for (int pass = 0; pass < split.passes; ++pass) {
-        const int shift = split.shift(pass), bits = split.width(pass);
+        const int shift = split.shift(pass), bits = kRadixBits;
 #pragma unroll
         for (int q = 0; q < 4; ++q) cnt[4 * l + q] = 0u;
         __builtin_amdgcn_wave_barrier();
@@ -825,6 +835,10 @@ __device__ __forceinline__ void wave_sort_segment(uint32_t* __restrict__ buf, ui
 // different lines proceed in parallel.
 constexpr uint32_t kLongLists = 64;
 constexpr uint32_t kLongCounterStride = 32;   // words: one counter per 128-byte line
+// Segments longer than kSegMax (sorted through the workspace, several times the work of
+// the others) go to one more list, at kLongLists * per words, counted in counter slot
+// kLongLists; slot kLongLists + 1 is the work counter of step 6b.
+constexpr uint32_t kHugeSlot = kLongLists, kWorkSlot = kLongLists + 1, kLongCounters = kLongLists + 2;
 
 // Step 6a: one wave per tile sorts segments of up to kWaveSegMax entries and appends the
 // longer ones to the lists for step 6b.
@@ -844,7 +858,8 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     const uint32_t n = end - start;
     if (n > kWaveSegMax) {
         if (lane_id() == 0) {
-            const uint32_t j = tile % kLongLists, per = (tiles_total + kLongLists - 1) / kLongLists;
+            const uint32_t per = (tiles_total + kLongLists - 1) / kLongLists;
+            const uint32_t j = n > kSegMax ? kHugeSlot : tile % kLongLists;
             long_lists[j * per + atomicAdd(&long_counts[j * kLongCounterStride], 1u)] = tile;
         }
         return;
@@ -852,19 +867,22 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     wave_sort_segment(sh.buf[w], sh.cnt[w], tile, start, n, zs, pidx, keys64);
 }
 
-// Step 6b: a resident grid of G workgroups sorts the listed long segments, workgroup g
-// taking items g, g + G, g + 2G, ... of the lists read one after another, one segment at a
-// time, with stable LSD radix passes: in LDS up to kSegMax entries, through the workspace
-// beyond. The sort is bound by the latency of its barriers and ballot chains, not by
-// bytes, so the kernel is held to 64 VGPRs: four workgroups per CU instead of two.
+// Step 6b: a resident grid sorts the listed long segments one at a time, with stable LSD
+// radix passes: in LDS up to kSegMax entries, through the workspace beyond. Workgroups take
+// the next item from a device-wide counter (one atomic per segment: a few thousand per
+// call, against tens of microseconds of work each), the longest segments first, so that no
+// workgroup is left with a run of long ones while the others have finished. The sort is
+// bound by the latency of its barriers and ballot chains, not by bytes, so the kernel is
+// held to 64 VGPRs: four workgroups per CU instead of two.
 __global__ void __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(8))) segment_sort_big_kernel(
     const uint32_t* __restrict__ ranges, uint32_t tiles_total, const uint32_t* __restrict__ zs,
     uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p,
     uint64_t capacity, const int32_t* __restrict__ status, const uint32_t* __restrict__ long_lists,
-    const uint32_t* __restrict__ long_counts, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
+    uint32_t* __restrict__ long_counts, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
     uint32_t* __restrict__ sv) {
     __shared__ SegShared sh;
     __shared__ uint32_t s_first[kLongLists + 1];   // index of each list's first item in the sequence
+    __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
     if ((uint64_t)*count_p > capacity) return;
     const uint32_t t = threadIdx.x;
@@ -876,17 +894,31 @@ __global__ void __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_e
         if (t == 0) s_first[0] = 0u;
     }
     __syncthreads();
-    const uint32_t total = s_first[kLongLists], per = (tiles_total + kLongLists - 1) / kLongLists;
-    uint32_t j = 0;
-    for (uint32_t i = blockIdx.x; i < total; i += gridDim.x) {
-        while (s_first[j + 1] <= i) ++j;   // items ascend, so the list index only grows
-        const uint32_t tile = long_lists[j * per + (i - s_first[j])];
+    const uint32_t per = (tiles_total + kLongLists - 1) / kLongLists;
+    const uint32_t n_huge = long_counts[kHugeSlot * kLongCounterStride];
+    const uint32_t total = n_huge + s_first[kLongLists];
+    uint32_t* work = long_counts + kWorkSlot * kLongCounterStride;
+    for (;;) {
+        if (t == 0) s_item = atomicAdd(work, 1u);
+        __syncthreads();
+        const uint32_t i = s_item;
+        if (i >= total) break;   // uniform: every thread read the same item
+        uint32_t tile;
+        if (i < n_huge) {
+            tile = long_lists[kHugeSlot * per + i];
+        } else {
+            // list j holds items [s_first[j], s_first[j + 1]) of the rest: j = the number of
+            // lists that end at or before the item
+            const uint32_t r = i - n_huge;
+            const uint32_t j = (uint32_t)__popcll(ballot64(s_first[lane_id() + 1] <= r));
+            tile = long_lists[j * per + (r - s_first[j])];
+        }
         const uint32_t start = ranges[2 * tile], n = ranges[2 * tile + 1] - start;
         if (n <= kSegMax)
             segment_sort_lds(sh, tile, start, n, zs, pidx, keys64);
         else
             segment_sort_global(sh, tile, start, n, zs, pidx, keys64, sk0, sk1, sv);
-        __syncthreads();
+        __syncthreads();   // also orders every read of s_item before the next write
     }
 }
 
@@ -918,9 +950,10 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.off_z_b = off;        off = align256(off + capacity * 4);
     // zero-initialised region: the digit totals of the passes and the long-segment counts
     p.off_hist = off;       off += (size_t)kMaxPasses * kTileRadix * 4;
-    p.off_long_counts = off; off = align256(off + (size_t)kLongLists * kLongCounterStride * 4);
+    p.off_long_counts = off; off = align256(off + (size_t)kLongCounters * kLongCounterStride * 4);
     p.off_block_sums = off; off = align256(off + (size_t)(p.scan_blocks + 1) * 4);
-    p.off_long_lists = off; off = align256(off + (size_t)(tiles + kLongLists) * 4);
+    // kLongLists lists of at most `per` tiles, then the list of the longest segments
+    p.off_long_lists = off; off = align256(off + (size_t)(2 * tiles + 2 * kLongLists) * 4);
     p.off_tcount = off;     off = align256(off + (size_t)p.sort_tiles * kTileRadix * 4);
     p.bytes = off;
     return p;

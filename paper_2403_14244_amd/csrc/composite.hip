@@ -537,69 +537,6 @@ __global__ void __launch_bounds__(256) tile_class_scatter_kernel(const uint32_t*
     if (i < n_items) order[start[b] + base[b] + local] = i;
 }
 
-// XCD-banded queue order (large launches): workgroups are dispatched round-robin over the
-// eight XCDs, so XCD x runs queue positions x, x + 8, x + 16, ... It is given band x of the
-// tiles - the contiguous range of tile indices that xcd_swizzle gives it in spatial order,
-// neighbouring tiles sharing particles in its L2 - in longest-list-first order: position
-// x + 8 i holds the i-th longest tile of band x. Band of a tile, and its index in the band:
-__device__ __forceinline__ uint32_t xcd_band(uint32_t t, uint32_t n, uint32_t& i) {
-    const uint32_t q = n >> 3, r = n & 7u;
-    if (t < r * (q + 1u)) {
-        i = t % (q + 1u);
-        return t / (q + 1u);
-    }
-    const uint32_t u = t - r * (q + 1u);
-    i = u % q;
-    return r + u / q;
-}
-
-constexpr int kBands = 8;
-
-__global__ void __launch_bounds__(256) tile_band_hist_kernel(const uint32_t* __restrict__ ranges, uint32_t tile0,
-                                                             uint32_t n_items, uint32_t cap,
-                                                             uint32_t* __restrict__ band_hist) {
-    __shared__ uint32_t h[kBands * kBuckets];
-    for (int k = threadIdx.x; k < kBands * kBuckets; k += 256) h[k] = 0u;
-    __syncthreads();
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < n_items; t += gridDim.x * blockDim.x) {
-        uint32_t i;
-        const uint32_t x = xcd_band(t, n_items, i);
-        atomicAdd(&h[x * kBuckets + length_bucket(ranges, tile0 + t, cap)], 1u);
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kBands * kBuckets; k += 256)
-        if (h[k]) atomicAdd(&band_hist[k], h[k]);
-}
-
-__global__ void __launch_bounds__(256) tile_band_scatter_kernel(const uint32_t* __restrict__ ranges, uint32_t tile0,
-                                                                uint32_t n_items, uint32_t cap,
-                                                                const uint32_t* __restrict__ band_hist,
-                                                                uint32_t* __restrict__ band_cursor,
-                                                                uint32_t* __restrict__ order) {
-    __shared__ uint32_t start[kBands * kBuckets], cnt[kBands * kBuckets], base[kBands * kBuckets];
-    for (int k = threadIdx.x; k < kBands * kBuckets; k += 256) {
-        const int x = k / kBuckets, c = k % kBuckets;
-        uint32_t sum = 0;
-        for (int b = kBuckets - 1; b > c; --b) sum += band_hist[x * kBuckets + b];
-        start[k] = sum;
-        cnt[k] = 0u;
-    }
-    __syncthreads();
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t k = 0, local = 0, x = 0;
-    if (t < n_items) {
-        uint32_t i;
-        x = xcd_band(t, n_items, i);
-        k = x * kBuckets + length_bucket(ranges, tile0 + t, cap);
-        local = atomicAdd(&cnt[k], 1u);
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < kBands * kBuckets; j += 256)
-        if (cnt[j]) base[j] = atomicAdd(&band_cursor[j], cnt[j]);
-    __syncthreads();
-    if (t < n_items) order[x + (uint32_t)kBands * (start[k] + base[k] + local)] = t;
-}
-
 int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, const isogs_bins* bins,
                       const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
                       uint32_t* n_last, float* ckpt, hipStream_t stream) {
@@ -634,28 +571,19 @@ uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv) {
     return most;
 }
 
-// Queue layout: the global class histogram (kBuckets words, read by the wide and backward
-// kernels), its cursors, the per-band histograms and cursors, then the order.
-constexpr size_t kQueueHead = 2 * kBuckets + 2 * kBands * kBuckets;
+// Queue layout: the class histogram (kBuckets words, read by the wide and backward
+// kernels), its cursors, then the order.
+constexpr size_t kQueueHead = 2 * kBuckets;
 
 size_t tile_queue_words(uint32_t n_tiles) { return kQueueHead + (size_t)n_tiles; }
 
 uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0, uint32_t n_tiles, uint32_t cap,
-                            hipStream_t stream, bool banded) {
+                            hipStream_t stream) {
     uint32_t* hist = q;
     uint32_t* cursor = q + kBuckets;
-    uint32_t* band_hist = q + 2 * kBuckets;
-    uint32_t* band_cursor = band_hist + kBands * kBuckets;
     uint32_t* order = q + kQueueHead;
     hipLaunchKernelGGL(fill_u32_kernel_c, dim3(1), dim3(128), 0, stream, q, (uint32_t)kQueueHead);
     const unsigned hb = std::min<unsigned>(256u, (n_tiles + 255u) / 256u);
-    if (banded && n_tiles >= 8 * kBands) {
-        hipLaunchKernelGGL(tile_band_hist_kernel, dim3(hb), dim3(256), 0, stream, ranges, tile0, n_tiles, cap,
-                           band_hist);
-        hipLaunchKernelGGL(tile_band_scatter_kernel, dim3((n_tiles + 255u) / 256u), dim3(256), 0, stream, ranges,
-                           tile0, n_tiles, cap, band_hist, band_cursor, order);
-        return order;
-    }
     hipLaunchKernelGGL(tile_class_hist_kernel, dim3(hb), dim3(256), 0, stream, ranges, tile0, n_tiles, cap, hist);
     hipLaunchKernelGGL(tile_class_scatter_kernel, dim3((n_tiles + 255u) / 256u), dim3(256), 0, stream, ranges, tile0,
                        n_tiles, cap, hist, cursor, order);
@@ -729,11 +657,7 @@ int launch_render_fwd_ordered(const isogs_projected* proj, const float* conic, c
         fill_render_pack(pk, cams, n_per_view, v0, nv, p_off, tile_base, pix_off, blocks);
         set_render_limits(pk, n_per_view, nv, bins->capacity);
         if (!blocks) continue;
-        // large launches of the compact walk: XCD-banded order (L2 locality of neighbouring
-        // tiles); the wide and pipelined walks keep the global longest-first order (their
-        // launches are bound by the longest tiles)
-        const bool banded = !(flags & ISOGS_FWD_WIDE) && blocks > kPipeTileLimit;
-        const uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream, banded);
+        const uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
         OrderedArgs a{reinterpret_cast<const float4*>(proj->record), reinterpret_cast<const float2*>(conic),
                       bins->pidx, bins->ranges, bins->status, bg[0], bg[1], bg[2], image, T_final, n_last,
                       reinterpret_cast<float4*>(ckpt), order, q, 0u};

@@ -39,10 +39,9 @@ size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv);
 // the compositing kernels), the class cursors, and the order array (returned).
 size_t tile_queue_words(uint32_t n_tiles);
 uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv);
-// banded: the XCD-banded order of large compact launches (each XCD a contiguous band of
-// tiles, longest first within it); otherwise one global longest-first order.
+// The tiles of a launch in longest-list-first order (length classes 0 and 32 - clz(len)).
 uint32_t* launch_tile_queue(uint32_t* q, const uint32_t* ranges, uint32_t tile0, uint32_t n_tiles, uint32_t cap,
-                            hipStream_t stream, bool banded = false);
+                            hipStream_t stream);
 // Workgroups of `threads` threads of `kernel` resident on the whole GPU at once.
 int resident_blocks(const void* kernel, int threads);
 
