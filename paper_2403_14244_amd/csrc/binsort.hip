@@ -112,12 +112,15 @@ __global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ p,
 __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const uint32_t* __restrict__ cnt, uint32_t n,
                                                                    uint32_t* __restrict__ block_sums) {
     __shared__ uint32_t s_tmp[4];
-    const uint32_t base = blockIdx.x * kScanBlock;
+    const uint32_t base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
     uint32_t acc = 0;
+    if (base + kScanItems <= n && (reinterpret_cast<uintptr_t>(cnt) & 15u) == 0) {
+        const uint4 a = *reinterpret_cast<const uint4*>(cnt + base);
+        const uint4 b = *reinterpret_cast<const uint4*>(cnt + base + 4);
+        acc = a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w;
+    } else {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const uint32_t i = base + k * kScanThreads + threadIdx.x;
-        acc += (i < n) ? cnt[i] : 0u;
+        for (int k = 0; k < kScanItems; ++k) acc += (base + k < n) ? cnt[base + k] : 0u;
     }
     uint32_t total;
     block_exclusive_scan(acc, s_tmp, total);
@@ -125,17 +128,26 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const uint32_
 }
 
 // Step 2b: exclusive scan of the block sums (one workgroup), total and capacity status.
+// Each thread takes a run of consecutive sums, so one workgroup scan covers up to
+// kScanThreads * kTopItems of them at a time (a 10-view call of 1M particles has about 5000).
+constexpr uint32_t kTopItems = 32;
 __global__ void __launch_bounds__(kScanThreads) scan_top_kernel(uint32_t* __restrict__ block_sums, uint32_t nb,
                                                                 uint64_t capacity, uint32_t* __restrict__ count,
                                                                 int32_t* __restrict__ status) {
     __shared__ uint32_t s_tmp[4];
     uint64_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nb; b0 += kScanThreads) {
-        const uint32_t i = b0 + threadIdx.x;
-        const uint32_t x = (i < nb) ? block_sums[i] : 0u;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kScanThreads * kTopItems) {
+        const uint32_t per = (min(nb - b0, kScanThreads * kTopItems) + kScanThreads - 1) / kScanThreads;
+        const uint32_t i0 = b0 + threadIdx.x * per, i1 = min(i0 + per, nb);
+        uint32_t sum = 0;
+        for (uint32_t i = i0; i < i1; ++i) sum += block_sums[i];
         uint32_t total;
-        const uint32_t ex = block_exclusive_scan(x, s_tmp, total);
-        if (i < nb) block_sums[i] = (uint32_t)(carry + ex);
+        uint64_t run = carry + block_exclusive_scan(sum, s_tmp, total);
+        for (uint32_t i = i0; i < i1; ++i) {
+            const uint32_t x = block_sums[i];
+            block_sums[i] = (uint32_t)run;
+            run += x;
+        }
         carry += total;
     }
     if (threadIdx.x == 0) {
@@ -150,21 +162,37 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
                                                                  const uint32_t* __restrict__ block_prefix,
                                                                  uint32_t* __restrict__ offsets) {
     __shared__ uint32_t s_tmp[4];
-    // each thread scans kScanItems consecutive particles (blocked), lanes then threads
+    // each thread scans kScanItems consecutive particles (blocked), lanes then threads; whole
+    // runs move as two 16-byte loads and stores when both arrays allow it
+    static_assert(kScanItems == 8, "two 16-byte vectors per thread");
     const uint32_t base = blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+    const bool vec = base + kScanItems <= n && ((reinterpret_cast<uintptr_t>(cnt) | reinterpret_cast<uintptr_t>(offsets)) & 15u) == 0;
     uint32_t v[kScanItems];
+    if (vec) {
+        const uint4 a = *reinterpret_cast<const uint4*>(cnt + base);
+        const uint4 b = *reinterpret_cast<const uint4*>(cnt + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? cnt[base + k] : 0u;
+    }
     uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < n) ? cnt[base + k] : 0u;
-        acc += v[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) acc += v[k];
     uint32_t total;
-    uint32_t run = block_exclusive_scan(acc, s_tmp, total) + block_prefix[blockIdx.x];
+    const uint32_t run = block_exclusive_scan(acc, s_tmp, total) + block_prefix[blockIdx.x];
+    uint32_t o[kScanItems];
+    o[0] = run;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) offsets[base + k] = run;
-        run += v[k];
+    for (int k = 1; k < kScanItems; ++k) o[k] = o[k - 1] + v[k - 1];
+    if (vec) {
+        *reinterpret_cast<uint4*>(offsets + base) = make_uint4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<uint4*>(offsets + base + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < n) offsets[base + k] = o[k];
     }
 }
 
@@ -526,7 +554,10 @@ __device__ __forceinline__ uint32_t digit_wave_prefix(SegShared& sh, uint32_t d)
 
 // Segment of n <= kSegMax entries sorted in LDS: items stay in registers between passes,
 // each pass ranks by one 8-bit digit of the depth bits, reorders through LDS and reloads
-// in position order. Only the bits that differ within the segment are sorted on.
+// in position order. Only the bits that differ within the segment are sorted on. The
+// positions past the segment's end, up to the wave's whole rounds, carry the key with all
+// bits set: its digit is the largest of every pass and those positions come after every
+// entry, so stability keeps them at the end and no pass needs a per-item validity mask.
 __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, uint32_t start, uint32_t n,
                                                  const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
                                                  uint64_t* __restrict__ keys64) {
@@ -534,22 +565,21 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
     const int items = (int)((n + kBigThreads - 1) / kBigThreads);
     const uint32_t wbase = w * kWave * (uint32_t)items;   // wave w owns positions [wbase, wbase + 64 items)
     uint32_t k[kBigItems], v[kBigItems], rk[kBigItems];
-    uint32_t valid = 0;
     uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
     // loads clamped into the segment rather than predicated, so that all of them are in
     // flight at once
 #pragma unroll
     for (int i = 0; i < kBigItems; ++i) {
         const uint32_t p = wbase + (uint32_t)i * kWave + l;
-        valid |= (uint32_t)(i < items && p < n) << i;
         v[i] = pidx[start + min(p, n - 1)];
         k[i] = zs[start + min(p, n - 1)];
     }
 #pragma unroll
     for (int i = 0; i < kBigItems; ++i) {
-        const bool ok = (valid >> i) & 1u;
+        const bool ok = i < items && wbase + (uint32_t)i * kWave + l < n;
         k_or |= ok ? k[i] : 0u;
         k_and &= ok ? k[i] : 0xFFFFFFFFu;
+        k[i] = ok ? k[i] : 0xFFFFFFFFu;
     }
     uint32_t all_or, all_and;
     block_or_and(k_or, k_and, sh.tmp, all_or, all_and);
@@ -560,10 +590,10 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
     const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
     const Split8 split(lo, hi);
     for (int pass = 0; pass < split.passes; ++pass) {
-        const int shift = split.shift(pass), bits = kRadixBits;
+        const int shift = split.shift(pass);
         zero_wcnt(sh, t);
         __syncthreads();
-        wave_rank<kBigItems>(k, shift, bits, valid, items, sh.wcnt[w], rk);
+        wave_rank<kBigItems>(k, shift, kRadixBits, 0xFFFFFFFFu, items, sh.wcnt[w], rk);
         __syncthreads();
         const uint32_t tot = t < kRadix ? digit_wave_prefix(sh, t) : 0u;
         uint32_t all;
@@ -573,8 +603,8 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
         uint32_t pos[kBigItems];
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i) {
-            if ((valid >> i) & 1u) {
-                const uint32_t d = digit_at(k[i], shift, bits);
+            if (i < items) {
+                const uint32_t d = digit_at(k[i], shift, kRadixBits);
                 pos[i] = sh.local[d] + sh.wcnt[w][d] + rk[i];
                 sh.buf[pos[i]] = k[i];
             }
@@ -582,21 +612,21 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i)
-            if ((valid >> i) & 1u) k[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
+            if (i < items) k[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i)
-            if ((valid >> i) & 1u) sh.buf[pos[i]] = v[i];
+            if (i < items) sh.buf[pos[i]] = v[i];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i)
-            if ((valid >> i) & 1u) v[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
+            if (i < items) v[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
     }
     // every read of the segment happened before block_or_and's barrier: in place is safe
 #pragma unroll
     for (int i = 0; i < kBigItems; ++i) {
-        if (!((valid >> i) & 1u)) continue;
         const uint32_t p = wbase + (uint32_t)i * kWave + l;
+        if (i >= items || p >= n) continue;
         pidx[start + p] = v[i];
         if (keys64) keys64[start + p] = ((uint64_t)tile << 32) | k[i];
     }
