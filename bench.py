@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--serve-sweep", default="1000,3000,10000",
                     help="extra arrival rates (req/s), 500 requests each, for the batch size and latency at load")
     ap.add_argument("--only-serving", action="store_true", help="run only the serving measurement")
+    ap.add_argument("--only-stress", action="store_true",
+                    help="run only the 6M 4K stress workload and print its JSON object")
     ap.add_argument("--only-field2d", action="store_true",
                     help="run only the 2D fit (2000 kernels, 512x512) and print its JSON object")
     ap.add_argument("--no-extra-workloads", action="store_true",
@@ -378,10 +380,26 @@ def stress_workload(dev, iters=3):
         e1.record()
         torch.cuda.synchronize()
         fwd.append(e0.elapsed_time(e1))
+    # load balance of the compositing launch: per-workgroup clock stamps (100 MHz) of the
+    # forward's compact walk and of the training step's wide walk, over the workgroups that
+    # composited a non-empty list
+    fp = R.project([g_init] * len(cams), cams)
+    bins = R.bin_sort(fp, [g_init.n] * len(cams), cams)
+    balance = {}
+    for name, wide in (("compact_walk", False), ("wide_walk", True)):
+        st = R.render_fwd_ordered(fp, [g_init.n] * len(cams), bins, cams, wide=wide, times=True)[3]
+        st = st.cpu().numpy()
+        on = st[:, 0] != 0
+        dur = (st[on, 1] - st[on, 0]) * 1e-2     # us
+        balance[name] = {"workgroups": int(on.sum()), "mean_us": round(float(dur.mean()), 2),
+                         "p99_us": round(float(np.percentile(dur, 99)), 1), "max_us": round(float(dur.max()), 1),
+                         "max_over_mean": round(float(dur.max() / dur.mean()), 1),
+                         "launch_span_us": round(float((st[on, 1].max() - st[on, 0].min()) * 1e-2), 1)}
+    del fp, bins
     return {"workload": "stress6m_4k_x8", "fwd_bwd_ms_per_iter": round(dt * 1e3, 2),
             "fwd_ms": round(sorted(fwd)[1], 2), "views": len(cams), "width": 3840, "height": 2160,
             "gaussians": 6_000_000, "mpix_per_s_fwd": round(len(cams) * 3840 * 2160 / (sorted(fwd)[1] * 1e-3) / 1e6, 1),
-            "tile_lists": lists}
+            "tile_lists": lists, "composite_workgroup_time": balance}
 
 
 def aniso_workload(dev, scene_iso, cams, batch_views=10, fwd_views=20, train_iters=10):
@@ -766,6 +784,10 @@ def main():
     import paper_2403_14244_amd as P
     if args.only_field2d:
         print(json.dumps(field2d_workload("cuda")), flush=True)
+        return
+    if args.only_stress:
+        torch.cuda.set_device(0)
+        print(json.dumps(stress_workload(torch.device("cuda:0"))), flush=True)
         return
     if args.only_serving:
         torch.cuda.set_device(0)

@@ -212,7 +212,8 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
                      float* checkpoints, void* stream);
 
 /* Flags of isogs_render_fwd_ordered. */
-#define ISOGS_FWD_WIDE 1u  /* wide walk for the longest tiles of small launches (see below) */
+#define ISOGS_FWD_WIDE 1u   /* wide walk for the longest tiles of small launches (see below) */
+#define ISOGS_FWD_TIMES 2u  /* per-workgroup clock stamps in the workspace (see below) */
 
 /* Same outputs as isogs_render_fwd (bitwise), with the tiles dispatched longest entry list
  * first: a queue of the tiles sorted by list length is built on the device and workgroup b
@@ -227,9 +228,15 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view,
  *          then agree with isogs_render_fwd up to rounding (products and sums associated
  *          per step) instead of bitwise; a single 1080p view composites about twice as
  *          fast. With or without the flag, a view's result does not depend on the other
- *          views of the launch.
- *   ws, ws_bytes  workspace (query with ws == NULL): the queue, 4 bytes per tile of the
- *                 largest group of 16 views, plus bookkeeping
+ *          views of the launch. ISOGS_FWD_TIMES (with either walk) adds a measurement of
+ *          load balance: the workspace grows by 80 bytes per tile of the call, and from byte
+ *          offset (the size queried without ISOGS_FWD_TIMES) - 256 it receives one
+ *          {start, end} pair of uint64 stamps of the GPU's constant 100 MHz clock per
+ *          workgroup: the workgroups of the launch for the group of views whose first tile
+ *          is the call's tile t occupy pairs 5t, 5t + 1, ...; a workgroup whose list was
+ *          empty, or that had no tile, leaves {0, 0}. The images are the same as without it.
+ *   ws, ws_bytes  workspace (query with ws == NULL, with the same flags): the queue, 4 bytes
+ *                 per tile of the largest group of 16 views, plus bookkeeping
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_WORKSPACE, ISOGS_ERR_DEVICE. */
 int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_view,
                              const isogs_bins* bins, const isogs_camera* cams, int32_t n_views,

@@ -18,6 +18,7 @@ ISOGS_ERR_WORKSPACE = -3
 ISOGS_ERR_DEVICE = -4
 
 ISOGS_FWD_WIDE = 1
+ISOGS_FWD_TIMES = 2
 ISOGS_STATIC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_render_fwd", "isogs_render_fwd_ordered",

@@ -209,7 +209,8 @@ int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_v
     if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
     if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
     if ((rc = check_cameras(cams, n_views))) return rc;
-    const size_t need = isogs::render_fwd_ordered_ws(cams, n_views);
+    if (flags & ~(ISOGS_FWD_WIDE | ISOGS_FWD_TIMES)) return fail(ISOGS_ERR_INVALID, "unknown flags %u", flags);
+    const size_t need = isogs::render_fwd_ordered_ws(cams, n_views, flags);
     if (!ws) {
         *ws_bytes = need;
         return ISOGS_OK;
@@ -222,7 +223,6 @@ int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_v
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
-    if (flags & ~ISOGS_FWD_WIDE) return fail(ISOGS_ERR_INVALID, "unknown flags %u", flags);
     if (isogs::launch_render_fwd_ordered(proj, nullptr, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
                                          checkpoints, flags, ws, (hipStream_t)stream))
         return device_fail("isogs_render_fwd_ordered");
@@ -303,7 +303,8 @@ int isogs_aniso_render_fwd(const isogs_aniso_projected* proj, const int32_t* n_p
     if (!n_per_view) return fail(ISOGS_ERR_INVALID, "n_per_view is NULL");
     if (!ws_bytes) return fail(ISOGS_ERR_INVALID, "ws_bytes is NULL");
     if ((rc = check_cameras(cams, n_views))) return rc;
-    const size_t need = isogs::render_fwd_ordered_ws(cams, n_views);
+    if (flags & ~(ISOGS_FWD_WIDE | ISOGS_FWD_TIMES)) return fail(ISOGS_ERR_INVALID, "unknown flags %u", flags);
+    const size_t need = isogs::render_fwd_ordered_ws(cams, n_views, flags);
     if (!ws) {
         *ws_bytes = need;
         return ISOGS_OK;
@@ -316,7 +317,6 @@ int isogs_aniso_render_fwd(const isogs_aniso_projected* proj, const int32_t* n_p
     if ((rc = check_aniso_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
     if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
-    if (flags & ~ISOGS_FWD_WIDE) return fail(ISOGS_ERR_INVALID, "unknown flags %u", flags);
     // a NULL conic selects the isotropic walk: give the anisotropic one a valid address
     // even when there is no particle
     static float no_conic[2];

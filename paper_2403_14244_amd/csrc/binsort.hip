@@ -867,8 +867,13 @@ constexpr uint32_t kLongLists = 64;
 constexpr uint32_t kLongCounterStride = 32;   // words: one counter per 128-byte line
 // Segments longer than kSegMax (sorted through the workspace, several times the work of
 // the others) go to one more list, at kLongLists * per words, counted in counter slot
-// kLongLists; slot kLongLists + 1 is the work counter of step 6b.
-constexpr uint32_t kHugeSlot = kLongLists, kWorkSlot = kLongLists + 1, kLongCounters = kLongLists + 2;
+// kLongLists; slot kLongLists + 1 is the work counter of step 6b. Segments longer than
+// kChunkMin are sorted by all workgroups together (step 6c): they are listed after that,
+// at kLongLists * per + tiles words, counted in slot kLongLists + 2; slot kLongLists + 3
+// receives their number of 4096-entry chunks.
+constexpr uint32_t kHugeSlot = kLongLists, kWorkSlot = kLongLists + 1, kChunkSlot = kLongLists + 2,
+                   kChunkTotalSlot = kLongLists + 3, kLongCounters = kLongLists + 4;
+constexpr uint32_t kChunkMin = 16384;
 
 // Step 6a: one wave per tile sorts segments of up to kWaveSegMax entries and appends the
 // longer ones to the lists for step 6b.
@@ -889,8 +894,13 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     if (n > kWaveSegMax) {
         if (lane_id() == 0) {
             const uint32_t per = (tiles_total + kLongLists - 1) / kLongLists;
-            const uint32_t j = n > kSegMax ? kHugeSlot : tile % kLongLists;
-            long_lists[j * per + atomicAdd(&long_counts[j * kLongCounterStride], 1u)] = tile;
+            if (n > kChunkMin) {
+                long_lists[kLongLists * per + tiles_total +
+                           atomicAdd(&long_counts[kChunkSlot * kLongCounterStride], 1u)] = tile;
+            } else {
+                const uint32_t j = n > kSegMax ? kHugeSlot : tile % kLongLists;
+                long_lists[j * per + atomicAdd(&long_counts[j * kLongCounterStride], 1u)] = tile;
+            }
         }
         return;
     }
@@ -952,6 +962,253 @@ __global__ void __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_e
     }
 }
 
+// Step 6c: the segments longer than kChunkMin, sorted by every workgroup together: each is
+// cut into 4096-entry chunks and sorted by stable LSD passes over the four bytes of the
+// depth bits, each pass as count (a digit histogram per chunk), scan (per segment: for each
+// digit, the prefix over its chunks, placed after the smaller digits' entries) and scatter
+// (each chunk ranks its entries per digit with ballots and writes them to their places,
+// reordered in LDS into runs). A pass whose byte is the same for every entry of a segment
+// would leave it unchanged: the scan marks it skipped and the segment stays where it is, so
+// each segment keeps its own record of which buffer holds it. Buffers: A = (depth bits,
+// pidx) as the tile passes left them, B = workspace. The grids are resident and stride over
+// the chunks (or segments); with no long segment every kernel leaves at once.
+struct ChunkPlan {
+    uint32_t* seg_start;    // [h] first entry of segment s
+    uint32_t* seg_n;        // [h] its length
+    uint32_t* chunk_first;  // [h + 1] index of its first chunk
+    uint32_t* seg_loc;      // [5][h] buffer holding segment s before pass p (0 = A, 1 = B)
+    uint32_t* seg_tile;     // [h] its tile
+    uint32_t* chunk_seg;    // [chunks] segment of each chunk
+    uint32_t* cnt;          // [chunks][kRadix] digit counts, then output bases
+    uint32_t h_max;
+};
+
+// One workgroup: the segment table, the chunk table and the chunk total.
+__global__ void __launch_bounds__(256) chunk_setup_kernel(const uint32_t* __restrict__ ranges, uint32_t tiles_total,
+                                                          const uint32_t* __restrict__ long_lists,
+                                                          uint32_t* __restrict__ long_counts, ChunkPlan cp) {
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t per = (tiles_total + kLongLists - 1) / kLongLists;
+    const uint32_t h = min(long_counts[kChunkSlot * kLongCounterStride], cp.h_max);
+    const uint32_t* list = long_lists + kLongLists * per + tiles_total;
+    uint32_t carry = 0;
+    for (uint32_t s0 = 0; s0 < h; s0 += 256) {
+        const uint32_t sid = s0 + threadIdx.x;
+        uint32_t start = 0, n = 0, tile = 0;
+        if (sid < h) {
+            tile = list[sid];
+            start = ranges[2 * tile];
+            n = ranges[2 * tile + 1] - start;
+        }
+        const uint32_t nch = (n + kSortTile - 1) / kSortTile;
+        uint32_t total;
+        const uint32_t first = carry + block_exclusive_scan(nch, s_tmp, total);
+        if (sid < h) {
+            cp.seg_start[sid] = start;
+            cp.seg_n[sid] = n;
+            cp.seg_tile[sid] = tile;
+            cp.chunk_first[sid] = first;
+            cp.seg_loc[sid] = 0u;
+            for (uint32_t c = 0; c < nch; ++c) cp.chunk_seg[first + c] = sid;
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        cp.chunk_first[h] = carry;
+        long_counts[kChunkTotalSlot * kLongCounterStride] = carry;
+    }
+}
+
+__device__ __forceinline__ uint32_t chunk_count_of(const uint32_t* long_counts) {
+    return long_counts[kChunkTotalSlot * kLongCounterStride];
+}
+
+// Entries [lo, hi) of chunk c, its segment and the buffer holding it before pass p.
+struct ChunkSpan {
+    uint32_t s, lo, hi, loc;
+};
+
+__device__ __forceinline__ ChunkSpan chunk_span(const ChunkPlan& cp, uint32_t c, int pass) {
+    ChunkSpan r;
+    r.s = cp.chunk_seg[c];
+    const uint32_t start = cp.seg_start[r.s], end = start + cp.seg_n[r.s];
+    r.lo = start + (c - cp.chunk_first[r.s]) * kSortTile;
+    r.hi = min(r.lo + kSortTile, end);
+    r.loc = cp.seg_loc[pass * cp.h_max + r.s];
+    return r;
+}
+
+__global__ void __launch_bounds__(kSortThreads) chunk_count_kernel(const uint32_t* __restrict__ a_key,
+                                                                   const uint32_t* __restrict__ b_key,
+                                                                   const uint32_t* __restrict__ long_counts,
+                                                                   ChunkPlan cp, int pass) {
+    __shared__ uint32_t s_h[kRadix];
+    const uint32_t nc = chunk_count_of(long_counts), t = threadIdx.x;
+    const int shift = 8 * pass;
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const ChunkSpan sp = chunk_span(cp, c, pass);
+        const uint32_t* key = sp.loc ? b_key : a_key;
+        s_h[t] = 0u;
+        // all of the chunk's loads in flight at once (clamped into the chunk), then the counts
+        uint32_t k[kSortItems];
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) k[i] = key[min(sp.lo + i * kSortThreads + t, sp.hi - 1)];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            if (sp.lo + i * kSortThreads + t >= sp.hi) continue;
+            const uint32_t d = digit_at(k[i], shift, 8);
+            // a byte shared by the whole wave (the leading bytes of close depths): one add
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+            const uint64_t act = ballot64(true);
+            if (ballot64(d != d0) == 0) {
+                if (lane_id() == (uint32_t)__builtin_ctzll(act)) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
+            } else {
+                atomicAdd(&s_h[d], 1u);
+            }
+        }
+        __syncthreads();
+        cp.cnt[(size_t)c * kRadix + t] = s_h[t];
+        __syncthreads();
+    }
+}
+
+// One segment per workgroup iteration, thread d for digit d.
+__global__ void __launch_bounds__(256) chunk_scan_kernel(const uint32_t* __restrict__ long_counts, ChunkPlan cp,
+                                                         int pass) {
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_nz[4];
+    static_assert(kRadix == 256, "one thread per digit");
+    const uint32_t h = min(long_counts[kChunkSlot * kLongCounterStride], cp.h_max), d = threadIdx.x;
+    for (uint32_t sid = blockIdx.x; sid < h; sid += gridDim.x) {
+        const uint32_t c0 = cp.chunk_first[sid], c1 = cp.chunk_first[sid + 1];
+        uint32_t run = 0;
+        for (uint32_t c = c0; c < c1; ++c) {
+            const uint32_t x = cp.cnt[(size_t)c * kRadix + d];
+            cp.cnt[(size_t)c * kRadix + d] = run;
+            run += x;
+        }
+        // a byte the same for every entry: the pass would not move anything
+        const uint32_t nz = (uint32_t)__popcll(ballot64(run != 0u));
+        if (lane_id() == 0) s_nz[d >> 6] = nz;
+        uint32_t total;
+        const uint32_t base = block_exclusive_scan(run, s_tmp, total) + cp.seg_start[sid];
+        const bool skip = s_nz[0] + s_nz[1] + s_nz[2] + s_nz[3] <= 1u;
+        const uint32_t loc = cp.seg_loc[pass * cp.h_max + sid];
+        if (d == 0) cp.seg_loc[(pass + 1) * cp.h_max + sid] = skip ? loc : loc ^ 1u;
+        if (!skip)
+            for (uint32_t c = c0; c < c1; ++c) cp.cnt[(size_t)c * kRadix + d] += base;
+        __syncthreads();   // s_nz and s_tmp are reused by the next segment
+    }
+}
+
+__global__ void __launch_bounds__(kSortThreads) chunk_scatter_kernel(uint32_t* __restrict__ a_key,
+                                                                     uint32_t* __restrict__ a_val,
+                                                                     uint32_t* __restrict__ b_key,
+                                                                     uint32_t* __restrict__ b_val,
+                                                                     const uint32_t* __restrict__ long_counts,
+                                                                     ChunkPlan cp, int pass) {
+    __shared__ uint32_t s_buf[kSortTile];
+    __shared__ uint32_t s_wcnt[4][kRadix];
+    __shared__ uint32_t s_local[kRadix];
+    __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_tmp[4];
+    const uint32_t nc = chunk_count_of(long_counts), t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int shift = 8 * pass;
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const ChunkSpan sp = chunk_span(cp, c, pass);
+        const uint32_t loc_next = cp.seg_loc[(pass + 1) * cp.h_max + sp.s];
+        if (loc_next == sp.loc) continue;   // skipped pass: uniform over the workgroup
+        const uint32_t* skey = sp.loc ? b_key : a_key;
+        const uint32_t* sval = sp.loc ? b_val : a_val;
+        uint32_t* dkey = sp.loc ? a_key : b_key;
+        uint32_t* dval = sp.loc ? a_val : b_val;
+        const uint32_t n_here = sp.hi - sp.lo;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_wcnt[k][t] = 0u;
+        // wave w owns chunk positions [w * 1024, +1024), item i of lane l at i * 64 + l;
+        // positions past the chunk's end carry the all-ones key (largest digit, placed last)
+        uint32_t k[kSortItems], v[kSortItems], rk[kSortItems];
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t j = w * (kSortTile / 4) + i * kWave + lane;
+            const uint32_t idx = sp.lo + min(j, n_here - 1);
+            k[i] = j < n_here ? skey[idx] : 0xFFFFFFFFu;
+            v[i] = sval[idx];
+        }
+        s_base[t] = cp.cnt[(size_t)c * kRadix + t];
+        __syncthreads();
+        wave_rank<kSortItems>(k, shift, kRadixBits, 0xFFFFFFFFu, kSortItems, s_wcnt[w], rk);
+        __syncthreads();
+        const uint32_t c0 = s_wcnt[0][t], c1 = s_wcnt[1][t], c2 = s_wcnt[2][t], c3 = s_wcnt[3][t];
+        s_wcnt[0][t] = 0u;
+        s_wcnt[1][t] = c0;
+        s_wcnt[2][t] = c0 + c1;
+        s_wcnt[3][t] = c0 + c1 + c2;
+        uint32_t tot;
+        const uint32_t lb = block_exclusive_scan(c0 + c1 + c2 + c3, s_tmp, tot);
+        s_local[t] = lb;
+        __syncthreads();
+        uint32_t lpos[kSortItems];
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t d = digit_at(k[i], shift, kRadixBits);
+            lpos[i] = s_local[d] + s_wcnt[w][d] + rk[i];
+            s_buf[lpos[i]] = k[i];
+        }
+        __syncthreads();
+        // runs per digit: position j of the reordered chunk goes to base[d] + (j - local[d])
+        uint32_t dig[kSortItems];
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t j = t + i * kSortThreads;
+            const uint32_t key = s_buf[j];
+            dig[i] = digit_at(key, shift, kRadixBits);
+            if (j < n_here) dkey[s_base[dig[i]] + (j - s_local[dig[i]])] = key;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) s_buf[lpos[i]] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t j = t + i * kSortThreads;
+            if (j < n_here) dval[s_base[dig[i]] + (j - s_local[dig[i]])] = s_buf[j];
+        }
+        __syncthreads();   // LDS is reused by the next chunk
+    }
+}
+
+// The sorted segments into pidx (those left in B) and keys64.
+__global__ void __launch_bounds__(256) chunk_final_kernel(const uint32_t* __restrict__ b_key,
+                                                          const uint32_t* __restrict__ b_val,
+                                                          const uint32_t* __restrict__ a_key,
+                                                          uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64,
+                                                          const uint32_t* __restrict__ long_counts, ChunkPlan cp) {
+    const uint32_t nc = chunk_count_of(long_counts);
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const ChunkSpan sp = chunk_span(cp, c, 4);
+        if (!sp.loc && !keys64) continue;   // already in place
+        const uint64_t tile = cp.seg_tile[sp.s];
+        const uint32_t* key = sp.loc ? b_key : a_key;
+        static_assert(kSortTile == 16 * 256, "sixteen entries per thread");
+        uint32_t v[16], k[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t j = min(sp.lo + i * 256 + threadIdx.x, sp.hi - 1);
+            v[i] = sp.loc ? b_val[j] : 0u;
+            k[i] = keys64 ? key[j] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t j = sp.lo + i * 256 + threadIdx.x;
+            if (j >= sp.hi) continue;
+            if (sp.loc) pidx[j] = v[i];
+            if (keys64) keys64[j] = (tile << 32) | k[i];
+        }
+    }
+}
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv, uint64_t capacity) {
@@ -982,8 +1239,16 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.off_hist = off;       off += (size_t)kMaxPasses * kTileRadix * 4;
     p.off_long_counts = off; off = align256(off + (size_t)kLongCounters * kLongCounterStride * 4);
     p.off_block_sums = off; off = align256(off + (size_t)(p.scan_blocks + 1) * 4);
-    // kLongLists lists of at most `per` tiles, then the list of the longest segments
-    p.off_long_lists = off; off = align256(off + (size_t)(2 * tiles + 2 * kLongLists) * 4);
+    // kLongLists lists of at most `per` tiles, the list of the segments sorted through the
+    // workspace, the list of the chunk-sorted ones
+    p.off_long_lists = off; off = align256(off + (size_t)(3 * tiles + 2 * kLongLists) * 4);
+    // the chunk sort's tables: at most h_max segments (longer than kChunkMin each) and
+    // capacity / 4096 + h_max chunks
+    p.chunk_h_max = (uint32_t)std::min<uint64_t>(tiles, capacity / (kChunkMin + 1) + 1);
+    p.chunk_max = (uint32_t)(capacity / kSortTile + p.chunk_h_max);
+    p.off_chunk_tables = off; off = align256(off + (size_t)(10 * (uint64_t)p.chunk_h_max + 1) * 4);
+    p.off_chunk_seg = off;   off = align256(off + (size_t)p.chunk_max * 4);
+    p.off_chunk_cnt = off;   off = align256(off + (size_t)p.chunk_max * kRadix * 4);
     p.off_tcount = off;     off = align256(off + (size_t)p.sort_tiles * kTileRadix * 4);
     p.bytes = off;
     return p;
@@ -1105,6 +1370,29 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
                            dim3(kBigThreads), 0, stream, bins->ranges, plan.tiles_total, zin, bins->pidx,
                            bins->keys, bins->count, plan.capacity, bins->status, long_lists, long_counts, keys_a,
                            keys_b, vals_alt);
+        // 6c. the longest segments, by all workgroups (A = (zin, pidx), B = (keys_a, vals_alt))
+        static int chunk_grid = 0;
+        if (!chunk_grid) chunk_grid = resident_blocks(reinterpret_cast<const void*>(chunk_scatter_kernel), kSortThreads);
+        if (!chunk_grid) return -1;
+        uint32_t* tables = reinterpret_cast<uint32_t*>(base + plan.off_chunk_tables);
+        const uint32_t hm = plan.chunk_h_max;
+        ChunkPlan cp{tables, tables + hm, tables + 2 * hm, tables + 3 * hm + 1, tables + 8 * hm + 1,
+                     reinterpret_cast<uint32_t*>(base + plan.off_chunk_seg),
+                     reinterpret_cast<uint32_t*>(base + plan.off_chunk_cnt), hm};
+        uint32_t* zmut = const_cast<uint32_t*>(zin);
+        const unsigned cg = (unsigned)std::min<uint32_t>(plan.chunk_max, (uint32_t)chunk_grid);
+        const unsigned sg = (unsigned)std::min<uint32_t>(hm, 1024u);
+        hipLaunchKernelGGL(chunk_setup_kernel, dim3(1), dim3(256), 0, stream, bins->ranges, plan.tiles_total,
+                           long_lists, long_counts, cp);
+        for (int pass = 0; pass < 4; ++pass) {
+            hipLaunchKernelGGL(chunk_count_kernel, dim3(cg), dim3(kSortThreads), 0, stream, zin, keys_a, long_counts,
+                               cp, pass);
+            hipLaunchKernelGGL(chunk_scan_kernel, dim3(sg), dim3(256), 0, stream, long_counts, cp, pass);
+            hipLaunchKernelGGL(chunk_scatter_kernel, dim3(cg), dim3(kSortThreads), 0, stream, zmut, bins->pidx, keys_a,
+                               vals_alt, long_counts, cp, pass);
+        }
+        hipLaunchKernelGGL(chunk_final_kernel, dim3(cg), dim3(256), 0, stream, keys_a, vals_alt, zin, bins->pidx,
+                           bins->keys, long_counts, cp);
     }
     return hipPeekAtLastError() == hipSuccess ? 0 : -1;
 }

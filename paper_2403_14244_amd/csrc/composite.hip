@@ -445,13 +445,35 @@ struct OrderedArgs {
     const uint32_t* order;
     const uint32_t* hist;
     uint32_t wide_slots;
+    uint64_t* times;          // ISOGS_FWD_TIMES: {start, end} per workgroup of the launch, else NULL
+};
+
+// Workgroup clock stamps (ISOGS_FWD_TIMES): the constant 100 MHz clock when the workgroup
+// starts and after its last wave has finished, written only by workgroups that composited
+// a non-empty list (the others leave zeros).
+struct WgStamp {
+    uint64_t t0;
+    __device__ explicit WgStamp(const OrderedArgs& a) : t0(a.times ? __builtin_amdgcn_s_memrealtime() : 0) {}
+    // logical: the tile's index within the launch (queue entries are launch-local)
+    __device__ void done(const OrderedArgs& a, const RenderPack& pk, uint32_t logical) const {
+        if (!a.times) return;   // uniform: a kernel argument
+        __syncthreads();
+        const uint32_t gt = pk.v[0].tile_base + logical;   // the launch's tiles are consecutive
+        if (threadIdx.x == 0 && a.ranges[2 * gt + 1] > a.ranges[2 * gt]) {
+            const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+            a.times[2 * (size_t)blockIdx.x] = t0;
+            a.times[2 * (size_t)blockIdx.x + 1] = t1;
+        }
+    }
 };
 
 template <bool PIPE, bool AN>
 __device__ __forceinline__ void ordered_tile(StagedSubT<AN>& sb, const RenderPack& pk, const OrderedArgs& a) {
     if (*a.status != kStatusOk) return write_overflow_tile(pk, a.order[blockIdx.x], a.image, a.T_final, a.n_last);
+    const WgStamp stamp(a);
     composite_tile<PIPE, PIPE, AN>(sb, pk, a.order[blockIdx.x], a.record, a.conic, a.pidx, a.ranges, a.bg_r, a.bg_g,
                                    a.bg_b, a.image, a.T_final, a.n_last, a.ckpt);
+    stamp.done(a, pk, a.order[blockIdx.x]);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompactWavesPerSimd)))
@@ -556,8 +578,28 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
     return 0;
 }
 
-size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv) {
-    return tile_queue_words(max_group_tiles(cams, nv)) * 4 + 256;
+// Workspace: the tile queue, then (ISOGS_FWD_TIMES) the clock stamps, 5 workgroups per tile
+// of the call at most (the wide launch adds four quadrant workgroups per long tile).
+static size_t queue_ws_bytes(const isogs_camera* cams, int32_t nv) {
+    return (tile_queue_words(max_group_tiles(cams, nv)) * 4 + 255) & ~(size_t)255;
+}
+
+static uint64_t call_tiles(const isogs_camera* cams, int32_t nv) {
+    uint64_t tiles = 0;
+    for (int j = 0; j < nv; ++j)
+        tiles += (uint64_t)(((cams[j].width + kTile - 1) / kTile) * ((cams[j].height + kTile - 1) / kTile));
+    return tiles;
+}
+
+size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv, uint32_t flags) {
+    size_t need = queue_ws_bytes(cams, nv);
+    if (flags & ISOGS_FWD_TIMES) need += (size_t)call_tiles(cams, nv) * 5 * 16;
+    return need + 256;
+}
+
+__global__ void __launch_bounds__(256) fill_stamps_kernel(uint64_t* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 uint32_t max_group_tiles(const isogs_camera* cams, int32_t nv) {
@@ -618,16 +660,19 @@ __device__ __forceinline__ void ordered_wide(unsigned char* smem, const RenderPa
     for (int c = kWideMinLog2 + 1; c < kBuckets; ++c) n_wide += a.hist[c];
     n_wide = min(n_wide, wide_slots);
     const uint32_t b = blockIdx.x;
+    const WgStamp stamp(a);
     if (b < 4 * wide_slots) {
         if ((b >> 2) >= n_wide) return;
         composite_quadrant(*reinterpret_cast<StagedQuadT<AN>*>(smem), pk, a.order[b >> 2], (int)(b & 3u), a.record,
                            a.conic, a.pidx, a.ranges, a.bg_r, a.bg_g, a.bg_b, a.image, a.T_final, a.n_last, a.ckpt);
+        stamp.done(a, pk, a.order[b >> 2]);
     } else {
         const uint32_t j = b - 4 * wide_slots;
         if (j < n_wide) return;
         composite_tile<true, false, AN>(*reinterpret_cast<StagedSubT<AN>*>(smem), pk, a.order[j], a.record, a.conic,
                                         a.pidx, a.ranges, a.bg_r, a.bg_g, a.bg_b, a.image, a.T_final, a.n_last,
                                         a.ckpt);
+        stamp.done(a, pk, a.order[j]);
     }
 }
 
@@ -649,6 +694,13 @@ int launch_render_fwd_ordered(const isogs_projected* proj, const float* conic, c
                               hipStream_t stream) {
     const bool an = conic != nullptr;
     uint32_t* q = static_cast<uint32_t*>(ws);
+    uint64_t* stamps = nullptr;
+    if (flags & ISOGS_FWD_TIMES) {
+        stamps = reinterpret_cast<uint64_t*>(static_cast<char*>(ws) + queue_ws_bytes(cams, nv));
+        const size_t n = (size_t)call_tiles(cams, nv) * 5 * 2;
+        hipLaunchKernelGGL(fill_stamps_kernel, dim3((unsigned)std::min<size_t>(1024, (n + 255) / 256)), dim3(256), 0,
+                           stream, stamps, n);
+    }
     uint32_t p_off = 0, tile_base = 0, pix_off = 0;
     for (int v0 = 0; v0 < nv; v0 += kMaxViews) {
         RenderPack pk{};
@@ -660,7 +712,8 @@ int launch_render_fwd_ordered(const isogs_projected* proj, const float* conic, c
         const uint32_t* order = launch_tile_queue(q, bins->ranges, tile0, blocks, pk.n_entries_cap, stream);
         OrderedArgs a{reinterpret_cast<const float4*>(proj->record), reinterpret_cast<const float2*>(conic),
                       bins->pidx, bins->ranges, bins->status, bg[0], bg[1], bg[2], image, T_final, n_last,
-                      reinterpret_cast<float4*>(ckpt), order, q, 0u};
+                      reinterpret_cast<float4*>(ckpt), order, q, 0u,
+                      stamps ? stamps + 2 * 5 * (size_t)tile0 : nullptr};
         if (flags & ISOGS_FWD_WIDE) {
             // a long tile holds at least 2^kWideMinLog2 of the group's entries
             a.wide_slots = (uint32_t)std::min<uint64_t>(blocks, (uint64_t)pk.n_entries_cap / (1u << kWideMinLog2) + 1);

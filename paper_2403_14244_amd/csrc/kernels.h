@@ -19,8 +19,10 @@ struct BinSortPlan {
     int tile_bits;          // bits of the largest global tile id
     uint32_t sort_tiles;    // 4096-entry sort tiles for `capacity`
     uint32_t scan_blocks;   // 2048-particle scan blocks
+    uint32_t chunk_h_max;   // segments sorted in chunks by all workgroups, at most
+    uint32_t chunk_max;     // their 4096-entry chunks, at most
     size_t off_keys_a, off_keys_b, off_vals_alt, off_z_a, off_z_b, off_hist, off_long_counts,
-        off_block_sums, off_long_lists, off_tcount, bytes;
+        off_block_sums, off_long_lists, off_tcount, off_chunk_tables, off_chunk_seg, off_chunk_cnt, bytes;
 };
 
 BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, int32_t nv, uint64_t capacity);
@@ -32,7 +34,7 @@ int launch_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, co
                       const isogs_camera* cams, int32_t nv, const float* bg, float* image, float* T_final,
                       uint32_t* n_last, float* ckpt, hipStream_t stream);
 
-size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv);
+size_t render_fwd_ordered_ws(const isogs_camera* cams, int32_t nv, uint32_t flags);
 
 // Longest-list-first tile queue of one launch group: words needed, the largest group, the
 // launch. The queue holds the length-class histogram (its first kBuckets words, read by

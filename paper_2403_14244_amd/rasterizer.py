@@ -219,11 +219,14 @@ class Rasterizer:
         return image, T, n_last
 
     def render_fwd_ordered(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0),
-                           out=None, ckpt=None, wide=False):
+                           out=None, ckpt=None, wide=False, times=False):
         """render_fwd with the tiles dispatched longest entry list first (same result).
         `wide`: the longest tiles of small launches are composited four lanes per pixel
         (same result up to rounding on those tiles; about twice as fast for one view).
-        `out` optionally supplies (image, T_final, n_last) buffers."""
+        `out` optionally supplies (image, T_final, n_last) buffers. `times`: also returns
+        the per-workgroup {start, end} stamps of the 100 MHz clock, int64 [5 * tiles, 2]
+        ({0, 0} for workgroups without a non-empty list), as a view of the workspace that
+        the next call on this rasterizer overwrites."""
         pix = sum(int(c.width) * int(c.height) for c in cams)
         if out is None:
             out = (torch.empty(3 * pix, dtype=_F32, device=self.device),
@@ -234,13 +237,22 @@ class Rasterizer:
         carr = A.camera_array(cams)
         npv = A.int_array(n_per_view)
         need = ctypes.c_size_t(0)
+        flags = (A.ISOGS_FWD_WIDE if wide else 0) | (A.ISOGS_FWD_TIMES if times else 0)
         args = (ctypes.byref(fp.abi()), npv, ctypes.byref(bins.abi()), carr, len(cams), bgc, _p(image), _p(T),
-                _p(n_last), _p(ckpt), A.ISOGS_FWD_WIDE if wide else 0)
+                _p(n_last), _p(ckpt), flags)
         A.check(A.lib().isogs_render_fwd_ordered(*args, None, ctypes.byref(need), _stream()))
         ws = self._workspace_q(need.value)
         have = ctypes.c_size_t(ws.numel())
         A.check(A.lib().isogs_render_fwd_ordered(*args, _p(ws), ctypes.byref(have), _stream()))
-        return image, T, n_last
+        if not times:
+            return image, T, n_last
+        base = ctypes.c_size_t(0)
+        A.check(A.lib().isogs_render_fwd_ordered(*args[:-1], flags & ~A.ISOGS_FWD_TIMES, None, ctypes.byref(base),
+                                                 _stream()))
+        tiles = sum(((int(c.width) + 15) // 16) * ((int(c.height) + 15) // 16) for c in cams)
+        off = base.value - 256
+        stamps = ws[off:off + tiles * 5 * 16].view(torch.int64).view(tiles * 5, 2)
+        return image, T, n_last, stamps
 
     def _workspace_q(self, nbytes):
         if not hasattr(self, "_wsq") or self._wsq.numel() < nbytes:

@@ -181,8 +181,13 @@ def test_ordered_forward_rejects_unknown_flags():
     need = ctypes.c_size_t(0)
     assert L.isogs_render_fwd_ordered(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, None, None,
                                       None, None, 0, None, ctypes.byref(need), None) == A.ISOGS_OK
+    # the stamps of ISOGS_FWD_TIMES: 80 bytes per tile more (64x48: 12 tiles)
+    need_t = ctypes.c_size_t(0)
+    assert L.isogs_render_fwd_ordered(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, None, None,
+                                      None, None, A.ISOGS_FWD_TIMES, None, ctypes.byref(need_t), None) == A.ISOGS_OK
+    assert need_t.value == need.value + 12 * 80
     out = ctypes.c_void_p(fake)
-    for flags in (2, 1 << 31, A.ISOGS_FWD_WIDE | 4):
+    for flags in (4, 1 << 31, A.ISOGS_FWD_WIDE | 4, A.ISOGS_FWD_TIMES | 8):
         assert L.isogs_render_fwd_ordered(ctypes.byref(proj), npv, ctypes.byref(bins), cams, 1, bg, out, out,
                                           out, None, flags, ctypes.c_void_p(fake), ctypes.byref(need),
                                           None) == A.ISOGS_ERR_INVALID

@@ -147,6 +147,22 @@ def _bin_case(name):
             views.append(TH.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
         return views, cams
+    if name in ("segment_chunked", "segment_chunked_ties"):
+        # segments sorted by all workgroups in 4096-entry chunks (longer than 16384 entries):
+        # 16384 (the last one sorted by one workgroup), 16385 (a chunk of one entry), 40000;
+        # with ties: 70000 entries of 8 depth values (only one byte of the depth bits varies:
+        # three passes skipped, the result left in the workspace) and 20000 over [0.5, 80]
+        # (all four bytes vary)
+        ties = name == "segment_chunked_ties"
+        views, cams = [], []
+        sizes = ((70000, [2.0 + k / 8 for k in range(8)]), (20000, None)) if ties else \
+            ((16384, None), (16385, None), (40000, None))
+        for k, (n, dep) in enumerate(sizes):
+            u, v, z, r = S.crowded_projected(n, 48, 32, 24.0, 8.0, 2.0, seed=80 + k + 10 * ties, max_radius=0.5,
+                                             depths=dep)
+            views.append(TH.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
+            cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
+        return views, cams
     if name == "segment_ties_bucketed":
         # one 3000-entry segment whose depths take 64 values: every bucket of the leading
         # bits holds one value many times, so positions decide the order inside buckets
@@ -180,7 +196,7 @@ def _bin_case(name):
 
 BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled",
              "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_ties_bucketed", "single_tile",
-             "all_tiles_long"]
+             "all_tiles_long", "segment_chunked", "segment_chunked_ties"]
 
 
 @pytest.mark.parametrize("case", BIN_CASES)

@@ -57,6 +57,48 @@ def test_ordered_equals_per_tile_launch(P, views):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("walk", ["pipelined", "compact", "wide"])
+def test_workgroup_stamps(P, walk):
+    """ISOGS_FWD_TIMES: the images are unchanged, every workgroup that composited a non-empty
+    list leaves start < end, the others {0, 0}; the compact and pipelined walks take one
+    workgroup per tile, so exactly the non-empty tiles are stamped (twenty views: two
+    launch groups, the second group's stamps from pair 5 t on)."""
+    import torch
+    note(f"workgroup stamps ({walk})")
+    sc = S.mixture_scene(60_000, seed=7)
+    sizes = {"pipelined": [(640, 360)] * 2, "compact": [(640, 640)] * 20, "wide": [(640, 360)] * 2}[walk]
+    cams = [S.orbit_camera(0.3 * i, 4.0, w, h) for i, (w, h) in enumerate(sizes)]
+    R = P.Rasterizer()
+    g = P.GaussianScene.from_host(sc)
+    fp = R.project([g] * len(cams), cams)
+    b = R.bin_sort(fp, [g.n] * len(cams), cams)
+    wide = walk == "wide"
+    a = [x.clone() for x in R.render_fwd_ordered(fp, [g.n] * len(cams), b, cams, wide=wide)]
+    img, T, nl, st = R.render_fwd_ordered(fp, [g.n] * len(cams), b, cams, wide=wide, times=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, (img, T, nl)):
+        assert torch.equal(x, y)
+    st = st.cpu().numpy()
+    lens = (b.ranges[:, 1] - b.ranges[:, 0]).cpu().numpy()
+    stamped = st[:, 0] != 0
+    assert np.all(st[stamped, 1] > st[stamped, 0]) and np.all(st[~stamped] == 0)
+    if walk == "wide":
+        assert stamped.sum() >= (lens > 0).sum()
+    else:
+        # group g's workgroups at pairs 5 t0 + b; one per tile
+        tiles = [((w + 15) // 16) * ((h + 15) // 16) for w, h in sizes]
+        t0 = 0
+        for v0 in range(0, len(sizes), 16):
+            n = sum(tiles[v0:v0 + 16])
+            grp = stamped[5 * t0:5 * t0 + n]
+            assert grp.sum() == (lens[t0:t0 + n] > 0).sum()
+            assert not stamped[5 * t0 + n:5 * (t0 + n)].any()
+            t0 += n
+    span = (st[stamped, 1].max() - st[stamped, 0].min()) * 10e-3
+    note(f"  {int(stamped.sum())} workgroups, mean {(st[stamped, 1] - st[stamped, 0]).mean() * 10e-3:.1f} us, "
+         f"launch span {span:.1f} us")
+
+
 def test_served_images_equal_alone_and_in_mix(P):
     import torch
     from paper_2403_14244_amd.serving import GpuExecutor, Request, Server
