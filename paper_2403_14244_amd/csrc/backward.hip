@@ -419,70 +419,93 @@ __global__ void __launch_bounds__(256) aniso_bwd_ordered_kernel(const RenderPack
     bwd_ordered(sb, pk, a);
 }
 
-// Gradient of each real SH basis polynomial (the forms used in the forward colour
-// evaluation) at direction (x, y, z); the tangential projection happens in the caller.
-__device__ __forceinline__ void sh_eval_grad(int deg, float x, float y, float z, float Y[16], float gx[16],
-                                             float gy[16], float gz[16]) {
-    constexpr float c1 = 0.48860251190291992f, c2a = 1.09254843059207907f, c2b = 0.31539156525252005f,
-                    c2c = 0.54627421529603959f, c3a = 0.59004358992664352f, c3b = 2.89061144264055405f,
-                    c3c = 0.45704579946446573f, c3d = 0.37317633259011540f, c3e = 1.44530572132027702f;
-    for (int k = 0; k < 16; ++k) Y[k] = gx[k] = gy[k] = gz[k] = 0.0f;
-    Y[0] = 1.0f;
-    if (deg < 1) return;
-    Y[1] = c1 * y; gy[1] = c1;
-    Y[2] = c1 * z; gz[2] = c1;
-    Y[3] = c1 * x; gx[3] = c1;
-    if (deg < 2) return;
-    const float xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = c2a * x * y; gx[4] = c2a * y; gy[4] = c2a * x;
-    Y[5] = c2a * y * z; gy[5] = c2a * z; gz[5] = c2a * y;
-    Y[6] = c2b * (3.0f * zz - 1.0f); gz[6] = 6.0f * c2b * z;
-    Y[7] = c2a * x * z; gx[7] = c2a * z; gz[7] = c2a * x;
-    Y[8] = c2c * (xx - yy); gx[8] = 2.0f * c2c * x; gy[8] = -2.0f * c2c * y;
-    if (deg < 3) return;
-    Y[9] = c3a * y * (3.0f * xx - yy); gx[9] = 6.0f * c3a * x * y; gy[9] = 3.0f * c3a * (xx - yy);
-    Y[10] = c3b * x * y * z; gx[10] = c3b * y * z; gy[10] = c3b * x * z; gz[10] = c3b * x * y;
-    Y[11] = c3c * y * (5.0f * zz - 1.0f); gy[11] = c3c * (5.0f * zz - 1.0f); gz[11] = 10.0f * c3c * y * z;
-    Y[12] = c3d * z * (5.0f * zz - 3.0f); gz[12] = c3d * (15.0f * zz - 3.0f);
-    Y[13] = c3c * x * (5.0f * zz - 1.0f); gx[13] = c3c * (5.0f * zz - 1.0f); gz[13] = 10.0f * c3c * x * z;
-    Y[14] = c3e * z * (xx - yy); gx[14] = 2.0f * c3e * x * z; gy[14] = -2.0f * c3e * y * z; gz[14] = c3e * (xx - yy);
-    Y[15] = c3a * x * (xx - 3.0f * yy); gx[15] = 3.0f * c3a * (xx - yy); gy[15] = -6.0f * c3a * x * y;
-}
-
 struct GradView {
     uint32_t p_off;
     float R[9], t[3], eye[3], f, cx, cy;
 };
 
+// Real SH basis polynomial K (the forms of the forward colour evaluation) and its gradient
+// at direction (x, y, z); K is a compile-time constant, so each call folds to its own term.
+template <int K>
+__device__ __forceinline__ void sh_term(float x, float y, float z, float& Y, float& gx, float& gy, float& gz) {
+    constexpr float c1 = 0.48860251190291992f, c2a = 1.09254843059207907f, c2b = 0.31539156525252005f,
+                    c2c = 0.54627421529603959f, c3a = 0.59004358992664352f, c3b = 2.89061144264055405f,
+                    c3c = 0.45704579946446573f, c3d = 0.37317633259011540f, c3e = 1.44530572132027702f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    gx = gy = gz = 0.0f;
+    if constexpr (K == 1) { Y = c1 * y; gy = c1; }
+    else if constexpr (K == 2) { Y = c1 * z; gz = c1; }
+    else if constexpr (K == 3) { Y = c1 * x; gx = c1; }
+    else if constexpr (K == 4) { Y = c2a * x * y; gx = c2a * y; gy = c2a * x; }
+    else if constexpr (K == 5) { Y = c2a * y * z; gy = c2a * z; gz = c2a * y; }
+    else if constexpr (K == 6) { Y = c2b * (3.0f * zz - 1.0f); gz = 6.0f * c2b * z; }
+    else if constexpr (K == 7) { Y = c2a * x * z; gx = c2a * z; gz = c2a * x; }
+    else if constexpr (K == 8) { Y = c2c * (xx - yy); gx = 2.0f * c2c * x; gy = -2.0f * c2c * y; }
+    else if constexpr (K == 9) { Y = c3a * y * (3.0f * xx - yy); gx = 6.0f * c3a * x * y; gy = 3.0f * c3a * (xx - yy); }
+    else if constexpr (K == 10) { Y = c3b * x * y * z; gx = c3b * y * z; gy = c3b * x * z; gz = c3b * x * y; }
+    else if constexpr (K == 11) { Y = c3c * y * (5.0f * zz - 1.0f); gy = c3c * (5.0f * zz - 1.0f); gz = 10.0f * c3c * y * z; }
+    else if constexpr (K == 12) { Y = c3d * z * (5.0f * zz - 3.0f); gz = c3d * (15.0f * zz - 3.0f); }
+    else if constexpr (K == 13) { Y = c3c * x * (5.0f * zz - 1.0f); gx = c3c * (5.0f * zz - 1.0f); gz = 10.0f * c3c * x * z; }
+    else if constexpr (K == 14) { Y = c3e * z * (xx - yy); gx = 2.0f * c3e * x * z; gy = -2.0f * c3e * y * z; gz = c3e * (xx - yy); }
+    else { static_assert(K == 15, "degree 3 at most"); Y = c3a * x * (xx - 3.0f * yy); gx = 3.0f * c3a * (xx - yy); gy = -6.0f * c3a * x * y; }
+}
+
+// The coefficients of one particle, held in registers across the views: coefficient k of
+// channel ch at c[3 k + ch].
+struct CoefRef {
+    const float* c;
+    __device__ float operator()(int k, int ch) const { return c[3 * k + ch]; }
+};
+
 // Colour of one view, rgb = max(0, c_0 + sum_k c_k Y_k(d)) with d = (mu - eye)/|mu - eye|:
 // adds the view's gradient (drgb, zero where the colour was clamped) to the coefficients'
-// and to the centre's (through the direction's tangential part).
+// and to the centre's (through the direction's tangential part). Each channel's sum runs
+// over k in ascending order, as in the forward evaluation, so the clamp decision agrees.
+template <int DEG, int KK = 1>
+__device__ __forceinline__ void sh_raw(const CoefRef& coef, float x, float y, float z, float raw[3]) {
+    if constexpr (KK < (DEG + 1) * (DEG + 1)) {
+        float Y, gx, gy, gz;
+        sh_term<KK>(x, y, z, Y, gx, gy, gz);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) raw[ch] = fmaf(coef(KK, ch), Y, raw[ch]);
+        sh_raw<DEG, KK + 1>(coef, x, y, z, raw);
+    }
+}
+
+template <int DEG, int KK = 1>
+__device__ __forceinline__ void sh_back(const CoefRef& coef, float x, float y, float z, const float d[3], float* gcol,
+                                        float& wdx, float& wdy, float& wdz) {
+    if constexpr (KK < (DEG + 1) * (DEG + 1)) {
+        float Y, gx, gy, gz;
+        sh_term<KK>(x, y, z, Y, gx, gy, gz);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            gcol[3 * KK + ch] += d[ch] * Y;
+            const float wk = d[ch] * coef(KK, ch);
+            wdx = fmaf(wk, gx, wdx);
+            wdy = fmaf(wk, gy, wdy);
+            wdz = fmaf(wk, gz, wdz);
+        }
+        sh_back<DEG, KK + 1>(coef, x, y, z, d, gcol, wdx, wdy, wdz);
+    }
+}
+
 template <int DEG>
-__device__ __forceinline__ void color_backward(const float* coef, const float drgb[3], const float eye[3], float mx,
+__device__ __forceinline__ void color_backward(const CoefRef& coef, const float drgb[3], const float eye[3], float mx,
                                                float my, float mz, float* gcol, float& gmx, float& gmy, float& gmz) {
-    constexpr int K = (DEG + 1) * (DEG + 1);
     const float ex = mx - eye[0], ey = my - eye[1], ez = mz - eye[2];
     const float inv_dist = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
     const float dxn = ex * inv_dist, dyn = ey * inv_dist, dzn = ez * inv_dist;
-    float Y[16], gx[16], gy[16], gz[16];
-    sh_eval_grad(DEG, dxn, dyn, dzn, Y, gx, gy, gz);
-    float wdx = 0.0f, wdy = 0.0f, wdz = 0.0f;
+    float raw[3] = {coef(0, 0), coef(0, 1), coef(0, 2)};
+    sh_raw<DEG>(coef, dxn, dyn, dzn, raw);
+    float d[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        float raw = coef[ch];
-#pragma unroll
-        for (int k = 1; k < K; ++k) raw = fmaf(coef[3 * k + ch], Y[k], raw);
-        const float d = (raw > 0.0f) ? drgb[ch] : 0.0f;
-        gcol[ch] += d;
-#pragma unroll
-        for (int k = 1; k < K; ++k) {
-            gcol[3 * k + ch] += d * Y[k];
-            const float wk = d * coef[3 * k + ch];
-            wdx = fmaf(wk, gx[k], wdx);
-            wdy = fmaf(wk, gy[k], wdy);
-            wdz = fmaf(wk, gz[k], wdz);
-        }
+        d[ch] = (raw[ch] > 0.0f) ? drgb[ch] : 0.0f;
+        gcol[ch] += d[ch];
     }
+    float wdx = 0.0f, wdy = 0.0f, wdz = 0.0f;
+    sh_back<DEG>(coef, dxn, dyn, dzn, d, gcol, wdx, wdy, wdz);
     const float radial = wdx * dxn + wdy * dyn + wdz * dzn;
     gmx += (wdx - radial * dxn) * inv_dist;
     gmy += (wdy - radial * dyn) * inv_dist;
@@ -507,7 +530,7 @@ struct GradPack {
 
 // One thread per particle of one scene; DEG is the scene's SH degree.
 template <int DEG>
-__global__ void __launch_bounds__(256) grad_project_kernel(const GradPack pk, const float4* __restrict__ rec,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) grad_project_kernel(const GradPack pk, const float4* __restrict__ rec,
                                                            const uint32_t* __restrict__ tile_count,
                                                            const uint32_t* __restrict__ offsets,
                                                            const uint32_t* __restrict__ count_p,
@@ -566,7 +589,7 @@ __global__ void __launch_bounds__(256) grad_project_kernel(const GradPack pk, co
         gmx += gv.R[0] * gpx + gv.R[3] * gpy + gv.R[6] * gpz;
         gmy += gv.R[1] * gpx + gv.R[4] * gpy + gv.R[7] * gpz;
         gmz += gv.R[2] * gpx + gv.R[5] * gpy + gv.R[8] * gpz;
-        color_backward<DEG>(coef, drgb, gv.eye, mx, my, mz, gcol, gmx, gmy, gmz);
+        color_backward<DEG>(CoefRef{coef}, drgb, gv.eye, mx, my, mz, gcol, gmx, gmy, gmz);
     }
     if (pk.accumulate) {
         pk.g_pos[i] += gmx;
@@ -748,7 +771,7 @@ __global__ void __launch_bounds__(256) aniso_grad_project_kernel(const AnisoGrad
         gmu64[1] += V[1] * dpx + V[4] * dpy + V[7] * dpz;
         gmu64[2] += V[2] * dpx + V[5] * dpy + V[8] * dpz;
         const float drgb[3] = {S[6], S[7], S[8]};
-        color_backward<DEG>(coef, drgb, gv.eye, mx, my, mz, gcol, gmx, gmy, gmz);
+        color_backward<DEG>(CoefRef{coef}, drgb, gv.eye, mx, my, mz, gcol, gmx, gmy, gmz);
     }
     float grot[4] = {0.0f, 0.0f, 0.0f, 0.0f}, gsc[3] = {0.0f, 0.0f, 0.0f};
     if (any) {
