@@ -357,10 +357,15 @@ __global__ void __launch_bounds__(256) tile_scan_kernel(uint32_t* __restrict__ t
     if (threadIdx.x == 0) hist[blockIdx.x] = carry;   // this digit's count over all entries
 }
 
+// BITS: the pass's digit width, a compile-time constant (the ballot chain then carries no
+// per-bit condition). Positions past the last entry (the final sort tile only) carry the
+// all-ones key, whose digit is the largest, so they sort behind every entry of the tile
+// and no step needs a per-item validity mask; only positions below n_here are written.
+template <int BITS>
 __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, const uint32_t* __restrict__ zin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t* __restrict__ zout,
-    const uint32_t* __restrict__ count_p, uint64_t capacity, int shift, int bits,
+    const uint32_t* __restrict__ count_p, uint64_t capacity, int shift,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ tcount, uint32_t stride) {
     __shared__ uint32_t s_buf[kSortTile];   // tile reordered by digit: keys, values, depth bits
     __shared__ uint16_t s_dig[kSortTile];    // digit at each reordered position
@@ -384,25 +389,20 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
 
     // load: wave w owns entries [tile*4096 + w*1024, +1024), item i of lane l at i*64 + l
     const uint32_t wbase = tile * kSortTile + w * (kSortTile / 4);
+    const uint32_t n_here = min((uint32_t)kSortTile, count - tile * kSortTile);
     uint32_t k[kSortItems], v[kSortItems], rk[kSortItems];
-    uint32_t valid = 0;
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t idx = wbase + i * kWave + lane;
-        const bool ok = idx < count;
-        valid |= (uint32_t)ok << i;
-        k[i] = ok ? kin[idx] : 0u;
+        k[i] = idx < count ? kin[idx] : 0xFFFFFFFFu;
     }
     // this tile's start of digits 2t, 2t+1: digit base over all entries + earlier tiles' count
     const uint32_t h0 = hist[2 * t], h1 = hist[2 * t + 1];
     const uint32_t e0 = tcount[(size_t)(2 * t) * stride + tile], e1 = tcount[(size_t)(2 * t + 1) * stride + tile];
-    wave_rank<kSortItems, kTileRadixBits>(k, shift, bits, valid, kSortItems, s_wcnt[w], rk);
+    wave_rank<kSortItems, BITS>(k, shift, BITS, 0xFFFFFFFFu, kSortItems, s_wcnt[w], rk);
     // values are needed only after the keys are placed: their loads overlap the scans
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const uint32_t idx = wbase + i * kWave + lane;
-        v[i] = ((valid >> i) & 1u) ? vin[idx] : 0u;
-    }
+    for (int i = 0; i < kSortItems; ++i) v[i] = vin[min(wbase + i * kWave + lane, count - 1)];
     __syncthreads();
 
     uint32_t mine[2];
@@ -430,21 +430,17 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
     uint32_t lpos[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        lpos[i] = 0xFFFFFFFFu;
-        if ((valid >> i) & 1u) {
-            const uint32_t d = digit_at(k[i], shift, bits);
-            lpos[i] = s_local[d] + s_wcnt[w][d] + rk[i];
-            s_buf[lpos[i]] = k[i];
-        }
+        const uint32_t d = digit_at(k[i], shift, BITS);
+        lpos[i] = s_local[d] + s_wcnt[w][d] + rk[i];
+        s_buf[lpos[i]] = k[i];
     }
     __syncthreads();
-    const uint32_t n_here = min((uint32_t)kSortTile, count - tile * kSortTile);
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const uint32_t j = t + i * kSortThreads;
         if (j < n_here) {
             const uint32_t key = s_buf[j];
-            const uint32_t dd = digit_at(key, shift, bits);
+            const uint32_t dd = digit_at(key, shift, BITS);
             s_dig[j] = (uint16_t)dd;
             const uint32_t dst = s_base[dd] + (j - s_local[dd]);
             if (dst < count) kout[dst] = key;
@@ -452,8 +448,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i)
-        if (lpos[i] != 0xFFFFFFFFu) s_buf[lpos[i]] = v[i];
+    for (int i = 0; i < kSortItems; ++i) s_buf[lpos[i]] = v[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
@@ -466,14 +461,10 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
     }
     // the depth bits follow the same path (loaded late to keep registers free)
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        const uint32_t idx = wbase + i * kWave + lane;
-        v[i] = ((valid >> i) & 1u) ? zin[idx] : 0u;
-    }
+    for (int i = 0; i < kSortItems; ++i) v[i] = zin[min(wbase + i * kWave + lane, count - 1)];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i)
-        if (lpos[i] != 0xFFFFFFFFu) s_buf[lpos[i]] = v[i];
+    for (int i = 0; i < kSortItems; ++i) s_buf[lpos[i]] = v[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
@@ -1338,9 +1329,13 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
                            plan.capacity, sh, wd, tcount, plan.sort_tiles);
         hipLaunchKernelGGL(tile_scan_kernel, dim3(kTileRadix), dim3(256), 0, stream, tcount, plan.sort_tiles,
                            bins->count, plan.capacity, hist + p * kTileRadix);
-        hipLaunchKernelGGL(sort_scatter_kernel, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, zin,
-                           kout, vout, zout, bins->count, plan.capacity, sh, wd, hist + p * kTileRadix, tcount,
-                           plan.sort_tiles);
+        // digit widths of the tile passes: 8 or 9 bits (DigitSplit of at most 32 bits, 9 at most)
+        static_assert(kTileRadixBits == 9, "scatter instantiated for 8- and 9-bit digits");
+        auto scatter = wd == 9 ? sort_scatter_kernel<9> : wd == 8 ? sort_scatter_kernel<8> : wd == 7 ? sort_scatter_kernel<7>
+                     : wd == 6 ? sort_scatter_kernel<6> : wd == 5 ? sort_scatter_kernel<5> : wd == 4 ? sort_scatter_kernel<4>
+                     : wd == 3 ? sort_scatter_kernel<3> : wd == 2 ? sort_scatter_kernel<2> : sort_scatter_kernel<1>;
+        hipLaunchKernelGGL(scatter, dim3(plan.sort_tiles), dim3(kSortThreads), 0, stream, kin, vin, zin, kout, vout,
+                           zout, bins->count, plan.capacity, sh, hist + p * kTileRadix, tcount, plan.sort_tiles);
         const uint32_t* tk = kin;
         const uint32_t* tv = vin;
         const uint32_t* tz = zin;
