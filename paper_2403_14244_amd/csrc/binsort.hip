@@ -1365,7 +1365,12 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
                            dim3(kBigThreads), 0, stream, bins->ranges, plan.tiles_total, zin, bins->pidx,
                            bins->keys, bins->count, plan.capacity, bins->status, long_lists, long_counts, keys_a,
                            keys_b, vals_alt);
-        // 6c. the longest segments, by all workgroups (A = (zin, pidx), B = (keys_a, vals_alt))
+        // 6c. the longest segments, by all workgroups (A = (zin, pidx), B = (keys_a, vals_alt)).
+        // A tile's list holds each particle of its view at most once, so without a view of
+        // more than kChunkMin particles there is no such segment and nothing is launched.
+        int32_t most = 0;
+        for (int v = 0; v < nv; ++v) most = std::max(most, n_per_view[v]);
+        if ((uint32_t)most <= kChunkMin) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
         static int chunk_grid = 0;
         if (!chunk_grid) chunk_grid = resident_blocks(reinterpret_cast<const void*>(chunk_scatter_kernel), kSortThreads);
         if (!chunk_grid) return -1;
