@@ -141,15 +141,14 @@ def bwd_pairs(n_last):
 
 def solo_stages(R, gs, batches, dL_seed=7):
     """Every stage of the benchmark call alone on one stream, with HIP events on that
-    stream around each library call: projection, bin sort, longest-first compositing (with
-    checkpoints) and the backward pass (random dL/dimage), per batch of views. Returns the
-    mean time per call of each stage (ms), and the work of the compositing walks."""
+    stream around each library call: projection, bin sort, longest-first compositing (as
+    the benchmark calls it, without checkpoints) and the backward pass (random dL/dimage,
+    from an untimed forward with checkpoints, as training runs it), per batch of views.
+    Returns the mean time per call of each stage (ms), and the work of the compositing
+    walks."""
     import torch
     st = {k: [] for k in ("project", "bin_sort", "render_fwd", "render_bwd")}
     fwd_pairs = bwd_p = entries = 0
-    for bc in batches:
-        # entry capacity sized with a checked bin sort (grows only): the timed calls then fit
-        R.bin_sort(R.project([gs] * len(bc), bc), [gs.n] * len(bc), bc, check=True)
     gen = torch.Generator(device=gs.pos.device)
     gen.manual_seed(dL_seed)
     for bc in batches:
@@ -160,9 +159,12 @@ def solo_stages(R, gs, batches, dL_seed=7):
         ev[1].record()
         bins = R.bin_sort(fp, npv, bc, check=False)
         ev[2].record()
+        # the forward as the benchmark launches it (no checkpoints); then, untimed, the
+        # training forward with checkpoints that the backward starts its chunks from
+        img, T, n_last = R.render_fwd_ordered(fp, npv, bins, bc)
+        ev[3].record()
         ck = R.checkpoint_buffer(bins)
         img, T, n_last = R.render_fwd_ordered(fp, npv, bins, bc, ckpt=ck)
-        ev[3].record()
         dL = torch.randn(img.shape, device=img.device, generator=gen)
         e_b0, e_b1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e_b0.record()
@@ -180,6 +182,13 @@ def solo_stages(R, gs, batches, dL_seed=7):
         del ck, dL, img, T, n_last, bins, fp
     nb = len(batches)
     return ({k: float(np.mean(v)) for k, v in st.items()}, fwd_pairs / nb, bwd_p / nb, entries / nb)
+
+
+def size_capacity(R, gs, batches):
+    """Entry capacity of the rasterizer sized with a checked bin sort of every batch (it only
+    grows), so that the unchecked timed calls fit."""
+    for bc in batches:
+        R.bin_sort(R.project([gs] * len(bc), bc), [gs.n] * len(bc), bc, check=True)
 
 
 def stage_rooflines(ms, fwd_pairs, bwd_pairs_, entries, n, views, pixels, tiles, sh_degree):
@@ -750,6 +759,7 @@ def cpu_baseline(scene, cam, budget_s):
 
 def roofline_phase(R, gs, batches, args):
     """Solo stage times and the roofline of the dominant kernel (compositing)."""
+    size_capacity(R, gs, batches)
     solo_stages(R, gs, batches[:1])       # warm: workspaces sized, code loaded
     ms, fwd_pairs, bwd_p, entries = solo_stages(R, gs, batches)
     B = len(batches[0])
@@ -763,8 +773,8 @@ def roofline_phase(R, gs, batches, args):
                 unit="TFLOP/s", frac=achieved / FP32_PEAK_TFLOPS, traffic=measured_traffic(comp_bytes),
                 frac_nonpacked=achieved / VALU_PEAK_TFLOPS, nonpacked_peak=round(VALU_PEAK_TFLOPS, 2),
                 launch_ms=ms["render_fwd"], launches=len(batches), measured="solo launches, HIP events on the "
-                "launch stream (isogs_render_fwd_ordered: the tile queue's two small kernels and the compositing "
-                "kernel)", pairs_per_launch=fwd_pairs, flops_per_pair=FLOPS_PER_PAIR, alg_bytes_per_launch=comp_bytes,
+                "launch stream (isogs_render_fwd_ordered as the benchmark calls it: the tile queue's three small "
+                "kernels and the compositing kernel)", pairs_per_launch=fwd_pairs, flops_per_pair=FLOPS_PER_PAIR, alg_bytes_per_launch=comp_bytes,
                 hbm_gbs_alg=comp_bytes / (ms["render_fwd"] * 1e-3) / 1e9, views_per_launch=B)
     log(f"solo stages per {B}-view call: " + ", ".join(f"{k} {v['us']} us" for k, v in stages.items()))
     log(f"composite: {ms['render_fwd'] * 1e3:.0f} us/launch alone, {fwd_pairs:.3e} pairs, {achieved:.2f} TFLOP/s "
@@ -848,7 +858,8 @@ def main():
         return stage, bins_all
 
     if args.pmc_probe:
-        solo_stages(R, gs, batches[:1])       # sizes the capacity and workspaces
+        size_capacity(R, gs, batches[:1])
+        solo_stages(R, gs, batches[:1])       # sizes the workspaces
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()

@@ -27,7 +27,8 @@ EXPORTED = ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_r
             "isogs_ssim_fwd", "isogs_ssim_bwd", "isogs_l1_fwd", "isogs_l1_bwd", "isogs_aniso_project",
             "isogs_aniso_render_fwd", "isogs_aniso_render_bwd", "isogs_loss_fwd", "isogs_loss_bwd",
             "isogs_field2d_merge", "isogs_octree_init", "isogs_field2d_aniso_bin", "isogs_field2d_aniso_fwd",
-            "isogs_field2d_aniso_bwd", "isogs_last_error", "isogs_version")
+            "isogs_field2d_aniso_bwd", "isogs_stream_create", "isogs_stream_destroy", "isogs_last_error",
+            "isogs_version")
 
 
 class Scene(ctypes.Structure):
@@ -148,6 +149,8 @@ def lib():
         L.isogs_field2d_aniso_bwd.argtypes = [P(Field2DAniso), P(Projected), vp, P(Bins), ctypes.c_int32,
                                               ctypes.c_int32, ctypes.c_float, vp, P(Field2DAniso), vp,
                                               P(ctypes.c_size_t), vp]
+        L.isogs_stream_create.argtypes = [P(ctypes.c_void_p)]
+        L.isogs_stream_destroy.argtypes = [vp]
         L.isogs_checkpoint_bytes.argtypes = [ctypes.c_uint64]
         L.isogs_checkpoint_bytes.restype = ctypes.c_size_t
         for name in ("isogs_project", "isogs_bin_sort", "isogs_bin_sort_static", "isogs_render_fwd", "isogs_render_fwd_ordered",

@@ -126,6 +126,22 @@ int check_field2d_sizes(int32_t K, int32_t width, int32_t height, float support,
 
 extern "C" {
 
+int isogs_stream_create(void** stream) {
+    g_error[0] = 0;
+    if (!stream) return fail(ISOGS_ERR_INVALID, "stream is NULL");
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return device_fail("isogs_stream_create");
+    *stream = s;
+    return ISOGS_OK;
+}
+
+int isogs_stream_destroy(void* stream) {
+    g_error[0] = 0;
+    if (!stream) return fail(ISOGS_ERR_INVALID, "stream is NULL");
+    if (hipStreamDestroy(static_cast<hipStream_t>(stream)) != hipSuccess) return device_fail("isogs_stream_destroy");
+    return ISOGS_OK;
+}
+
 const char* isogs_last_error(void) { return g_error; }
 
 const char* isogs_version(void) { return "isogs 0.1 gfx950"; }

@@ -216,6 +216,25 @@ class SimulatedExecutor(Executor):
                 r.result = self.render(r)
 
 
+def _own_streams(n, device):
+    """`n` HIP streams created for this executor by the library (default priority,
+    non-blocking), wrapped as torch streams. Each new stream takes the least used of the
+    process's hardware queues, so the slots' streams sit on different queues; streams handed
+    out by torch's pool were created together long before and can share one, which runs
+    their work in turn."""
+    import ctypes
+    import torch
+    from . import _abi as A
+    handles, streams = [], []
+    with torch.cuda.device(device):
+        for _ in range(n):
+            h = ctypes.c_void_p()
+            A.check(A.lib().isogs_stream_create(ctypes.byref(h)))
+            handles.append(h.value)
+            streams.append(torch.cuda.ExternalStream(h.value, device=device))
+    return handles, streams
+
+
 class GpuExecutor(Executor):
     """Runs batches through the C ABI on `n_streams` HIP streams (default priority).
 
@@ -234,7 +253,10 @@ class GpuExecutor(Executor):
         self.spans = []
         self.scenes = scenes                    # name -> GaussianScene (resident)
         self.device = torch.device(device)
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
+        # the streams live as long as the process: events that torch records on them (its
+        # pinned-memory allocator's, for the status copies) may be queried after the
+        # executor is gone, and a destroyed stream would leave them dangling
+        self._handles, self.streams = _own_streams(n_streams, self.device)
         self.busy = [False] * n_streams
         self.rasters = [Rasterizer(self.device) for _ in range(n_streams)]
         # one pinned {count, status} word pair per slot, reused: a slot runs one batch at a time

@@ -388,3 +388,11 @@ def test_tree_and_loss_calls_validate_without_a_device():
     assert need.value >= 16 * 16 * 56
     assert L.isogs_loss_fwd(None, None, 3, 8, 8, 1.5, None, None, ctypes.byref(need), None) == A.ISOGS_ERR_INVALID
     assert L.isogs_loss_fwd(None, None, 3, 8, 8, 0.2, None, None, ctypes.byref(need), None) == A.ISOGS_OK
+
+
+def test_stream_calls_reject_null_before_touching_the_device():
+    A = _abi()
+    L = A.lib()
+    assert L.isogs_stream_create(None) == A.ISOGS_ERR_INVALID
+    assert b"stream" in L.isogs_last_error()
+    assert L.isogs_stream_destroy(None) == A.ISOGS_ERR_INVALID
