@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-inflight", type=int, default=2,
                     help="batches in flight at once (one HIP stream each)")
-    ap.add_argument("--serve-warmup", type=int, default=100, help="warm-up requests before the measured trace")
+    ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before the measured trace")
     ap.add_argument("--serve-sweep", default="1000,3000,10000",
                     help="extra arrival rates (req/s), 500 requests each, for the batch size and latency at load")
     ap.add_argument("--only-serving", action="store_true", help="run only the serving measurement")
@@ -250,9 +250,11 @@ def serving_benchmark(args, dev):
               for k, r in enumerate(rates)}
     ex = GpuExecutor(scenes, dev, n_streams=args.serve_inflight, record_spans=True)
     ex.calibrate(warm + reqs + [q for v in sweeps.values() for q in v])
+    log(f"serving: {len(warm)} warm-up requests ...")
     Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=args.serve_inflight).run(warm)
     torch.cuda.synchronize()
     ex.spans.clear()
+    log(f"serving: trace of {len(reqs)} requests at {args.serve_rate:g}/s ...")
     srv = Server(ex, pool_bytes=16 << 30, max_batch=16, max_inflight=args.serve_inflight)
     st = srv.run(reqs)
     ov = ex.device_overlap()
