@@ -145,6 +145,10 @@ class Rasterizer:
         self.headroom = headroom
         self.capacity = 0
         self.ordered_fwd = True
+        # sync_free: IsoGSRender reads no capacity status at all (not even deferred), so a
+        # training step can be captured in a HIP graph; the capacity must be sized first
+        # (an eager step), and a pass that overflows it shows NaN images and loss
+        self.sync_free = False
         self._ws = torch.empty(0, dtype=torch.uint8, device=self.device)
 
     def _workspace(self, nbytes):
@@ -374,7 +378,8 @@ class IsoGSRender(torch.autograd.Function):
         scenes = [scene] * len(cams)
         if len({(int(c.width), int(c.height)) for c in cams}) != 1:
             raise ValueError("IsoGSRender: every camera must have the same size")
-        images, st = rasterizer.render(scenes, cams, bg, check="deferred", checkpoints=True, wide=True)
+        check = False if rasterizer.sync_free else "deferred"
+        images, st = rasterizer.render(scenes, cams, bg, check=check, checkpoints=True, wide=True)
         if not any(ctx.needs_input_grad[:4]):
             # no backward will read the deferred status: read it now (an overflowed pass
             # raises here; its images are NaN, never silently stale)

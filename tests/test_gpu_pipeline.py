@@ -407,6 +407,60 @@ def test_autograd_function_and_determinism(P, torch_cuda):
     _grads_vs_oracle(dict(zip(("pos", "scale", "opacity", "color"), outs[0][1])), ref, "autograd L1")
 
 
+@pytest.mark.skip(reason="ending the capture of this step (torch.cuda.graph) crashed the process with a segmentation "
+                         "fault inside capture_end on the MI355X box; the cause is not found, so the capture of the 3D "
+                         "training step is not used (the 2D fit's capture is tested and used)")
+def test_training_step_replays_in_a_hip_graph(P, torch_cuda):
+    """A forward + backward training step (projection, bin sort, wide forward with
+    checkpoints, the library's L1 loss, backward) captured once in a HIP graph with a
+    rasterizer that reads no status, replayed several times with eager work and
+    synchronisations in between: every replay's image, loss and gradients equal the eager
+    step's bitwise (the library's fills are kernels, no memset node is recorded)."""
+    torch = torch_cuda
+    sc = S.mixture_scene(60_000, seed=12)
+    cams = [S.orbit_camera(0.2, 4.0, 320, 240), S.orbit_camera(1.1, 4.0, 320, 240)]
+    note("training step in a HIP graph: 60k Gaussians, 2 views of 320x240")
+    target = torch.from_numpy(np.random.default_rng(3).uniform(0, 1, (2, 3, 240, 320)).astype(np.float32)).cuda()
+    params = [torch.from_numpy(np.ascontiguousarray(a)).cuda().requires_grad_(True)
+              for a in (sc.pos, sc.scale, sc.opacity, sc.color)]
+    R = P.Rasterizer()
+
+    def step():
+        for q in params:
+            q.grad = None
+        img = P.IsoGSRender.apply(*params, sc.sh_degree, cams, (0.0, 0.0, 0.0), R)
+        loss = P.l1_loss(img, target)
+        loss.backward()
+        return img, loss
+
+    img, loss = step()                       # eager, checked: sizes the capacity
+    ref = (img.detach().clone(), loss.detach().clone(), [q.grad.clone() for q in params])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    for q in params:
+        q.grad = None
+    R.sync_free = True
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g_img, g_loss = step()
+    g_grads = [q.grad for q in params]       # the graph's own gradient buffers
+    R.sync_free = False
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(g_img, ref[0]) and torch.equal(g_loss, ref[1]), rep
+        for g, r in zip(g_grads, ref[2]):
+            assert torch.equal(g, r), rep
+        # eager work between replays (another eager step on the same rasterizer)
+        e_img, _ = step()
+        torch.cuda.synchronize()
+        assert torch.equal(e_img.detach(), ref[0])
+
+
 def test_autograd_output_guarded_against_inplace_changes(P, torch_cuda):
     """The batch returned by the autograd forward is the render buffer itself (no copy),
     which the backward reads; an in-place change of it must make the backward fail
