@@ -18,7 +18,8 @@
 //   5. finalize    tile ranges [start, end)
 //   6. segments    stable sort of each tile's segment on the depth bits (and the 64-bit
 //                  (tile, depth) keys, when the caller asks for them): one wave per short
-//                  segment, one workgroup per long one
+//                  segment, two, four or eight waves per longer one (several segments to a
+//                  workgroup), the whole workgroup beyond 4096 entries
 #include "common.h"
 #include <algorithm>
 
@@ -519,10 +520,10 @@ __device__ __forceinline__ void block_or_and(uint32_t x_or, uint32_t x_and, uint
 }
 
 struct SegShared {
-    uint32_t buf[kSegMax];        // segment reordered by digit: keys, then values
+    uint32_t buf[kSegMax];                      // segments reordered by digit: keys, then values
     uint32_t wcnt[kBigWaves][kRadix];
-    uint32_t local[kRadix];       // LDS path: digit bases; global path: digit histogram
-    uint32_t run[kRadix];         // global path: next output position of each digit
+    uint32_t local[kBigWaves / 2][kRadix];      // group path: each group's digit bases; global
+                                                // path: digit histogram [0], next output position [1]
     uint32_t tmp[2 * kBigWaves];
 };
 
@@ -543,27 +544,45 @@ __device__ __forceinline__ uint32_t digit_wave_prefix(SegShared& sh, uint32_t d)
     return run;
 }
 
-// Segment of n <= kSegMax entries sorted in LDS: items stay in registers between passes,
-// each pass ranks by one 8-bit digit of the depth bits, reorders through LDS and reloads
-// in position order. Only the bits that differ within the segment are sorted on. The
-// positions past the segment's end, up to the wave's whole rounds, carry the key with all
-// bits set: its digit is the largest of every pass and those positions come after every
-// entry, so stability keeps them at the end and no pass needs a per-item validity mask.
-__device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, uint32_t start, uint32_t n,
-                                                 const uint32_t* __restrict__ zs, uint32_t* __restrict__ pidx,
-                                                 uint64_t* __restrict__ keys64) {
-    const uint32_t t = threadIdx.x, w = t >> 6, l = lane_id();
-    const int items = (int)((n + kBigThreads - 1) / kBigThreads);
-    const uint32_t wbase = w * kWave * (uint32_t)items;   // wave w owns positions [wbase, wbase + 64 items)
+// Segments of up to 512 G entries sorted in LDS by groups of G waves (G = 2, 4 or 8, the
+// same for the whole workgroup): the workgroup sorts kBigWaves / G segments side by side,
+// group g (waves gG .. gG + G - 1) the segment (tile, start, n) that its threads pass
+// (n = 0: none), so that the barriers and latencies of a pass are shared by several
+// segments. Items stay in registers between passes; each pass ranks by one 8-bit digit of
+// the depth bits within each wave (ballots), turns the group's digit counts into bases,
+// reorders the keys and then the values through the group's part of LDS and reloads them
+// in position order. Only the bits that differ within a segment are sorted on. Positions
+// past the segment's end, up to the group's whole rounds, carry the key with all bits set:
+// its digit is the largest of every pass and those positions come after every entry, so
+// stability keeps them at the end and no pass needs a per-item validity mask. G is a
+// parameter rather than a template argument so that the kernel holds one copy of this
+// code (three copies take more registers than the kernel may use).
+__device__ __forceinline__ void segment_sort_groups(SegShared& sh, uint32_t G, uint32_t tile, uint32_t start,
+                                                    uint32_t n, const uint32_t* __restrict__ zs,
+                                                    uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64) {
+    static_assert(kBigWaves == 8 && kRadix == 256 && kBigItems * kWave * kBigWaves == (int)kSegMax, "group layout");
+    // the segment is the same for every lane of a wave, G for the whole workgroup: scalars
+    G = __builtin_amdgcn_readfirstlane(G);
+    tile = __builtin_amdgcn_readfirstlane(tile);
+    start = __builtin_amdgcn_readfirstlane(start);
+    n = __builtin_amdgcn_readfirstlane(n);
+    const uint32_t t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), l = lane_id();
+    const uint32_t group_threads = kWave * G;
+    const uint32_t g = w / G, g0 = g * G, tg = t - g * group_threads;
+    uint32_t* buf = sh.buf + g * group_threads * kBigItems;
+    const int items = (int)((n + group_threads - 1) / group_threads);   // uniform within the group
+    const uint32_t wbase = (w - g0) * kWave * (uint32_t)items;          // this wave's first position
     uint32_t k[kBigItems], v[kBigItems], rk[kBigItems];
     uint32_t k_or = 0u, k_and = 0xFFFFFFFFu;
-    // loads clamped into the segment rather than predicated, so that all of them are in
-    // flight at once
+    if (n) {
+        // loads clamped into the segment rather than predicated, so that all of them are in
+        // flight at once
 #pragma unroll
-    for (int i = 0; i < kBigItems; ++i) {
-        const uint32_t p = wbase + (uint32_t)i * kWave + l;
-        v[i] = pidx[start + min(p, n - 1)];
-        k[i] = zs[start + min(p, n - 1)];
+        for (int i = 0; i < kBigItems; ++i) {
+            const uint32_t p = min(wbase + (uint32_t)i * kWave + l, n - 1);
+            v[i] = pidx[start + p];
+            k[i] = zs[start + p];
+        }
     }
 #pragma unroll
     for (int i = 0; i < kBigItems; ++i) {
@@ -572,53 +591,111 @@ __device__ __forceinline__ void segment_sort_lds(SegShared& sh, uint32_t tile, u
         k_and &= ok ? k[i] : 0xFFFFFFFFu;
         k[i] = ok ? k[i] : 0xFFFFFFFFu;
     }
-    uint32_t all_or, all_and;
-    block_or_and(k_or, k_and, sh.tmp, all_or, all_and);
-    const uint32_t diff = all_or ^ all_and;
-    // uniform by construction; readfirstlane tells the compiler, so the digit loops branch
-    // on scalars
-    const int lo = __builtin_amdgcn_readfirstlane(diff ? __builtin_ctz(diff) : 0);
-    const int hi = __builtin_amdgcn_readfirstlane(diff ? 32 - __builtin_clz(diff) : 0);
-    const Split8 split(lo, hi);
-    for (int pass = 0; pass < split.passes; ++pass) {
-        const int shift = split.shift(pass);
-        zero_wcnt(sh, t);
-        __syncthreads();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        k_or |= __shfl_xor(k_or, o, kWave);
+        k_and &= __shfl_xor(k_and, o, kWave);
+    }
+    if (l == 0) {
+        sh.tmp[w] = k_or;
+        sh.tmp[kBigWaves + w] = k_and;
+    }
+    __syncthreads();
+    // the differing bits of every group (its waves' OR and AND; an empty group has OR 0 and
+    // AND all ones: no differing bit): this group's first bit, the most passes of any group
+    int lo = 0, passes = 0;
+    {
+        uint32_t a_or = 0u, a_and = 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t q = 0; q < (uint32_t)kBigWaves; ++q) {
+            a_or |= sh.tmp[q];
+            a_and &= sh.tmp[kBigWaves + q];
+            if (((q + 1) & (G - 1)) == 0) {   // q is the last wave of group q / G
+                const uint32_t diff = a_or & ~a_and;
+                const int glo = diff ? __builtin_ctz(diff) : 0;
+                const int ghi = diff ? 32 - __builtin_clz(diff) : 0;
+                passes = max(passes, (ghi - glo + kRadixBits - 1) / kRadixBits);
+                if (q / G == g) lo = glo;
+                a_or = 0u;
+                a_and = 0xFFFFFFFFu;
+            }
+        }
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    passes = __builtin_amdgcn_readfirstlane(passes);
+    // digits of this thread in the group's scan: 2 tg, 2 tg + 1 for G = 2, tg otherwise
+    const uint32_t nd = G == 2 ? 2u : 1u, d0 = tg * nd;
+    // Every group makes every pass, on bits [min(lo + 8 pass, 24), +8): a pass on bits at or
+    // above the segment's differing ones, or one that re-ranks its most significant
+    // differing bits, is a stable pass over keys already in that order and changes nothing.
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = min(lo + pass * kRadixBits, 32 - kRadixBits);
+        // each wave clears its own counters: LDS operations of one wave complete in order
+#pragma unroll
+        for (int q = 0; q < kRadix / kWave; ++q) sh.wcnt[w][q * kWave + l] = 0u;
         wave_rank<kBigItems>(k, shift, kRadixBits, 0xFFFFFFFFu, items, sh.wcnt[w], rk);
         __syncthreads();
-        const uint32_t tot = t < kRadix ? digit_wave_prefix(sh, t) : 0u;
-        uint32_t all;
-        const uint32_t lb = block_exclusive_scan<kBigWaves>(tot, sh.tmp, all);
-        if (t < kRadix) sh.local[t] = lb;
+        // this thread's digits: prefixes over the group's waves, the group's totals
+        uint32_t tot[2], mine = 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < 2; ++j) {
+            const uint32_t d = d0 + j;
+            uint32_t run = 0u;
+            if (j < nd && d < (uint32_t)kRadix) {
+#pragma unroll
+                for (uint32_t q = 0; q < (uint32_t)kBigWaves; ++q) {
+                    if (q < G) {
+                        const uint32_t c = sh.wcnt[g0 + q][d];
+                        sh.wcnt[g0 + q][d] = run;
+                        run += c;
+                    }
+                }
+            }
+            tot[j] = run;
+            mine += run;
+        }
+        // exclusive scan of the totals over the group's threads (digit order)
+        const uint32_t inc = wave_inclusive_scan(mine);
+        if (l == kWave - 1) sh.tmp[w] = inc;
+        __syncthreads();
+        uint32_t base = inc - mine;
+#pragma unroll
+        for (uint32_t q = 0; q < (uint32_t)kBigWaves; ++q) base += (g0 + q < w) ? sh.tmp[g0 + q] : 0u;
+#pragma unroll
+        for (uint32_t j = 0; j < 2; ++j) {
+            const uint32_t d = d0 + j;
+            if (j < nd && d < (uint32_t)kRadix) sh.local[g][d] = base;
+            base += tot[j];
+        }
         __syncthreads();
         uint32_t pos[kBigItems];
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i) {
             if (i < items) {
                 const uint32_t d = digit_at(k[i], shift, kRadixBits);
-                pos[i] = sh.local[d] + sh.wcnt[w][d] + rk[i];
-                sh.buf[pos[i]] = k[i];
+                pos[i] = sh.local[g][d] + sh.wcnt[w][d] + rk[i];
+                buf[pos[i]] = k[i];
             }
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i)
-            if (i < items) k[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
+            if (i < items) k[i] = buf[wbase + (uint32_t)i * kWave + l];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i)
-            if (i < items) sh.buf[pos[i]] = v[i];
+            if (i < items) buf[pos[i]] = v[i];
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kBigItems; ++i)
-            if (i < items) v[i] = sh.buf[wbase + (uint32_t)i * kWave + l];
+            if (i < items) v[i] = buf[wbase + (uint32_t)i * kWave + l];
     }
-    // every read of the segment happened before block_or_and's barrier: in place is safe
+    // every read of the segment happened before the first barrier: in place is safe
 #pragma unroll
     for (int i = 0; i < kBigItems; ++i) {
         const uint32_t p = wbase + (uint32_t)i * kWave + l;
         if (i >= items || p >= n) continue;
-        pidx[start + p] = v[i];
+        if (passes) pidx[start + p] = v[i];
         if (keys64) keys64[start + p] = ((uint64_t)tile << 32) | k[i];
     }
 }
@@ -664,7 +741,7 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
     uint32_t *src_k = sk0, *src_v = sv, *dst_k = sk1, *dst_v = pidx;
     if (passes > 0) {
         // digit histogram of the first pass
-        if (t < kRadix) sh.local[t] = 0u;
+        if (t < kRadix) sh.local[0][t] = 0u;
         __syncthreads();
         for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
             uint32_t kk[kBigItems];
@@ -672,7 +749,7 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
             for (int i = 0; i < kBigItems; ++i) kk[i] = src_k[start + min(c0 + (uint32_t)i * kBigThreads + t, n - 1)];
 #pragma unroll
             for (int i = 0; i < kBigItems; ++i)
-                if (c0 + (uint32_t)i * kBigThreads + t < n) atomicAdd(&sh.local[digit_at(kk[i], split.shift(0), kRadixBits)], 1u);
+                if (c0 + (uint32_t)i * kBigThreads + t < n) atomicAdd(&sh.local[0][digit_at(kk[i], split.shift(0), kRadixBits)], 1u);
         }
         __syncthreads();
     }
@@ -681,11 +758,11 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
         const bool has_next = pass + 1 < passes;
         const int next_shift = has_next ? split.shift(pass + 1) : 0, next_bits = kRadixBits;
         uint32_t all;
-        const uint32_t h = t < kRadix ? sh.local[t] : 0u;
+        const uint32_t h = t < kRadix ? sh.local[0][t] : 0u;
         const uint32_t rb = block_exclusive_scan<kBigWaves>(h, sh.tmp, all);
         if (t < kRadix) {
-            sh.run[t] = rb;
-            sh.local[t] = 0u;   // now the next pass's histogram
+            sh.local[1][t] = rb;
+            sh.local[0][t] = 0u;   // now the next pass's histogram
         }
         for (uint32_t c0 = 0; c0 < n; c0 += kSegMax) {
             const uint32_t cn = min(kSegMax, n - c0);
@@ -711,13 +788,13 @@ __device__ __forceinline__ void segment_sort_global(SegShared& sh, uint32_t tile
             for (int i = 0; i < kBigItems; ++i) {
                 if (!((valid >> i) & 1u)) continue;
                 const uint32_t d = digit_at(k[i], shift, bits);
-                const uint32_t o = sh.run[d] + sh.wcnt[w][d] + rk[i];
+                const uint32_t o = sh.local[1][d] + sh.wcnt[w][d] + rk[i];
                 dst_k[start + o] = k[i];
                 dst_v[start + o] = v[i];
-                if (has_next) atomicAdd(&sh.local[digit_at(k[i], next_shift, next_bits)], 1u);
+                if (has_next) atomicAdd(&sh.local[0][digit_at(k[i], next_shift, next_bits)], 1u);
             }
             __syncthreads();
-            if (t < kRadix) sh.run[t] += tot;
+            if (t < kRadix) sh.local[1][t] += tot;
         }
         __syncthreads();
         uint32_t* tk = src_k;
@@ -850,21 +927,31 @@ __device__ __forceinline__ void wave_sort_segment(uint32_t* __restrict__ buf, ui
     }
 }
 
-// The long segments are listed for step 6b in kLongLists lists, tile t in list t mod
-// kLongLists, each with its own counter on its own 128-byte line: appends to one device-wide
-// counter are serialised in memory (the XCDs' L2s are not coherent), while appends to
-// different lines proceed in parallel.
+// The long segments are listed for step 6b by size class: class 0 up to kSegMax entries
+// (sorted by a whole workgroup), class 1 up to kSegMax / 2 (two at once), class 2 up to
+// kSegMax / 4 (four at once). Each class has kLongLists lists, tile t in list t mod
+// kLongLists, each with its own counter on its own 128-byte line: appends to one
+// device-wide counter are serialised in memory (the XCDs' L2s are not coherent), while
+// appends to different lines proceed in parallel. List j of class c is list c kLongLists + j
+// at (c kLongLists + j) * per words.
 constexpr uint32_t kLongLists = 64;
+constexpr uint32_t kClasses = 3;
+constexpr uint32_t kClassLists = kClasses * kLongLists;
 constexpr uint32_t kLongCounterStride = 32;   // words: one counter per 128-byte line
 // Segments longer than kSegMax (sorted through the workspace, several times the work of
-// the others) go to one more list, at kLongLists * per words, counted in counter slot
-// kLongLists; slot kLongLists + 1 is the work counter of step 6b. Segments longer than
-// kChunkMin are sorted by all workgroups together (step 6c): they are listed after that,
-// at kLongLists * per + tiles words, counted in slot kLongLists + 2; slot kLongLists + 3
-// receives their number of 4096-entry chunks.
-constexpr uint32_t kHugeSlot = kLongLists, kWorkSlot = kLongLists + 1, kChunkSlot = kLongLists + 2,
-                   kChunkTotalSlot = kLongLists + 3, kLongCounters = kLongLists + 4;
+// the others) go to one more list, at kClassLists * per words, counted in counter slot
+// kHugeSlot; slot kWorkSlot is the work counter of step 6b. Segments longer than kChunkMin
+// are sorted by all workgroups together (step 6c): they are listed after that, at
+// kClassLists * per + tiles words, counted in slot kChunkSlot; slot kChunkTotalSlot receives
+// their number of 4096-entry chunks.
+constexpr uint32_t kHugeSlot = kClassLists, kWorkSlot = kClassLists + 1, kChunkSlot = kClassLists + 2,
+                   kChunkTotalSlot = kClassLists + 3, kLongCounters = kClassLists + 4;
 constexpr uint32_t kChunkMin = 16384;
+
+// Size class of a segment of kWaveSegMax < n <= kSegMax entries.
+__device__ __forceinline__ uint32_t seg_class(uint32_t n) {
+    return n > kSegMax / 2 ? 0u : n > kSegMax / 4 ? 1u : 2u;
+}
 
 // Step 6a: one wave per tile sorts segments of up to kWaveSegMax entries and appends the
 // longer ones to the lists for step 6b.
@@ -886,10 +973,10 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
         if (lane_id() == 0) {
             const uint32_t per = (tiles_total + kLongLists - 1) / kLongLists;
             if (n > kChunkMin) {
-                long_lists[kLongLists * per + tiles_total +
+                long_lists[kClassLists * per + tiles_total +
                            atomicAdd(&long_counts[kChunkSlot * kLongCounterStride], 1u)] = tile;
             } else {
-                const uint32_t j = n > kSegMax ? kHugeSlot : tile % kLongLists;
+                const uint32_t j = n > kSegMax ? kHugeSlot : seg_class(n) * kLongLists + tile % kLongLists;
                 long_lists[j * per + atomicAdd(&long_counts[j * kLongCounterStride], 1u)] = tile;
             }
         }
@@ -898,57 +985,73 @@ __global__ void __launch_bounds__(kSortThreads) segment_sort_small_kernel(
     wave_sort_segment(sh.buf[w], sh.cnt[w], tile, start, n, zs, pidx, keys64);
 }
 
-// Step 6b: a resident grid sorts the listed long segments one at a time, with stable LSD
-// radix passes: in LDS up to kSegMax entries, through the workspace beyond. Workgroups take
-// the next item from a device-wide counter (one atomic per segment: a few thousand per
-// call, against tens of microseconds of work each), the longest segments first, so that no
-// workgroup is left with a run of long ones while the others have finished. The sort is
-// bound by the latency of its barriers and ballot chains, not by bytes, so the kernel is
-// held to 64 VGPRs: four workgroups per CU instead of two.
-__global__ void __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(8))) segment_sort_big_kernel(
+// Tile of item r of class c: list j holds the class's items [first[j], first[j + 1]), so j
+// is the number of lists that end at or before r (one ballot of the wave).
+__device__ __forceinline__ uint32_t class_item(const uint32_t* __restrict__ long_lists, uint32_t per, uint32_t c,
+                                               const uint32_t* first, uint32_t r) {
+    const uint32_t j = (uint32_t)__popcll(ballot64(first[lane_id() + 1] <= r));
+    return long_lists[(c * kLongLists + j) * per + (r - first[j])];
+}
+
+// Step 6b: a resident grid sorts the listed long segments, with stable LSD radix passes: in
+// LDS up to kSegMax entries, through the workspace beyond. Workgroups take the next item
+// from a device-wide counter (one atomic per item: a few thousand per call, against tens of
+// microseconds of work each), the longest segments first, so that no workgroup is left with
+// a run of long ones while the others have finished: the segments sorted through the
+// workspace, then class 0 one per item, class 1 two per item, class 2 four per item. The
+// sort is bound by its ballot chains and the latency of its barriers, not by bytes, so the
+// kernel is held to 80 VGPRs: three workgroups per CU (at 64 the group sort spills to
+// scratch memory, without a limit two workgroups fit).
+__global__ void __launch_bounds__(kBigThreads) __attribute__((amdgpu_waves_per_eu(6))) segment_sort_big_kernel(
     const uint32_t* __restrict__ ranges, uint32_t tiles_total, const uint32_t* __restrict__ zs,
     uint32_t* __restrict__ pidx, uint64_t* __restrict__ keys64, const uint32_t* __restrict__ count_p,
     uint64_t capacity, const int32_t* __restrict__ status, const uint32_t* __restrict__ long_lists,
     uint32_t* __restrict__ long_counts, uint32_t* __restrict__ sk0, uint32_t* __restrict__ sk1,
     uint32_t* __restrict__ sv) {
     __shared__ SegShared sh;
-    __shared__ uint32_t s_first[kLongLists + 1];   // index of each list's first item in the sequence
+    __shared__ uint32_t s_first[kClasses][kLongLists + 1];   // each list's first item within its class
     __shared__ uint32_t s_item;
     if (*status != kStatusOk) return;
     if ((uint64_t)*count_p > capacity) return;
     const uint32_t t = threadIdx.x;
-    if (t < kWave) {
-        static_assert(kLongLists == kWave, "one lane per list");
-        const uint32_t c = long_counts[t * kLongCounterStride];
-        const uint32_t incl = wave_inclusive_scan(c);
-        s_first[t + 1] = incl;
-        if (t == 0) s_first[0] = 0u;
+    static_assert(kLongLists == kWave, "one lane per list");
+    if (t < kClasses * kWave) {
+        const uint32_t c = t / kWave, lane = lane_id();
+        const uint32_t incl = wave_inclusive_scan(long_counts[(c * kLongLists + lane) * kLongCounterStride]);
+        s_first[c][lane + 1] = incl;
+        if (lane == 0) s_first[c][0] = 0u;
     }
     __syncthreads();
     const uint32_t per = (tiles_total + kLongLists - 1) / kLongLists;
     const uint32_t n_huge = long_counts[kHugeSlot * kLongCounterStride];
-    const uint32_t total = n_huge + s_first[kLongLists];
+    const uint32_t n0 = s_first[0][kLongLists], n1 = s_first[1][kLongLists], n2 = s_first[2][kLongLists];
+    const uint32_t e0 = n_huge + n0, e1 = e0 + (n1 + 1) / 2, total = e1 + (n2 + 3) / 4;
     uint32_t* work = long_counts + kWorkSlot * kLongCounterStride;
+    const uint32_t w = t >> 6;
     for (;;) {
         if (t == 0) s_item = atomicAdd(work, 1u);
         __syncthreads();
         const uint32_t i = s_item;
         if (i >= total) break;   // uniform: every thread read the same item
-        uint32_t tile;
         if (i < n_huge) {
-            tile = long_lists[kHugeSlot * per + i];
-        } else {
-            // list j holds items [s_first[j], s_first[j + 1]) of the rest: j = the number of
-            // lists that end at or before the item
-            const uint32_t r = i - n_huge;
-            const uint32_t j = (uint32_t)__popcll(ballot64(s_first[lane_id() + 1] <= r));
-            tile = long_lists[j * per + (r - s_first[j])];
-        }
-        const uint32_t start = ranges[2 * tile], n = ranges[2 * tile + 1] - start;
-        if (n <= kSegMax)
-            segment_sort_lds(sh, tile, start, n, zs, pidx, keys64);
-        else
+            const uint32_t tile = long_lists[kHugeSlot * per + i];
+            const uint32_t start = ranges[2 * tile], n = ranges[2 * tile + 1] - start;
             segment_sort_global(sh, tile, start, n, zs, pidx, keys64, sk0, sk1, sv);
+        } else {
+            // class 0: one segment per item (groups of 8 waves), class 1: two (4 waves each),
+            // class 2: four (2 waves each)
+            const uint32_t c = i < e0 ? 0u : i < e1 ? 1u : 2u;
+            const uint32_t G = kBigWaves >> c;
+            const uint32_t r = c == 0 ? i - n_huge : c == 1 ? 2 * (i - e0) + w / G : 4 * (i - e1) + w / G;
+            const uint32_t nc = c == 0 ? n0 : c == 1 ? n1 : n2;
+            uint32_t tile = 0, start = 0, n = 0;
+            if (r < nc) {
+                tile = class_item(long_lists, per, c, s_first[c], r);
+                start = ranges[2 * tile];
+                n = ranges[2 * tile + 1] - start;
+            }
+            segment_sort_groups(sh, G, tile, start, n, zs, pidx, keys64);
+        }
         __syncthreads();   // also orders every read of s_item before the next write
     }
 }
@@ -981,7 +1084,7 @@ __global__ void __launch_bounds__(256) chunk_setup_kernel(const uint32_t* __rest
     __shared__ uint32_t s_tmp[4];
     const uint32_t per = (tiles_total + kLongLists - 1) / kLongLists;
     const uint32_t h = min(long_counts[kChunkSlot * kLongCounterStride], cp.h_max);
-    const uint32_t* list = long_lists + kLongLists * per + tiles_total;
+    const uint32_t* list = long_lists + kClassLists * per + tiles_total;
     uint32_t carry = 0;
     for (uint32_t s0 = 0; s0 < h; s0 += 256) {
         const uint32_t sid = s0 + threadIdx.x;
@@ -1230,9 +1333,9 @@ BinSortPlan plan_bin_sort(const int32_t* n_per_view, const isogs_camera* cams, i
     p.off_hist = off;       off += (size_t)kMaxPasses * kTileRadix * 4;
     p.off_long_counts = off; off = align256(off + (size_t)kLongCounters * kLongCounterStride * 4);
     p.off_block_sums = off; off = align256(off + (size_t)(p.scan_blocks + 1) * 4);
-    // kLongLists lists of at most `per` tiles, the list of the segments sorted through the
+    // kClassLists lists of at most `per` tiles, the list of the segments sorted through the
     // workspace, the list of the chunk-sorted ones
-    p.off_long_lists = off; off = align256(off + (size_t)(3 * tiles + 2 * kLongLists) * 4);
+    p.off_long_lists = off; off = align256(off + (size_t)(5 * tiles + 2 * kClassLists) * 4);
     // the chunk sort's tables: at most h_max segments (longer than kChunkMin each) and
     // capacity / 4096 + h_max chunks
     p.chunk_h_max = (uint32_t)std::min<uint64_t>(tiles, capacity / (kChunkMin + 1) + 1);

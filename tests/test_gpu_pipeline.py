@@ -163,6 +163,19 @@ def _bin_case(name):
             views.append(TH.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
         return views, cams
+    if name == "segment_groups":
+        # segments of 513 .. 4096 entries, one per view, sorted several to a workgroup (up to
+        # 1024 entries four at once, up to 2048 two at once): odd numbers in each size class
+        # leave groups empty, and tied depths (one digit pass) share workgroups with spread
+        # ones (three passes)
+        views, cams = [], []
+        tied = [2.0 + k / 8 for k in range(8)]
+        for k, n in enumerate((513, 600, 700, 1024, 777, 888, 999, 1025, 1500, 2048, 2049, 3000, 4096)):
+            u, v, z, r = S.crowded_projected(n, 48, 32, 24.0, 8.0, 2.0, seed=120 + k, max_radius=0.5,
+                                             depths=tied if k % 3 == 1 else None)
+            views.append(TH.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
+            cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
+        return views, cams
     if name == "segment_ties_bucketed":
         # one 3000-entry segment whose depths take 64 values: every bucket of the leading
         # bits holds one value many times, so positions decide the order inside buckets
@@ -195,7 +208,7 @@ def _bin_case(name):
 
 
 BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled",
-             "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_ties_bucketed", "single_tile",
+             "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_groups", "segment_ties_bucketed", "single_tile",
              "all_tiles_long", "segment_chunked", "segment_chunked_ties"]
 
 
