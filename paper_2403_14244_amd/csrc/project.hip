@@ -45,8 +45,11 @@ __device__ __forceinline__ void sh_eval(int deg, float x, float y, float z, floa
     Y[15] = SHConst::c3a * x * (xx - 3.0f * yy);
 }
 
+// A view's camera as the projection uses it: the geometry in FP64 (converted once on the
+// host), with 1/f^2 for the footprint scale.
 struct ProjCam {
-    float R[9], t[3], eye[3], f, cx, cy, near_z;
+    double R[9], t[3], f, inv_f2, cx, cy, near_z;
+    float eye[3];
     int32_t width, height;
     uint32_t p_off;   // first packed record of this view
 };
@@ -86,23 +89,27 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4*
     }
     const bool param_ok = finite_in && sigma > 0.0f && (double)opa >= 1.0 / 255.0;
     const double root = param_ok ? sqrt(log(255.0 * (double)opa)) : 0.0;
+    const double sig = (double)sigma, inv_sig2 = 1.0 / (sig * sig);
+    const double dx = mx, dy = my, dz = mz;
 
     for (int vi = 0; vi < pk.nv; ++vi) {
         const ProjCam& pv = pk.c[vi];
         const uint32_t o = pv.p_off + i;
-        const double px = (double)pv.R[0] * mx + (double)pv.R[1] * my + (double)pv.R[2] * mz + (double)pv.t[0];
-        const double py = (double)pv.R[3] * mx + (double)pv.R[4] * my + (double)pv.R[5] * mz + (double)pv.t[1];
-        const double pz = (double)pv.R[6] * mx + (double)pv.R[7] * my + (double)pv.R[8] * mz + (double)pv.t[2];
-        const double f = (double)pv.f;
-        const double u64 = f * px / pz + (double)pv.cx;
-        const double v64 = f * py / pz + (double)pv.cy;
-        const double s64 = f * (double)sigma / pz;
+        const double px = pv.R[0] * dx + pv.R[1] * dy + pv.R[2] * dz + pv.t[0];
+        const double py = pv.R[3] * dx + pv.R[4] * dy + pv.R[5] * dz + pv.t[1];
+        const double pz = pv.R[6] * dx + pv.R[7] * dy + pv.R[8] * dz + pv.t[2];
+        // one division per view: u = f px / z + cx, v = f py / z + cy, s = f sigma / z and
+        // 1/s^2 = z^2 / (f^2 sigma^2), each within a few FP64 ulps before the FP32 rounding
+        const double inv_z = 1.0 / pz;
+        const double u64 = pv.f * px * inv_z + pv.cx;
+        const double v64 = pv.f * py * inv_z + pv.cy;
+        const double s64 = pv.f * sig * inv_z;
         // the stored footprint must have a normal FP32 form: centre, 1/s^2 and radius
         // finite, 1/s^2 at least the smallest normal value (a denormal may be flushed)
         const float u = (float)u64, v = (float)v64;
-        const float inv_s2 = (float)(1.0 / (s64 * s64));
+        const float inv_s2 = (float)(pz * pz * (pv.inv_f2 * inv_sig2));
         const float r = (float)(s64 * root * (1.0 + 0x1p-10) + 0x1p-6);
-        const bool vis = param_ok && pz > (double)pv.near_z && isfinite(u) && isfinite(v) && isfinite(s64) &&
+        const bool vis = param_ok && pz > pv.near_z && isfinite(u) && isfinite(v) && isfinite(s64) &&
                          s64 > 0.0 && isfinite(inv_s2) && inv_s2 >= 0x1p-126f && isfinite(r);
         float4 fp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float4 cr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -138,6 +145,19 @@ __global__ void __launch_bounds__(256) project_kernel(const ProjPack pk, float4*
         depth[o] = z32;
         tile_count[o] = cnt;
     }
+}
+
+static void fill_proj_cam(ProjCam& c, const isogs_camera& cam, uint32_t p_off) {
+    for (int k = 0; k < 9; ++k) c.R[k] = cam.R[k];
+    for (int k = 0; k < 3; ++k) c.t[k] = cam.t[k], c.eye[k] = cam.eye[k];
+    c.f = cam.f;
+    c.inv_f2 = 1.0 / ((double)cam.f * (double)cam.f);
+    c.cx = cam.cx;
+    c.cy = cam.cy;
+    c.near_z = cam.near_z;
+    c.width = cam.width;
+    c.height = cam.height;
+    c.p_off = p_off;
 }
 
 int launch_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t nv, const isogs_projected* out,
@@ -180,17 +200,7 @@ int launch_project(const isogs_scene* scenes, const isogs_camera* cams, int32_t 
                 su.color != sc.color || su.n != sc.n || su.sh_degree != sc.sh_degree)
                 continue;
             done[u] = true;
-            const isogs_camera& cam = cams[u];
-            ProjCam& c = pk.c[pk.nv++];
-            for (int k = 0; k < 9; ++k) c.R[k] = cam.R[k];
-            for (int k = 0; k < 3; ++k) c.t[k] = cam.t[k], c.eye[k] = cam.eye[k];
-            c.f = cam.f;
-            c.cx = cam.cx;
-            c.cy = cam.cy;
-            c.near_z = cam.near_z;
-            c.width = cam.width;
-            c.height = cam.height;
-            c.p_off = off[u];
+            fill_proj_cam(pk.c[pk.nv++], cams[u], off[u]);
             if (pk.nv == kMaxViews && flush()) return -1;
         }
         if (flush()) return -1;
@@ -261,13 +271,13 @@ __global__ void __launch_bounds__(256) aniso_project_kernel(const AnisoProjPack 
         const uint32_t o = pv.p_off + i;
         double V[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) V[k] = (double)pv.R[k];
-        const double px = V[0] * mx + V[1] * my + V[2] * mz + (double)pv.t[0];
-        const double py = V[3] * mx + V[4] * my + V[5] * mz + (double)pv.t[1];
-        const double pz = V[6] * mx + V[7] * my + V[8] * mz + (double)pv.t[2];
-        const double f = (double)pv.f;
-        const double u64 = f * px / pz + (double)pv.cx;
-        const double v64 = f * py / pz + (double)pv.cy;
+        for (int k = 0; k < 9; ++k) V[k] = pv.R[k];
+        const double px = V[0] * mx + V[1] * my + V[2] * mz + pv.t[0];
+        const double py = V[3] * mx + V[4] * my + V[5] * mz + pv.t[1];
+        const double pz = V[6] * mx + V[7] * my + V[8] * mz + pv.t[2];
+        const double f = pv.f;
+        const double u64 = f * px / pz + pv.cx;
+        const double v64 = f * py / pz + pv.cy;
         // T = J V, J = [[f/z, 0, -f p_x/z^2], [0, f/z, -f p_y/z^2]]
         const double j0 = f / pz, j2 = -f * px / (pz * pz), j5 = -f * py / (pz * pz);
         double T0[3], T1[3];
@@ -292,7 +302,7 @@ __global__ void __launch_bounds__(256) aniso_project_kernel(const AnisoProjPack 
         const float u = (float)u64, v = (float)v64;
         const float A = (float)(c / det), B = (float)(-b / det), C = (float)(a / det);
         const float r = (float)(sqrt(lam) * root * (1.0 + 0x1p-10) + 0x1p-6);
-        const bool vis = param_ok && pz > (double)pv.near_z && isfinite(u) && isfinite(v) && isfinite(det) &&
+        const bool vis = param_ok && pz > pv.near_z && isfinite(u) && isfinite(v) && isfinite(det) &&
                          det > 0.0 && isfinite(A) && isfinite(B) && isfinite(C) && A >= 0x1p-126f &&
                          C >= 0x1p-126f && isfinite(r);
         float4 fp = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -331,18 +341,6 @@ __global__ void __launch_bounds__(256) aniso_project_kernel(const AnisoProjPack 
         depth[o] = z32;
         tile_count[o] = cnt;
     }
-}
-
-static void fill_proj_cam(ProjCam& c, const isogs_camera& cam, uint32_t p_off) {
-    for (int k = 0; k < 9; ++k) c.R[k] = cam.R[k];
-    for (int k = 0; k < 3; ++k) c.t[k] = cam.t[k], c.eye[k] = cam.eye[k];
-    c.f = cam.f;
-    c.cx = cam.cx;
-    c.cy = cam.cy;
-    c.near_z = cam.near_z;
-    c.width = cam.width;
-    c.height = cam.height;
-    c.p_off = p_off;
 }
 
 int launch_aniso_project(const isogs_aniso_scene* scenes, const isogs_camera* cams, int32_t nv,
