@@ -159,9 +159,9 @@ def solo_stages(R, gs, batches, dL_seed=7):
         ev[1].record()
         bins = R.bin_sort(fp, npv, bc, check=False)
         ev[2].record()
-        # the forward as the benchmark launches it (no checkpoints); then, untimed, the
+        # the forward as the benchmark launches it (no checkpoints, no n_last); then, untimed, the
         # training forward with checkpoints that the backward starts its chunks from
-        img, T, n_last = R.render_fwd_ordered(fp, npv, bins, bc)
+        img, T, n_last = R.render_fwd_ordered(fp, npv, bins, bc, last=False)
         ev[3].record()
         ck = R.checkpoint_buffer(bins)
         img, T, n_last = R.render_fwd_ordered(fp, npv, bins, bc, ckpt=ck)
@@ -443,7 +443,7 @@ def aniso_workload(dev, scene_iso, cams, batch_views=10, fwd_views=20, train_ite
             for bc in batches:
                 fp = R.project([g] * len(bc), bc)
                 bins = R.bin_sort(fp, [g.n] * len(bc), bc, check=check)
-                R.render_fwd_ordered(fp, [g.n] * len(bc), bins, bc)
+                R.render_fwd_ordered(fp, [g.n] * len(bc), bins, bc, last=False)
                 ents.append(bins)
             return ents
 
@@ -847,7 +847,7 @@ def main():
                 ev[1].record(s)
                 bins = Rk.bin_sort(fp, [gs.n] * len(bc), bc, check=check)
                 ev[2].record(s)
-                Rk.render_fwd_ordered(fp, [gs.n] * len(bc), bins, bc)
+                Rk.render_fwd_ordered(fp, [gs.n] * len(bc), bins, bc, last=False)
                 ev[3].record(s)
             stage["project"].append((ev[0], ev[1]))
             stage["bin_sort"].append((ev[1], ev[2]))

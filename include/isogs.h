@@ -202,7 +202,9 @@ size_t isogs_checkpoint_bytes(uint64_t capacity);
  *   image     [sum 3 H_v W_v]  planar per view: [V][3][H][W]
  *   T_final   [sum H_v W_v]    transmittance left after the last composited entry
  *   n_last    [sum H_v W_v]    1 + tile-list position of the last contributing entry
- *                              (0 if none); the backward pass starts there
+ *                              (0 if none); the backward pass starts there. NULL: not
+ *                              written (a forward that no backward pass follows; the
+ *                              longest-first walks then do not track it)
  *   checkpoints  NULL, or a buffer of isogs_checkpoint_bytes(bins->capacity) bytes that
  *                receives the compositing checkpoints (see above)
  * Errors: ISOGS_ERR_INVALID, ISOGS_ERR_DEVICE. */

@@ -115,12 +115,13 @@ class AnisoRasterizer(Rasterizer):
         raise NotImplementedError("the anisotropic family composites longest list first: use render_fwd_ordered")
 
     def render_fwd_ordered(self, af: AnisoFootprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0),
-                           out=None, ckpt=None, wide=False):
+                           out=None, ckpt=None, wide=False, last=True):
+        """`last=False`: no n_last (None), for a forward that no backward pass follows."""
         pix = sum(int(c.width) * int(c.height) for c in cams)
         if out is None:
             out = (torch.empty(3 * pix, dtype=_F32, device=self.device),
                    torch.empty(pix, dtype=_F32, device=self.device),
-                   torch.empty(pix, dtype=torch.int32, device=self.device))
+                   torch.empty(pix, dtype=torch.int32, device=self.device) if last else None)
         image, T, n_last = out
         bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
         args = (ctypes.byref(af.aniso_abi()), A.int_array(n_per_view), ctypes.byref(bins.abi()),

@@ -208,7 +208,7 @@ int isogs_render_fwd(const isogs_projected* proj, const int32_t* n_per_view, con
     if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
-    if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (!image || !T_final) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
     if (isogs::launch_render_fwd(proj, n_per_view, bins, cams, n_views, bg, image, T_final, n_last, checkpoints,
                                  (hipStream_t)stream))
         return device_fail("isogs_render_fwd");
@@ -238,7 +238,7 @@ int isogs_render_fwd_ordered(const isogs_projected* proj, const int32_t* n_per_v
     if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
     if ((rc = check_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
-    if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (!image || !T_final) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
     if (isogs::launch_render_fwd_ordered(proj, nullptr, n_per_view, bins, cams, n_views, bg, image, T_final, n_last,
                                          checkpoints, flags, ws, (hipStream_t)stream))
         return device_fail("isogs_render_fwd_ordered");
@@ -332,7 +332,7 @@ int isogs_aniso_render_fwd(const isogs_aniso_projected* proj, const int32_t* n_p
     if ((rc = check_totals(n_per_view, cams, n_views, &n, &tiles, nullptr))) return rc;
     if ((rc = check_aniso_projected(proj, n))) return rc;
     if ((rc = check_bins(bins, n, tiles))) return rc;
-    if (!image || !T_final || !n_last) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
+    if (!image || !T_final) return fail(ISOGS_ERR_INVALID, "output buffer is NULL");
     // a NULL conic selects the isotropic walk: give the anisotropic one a valid address
     // even when there is no particle
     static float no_conic[2];

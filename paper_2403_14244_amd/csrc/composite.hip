@@ -7,10 +7,10 @@ namespace isogs {
 
 // Composites one staged entry into a pixel's running state (branch-free; the dummy pad
 // record has log2(o) = -inf, so alpha = 0 and it changes nothing). T loses the weight it
-// gives away, T - alpha T; `lastj` keeps the staged slot (carried in c.w) of the last entry
-// used in the current batch (slots only increase along a list). TERM: the pixel stops
-// after the entry that takes T below kTMin.
-template <bool TERM, bool AN>
+// gives away, T - alpha T; with LAST, `lastj` keeps the staged slot (carried in c.w) of the
+// last entry used in the current batch (slots only increase along a list). TERM: the pixel
+// stops after the entry that takes T below kTMin.
+template <bool TERM, bool AN, bool LAST = true>
 __device__ __forceinline__ void composite_entry(const float4& f, const float4& c, const float2& k, float px, float py,
                                                 float& T, float& cr, float& cg, float& cb, uint32_t& lastj,
                                                 bool& done) {
@@ -23,7 +23,7 @@ __device__ __forceinline__ void composite_entry(const float4& f, const float4& c
     cg = fmaf(c.y, wgt, cg);
     cb = fmaf(c.z, wgt, cb);
     T = T - wgt;
-    lastj = use ? __float_as_uint(c.w) : lastj;
+    if (LAST) lastj = use ? __float_as_uint(c.w) : lastj;
     if (TERM) done = done || (T < kTMin);
 }
 
@@ -98,8 +98,9 @@ __device__ __forceinline__ TilePixel tile_pixel(const RenderPack& pk, uint32_t l
 // beside it on its CU (more registers): the reads of the entries of step k + 4 and of the
 // list words of step k + 8 are issued while step k is composited, so that the walk does not
 // wait on dependent round trips.
+// LAST: track the last entry used (s.last); without it s.last stays 0.
 // Contains __syncthreads.
-template <bool TERM, bool PIPE, bool PL, bool AN>
+template <bool TERM, bool PIPE, bool PL, bool AN, bool LAST = true>
 __device__ __forceinline__ void composite_range(StagedSubT<AN>& sb, const RenderPack& pk, const TilePixel& p,
                                                 const float4* __restrict__ record, const float2* __restrict__ conic,
                                                 const uint32_t* __restrict__ pidx, uint32_t lo, uint32_t hi,
@@ -136,8 +137,8 @@ __device__ __forceinline__ void composite_range(StagedSubT<AN>& sb, const Render
         auto composite_step = [&](const Step4& st) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                composite_entry<TERM, AN>(st.f[e], st.c[e], st.k[e], p.px, p.py, s.T, s.cr, s.cg, s.cb, lastj,
-                                          s.done);
+                composite_entry<TERM, AN, LAST>(st.f[e], st.c[e], st.k[e], p.px, p.py, s.T, s.cr, s.cg, s.cb,
+                                                lastj, s.done);
         };
         if (!PL) {
             for (uint32_t k = 0; k < steps; k += 4) {
@@ -167,7 +168,7 @@ __device__ __forceinline__ void composite_range(StagedSubT<AN>& sb, const Render
                 if (TERM && ballot64(!s.done) == 0) break;
             }
         }
-        if (lastj != 0xFFFFFFFFu) s.last = pos0 + lastj;
+        if (LAST && lastj != 0xFFFFFFFFu) s.last = pos0 + lastj;
         if (PIPE) cur = nxt;
     }
 }
@@ -183,7 +184,7 @@ __device__ __forceinline__ void write_pixel(const TilePixel& p, const PixelState
     img[hw + pix] = fmaf(s.T, bg_g, s.cg);
     img[2 * hw + pix] = fmaf(s.T, bg_b, s.cb);
     T_final[p.pix_off + pix] = s.T;
-    n_last[p.pix_off + pix] = s.last;
+    if (n_last) n_last[p.pix_off + pix] = s.last;
 }
 
 // On a capacity overflow the bins hold no valid lists: the tile's pixels get NaN colour
@@ -204,11 +205,11 @@ __device__ __forceinline__ void write_overflow_tile(const RenderPack& pk, uint32
     img[hw + pix] = nan;
     img[2 * hw + pix] = nan;
     T_final[vd.pix_off + pix] = nan;
-    n_last[vd.pix_off + pix] = 0u;
+    if (n_last) n_last[vd.pix_off + pix] = 0u;
 }
 
 // Composites one whole tile (logical index within the launch). Contains __syncthreads.
-template <bool PIPE, bool PL, bool AN>
+template <bool PIPE, bool PL, bool AN, bool LAST = true>
 __device__ __forceinline__ void composite_tile(StagedSubT<AN>& sb, const RenderPack& pk, uint32_t logical,
                                                const float4* __restrict__ record, const float2* __restrict__ conic,
                                                const uint32_t* __restrict__ pidx,
@@ -217,7 +218,7 @@ __device__ __forceinline__ void composite_tile(StagedSubT<AN>& sb, const RenderP
                                                uint32_t* __restrict__ n_last, float4* __restrict__ ckpt) {
     const TilePixel p = tile_pixel(pk, logical, ranges);
     PixelState s{1.0f, 0.0f, 0.0f, 0.0f, 0u, !p.inside};
-    composite_range<true, PIPE, PL, AN>(sb, pk, p, record, conic, pidx, 0, p.len, s, ckpt);
+    composite_range<true, PIPE, PL, AN, LAST>(sb, pk, p, record, conic, pidx, 0, p.len, s, ckpt);
     write_pixel(p, s, bg_r, bg_g, bg_b, image, T_final, n_last);
 }
 
@@ -415,7 +416,7 @@ __device__ __forceinline__ void composite_quadrant(StagedQuadT<AN>& sq, const Re
         img[hw + pix] = fmaf(T, bg_g, cg);
         img[2 * hw + pix] = fmaf(T, bg_b, cb);
         T_final[vd.pix_off + pix] = T;
-        n_last[vd.pix_off + pix] = last;
+        if (n_last) n_last[vd.pix_off + pix] = last;
     }
 }
 
@@ -467,24 +468,27 @@ struct WgStamp {
     }
 };
 
-template <bool PIPE, bool AN>
+// LAST: the caller asked for n_last (without it the walk does not track the last entry).
+template <bool PIPE, bool AN, bool LAST>
 __device__ __forceinline__ void ordered_tile(StagedSubT<AN>& sb, const RenderPack& pk, const OrderedArgs& a) {
     if (*a.status != kStatusOk) return write_overflow_tile(pk, a.order[blockIdx.x], a.image, a.T_final, a.n_last);
     const WgStamp stamp(a);
-    composite_tile<PIPE, PIPE, AN>(sb, pk, a.order[blockIdx.x], a.record, a.conic, a.pidx, a.ranges, a.bg_r, a.bg_g,
+    composite_tile<PIPE, PIPE, AN, LAST>(sb, pk, a.order[blockIdx.x], a.record, a.conic, a.pidx, a.ranges, a.bg_r, a.bg_g,
                                    a.bg_b, a.image, a.T_final, a.n_last, a.ckpt);
     stamp.done(a, pk, a.order[blockIdx.x]);
 }
 
+template <bool LAST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kCompactWavesPerSimd)))
 composite_fwd_ordered_kernel(const RenderPack pk, const OrderedArgs a) {
     __shared__ StagedSubT<false> sb;
-    ordered_tile<false>(sb, pk, a);
+    ordered_tile<false, false, LAST>(sb, pk, a);
 }
 
+template <bool LAST>
 __global__ void __launch_bounds__(256) composite_fwd_ordered_pipe_kernel(const RenderPack pk, const OrderedArgs a) {
     __shared__ StagedSubT<false> sb;
-    ordered_tile<true>(sb, pk, a);
+    ordered_tile<true, false, LAST>(sb, pk, a);
 }
 
 // The anisotropic family (eq. 5 kernels): the same walks with the conic staged beside each
@@ -493,15 +497,17 @@ __global__ void __launch_bounds__(256) composite_fwd_ordered_pipe_kernel(const R
 constexpr int kAnisoCompactWavesPerSimd = 5;
 constexpr int kAnisoWideWavesPerSimd = 4;
 
+template <bool LAST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kAnisoCompactWavesPerSimd)))
 aniso_fwd_ordered_kernel(const RenderPack pk, const OrderedArgs a) {
     __shared__ StagedSubT<true> sb;
-    ordered_tile<false>(sb, pk, a);
+    ordered_tile<false, true, LAST>(sb, pk, a);
 }
 
+template <bool LAST>
 __global__ void __launch_bounds__(256) aniso_fwd_ordered_pipe_kernel(const RenderPack pk, const OrderedArgs a) {
     __shared__ StagedSubT<true> sb;
-    ordered_tile<true>(sb, pk, a);
+    ordered_tile<true, true, LAST>(sb, pk, a);
 }
 
 // Launches of at most this many tiles use the pipelined walk (measured crossover on the
@@ -720,11 +726,13 @@ int launch_render_fwd_ordered(const isogs_projected* proj, const float* conic, c
             hipLaunchKernelGGL(an ? aniso_fwd_ordered_wide_kernel : composite_fwd_ordered_wide_kernel,
                                dim3(4 * a.wide_slots + blocks), dim3(256), 0, stream, pk, a);
         } else if (blocks <= kPipeTileLimit) {
-            hipLaunchKernelGGL(an ? aniso_fwd_ordered_pipe_kernel : composite_fwd_ordered_pipe_kernel, dim3(blocks),
-                               dim3(256), 0, stream, pk, a);
+            auto k = an ? (n_last ? aniso_fwd_ordered_pipe_kernel<true> : aniso_fwd_ordered_pipe_kernel<false>)
+                        : (n_last ? composite_fwd_ordered_pipe_kernel<true> : composite_fwd_ordered_pipe_kernel<false>);
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, stream, pk, a);
         } else {
-            hipLaunchKernelGGL(an ? aniso_fwd_ordered_kernel : composite_fwd_ordered_kernel, dim3(blocks), dim3(256), 0,
-                               stream, pk, a);
+            auto k = an ? (n_last ? aniso_fwd_ordered_kernel<true> : aniso_fwd_ordered_kernel<false>)
+                        : (n_last ? composite_fwd_ordered_kernel<true> : composite_fwd_ordered_kernel<false>);
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, stream, pk, a);
         }
         if (hipPeekAtLastError() != hipSuccess) return -1;
     }

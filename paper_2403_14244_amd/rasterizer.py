@@ -209,13 +209,15 @@ class Rasterizer:
         nbytes = int(A.lib().isogs_checkpoint_bytes(bins.capacity))
         return torch.empty(nbytes // 4, dtype=_F32, device=self.device)
 
-    def render_fwd(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0), ckpt=None):
+    def render_fwd(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0), ckpt=None,
+                   last=True):
         """Composites every view; with `ckpt` (from checkpoint_buffer) also stores the
-        checkpoints that let render_bwd split long tiles."""
+        checkpoints that let render_bwd split long tiles. `last=False`: no n_last (None),
+        for a forward that no backward pass follows."""
         pix = sum(int(c.width) * int(c.height) for c in cams)
         image = torch.empty(3 * pix, dtype=_F32, device=self.device)
         T = torch.empty(pix, dtype=_F32, device=self.device)
-        n_last = torch.empty(pix, dtype=torch.int32, device=self.device)
+        n_last = torch.empty(pix, dtype=torch.int32, device=self.device) if last else None
         bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
         A.check(A.lib().isogs_render_fwd(ctypes.byref(fp.abi()), A.int_array(n_per_view), ctypes.byref(bins.abi()),
                                          A.camera_array(cams), len(cams), bgc, _p(image), _p(T), _p(n_last),
@@ -223,19 +225,21 @@ class Rasterizer:
         return image, T, n_last
 
     def render_fwd_ordered(self, fp: Footprints, n_per_view, bins: TileBins, cams, bg=(0.0, 0.0, 0.0),
-                           out=None, ckpt=None, wide=False, times=False):
+                           out=None, ckpt=None, wide=False, times=False, last=True):
         """render_fwd with the tiles dispatched longest entry list first (same result).
         `wide`: the longest tiles of small launches are composited four lanes per pixel
         (same result up to rounding on those tiles; about twice as fast for one view).
-        `out` optionally supplies (image, T_final, n_last) buffers. `times`: also returns
-        the per-workgroup {start, end} stamps of the 100 MHz clock, int64 [5 * tiles, 2]
-        ({0, 0} for workgroups without a non-empty list), as a view of the workspace that
-        the next call on this rasterizer overwrites."""
+        `out` optionally supplies (image, T_final, n_last) buffers (n_last may be None).
+        `last=False`: no n_last (None), for a forward that no backward pass follows (the
+        walk then skips tracking the last entry). `times`: also returns the per-workgroup
+        {start, end} stamps of the 100 MHz clock, int64 [5 * tiles, 2] ({0, 0} for
+        workgroups without a non-empty list), as a view of the workspace that the next call
+        on this rasterizer overwrites."""
         pix = sum(int(c.width) * int(c.height) for c in cams)
         if out is None:
             out = (torch.empty(3 * pix, dtype=_F32, device=self.device),
                    torch.empty(pix, dtype=_F32, device=self.device),
-                   torch.empty(pix, dtype=torch.int32, device=self.device))
+                   torch.empty(pix, dtype=torch.int32, device=self.device) if last else None)
         image, T, n_last = out
         bgc = (ctypes.c_float * 3)(*[float(b) for b in bg])
         carr = A.camera_array(cams)

@@ -310,7 +310,7 @@ class GpuExecutor(Executor):
         with torch.cuda.stream(s):
             fp = R.project(scenes, cams)
             bins = R.bin_sort(fp, npv, cams, check=False, capacity=cap)
-            img, T, nl = R.render_fwd_ordered(fp, npv, bins, cams, wide=True)
+            img, _, _ = R.render_fwd_ordered(fp, npv, bins, cams, wide=True, last=False)
             status = self.status_host[si]   # {count, status}
             status.copy_(bins.count.as_strided((2,), (1,)), non_blocking=True)
             ev = torch.cuda.Event(enable_timing=self.record_spans)
@@ -335,7 +335,7 @@ class GpuExecutor(Executor):
             with torch.cuda.stream(self.streams[h["si"]]):
                 bins = R.bin_sort(h["fp"], h["npv"], h["cams"], check=True,
                                   capacity=int(count * self.headroom) + 4096)
-                img, _, _ = R.render_fwd_ordered(h["fp"], h["npv"], bins, h["cams"], wide=True)
+                img, _, _ = R.render_fwd_ordered(h["fp"], h["npv"], bins, h["cams"], wide=True, last=False)
             self.streams[h["si"]].synchronize()
         for r, im in zip(h["batch"], split_images(img, h["cams"])):
             r.result = im

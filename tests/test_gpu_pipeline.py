@@ -779,3 +779,38 @@ def test_twenty_views_in_one_call(P, torch_cuda):
         idx = [i for i in range(20) if i % 2 == par]
         ref = O.scene_grads(sc, [cams[i] for i in idx], [Ws[i].astype(np.float64) for i in idx])
         _grads_vs_oracle(g, ref, f"scene {'AB'[par]}")
+
+
+@pytest.mark.parametrize("family", ["iso", "aniso"])
+@pytest.mark.parametrize("walk", ["pipelined", "compact", "wide"])
+def test_forward_without_n_last_is_the_same(P, torch_cuda, family, walk):
+    """A forward that passes no n_last (no backward follows) composites the same images and
+    transmittance bitwise: the walks only skip tracking the last entry. One view takes the
+    pipelined walk; sixteen 656x656 views (26896 tiles) the compact one."""
+    torch = torch_cuda
+    base = S.uniform_cube_scene(6000, seed=91, log_scale_mean=math.log(0.06), log_scale_std=0.4)
+    cams = [S.look_at_camera((0.0, 0.0, 3.2), width=48, height=40)] if walk != "compact" else \
+        [S.orbit_camera(0.3 * i, 4.0, 656, 656) for i in range(16)]
+    note(f"forward without n_last: {family}, {walk} walk, {len(cams)} view(s)")
+    if family == "iso":
+        R = P.Rasterizer()
+        g = P.GaussianScene.from_host(base)
+    else:
+        R = P.AnisoRasterizer()
+        g = P.AnisoGaussianScene.from_host(S.aniso_from_iso(base))
+    fp = R.project([g] * len(cams), cams)
+    b = R.bin_sort(fp, [g.n] * len(cams), cams)
+    full = R.render_fwd_ordered(fp, [g.n] * len(cams), b, cams, (0.2, 0.1, 0.3), wide=walk == "wide")
+    bare = R.render_fwd_ordered(fp, [g.n] * len(cams), b, cams, (0.2, 0.1, 0.3), wide=walk == "wide", last=False)
+    torch.cuda.synchronize()
+    assert bare[2] is None
+    assert int((full[2] > 0).sum()) > 0
+    assert torch.equal(full[0], bare[0])
+    assert torch.equal(full[1], bare[1])
+    if family == "iso":
+        # the one-workgroup-per-tile kernel without n_last as well
+        spat = R.render_fwd(fp, [g.n] * len(cams), b, cams, (0.2, 0.1, 0.3), last=False)
+        torch.cuda.synchronize()
+        assert spat[2] is None
+        if walk != "wide":
+            assert torch.equal(spat[0], full[0]) and torch.equal(spat[1], full[1])
