@@ -47,8 +47,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--views", type=int, default=100)
     ap.add_argument("--batch-views", type=int, default=10)
     ap.add_argument("--streams", type=int, default=4,
@@ -830,7 +830,7 @@ def main():
     rasters = [R] + [P.Rasterizer(dev, headroom=1.1) for _ in streams[1:]]
 
     # size the entry capacity on the warm-up pass
-    def forward_step(check):
+    def forward_step(check, spans=True):
         stage = dict(project=[], bin_sort=[], render_fwd=[])
         bins_all = []
         go = torch.cuda.Event()
@@ -840,18 +840,20 @@ def main():
         for k, bc in enumerate(batches):
             s, Rk = streams[k % len(streams)], rasters[k % len(streams)]
             with torch.cuda.stream(s):
-                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if spans else [None] * 4
+                mark = (lambda e: e.record(s)) if spans else (lambda e: None)
                 scenes = [gs] * len(bc)
-                ev[0].record(s)
+                mark(ev[0])
                 fp = Rk.project(scenes, bc)
-                ev[1].record(s)
+                mark(ev[1])
                 bins = Rk.bin_sort(fp, [gs.n] * len(bc), bc, check=check)
-                ev[2].record(s)
+                mark(ev[2])
                 Rk.render_fwd_ordered(fp, [gs.n] * len(bc), bins, bc, last=False)
-                ev[3].record(s)
-            stage["project"].append((ev[0], ev[1]))
-            stage["bin_sort"].append((ev[1], ev[2]))
-            stage["render_fwd"].append((ev[2], ev[3]))
+                mark(ev[3])
+            if spans:
+                stage["project"].append((ev[0], ev[1]))
+                stage["bin_sort"].append((ev[1], ev[2]))
+                stage["render_fwd"].append((ev[2], ev[3]))
             bins_all.append(bins)
         for s in streams[1:]:
             done = torch.cuda.Event()
@@ -888,18 +890,20 @@ def main():
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stages = []
     for _ in range(args.steps):
-        st, bins_all = forward_step(check=False)
-        stages.append(st)
+        _, bins_all = forward_step(check=False, spans=False)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for b in bins_all:
         b.verify()
     ms_step = elapsed / args.steps * 1e3
     mpix = args.steps * args.views * args.width * args.height / elapsed / 1e6
-    stage_ms = {k: sum(a.elapsed_time(b) for st in stages for a, b in st[k]) / args.steps for k in stages[0]}
-    log(f"forward: {ms_step:.2f} ms/step, {mpix:.1f} Mpix/s, stages {stage_ms}")
+    # the stage spans of one more step, with timing events between the stages (outside the
+    # timed region: the events are instrumentation, not part of the workload)
+    st, _ = forward_step(check=False, spans=True)
+    torch.cuda.synchronize()
+    stage_ms = {k: sum(a.elapsed_time(b) for a, b in st[k]) for k in st}
+    log(f"forward: {ms_step:.2f} ms/step, {mpix:.1f} Mpix/s, stages of one instrumented step {stage_ms}")
 
     # per-stage rooflines from solo launches (nothing else on the GPU), one call per batch;
     # the dominant kernel is compositing, bound by the FP32 VALU: work = evaluated (pixel,
