@@ -298,18 +298,22 @@ __global__ void __launch_bounds__(kSortThreads) tile_count_kernel(const uint32_t
                                                                   const uint32_t* __restrict__ count_p,
                                                                   uint64_t capacity, int shift, int bits,
                                                                   uint32_t* __restrict__ tcount, uint32_t stride) {
-    __shared__ uint32_t s_h[kTileRadix];
+    // four copies of the counters, lane l adding to copy l mod 4: lanes of one instruction
+    // that share a digit (many do in the second pass, whose input is ordered by the low
+    // digit) mostly hit different copies, at different banks (copies kTileRadix + 1 apart)
+    constexpr uint32_t kCopy = kTileRadix + 1;
+    __shared__ uint32_t s_h[4 * kCopy];
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     const uint32_t n_tiles = (count + kSortTile - 1) / kSortTile;
     if (blockIdx.x >= n_tiles) return;
     const uint32_t tile = xcd_swizzle(blockIdx.x, n_tiles), t = threadIdx.x;
-    s_h[t] = 0u;
-    s_h[t + 256] = 0u;
+    for (uint32_t q = t; q < 4 * kCopy; q += kSortThreads) s_h[q] = 0u;
     __syncthreads();
     uint32_t k[kSortItems];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) k[i] = kin[min(tile * kSortTile + i * kSortThreads + t, count - 1)];
+    uint32_t* h = s_h + (lane_id() & 3u) * kCopy;
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
         const bool ok = tile * kSortTile + i * kSortThreads + t < count;
@@ -320,12 +324,13 @@ __global__ void __launch_bounds__(kSortThreads) tile_count_kernel(const uint32_t
         if (ballot64(ok && d != d0) == 0) {
             if (lane_id() == 0 && act) atomicAdd(&s_h[d0], (uint32_t)__popcll(act));
         } else if (ok) {
-            atomicAdd(&s_h[d], 1u);
+            atomicAdd(&h[d], 1u);
         }
     }
     __syncthreads();
-    tcount[(size_t)t * stride + tile] = s_h[t];
-    tcount[(size_t)(t + 256) * stride + tile] = s_h[t + 256];
+#pragma unroll
+    for (uint32_t d = t; d < (uint32_t)kTileRadix; d += kSortThreads)
+        tcount[(size_t)d * stride + tile] = s_h[d] + s_h[kCopy + d] + s_h[2 * kCopy + d] + s_h[3 * kCopy + d];
 }
 
 __global__ void __launch_bounds__(256) tile_scan_kernel(uint32_t* __restrict__ tcount, uint32_t stride,
