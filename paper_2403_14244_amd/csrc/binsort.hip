@@ -483,19 +483,37 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
     }
 }
 
-// Step 5: tile ranges from the sorted tile ids.
+// Step 5: tile ranges from the sorted tile ids, four consecutive entries per thread (one
+// 16-byte load; the workspace and its sections are 256-byte aligned) and the two
+// neighbours of the run.
 __global__ void __launch_bounds__(256) finalize_kernel(const uint32_t* __restrict__ keys,
                                                        const uint32_t* __restrict__ count_p, uint64_t capacity,
                                                        uint32_t tiles_total, uint32_t* __restrict__ ranges) {
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        const uint32_t tl = keys[i];
-        const uint32_t prev = i > 0 ? keys[i - 1] : 0xFFFFFFFFu;
-        const uint32_t next = i + 1 < count ? keys[i + 1] : 0xFFFFFFFFu;
-        if (tl < tiles_total) {
-            if (tl != prev) ranges[2 * tl] = i;
-            if (tl != next) ranges[2 * tl + 1] = i + 1;
+    const uint32_t groups = (count + 3) / 4;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += gridDim.x * blockDim.x) {
+        const uint32_t i0 = 4 * g;
+        uint32_t k[6];   // ids of entries i0 - 1 .. i0 + 4; none past the ends (all ones)
+        k[0] = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+        if (i0 + 4 <= count) {
+            const uint4 q = *reinterpret_cast<const uint4*>(keys + i0);
+            k[1] = q.x;
+            k[2] = q.y;
+            k[3] = q.z;
+            k[4] = q.w;
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) k[1 + j] = i0 + j < count ? keys[i0 + j] : 0xFFFFFFFFu;
+        }
+        k[5] = i0 + 4 < count ? keys[i0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + j, tl = k[1 + j];
+            if (i < count && tl < tiles_total) {
+                if (tl != k[j]) ranges[2 * tl] = i;
+                if (tl != k[j + 2]) ranges[2 * tl + 1] = i + 1;
+            }
         }
     }
 }
@@ -1455,7 +1473,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         zout = const_cast<uint32_t*>(tz);
     }
     // 5. ranges
-    const unsigned fin_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 255) / 256);
+    const unsigned fin_blocks = (unsigned)std::min<uint64_t>(2048, (plan.capacity + 1023) / 1024);
     hipLaunchKernelGGL(finalize_kernel, dim3(fin_blocks), dim3(256), 0, stream, kin, bins->count, plan.capacity,
                        plan.tiles_total, bins->ranges);
     // 6. depth order within every tile (zin: depth bits in the order of pidx; the tile-id
