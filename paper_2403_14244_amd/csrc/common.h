@@ -68,11 +68,12 @@ __device__ __forceinline__ bool tile_member(float u, float v, float r2, int tx, 
 
 // Candidate tile box of a footprint: every tile that can pass tile_member lies inside.
 // A tile left of u needs 16 tx + 15.5 >= u - r, one right of u needs 16 tx + 0.5 <= u + r;
-// the extra half pixel absorbs FP32 rounding of the test.
+// the extra half pixel absorbs FP32 rounding of the test: a tile below the lower bound has
+// its last pixel centre more than r + 0.5 from u, far outside any rounding of tile_member.
 __device__ __forceinline__ void tile_box(float u, float v, float r, int tiles_x, int tiles_y, int& tx0,
                                          int& tx1, int& ty0, int& ty1) {
-    tx0 = max(0, (int)floorf((u - r - 16.0f) * (1.0f / kTile)));
-    ty0 = max(0, (int)floorf((v - r - 16.0f) * (1.0f / kTile)));
+    tx0 = max(0, (int)ceilf((u - r - 16.0f) * (1.0f / kTile)));
+    ty0 = max(0, (int)ceilf((v - r - 16.0f) * (1.0f / kTile)));
     tx1 = min(tiles_x - 1, (int)floorf((u + r) * (1.0f / kTile)));
     ty1 = min(tiles_y - 1, (int)floorf((v + r) * (1.0f / kTile)));
 }
