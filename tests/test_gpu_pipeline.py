@@ -163,6 +163,25 @@ def _bin_case(name):
             views.append(TH.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
         return views, cams
+    if name == "tile_edges":
+        # disks whose edges fall on, just inside and just outside tile borders and pixel
+        # centres (the candidate tile box and the membership test at their margins), in a
+        # 200x170 view whose last tile column and row are partial
+        offs = np.array([0.0, 0.25, 0.5, 0.5 - 2.0 ** -10, 0.5 + 2.0 ** -10, 8.0, 15.5, 15.75, 16.0 - 2.0 ** -10])
+        radii = np.array([0.25, 0.5, 1.0, 4.0, 7.5, 15.5, 16.0, 16.5, 24.0, 40.0])
+        us, vs, rs = [], [], []
+        for k in (0, 3, 11, 12):
+            for ox in offs:
+                for oy in offs[::3]:
+                    for r in radii:
+                        us.append(16 * k + ox)
+                        vs.append(16 * (k % 10) + oy)
+                        rs.append(r)
+        u = np.array(us, np.float32)
+        v = np.array(vs, np.float32)
+        r = np.array(rs, np.float32)
+        z = np.random.default_rng(5).uniform(0.5, 8.0, u.shape[0]).astype(np.float32)
+        return [TH.synthetic_f32_footprints(u, v, z, r, 200, 170, seed=9)], [S.look_at_camera((0, 0, 3), width=200, height=170)]
     if name == "segment_groups":
         # segments of 513 .. 4096 entries, one per view, sorted several to a workgroup (up to
         # 1024 entries four at once, up to 2048 two at once): odd numbers in each size class
@@ -208,7 +227,7 @@ def _bin_case(name):
 
 
 BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled",
-             "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_groups", "segment_ties_bucketed", "single_tile",
+             "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_groups", "tile_edges", "segment_ties_bucketed", "single_tile",
              "all_tiles_long", "segment_chunked", "segment_chunked_ties"]
 
 
