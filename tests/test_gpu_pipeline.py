@@ -805,11 +805,12 @@ def test_twenty_views_in_one_call(P, torch_cuda):
 def test_forward_without_n_last_is_the_same(P, torch_cuda, family, walk):
     """A forward that passes no n_last (no backward follows) composites the same images and
     transmittance bitwise: the walks only skip tracking the last entry. One view takes the
-    pipelined walk; sixteen 656x656 views (26896 tiles) the compact one."""
+    pipelined walk; twenty 656x656 views are two launch groups, the first sixteen views
+    (26896 tiles) in the compact walk, the last four in the pipelined one."""
     torch = torch_cuda
     base = S.uniform_cube_scene(6000, seed=91, log_scale_mean=math.log(0.06), log_scale_std=0.4)
     cams = [S.look_at_camera((0.0, 0.0, 3.2), width=48, height=40)] if walk != "compact" else \
-        [S.orbit_camera(0.3 * i, 4.0, 656, 656) for i in range(16)]
+        [S.orbit_camera(0.3 * i, 4.0, 656, 656) for i in range(20)]
     note(f"forward without n_last: {family}, {walk} walk, {len(cams)} view(s)")
     if family == "iso":
         R = P.Rasterizer()
