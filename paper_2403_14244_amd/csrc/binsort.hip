@@ -648,9 +648,11 @@ __device__ __forceinline__ void segment_sort_groups(SegShared& sh, uint32_t G, u
     passes = __builtin_amdgcn_readfirstlane(passes);
     // digits of this thread in the group's scan: 2 tg, 2 tg + 1 for G = 2, tg otherwise
     const uint32_t nd = G == 2 ? 2u : 1u, d0 = tg * nd;
-    // Every group makes every pass, on bits [min(lo + 8 pass, 24), +8): a pass on bits at or
-    // above the segment's differing ones, or one that re-ranks its most significant
-    // differing bits, is a stable pass over keys already in that order and changes nothing.
+    // Every group makes the most passes any group needs, pass p on bits [min(lo + 8 p, 24),
+    // +8). A group's extra passes rank bits above its differing ones (equal within the
+    // segment) or its most significant differing bits again: stable passes over keys
+    // already in that order, which change nothing. Where the clamp makes a group's own last
+    // pass overlap the one before, the stable LSD order is still the sorted one.
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = min(lo + pass * kRadixBits, 32 - kRadixBits);
         // each wave clears its own counters: LDS operations of one wave complete in order
