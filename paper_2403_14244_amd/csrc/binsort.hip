@@ -200,12 +200,12 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
 
 // Step 3: one entry per (particle, member tile); entries of a particle are consecutive
 // from its offset, tiles in row-major order. A particle writes no more entries than its
-// tile count says (the count may come from elsewhere); missing ones get the sentinel id
-// 0xFFFFFFFF, which sorts last and belongs to no tile. One workgroup per chunk of 256
-// particles of a view.
+// tile count says (the count may come from elsewhere; here it is the difference of
+// consecutive offsets, which the scan made from those counts, the last one's from the
+// total); missing ones get the sentinel id 0xFFFFFFFF, which sorts last and belongs to no
+// tile. One workgroup per chunk of 256 particles of a view.
 __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ record,
-                                                   const uint32_t* __restrict__ tile_count,
-                                                   const uint32_t* __restrict__ offsets,
+                                                   const uint32_t* __restrict__ offsets, uint32_t n_total,
                                                    const float* __restrict__ depth,
                                                    const uint32_t* __restrict__ count_p, uint64_t capacity,
                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
@@ -218,8 +218,10 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
     const uint32_t first = vd.p_off + (c - pk.block_begin[vi]) * 256u;
     const uint32_t last = min(first + 255u, vd.p_off + vd.n - 1u);
     const uint32_t i = first + threadIdx.x;
-    const uint32_t want = i <= last ? tile_count[i] : 0u;
-    const uint32_t e0 = want ? offsets[i] : 0u;
+    if (i > last) return;
+    const uint32_t e0 = offsets[i];
+    const uint32_t e1 = i + 1 < n_total ? offsets[i + 1] : count;
+    const uint32_t want = e1 - e0;
     if (!want || (uint64_t)e0 + want > count) return;
     const float4 fp = record[2 * (size_t)i];
     const float r = record[2 * (size_t)i + 1].w;
@@ -1439,7 +1441,7 @@ int launch_bin_sort(const BinSortPlan& plan, const isogs_projected* proj, const 
         pk.block_begin[pk.nv] = blocks;
         if (!blocks) continue;
         hipLaunchKernelGGL(emit_kernel, dim3(blocks), dim3(256), 0, stream, pk,
-                           reinterpret_cast<const float4*>(proj->record), proj->tile_count, bins->offsets,
+                           reinterpret_cast<const float4*>(proj->record), bins->offsets, plan.n_total,
                            proj->depth, bins->count, plan.capacity, keys_a, v_emit, z_a);
     }
     if (plan.capacity == 0) return hipPeekAtLastError() == hipSuccess ? 0 : -1;
