@@ -173,9 +173,9 @@ int isogs_bin_sort(const isogs_projected* proj, const int32_t* n_per_view,
  * runs on until the process ends (its address is looked up once per device, on the first
  * call with that device current). The caller still owns and passes proj and bins.
  *   - Limit: the call needs the scratch isogs_bin_sort reports for the same arguments
- *     (about 20 bytes per entry of capacity plus 2 KB per 4096 entries and 4 bytes per
- *     tile); above ISOGS_STATIC_SCRATCH_BYTES it returns ISOGS_ERR_WORKSPACE and launches
- *     nothing (128 MiB: about 6M entries, three 1080p views of a 1M-particle scene).
+ *     (about 21 bytes per entry of capacity, 20 bytes per tile and 0.3 MB); above
+ *     ISOGS_STATIC_SCRATCH_BYTES it returns ISOGS_ERR_WORKSPACE and launches nothing
+ *     (128 MiB: about 6M entries, three 1080p views of a 1M-particle scene).
  *   - No hipMalloc, hipFree or allocating library call is made; the bookkeeping that must
  *     start at zero is cleared by a kernel on `stream` at every call.
  *   - Every call on one GPU shares that GPU's array, which keeps the last call's contents:
