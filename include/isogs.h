@@ -592,13 +592,15 @@ int isogs_l1_fwd(const float* image, const float* target, int64_t n, float* loss
 int isogs_l1_bwd(const float* image, const float* target, int64_t n, const float* dL_dloss,
                  float* dL_dimage, void* stream);
 
-/* A HIP stream of default priority (non-blocking with respect to the null stream) created
- * on the current device, for callers that run work on several streams at once and need each
- * on a hardware queue of its own: a stream takes the least used of the process's hardware
- * queues when it is created, while streams created together earlier (a framework's pool)
- * can share one, which runs their work in turn. The stream is the caller's to destroy with
- * isogs_stream_destroy once its work is done. Errors: ISOGS_ERR_INVALID (NULL stream),
- * ISOGS_ERR_DEVICE. */
+/* A HIP stream of default priority on the current device with a hardware queue of its own,
+ * for callers that run work on several streams at once and need it to overlap on the device:
+ * a plain stream takes the least used queue of the process's shared pool when it is
+ * created, so that two streams made one after the other can share a queue, which then runs
+ * their work in turn. The stream is created with a CU mask that enables every CU, which
+ * gives it a queue outside that pool. Like a stream from hipStreamCreate it is ordered with
+ * the null stream (work on either waits for earlier work on the other). The stream is the
+ * caller's to destroy with isogs_stream_destroy once its work is done. Errors:
+ * ISOGS_ERR_INVALID (NULL stream), ISOGS_ERR_DEVICE. */
 int isogs_stream_create(void** stream);
 int isogs_stream_destroy(void* stream);
 

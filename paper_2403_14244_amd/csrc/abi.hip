@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, workspace sizing and dispatch.
+#include <algorithm>
 #include <math.h>
 #include <mutex>
 #include <stdarg.h>
@@ -129,8 +130,18 @@ extern "C" {
 int isogs_stream_create(void** stream) {
     g_error[0] = 0;
     if (!stream) return fail(ISOGS_ERR_INVALID, "stream is NULL");
+    // A stream with a CU mask gets a hardware queue created for it alone; streams without
+    // one share the process's pool of queues, where two of them can land on the same queue
+    // (the least used one at creation) and then run in turn. The mask enables every CU.
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return device_fail("isogs_stream_create");
+    uint32_t mask[32] = {};
+    const int words = std::min((cus + 31) / 32, 32);
+    for (int c = 0; c < std::min(cus, 32 * 32); ++c) mask[c / 32] |= 1u << (c % 32);
     hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return device_fail("isogs_stream_create");
+    if (hipExtStreamCreateWithCUMask(&s, (uint32_t)words, mask) != hipSuccess) return device_fail("isogs_stream_create");
     *stream = s;
     return ISOGS_OK;
 }

@@ -217,11 +217,10 @@ class SimulatedExecutor(Executor):
 
 
 def _own_streams(n, device):
-    """`n` HIP streams created for this executor by the library (default priority,
-    non-blocking), wrapped as torch streams. Each new stream takes the least used of the
-    process's hardware queues, so the slots' streams sit on different queues; streams handed
-    out by torch's pool were created together long before and can share one, which runs
-    their work in turn."""
+    """`n` HIP streams created for this executor by the library (default priority, each on a
+    hardware queue of its own), wrapped as torch streams. Streams from the process's shared
+    pool of queues (torch's own, plain hipStreamCreate) can share a queue, which runs their
+    work in turn."""
     import ctypes
     import torch
     from . import _abi as A
@@ -239,9 +238,9 @@ class GpuExecutor(Executor):
     """Runs batches through the C ABI on `n_streams` HIP streams (default priority).
 
     Batches of different slots overlap on the device only where their streams sit on
-    different hardware queues: HIP gives each process a pool of GPU_MAX_HW_QUEUES of them
-    (4 by default) shared by every stream the process creates, torch's own included; run
-    with 8 (set before the HIP runtime starts) to keep the slots apart."""
+    different hardware queues: the slots' streams come from `isogs_stream_create`, which
+    gives each a queue of its own outside the pool of GPU_MAX_HW_QUEUES queues that HIP
+    shares among the process's other streams."""
 
     def __init__(self, scenes: dict, device="cuda", n_streams=2, headroom=1.3, record_spans=False):
         import torch
