@@ -139,6 +139,15 @@ def bwd_pairs(n_last):
     return int(n_last.long().sum().item())
 
 
+def hold_stream():
+    """Queue a spin kernel on the current stream (5M cycles of the device clock: about 2 ms
+    at 2.4 GHz) so that the host enqueues the launches that follow while the device is busy:
+    HIP events placed after it then time the device's work alone, with no host launch
+    latency between a synchronisation and the first kernel."""
+    import torch
+    torch.cuda._sleep(5_000_000)
+
+
 def solo_stages(R, gs, batches, dL_seed=7):
     """Every stage of the benchmark call alone on one stream, with HIP events on that
     stream around each library call: projection, bin sort, longest-first compositing (as
@@ -154,6 +163,7 @@ def solo_stages(R, gs, batches, dL_seed=7):
     for bc in batches:
         npv = [gs.n] * len(bc)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        hold_stream()
         ev[0].record()
         fp = R.project([gs] * len(bc), bc)
         ev[1].record()
@@ -386,6 +396,7 @@ def stress_workload(dev, iters=3):
     fwd = []
     for _ in range(3):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        hold_stream()
         e0.record()
         R.render([g_init] * len(cams), cams, check=False)
         e1.record()
@@ -557,6 +568,7 @@ def field2d_workload(dev, iters=100):
             fp, bins = R.bin(mu.detach(), s.detach(), a.detach())
             w = torch.sign(R.render(fp, bins, 2000) - tgt) / tgt.numel()
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            hold_stream()
             ev[0].record()
             for _ in range(20):
                 R.render(fp, bins, 2000)
@@ -626,6 +638,7 @@ def field2d_workload(dev, iters=100):
             afp, acc, abins = Ra.bin(amu.detach(), ath.detach(), asc.detach(), aa.detach())
             aw = torch.sign(Ra.render(afp, acc, abins, 2000) - tgt) / tgt.numel()
             aev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            hold_stream()
             aev[0].record()
             for _ in range(20):
                 Ra.render(afp, acc, abins, 2000)
