@@ -203,13 +203,20 @@ __global__ void __launch_bounds__(kScanThreads) scan_down_kernel(const uint32_t*
 // tile count says (the count may come from elsewhere; here it is the difference of
 // consecutive offsets, which the scan made from those counts, the last one's from the
 // total); missing ones get the sentinel id 0xFFFFFFFF, which sorts last and belongs to no
-// tile. One workgroup per chunk of 256 particles of a view.
+// tile. One workgroup per chunk of 256 particles of a view. The chunk's entries are one
+// run of the output; when it holds at most kEmitStage entries they are gathered in LDS
+// (tile id and owner) and written as whole runs, else each particle writes its own.
+constexpr uint32_t kEmitStage = 2048;
+
 __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const float4* __restrict__ record,
                                                    const uint32_t* __restrict__ offsets, uint32_t n_total,
                                                    const float* __restrict__ depth,
                                                    const uint32_t* __restrict__ count_p, uint64_t capacity,
                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                    uint32_t* __restrict__ zbits) {
+    __shared__ uint32_t s_key[kEmitStage];
+    __shared__ uint8_t s_own[kEmitStage];
+    __shared__ uint32_t s_z[256];
     const uint32_t count = *count_p;
     if ((uint64_t)count > capacity) return;
     const uint32_t c = blockIdx.x;
@@ -217,34 +224,72 @@ __global__ void __launch_bounds__(256) emit_kernel(const ViewPack pk, const floa
     const ViewDesc& vd = pk.v[vi];
     const uint32_t first = vd.p_off + (c - pk.block_begin[vi]) * 256u;
     const uint32_t last = min(first + 255u, vd.p_off + vd.n - 1u);
+    // the chunk's run [E0, E1), uniform over the workgroup
+    const uint32_t E0 = offsets[first];
+    const uint32_t E1 = last + 1 < n_total ? offsets[last + 1] : count;
+    const bool staged = E1 >= E0 && E1 <= count && E1 - E0 <= kEmitStage;
     const uint32_t i = first + threadIdx.x;
-    if (i > last) return;
-    const uint32_t e0 = offsets[i];
-    const uint32_t e1 = i + 1 < n_total ? offsets[i + 1] : count;
-    const uint32_t want = e1 - e0;
-    if (!want || (uint64_t)e0 + want > count) return;
-    const float4 fp = record[2 * (size_t)i];
-    const float r = record[2 * (size_t)i + 1].w;
-    const uint32_t z = __float_as_uint(depth[i]);
-    int tx0, tx1, ty0, ty1;
-    tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
-    const float r2 = r * r;
+    uint32_t e0 = 0, want = 0;
+    if (i <= last) {
+        e0 = offsets[i];
+        want = (i + 1 < n_total ? offsets[i + 1] : count) - e0;
+        if ((uint64_t)e0 + want > count) want = 0;
+    }
+    uint32_t z = 0;
+    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
+    float fx = 0.f, fy = 0.f, r2 = 0.f;
+    if (want) {
+        const float4 fp = record[2 * (size_t)i];
+        const float r = record[2 * (size_t)i + 1].w;
+        z = __float_as_uint(depth[i]);
+        fx = fp.x;
+        fy = fp.y;
+        r2 = r * r;
+        tile_box(fp.x, fp.y, r, vd.tiles_x, vd.tiles_y, tx0, tx1, ty0, ty1);
+    }
     const float w_lim = (float)vd.width - 0.5f, h_lim = (float)vd.height - 0.5f;
-    uint32_t j = 0;
-    for (int ty = ty0; ty <= ty1 && j < want; ++ty) {
-        for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
-            if (!tile_member(fp.x, fp.y, r2, tx, ty, w_lim, h_lim)) continue;
-            const uint32_t e = e0 + j++;
-            keys[e] = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
+    if (!staged) {
+        uint32_t j = 0;
+        for (int ty = ty0; ty <= ty1 && j < want; ++ty) {
+            for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
+                if (!tile_member(fx, fy, r2, tx, ty, w_lim, h_lim)) continue;
+                const uint32_t e = e0 + j++;
+                keys[e] = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
+                vals[e] = i;
+                zbits[e] = z;
+            }
+        }
+        for (; j < want; ++j) {
+            const uint32_t e = e0 + j;
+            keys[e] = 0xFFFFFFFFu;
             vals[e] = i;
             zbits[e] = z;
         }
+        return;
+    }
+    // staged: every entry of the run belongs to one particle of the chunk (the offsets are
+    // non-decreasing), so each LDS slot is written once
+    s_z[threadIdx.x] = z;
+    const uint32_t l0 = e0 - E0;
+    uint32_t j = 0;
+    for (int ty = ty0; ty <= ty1 && j < want; ++ty) {
+        for (int tx = tx0; tx <= tx1 && j < want; ++tx) {
+            if (!tile_member(fx, fy, r2, tx, ty, w_lim, h_lim)) continue;
+            s_key[l0 + j] = vd.tile_base + (uint32_t)(ty * vd.tiles_x + tx);
+            s_own[l0 + j] = (uint8_t)threadIdx.x;
+            ++j;
+        }
     }
     for (; j < want; ++j) {
-        const uint32_t e = e0 + j;
-        keys[e] = 0xFFFFFFFFu;
-        vals[e] = i;
-        zbits[e] = z;
+        s_key[l0 + j] = 0xFFFFFFFFu;
+        s_own[l0 + j] = (uint8_t)threadIdx.x;
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < E1 - E0; q += 256u) {
+        const uint32_t o = s_own[q];
+        keys[E0 + q] = s_key[q];
+        vals[E0 + q] = first + o;
+        zbits[E0 + q] = s_z[o];
     }
 }
 

@@ -195,6 +195,20 @@ def _bin_case(name):
             views.append(TH.synthetic_f32_footprints(u, v, z, r, 48, 32, seed=k))
             cams.append(S.look_at_camera((0, 0, 3), width=48, height=32))
         return views, cams
+    if name == "emit_runs":
+        # the emit step writes a chunk of 256 particles' entries through LDS when the chunk
+        # holds at most 2048 of them, else each particle writes its own: views of small,
+        # medium (chunks on both sides of 2048) and large disks
+        rng = np.random.default_rng(91)
+        views, cams = [], []
+        for k, (n, r0, r1) in enumerate([(1536, 0.5, 12.0), (1280, 10.8, 22.8), (768, 40.0, 90.0)]):
+            u = rng.uniform(0, 400, n).astype(np.float32)
+            v = rng.uniform(0, 300, n).astype(np.float32)
+            z = rng.uniform(0.5, 9.0, n).astype(np.float32)
+            r = rng.uniform(r0, r1, n).astype(np.float32)
+            views.append(TH.synthetic_f32_footprints(u, v, z, r, 400, 300, seed=k))
+            cams.append(S.look_at_camera((0, 0, 3), width=400, height=300))
+        return views, cams
     if name == "segment_ties_bucketed":
         # one 3000-entry segment whose depths take 64 values: every bucket of the leading
         # bits holds one value many times, so positions decide the order inside buckets
@@ -228,7 +242,7 @@ def _bin_case(name):
 
 BIN_CASES = ["cube10k_256", "mix_batch_3views", "random_ties", "random_wide", "mix200k_1080p", "empty_and_culled",
              "crowd_wide_depth", "crowd_narrow_depth", "segment_boundaries", "segment_groups", "tile_edges", "segment_ties_bucketed", "single_tile",
-             "all_tiles_long", "segment_chunked", "segment_chunked_ties"]
+             "all_tiles_long", "segment_chunked", "segment_chunked_ties", "emit_runs"]
 
 
 @pytest.mark.parametrize("case", BIN_CASES)
@@ -236,6 +250,16 @@ def test_bin_sort_bit_exact(P, torch_cuda, case):
     views, cams = _bin_case(case)
     ob = O.bin_sort_ref(views)
     note(f"bin_sort {case}: {ob.keys.shape[0]} entries")
+    if case == "emit_runs":
+        # entries per chunk of 256 particles of a view: both sides of 2048 occur
+        ends = np.append(ob.offsets[1:].astype(np.int64), ob.keys.shape[0])
+        p0, runs = 0, []
+        for vw in views:
+            n = vw["u"].shape[0]
+            runs += [int(ends[min(p0 + c + 255, p0 + n - 1)] - int(ob.offsets[p0 + c])) for c in range(0, n, 256)]
+            p0 += n
+        assert min(runs) <= 2048 < max(runs) and sum(2000 <= x <= 2048 for x in runs) >= 2 and \
+            sum(2048 < x <= 2100 for x in runs) >= 1, runs
     R = P.Rasterizer()
     fp = TH.upload_footprints(views, ob)
     npv = [v["u"].shape[0] for v in views]
