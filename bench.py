@@ -27,9 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# the forward's four streams and the serving slots' streams each on a hardware queue of
-# their own (HIP's default pool of 4 per process would make some share one and run in
-# turn); set before the HIP runtime starts
+# room for the forward's four streams in HIP's per-process pool of hardware queues (4 by
+# default, shared with torch's own streams; streams that share a queue run in turn); the
+# serving slots' streams get queues outside the pool; set before the HIP runtime starts
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 

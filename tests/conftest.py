@@ -5,8 +5,8 @@ import pytest
 
 # HIP maps streams onto a per-process pool of hardware queues (4 by default); past that,
 # streams share queues and their work runs one after another. The GPU tests create a few
-# streams per test (serving slots, overlap checks): eight queues keep them apart. Set
-# before the HIP runtime starts.
+# streams per test (the serving slots' own get queues outside the pool): eight queues keep
+# them apart. Set before the HIP runtime starts.
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
